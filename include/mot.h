@@ -1,0 +1,250 @@
+/*
+ * mot.h -- C ABI of the MI355X (gfx950) library for tree- and circle-structured
+ * entropic multi-marginal optimal transport solved by Sinkhorn iterations whose
+ * Gaussian-kernel products run either by direct summation or by NFFT-based
+ * fast summation (Ba & Quellmalz, "Accelerating the Sinkhorn algorithm for
+ * sparse multi-marginal optimal transport by fast Fourier transforms").
+ *
+ * Conventions shared by every call
+ *   - Marginals are numbered 0..K-1; the paper's marginal 1 (the tree root and
+ *     the circle's first node) is marginal 0.
+ *   - Points of all marginals are passed concatenated: a row-major
+ *     (sum_k n_k) x d array of doubles, marginal k occupying rows
+ *     [off_k, off_k + n_k) with off_k = n_0 + ... + n_{k-1}.  Weights, scaling
+ *     vectors and marginals are concatenated the same way.
+ *   - ptr_kind says whether a caller buffer is host memory (MOT_HOST) or device
+ *     memory of the plan's GPU (MOT_DEVICE).  The caller owns every buffer it
+ *     passes; the library copies inputs and writes outputs, never keeps them.
+ *   - Every call returns an int status: MOT_OK (0), MOT_MAXITER (1: stopped at
+ *     the sweep limit, results valid) or a negative error code.  No exception
+ *     crosses the ABI.  mot_strerror() gives a static description.
+ *   - A plan is bound to one HIP stream.  All work of a call is enqueued on it;
+ *     calls that return results to host memory synchronise that stream.  Two
+ *     plans may be used from different threads; one plan must not be.
+ */
+#ifndef MOT_H
+#define MOT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes --------------------------------------------------------------- */
+#define MOT_OK 0
+#define MOT_MAXITER 1      /* sweep limit reached before the stopping test held        */
+#define MOT_EINVAL (-1)    /* invalid argument (sizes, topology, weights, eta, ...)      */
+#define MOT_EDOMAIN (-2)   /* fast-summation parameters cannot represent the points      */
+#define MOT_ENOMEM (-3)    /* device allocation failed or admission budget exceeded      */
+#define MOT_EDEVICE (-4)   /* HIP runtime error                                          */
+#define MOT_ENUMERIC (-6)  /* a scaling vector became Inf/NaN (kernel underflow)         */
+#define MOT_EUNSUPPORTED (-7) /* combination of options not provided                      */
+
+/* ---- enumerations ---------------------------------------------------------------- */
+#define MOT_TREE 0         /* cost decouples along a tree (Sec. 4.1)                      */
+#define MOT_CIRCLE 1       /* cost decouples along a circle (Sec. 4.2)                    */
+
+#define MOT_DIRECT 0       /* kernel products by direct O(N^2) summation, eq. (fastsum-sum) */
+#define MOT_NFFT 1         /* kernel products by NFFT fast summation, Algorithm 4         */
+#define MOT_DENSE 2        /* circle only: dense matrix products on MFMA                  */
+
+#define MOT_PREC_FP64 0    /* direct path: FP64 exp and accumulation                      */
+#define MOT_PREC_MIXED 1   /* direct path: FP32 exp, FP32 tile sums, FP64 across tiles;
+                              NFFT path: FP32 spread/FFT/interpolation                    */
+#define MOT_PREC_BF16 2    /* dense circle: BF16 operands, FP32 accumulation              */
+#define MOT_PREC_FP16 3    /* dense circle: FP16 operands (power-of-two scaled), FP32 acc. */
+#define MOT_PREC_BF16X3 4  /* dense circle: split BF16 (hi*hi + hi*lo + lo*hi), FP32 acc.  */
+
+#define MOT_HOST 0
+#define MOT_DEVICE 1
+
+/* Fast-summation parameters (Sec. 5, Algorithm 4).  A zero field is chosen by the
+ * library's autotuner from d, eta, the point extent and the sizes.
+ *   M      half bandwidth: kappa_hat is used on {-M..M-1}^d (2M coefficients per dim)
+ *   n      oversampled FFT grid per dimension (power of two, 16..512)
+ *   m      window cutoff: Kaiser-Bessel window supported on |s| <= m grid cells,
+ *          2m taps per dimension
+ *   p      smoothness of the boundary polynomial kappa_B (degree 2p)
+ *   tau    half period of the periodised kernel; must exceed eps_B plus the
+ *          largest distance between points of the two marginals of any edge
+ *   eps_B  width of the boundary interval of the regularised kernel
+ *   tile   edge (in grid cells) of the binning tiles that spreading/interpolation
+ *          work on
+ *   chunk  maximum points per spreading work item                              */
+typedef struct {
+    int32_t M, n, m, p;
+    double tau, eps_B;
+    int32_t tile, chunk;
+    double target_rel_err; /* autotuner accuracy target for one product (0 = 1e-7) */
+} mot_fastsum_params;
+
+/* Optional device-memory provider (e.g. PyTorch's caching allocator).  NULL
+ * means hipMalloc/hipFree.  alloc returns NULL on failure. */
+typedef struct {
+    void *(*alloc)(size_t bytes, void *ctx);
+    void (*free)(void *ptr, void *ctx);
+    void *ctx;
+} mot_allocator;
+
+typedef struct mot_plan_s *mot_plan;
+
+/* Chosen parameters and layout of a plan (for reporting and tests). */
+typedef struct {
+    int32_t K, d, topology, path, precision;
+    int32_t M, n, m, p, tile, chunk;
+    double tau, eps_B, eta;
+    double scale;        /* grid cells per unit length, s = n / (2 tau)            */
+    double offset[3];    /* grid coordinate of the origin per dimension, o_c       */
+    int32_t box_lo[3];   /* first grid index of the active box per dimension       */
+    int32_t box_len[3];  /* active box extent per dimension                        */
+    int32_t depth;       /* tree depth (levels below the root)                     */
+    size_t device_bytes; /* device memory held by the plan                         */
+    int32_t products_per_sweep;
+} mot_plan_info;
+
+/* Create a plan: copy the problem to the device and precompute everything the
+ * sweeps need.  Follows the discrete problem of Secs. 2-4: K marginals
+ * mu^k = sum_i mu^k_i delta_{x^k_i} with x^k_i in R^d, cost = sum over the edges
+ * of the tree/circle of squared Euclidean distances, entropic regularisation eta.
+ *   n        [K] sizes n_k >= 1 (host memory)
+ *   points   concatenated (sum n_k) x d doubles (ptr_kind)
+ *   weights  concatenated sum n_k doubles, each marginal >= 0 summing to 1 within
+ *            1e-9 (ptr_kind); weights are not renormalised
+ *   parent   tree only: [K] host ints, parent[0] = -1, 0 <= parent[k] < k; NULL
+ *            for a circle (edges {k, k+1 mod K}, K >= 3)
+ *   eta      > 0
+ *   path     MOT_DIRECT, MOT_NFFT or (circle) MOT_DENSE
+ *   precision see MOT_PREC_*; MOT_PREC_FP64 only with MOT_DIRECT
+ *   fs       fast-summation parameters (NFFT path); NULL = all autotuned
+ *   stream   hipStream_t to enqueue on; NULL = a stream the plan creates
+ * Scaling vectors start at phi^(0) = 1.  On failure *out is NULL.           */
+int mot_plan_create(mot_plan *out, int32_t K, int32_t d, const int64_t *n, const double *points,
+                    const double *weights, int32_t topology, const int32_t *parent, double eta,
+                    int32_t path, int32_t precision, const mot_fastsum_params *fs,
+                    int32_t ptr_kind, void *stream, const mot_allocator *alloc);
+
+/* Run Sinkhorn sweeps: Algorithm 2 (tree) or Algorithm 3 (circle).  One sweep
+ * updates every scaling vector once and recomputes the messages; it costs
+ * 2(K-1) kernel products (tree) or 2(K-2) matrix products (circle).
+ *   max_sweeps    sweep limit (>= 0)
+ *   delta_S       stop when |S^(r) - S^(r-1)| < delta_S (0 = off)
+ *   tol_marginal  stop when the L1 error of the first marginal after the sweep,
+ *                 |P_0 - mu^0|_1, is <= tol_marginal (0 = off)
+ *   check_every   stopping tests are read back every check_every sweeps (>= 1)
+ *   sweeps_done, S_last, marg_err  optional outputs (host), may be NULL
+ * Returns MOT_OK when a stopping test held, MOT_MAXITER at the limit,
+ * MOT_ENUMERIC if a scaling vector became non-finite.  Sweeps continue from the
+ * plan's current scaling vectors (warm start). */
+int mot_sinkhorn(mot_plan plan, int32_t max_sweeps, double delta_S, double tol_marginal,
+                 int32_t check_every, int32_t *sweeps_done, double *S_last, double *marg_err);
+
+/* S^(r) of every sweep run so far on this plan (Algorithm 2/3, the dual
+ * objective of Theorem 3.1 one sweep behind).  Writes min(count, stored) values
+ * to host memory and returns the number written (>= 0) or an error. */
+int mot_get_S_history(mot_plan plan, double *S_out, int32_t count);
+
+/* Marginals P_k(K (.) Phi) at the current scaling vectors (Theorem 4.1 for a
+ * tree, Theorem 4.3 for a circle), by one consistent upward and downward
+ * pass.  P_out (optional) receives the concatenated marginals (ptr_kind);
+ * l1_err (optional, host, [K]) receives |P_k - mu^k|_1. */
+int mot_marginals(mot_plan plan, double *P_out, double *l1_err, int32_t ptr_kind);
+
+/* Read / overwrite the scaling vectors phi^k (concatenated, original point
+ * order).  Setting them warm-starts or resumes a solve. */
+int mot_get_scalings(mot_plan plan, double *phi_out, int32_t ptr_kind);
+int mot_set_scalings(mot_plan plan, const double *phi_in, int32_t ptr_kind);
+
+/* One kernel product with the plan's path: out = K^{(t,s)} v, i.e.
+ * out_i = sum_j v_j exp(-|x^t_i - x^s_j|^2 / eta) (Sec. 5, eq. fastsum-sum),
+ * approximated by Algorithm 4 on the NFFT path.  v has n_s entries, out n_t
+ * (original point order, ptr_kind).  Tree plans accept any pair (t, s), circle
+ * plans any pair.  For parity tests of a single product. */
+int mot_apply_kernel(mot_plan plan, int32_t t, int32_t s, const double *v, double *out,
+                     int32_t ptr_kind);
+
+int mot_plan_get_info(mot_plan plan, mot_plan_info *info);
+
+/* Device bytes a plan with these arguments would hold (admission control).
+ * fs as in mot_plan_create; parameters left zero are autotuned from eta and
+ * an assumed point extent of half_width (points in [-half_width, half_width)^d). */
+int mot_plan_footprint(int32_t K, int32_t d, const int64_t *n, int32_t topology, int32_t path,
+                       int32_t precision, double eta, double half_width,
+                       const mot_fastsum_params *fs, size_t *bytes);
+
+/* Release the plan and all its device memory (synchronises its stream). */
+int mot_plan_destroy(mot_plan plan);
+
+const char *mot_strerror(int status);
+
+/* ---- building block: point binning ------------------------------------------------
+ * The node ordering the NFFT path uses (not in the paper):
+ *   u_c = x_c * s_c + o_c   (FP64, product rounded before the add, no FMA)
+ *   cell_c = clamp(floor(u_c), 0, n - 1),  tile_c = cell_c / T
+ *   tile = row-major linearisation over ceil(n/T)^d tiles, coordinate 0 slowest
+ *   perm = stable sort of the point indices by tile (ties by ascending index)
+ *   tile_off[t] = first sorted position of tile t; tile_off[ntiles] = npts
+ * x is npts x d (ptr_kind), s and o are [d] host arrays; cell (npts x d), perm
+ * (npts) and tile_off (ceil(n/T)^d + 1) are written to ptr_kind memory.  Runs on
+ * the GPU (stream may be NULL = default stream) and synchronises. */
+int mot_bin_points(int32_t d, int64_t npts, const double *x, const double *s, const double *o,
+                   int32_t n, int32_t T, int32_t *cell, int32_t *perm, int32_t *tile_off,
+                   int32_t ptr_kind, void *stream);
+
+/* ---- batched form ------------------------------------------------------------------
+ * Run `sweeps` Sinkhorn sweeps on `count` tree plans at once: every level of
+ * every plan's sweep is executed by shared launches (all edges at a tree depth
+ * across all plans in one set of kernels), and the whole batched sweep is
+ * captured once as a HIP graph and replayed.  All plans must share one stream
+ * and use the NFFT or direct path.  Equivalent, plan by plan, to mot_sinkhorn
+ * with the same sweep count and no stopping tests. */
+typedef struct mot_batch_s *mot_batch;
+int mot_batch_create(mot_batch *out, mot_plan *plans, int32_t count);
+int mot_batch_sinkhorn(mot_batch batch, int32_t sweeps, int32_t use_graph);
+int mot_batch_destroy(mot_batch batch);
+
+/* ---- serving form ------------------------------------------------------------------
+ * A continuous-batching solver service on one GPU.  Requests (complete MOT
+ * problems) are admitted when their device footprint fits the HBM budget and a
+ * slot is free; admitted problems stay resident and advance together, one
+ * batched sweep at a time, until each meets its stopping test; finished ones
+ * leave and waiting ones enter between sweeps.  Requests that can never fit
+ * are refused with MOT_ENOMEM at submission. */
+typedef struct mot_server_s *mot_server;
+typedef struct {
+    int32_t K, d, topology;
+    const int64_t *n;          /* [K] host                                            */
+    const double *points;      /* host, concatenated as in mot_plan_create            */
+    const double *weights;     /* host                                                */
+    const int32_t *parent;     /* tree: [K] host; circle: NULL                        */
+    double eta;
+    int32_t path, precision;   /* as in mot_plan_create                               */
+    double tol_marginal;       /* stop when |P_0 - mu^0|_1 <= tol                     */
+    int32_t max_sweeps;
+} mot_request;
+
+typedef struct {
+    int32_t status;            /* MOT_OK, MOT_MAXITER, MOT_ENUMERIC, ...              */
+    int32_t sweeps;
+    double marg_err, S_last;
+    double t_submit, t_admit, t_done; /* seconds on the server's monotonic clock       */
+} mot_result;
+
+int mot_server_create(mot_server *out, size_t hbm_budget, int32_t max_slots, void *stream);
+/* Queue a request (copied).  *ticket identifies it.  Thread-safe. */
+int mot_server_submit(mot_server srv, const mot_request *req, uint64_t *ticket);
+/* Run the service loop for at most `seconds` (or until idle when idle_exit != 0).
+ * Returns the number of requests completed during the call. */
+int mot_server_run(mot_server srv, double seconds, int32_t idle_exit);
+/* Fetch a finished request: returns MOT_OK and fills *res (and phi_out, host,
+ * concatenated, optional) once done; MOT_EINVAL for unknown tickets and 1 while
+ * still pending.  A fetched result is released. */
+int mot_server_fetch(mot_server srv, uint64_t ticket, mot_result *res, double *phi_out);
+double mot_server_clock(mot_server srv);
+int mot_server_destroy(mot_server srv);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MOT_H */

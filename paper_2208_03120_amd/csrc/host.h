@@ -1,0 +1,179 @@
+// Host-side structures of the library: plans, launch steps, device memory.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "mot_internal.h"
+
+#define MOT_HIP(expr)                                       \
+    do {                                                    \
+        hipError_t _e = (expr);                             \
+        if (_e != hipSuccess) return ::mot::hip_fail(_e, #expr, __FILE__, __LINE__); \
+    } while (0)
+
+#define MOT_TRY(expr)              \
+    do {                           \
+        int _rc = (expr);          \
+        if (_rc < 0) return _rc;   \
+    } while (0)
+
+namespace mot {
+
+int hip_fail(hipError_t e, const char *what, const char *file, int line);
+void log_msg(const char *fmt, ...);
+
+// ---------------------------------------------------------------------------------------
+// Device memory owned by a plan (through the caller's allocator or hipMalloc).
+struct Arena {
+    mot_allocator alloc{};
+    bool custom = false;
+    std::vector<void *> blocks;
+    size_t bytes = 0;
+    int get(size_t nbytes, void **out);
+    template <class T>
+    int get_n(size_t count, T **out)
+    {
+        void *p = nullptr;
+        int rc = get(count * sizeof(T) + 256, &p);
+        *out = (T *)p;
+        return rc;
+    }
+    void release();
+};
+
+// ---------------------------------------------------------------------------------------
+// Fast-summation parameters resolved for a plan.
+struct NfftParams {
+    int M = 0, n = 0, m = 0, p = 0, T = 0, chunk = 0;
+    double tau = 0, eps_B = 0;
+    double sigma = 0;
+    double s = 0;         // grid cells per unit length
+    double o[3] = {0, 0, 0};
+    int lo[3] = {0, 0, 0}, L[3] = {1, 1, 1}, ntile[3] = {1, 1, 1}, tmin[3] = {0, 0, 0};
+    int W = 0;
+    double kb_b = 0, kb_inv_den = 0, kb_edge = 0;
+    double est_err = 0;   // autotuner's error estimate for one product (relative)
+};
+
+// Bounding box of all points.
+struct Extent {
+    double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0}, ctr[3] = {0, 0, 0};
+    double diag = 0, width_max = 0;
+};
+
+// params.cpp
+int resolve_params(int d, double eta, const Extent &ext, const mot_fastsum_params *fs,
+                   int64_t n_max, NfftParams *out);
+int build_box(int d, const Extent &ext, NfftParams *P);
+void kappa_B_shifted(double eta, double tau, double eps_B, int p, std::vector<double> &q);
+double kappa_R(double r, double eta, double tau, double eps_B, const std::vector<double> &q);
+void kappa_hat_even(int d, int M, double eta, double tau, double eps_B, int p,
+                    std::vector<double> &khat);  // (M+1)^d entries, |k_c| = 0..M
+void build_multiplier(int d, const NfftParams &P, double eta, std::vector<float> &D);
+void build_twiddle(int n, std::vector<float2> &tw);
+double kb_fourier(double k, const NfftParams &P);  // normalised window transform
+
+// ---------------------------------------------------------------------------------------
+// A launch step of a sweep schedule.  Steps reference device job and item arrays owned
+// by the schedule.
+enum StepKind { ST_NODE, ST_DIRECT, ST_SPREAD, ST_FOLD, ST_FFT, ST_INTERP, ST_FINAL, ST_FILL_INT };
+
+struct Step {
+    StepKind kind;
+    int d = 0, n = 0, fft_kind = 0, precision = 0, max_patch = 0;
+    const void *jobs = nullptr;   // device ProdJob / NodeJob / FinalJob array
+    const void *items = nullptr;  // device int2 / int4 array
+    int n_items = 0;
+    const float2 *twiddle = nullptr;
+    int32_t *fill_ptr = nullptr;
+    int32_t fill_value = 0;
+    int64_t fill_count = 0;
+};
+
+int run_steps(const std::vector<Step> &steps, hipStream_t s);
+
+// ---------------------------------------------------------------------------------------
+// Per-marginal device data (binned order).
+struct MargDev {
+    int64_t n = 0;
+    double *pts = nullptr;   // n x d, binned order
+    int32_t *perm = nullptr; // binned position -> original index
+    double *mu = nullptr, *phi = nullptr, *gamma = nullptr, *beta = nullptr;
+    double *down_src = nullptr, *up_src = nullptr, *marg = nullptr;
+    // NFFT layout
+    uint32_t *cell = nullptr;
+    float *frac = nullptr;
+    int32_t *chunk_start = nullptr, *chunk_tile = nullptr, *tile_chunks = nullptr;
+    int nchunks = 0;
+    std::vector<int32_t> h_chunk_tile;
+};
+
+struct Schedule {
+    std::vector<Step> sweep, init_up, marg_pass;
+    Arena *arena = nullptr;
+    hipGraphExec_t graph = nullptr;
+    hipGraph_t graph_def = nullptr;
+    int n_partials = 0;
+    void destroy();
+};
+
+}  // namespace mot
+
+// The opaque plan.
+struct mot_plan_s {
+    int K = 0, d = 0, topology = 0, path = 0, precision = 0;
+    double eta = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int device = 0;
+    mot::Arena arena;
+    std::vector<int64_t> n, off;
+    std::vector<int> parent, depth;
+    std::vector<std::vector<int>> children;
+    int depth_max = 0;
+    mot::Extent ext;
+    mot::NfftParams P;
+    std::vector<mot::MargDev> marg;
+    // product jobs: index 2k = down job of k (gamma_k), 2k+1 = up job of k (beta_k); slot
+    // 2K is the stand-alone product used by mot_apply_kernel
+    std::vector<mot::ProdJob> jobs;
+    mot::ProdJob *jobs_dev = nullptr;
+    int32_t *exp_slots = nullptr;  // [2K + 1]
+    float *D = nullptr;
+    float2 *twiddle = nullptr;
+    // statistics
+    int32_t *sweep_ctr = nullptr, *flag = nullptr, *flag_hist = nullptr, *ticket = nullptr;
+    double *S_hist = nullptr, *err_hist = nullptr;
+    double *s_partial = nullptr, *l1_partial = nullptr;
+    int hist_cap = 0;
+    int host_sweeps = 0;  // sweeps run (host count)
+    mot::Schedule sched;
+    // circle state (circle.hip)
+    void *circle = nullptr;
+    // stand-alone product buffers (lazily sized)
+    double *apply_in = nullptr, *apply_out = nullptr;
+    int64_t apply_cap = 0;
+    float *apply_patches = nullptr;
+    int apply_patch_cap = 0;
+};
+
+namespace mot {
+int tree_build_schedule(mot_plan_s *P);
+int tree_run_sweeps(mot_plan_s *P, int sweeps, bool use_graph);
+int tree_marginals(mot_plan_s *P, double *P_sorted_all);
+int tree_init_up(mot_plan_s *P);
+void prod_items(const std::vector<ProdJob> &jobs_host, const std::vector<int> &job_ids,
+                const std::vector<int> &global_ids, std::vector<Step> &steps, Arena &arena,
+                const void *jobs_dev, const float2 *twiddle_for_n(int n), int &rc);
+int circle_create(mot_plan_s *P, const mot_fastsum_params *fs);
+int circle_run_sweeps(mot_plan_s *P, int sweeps);
+int circle_marginals(mot_plan_s *P, double *P_sorted_all);
+void circle_destroy(mot_plan_s *P);
+size_t circle_footprint(int K, const int64_t *n, int path, int precision);
+const float2 *device_twiddle(int n);
+}  // namespace mot

@@ -1,0 +1,153 @@
+// Direct Gaussian-kernel products (a7), the plain O(n_t n_s) path:
+//   out_i = sum_j v_j exp(-|x_i - y_j|^2 / eta)      (Sec. 5, eq. fastsum-sum)
+//
+// FP64 variant: one target per thread, sources staged through LDS in tiles of 256,
+// accumulated sequentially in ascending source order (the order of the definition).
+//
+// Mixed variant: FP32 transcendental with FP64 accumulation across tiles.  With
+// c = log2(e) / eta and coordinates taken relative to the point cloud's centre,
+//   exp(-|x - y|^2 / eta) = exp2(a_x + a_y + x'.y'),  a_x = -c|x|^2, a_y = -c|y|^2,
+//   y' = 2 c y,
+// so each pair costs d FMAs, one add, one v_exp_f32 and one FMA.  Source values are
+// scaled by 2^-e (e = exponent of max v) so FP32 never under- or overflows; partial sums
+// over 64 sources are added into FP64 accumulators.  Each thread owns R targets to reuse
+// every LDS read R times.  This kernel is bound by the transcendental rate.
+#include "mot_internal.h"
+
+namespace mot {
+
+template <int D>
+__global__ __launch_bounds__(256) void direct_fp64_kernel(const ProdJob *__restrict__ jobs,
+                                                          const int4 *__restrict__ items, int n_items)
+{
+    __shared__ double sy[256 * D];
+    __shared__ double sv[256];
+    const int tid = threadIdx.x;
+    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const int4 itm = items[it];
+        const ProdJob &J = jobs[itm.x];
+        const int64_t i = (int64_t)itm.y + tid;
+        const bool act = i < J.nt;
+        double x[D];
+#pragma unroll
+        for (int c = 0; c < D; ++c) x[c] = act ? J.tgt_pts[i * D + c] : 0.0;
+        const double eta = J.eta;
+        double acc = 0.0;
+        for (int64_t j0 = 0; j0 < J.ns; j0 += 256) {
+            const int nj = (int)min((int64_t)256, J.ns - j0);
+            __syncthreads();
+            if (tid < nj) {
+#pragma unroll
+                for (int c = 0; c < D; ++c) sy[tid * D + c] = J.src_pts[(j0 + tid) * D + c];
+                sv[tid] = J.v[j0 + tid];
+            }
+            __syncthreads();
+            for (int jj = 0; jj < nj; ++jj) {
+                double d2 = 0.0;
+#pragma unroll
+                for (int c = 0; c < D; ++c) {
+                    const double df = x[c] - sy[jj * D + c];
+                    d2 += df * df;
+                }
+                acc += sv[jj] * exp(-d2 / eta);
+            }
+        }
+        if (act) J.out[i] = acc;
+    }
+}
+
+constexpr int kDirectR = 4;
+
+template <int D>
+__global__ __launch_bounds__(256) void direct_mixed_kernel(const ProdJob *__restrict__ jobs,
+                                                           const int4 *__restrict__ items, int n_items)
+{
+    __shared__ float4 sy[256];
+    __shared__ float sv[256];
+    const int tid = threadIdx.x;
+    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const int4 itm = items[it];
+        const ProdJob &J = jobs[itm.x];
+        const double c2 = 1.4426950408889634 / J.eta;  // log2(e) / eta
+        int e = *J.v_exp;
+        if (e == INT32_MIN) e = 0;
+        float xs[kDirectR][3], ax[kDirectR];
+        double acc[kDirectR];
+#pragma unroll
+        for (int r = 0; r < kDirectR; ++r) {
+            const int64_t i = (int64_t)itm.y + tid + 256 * r;
+            double nrm = 0.0;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                double dx = 0.0;
+                if (c < D && i < J.nt) dx = J.tgt_pts[i * D + c] - J.ctr[c];
+                xs[r][c] = (float)dx;
+                nrm += dx * dx;
+            }
+            ax[r] = (float)(-c2 * nrm);
+            acc[r] = 0.0;
+        }
+        for (int64_t j0 = 0; j0 < J.ns; j0 += 256) {
+            const int nj = (int)min((int64_t)256, J.ns - j0);
+            __syncthreads();
+            if (tid < nj) {
+                double dy[3] = {0.0, 0.0, 0.0}, nrm = 0.0;
+#pragma unroll
+                for (int c = 0; c < D; ++c) {
+                    dy[c] = J.src_pts[(j0 + tid) * D + c] - J.ctr[c];
+                    nrm += dy[c] * dy[c];
+                }
+                sy[tid] = make_float4((float)(2.0 * c2 * dy[0]), (float)(2.0 * c2 * dy[1]),
+                                      (float)(2.0 * c2 * dy[2]), (float)(-c2 * nrm));
+                sv[tid] = (float)ldexp(J.v[j0 + tid], -e);
+            }
+            __syncthreads();
+            for (int jb = 0; jb < nj; jb += 64) {
+                const int je = min(nj, jb + 64);
+                float part[kDirectR];
+#pragma unroll
+                for (int r = 0; r < kDirectR; ++r) part[r] = 0.0f;
+                for (int jj = jb; jj < je; ++jj) {
+                    const float4 s = sy[jj];
+                    const float w = sv[jj];
+#pragma unroll
+                    for (int r = 0; r < kDirectR; ++r) {
+                        float arg = ax[r] + s.w;
+                        arg = fmaf(xs[r][0], s.x, arg);
+                        if (D > 1) arg = fmaf(xs[r][1], s.y, arg);
+                        if (D > 2) arg = fmaf(xs[r][2], s.z, arg);
+                        part[r] = fmaf(w, __builtin_amdgcn_exp2f(arg), part[r]);
+                    }
+                }
+#pragma unroll
+                for (int r = 0; r < kDirectR; ++r) acc[r] += (double)part[r];
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < kDirectR; ++r) {
+            const int64_t i = (int64_t)itm.y + tid + 256 * r;
+            if (i < J.nt) J.out[i] = ldexp(acc[r], e);
+        }
+    }
+}
+
+int direct_targets_per_item(int precision) { return precision == MOT_PREC_FP64 ? 256 : 256 * kDirectR; }
+
+hipError_t launch_direct(int d, const ProdJob *jobs_dev, const int4 *items, int n_items,
+                         int precision, hipStream_t s)
+{
+    if (n_items == 0) return hipSuccess;
+    const int grid = n_items < 16384 ? n_items : 16384;
+    if (precision == MOT_PREC_FP64) {
+        if (d == 1) hipLaunchKernelGGL(direct_fp64_kernel<1>, dim3(grid), dim3(256), 0, s, jobs_dev, items, n_items);
+        if (d == 2) hipLaunchKernelGGL(direct_fp64_kernel<2>, dim3(grid), dim3(256), 0, s, jobs_dev, items, n_items);
+        if (d == 3) hipLaunchKernelGGL(direct_fp64_kernel<3>, dim3(grid), dim3(256), 0, s, jobs_dev, items, n_items);
+    } else {
+        if (d == 1) hipLaunchKernelGGL(direct_mixed_kernel<1>, dim3(grid), dim3(256), 0, s, jobs_dev, items, n_items);
+        if (d == 2) hipLaunchKernelGGL(direct_mixed_kernel<2>, dim3(grid), dim3(256), 0, s, jobs_dev, items, n_items);
+        if (d == 3) hipLaunchKernelGGL(direct_mixed_kernel<3>, dim3(grid), dim3(256), 0, s, jobs_dev, items, n_items);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace mot

@@ -1,0 +1,461 @@
+// NFFT fast-summation kernels for gfx950: point binning, window spreading into LDS
+// patches, the deterministic patch fold, and grid-to-point interpolation.
+//
+// Fast summation (Sec. 5, Algorithm 4) evaluates beta = F_t (kappa_hat (.) F*_s v).
+// The adjoint NDFT F*_s is approximated by spreading v onto an oversampled grid of n
+// cells per dimension with a Kaiser-Bessel window followed by an FFT; the NDFT F_t by an
+// inverse FFT followed by interpolation with the same window.  Grid coordinates of a
+// point x are u = x * s + o with s = n / (2 tau) (the 2 tau-periodic kernel becomes
+// n-periodic); each point touches the 2m grid cells l = cell - m + 1 .. cell + m per
+// dimension, cell = floor(u).
+//
+// Work decomposition: points are stable-sorted by tile (T^d cells).  A spreading work
+// item is a chunk of points of one tile; it accumulates into a (T + 2m - 1)^d patch in
+// LDS with LDS atomics, then writes the patch once to global memory.  A fold pass sums
+// the overlapping patches of neighbouring tiles into the box grid in a fixed order --
+// no global atomics, and the grid does not depend on which other jobs share a launch.
+// Interpolation loads a tile's patch of the result grid into LDS and gathers from it.
+#include "mot_internal.h"
+
+namespace mot {
+
+// ---------------------------------------------------------------------------------------
+// Binning
+
+__global__ void bin_cells_kernel(int d, int64_t npts, const double *__restrict__ x, double s0,
+                                 double s1, double s2, double o0, double o1, double o2, int n,
+                                 int T, int32_t *__restrict__ cell, int32_t *__restrict__ tile)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= npts) return;
+    const double sc[3] = {s0, s1, s2}, oc[3] = {o0, o1, o2};
+    int tpd = (n + T - 1) / T;
+    int32_t t = 0;
+    for (int c = 0; c < d; ++c) {
+        // u = x*s + o with both operations rounded separately (no FMA contraction)
+        double u = __dadd_rn(__dmul_rn(x[i * d + c], sc[c]), oc[c]);
+        double f = floor(u);
+        int ci = !(f >= 0.0) ? 0 : (f > (double)(n - 1) ? n - 1 : (int)f);
+        cell[i * d + c] = ci;
+        t = t * tpd + ci / T;
+    }
+    tile[i] = t;
+}
+
+hipError_t launch_bin_cells(int d, int64_t npts, const double *x, double s0, double s1, double s2,
+                            double o0, double o1, double o2, int n, int T, int32_t *cell,
+                            int32_t *tile, hipStream_t st)
+{
+    if (npts == 0) return hipSuccess;
+    int blocks = (int)((npts + 255) / 256);
+    hipLaunchKernelGGL(bin_cells_kernel, dim3(blocks), dim3(256), 0, st, d, npts, x, s0, s1, s2,
+                       o0, o1, o2, n, T, cell, tile);
+    return hipGetLastError();
+}
+
+// Stable sort by tile: bitonic sort of the unique 64-bit keys (tile << 32 | index).
+__global__ void make_keys_kernel(int64_t npts, int64_t npad, const int32_t *__restrict__ tile,
+                                 uint64_t *__restrict__ keys)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= npad) return;
+    keys[i] = i < npts ? (((uint64_t)(uint32_t)tile[i]) << 32) | (uint64_t)i : ~0ull;
+}
+
+// One global compare-exchange step (k, j) of the bitonic network.
+__global__ void bitonic_global_kernel(uint64_t *keys, int64_t npad, int64_t k, int64_t j)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= npad) return;
+    int64_t p = i ^ j;
+    if (p > i) {
+        uint64_t a = keys[i], b = keys[p];
+        bool up = (i & k) == 0;
+        if ((a > b) == up) {
+            keys[i] = b;
+            keys[p] = a;
+        }
+    }
+}
+
+// All steps with j < 1024 of stage k (or the full sort of 1024-element blocks when
+// k_full != 0) inside LDS.
+__global__ __launch_bounds__(512) void bitonic_local_kernel(uint64_t *keys, int64_t npad,
+                                                            int64_t k, int k_full)
+{
+    __shared__ uint64_t sk[1024];
+    int64_t base = (int64_t)blockIdx.x * 1024;
+    for (int t = threadIdx.x; t < 1024; t += blockDim.x) sk[t] = keys[base + t];
+    __syncthreads();
+    int64_t kk0 = k_full ? 2 : k, kk1 = k_full ? 1024 : k;
+    for (int64_t kk = kk0; kk <= kk1; kk <<= 1) {
+        int64_t j0 = k_full ? kk / 2 : 512;
+        for (int64_t j = j0; j > 0; j >>= 1) {
+            for (int t = threadIdx.x; t < 1024; t += blockDim.x) {
+                int p = t ^ (int)j;
+                if (p > t) {
+                    int64_t gi = base + t;
+                    bool up = (gi & kk) == 0;
+                    uint64_t a = sk[t], b = sk[p];
+                    if ((a > b) == up) {
+                        sk[t] = b;
+                        sk[p] = a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int t = threadIdx.x; t < 1024; t += blockDim.x) keys[base + t] = sk[t];
+}
+
+__global__ void keys_to_perm_kernel(int64_t npts, int64_t ntiles, const uint64_t *__restrict__ keys,
+                                    int32_t *__restrict__ perm, int32_t *__restrict__ tile_off)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > npts) return;
+    int64_t t_prev = i == 0 ? -1 : (int64_t)(keys[i - 1] >> 32);
+    int64_t t_cur = i == npts ? ntiles : (int64_t)(keys[i] >> 32);
+    if (i < npts) perm[i] = (int32_t)(keys[i] & 0xffffffffull);
+    for (int64_t t = t_prev + 1; t <= t_cur; ++t) tile_off[t] = (int32_t)i;
+}
+
+size_t stable_tile_sort_scratch(int64_t npts, int64_t /*ntiles*/)
+{
+    int64_t npad = 1024;
+    while (npad < npts) npad <<= 1;
+    return (size_t)npad * sizeof(uint64_t);
+}
+
+hipError_t stable_tile_sort(int64_t npts, const int32_t *tile, int64_t ntiles, int32_t *perm,
+                            int32_t *tile_off, void *scratch, size_t scratch_bytes, hipStream_t st)
+{
+    int64_t npad = 1024;
+    while (npad < npts) npad <<= 1;
+    if (scratch_bytes < (size_t)npad * sizeof(uint64_t)) return hipErrorInvalidValue;
+    uint64_t *keys = (uint64_t *)scratch;
+    int blocks = (int)((npad + 255) / 256);
+    hipLaunchKernelGGL(make_keys_kernel, dim3(blocks), dim3(256), 0, st, npts, npad, tile, keys);
+    int lblocks = (int)(npad / 1024);
+    hipLaunchKernelGGL(bitonic_local_kernel, dim3(lblocks), dim3(512), 0, st, keys, npad,
+                       (int64_t)0, 1);
+    for (int64_t k = 2048; k <= npad; k <<= 1) {
+        for (int64_t j = k / 2; j >= 1024; j >>= 1)
+            hipLaunchKernelGGL(bitonic_global_kernel, dim3(blocks), dim3(256), 0, st, keys, npad,
+                               k, j);
+        hipLaunchKernelGGL(bitonic_local_kernel, dim3(lblocks), dim3(512), 0, st, keys, npad, k, 0);
+    }
+    int pblocks = (int)((npts + 1 + 255) / 256);
+    hipLaunchKernelGGL(keys_to_perm_kernel, dim3(pblocks), dim3(256), 0, st, npts, ntiles, keys,
+                       perm, tile_off);
+    return hipGetLastError();
+}
+
+// Binned layout of sorted points: tile-relative cell (10 bits per dimension) and the
+// fractional offset u - cell as FP32.  u is recomputed with the binning's operations,
+// so the cell is the one the point was sorted by.
+__global__ void point_layout_kernel(int d, int64_t npts, const double *__restrict__ pts, double s0,
+                                    double s1, double s2, double o0, double o1, double o2, int T,
+                                    uint32_t *__restrict__ cellpk, float *__restrict__ frac)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= npts) return;
+    const double sc[3] = {s0, s1, s2}, oc[3] = {o0, o1, o2};
+    uint32_t pk = 0;
+    for (int c = 0; c < d; ++c) {
+        double u = __dadd_rn(__dmul_rn(pts[i * d + c], sc[c]), oc[c]);
+        double f = floor(u);
+        int ci = (int)f;
+        pk |= (uint32_t)(ci % T) << (10 * c);
+        frac[i * d + c] = (float)(u - f);
+    }
+    cellpk[i] = pk;
+}
+
+hipError_t launch_point_layout_s(int d, int64_t npts, const double *pts, const double *s,
+                                 const double *o, int T, uint32_t *cellpk, float *frac,
+                                 hipStream_t st)
+{
+    if (npts == 0) return hipSuccess;
+    int blocks = (int)((npts + 255) / 256);
+    hipLaunchKernelGGL(point_layout_kernel, dim3(blocks), dim3(256), 0, st, d, npts, pts, s[0],
+                       d > 1 ? s[1] : 0.0, d > 2 ? s[2] : 0.0, o[0], d > 1 ? o[1] : 0.0,
+                       d > 2 ? o[2] : 0.0, T, cellpk, frac);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------
+// Kaiser-Bessel window in grid units, normalised to 1 at s = 0:
+//   psi(s) = (m / r) sinh(b r) / sinh(b m),  r = sqrt(m^2 - s^2),  |s| <= m,
+// evaluated as (m / r) exp(b (r - m)) (1 - exp(-2 b r)) / (1 - exp(-2 b m)) with
+// r - m = -s^2 / (r + m), which keeps the central taps accurate to a few FP32 ulps.
+// Its Fourier transform is known in closed form (used on the host for the multiplier).
+__device__ __forceinline__ float kb_window(float s, float m, float b, float inv_den, float edge)
+{
+    const float s2 = s * s;
+    const float r = sqrtf(fmaxf(m * m - s2, 0.0f));
+    if (r < 1e-3f) return edge;
+    const float y = -b * s2 / (r + m);
+    const float t = expf(-2.0f * b * r);
+    return (m / r) * expf(y) * (1.0f - t) * inv_den;
+}
+
+__device__ __forceinline__ int floor_div(int a, int b)  // floor(a / b) for b > 0
+{
+    return a >= 0 ? a / b : -((-a + b - 1) / b);
+}
+
+constexpr int kPtsPerBatch = 64;
+constexpr int kNfftThreads = 256;
+
+// ---------------------------------------------------------------------------------------
+// Spreading (a2): item = (job, chunk of source points).  The patch of the chunk's tile
+// starts at box cell tile * T; a point with tile-relative cell r touches patch cells
+// r + j, j = 0 .. 2m-1, with window argument s = frac + m - 1 - j.
+template <int D>
+__global__ __launch_bounds__(kNfftThreads) void spread_kernel(const ProdJob *__restrict__ jobs,
+                                                              const int2 *__restrict__ items,
+                                                              int n_items)
+{
+    extern __shared__ float patch[];
+    __shared__ float wtab[kPtsPerBatch][D][kMaxTaps];
+    __shared__ int cellr[kPtsPerBatch][D];
+    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const int2 itm = items[it];
+        const ProdJob &J = jobs[itm.x];
+        const int W = J.W, taps = 2 * J.m;
+        int patch_elems = W;
+        for (int c = 1; c < D; ++c) patch_elems *= W;
+        for (int t = threadIdx.x; t < patch_elems; t += blockDim.x) patch[t] = 0.0f;
+        const int p0 = J.src_chunk_start[itm.y], p1 = J.src_chunk_start[itm.y + 1];
+        int e = *J.v_exp;
+        if (e == INT32_MIN) e = 0;
+        const float mf = (float)J.m, b = J.kb_b, idn = J.kb_inv_den, edge = J.kb_edge;
+        __syncthreads();
+        for (int pb = p0; pb < p1; pb += kPtsPerBatch) {
+            const int np = min(kPtsPerBatch, p1 - pb);
+            // window values of every (point, dimension, tap); v folded into dimension 0
+            for (int t = threadIdx.x; t < np * D; t += blockDim.x) {
+                const int p = t / D, c = t - p * D;
+                const int64_t gi = pb + p;
+                const float f = J.src_frac[gi * D + c];
+                const float scale = c == 0 ? (float)ldexp(J.v[gi], -e) : 1.0f;
+                for (int j = 0; j < taps; ++j)
+                    wtab[p][c][j] = scale * kb_window(f + (mf - 1.0f) - (float)j, mf, b, idn, edge);
+                cellr[p][c] = (int)((J.src_cell[gi] >> (10 * c)) & 1023u);
+            }
+            __syncthreads();
+            if constexpr (D == 3) {
+                const int slots = np * taps * taps;
+                for (int sl = threadIdx.x; sl < slots; sl += blockDim.x) {
+                    const int p = sl / (taps * taps);
+                    const int rem = sl - p * taps * taps;
+                    const int j0 = rem / taps, j1 = rem - j0 * taps;
+                    const float s01 = wtab[p][0][j0] * wtab[p][1][j1];
+                    float *dst = patch + ((cellr[p][0] + j0) * W + (cellr[p][1] + j1)) * W + cellr[p][2];
+                    for (int j2 = 0; j2 < taps; ++j2) atomicAdd(dst + j2, s01 * wtab[p][2][j2]);
+                }
+            } else if constexpr (D == 2) {
+                const int slots = np * taps;
+                for (int sl = threadIdx.x; sl < slots; sl += blockDim.x) {
+                    const int p = sl / taps, j0 = sl - p * taps;
+                    const float s0 = wtab[p][0][j0];
+                    float *dst = patch + (cellr[p][0] + j0) * W + cellr[p][1];
+                    for (int j1 = 0; j1 < taps; ++j1) atomicAdd(dst + j1, s0 * wtab[p][1][j1]);
+                }
+            } else {
+                for (int sl = threadIdx.x; sl < np * taps; sl += blockDim.x) {
+                    const int p = sl / taps, j0 = sl - p * taps;
+                    atomicAdd(patch + cellr[p][0] + j0, wtab[p][0][j0]);
+                }
+            }
+            __syncthreads();
+        }
+        float *out = J.patches + (int64_t)itm.y * patch_elems;
+        for (int t = threadIdx.x; t < patch_elems; t += blockDim.x) out[t] = patch[t];
+        __syncthreads();
+    }
+}
+
+// Fold (a2, second half): box grid cell g = sum of the patches covering it, tiles in
+// ascending order and chunks in ascending order within a tile.
+// item = (job, first cell of a run of 256 consecutive box cells).
+template <int D>
+__global__ __launch_bounds__(256) void fold_kernel(const ProdJob *__restrict__ jobs,
+                                                   const int2 *__restrict__ items, int n_items)
+{
+    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const int2 itm = items[it];
+        const ProdJob &J = jobs[itm.x];
+        int64_t total = J.L[0];
+        for (int c = 1; c < D; ++c) total *= J.L[c];
+        const int64_t g = (int64_t)itm.y + threadIdx.x;
+        if (g >= total) continue;
+        int gc[3] = {0, 0, 0};
+        int64_t rem = g;
+        for (int c = D - 1; c >= 0; --c) {
+            gc[c] = (int)(rem % J.L[c]);
+            rem /= J.L[c];
+        }
+        const int W = J.W, T = J.T;
+        int tlo[3] = {0, 0, 0}, thi[3] = {0, 0, 0};
+        for (int c = 0; c < D; ++c) {
+            tlo[c] = max(0, floor_div(gc[c] - W + T, T));  // ceil((g - W + 1) / T)
+            thi[c] = min(J.ntile[c] - 1, gc[c] / T);
+        }
+        int patch_elems = W;
+        for (int c = 1; c < D; ++c) patch_elems *= W;
+        float acc = 0.0f;
+        for (int t0 = tlo[0]; t0 <= thi[0]; ++t0)
+            for (int t1 = tlo[1]; t1 <= thi[1]; ++t1)
+                for (int t2 = tlo[2]; t2 <= thi[2]; ++t2) {
+                    int tl = t0, loc = gc[0] - t0 * T;
+                    if constexpr (D > 1) {
+                        tl = tl * J.ntile[1] + t1;
+                        loc = loc * W + (gc[1] - t1 * T);
+                    }
+                    if constexpr (D > 2) {
+                        tl = tl * J.ntile[2] + t2;
+                        loc = loc * W + (gc[2] - t2 * T);
+                    }
+                    const int c0 = J.src_tile_chunks[tl], c1 = J.src_tile_chunks[tl + 1];
+                    for (int ch = c0; ch < c1; ++ch) acc += J.patches[(int64_t)ch * patch_elems + loc];
+                }
+        J.grid[g] = acc;
+    }
+}
+
+// Interpolation (a6): item = (job, chunk of target points).  out = 2^e * sum of the
+// window-weighted grid values around each point (FP32 sums, FP64 result), where e is the
+// exponent the source vector was scaled by before spreading.
+template <int D>
+__global__ __launch_bounds__(kNfftThreads) void interp_kernel(const ProdJob *__restrict__ jobs,
+                                                              const int2 *__restrict__ items,
+                                                              int n_items)
+{
+    extern __shared__ float patch[];
+    __shared__ float wtab[kPtsPerBatch][D][kMaxTaps];
+    __shared__ int cellr[kPtsPerBatch][D];
+    __shared__ float acc[kPtsPerBatch];
+    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const int2 itm = items[it];
+        const ProdJob &J = jobs[itm.x];
+        const int W = J.W, taps = 2 * J.m, T = J.T;
+        int patch_elems = W;
+        for (int c = 1; c < D; ++c) patch_elems *= W;
+        int tcoord[3] = {0, 0, 0};
+        {
+            int rem = J.tgt_chunk_tile[itm.y];
+            for (int c = D - 1; c >= 0; --c) {
+                tcoord[c] = rem % J.ntile[c];
+                rem /= J.ntile[c];
+            }
+        }
+        for (int t = threadIdx.x; t < patch_elems; t += blockDim.x) {
+            int loc[3] = {0, 0, 0}, rem = t;
+            for (int c = D - 1; c >= 0; --c) {
+                loc[c] = rem % W;
+                rem /= W;
+            }
+            int64_t gidx = tcoord[0] * T + loc[0];
+            for (int c = 1; c < D; ++c) gidx = gidx * J.L[c] + tcoord[c] * T + loc[c];
+            patch[t] = J.grid[gidx];
+        }
+        int e = *J.v_exp;
+        if (e == INT32_MIN) e = 0;
+        const int p0 = J.tgt_chunk_start[itm.y], p1 = J.tgt_chunk_start[itm.y + 1];
+        const float mf = (float)J.m, b = J.kb_b, idn = J.kb_inv_den, edge = J.kb_edge;
+        __syncthreads();
+        for (int pb = p0; pb < p1; pb += kPtsPerBatch) {
+            const int np = min(kPtsPerBatch, p1 - pb);
+            for (int t = threadIdx.x; t < np * D; t += blockDim.x) {
+                const int p = t / D, c = t - p * D;
+                const int64_t gi = pb + p;
+                const float f = J.tgt_frac[gi * D + c];
+                for (int j = 0; j < taps; ++j)
+                    wtab[p][c][j] = kb_window(f + (mf - 1.0f) - (float)j, mf, b, idn, edge);
+                cellr[p][c] = (int)((J.tgt_cell[gi] >> (10 * c)) & 1023u);
+            }
+            for (int t = threadIdx.x; t < np; t += blockDim.x) acc[t] = 0.0f;
+            __syncthreads();
+            const int slots = np * taps;
+            for (int sl = threadIdx.x; sl < slots; sl += blockDim.x) {
+                const int p = sl / taps, j0 = sl - p * taps;
+                float part = 0.0f;
+                if constexpr (D == 3) {
+                    const float *src = patch + ((cellr[p][0] + j0) * W + cellr[p][1]) * W + cellr[p][2];
+                    for (int j1 = 0; j1 < taps; ++j1) {
+                        float row = 0.0f;
+                        for (int j2 = 0; j2 < taps; ++j2) row += src[j1 * W + j2] * wtab[p][2][j2];
+                        part += row * wtab[p][1][j1];
+                    }
+                } else if constexpr (D == 2) {
+                    const float *src = patch + (cellr[p][0] + j0) * W + cellr[p][1];
+                    for (int j1 = 0; j1 < taps; ++j1) part += src[j1] * wtab[p][1][j1];
+                } else {
+                    part = patch[cellr[p][0] + j0];
+                }
+                atomicAdd(&acc[p], part * wtab[p][0][j0]);
+            }
+            __syncthreads();
+            for (int t = threadIdx.x; t < np; t += blockDim.x) J.out[pb + t] = ldexp((double)acc[t], e);
+            __syncthreads();
+        }
+    }
+}
+
+static int nfft_grid(int n_items)
+{
+    return n_items < 4096 ? n_items : 4096;
+}
+
+hipError_t launch_spread(int d, const ProdJob *jobs, const int2 *items, int n_items,
+                         int max_patch_elems, hipStream_t s)
+{
+    if (n_items == 0) return hipSuccess;
+    const size_t lds = (size_t)max_patch_elems * sizeof(float);
+    if (d == 3)
+        hipLaunchKernelGGL(spread_kernel<3>, dim3(nfft_grid(n_items)), dim3(kNfftThreads), lds, s,
+                           jobs, items, n_items);
+    else if (d == 2)
+        hipLaunchKernelGGL(spread_kernel<2>, dim3(nfft_grid(n_items)), dim3(kNfftThreads), lds, s,
+                           jobs, items, n_items);
+    else
+        hipLaunchKernelGGL(spread_kernel<1>, dim3(nfft_grid(n_items)), dim3(kNfftThreads), lds, s,
+                           jobs, items, n_items);
+    return hipGetLastError();
+}
+
+hipError_t launch_fold(int d, const ProdJob *jobs, const int2 *items, int n_items, hipStream_t s)
+{
+    if (n_items == 0) return hipSuccess;
+    if (d == 3)
+        hipLaunchKernelGGL(fold_kernel<3>, dim3(nfft_grid(n_items)), dim3(256), 0, s, jobs, items,
+                           n_items);
+    else if (d == 2)
+        hipLaunchKernelGGL(fold_kernel<2>, dim3(nfft_grid(n_items)), dim3(256), 0, s, jobs, items,
+                           n_items);
+    else
+        hipLaunchKernelGGL(fold_kernel<1>, dim3(nfft_grid(n_items)), dim3(256), 0, s, jobs, items,
+                           n_items);
+    return hipGetLastError();
+}
+
+hipError_t launch_interp(int d, const ProdJob *jobs, const int2 *items, int n_items,
+                         int max_patch_elems, hipStream_t s)
+{
+    if (n_items == 0) return hipSuccess;
+    const size_t lds = (size_t)max_patch_elems * sizeof(float);
+    if (d == 3)
+        hipLaunchKernelGGL(interp_kernel<3>, dim3(nfft_grid(n_items)), dim3(kNfftThreads), lds, s,
+                           jobs, items, n_items);
+    else if (d == 2)
+        hipLaunchKernelGGL(interp_kernel<2>, dim3(nfft_grid(n_items)), dim3(kNfftThreads), lds, s,
+                           jobs, items, n_items);
+    else
+        hipLaunchKernelGGL(interp_kernel<1>, dim3(nfft_grid(n_items)), dim3(kNfftThreads), lds, s,
+                           jobs, items, n_items);
+    return hipGetLastError();
+}
+
+}  // namespace mot

@@ -1,0 +1,306 @@
+// FP64 node updates of the tree sweep (a8, a10) and small utility kernels.
+//
+// Algorithm 2 in terms of per-node elementwise work (cp = prod_{t in C_k} beta_t, the
+// children's messages multiplied in ascending child order starting from 1):
+//   update:    phi^k <- mu^k / (gamma_k * cp)            (gamma_root = 1)
+//              S terms: sum mu^k log phi^k_old, and for the root
+//              sum (mu / phi_new) phi_old (the last term of S^(r))
+//   down src:  u_c = (phi^k * gamma_k) * prod_{t in C_k, t != c} beta_t   for every child c
+//              (the vector whose transposed kernel product gives gamma_c, eq. gamma_tree)
+//   up src:    v_k = phi^k * cp                             (beta_k = K^{(p,k)} v_k)
+//   marginal:  P_k = (phi^k * gamma_k) * cp               (Theorem 4.1), and |P_k - mu^k|
+// Every product vector also records max_i exponent(value) in the job's slot so the
+// product kernels can scale it into FP32 range without loss.
+// Per-item partial sums go to distinct slots (no floating-point atomics): reductions
+// are deterministic.
+#include "mot_internal.h"
+
+namespace mot {
+
+constexpr int kNodeElems = 1024;  // elements per node item (4 per thread)
+constexpr int kRegChildren = 16;  // children held in registers
+
+__device__ __forceinline__ int exp_of(double v)
+{
+    return (v > 0.0 && v < INFINITY) ? ilogb(v) : INT32_MIN;
+}
+
+__device__ __forceinline__ int wave_max_int(int v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = max(v, __shfl_xor(v, o));
+    return v;
+}
+
+__device__ __forceinline__ double block_sum(double v, double *red)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    __syncthreads();
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[w];
+    return s;
+}
+
+__global__ __launch_bounds__(256) void node_kernel(const NodeJob *__restrict__ jobs,
+                                                   const int2 *__restrict__ items, int n_items)
+{
+    __shared__ double red[4];
+    const int tid = threadIdx.x;
+    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const int2 itm = items[it];
+        const NodeJob &J = jobs[itm.x];
+        const int op = J.op;
+        const bool upd = op & 1, dsrc = op & 2, usrc = op & 4, root = op & 8, marg = op & 16;
+        const int nch = J.nchild;
+        const bool regs = nch <= kRegChildren;
+        double s1 = 0.0, s2 = 0.0;
+        int em_up = INT32_MIN;
+        int em[kRegChildren];
+#pragma unroll
+        for (int c = 0; c < kRegChildren; ++c) em[c] = INT32_MIN;
+        bool bad = false;
+        for (int k = 0; k < kNodeElems / 256; ++k) {
+            const int64_t i = (int64_t)itm.y + tid + 256 * k;
+            if (i >= J.n) break;
+            double b[kRegChildren];
+            double cp = 1.0;
+            if (regs) {
+#pragma unroll
+                for (int t = 0; t < kRegChildren; ++t) {
+                    b[t] = t < nch ? J.beta[t][i] : 1.0;
+                    if (t < nch) cp *= b[t];
+                }
+            } else {
+                for (int t = 0; t < nch; ++t) cp *= J.beta[t][i];
+            }
+            const double g = root ? 1.0 : J.gamma[i];
+            const double mu = J.mu[i];
+            double ph = J.phi[i];
+            if (upd) {
+                const double nv = mu / (g * cp);
+                if (mu > 0.0) {
+                    s1 += mu * log(ph);
+                    if (root) s2 += (mu / nv) * ph;
+                }
+                if (!isfinite(nv)) bad = true;
+                J.phi[i] = nv;
+                ph = nv;
+            }
+            if (marg) {
+                const double P = (ph * g) * cp;
+                J.marg_out[i] = P;
+                s1 += fabs(P - mu);
+            }
+            if (usrc) {
+                const double v = ph * cp;
+                J.up_src[i] = v;
+                em_up = max(em_up, exp_of(v));
+            }
+            if (dsrc) {
+                const double pg = ph * g;
+                if (regs) {
+#pragma unroll
+                    for (int c = 0; c < kRegChildren; ++c) {
+                        if (c >= nch) break;
+                        double w = 1.0;
+#pragma unroll
+                        for (int t = 0; t < kRegChildren; ++t)
+                            if (t < nch && t != c) w *= b[t];
+                        const double u = pg * w;
+                        J.down_src[c][i] = u;
+                        em[c] = max(em[c], exp_of(u));
+                    }
+                } else {
+                    for (int c = 0; c < nch; ++c) {
+                        double w = 1.0;
+                        for (int t = 0; t < nch; ++t)
+                            if (t != c) w *= J.beta[t][i];
+                        const double u = pg * w;
+                        J.down_src[c][i] = u;
+                        atomicMax(J.down_exp[c], exp_of(u));
+                    }
+                }
+            }
+        }
+        if (bad) atomicOr(J.flag, 1);
+        if (usrc) {
+            const int m = wave_max_int(em_up);
+            if ((tid & 63) == 0 && m != INT32_MIN) atomicMax(J.up_exp, m);
+        }
+        if (dsrc && regs) {
+#pragma unroll
+            for (int c = 0; c < kRegChildren; ++c) {
+                if (c < nch) {  // nch is uniform over the block
+                    const int m = wave_max_int(em[c]);
+                    if ((tid & 63) == 0 && m != INT32_MIN) atomicMax(J.down_exp[c], m);
+                }
+            }
+        }
+        if (upd || marg) {
+            const double t1 = block_sum(s1, red);
+            const double t2 = block_sum(s2, red);
+            if (tid == 0) {
+                const int slot = J.block0 + (int)(itm.y / kNodeElems);
+                J.partial[2 * slot] = t1;
+                J.partial[2 * slot + 1] = t2;
+            }
+        }
+    }
+}
+
+hipError_t launch_node(const NodeJob *jobs_dev, const int2 *items, int n_items, hipStream_t s)
+{
+    if (n_items == 0) return hipSuccess;
+    const int grid = n_items < 8192 ? n_items : 8192;
+    hipLaunchKernelGGL(node_kernel, dim3(grid), dim3(256), 0, s, jobs_dev, items, n_items);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------
+// Sweep finalisation.  item = (job, first root element).  Computes the root marginal
+// P_0 = phi^0 * prod_{t in C_0} beta_t after the upward pass and its L1 error; the last
+// block of a job (atomic ticket) reduces all partial sums in a fixed order, records
+//   S^(r) = eta * (sum mu log phi_old - sum (mu / phi_new) phi_old)
+// and the error at the plan's sweep counter, and re-arms the exponent slots and the
+// ticket for the next sweep.
+__global__ __launch_bounds__(256) void finalize_kernel(const FinalJob *__restrict__ jobs,
+                                                       const int2 *__restrict__ items, int n_items)
+{
+    __shared__ double red[4];
+    __shared__ int last;
+    const int tid = threadIdx.x;
+    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const int2 itm = items[it];
+        const FinalJob &J = jobs[itm.x];
+        double l1 = 0.0;
+        for (int k = 0; k < kNodeElems / 256; ++k) {
+            const int64_t i = (int64_t)itm.y + tid + 256 * k;
+            if (i >= J.n0) break;
+            double cp = 1.0;
+            for (int t = 0; t < J.nchild; ++t) cp *= J.root_beta[t][i];
+            l1 += fabs(J.phi0[i] * cp - J.mu0[i]);
+        }
+        const double tot = block_sum(l1, red);
+        const int blk = (int)(itm.y / kNodeElems);
+        if (tid == 0) {
+            J.l1_partial[blk] = tot;
+            __threadfence();
+            const int ticket = atomicAdd(J.ticket, 1);
+            last = ticket == J.n_items - 1;
+        }
+        __syncthreads();
+        if (last) {
+            __threadfence();
+            if (tid == 0) {
+                double s1 = 0.0, s2 = 0.0, e1 = 0.0;
+                for (int p = 0; p < J.n_partials; ++p) {
+                    s1 += J.s_partial[2 * p];
+                    s2 += J.s_partial[2 * p + 1];
+                }
+                for (int p = 0; p < J.n_items; ++p) e1 += J.l1_partial[p];
+                const int r = *J.sweep_ctr;
+                const int slot = r % J.hist_cap;
+                J.S_hist[slot] = J.eta * (s1 - s2);
+                J.err_hist[slot] = e1;
+                J.flag_hist[slot] = *J.flag;
+                *J.sweep_ctr = r + 1;
+                *J.ticket = 0;
+            }
+            for (int s = tid; s < J.n_exp_slots; s += blockDim.x) J.exp_slots[s] = INT32_MIN;
+        }
+        __syncthreads();
+    }
+}
+
+hipError_t launch_finalize(const FinalJob *jobs, const int2 *items, int n_items, hipStream_t s)
+{
+    if (n_items == 0) return hipSuccess;
+    hipLaunchKernelGGL(finalize_kernel, dim3(n_items), dim3(256), 0, s, jobs, items, n_items);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------
+// Utilities
+
+__global__ void fill_int_kernel(int32_t *p, int32_t v, int64_t n)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+__global__ void fill_double_kernel(double *p, double v, int64_t n)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+hipError_t launch_fill_int(int32_t *p, int32_t value, int64_t count, hipStream_t s)
+{
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_int_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, p,
+                       value, count);
+    return hipGetLastError();
+}
+hipError_t launch_fill_double(double *p, double value, int64_t count, hipStream_t s)
+{
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_double_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s,
+                       p, value, count);
+    return hipGetLastError();
+}
+
+// dst[i] = src[perm[i]] for rows of d doubles (original -> binned order)
+__global__ void gather_rows_kernel(const double *__restrict__ src, const int32_t *__restrict__ perm,
+                                   int64_t n, int d, double *__restrict__ dst)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t j = perm[i];
+    for (int c = 0; c < d; ++c) dst[i * d + c] = src[j * d + c];
+}
+// dst[perm[i]] = src[i] (binned -> original order)
+__global__ void scatter_vec_kernel(const double *__restrict__ src, const int32_t *__restrict__ perm,
+                                   int64_t n, double *__restrict__ dst)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[perm[i]] = src[i];
+}
+hipError_t launch_gather_rows(const double *src, const int32_t *perm, int64_t n, int d, double *dst,
+                              hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(gather_rows_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, src,
+                       perm, n, d, dst);
+    return hipGetLastError();
+}
+hipError_t launch_scatter_vec(const double *src, const int32_t *perm, int64_t n, double *dst,
+                              hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(scatter_vec_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, src,
+                       perm, n, dst);
+    return hipGetLastError();
+}
+
+// max exponent of a vector into a slot (for products requested outside a sweep)
+__global__ void vec_exp_kernel(const double *__restrict__ v, int64_t n, int32_t *slot)
+{
+    int m = INT32_MIN;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        m = max(m, exp_of(v[i]));
+    m = wave_max_int(m);
+    if ((threadIdx.x & 63) == 0 && m != INT32_MIN) atomicMax(slot, m);
+}
+hipError_t launch_vec_exp(const double *v, int64_t n, int32_t *slot, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    int blocks = (int)((n + 255) / 256);
+    if (blocks > 1024) blocks = 1024;
+    hipLaunchKernelGGL(vec_exp_kernel, dim3(blocks), dim3(256), 0, s, v, n, slot);
+    return hipGetLastError();
+}
+
+}  // namespace mot

@@ -1,0 +1,146 @@
+// Internal declarations of the MI355X multi-marginal Sinkhorn library.
+// Shared by the host-side plan/scheduler code and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/mot.h"
+
+namespace mot {
+
+// ---------------------------------------------------------------------------------------
+// Limits of the kernels.
+constexpr int kMaxD = 3;
+constexpr int kMaxTaps = 16;      // 2m taps per dimension, m <= 8
+constexpr int kMaxN = 512;        // FFT grid per dimension
+constexpr int kMinN = 16;
+constexpr int kMaxChildren = 64;  // children per tree node handled by the node kernels
+
+// ---------------------------------------------------------------------------------------
+// Device-side job descriptors.  Plain structs copied to device memory once per plan
+// (or per batch); kernels read them through an item table of (job, sub-range) pairs.
+
+// One Gaussian-kernel product out = K^{(t,s)} v (eq. fastsum-sum), by direct summation
+// or by NFFT fast summation (Algorithm 4).  Vectors are FP64 in the marginals' binned
+// (sorted) point order.
+struct ProdJob {
+    int32_t d, path, precision, pad0;
+    // vectors
+    const double *v;   // source vector, n_s entries
+    int32_t *v_exp;    // slot holding max_j exponent(|v_j|) (atomicMax), reset per sweep
+    double *out;       // target vector, n_t entries
+    int64_t ns, nt;
+    double eta;
+    double ctr[3];     // centre of the point cloud (mixed direct path works relative to it)
+    // direct path: sorted FP64 coordinates (n x d) of sources and targets
+    const double *src_pts, *tgt_pts;
+    // NFFT path, source and target binned layouts
+    const uint32_t *src_cell, *tgt_cell;  // tile-relative cell coordinates, 10 bits per dim
+    const float *src_frac, *tgt_frac;     // n x d offsets u - cell, in [0, 1]
+    const int32_t *src_chunk_start, *tgt_chunk_start;  // point range of each chunk
+    const int32_t *src_chunk_tile, *tgt_chunk_tile;    // box-relative tile of each chunk
+    const int32_t *src_tile_chunks;       // [ntiles+1] chunk range of each box tile
+    int32_t src_nchunks, tgt_nchunks;
+    // NFFT geometry
+    int32_t n, M, m, T;
+    int32_t L[3];      // active box extent per dimension (grid cells)
+    int32_t lo[3];     // active box first grid index per dimension
+    int32_t ntile[3];  // box tiles per dimension
+    int32_t W;         // patch edge T + 2m - 1
+    float kb_b;        // Kaiser-Bessel shape parameter b = pi (2 - 1/sigma)
+    float kb_inv_den;  // 1 / (1 - exp(-2 b m))
+    float kb_edge;     // window value at |s| = m
+    const float *D;    // multiplier on the half spectrum, layout [A2][A1][2M+1]
+    const float2 *twiddle;  // exp(-2 pi i k / n), k < n/2
+    // NFFT work buffers
+    float *patches;    // src_nchunks * W^d
+    float *grid;       // L0*L1*L2 real (box grid, coordinate 0 slowest)
+    float2 *spec0, *spec1;
+    int64_t spec_elems;
+};
+
+// Node update descriptors for the tree sweep (Algorithm 2), FP64.
+// DOWN: phi^k <- mu^k / (gamma_k (.) prod_{t in C_k} beta_t), S terms, and the
+//       product sources u_c = phi^k (.) gamma_k (.) prod_{t in C_k \ c} beta_t.
+// UP:   v_k = phi^k (.) prod_{t in C_k} beta_t (source of beta_k's product).
+struct NodeJob {
+    int32_t op;          // bit 0: down update, bit 1: down sources, bit 2: up source,
+                         // bit 3: root (gamma = 1, extra S term), bit 4: marginal only
+    int32_t nchild;
+    int64_t n;
+    const double *mu;
+    double *phi;
+    const double *gamma;        // NULL for the root
+    const double *const *beta;  // device array [nchild] of child beta vectors (length n)
+    double *const *down_src;    // device array [nchild] of product source vectors
+    int32_t *const *down_exp;   // device array [nchild] of exponent slots
+    double *up_src;             // source vector of beta_k's product
+    int32_t *up_exp;
+    double *marg_out;           // marginal output (op bit 4)
+    double *partial;            // per-item partial sums, 2 doubles per item
+    int32_t *flag;              // set to 1 if an updated phi is not finite
+    int32_t block0;             // first partial slot of this job
+    int32_t pad;
+};
+
+// Sweep finalisation of one tree plan.
+struct FinalJob {
+    int64_t n0;
+    const double *mu0, *phi0;
+    const double *const *root_beta;  // device array [nchild]
+    int32_t nchild, n_items;         // items of this job in the finalize launch
+    const double *s_partial;         // node partial sums (2 per slot)
+    int32_t n_partials, hist_cap;
+    double *l1_partial;              // [n_items]
+    int32_t *ticket, *sweep_ctr, *flag, *flag_hist;
+    double *S_hist, *err_hist;
+    int32_t *exp_slots;
+    int32_t n_exp_slots, pad;
+    double eta;
+};
+
+// ---------------------------------------------------------------------------------------
+// Kernel launchers (implemented in the .hip files).
+int direct_targets_per_item(int precision);
+hipError_t launch_direct(int d, const ProdJob *jobs_dev, const int4 *items, int n_items,
+                         int precision, hipStream_t s);
+hipError_t launch_node(const NodeJob *jobs_dev, const int2 *items, int n_items, hipStream_t s);
+hipError_t launch_finalize(const FinalJob *jobs, const int2 *items, int n_items, hipStream_t s);
+hipError_t launch_fill_int(int32_t *p, int32_t value, int64_t count, hipStream_t s);
+hipError_t launch_fill_double(double *p, double value, int64_t count, hipStream_t s);
+hipError_t launch_vec_exp(const double *v, int64_t n, int32_t *slot, hipStream_t s);
+hipError_t launch_gather_rows(const double *src, const int32_t *perm, int64_t n, int d, double *dst,
+                              hipStream_t s);
+hipError_t launch_scatter_vec(const double *src, const int32_t *perm, int64_t n, double *dst,
+                              hipStream_t s);
+
+// Binning (a1): cells and tile ids, then a stable sort by tile.
+hipError_t launch_bin_cells(int d, int64_t npts, const double *x, double s0, double s1, double s2,
+                            double o0, double o1, double o2, int n, int T, int32_t *cell,
+                            int32_t *tile, hipStream_t st);
+size_t stable_tile_sort_scratch(int64_t npts, int64_t ntiles);
+hipError_t stable_tile_sort(int64_t npts, const int32_t *tile, int64_t ntiles, int32_t *perm,
+                            int32_t *tile_off, void *scratch, size_t scratch_bytes, hipStream_t st);
+hipError_t launch_point_layout_s(int d, int64_t npts, const double *pts, const double *s,
+                                 const double *o, int T, uint32_t *cellpk, float *frac,
+                                 hipStream_t st);
+
+// NFFT pipeline kernels (a2-a6).
+constexpr int kNodeItemElems = 1024;
+constexpr int kFoldItemCells = 256;
+constexpr int kFftLinesPerItem = 16;
+hipError_t launch_spread(int d, const ProdJob *jobs, const int2 *items, int n_items,
+                         int max_patch_elems, hipStream_t s);
+hipError_t launch_fold(int d, const ProdJob *jobs, const int2 *items, int n_items, hipStream_t s);
+hipError_t launch_interp(int d, const ProdJob *jobs, const int2 *items, int n_items,
+                         int max_patch_elems, hipStream_t s);
+// FFT passes. kind: 0 = R2C along the fastest axis, 1 = forward C2C, 2 = fused
+// forward + multiply + inverse, 3 = inverse C2C, 4 = C2R (with multiply when d == 1).
+hipError_t launch_fft_pass(int kind, int n, const ProdJob *jobs, const int4 *items, int n_items,
+                           const float2 *twiddle, hipStream_t s);
+
+}  // namespace mot

@@ -1,0 +1,1329 @@
+// Plans, the tree sweep scheduler and the C ABI (tree topology; the circle driver lives
+// in circle.hip, batching in batch.cpp, serving in server.cpp).
+//
+// Tree sweeps follow Algorithm 2 level by level.  Algorithm 2 computes gamma_k and
+// phi^k for k = 1..K and then beta_k for k = K..2; gamma_k reads only its parent's new
+// values and the previous sweep's beta, and beta_k reads only its children's new beta,
+// so all nodes at one depth are independent and run in the same launches:
+//   DOWN(0) PROD_DOWN(1) DOWN(1) ... DOWN(D) PROD_UP(D) UP(D-1) PROD_UP(D-1) ... UP(1)
+//   PROD_UP(1) FINAL
+// DOWN(l): phi update of the nodes at depth l and the product sources of their
+// children (and the beta source of leaves); UP(l): beta sources of the inner nodes at
+// depth l; PROD_*: the kernel products of the edges into depth l; FINAL: S^(r) and the
+// first marginal's error.  The sequence is captured once as a HIP graph.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <map>
+#include <mutex>
+
+#include "host.h"
+
+namespace mot {
+
+static bool log_enabled()
+{
+    static int on = -1;
+    if (on < 0) on = getenv("MOT_LOG") ? 1 : 0;
+    return on == 1;
+}
+
+void log_msg(const char *fmt, ...)
+{
+    if (!log_enabled()) return;
+    va_list ap;
+    va_start(ap, fmt);
+    fprintf(stderr, "[mot] ");
+    vfprintf(stderr, fmt, ap);
+    fprintf(stderr, "\n");
+    va_end(ap);
+}
+
+int hip_fail(hipError_t e, const char *what, const char *file, int line)
+{
+    fprintf(stderr, "[mot] HIP error %d (%s) at %s:%d: %s\n", (int)e, hipGetErrorString(e), file,
+            line, what);
+    return e == hipErrorOutOfMemory ? MOT_ENOMEM : MOT_EDEVICE;
+}
+
+int Arena::get(size_t nbytes, void **out)
+{
+    void *p = nullptr;
+    if (nbytes == 0) nbytes = 256;
+    if (custom) {
+        p = alloc.alloc(nbytes, alloc.ctx);
+        if (!p) return MOT_ENOMEM;
+    } else {
+        hipError_t e = hipMalloc(&p, nbytes);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return MOT_ENOMEM;
+        }
+    }
+    blocks.push_back(p);
+    bytes += nbytes;
+    *out = p;
+    return MOT_OK;
+}
+
+void Arena::release()
+{
+    for (void *p : blocks) {
+        if (custom)
+            alloc.free(p, alloc.ctx);
+        else
+            (void)hipFree(p);
+    }
+    blocks.clear();
+    bytes = 0;
+}
+
+void Schedule::destroy()
+{
+    if (graph) (void)hipGraphExecDestroy(graph);
+    if (graph_def) (void)hipGraphDestroy(graph_def);
+    graph = nullptr;
+    graph_def = nullptr;
+    sweep.clear();
+    init_up.clear();
+    marg_pass.clear();
+}
+
+// Twiddle tables exp(-2 pi i k / n), one per (device, n), kept for the process lifetime.
+const float2 *device_twiddle(int n)
+{
+    static std::mutex mu;
+    static std::map<std::pair<int, int>, float2 *> cache;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    std::lock_guard<std::mutex> lk(mu);
+    auto key = std::make_pair(dev, n);
+    auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+    std::vector<float2> tw;
+    build_twiddle(n, tw);
+    float2 *d = nullptr;
+    if (hipMalloc(&d, tw.size() * sizeof(float2)) != hipSuccess) return nullptr;
+    if (hipMemcpy(d, tw.data(), tw.size() * sizeof(float2), hipMemcpyHostToDevice) != hipSuccess)
+        return nullptr;
+    cache[key] = d;
+    return d;
+}
+
+int run_steps(const std::vector<Step> &steps, hipStream_t s)
+{
+    for (const Step &st : steps) {
+        switch (st.kind) {
+        case ST_NODE:
+            MOT_HIP(launch_node((const NodeJob *)st.jobs, (const int2 *)st.items, st.n_items, s));
+            break;
+        case ST_DIRECT:
+            MOT_HIP(launch_direct(st.d, (const ProdJob *)st.jobs, (const int4 *)st.items, st.n_items,
+                                  st.precision, s));
+            break;
+        case ST_SPREAD:
+            MOT_HIP(launch_spread(st.d, (const ProdJob *)st.jobs, (const int2 *)st.items, st.n_items,
+                                  st.max_patch, s));
+            break;
+        case ST_FOLD:
+            MOT_HIP(launch_fold(st.d, (const ProdJob *)st.jobs, (const int2 *)st.items, st.n_items, s));
+            break;
+        case ST_FFT:
+            MOT_HIP(launch_fft_pass(st.fft_kind, st.n, (const ProdJob *)st.jobs, (const int4 *)st.items,
+                                    st.n_items, st.twiddle, s));
+            break;
+        case ST_INTERP:
+            MOT_HIP(launch_interp(st.d, (const ProdJob *)st.jobs, (const int2 *)st.items, st.n_items,
+                                  st.max_patch, s));
+            break;
+        case ST_FINAL:
+            MOT_HIP(launch_finalize((const FinalJob *)st.jobs, (const int2 *)st.items, st.n_items, s));
+            break;
+        case ST_FILL_INT:
+            MOT_HIP(launch_fill_int(st.fill_ptr, st.fill_value, st.fill_count, s));
+            break;
+        }
+    }
+    return MOT_OK;
+}
+
+// ---------------------------------------------------------------------------------------
+// Step construction.
+
+struct StepBuilder {
+    Arena *arena;
+    std::vector<Step> *out;
+    int rc = MOT_OK;
+
+    template <class T>
+    const T *upload(const std::vector<T> &v)
+    {
+        if (rc < 0 || v.empty()) return nullptr;
+        T *d = nullptr;
+        rc = arena->get_n<T>(v.size(), &d);
+        if (rc < 0) return nullptr;
+        if (hipMemcpy(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess)
+            rc = MOT_EDEVICE;
+        return d;
+    }
+
+    void node(const NodeJob *jobs_dev, const std::vector<NodeJob> &host_jobs,
+              const std::vector<int> &ids)
+    {
+        std::vector<int2> items;
+        for (int j : ids)
+            for (int64_t e = 0; e < host_jobs[j].n; e += kNodeItemElems) items.push_back(make_int2(j, (int)e));
+        if (items.empty()) return;
+        Step st{ST_NODE};
+        st.jobs = jobs_dev;
+        st.items = upload(items);
+        st.n_items = (int)items.size();
+        out->push_back(st);
+    }
+
+    void final_(const FinalJob *jobs_dev, const std::vector<FinalJob> &host_jobs)
+    {
+        std::vector<int2> items;
+        for (size_t j = 0; j < host_jobs.size(); ++j)
+            for (int64_t e = 0; e < host_jobs[j].n0; e += kNodeItemElems) items.push_back(make_int2((int)j, (int)e));
+        Step st{ST_FINAL};
+        st.jobs = jobs_dev;
+        st.items = upload(items);
+        st.n_items = (int)items.size();
+        out->push_back(st);
+    }
+
+    static void fft_dims(const ProdJob &J, int kind, int *A2, int *A1)
+    {
+        const int H = J.M + 1, B = 2 * J.M + 1;
+        if (J.d == 3) {
+            const int a2[5] = {J.L[0], H, H, J.L[0], J.L[0]};
+            const int a1[5] = {J.L[1], J.L[0], B, H, J.L[1]};
+            *A2 = a2[kind];
+            *A1 = a1[kind];
+        } else if (J.d == 2) {
+            *A2 = 1;
+            *A1 = kind == 2 ? H : J.L[0];
+        } else {
+            *A2 = 1;
+            *A1 = 1;
+        }
+    }
+
+    // Steps computing every product job in ids (indices into host_jobs / jobs_dev).
+    void products(const ProdJob *jobs_dev, const std::vector<ProdJob> &host_jobs,
+                  const std::vector<int> &ids)
+    {
+        std::map<std::pair<int, int>, std::vector<int4>> direct;  // (d, precision)
+        std::map<int, std::vector<int2>> spread, fold, interp;   // d
+        std::map<std::pair<int, int>, std::vector<int4>> fft[5]; // (d, n) per pass kind
+        std::map<int, int> max_patch;
+        for (int j : ids) {
+            const ProdJob &J = host_jobs[j];
+            if (J.path == MOT_DIRECT) {
+                const int tpi = direct_targets_per_item(J.precision);
+                auto &v = direct[{J.d, J.precision}];
+                for (int64_t t = 0; t < J.nt; t += tpi) v.push_back(make_int4(j, (int)t, 0, 0));
+                continue;
+            }
+            for (int c = 0; c < J.src_nchunks; ++c) spread[J.d].push_back(make_int2(j, c));
+            int64_t cells = 1;
+            for (int c = 0; c < J.d; ++c) cells *= J.L[c];
+            for (int64_t g = 0; g < cells; g += kFoldItemCells) fold[J.d].push_back(make_int2(j, (int)g));
+            for (int c = 0; c < J.tgt_nchunks; ++c) interp[J.d].push_back(make_int2(j, c));
+            int pe = 1;
+            for (int c = 0; c < J.d; ++c) pe *= J.W;
+            max_patch[J.d] = std::max(max_patch[J.d], pe);
+            const int kinds3[5] = {0, 1, 2, 3, 4}, kinds2[3] = {0, 2, 4}, kinds1[2] = {0, 4};
+            const int *kinds = J.d == 3 ? kinds3 : (J.d == 2 ? kinds2 : kinds1);
+            const int nk = J.d == 3 ? 5 : (J.d == 2 ? 3 : 2);
+            for (int q = 0; q < nk; ++q) {
+                int A2, A1;
+                fft_dims(J, kinds[q], &A2, &A1);
+                auto &v = fft[kinds[q]][{J.d, J.n}];
+                for (int a2 = 0; a2 < A2; ++a2)
+                    for (int a1 = 0; a1 < A1; a1 += kFftLinesPerItem) v.push_back(make_int4(j, a2, a1, 0));
+            }
+        }
+        for (auto &kv : direct) {
+            Step st{ST_DIRECT};
+            st.d = kv.first.first;
+            st.precision = kv.first.second;
+            st.jobs = jobs_dev;
+            st.items = upload(kv.second);
+            st.n_items = (int)kv.second.size();
+            out->push_back(st);
+        }
+        for (auto &kv : spread) {
+            Step st{ST_SPREAD};
+            st.d = kv.first;
+            st.max_patch = max_patch[kv.first];
+            st.jobs = jobs_dev;
+            st.items = upload(kv.second);
+            st.n_items = (int)kv.second.size();
+            out->push_back(st);
+        }
+        for (auto &kv : fold) {
+            Step st{ST_FOLD};
+            st.d = kv.first;
+            st.jobs = jobs_dev;
+            st.items = upload(kv.second);
+            st.n_items = (int)kv.second.size();
+            out->push_back(st);
+        }
+        for (int kind = 0; kind < 5; ++kind)
+            for (auto &kv : fft[kind]) {
+                Step st{ST_FFT};
+                st.d = kv.first.first;
+                st.n = kv.first.second;
+                st.fft_kind = kind;
+                st.twiddle = device_twiddle(st.n);
+                if (!st.twiddle) rc = MOT_EDEVICE;
+                st.jobs = jobs_dev;
+                st.items = upload(kv.second);
+                st.n_items = (int)kv.second.size();
+                out->push_back(st);
+            }
+        for (auto &kv : interp) {
+            Step st{ST_INTERP};
+            st.d = kv.first;
+            st.max_patch = max_patch[kv.first];
+            st.jobs = jobs_dev;
+            st.items = upload(kv.second);
+            st.n_items = (int)kv.second.size();
+            out->push_back(st);
+        }
+    }
+};
+
+// ---------------------------------------------------------------------------------------
+// Tree plans
+
+struct TreeNodeJobs {
+    std::vector<NodeJob> down, up, init, marg;
+};
+
+}  // namespace mot
+
+using namespace mot;
+
+// Per-plan host-side job tables (kept with the plan for batching).
+struct TreeTables {
+    std::vector<NodeJob> njobs;  // [0,K) down, [K,2K) up, [2K,3K) init-up, [3K,4K) marginal
+    std::vector<FinalJob> fjob;
+    NodeJob *njobs_dev = nullptr;
+    FinalJob *fjob_dev = nullptr;
+    int n_down_partials = 0, n_marg_partials = 0;
+    std::vector<int> marg_block0;  // first partial slot of each node's marginal job
+};
+
+static std::map<const mot_plan_s *, TreeTables *> &tables_map()
+{
+    static std::map<const mot_plan_s *, TreeTables *> m;
+    return m;
+}
+static std::mutex g_tables_mu;
+
+static TreeTables *tables_of(const mot_plan_s *P)
+{
+    std::lock_guard<std::mutex> lk(g_tables_mu);
+    auto it = tables_map().find(P);
+    return it == tables_map().end() ? nullptr : it->second;
+}
+
+namespace mot {
+
+// Build the per-plan node jobs, the finalize job and the three step sequences.
+int tree_build_schedule(mot_plan_s *P)
+{
+    const int K = P->K;
+    TreeTables *T = new TreeTables();
+    {
+        std::lock_guard<std::mutex> lk(g_tables_mu);
+        tables_map()[P] = T;
+    }
+    T->njobs.resize(4 * K);
+    int slot = 0;
+    // device pointer arrays per node: child betas, child down sources, child exp slots
+    for (int k = 0; k < K; ++k) {
+        const auto &ch = P->children[k];
+        std::vector<const double *> bptr;
+        std::vector<double *> dptr;
+        std::vector<int32_t *> eptr;
+        for (int c : ch) {
+            bptr.push_back(P->marg[c].beta);
+            dptr.push_back(P->marg[c].down_src);
+            eptr.push_back(P->exp_slots + 2 * c);
+        }
+        const double **bdev = nullptr;
+        double **ddev = nullptr;
+        int32_t **edev = nullptr;
+        if (!ch.empty()) {
+            MOT_TRY(P->arena.get_n(ch.size(), &bdev));
+            MOT_TRY(P->arena.get_n(ch.size(), &ddev));
+            MOT_TRY(P->arena.get_n(ch.size(), &edev));
+            MOT_HIP(hipMemcpy(bdev, bptr.data(), ch.size() * sizeof(void *), hipMemcpyHostToDevice));
+            MOT_HIP(hipMemcpy(ddev, dptr.data(), ch.size() * sizeof(void *), hipMemcpyHostToDevice));
+            MOT_HIP(hipMemcpy(edev, eptr.data(), ch.size() * sizeof(void *), hipMemcpyHostToDevice));
+        }
+        NodeJob base{};
+        base.nchild = (int)ch.size();
+        base.n = P->marg[k].n;
+        base.mu = P->marg[k].mu;
+        base.phi = P->marg[k].phi;
+        base.gamma = k == 0 ? nullptr : P->marg[k].gamma;
+        base.beta = bdev;
+        base.down_src = ddev;
+        base.down_exp = edev;
+        base.up_src = P->marg[k].up_src;
+        base.up_exp = P->exp_slots + 2 * k + 1;
+        base.marg_out = P->marg[k].marg;
+        base.partial = P->s_partial;
+        base.flag = P->flag;
+        const int items = (int)((base.n + kNodeItemElems - 1) / kNodeItemElems);
+        // DOWN: update (+ root) + down sources (+ up source for leaves)
+        NodeJob dn = base;
+        dn.op = 1 | (ch.empty() ? 0 : 2) | ((ch.empty() && k > 0) ? 4 : 0) | (k == 0 ? 8 : 0);
+        dn.block0 = slot;
+        slot += items;
+        T->njobs[k] = dn;
+        // UP: beta source of inner non-root nodes
+        NodeJob up = base;
+        up.op = 4;
+        T->njobs[K + k] = up;
+        // INIT: beta source of every non-root node
+        NodeJob in = base;
+        in.op = 4;
+        T->njobs[2 * K + k] = in;
+        T->marg_block0.push_back(0);
+    }
+    T->n_down_partials = slot;
+    for (int k = 0; k < K; ++k) {
+        NodeJob mg = T->njobs[k];
+        mg.op = 16 | (P->children[k].empty() ? 0 : 2) | (k == 0 ? 8 : 0);
+        mg.block0 = slot;
+        T->marg_block0[k] = slot;
+        slot += (int)((mg.n + kNodeItemElems - 1) / kNodeItemElems);
+        T->njobs[3 * K + k] = mg;
+    }
+    T->n_marg_partials = slot - T->n_down_partials;
+    // finalize job
+    {
+        FinalJob F{};
+        F.n0 = P->marg[0].n;
+        F.mu0 = P->marg[0].mu;
+        F.phi0 = P->marg[0].phi;
+        F.root_beta = T->njobs[0].beta;
+        F.nchild = T->njobs[0].nchild;
+        F.n_items = (int)((F.n0 + kNodeItemElems - 1) / kNodeItemElems);
+        F.s_partial = P->s_partial;
+        F.n_partials = T->n_down_partials;
+        F.hist_cap = P->hist_cap;
+        F.l1_partial = P->l1_partial;
+        F.ticket = P->ticket;
+        F.sweep_ctr = P->sweep_ctr;
+        F.flag = P->flag;
+        F.flag_hist = P->flag_hist;
+        F.S_hist = P->S_hist;
+        F.err_hist = P->err_hist;
+        F.exp_slots = P->exp_slots;
+        F.n_exp_slots = 2 * K + 1;
+        F.eta = P->eta;
+        T->fjob.push_back(F);
+    }
+    MOT_TRY(P->arena.get_n(T->njobs.size(), &T->njobs_dev));
+    MOT_HIP(hipMemcpy(T->njobs_dev, T->njobs.data(), T->njobs.size() * sizeof(NodeJob),
+                      hipMemcpyHostToDevice));
+    MOT_TRY(P->arena.get_n(1, &T->fjob_dev));
+    MOT_HIP(hipMemcpy(T->fjob_dev, T->fjob.data(), sizeof(FinalJob), hipMemcpyHostToDevice));
+    return MOT_OK;
+}
+
+// Steps of one sweep / the initial upward pass / the marginal pass for a set of tree
+// plans whose node, product and final jobs are concatenated in the given device
+// arrays (offsets per plan).
+struct TreeRef {
+    mot_plan_s *P;
+    int pbase, nbase, fbase;
+};
+
+int tree_steps(const std::vector<TreeRef> &refs, const std::vector<ProdJob> &pj,
+               const ProdJob *pj_dev, const std::vector<NodeJob> &nj, const NodeJob *nj_dev,
+               const std::vector<FinalJob> &fj, const FinalJob *fj_dev, Arena &arena,
+               std::vector<Step> &sweep, std::vector<Step> &init_up, std::vector<Step> &marg)
+{
+    int maxD = 0;
+    for (auto &r : refs) maxD = std::max(maxD, r.P->depth_max);
+    StepBuilder B{&arena, &sweep};
+    auto nodes_at = [&](int level, int which, bool inner_only, bool nonroot) {
+        std::vector<int> ids;
+        for (auto &r : refs) {
+            const int K = r.P->K;
+            for (int k = 0; k < K; ++k) {
+                if (r.P->depth[k] != level) continue;
+                if (inner_only && r.P->children[k].empty()) continue;
+                if (nonroot && k == 0) continue;
+                ids.push_back(r.nbase + which * K + k);
+            }
+        }
+        return ids;
+    };
+    auto prods_at = [&](int level, int dir) {  // dir 0: down job (gamma_k), 1: up (beta_k)
+        std::vector<int> ids;
+        for (auto &r : refs)
+            for (int k = 1; k < r.P->K; ++k)
+                if (r.P->depth[k] == level) ids.push_back(r.pbase + 2 * k + dir);
+        return ids;
+    };
+    // ---- sweep
+    for (int l = 0; l <= maxD; ++l) {
+        B.node(nj_dev, nj, nodes_at(l, 0, false, false));
+        if (l < maxD) B.products(pj_dev, pj, prods_at(l + 1, 0));
+    }
+    for (int l = maxD; l >= 1; --l) {
+        B.products(pj_dev, pj, prods_at(l, 1));
+        if (l - 1 >= 1) B.node(nj_dev, nj, nodes_at(l - 1, 1, true, true));
+    }
+    B.final_(fj_dev, fj);
+    if (B.rc < 0) return B.rc;
+    // ---- initial upward pass (Algorithm 2, first loop)
+    B.out = &init_up;
+    for (int l = maxD; l >= 1; --l) {
+        B.node(nj_dev, nj, nodes_at(l, 2, false, true));
+        B.products(pj_dev, pj, prods_at(l, 1));
+    }
+    if (B.rc < 0) return B.rc;
+    // ---- marginals: upward pass, then a downward pass that evaluates P_k
+    B.out = &marg;
+    for (int l = maxD; l >= 1; --l) {
+        B.node(nj_dev, nj, nodes_at(l, 2, false, true));
+        B.products(pj_dev, pj, prods_at(l, 1));
+    }
+    for (int l = 0; l <= maxD; ++l) {
+        B.node(nj_dev, nj, nodes_at(l, 3, false, false));
+        if (l < maxD) B.products(pj_dev, pj, prods_at(l + 1, 0));
+    }
+    return B.rc;
+}
+
+}  // namespace mot
+
+// ---------------------------------------------------------------------------------------
+// Plan creation helpers
+
+static int copy_in(const double *src, size_t count, int ptr_kind, std::vector<double> &host)
+{
+    host.resize(count);
+    if (count == 0) return MOT_OK;
+    if (ptr_kind == MOT_DEVICE) {
+        MOT_HIP(hipMemcpy(host.data(), src, count * sizeof(double), hipMemcpyDeviceToHost));
+    } else {
+        memcpy(host.data(), src, count * sizeof(double));
+    }
+    return MOT_OK;
+}
+
+static int validate_common(int K, int d, const int64_t *n, double eta, const std::vector<double> &w,
+                           const std::vector<double> &pts, int64_t total)
+{
+    if (K < 2 || d < 1 || d > 3 || !(eta > 0.0) || !std::isfinite(eta)) return MOT_EINVAL;
+    int64_t off = 0;
+    for (int k = 0; k < K; ++k) {
+        if (n[k] < 1 || n[k] > (int64_t)1 << 30) return MOT_EINVAL;
+        double s = 0.0;
+        for (int64_t i = 0; i < n[k]; ++i) {
+            const double v = w[off + i];
+            if (!(v >= 0.0) || !std::isfinite(v)) return MOT_EINVAL;
+            s += v;
+        }
+        if (std::fabs(s - 1.0) > 1e-9) return MOT_EINVAL;
+        off += n[k];
+    }
+    for (int64_t i = 0; i < total * d; ++i)
+        if (!std::isfinite(pts[i])) return MOT_EINVAL;
+    return MOT_OK;
+}
+
+static Extent extent_of(int d, const std::vector<double> &pts, int64_t total)
+{
+    Extent E;
+    for (int c = 0; c < d; ++c) {
+        E.lo[c] = INFINITY;
+        E.hi[c] = -INFINITY;
+    }
+    for (int64_t i = 0; i < total; ++i)
+        for (int c = 0; c < d; ++c) {
+            E.lo[c] = std::min(E.lo[c], pts[i * d + c]);
+            E.hi[c] = std::max(E.hi[c], pts[i * d + c]);
+        }
+    double s2 = 0.0;
+    for (int c = 0; c < d; ++c) {
+        E.ctr[c] = 0.5 * (E.lo[c] + E.hi[c]);
+        const double w = E.hi[c] - E.lo[c];
+        s2 += w * w;
+        E.width_max = std::max(E.width_max, w);
+    }
+    E.diag = std::sqrt(s2);
+    return E;
+}
+
+// Bin one marginal's points (original order, device) and build its binned layout.
+static int bin_marginal(mot_plan_s *P, int k, const double *pts_orig_dev, void *scratch,
+                        size_t scratch_bytes, int32_t *cell_tmp, int32_t *tile_tmp,
+                        int32_t *tile_off_dev, std::vector<int32_t> &tile_off_host)
+{
+    MargDev &G = P->marg[k];
+    const NfftParams &Q = P->P;
+    const int d = P->d, n = Q.n, T = Q.T;
+    const int tpd = (n + T - 1) / T;
+    int64_t ntiles = 1;
+    for (int c = 0; c < d; ++c) ntiles *= tpd;
+    MOT_HIP(launch_bin_cells(d, G.n, pts_orig_dev, Q.s, Q.s, Q.s, Q.o[0], Q.o[1], Q.o[2], n, T,
+                             cell_tmp, tile_tmp, P->stream));
+    MOT_HIP(stable_tile_sort(G.n, tile_tmp, ntiles, G.perm, tile_off_dev, scratch, scratch_bytes,
+                             P->stream));
+    MOT_HIP(launch_gather_rows(pts_orig_dev, G.perm, G.n, d, G.pts, P->stream));
+    const double sv[3] = {Q.s, Q.s, Q.s};
+    MOT_HIP(launch_point_layout_s(d, G.n, G.pts, sv, Q.o, T, G.cell, G.frac, P->stream));
+    tile_off_host.resize(ntiles + 1);
+    MOT_HIP(hipMemcpyAsync(tile_off_host.data(), tile_off_dev, (ntiles + 1) * sizeof(int32_t),
+                           hipMemcpyDeviceToHost, P->stream));
+    MOT_HIP(hipStreamSynchronize(P->stream));
+    // Chunks over the box tiles in row-major order (coordinate 0 slowest).  Box tiles in
+    // that order are a monotone subsequence of the global tile order the points are
+    // sorted by, and every point lies in a box tile, so consecutive chunks are
+    // consecutive ranges of the sorted points: chunk c = [starts[c], starts[c+1]).
+    int64_t nbox = 1;
+    for (int c = 0; c < d; ++c) nbox *= Q.ntile[c];
+    std::vector<int32_t> starts, tiles, tch2;
+    tch2.push_back(0);
+    int64_t covered = 0;
+    for (int64_t bt = 0; bt < nbox; ++bt) {
+        int64_t rem = bt, gt = 0;
+        int tc[3] = {0, 0, 0};
+        for (int c = d - 1; c >= 0; --c) {
+            tc[c] = (int)(rem % Q.ntile[c]);
+            rem /= Q.ntile[c];
+        }
+        for (int c = 0; c < d; ++c) gt = gt * tpd + (Q.tmin[c] + tc[c]);
+        const int a = tile_off_host[gt], b = tile_off_host[gt + 1];
+        if (a != covered && b > a) return MOT_EDOMAIN;
+        for (int s = a; s < b; s += Q.chunk) {
+            starts.push_back(s);
+            tiles.push_back((int32_t)bt);
+        }
+        covered += b - a;
+        tch2.push_back((int32_t)starts.size());
+    }
+    if (covered != G.n) return MOT_EDOMAIN;  // a point outside the box tiles
+    std::vector<int32_t> bounds = starts;
+    bounds.push_back((int32_t)G.n);
+    G.nchunks = (int)starts.size();
+    G.h_chunk_tile = tiles;
+    MOT_TRY(P->arena.get_n(bounds.size() + 2, &G.chunk_start));
+    MOT_TRY(P->arena.get_n(tiles.size() + 1, &G.chunk_tile));
+    MOT_TRY(P->arena.get_n(tch2.size() + 1, &G.tile_chunks));
+    MOT_HIP(hipMemcpy(G.chunk_start, bounds.data(), bounds.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    MOT_HIP(hipMemcpy(G.chunk_tile, tiles.data(), tiles.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    MOT_HIP(hipMemcpy(G.tile_chunks, tch2.data(), tch2.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    return MOT_OK;
+}
+
+// Fill the product job j: out(target t) = K^{(t,s)} v(source s).
+static int make_prod_job(mot_plan_s *P, int t, int s, const double *v, int32_t *slot, double *out,
+                         ProdJob *J, float *patches, bool alloc_buffers = true)
+{
+    ProdJob &Q = *J;
+    Q = ProdJob{};
+    Q.d = P->d;
+    Q.path = P->path;
+    Q.precision = P->precision;
+    Q.v = v;
+    Q.v_exp = slot;
+    Q.out = out;
+    Q.ns = P->marg[s].n;
+    Q.nt = P->marg[t].n;
+    Q.eta = P->eta;
+    for (int c = 0; c < 3; ++c) Q.ctr[c] = P->ext.ctr[c];
+    Q.src_pts = P->marg[s].pts;
+    Q.tgt_pts = P->marg[t].pts;
+    if (P->path != MOT_NFFT) return MOT_OK;
+    const NfftParams &N = P->P;
+    const MargDev &S = P->marg[s], &Tm = P->marg[t];
+    Q.src_cell = S.cell;
+    Q.tgt_cell = Tm.cell;
+    Q.src_frac = S.frac;
+    Q.tgt_frac = Tm.frac;
+    Q.src_chunk_start = S.chunk_start;
+    Q.tgt_chunk_start = Tm.chunk_start;
+    Q.src_chunk_tile = S.chunk_tile;
+    Q.tgt_chunk_tile = Tm.chunk_tile;
+    Q.src_tile_chunks = S.tile_chunks;
+    Q.src_nchunks = S.nchunks;
+    Q.tgt_nchunks = Tm.nchunks;
+    Q.n = N.n;
+    Q.M = N.M;
+    Q.m = N.m;
+    Q.T = N.T;
+    for (int c = 0; c < 3; ++c) {
+        Q.L[c] = N.L[c];
+        Q.lo[c] = N.lo[c];
+        Q.ntile[c] = N.ntile[c];
+    }
+    Q.W = N.W;
+    Q.kb_b = (float)N.kb_b;
+    Q.kb_inv_den = (float)N.kb_inv_den;
+    Q.kb_edge = (float)N.kb_edge;
+    Q.D = P->D;
+    Q.twiddle = device_twiddle(N.n);
+    int64_t pe = 1, cells = 1;
+    for (int c = 0; c < P->d; ++c) {
+        pe *= N.W;
+        cells *= N.L[c];
+    }
+    const int H = N.M + 1, B = 2 * N.M + 1;
+    int64_t spec = H;
+    if (P->d == 2) spec = (int64_t)H * N.L[0];
+    if (P->d == 3) spec = (int64_t)H * N.L[0] * std::max(N.L[1], B);
+    Q.spec_elems = spec;
+    if (!alloc_buffers) return MOT_OK;
+    if (patches) {
+        Q.patches = patches;
+    } else {
+        MOT_TRY(P->arena.get_n((size_t)S.nchunks * pe, &Q.patches));
+    }
+    MOT_TRY(P->arena.get_n((size_t)cells, &Q.grid));
+    MOT_TRY(P->arena.get_n((size_t)spec, &Q.spec0));
+    MOT_TRY(P->arena.get_n((size_t)spec, &Q.spec1));
+    return MOT_OK;
+}
+
+static int plan_stats_alloc(mot_plan_s *P, int n_partials_hint)
+{
+    P->hist_cap = 1 << 16;
+    MOT_TRY(P->arena.get_n(4, &P->sweep_ctr));
+    MOT_TRY(P->arena.get_n(4, &P->flag));
+    MOT_TRY(P->arena.get_n(4, &P->ticket));
+    MOT_TRY(P->arena.get_n(P->hist_cap, &P->flag_hist));
+    MOT_TRY(P->arena.get_n(P->hist_cap, &P->S_hist));
+    MOT_TRY(P->arena.get_n(P->hist_cap, &P->err_hist));
+    MOT_TRY(P->arena.get_n(2 * (size_t)n_partials_hint + 16, &P->s_partial));
+    MOT_TRY(P->arena.get_n((size_t)n_partials_hint + 16, &P->l1_partial));
+    MOT_HIP(launch_fill_int(P->sweep_ctr, 0, 1, P->stream));
+    MOT_HIP(launch_fill_int(P->flag, 0, 1, P->stream));
+    MOT_HIP(launch_fill_int(P->ticket, 0, 1, P->stream));
+    return MOT_OK;
+}
+
+static int create_tree(mot_plan_s *P, const std::vector<double> &pts_h, const std::vector<double> &w_h,
+                       const mot_fastsum_params *fs)
+{
+    const int K = P->K, d = P->d;
+    // topology: children lists and depths
+    P->children.assign(K, {});
+    P->depth.assign(K, 0);
+    for (int k = 1; k < K; ++k) {
+        P->children[P->parent[k]].push_back(k);
+        P->depth[k] = P->depth[P->parent[k]] + 1;
+        P->depth_max = std::max(P->depth_max, P->depth[k]);
+    }
+    for (int k = 0; k < K; ++k)
+        if ((int)P->children[k].size() > kMaxChildren) return MOT_EUNSUPPORTED;
+    int64_t nmax = 0;
+    for (int k = 0; k < K; ++k) nmax = std::max(nmax, P->n[k]);
+    if (P->path == MOT_NFFT) {
+        MOT_TRY(resolve_params(d, P->eta, P->ext, fs, nmax, &P->P));
+        std::vector<float> D;
+        build_multiplier(d, P->P, P->eta, D);
+        MOT_TRY(P->arena.get_n(D.size(), &P->D));
+        MOT_HIP(hipMemcpy(P->D, D.data(), D.size() * sizeof(float), hipMemcpyHostToDevice));
+        if (!device_twiddle(P->P.n)) return MOT_EDEVICE;
+        log_msg("NFFT params: M=%d n=%d m=%d p=%d tau=%.6g eps_B=%.6g T=%d box=%dx%dx%d est_err=%.3g",
+                P->P.M, P->P.n, P->P.m, P->P.p, P->P.tau, P->P.eps_B, P->P.T, P->P.L[0], P->P.L[1],
+                P->P.L[2], P->P.est_err);
+    }
+    // device inputs (original order) and per-marginal arrays
+    double *pts_dev = nullptr;
+    MOT_TRY(P->arena.get_n(pts_h.size(), &pts_dev));
+    MOT_HIP(hipMemcpy(pts_dev, pts_h.data(), pts_h.size() * sizeof(double), hipMemcpyHostToDevice));
+    P->marg.resize(K);
+    int total_partials = 0;
+    for (int k = 0; k < K; ++k) {
+        MargDev &G = P->marg[k];
+        G.n = P->n[k];
+        MOT_TRY(P->arena.get_n((size_t)G.n * d, &G.pts));
+        MOT_TRY(P->arena.get_n((size_t)G.n, &G.perm));
+        MOT_TRY(P->arena.get_n((size_t)G.n, &G.mu));
+        MOT_TRY(P->arena.get_n((size_t)G.n, &G.phi));
+        MOT_TRY(P->arena.get_n((size_t)G.n, &G.gamma));
+        MOT_TRY(P->arena.get_n((size_t)G.n, &G.up_src));
+        MOT_TRY(P->arena.get_n((size_t)G.n, &G.marg));
+        if (k > 0) {
+            MOT_TRY(P->arena.get_n((size_t)P->n[P->parent[k]], &G.beta));
+            MOT_TRY(P->arena.get_n((size_t)P->n[P->parent[k]], &G.down_src));
+        }
+        if (P->path == MOT_NFFT) {
+            MOT_TRY(P->arena.get_n((size_t)G.n, &G.cell));
+            MOT_TRY(P->arena.get_n((size_t)G.n * d, &G.frac));
+        }
+        total_partials += 2 * (int)((G.n + kNodeItemElems - 1) / kNodeItemElems);
+    }
+    // binning / ordering
+    if (P->path == MOT_NFFT) {
+        const int tpd = (P->P.n + P->P.T - 1) / P->P.T;
+        int64_t ntiles = 1;
+        for (int c = 0; c < d; ++c) ntiles *= tpd;
+        const size_t sb = stable_tile_sort_scratch(nmax, ntiles);
+        void *scratch = nullptr;
+        int32_t *cell_tmp = nullptr, *tile_tmp = nullptr, *toff = nullptr;
+        MOT_TRY(P->arena.get(sb, &scratch));
+        MOT_TRY(P->arena.get_n((size_t)nmax * d, &cell_tmp));
+        MOT_TRY(P->arena.get_n((size_t)nmax, &tile_tmp));
+        MOT_TRY(P->arena.get_n((size_t)ntiles + 1, &toff));
+        std::vector<int32_t> toff_h;
+        for (int k = 0; k < K; ++k)
+            MOT_TRY(bin_marginal(P, k, pts_dev + P->off[k] * d, scratch, sb, cell_tmp, tile_tmp, toff,
+                                 toff_h));
+    } else {
+        for (int k = 0; k < K; ++k) {
+            std::vector<int32_t> id(P->n[k]);
+            for (int64_t i = 0; i < P->n[k]; ++i) id[i] = (int32_t)i;
+            MOT_HIP(hipMemcpy(P->marg[k].perm, id.data(), id.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+            MOT_HIP(hipMemcpy(P->marg[k].pts, pts_h.data() + P->off[k] * d, P->n[k] * d * sizeof(double),
+                              hipMemcpyHostToDevice));
+        }
+    }
+    // weights in binned order, phi = 1
+    double *w_dev = nullptr;
+    MOT_TRY(P->arena.get_n(w_h.size(), &w_dev));
+    MOT_HIP(hipMemcpy(w_dev, w_h.data(), w_h.size() * sizeof(double), hipMemcpyHostToDevice));
+    for (int k = 0; k < K; ++k) {
+        MOT_HIP(launch_gather_rows(w_dev + P->off[k], P->marg[k].perm, P->n[k], 1, P->marg[k].mu, P->stream));
+        MOT_HIP(launch_fill_double(P->marg[k].phi, 1.0, P->n[k], P->stream));
+    }
+    // exponent slots and statistics
+    MOT_TRY(P->arena.get_n(2 * K + 1, &P->exp_slots));
+    MOT_HIP(launch_fill_int(P->exp_slots, INT32_MIN, 2 * K + 1, P->stream));
+    MOT_TRY(plan_stats_alloc(P, total_partials));
+    // product jobs
+    P->jobs.assign(2 * K + 1, ProdJob{});
+    for (int k = 1; k < K; ++k) {
+        const int p = P->parent[k];
+        // down: gamma_k = K^{(k,p)} u_k  (targets k, sources p)
+        MOT_TRY(make_prod_job(P, k, p, P->marg[k].down_src, P->exp_slots + 2 * k, P->marg[k].gamma,
+                              &P->jobs[2 * k], nullptr));
+        // up: beta_k = K^{(p,k)} v_k  (targets p, sources k)
+        MOT_TRY(make_prod_job(P, p, k, P->marg[k].up_src, P->exp_slots + 2 * k + 1, P->marg[k].beta,
+                              &P->jobs[2 * k + 1], nullptr));
+    }
+    MOT_TRY(P->arena.get_n(P->jobs.size(), &P->jobs_dev));
+    MOT_HIP(hipMemcpy(P->jobs_dev, P->jobs.data(), P->jobs.size() * sizeof(ProdJob), hipMemcpyHostToDevice));
+    MOT_TRY(tree_build_schedule(P));
+    TreeTables *T = tables_of(P);
+    std::vector<TreeRef> refs{{P, 0, 0, 0}};
+    MOT_TRY(tree_steps(refs, P->jobs, P->jobs_dev, T->njobs, T->njobs_dev, T->fjob, T->fjob_dev,
+                       P->arena, P->sched.sweep, P->sched.init_up, P->sched.marg_pass));
+    MOT_TRY(run_steps(P->sched.init_up, P->stream));
+    MOT_HIP(launch_fill_int(P->exp_slots, INT32_MIN, 2 * K + 1, P->stream));
+    MOT_HIP(hipStreamSynchronize(P->stream));
+    return MOT_OK;
+}
+
+// ---------------------------------------------------------------------------------------
+// Sweeps
+
+namespace mot {
+
+int tree_run_sweeps(mot_plan_s *P, int sweeps, bool use_graph)
+{
+    if (sweeps <= 0) return MOT_OK;
+    if (use_graph && !P->sched.graph) {
+        hipGraph_t g = nullptr;
+        MOT_HIP(hipStreamBeginCapture(P->stream, hipStreamCaptureModeThreadLocal));
+        int rc = run_steps(P->sched.sweep, P->stream);
+        hipError_t e = hipStreamEndCapture(P->stream, &g);
+        if (rc < 0) return rc;
+        MOT_HIP(e);
+        MOT_HIP(hipGraphInstantiate(&P->sched.graph, g, nullptr, nullptr, 0));
+        P->sched.graph_def = g;
+    }
+    for (int r = 0; r < sweeps; ++r) {
+        if (use_graph) {
+            MOT_HIP(hipGraphLaunch(P->sched.graph, P->stream));
+        } else {
+            MOT_TRY(run_steps(P->sched.sweep, P->stream));
+        }
+    }
+    P->host_sweeps += sweeps;
+    return MOT_OK;
+}
+
+int tree_init_up(mot_plan_s *P)
+{
+    MOT_HIP(launch_fill_int(P->exp_slots, INT32_MIN, 2 * P->K + 1, P->stream));
+    MOT_TRY(run_steps(P->sched.init_up, P->stream));
+    MOT_HIP(launch_fill_int(P->exp_slots, INT32_MIN, 2 * P->K + 1, P->stream));
+    return MOT_OK;
+}
+
+}  // namespace mot
+
+// ---------------------------------------------------------------------------------------
+// C ABI
+
+static bool use_graphs()
+{
+    static int v = -1;
+    if (v < 0) {
+        const char *e = getenv("MOT_NO_GRAPH");
+        v = (e && atoi(e) != 0) ? 0 : 1;
+    }
+    return v == 1;
+}
+
+extern "C" {
+
+const char *mot_strerror(int s)
+{
+    switch (s) {
+    case MOT_OK: return "ok";
+    case MOT_MAXITER: return "sweep limit reached";
+    case MOT_EINVAL: return "invalid argument";
+    case MOT_EDOMAIN: return "fast-summation parameters cannot represent the points";
+    case MOT_ENOMEM: return "out of device memory or admission budget";
+    case MOT_EDEVICE: return "HIP runtime error";
+    case MOT_ENUMERIC: return "a scaling vector became Inf/NaN";
+    case MOT_EUNSUPPORTED: return "unsupported combination of options";
+    default: return "unknown status";
+    }
+}
+
+int mot_plan_destroy(mot_plan P)
+{
+    if (!P) return MOT_EINVAL;
+    if (P->stream) (void)hipStreamSynchronize(P->stream);
+    if (P->circle) circle_destroy(P);
+    P->sched.destroy();
+    {
+        std::lock_guard<std::mutex> lk(g_tables_mu);
+        auto it = tables_map().find(P);
+        if (it != tables_map().end()) {
+            delete it->second;
+            tables_map().erase(it);
+        }
+    }
+    P->arena.release();
+    if (P->own_stream && P->stream) (void)hipStreamDestroy(P->stream);
+    delete P;
+    return MOT_OK;
+}
+
+int mot_plan_create(mot_plan *out, int32_t K, int32_t d, const int64_t *n, const double *points,
+                    const double *weights, int32_t topology, const int32_t *parent, double eta,
+                    int32_t path, int32_t precision, const mot_fastsum_params *fs, int32_t ptr_kind,
+                    void *stream, const mot_allocator *alloc)
+{
+    if (!out) return MOT_EINVAL;
+    *out = nullptr;
+    if (!n || !points || !weights || K < 2 || d < 1 || d > 3) return MOT_EINVAL;
+    if (topology != MOT_TREE && topology != MOT_CIRCLE) return MOT_EINVAL;
+    if (path != MOT_DIRECT && path != MOT_NFFT && path != MOT_DENSE) return MOT_EINVAL;
+    if (path == MOT_DENSE && topology != MOT_CIRCLE) return MOT_EUNSUPPORTED;
+    if (precision == MOT_PREC_FP64 && path != MOT_DIRECT) return MOT_EUNSUPPORTED;
+    if (path == MOT_DIRECT && precision != MOT_PREC_FP64 && precision != MOT_PREC_MIXED)
+        return MOT_EUNSUPPORTED;
+    if (path == MOT_NFFT && precision != MOT_PREC_MIXED) return MOT_EUNSUPPORTED;
+    if (topology == MOT_TREE) {
+        if (!parent || parent[0] != -1) return MOT_EINVAL;
+        for (int k = 1; k < K; ++k)
+            if (parent[k] < 0 || parent[k] >= k) return MOT_EINVAL;
+    } else if (K < 3) {
+        return MOT_EINVAL;
+    }
+    int64_t total = 0;
+    for (int k = 0; k < K; ++k) {
+        if (n[k] < 1) return MOT_EINVAL;
+        total += n[k];
+    }
+    std::vector<double> pts_h, w_h;
+    int rc = copy_in(points, (size_t)total * d, ptr_kind, pts_h);
+    if (rc < 0) return rc;
+    rc = copy_in(weights, (size_t)total, ptr_kind, w_h);
+    if (rc < 0) return rc;
+    rc = validate_common(K, d, n, eta, w_h, pts_h, total);
+    if (rc < 0) return rc;
+
+    mot_plan_s *P = new mot_plan_s();
+    P->K = K;
+    P->d = d;
+    P->topology = topology;
+    P->path = path;
+    P->precision = precision;
+    P->eta = eta;
+    (void)hipGetDevice(&P->device);
+    if (alloc && alloc->alloc && alloc->free) {
+        P->arena.alloc = *alloc;
+        P->arena.custom = true;
+    }
+    if (stream) {
+        P->stream = (hipStream_t)stream;
+    } else {
+        if (hipStreamCreateWithFlags(&P->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete P;
+            return MOT_EDEVICE;
+        }
+        P->own_stream = true;
+    }
+    P->n.assign(n, n + K);
+    P->off.assign(K + 1, 0);
+    for (int k = 0; k < K; ++k) P->off[k + 1] = P->off[k] + n[k];
+    if (topology == MOT_TREE) P->parent.assign(parent, parent + K);
+    P->ext = extent_of(d, pts_h, total);
+    if (topology == MOT_TREE)
+        rc = create_tree(P, pts_h, w_h, fs);
+    else
+        rc = circle_create(P, fs);
+    if (rc < 0) {
+        (void)hipStreamSynchronize(P->stream);
+        mot_plan_destroy(P);
+        return rc;
+    }
+    *out = P;
+    return MOT_OK;
+}
+
+int mot_plan_get_info(mot_plan P, mot_plan_info *info)
+{
+    if (!P || !info) return MOT_EINVAL;
+    mot_plan_info I{};
+    I.K = P->K;
+    I.d = P->d;
+    I.topology = P->topology;
+    I.path = P->path;
+    I.precision = P->precision;
+    I.M = P->P.M;
+    I.n = P->P.n;
+    I.m = P->P.m;
+    I.p = P->P.p;
+    I.tile = P->P.T;
+    I.chunk = P->P.chunk;
+    I.tau = P->P.tau;
+    I.eps_B = P->P.eps_B;
+    I.eta = P->eta;
+    I.scale = P->P.s;
+    for (int c = 0; c < 3; ++c) {
+        I.offset[c] = P->P.o[c];
+        I.box_lo[c] = P->P.lo[c];
+        I.box_len[c] = P->P.L[c];
+    }
+    I.depth = P->depth_max;
+    I.device_bytes = P->arena.bytes;
+    I.products_per_sweep = P->topology == MOT_TREE ? 2 * (P->K - 1) : 2 * (P->K - 2);
+    *info = I;
+    return MOT_OK;
+}
+
+int mot_sinkhorn(mot_plan P, int32_t max_sweeps, double delta_S, double tol_marginal,
+                 int32_t check_every, int32_t *sweeps_done, double *S_last, double *marg_err)
+{
+    if (!P || max_sweeps < 0) return MOT_EINVAL;
+    if (check_every < 1) check_every = 1;
+    const bool stopping = delta_S > 0.0 || tol_marginal > 0.0;
+    int done = 0, status = MOT_MAXITER;
+    int32_t ctr0 = 0;
+    MOT_HIP(hipMemcpyAsync(&ctr0, P->sweep_ctr, 4, hipMemcpyDeviceToHost, P->stream));
+    MOT_HIP(hipStreamSynchronize(P->stream));
+    double lastS = NAN, lastE = NAN;
+    while (done < max_sweeps) {
+        const int batch = stopping ? std::min(check_every, max_sweeps - done) : max_sweeps - done;
+        int rc = P->topology == MOT_TREE ? tree_run_sweeps(P, batch, use_graphs())
+                                         : circle_run_sweeps(P, batch);
+        if (rc < 0) return rc;
+        done += batch;
+        // read the last recorded values
+        const int idx = (ctr0 + done - 1) % P->hist_cap;
+        const int idxp = (ctr0 + done - 2 + P->hist_cap) % P->hist_cap;
+        double h[2] = {0, 0}, e = 0;
+        int32_t fl = 0;
+        MOT_HIP(hipMemcpyAsync(&h[1], P->S_hist + idx, 8, hipMemcpyDeviceToHost, P->stream));
+        MOT_HIP(hipMemcpyAsync(&h[0], P->S_hist + idxp, 8, hipMemcpyDeviceToHost, P->stream));
+        MOT_HIP(hipMemcpyAsync(&e, P->err_hist + idx, 8, hipMemcpyDeviceToHost, P->stream));
+        MOT_HIP(hipMemcpyAsync(&fl, P->flag, 4, hipMemcpyDeviceToHost, P->stream));
+        MOT_HIP(hipStreamSynchronize(P->stream));
+        lastS = h[1];
+        lastE = e;
+        if (fl) {
+            status = MOT_ENUMERIC;
+            break;
+        }
+        if (tol_marginal > 0.0 && e <= tol_marginal) {
+            status = MOT_OK;
+            break;
+        }
+        if (delta_S > 0.0 && (ctr0 + done) >= 2 && std::fabs(h[1] - h[0]) < delta_S) {
+            status = MOT_OK;
+            break;
+        }
+    }
+    if (sweeps_done) *sweeps_done = done;
+    if (S_last) *S_last = lastS;
+    if (marg_err) *marg_err = lastE;
+    return status;
+}
+
+int mot_get_S_history(mot_plan P, double *S_out, int32_t count)
+{
+    if (!P || (!S_out && count > 0)) return MOT_EINVAL;
+    int32_t ctr = 0;
+    MOT_HIP(hipMemcpyAsync(&ctr, P->sweep_ctr, 4, hipMemcpyDeviceToHost, P->stream));
+    MOT_HIP(hipStreamSynchronize(P->stream));
+    const int avail = std::min(ctr, P->hist_cap);
+    const int nout = std::min(avail, (int)count);
+    const int first = ctr - avail;
+    for (int i = 0; i < nout; ++i) {
+        const int slot = (first + i) % P->hist_cap;
+        MOT_HIP(hipMemcpyAsync(S_out + i, P->S_hist + slot, 8, hipMemcpyDeviceToHost, P->stream));
+    }
+    MOT_HIP(hipStreamSynchronize(P->stream));
+    return nout;
+}
+
+static int scatter_out(mot_plan P, double *const *src_sorted, double *dst, int ptr_kind)
+{
+    // binned order -> original order, concatenated
+    double *tmp = nullptr;
+    const int64_t total = P->off[P->K];
+    if (ptr_kind == MOT_DEVICE) {
+        tmp = dst;
+    } else {
+        if (hipMalloc(&tmp, total * sizeof(double)) != hipSuccess) return MOT_ENOMEM;
+    }
+    for (int k = 0; k < P->K; ++k)
+        MOT_HIP(launch_scatter_vec(src_sorted[k], P->marg[k].perm, P->n[k], tmp + P->off[k], P->stream));
+    if (ptr_kind != MOT_DEVICE) {
+        MOT_HIP(hipMemcpyAsync(dst, tmp, total * sizeof(double), hipMemcpyDeviceToHost, P->stream));
+        MOT_HIP(hipStreamSynchronize(P->stream));
+        (void)hipFree(tmp);
+    } else {
+        MOT_HIP(hipStreamSynchronize(P->stream));
+    }
+    return MOT_OK;
+}
+
+int mot_get_scalings(mot_plan P, double *phi_out, int32_t ptr_kind)
+{
+    if (!P || !phi_out) return MOT_EINVAL;
+    std::vector<double *> src(P->K);
+    for (int k = 0; k < P->K; ++k) src[k] = P->marg[k].phi;
+    return scatter_out(P, src.data(), phi_out, ptr_kind);
+}
+
+int mot_set_scalings(mot_plan P, const double *phi_in, int32_t ptr_kind)
+{
+    if (!P || !phi_in) return MOT_EINVAL;
+    const int64_t total = P->off[P->K];
+    double *tmp = nullptr;
+    if (hipMalloc(&tmp, total * sizeof(double)) != hipSuccess) return MOT_ENOMEM;
+    MOT_HIP(hipMemcpyAsync(tmp, phi_in, total * sizeof(double),
+                           ptr_kind == MOT_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                           P->stream));
+    for (int k = 0; k < P->K; ++k)
+        MOT_HIP(launch_gather_rows(tmp + P->off[k], P->marg[k].perm, P->n[k], 1, P->marg[k].phi, P->stream));
+    int rc = MOT_OK;
+    if (P->topology == MOT_TREE) rc = tree_init_up(P);
+    MOT_HIP(hipStreamSynchronize(P->stream));
+    (void)hipFree(tmp);
+    if (rc < 0) return rc;
+    if (P->topology == MOT_CIRCLE) return circle_run_sweeps(P, 0);
+    return MOT_OK;
+}
+
+int mot_marginals(mot_plan P, double *P_out, double *l1_err, int32_t ptr_kind)
+{
+    if (!P) return MOT_EINVAL;
+    if (P->topology == MOT_CIRCLE) {
+        MOT_TRY(circle_marginals(P, nullptr));
+    } else {
+        MOT_HIP(launch_fill_int(P->exp_slots, INT32_MIN, 2 * P->K + 1, P->stream));
+        MOT_TRY(run_steps(P->sched.marg_pass, P->stream));
+        MOT_HIP(launch_fill_int(P->exp_slots, INT32_MIN, 2 * P->K + 1, P->stream));
+        // the marginal pass overwrote beta with values at the current phi (the same
+        // values a following sweep expects), and gamma with consistent values
+    }
+    MOT_HIP(hipStreamSynchronize(P->stream));
+    if (l1_err) {
+        if (P->topology == MOT_TREE) {
+            TreeTables *T = tables_of(P);
+            std::vector<double> part(2 * (size_t)(T->n_down_partials + T->n_marg_partials));
+            MOT_HIP(hipMemcpy(part.data(), P->s_partial, part.size() * sizeof(double), hipMemcpyDeviceToHost));
+            for (int k = 0; k < P->K; ++k) {
+                const int items = (int)((P->n[k] + kNodeItemElems - 1) / kNodeItemElems);
+                double s = 0.0;
+                for (int i = 0; i < items; ++i) s += part[2 * (T->marg_block0[k] + i)];
+                l1_err[k] = s;
+            }
+        } else {
+            std::vector<double> Pm(P->off[P->K]), mu(P->off[P->K]);
+            for (int k = 0; k < P->K; ++k) {
+                MOT_HIP(hipMemcpy(Pm.data() + P->off[k], P->marg[k].marg, P->n[k] * 8, hipMemcpyDeviceToHost));
+                MOT_HIP(hipMemcpy(mu.data() + P->off[k], P->marg[k].mu, P->n[k] * 8, hipMemcpyDeviceToHost));
+                double s = 0.0;
+                for (int64_t i = 0; i < P->n[k]; ++i) s += std::fabs(Pm[P->off[k] + i] - mu[P->off[k] + i]);
+                l1_err[k] = s;
+            }
+        }
+    }
+    if (P_out) {
+        std::vector<double *> src(P->K);
+        for (int k = 0; k < P->K; ++k) src[k] = P->marg[k].marg;
+        MOT_TRY(scatter_out(P, src.data(), P_out, ptr_kind));
+    }
+    return MOT_OK;
+}
+
+int mot_apply_kernel(mot_plan P, int32_t t, int32_t s, const double *v, double *out, int32_t ptr_kind)
+{
+    if (!P || !v || !out || t < 0 || s < 0 || t >= P->K || s >= P->K) return MOT_EINVAL;
+    if (P->topology == MOT_CIRCLE && P->path == MOT_DENSE) return MOT_EUNSUPPORTED;
+    const int64_t cap = *std::max_element(P->n.begin(), P->n.end());
+    if (!P->apply_in) {
+        MOT_TRY(P->arena.get_n((size_t)cap, &P->apply_in));
+        MOT_TRY(P->arena.get_n((size_t)cap, &P->apply_out));
+        P->apply_cap = cap;
+    }
+    // v (original order) -> binned order of s
+    double *tmp = nullptr;
+    if (hipMalloc(&tmp, (P->n[s] + P->n[t]) * sizeof(double)) != hipSuccess) return MOT_ENOMEM;
+    MOT_HIP(hipMemcpyAsync(tmp, v, P->n[s] * sizeof(double),
+                           ptr_kind == MOT_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                           P->stream));
+    MOT_HIP(launch_gather_rows(tmp, P->marg[s].perm, P->n[s], 1, P->apply_in, P->stream));
+    int32_t *slot = P->exp_slots + 2 * P->K;
+    MOT_HIP(launch_fill_int(slot, INT32_MIN, 1, P->stream));
+    MOT_HIP(launch_vec_exp(P->apply_in, P->n[s], slot, P->stream));
+    // job slot 2K: buffers sized for the largest chunk count, allocated on first use
+    ProdJob &slotjob = P->jobs[2 * P->K];
+    if (P->path == MOT_NFFT && !slotjob.grid) {
+        int maxc = 0;
+        for (auto &g : P->marg) maxc = std::max(maxc, g.nchunks);
+        int64_t pe = 1;
+        for (int c = 0; c < P->d; ++c) pe *= P->P.W;
+        MOT_TRY(P->arena.get_n((size_t)maxc * pe, &P->apply_patches));
+        MOT_TRY(make_prod_job(P, t, s, P->apply_in, slot, P->apply_out, &slotjob, P->apply_patches));
+    }
+    ProdJob J;
+    MOT_TRY(make_prod_job(P, t, s, P->apply_in, slot, P->apply_out, &J, nullptr, false));
+    J.patches = P->apply_patches;
+    J.grid = slotjob.grid;
+    J.spec0 = slotjob.spec0;
+    J.spec1 = slotjob.spec1;
+    ProdJob *jd = P->jobs_dev + 2 * P->K;
+    MOT_HIP(hipMemcpyAsync(jd, &J, sizeof(ProdJob), hipMemcpyHostToDevice, P->stream));
+    std::vector<Step> steps;
+    StepBuilder B{&P->arena, &steps};
+    std::vector<ProdJob> hj(2 * P->K + 1);
+    hj[2 * P->K] = J;
+    B.products(P->jobs_dev, hj, {2 * P->K});
+    if (B.rc < 0) return B.rc;
+    MOT_TRY(run_steps(steps, P->stream));
+    MOT_HIP(launch_scatter_vec(P->apply_out, P->marg[t].perm, P->n[t], tmp + P->n[s], P->stream));
+    MOT_HIP(hipMemcpyAsync(out, tmp + P->n[s], P->n[t] * sizeof(double),
+                           ptr_kind == MOT_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                           P->stream));
+    MOT_HIP(hipStreamSynchronize(P->stream));
+    (void)hipFree(tmp);
+    return MOT_OK;
+}
+
+int mot_bin_points(int32_t d, int64_t npts, const double *x, const double *s, const double *o,
+                   int32_t n, int32_t T, int32_t *cell, int32_t *perm, int32_t *tile_off,
+                   int32_t ptr_kind, void *stream)
+{
+    if (d < 1 || d > 3 || npts < 0 || !x || !s || !o || n < 1 || T < 1 || !cell || !perm || !tile_off)
+        return MOT_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    const int tpd = (n + T - 1) / T;
+    int64_t ntiles = 1;
+    for (int c = 0; c < d; ++c) ntiles *= tpd;
+    if (ntiles > ((int64_t)1 << 30)) return MOT_EINVAL;
+    const size_t sb = stable_tile_sort_scratch(npts, ntiles);
+    double *xd = nullptr;
+    int32_t *cd = nullptr, *td = nullptr, *pd = nullptr, *od = nullptr;
+    void *scratch = nullptr;
+    MOT_HIP(hipMalloc(&xd, std::max<int64_t>(npts, 1) * d * sizeof(double)));
+    MOT_HIP(hipMalloc(&cd, std::max<int64_t>(npts, 1) * d * sizeof(int32_t)));
+    MOT_HIP(hipMalloc(&td, std::max<int64_t>(npts, 1) * sizeof(int32_t)));
+    MOT_HIP(hipMalloc(&pd, std::max<int64_t>(npts, 1) * sizeof(int32_t)));
+    MOT_HIP(hipMalloc(&od, (ntiles + 1) * sizeof(int32_t)));
+    MOT_HIP(hipMalloc(&scratch, sb));
+    const hipMemcpyKind kin = ptr_kind == MOT_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    const hipMemcpyKind kout = ptr_kind == MOT_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    if (npts > 0) MOT_HIP(hipMemcpyAsync(xd, x, npts * d * sizeof(double), kin, st));
+    MOT_HIP(launch_bin_cells(d, npts, xd, s[0], d > 1 ? s[1] : 0.0, d > 2 ? s[2] : 0.0, o[0],
+                             d > 1 ? o[1] : 0.0, d > 2 ? o[2] : 0.0, n, T, cd, td, st));
+    MOT_HIP(stable_tile_sort(npts, td, ntiles, pd, od, scratch, sb, st));
+    if (npts > 0) {
+        MOT_HIP(hipMemcpyAsync(cell, cd, npts * d * sizeof(int32_t), kout, st));
+        MOT_HIP(hipMemcpyAsync(perm, pd, npts * sizeof(int32_t), kout, st));
+    }
+    MOT_HIP(hipMemcpyAsync(tile_off, od, (ntiles + 1) * sizeof(int32_t), kout, st));
+    MOT_HIP(hipStreamSynchronize(st));
+    (void)hipFree(xd);
+    (void)hipFree(cd);
+    (void)hipFree(td);
+    (void)hipFree(pd);
+    (void)hipFree(od);
+    (void)hipFree(scratch);
+    return MOT_OK;
+}
+
+int mot_plan_footprint(int32_t K, int32_t d, const int64_t *n, int32_t topology, int32_t path,
+                       int32_t precision, double eta, double half_width,
+                       const mot_fastsum_params *fs, size_t *bytes)
+{
+    if (!n || !bytes || K < 2 || d < 1 || d > 3) return MOT_EINVAL;
+    int64_t total = 0, nmax = 0;
+    for (int k = 0; k < K; ++k) {
+        total += n[k];
+        nmax = std::max(nmax, n[k]);
+    }
+    size_t b = 0;
+    // per point: points, perm, mu, phi, gamma, up/down sources, beta, marginal, layout
+    b += (size_t)total * (8 * d + 4 + 8 * 7 + 4 + 4 * d);
+    if (topology == MOT_CIRCLE) {
+        b += circle_footprint(K, n, path, precision);
+    } else if (path == MOT_NFFT) {
+        Extent E;
+        for (int c = 0; c < d; ++c) {
+            E.lo[c] = -half_width;
+            E.hi[c] = half_width;
+        }
+        E.diag = 2.0 * half_width * std::sqrt((double)d);
+        NfftParams Q;
+        int rc = resolve_params(d, eta, E, fs, nmax, &Q);
+        if (rc < 0) return rc;
+        int64_t cells = 1, pe = 1;
+        for (int c = 0; c < d; ++c) {
+            cells *= Q.L[c];
+            pe *= Q.W;
+        }
+        const int H = Q.M + 1, B = 2 * Q.M + 1;
+        int64_t spec = H;
+        if (d == 2) spec = (int64_t)H * Q.L[0];
+        if (d == 3) spec = (int64_t)H * Q.L[0] * std::max(Q.L[1], B);
+        int64_t tiles = 1;
+        for (int c = 0; c < d; ++c) tiles *= Q.ntile[c];
+        const int64_t chunks = tiles + total / std::max(1, Q.chunk) + K;
+        b += (size_t)(2 * (K - 1) + 1) * (cells * 4 + spec * 16);
+        b += (size_t)2 * chunks * pe * 4;
+        b += (size_t)H * B * B * 4;
+    }
+    b += (size_t)(1 << 16) * 20 + (1 << 20);
+    *bytes = b;
+    return MOT_OK;
+}
+
+}  // extern "C"

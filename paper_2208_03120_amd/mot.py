@@ -1,0 +1,379 @@
+"""Thin ctypes binding of libmot.so (argument marshalling only).
+
+Every computation runs in the library's gfx950 kernels; this module only converts
+Python/numpy/torch arguments into the C ABI of include/mot.h.  PyTorch, when present,
+supplies the HIP stream and (optionally) device memory through its caching allocator.
+The library must be built (``paper_2208_03120_amd.build.build()``); importing this
+module without it raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmot.so")
+
+OK, MAXITER = 0, 1
+EINVAL, EDOMAIN, ENOMEM, EDEVICE, ENUMERIC, EUNSUPPORTED = -1, -2, -3, -4, -6, -7
+TREE, CIRCLE = 0, 1
+DIRECT, NFFT, DENSE = 0, 1, 2
+PREC_FP64, PREC_MIXED, PREC_BF16, PREC_FP16, PREC_BF16X3 = 0, 1, 2, 3, 4
+HOST, DEVICE = 0, 1
+
+
+class MotError(RuntimeError):
+    def __init__(self, status, what=""):
+        self.status = status
+        super().__init__("%s: %s (%d)" % (what, _lib.mot_strerror(status).decode(), status))
+
+
+class FastsumParams(ctypes.Structure):
+    _fields_ = [("M", ctypes.c_int32), ("n", ctypes.c_int32), ("m", ctypes.c_int32),
+                ("p", ctypes.c_int32), ("tau", ctypes.c_double), ("eps_B", ctypes.c_double),
+                ("tile", ctypes.c_int32), ("chunk", ctypes.c_int32),
+                ("target_rel_err", ctypes.c_double)]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("K", ctypes.c_int32), ("d", ctypes.c_int32), ("topology", ctypes.c_int32),
+                ("path", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("M", ctypes.c_int32), ("n", ctypes.c_int32), ("m", ctypes.c_int32),
+                ("p", ctypes.c_int32), ("tile", ctypes.c_int32), ("chunk", ctypes.c_int32),
+                ("tau", ctypes.c_double), ("eps_B", ctypes.c_double), ("eta", ctypes.c_double),
+                ("scale", ctypes.c_double), ("offset", ctypes.c_double * 3),
+                ("box_lo", ctypes.c_int32 * 3), ("box_len", ctypes.c_int32 * 3),
+                ("depth", ctypes.c_int32), ("device_bytes", ctypes.c_size_t),
+                ("products_per_sweep", ctypes.c_int32)]
+
+
+class Allocator(ctypes.Structure):
+    _fields_ = [("alloc", ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)),
+                ("free", ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)),
+                ("ctx", ctypes.c_void_p)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("K", ctypes.c_int32), ("d", ctypes.c_int32), ("topology", ctypes.c_int32),
+                ("n", ctypes.POINTER(ctypes.c_int64)), ("points", ctypes.POINTER(ctypes.c_double)),
+                ("weights", ctypes.POINTER(ctypes.c_double)),
+                ("parent", ctypes.POINTER(ctypes.c_int32)), ("eta", ctypes.c_double),
+                ("path", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("tol_marginal", ctypes.c_double), ("max_sweeps", ctypes.c_int32)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("sweeps", ctypes.c_int32),
+                ("marg_err", ctypes.c_double), ("S_last", ctypes.c_double),
+                ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double),
+                ("t_done", ctypes.c_double)]
+
+
+# names declared in include/mot.h, used by the ABI export test
+EXPORTED = ["mot_plan_create", "mot_sinkhorn", "mot_get_S_history", "mot_marginals",
+            "mot_get_scalings", "mot_set_scalings", "mot_apply_kernel", "mot_plan_get_info",
+            "mot_plan_footprint", "mot_plan_destroy", "mot_strerror", "mot_bin_points",
+            "mot_batch_create", "mot_batch_sinkhorn", "mot_batch_destroy", "mot_server_create",
+            "mot_server_submit", "mot_server_run", "mot_server_fetch", "mot_server_clock",
+            "mot_server_destroy"]
+
+_P = ctypes.POINTER
+_dp = _P(ctypes.c_double)
+_ip = _P(ctypes.c_int32)
+_lp = _P(ctypes.c_int64)
+_vp = ctypes.c_void_p
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libmot.so is not built; run paper_2208_03120_amd.build.build() "
+                          "(hipcc --offload-arch=gfx950)")
+    lib = ctypes.CDLL(LIB_PATH)
+    sig = {
+        "mot_plan_create": (ctypes.c_int, [_P(_vp), ctypes.c_int32, ctypes.c_int32, _lp, _dp, _dp,
+                                           ctypes.c_int32, _ip, ctypes.c_double, ctypes.c_int32,
+                                           ctypes.c_int32, _P(FastsumParams), ctypes.c_int32, _vp,
+                                           _P(Allocator)]),
+        "mot_sinkhorn": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                                        ctypes.c_int32, _ip, _dp, _dp]),
+        "mot_get_S_history": (ctypes.c_int, [_vp, _dp, ctypes.c_int32]),
+        "mot_marginals": (ctypes.c_int, [_vp, _dp, _dp, ctypes.c_int32]),
+        "mot_get_scalings": (ctypes.c_int, [_vp, _dp, ctypes.c_int32]),
+        "mot_set_scalings": (ctypes.c_int, [_vp, _dp, ctypes.c_int32]),
+        "mot_apply_kernel": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32, _dp, _dp,
+                                            ctypes.c_int32]),
+        "mot_plan_get_info": (ctypes.c_int, [_vp, _P(PlanInfo)]),
+        "mot_plan_footprint": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, _lp, ctypes.c_int32,
+                                              ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
+                                              ctypes.c_double, _P(FastsumParams),
+                                              _P(ctypes.c_size_t)]),
+        "mot_plan_destroy": (ctypes.c_int, [_vp]),
+        "mot_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+        "mot_bin_points": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int64, _dp, _dp, _dp,
+                                          ctypes.c_int32, ctypes.c_int32, _ip, _ip, _ip,
+                                          ctypes.c_int32, _vp]),
+        "mot_batch_create": (ctypes.c_int, [_P(_vp), _P(_vp), ctypes.c_int32]),
+        "mot_batch_sinkhorn": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32]),
+        "mot_batch_destroy": (ctypes.c_int, [_vp]),
+        "mot_server_create": (ctypes.c_int, [_P(_vp), ctypes.c_size_t, ctypes.c_int32, _vp]),
+        "mot_server_submit": (ctypes.c_int, [_vp, _P(Request), _P(ctypes.c_uint64)]),
+        "mot_server_run": (ctypes.c_int, [_vp, ctypes.c_double, ctypes.c_int32]),
+        "mot_server_fetch": (ctypes.c_int, [_vp, ctypes.c_uint64, _P(Result), _dp]),
+        "mot_server_clock": (ctypes.c_double, [_vp]),
+        "mot_server_destroy": (ctypes.c_int, [_vp]),
+    }
+    for name, (res, args) in sig.items():
+        if hasattr(lib, name):
+            f = getattr(lib, name)
+            f.restype = res
+            f.argtypes = args
+    return lib
+
+
+_lib = _load()
+
+
+def lib():
+    return _lib
+
+
+def strerror(status):
+    return _lib.mot_strerror(status).decode()
+
+
+def _check(status, what):
+    if status < 0:
+        raise MotError(status, what)
+    return status
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _dptr(a):
+    return a.ctypes.data_as(_dp)
+
+
+def _concat(points, weights):
+    d = int(points[0].shape[1])
+    sizes = np.array([p.shape[0] for p in points], dtype=np.int64)
+    pts = _f64(np.concatenate([np.asarray(p, dtype=np.float64).reshape(-1, d) for p in points]))
+    w = _f64(np.concatenate([np.asarray(x, dtype=np.float64) for x in weights]))
+    return d, sizes, pts, w
+
+
+def _split(cat, sizes):
+    off = np.concatenate([[0], np.cumsum(sizes)])
+    return [cat[off[k]:off[k + 1]].copy() for k in range(len(sizes))]
+
+
+def fastsum_params(M=0, n=0, m=0, p=0, tau=0.0, eps_B=0.0, tile=0, chunk=0, target=0.0):
+    return FastsumParams(M, n, m, p, tau, eps_B, tile, chunk, target)
+
+
+def current_stream():
+    """The current PyTorch HIP stream handle (or None when no GPU is visible)."""
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    except Exception:
+        pass
+    return None
+
+
+class Plan:
+    """One multi-marginal OT problem resident on the GPU (mot_plan_create)."""
+
+    def __init__(self, points, weights, topology=TREE, parent=None, eta=0.1, path=NFFT,
+                 precision=None, fastsum=None, stream=None):
+        if precision is None:
+            precision = PREC_MIXED if path != DENSE else PREC_BF16
+        d, sizes, pts, w = _concat(points, weights)
+        self.sizes = sizes
+        self.K = len(sizes)
+        self.d = d
+        self._h = ctypes.c_void_p()
+        par = None
+        if topology == TREE:
+            par = np.ascontiguousarray(parent, dtype=np.int32)
+        fs = ctypes.byref(fastsum) if fastsum is not None else None
+        st = stream if stream is not None else current_stream()
+        rc = _lib.mot_plan_create(ctypes.byref(self._h), self.K, d, sizes.ctypes.data_as(_lp),
+                                  _dptr(pts), _dptr(w), topology,
+                                  par.ctypes.data_as(_ip) if par is not None else None,
+                                  float(eta), path, precision, fs, HOST, st, None)
+        _check(rc, "mot_plan_create")
+
+    def close(self):
+        if self._h:
+            _lib.mot_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def sinkhorn(self, max_sweeps, delta_S=0.0, tol_marginal=0.0, check_every=1):
+        done = ctypes.c_int32(0)
+        S = ctypes.c_double(0)
+        e = ctypes.c_double(0)
+        rc = _lib.mot_sinkhorn(self._h, int(max_sweeps), float(delta_S), float(tol_marginal),
+                               int(check_every), ctypes.byref(done), ctypes.byref(S),
+                               ctypes.byref(e))
+        _check(rc, "mot_sinkhorn") if rc != ENUMERIC else None
+        return rc, done.value, S.value, e.value
+
+    def S_history(self, count=1 << 16):
+        out = np.zeros(count)
+        n = _check(_lib.mot_get_S_history(self._h, _dptr(out), count), "mot_get_S_history")
+        return out[:n].copy()
+
+    def scalings(self):
+        out = np.zeros(int(self.sizes.sum()))
+        _check(_lib.mot_get_scalings(self._h, _dptr(out), HOST), "mot_get_scalings")
+        return _split(out, self.sizes)
+
+    def set_scalings(self, phi):
+        cat = _f64(np.concatenate(phi))
+        _check(_lib.mot_set_scalings(self._h, _dptr(cat), HOST), "mot_set_scalings")
+
+    def marginals(self):
+        out = np.zeros(int(self.sizes.sum()))
+        l1 = np.zeros(self.K)
+        _check(_lib.mot_marginals(self._h, _dptr(out), _dptr(l1), HOST), "mot_marginals")
+        return _split(out, self.sizes), l1
+
+    def apply(self, t, s, v):
+        v = _f64(v)
+        out = np.zeros(int(self.sizes[t]))
+        _check(_lib.mot_apply_kernel(self._h, int(t), int(s), _dptr(v), _dptr(out), HOST),
+               "mot_apply_kernel")
+        return out
+
+    def info(self):
+        I = PlanInfo()
+        _check(_lib.mot_plan_get_info(self._h, ctypes.byref(I)), "mot_plan_get_info")
+        return {f: (list(getattr(I, f)) if f in ("offset", "box_lo", "box_len") else getattr(I, f))
+                for f, _ in PlanInfo._fields_}
+
+
+def bin_points(x, s, o, n, T, stream=None):
+    """GPU point binning (mot_bin_points): cells, stable tile permutation, tile offsets."""
+    x = _f64(x)
+    npts, d = x.shape
+    s = _f64(np.broadcast_to(np.asarray(s, dtype=np.float64), (d,)))
+    o = _f64(np.broadcast_to(np.asarray(o, dtype=np.float64), (d,)))
+    tpd = (n + T - 1) // T
+    cell = np.zeros((npts, d), dtype=np.int32)
+    perm = np.zeros(npts, dtype=np.int32)
+    toff = np.zeros(tpd ** d + 1, dtype=np.int32)
+    st = stream if stream is not None else current_stream()
+    _check(_lib.mot_bin_points(d, npts, _dptr(x), _dptr(s), _dptr(o), int(n), int(T),
+                               cell.ctypes.data_as(_ip), perm.ctypes.data_as(_ip),
+                               toff.ctypes.data_as(_ip), HOST, st), "mot_bin_points")
+    return cell, perm, toff
+
+
+def footprint(sizes, d, topology, path, precision, eta, half_width=0.25, fastsum=None):
+    sizes = np.ascontiguousarray(sizes, dtype=np.int64)
+    out = ctypes.c_size_t(0)
+    fs = ctypes.byref(fastsum) if fastsum is not None else None
+    _check(_lib.mot_plan_footprint(len(sizes), d, sizes.ctypes.data_as(_lp), topology, path,
+                                   precision, float(eta), float(half_width), fs,
+                                   ctypes.byref(out)), "mot_plan_footprint")
+    return out.value
+
+
+class Batch:
+    """Many tree plans advanced together by shared launches (mot_batch_*)."""
+
+    def __init__(self, plans):
+        self.plans = list(plans)
+        arr = (ctypes.c_void_p * len(self.plans))(*[p.handle.value for p in self.plans])
+        self._h = ctypes.c_void_p()
+        _check(_lib.mot_batch_create(ctypes.byref(self._h), arr, len(self.plans)),
+               "mot_batch_create")
+
+    def sinkhorn(self, sweeps, use_graph=True):
+        return _check(_lib.mot_batch_sinkhorn(self._h, int(sweeps), int(bool(use_graph))),
+                      "mot_batch_sinkhorn")
+
+    def close(self):
+        if self._h:
+            _lib.mot_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous-batching solver service (mot_server_*)."""
+
+    def __init__(self, hbm_budget, max_slots=64, stream=None):
+        self._h = ctypes.c_void_p()
+        st = stream if stream is not None else current_stream()
+        _check(_lib.mot_server_create(ctypes.byref(self._h), int(hbm_budget), int(max_slots), st),
+               "mot_server_create")
+        self._keep = {}
+
+    def submit(self, inst, path=NFFT, precision=None, tol=1e-6, max_sweeps=2000):
+        if precision is None:
+            precision = PREC_MIXED if path != DENSE else PREC_BF16X3
+        d, sizes, pts, w = _concat(inst.points, inst.weights)
+        par = None if inst.parent is None else np.ascontiguousarray(inst.parent, dtype=np.int32)
+        req = Request(len(sizes), d, inst.topology, sizes.ctypes.data_as(_lp), _dptr(pts),
+                      _dptr(w), par.ctypes.data_as(_ip) if par is not None else None,
+                      float(inst.eta), path, precision, float(tol), int(max_sweeps))
+        t = ctypes.c_uint64(0)
+        rc = _lib.mot_server_submit(self._h, ctypes.byref(req), ctypes.byref(t))
+        if rc < 0:
+            return rc, None
+        self._keep[t.value] = sizes
+        return OK, t.value
+
+    def run(self, seconds, idle_exit=True):
+        return _check(_lib.mot_server_run(self._h, float(seconds), int(bool(idle_exit))),
+                      "mot_server_run")
+
+    def fetch(self, ticket, want_phi=False):
+        res = Result()
+        sizes = self._keep.get(ticket)
+        phi = np.zeros(int(sizes.sum())) if (want_phi and sizes is not None) else None
+        rc = _lib.mot_server_fetch(self._h, ctypes.c_uint64(ticket), ctypes.byref(res),
+                                   _dptr(phi) if phi is not None else None)
+        if rc == 1:
+            return None
+        _check(rc, "mot_server_fetch")
+        self._keep.pop(ticket, None)
+        out = {f: getattr(res, f) for f, _ in Result._fields_}
+        if phi is not None:
+            out["phi"] = _split(phi, sizes)
+        return out
+
+    def clock(self):
+        return _lib.mot_server_clock(self._h)
+
+    def close(self):
+        if self._h:
+            _lib.mot_server_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
