@@ -32,6 +32,22 @@ def _compile(src):
     return obj, msgs
 
 
+def _torch_lib_dir():
+    """Directory of PyTorch's bundled HIP runtime.  Linking against it keeps a single
+    HIP runtime in processes that also use PyTorch (two runtimes in one process do
+    not share devices)."""
+    try:
+        import importlib.util
+        spec = importlib.util.find_spec("torch")
+        if spec and spec.origin:
+            d = os.path.join(os.path.dirname(spec.origin), "lib")
+            if os.path.exists(os.path.join(d, "libamdhip64.so")):
+                return d
+    except Exception:
+        pass
+    return None
+
+
 def build(verbose=False) -> str:
     os.makedirs(OBJ, exist_ok=True)
     srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
@@ -41,7 +57,12 @@ def build(verbose=False) -> str:
         if verbose and msgs.strip():
             print(msgs, file=sys.stderr)
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + [o for o, _ in results]
+    tl = _torch_lib_dir()
+    if tl:
+        cmd = (["g++", "-shared", "-fPIC", "-o", tmp] + [o for o, _ in results] +
+               ["-L" + tl, "-l:libamdhip64.so", "-Wl,-rpath," + tl, "-Wl,--no-undefined"])
+    else:
+        cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + [o for o, _ in results]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed:\n" + r.stdout + r.stderr)

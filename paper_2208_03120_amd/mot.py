@@ -87,6 +87,13 @@ _vp = ctypes.c_void_p
 
 
 def _load():
+    # PyTorch bundles its own HIP runtime.  Import it first so that libmot.so binds to
+    # that runtime (same soname) instead of loading a second one, which would leave the
+    # process with two HIP runtimes that do not share devices.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     if not os.path.exists(LIB_PATH):
         raise ImportError("libmot.so is not built; run paper_2208_03120_amd.build.build() "
                           "(hipcc --offload-arch=gfx950)")
