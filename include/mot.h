@@ -71,7 +71,7 @@ extern "C" {
  *          largest distance between points of the two marginals of any edge
  *   eps_B  width of the boundary interval of the regularised kernel
  *   tile   edge (in grid cells) of the binning tiles that spreading/interpolation
- *          work on
+ *          work on; always 17 - 2m (their patches are 16 cells wide), 0 = derive
  *   chunk  maximum points per spreading work item                              */
 typedef struct {
     int32_t M, n, m, p;
@@ -177,6 +177,18 @@ int mot_plan_footprint(int32_t K, int32_t d, const int64_t *n, int32_t topology,
 int mot_plan_destroy(mot_plan plan);
 
 const char *mot_strerror(int status);
+
+/* Per-step device timing of the plan's sweep (tree plans): runs `sweeps` sweeps with a
+ * HIP event pair around every launch of the sweep schedule on the plan's stream and
+ * reports, per schedule position, the kernel kind and the mean duration.  kind:
+ * 0 node update, 1 direct product, 2 spread, 3 fold, 4 FFT pass (fft_kind 0..4),
+ * 5 interpolation, 6 sweep finalisation.  Returns the number of entries written
+ * (<= max_out) or an error.  The sweeps advance the plan like mot_sinkhorn. */
+typedef struct {
+    int32_t kind, d, n, fft_kind, n_items, calls;
+    double ms_mean;
+} mot_step_timing;
+int mot_plan_profile(mot_plan plan, int32_t sweeps, mot_step_timing *out, int32_t max_out);
 
 /* ---- building block: point binning ------------------------------------------------
  * The node ordering the NFFT path uses (not in the paper):

@@ -10,11 +10,13 @@
 // dimension, cell = floor(u).
 //
 // Work decomposition: points are stable-sorted by tile (T^d cells).  A spreading work
-// item is a chunk of points of one tile; it accumulates into a (T + 2m - 1)^d patch in
-// LDS with LDS atomics, then writes the patch once to global memory.  A fold pass sums
-// the overlapping patches of neighbouring tiles into the box grid in a fixed order --
-// no global atomics, and the grid does not depend on which other jobs share a launch.
-// Interpolation loads a tile's patch of the result grid into LDS and gathers from it.
+// item is a chunk of points of one tile; it produces the tile's 16^d patch as a matrix
+// product on the MFMA units and writes it once to global memory.  A fold pass sums the
+// overlapping patches of neighbouring tiles into the box grid in a fixed order -- no
+// atomics anywhere (gfx950 executes LDS float atomics lane by lane, far below LDS
+// read rates), and the grid does not depend on which other jobs share a launch.
+// Interpolation loads a tile's patch of the result grid into LDS and contracts it with
+// the points' windows, again on the MFMA units.
 #include "mot_internal.h"
 
 namespace mot {
@@ -205,75 +207,112 @@ __device__ __forceinline__ int floor_div(int a, int b)  // floor(a / b) for b > 
     return a >= 0 ? a / b : -((-a + b - 1) / b);
 }
 
-constexpr int kPtsPerBatch = 64;
-constexpr int kNfftThreads = 256;
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 // ---------------------------------------------------------------------------------------
-// Spreading (a2): item = (job, chunk of source points).  The patch of the chunk's tile
-// starts at box cell tile * T; a point with tile-relative cell r touches patch cells
-// r + j, j = 0 .. 2m-1, with window argument s = frac + m - 1 - j.
+// Spreading and interpolation as dense tile contractions on FP32 MFMA.
+//
+// A tile holds T = 17 - 2m cells per dimension, so the patch of cells its points touch
+// is exactly 16 wide (T + 2m - 1).  For a point p with tile-relative cell r and
+// fractional offset f, the "shifted window" of dimension c is the 16-vector
+//   w_c[q] = psi(f + m - 1 + r - q)  if 0 <= q - r < 2m,  else 0,
+// so that the point's contribution to patch cell (a, b, c') is v w_0[a] w_1[b] w_2[c'].
+// Spreading a chunk of points is then the contraction
+//   G[a][(b,c')] = sum_p X[a][p] Y[p][(b,c')],   X[a][p] = v_p w_0[a],
+//   Y[p][(b,c')] = w_1[b] w_2[c'],
+// a 16 x 256 x P matrix product done with v_mfma_f32_16x16x4_f32 (4 points per step,
+// 16 output tiles, one per b).  Interpolation contracts the other way:
+//   Z[p][a] = sum_{(b,c')} Y[p][(b,c')] G[a][(b,c')],  beta_p = sum_a w_0[a] Z[p][a].
+// No atomics: each chunk owns its patch (spreading), each point its sum (interpolation).
+// One wavefront per work item; points are taken 16 at a time.
+constexpr int kPatch = 16;
+constexpr int kIS = 260;  // padded LDS row stride of the interpolation patch (16 x 256)
+
 template <int D>
-__global__ __launch_bounds__(kNfftThreads) void spread_kernel(const ProdJob *__restrict__ jobs,
-                                                              const int2 *__restrict__ items,
-                                                              int n_items)
+__device__ __forceinline__ void shifted_windows(const ProdJob &J, const uint32_t *cellpk,
+                                                const float *frac, int64_t pb, int np, float vscale0,
+                                                const double *v, int e, float (*win)[D][kPatch])
 {
-    extern __shared__ float patch[];
-    __shared__ float wtab[kPtsPerBatch][D][kMaxTaps];
-    __shared__ int cellr[kPtsPerBatch][D];
+    const int lane = threadIdx.x;
+    const int taps = 2 * J.m;
+    const float mf = (float)J.m, b = J.kb_b, idn = J.kb_inv_den, edge = J.kb_edge;
+    for (int t = lane; t < 16 * D * kPatch; t += 64) {
+        const int p = t / (D * kPatch), c = (t / kPatch) % D, q = t % kPatch;
+        float w = 0.0f;
+        if (p < np) {
+            const int64_t gi = pb + p;
+            const int r = (int)((cellpk[gi] >> (10 * c)) & 1023u);
+            const int j = q - r;
+            if (j >= 0 && j < taps) {
+                w = kb_window(frac[gi * D + c] + (mf - 1.0f) - (float)j, mf, b, idn, edge);
+                if (c == 0 && v) w *= (float)ldexp(v[gi], -e) * vscale0;
+            }
+        }
+        win[p][c][q] = w;
+    }
+}
+
+template <int D>
+__global__ __launch_bounds__(64) void spread_kernel(const ProdJob *__restrict__ jobs,
+                                                    const int2 *__restrict__ items, int n_items)
+{
+    __shared__ float win[16][D][kPatch];
+    const int l = threadIdx.x, li = l & 15, lk = l >> 4;
     for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
         const int2 itm = items[it];
         const ProdJob &J = jobs[itm.x];
-        const int W = J.W, taps = 2 * J.m;
-        int patch_elems = W;
-        for (int c = 1; c < D; ++c) patch_elems *= W;
-        for (int t = threadIdx.x; t < patch_elems; t += blockDim.x) patch[t] = 0.0f;
         const int p0 = J.src_chunk_start[itm.y], p1 = J.src_chunk_start[itm.y + 1];
         int e = *J.v_exp;
         if (e == INT32_MIN) e = 0;
-        const float mf = (float)J.m, b = J.kb_b, idn = J.kb_inv_den, edge = J.kb_edge;
-        __syncthreads();
-        for (int pb = p0; pb < p1; pb += kPtsPerBatch) {
-            const int np = min(kPtsPerBatch, p1 - pb);
-            // window values of every (point, dimension, tap); v folded into dimension 0
-            for (int t = threadIdx.x; t < np * D; t += blockDim.x) {
-                const int p = t / D, c = t - p * D;
-                const int64_t gi = pb + p;
-                const float f = J.src_frac[gi * D + c];
-                const float scale = c == 0 ? (float)ldexp(J.v[gi], -e) : 1.0f;
-                for (int j = 0; j < taps; ++j)
-                    wtab[p][c][j] = scale * kb_window(f + (mf - 1.0f) - (float)j, mf, b, idn, edge);
-                cellr[p][c] = (int)((J.src_cell[gi] >> (10 * c)) & 1023u);
-            }
+        constexpr int NT = D == 3 ? 16 : 1;
+        f32x4 acc[NT];
+        float acc1 = 0.0f;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+        for (int pb = p0; pb < p1; pb += 16) {
+            const int np = min(16, p1 - pb);
+            shifted_windows<D>(J, J.src_cell, J.src_frac, pb, np, 1.0f, J.v, e, win);
             __syncthreads();
             if constexpr (D == 3) {
-                const int slots = np * taps * taps;
-                for (int sl = threadIdx.x; sl < slots; sl += blockDim.x) {
-                    const int p = sl / (taps * taps);
-                    const int rem = sl - p * taps * taps;
-                    const int j0 = rem / taps, j1 = rem - j0 * taps;
-                    const float s01 = wtab[p][0][j0] * wtab[p][1][j1];
-                    float *dst = patch + ((cellr[p][0] + j0) * W + (cellr[p][1] + j1)) * W + cellr[p][2];
-                    for (int j2 = 0; j2 < taps; ++j2) atomicAdd(dst + j2, s01 * wtab[p][2][j2]);
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    const int pk = 4 * s + lk;
+                    const float x = win[pk][0][li];
+                    const float wz = win[pk][2][li];
+                    float wy[16];
+#pragma unroll
+                    for (int q = 0; q < 16; ++q) wy[q] = win[pk][1][q];
+#pragma unroll
+                    for (int bt = 0; bt < 16; ++bt)
+                        acc[bt] = __builtin_amdgcn_mfma_f32_16x16x4f32(x, wy[bt] * wz, acc[bt], 0, 0, 0);
                 }
             } else if constexpr (D == 2) {
-                const int slots = np * taps;
-                for (int sl = threadIdx.x; sl < slots; sl += blockDim.x) {
-                    const int p = sl / taps, j0 = sl - p * taps;
-                    const float s0 = wtab[p][0][j0];
-                    float *dst = patch + (cellr[p][0] + j0) * W + cellr[p][1];
-                    for (int j1 = 0; j1 < taps; ++j1) atomicAdd(dst + j1, s0 * wtab[p][1][j1]);
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    const int pk = 4 * s + lk;
+                    acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(win[pk][0][li], win[pk][1][li], acc[0],
+                                                                 0, 0, 0);
                 }
             } else {
-                for (int sl = threadIdx.x; sl < np * taps; sl += blockDim.x) {
-                    const int p = sl / taps, j0 = sl - p * taps;
-                    atomicAdd(patch + cellr[p][0] + j0, wtab[p][0][j0]);
-                }
+#pragma unroll
+                for (int s = 0; s < 4; ++s) acc1 += win[4 * s + lk][0][li];
             }
             __syncthreads();
         }
-        float *out = J.patches + (int64_t)itm.y * patch_elems;
-        for (int t = threadIdx.x; t < patch_elems; t += blockDim.x) out[t] = patch[t];
-        __syncthreads();
+        float *out = J.patches + (int64_t)itm.y * (D == 3 ? 4096 : (D == 2 ? 256 : 16));
+        if constexpr (D == 3) {
+#pragma unroll
+            for (int bt = 0; bt < 16; ++bt)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) out[((4 * lk + r) * 16 + bt) * 16 + li] = acc[bt][r];
+        } else if constexpr (D == 2) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) out[(4 * lk + r) * 16 + li] = acc[0][r];
+        } else {
+            acc1 += __shfl_xor(acc1, 16);
+            acc1 += __shfl_xor(acc1, 32);
+            if (lk == 0) out[li] = acc1;
+        }
     }
 }
 
@@ -325,80 +364,88 @@ __global__ __launch_bounds__(256) void fold_kernel(const ProdJob *__restrict__ j
     }
 }
 
-// Interpolation (a6): item = (job, chunk of target points).  out = 2^e * sum of the
-// window-weighted grid values around each point (FP32 sums, FP64 result), where e is the
-// exponent the source vector was scaled by before spreading.
+// Interpolation (a6): item = (job, chunk of target points).  out = 2^e * beta with beta
+// the window-weighted sum of the grid around each point (FP32, written as FP64), where e
+// is the exponent the source vector was scaled by before spreading.
 template <int D>
-__global__ __launch_bounds__(kNfftThreads) void interp_kernel(const ProdJob *__restrict__ jobs,
-                                                              const int2 *__restrict__ items,
-                                                              int n_items)
+__global__ __launch_bounds__(64) void interp_kernel(const ProdJob *__restrict__ jobs,
+                                                    const int2 *__restrict__ items, int n_items)
 {
-    extern __shared__ float patch[];
-    __shared__ float wtab[kPtsPerBatch][D][kMaxTaps];
-    __shared__ int cellr[kPtsPerBatch][D];
-    __shared__ float acc[kPtsPerBatch];
+    constexpr int RS = D == 3 ? kIS : (D == 2 ? 17 : 16);  // padded row stride of G[a][...]
+    __shared__ float G[16 * RS];
+    __shared__ float win[16][D][kPatch];
+    const int l = threadIdx.x, li = l & 15, lk = l >> 4;
     for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
         const int2 itm = items[it];
         const ProdJob &J = jobs[itm.x];
-        const int W = J.W, taps = 2 * J.m, T = J.T;
-        int patch_elems = W;
-        for (int c = 1; c < D; ++c) patch_elems *= W;
-        int tcoord[3] = {0, 0, 0};
+        const int T = J.T;
+        int tc[3] = {0, 0, 0};
         {
             int rem = J.tgt_chunk_tile[itm.y];
             for (int c = D - 1; c >= 0; --c) {
-                tcoord[c] = rem % J.ntile[c];
+                tc[c] = rem % J.ntile[c];
                 rem /= J.ntile[c];
             }
         }
-        for (int t = threadIdx.x; t < patch_elems; t += blockDim.x) {
-            int loc[3] = {0, 0, 0}, rem = t;
-            for (int c = D - 1; c >= 0; --c) {
-                loc[c] = rem % W;
-                rem /= W;
-            }
-            int64_t gidx = tcoord[0] * T + loc[0];
-            for (int c = 1; c < D; ++c) gidx = gidx * J.L[c] + tcoord[c] * T + loc[c];
-            patch[t] = J.grid[gidx];
+        // patch of the result grid: box cells tile * T + (0..15) per dimension
+        constexpr int PE = D == 3 ? 4096 : (D == 2 ? 256 : 16);
+        for (int t = l; t < PE; t += 64) {
+            const int a = D == 1 ? t : (D == 2 ? t / 16 : t / 256);
+            const int bb = D == 2 ? t % 16 : (t / 16) % 16;
+            const int cc = t % 16;
+            int64_t gidx = tc[0] * T + a;
+            if (D >= 2) gidx = gidx * J.L[1] + tc[1] * T + (D == 2 ? bb : bb);
+            if (D == 3) gidx = gidx * J.L[2] + tc[2] * T + cc;
+            const int loc = D == 3 ? a * RS + bb * 16 + cc : (D == 2 ? a * RS + bb : a);
+            G[loc] = J.grid[gidx];
         }
         int e = *J.v_exp;
         if (e == INT32_MIN) e = 0;
         const int p0 = J.tgt_chunk_start[itm.y], p1 = J.tgt_chunk_start[itm.y + 1];
-        const float mf = (float)J.m, b = J.kb_b, idn = J.kb_inv_den, edge = J.kb_edge;
         __syncthreads();
-        for (int pb = p0; pb < p1; pb += kPtsPerBatch) {
-            const int np = min(kPtsPerBatch, p1 - pb);
-            for (int t = threadIdx.x; t < np * D; t += blockDim.x) {
-                const int p = t / D, c = t - p * D;
-                const int64_t gi = pb + p;
-                const float f = J.tgt_frac[gi * D + c];
-                for (int j = 0; j < taps; ++j)
-                    wtab[p][c][j] = kb_window(f + (mf - 1.0f) - (float)j, mf, b, idn, edge);
-                cellr[p][c] = (int)((J.tgt_cell[gi] >> (10 * c)) & 1023u);
-            }
-            for (int t = threadIdx.x; t < np; t += blockDim.x) acc[t] = 0.0f;
+        for (int pb = p0; pb < p1; pb += 16) {
+            const int np = min(16, p1 - pb);
+            shifted_windows<D>(J, J.tgt_cell, J.tgt_frac, pb, np, 1.0f, nullptr, 0, win);
             __syncthreads();
-            const int slots = np * taps;
-            for (int sl = threadIdx.x; sl < slots; sl += blockDim.x) {
-                const int p = sl / taps, j0 = sl - p * taps;
-                float part = 0.0f;
-                if constexpr (D == 3) {
-                    const float *src = patch + ((cellr[p][0] + j0) * W + cellr[p][1]) * W + cellr[p][2];
-                    for (int j1 = 0; j1 < taps; ++j1) {
-                        float row = 0.0f;
-                        for (int j2 = 0; j2 < taps; ++j2) row += src[j1 * W + j2] * wtab[p][2][j2];
-                        part += row * wtab[p][1][j1];
-                    }
-                } else if constexpr (D == 2) {
-                    const float *src = patch + (cellr[p][0] + j0) * W + cellr[p][1];
-                    for (int j1 = 0; j1 < taps; ++j1) part += src[j1] * wtab[p][1][j1];
-                } else {
-                    part = patch[cellr[p][0] + j0];
+            if constexpr (D == 1) {
+                if (l < np) {
+                    float s = 0.0f;
+#pragma unroll
+                    for (int a = 0; a < 16; ++a) s += G[a] * win[l][0][a];
+                    J.out[pb + l] = ldexp((double)s, e);
                 }
-                atomicAdd(&acc[p], part * wtab[p][0][j0]);
+            } else {
+                f32x4 acc = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+                if constexpr (D == 3) {
+                    float wy[16], wzk[4];
+#pragma unroll
+                    for (int q = 0; q < 16; ++q) wy[q] = win[li][1][q];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) wzk[q] = win[li][2][4 * q + lk];
+#pragma unroll
+                    for (int s = 0; s < 64; ++s) {
+                        const float A = wy[s >> 2] * wzk[s & 3];
+                        const float Bv = G[li * RS + (s >> 2) * 16 + 4 * (s & 3) + lk];
+                        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(A, Bv, acc, 0, 0, 0);
+                    }
+                } else {
+#pragma unroll
+                    for (int s = 0; s < 4; ++s)
+                        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(win[li][1][4 * s + lk],
+                                                                  G[li * RS + 4 * s + lk], acc, 0, 0, 0);
+                }
+                // acc[r] = Z[p = 4 lk + r][a = li]; beta_p = sum_a w_0[a] Z[p][a]
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int p = 4 * lk + r;
+                    float z = acc[r] * win[p][0][li];
+                    z += __shfl_xor(z, 1);
+                    z += __shfl_xor(z, 2);
+                    z += __shfl_xor(z, 4);
+                    z += __shfl_xor(z, 8);
+                    if (li == 0 && p < np) J.out[pb + p] = ldexp((double)z, e);
+                }
             }
-            __syncthreads();
-            for (int t = threadIdx.x; t < np; t += blockDim.x) J.out[pb + t] = ldexp((double)acc[t], e);
             __syncthreads();
         }
     }
@@ -406,23 +453,22 @@ __global__ __launch_bounds__(kNfftThreads) void interp_kernel(const ProdJob *__r
 
 static int nfft_grid(int n_items)
 {
-    return n_items < 4096 ? n_items : 4096;
+    return n_items < 65535 ? n_items : 65535;
 }
 
 hipError_t launch_spread(int d, const ProdJob *jobs, const int2 *items, int n_items,
-                         int max_patch_elems, hipStream_t s)
+                         int /*max_patch_elems*/, hipStream_t s)
 {
     if (n_items == 0) return hipSuccess;
-    const size_t lds = (size_t)max_patch_elems * sizeof(float);
     if (d == 3)
-        hipLaunchKernelGGL(spread_kernel<3>, dim3(nfft_grid(n_items)), dim3(kNfftThreads), lds, s,
-                           jobs, items, n_items);
+        hipLaunchKernelGGL(spread_kernel<3>, dim3(nfft_grid(n_items)), dim3(64), 0, s, jobs, items,
+                           n_items);
     else if (d == 2)
-        hipLaunchKernelGGL(spread_kernel<2>, dim3(nfft_grid(n_items)), dim3(kNfftThreads), lds, s,
-                           jobs, items, n_items);
+        hipLaunchKernelGGL(spread_kernel<2>, dim3(nfft_grid(n_items)), dim3(64), 0, s, jobs, items,
+                           n_items);
     else
-        hipLaunchKernelGGL(spread_kernel<1>, dim3(nfft_grid(n_items)), dim3(kNfftThreads), lds, s,
-                           jobs, items, n_items);
+        hipLaunchKernelGGL(spread_kernel<1>, dim3(nfft_grid(n_items)), dim3(64), 0, s, jobs, items,
+                           n_items);
     return hipGetLastError();
 }
 
@@ -442,19 +488,18 @@ hipError_t launch_fold(int d, const ProdJob *jobs, const int2 *items, int n_item
 }
 
 hipError_t launch_interp(int d, const ProdJob *jobs, const int2 *items, int n_items,
-                         int max_patch_elems, hipStream_t s)
+                         int /*max_patch_elems*/, hipStream_t s)
 {
     if (n_items == 0) return hipSuccess;
-    const size_t lds = (size_t)max_patch_elems * sizeof(float);
     if (d == 3)
-        hipLaunchKernelGGL(interp_kernel<3>, dim3(nfft_grid(n_items)), dim3(kNfftThreads), lds, s,
-                           jobs, items, n_items);
+        hipLaunchKernelGGL(interp_kernel<3>, dim3(nfft_grid(n_items)), dim3(64), 0, s, jobs, items,
+                           n_items);
     else if (d == 2)
-        hipLaunchKernelGGL(interp_kernel<2>, dim3(nfft_grid(n_items)), dim3(kNfftThreads), lds, s,
-                           jobs, items, n_items);
+        hipLaunchKernelGGL(interp_kernel<2>, dim3(nfft_grid(n_items)), dim3(64), 0, s, jobs, items,
+                           n_items);
     else
-        hipLaunchKernelGGL(interp_kernel<1>, dim3(nfft_grid(n_items)), dim3(kNfftThreads), lds, s,
-                           jobs, items, n_items);
+        hipLaunchKernelGGL(interp_kernel<1>, dim3(nfft_grid(n_items)), dim3(64), 0, s, jobs, items,
+                           n_items);
     return hipGetLastError();
 }
 

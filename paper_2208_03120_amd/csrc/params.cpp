@@ -279,7 +279,8 @@ static double kb_err(int m, double sigma)
            std::exp(-2.0 * M_PI * m * a);
 }
 
-static int default_tile(int d) { return d == 3 ? 8 : (d == 2 ? 16 : 64); }
+// Spreading and interpolation work on 16-cell patches: tiles of T = 17 - 2m cells.
+static int tile_for(int m) { return 17 - 2 * m; }
 
 int resolve_params(int d, double eta, const Extent &ext, const mot_fastsum_params *fs,
                    int64_t n_max, NfftParams *out)
@@ -290,7 +291,7 @@ int resolve_params(int d, double eta, const Extent &ext, const mot_fastsum_param
         return MOT_EINVAL;
     if (F.n > 0 && (F.n < kMinN || F.n > kMaxN || (F.n & (F.n - 1)) != 0)) return MOT_EINVAL;
     if (F.M > 0 && F.n > 0 && 2 * F.M >= F.n) return MOT_EINVAL;
-    if (F.tile > 1000) return MOT_EINVAL;
+    if (F.tile > 0 && F.m > 0 && F.tile != tile_for(F.m)) return MOT_EINVAL;
     const double target = F.target_rel_err > 0 ? F.target_rel_err : 1e-7;
     const double diag = std::max(ext.diag, 1e-12);
     NfftParams best;
@@ -345,8 +346,7 @@ int resolve_params(int d, double eta, const Extent &ext, const mot_fastsum_param
                 P.tau = tau;
                 P.eps_B = eb;
                 P.sigma = sigma;
-                P.T = F.tile > 0 ? F.tile : default_tile(d);
-                while (P.T > 2 && build_box(d, ext, &P) != MOT_OK) P.T /= 2;
+                P.T = tile_for(m);
                 if (build_box(d, ext, &P) != MOT_OK) continue;
                 P.kb_b = M_PI * (2.0 - 1.0 / sigma);
                 double box = 1.0;
@@ -363,7 +363,7 @@ int resolve_params(int d, double eta, const Extent &ext, const mot_fastsum_param
     if (best_cost < 0) return MOT_EDOMAIN;
     best.kb_inv_den = 1.0 / (1.0 - std::exp(-2.0 * best.kb_b * best.m));
     best.kb_edge = best.m * 2.0 * best.kb_b * std::exp(-best.kb_b * best.m) * best.kb_inv_den;
-    int chunk = F.chunk > 0 ? F.chunk : 1024;
+    int chunk = F.chunk > 0 ? F.chunk : (d == 3 ? 512 : 2048);
     best.chunk = chunk;
     *out = best;
     return MOT_OK;

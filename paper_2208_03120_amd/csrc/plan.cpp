@@ -1074,6 +1074,47 @@ int mot_sinkhorn(mot_plan P, int32_t max_sweeps, double delta_S, double tol_marg
     return status;
 }
 
+int mot_plan_profile(mot_plan P, int32_t sweeps, mot_step_timing *out, int32_t max_out)
+{
+    if (!P || sweeps < 1 || (!out && max_out > 0)) return MOT_EINVAL;
+    if (P->topology != MOT_TREE) return MOT_EUNSUPPORTED;
+    const auto &steps = P->sched.sweep;
+    const size_t ns = steps.size();
+    std::vector<hipEvent_t> ev(2 * ns);
+    for (auto &e : ev) MOT_HIP(hipEventCreate(&e));
+    std::vector<double> acc(ns, 0.0);
+    for (int r = 0; r < sweeps; ++r) {
+        for (size_t i = 0; i < ns; ++i) {
+            MOT_HIP(hipEventRecord(ev[2 * i], P->stream));
+            std::vector<Step> one{steps[i]};
+            MOT_TRY(run_steps(one, P->stream));
+            MOT_HIP(hipEventRecord(ev[2 * i + 1], P->stream));
+        }
+        MOT_HIP(hipStreamSynchronize(P->stream));
+        for (size_t i = 0; i < ns; ++i) {
+            float ms = 0.f;
+            MOT_HIP(hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]));
+            acc[i] += ms;
+        }
+    }
+    P->host_sweeps += sweeps;
+    for (auto &e : ev) (void)hipEventDestroy(e);
+    const int nout = std::min((int)ns, (int)max_out);
+    static const int kind_code[] = {0, 1, 2, 3, 4, 5, 6, 7};
+    for (int i = 0; i < nout; ++i) {
+        mot_step_timing t{};
+        t.kind = kind_code[steps[i].kind];
+        t.d = steps[i].d;
+        t.n = steps[i].n;
+        t.fft_kind = steps[i].fft_kind;
+        t.n_items = steps[i].n_items;
+        t.calls = sweeps;
+        t.ms_mean = acc[i] / sweeps;
+        out[i] = t;
+    }
+    return nout;
+}
+
 int mot_get_S_history(mot_plan P, double *S_out, int32_t count)
 {
     if (!P || (!S_out && count > 0)) return MOT_EINVAL;

@@ -55,6 +55,16 @@ class Allocator(ctypes.Structure):
                 ("ctx", ctypes.c_void_p)]
 
 
+class StepTiming(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("d", ctypes.c_int32), ("n", ctypes.c_int32),
+                ("fft_kind", ctypes.c_int32), ("n_items", ctypes.c_int32), ("calls", ctypes.c_int32),
+                ("ms_mean", ctypes.c_double)]
+
+
+STEP_KIND = {0: "node", 1: "direct", 2: "spread", 3: "fold", 4: "fft", 5: "interp", 6: "final",
+             7: "fill"}
+
+
 class Request(ctypes.Structure):
     _fields_ = [("K", ctypes.c_int32), ("d", ctypes.c_int32), ("topology", ctypes.c_int32),
                 ("n", ctypes.POINTER(ctypes.c_int64)), ("points", ctypes.POINTER(ctypes.c_double)),
@@ -75,6 +85,7 @@ class Result(ctypes.Structure):
 EXPORTED = ["mot_plan_create", "mot_sinkhorn", "mot_get_S_history", "mot_marginals",
             "mot_get_scalings", "mot_set_scalings", "mot_apply_kernel", "mot_plan_get_info",
             "mot_plan_footprint", "mot_plan_destroy", "mot_strerror", "mot_bin_points",
+            "mot_plan_profile",
             "mot_batch_create", "mot_batch_sinkhorn", "mot_batch_destroy", "mot_server_create",
             "mot_server_submit", "mot_server_run", "mot_server_fetch", "mot_server_clock",
             "mot_server_destroy"]
@@ -117,6 +128,7 @@ def _load():
                                               ctypes.c_double, _P(FastsumParams),
                                               _P(ctypes.c_size_t)]),
         "mot_plan_destroy": (ctypes.c_int, [_vp]),
+        "mot_plan_profile": (ctypes.c_int, [_vp, ctypes.c_int32, _P(StepTiming), ctypes.c_int32]),
         "mot_strerror": (ctypes.c_char_p, [ctypes.c_int]),
         "mot_bin_points": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int64, _dp, _dp, _dp,
                                           ctypes.c_int32, ctypes.c_int32, _ip, _ip, _ip,
@@ -266,6 +278,14 @@ class Plan:
         _check(_lib.mot_apply_kernel(self._h, int(t), int(s), _dptr(v), _dptr(out), HOST),
                "mot_apply_kernel")
         return out
+
+    def profile(self, sweeps):
+        """Per-launch mean device time (ms) of one sweep, from HIP events."""
+        arr = (StepTiming * 512)()
+        n = _check(_lib.mot_plan_profile(self._h, int(sweeps), arr, 512), "mot_plan_profile")
+        return [{"kind": STEP_KIND.get(arr[i].kind, "?"), "d": arr[i].d, "n": arr[i].n,
+                 "fft_kind": arr[i].fft_kind, "n_items": arr[i].n_items, "ms": arr[i].ms_mean}
+                for i in range(n)]
 
     def info(self):
         I = PlanInfo()
