@@ -76,6 +76,7 @@ void kappa_hat_even(int d, int M, double eta, double tau, double eps_B, int p,
                     std::vector<double> &khat);  // (M+1)^d entries, |k_c| = 0..M
 void build_multiplier(int d, const NfftParams &P, double eta, std::vector<float> &D);
 void build_twiddle(int n, std::vector<float2> &tw);
+void build_window_poly(const NfftParams &P, std::vector<float> &coef);
 double kb_fourier(double k, const NfftParams &P);  // normalised window transform
 
 // ---------------------------------------------------------------------------------------
@@ -145,6 +146,7 @@ struct mot_plan_s {
     mot::ProdJob *jobs_dev = nullptr;
     int32_t *exp_slots = nullptr;  // [2K + 1]
     float *D = nullptr;
+    float *winpoly = nullptr;
     float2 *twiddle = nullptr;
     // statistics
     int32_t *sweep_ctr = nullptr, *flag = nullptr, *flag_hist = nullptr, *ticket = nullptr;

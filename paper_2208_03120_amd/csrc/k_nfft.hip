@@ -189,19 +189,9 @@ hipError_t launch_point_layout_s(int d, int64_t npts, const double *pts, const d
 // ---------------------------------------------------------------------------------------
 // Kaiser-Bessel window in grid units, normalised to 1 at s = 0:
 //   psi(s) = (m / r) sinh(b r) / sinh(b m),  r = sqrt(m^2 - s^2),  |s| <= m,
-// evaluated as (m / r) exp(b (r - m)) (1 - exp(-2 b r)) / (1 - exp(-2 b m)) with
-// r - m = -s^2 / (r + m), which keeps the central taps accurate to a few FP32 ulps.
-// Its Fourier transform is known in closed form (used on the host for the multiplier).
-__device__ __forceinline__ float kb_window(float s, float m, float b, float inv_den, float edge)
-{
-    const float s2 = s * s;
-    const float r = sqrtf(fmaxf(m * m - s2, 0.0f));
-    if (r < 1e-3f) return edge;
-    const float y = -b * s2 / (r + m);
-    const float t = expf(-2.0f * b * r);
-    return (m / r) * expf(y) * (1.0f - t) * inv_den;
-}
-
+// b = pi (2 - 1/sigma).  Its Fourier transform is I0(m sqrt(b^2 - w^2)) (used on the host
+// for the spectral multiplier).  On the device it is evaluated from 2m degree-9
+// polynomials, one per unit interval of s, fitted on the host in FP64.
 __device__ __forceinline__ int floor_div(int a, int b)  // floor(a / b) for b > 0
 {
     return a >= 0 ? a / b : -((-a + b - 1) / b);
@@ -226,30 +216,64 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 // No atomics: each chunk owns its patch (spreading), each point its sum (interpolation).
 // One wavefront per work item; points are taken 16 at a time.
 constexpr int kPatch = 16;
-constexpr int kIS = 260;  // padded LDS row stride of the interpolation patch (16 x 256)
+
+// Per-lane data of one (point, dimension) row of a 16-point batch, prefetched a batch
+// ahead: lane t < 16 D holds row t = p D + c.
+struct RowData {
+    uint32_t cell;
+    float frac;
+    double v;
+};
 
 template <int D>
-__device__ __forceinline__ void shifted_windows(const ProdJob &J, const uint32_t *cellpk,
-                                                const float *frac, int64_t pb, int np, float vscale0,
-                                                const double *v, int e, float (*win)[D][kPatch])
+__device__ __forceinline__ void load_rows(const uint32_t *cellpk, const float *frac, const double *v,
+                                          int64_t pb, int np, RowData &rd)
 {
-    const int lane = threadIdx.x;
-    const int taps = 2 * J.m;
-    const float mf = (float)J.m, b = J.kb_b, idn = J.kb_inv_den, edge = J.kb_edge;
-    for (int t = lane; t < 16 * D * kPatch; t += 64) {
-        const int p = t / (D * kPatch), c = (t / kPatch) % D, q = t % kPatch;
-        float w = 0.0f;
+    const int t = threadIdx.x, p = t / D, c = t - p * D;
+    rd.cell = 0u;
+    rd.frac = 0.0f;
+    rd.v = 0.0;
+    if (t < 16 * D && p < np) {
+        const int64_t gi = pb + p;
+        rd.cell = (cellpk[gi] >> (10 * c)) & 1023u;
+        rd.frac = frac[gi * D + c];
+        if (c == 0 && v) rd.v = v[gi];
+    }
+}
+
+// Fill win[p][c][0..15] with the shifted windows of the batch: lane t owns row t, zeroes
+// it and writes its 2m taps at positions r + j, tap j evaluated by Horner's rule at
+// t = f - 1/2 on interval 2m - 1 - j (coefficients read from LDS, the same address on
+// every lane).
+template <int D>
+__device__ __forceinline__ void shifted_windows(const ProdJob &J, const float *cf_lds, const RowData &rd,
+                                                int np, bool scale_v, int e, float (*win)[D][kPatch])
+{
+    const int t = threadIdx.x, p = t / D, c = t - p * D;
+    if (t < 16 * D) {
+        float4 *row4 = reinterpret_cast<float4 *>(&win[p][c][0]);
+#pragma unroll
+        for (int q = 0; q < kPatch / 4; ++q) row4[q] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         if (p < np) {
-            const int64_t gi = pb + p;
-            const int r = (int)((cellpk[gi] >> (10 * c)) & 1023u);
-            const int j = q - r;
-            if (j >= 0 && j < taps) {
-                w = kb_window(frac[gi * D + c] + (mf - 1.0f) - (float)j, mf, b, idn, edge);
-                if (c == 0 && v) w *= (float)ldexp(v[gi], -e) * vscale0;
+            const int taps = 2 * J.m;
+            const float x = rd.frac - 0.5f;
+            const float sc = (c == 0 && scale_v) ? (float)ldexp(rd.v, -e) : 1.0f;
+            float *row = &win[p][c][rd.cell];
+            for (int j = 0; j < taps; ++j) {
+                const float *cf = cf_lds + (taps - 1 - j) * (kWinDeg + 1);
+                float w = cf[kWinDeg];
+#pragma unroll
+                for (int i = kWinDeg - 1; i >= 0; --i) w = fmaf(w, x, cf[i]);
+                row[j] = sc * w;
             }
         }
-        win[p][c][q] = w;
     }
+}
+
+__device__ __forceinline__ void load_poly_lds(const ProdJob &J, float *cf_lds)
+{
+    const int n = 2 * J.m * (kWinDeg + 1);
+    for (int i = threadIdx.x; i < n; i += blockDim.x) cf_lds[i] = J.winpoly[i];
 }
 
 template <int D>
@@ -257,6 +281,7 @@ __global__ __launch_bounds__(64) void spread_kernel(const ProdJob *__restrict__ 
                                                     const int2 *__restrict__ items, int n_items)
 {
     __shared__ float win[16][D][kPatch];
+    __shared__ float cf_lds[2 * (kMaxTaps / 2) * (kWinDeg + 1)];
     const int l = threadIdx.x, li = l & 15, lk = l >> 4;
     for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
         const int2 itm = items[it];
@@ -264,6 +289,10 @@ __global__ __launch_bounds__(64) void spread_kernel(const ProdJob *__restrict__ 
         const int p0 = J.src_chunk_start[itm.y], p1 = J.src_chunk_start[itm.y + 1];
         int e = *J.v_exp;
         if (e == INT32_MIN) e = 0;
+        load_poly_lds(J, cf_lds);
+        RowData rd;
+        load_rows<D>(J.src_cell, J.src_frac, J.v, p0, min(16, p1 - p0), rd);
+        __syncthreads();
         constexpr int NT = D == 3 ? 16 : 1;
         f32x4 acc[NT];
         float acc1 = 0.0f;
@@ -271,7 +300,8 @@ __global__ __launch_bounds__(64) void spread_kernel(const ProdJob *__restrict__ 
         for (int t = 0; t < NT; ++t) acc[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
         for (int pb = p0; pb < p1; pb += 16) {
             const int np = min(16, p1 - pb);
-            shifted_windows<D>(J, J.src_cell, J.src_frac, pb, np, 1.0f, J.v, e, win);
+            shifted_windows<D>(J, cf_lds, rd, np, true, e, win);
+            if (pb + 16 < p1) load_rows<D>(J.src_cell, J.src_frac, J.v, pb + 16, min(16, p1 - pb - 16), rd);
             __syncthreads();
             if constexpr (D == 3) {
 #pragma unroll
@@ -367,13 +397,16 @@ __global__ __launch_bounds__(256) void fold_kernel(const ProdJob *__restrict__ j
 // Interpolation (a6): item = (job, chunk of target points).  out = 2^e * beta with beta
 // the window-weighted sum of the grid around each point (FP32, written as FP64), where e
 // is the exponent the source vector was scaled by before spreading.
+// The MFMA B operand, G[a][(b,c')] for this lane's a = lane % 16 and c' = 4q + lane / 16,
+// is the same for every point of the chunk: it is loaded once into registers.
 template <int D>
 __global__ __launch_bounds__(64) void interp_kernel(const ProdJob *__restrict__ jobs,
                                                     const int2 *__restrict__ items, int n_items)
 {
-    constexpr int RS = D == 3 ? kIS : (D == 2 ? 17 : 16);  // padded row stride of G[a][...]
-    __shared__ float G[16 * RS];
+    constexpr int NB = D == 3 ? 64 : (D == 2 ? 4 : 1);  // B values per lane
     __shared__ float win[16][D][kPatch];
+    __shared__ float cf_lds[2 * (kMaxTaps / 2) * (kWinDeg + 1)];
+    __shared__ float G1[16];
     const int l = threadIdx.x, li = l & 15, lk = l >> 4;
     for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
         const int2 itm = items[it];
@@ -387,31 +420,37 @@ __global__ __launch_bounds__(64) void interp_kernel(const ProdJob *__restrict__ 
                 rem /= J.ntile[c];
             }
         }
-        // patch of the result grid: box cells tile * T + (0..15) per dimension
-        constexpr int PE = D == 3 ? 4096 : (D == 2 ? 256 : 16);
-        for (int t = l; t < PE; t += 64) {
-            const int a = D == 1 ? t : (D == 2 ? t / 16 : t / 256);
-            const int bb = D == 2 ? t % 16 : (t / 16) % 16;
-            const int cc = t % 16;
-            int64_t gidx = tc[0] * T + a;
-            if (D >= 2) gidx = gidx * J.L[1] + tc[1] * T + (D == 2 ? bb : bb);
-            if (D == 3) gidx = gidx * J.L[2] + tc[2] * T + cc;
-            const int loc = D == 3 ? a * RS + bb * 16 + cc : (D == 2 ? a * RS + bb : a);
-            G[loc] = J.grid[gidx];
+        float Bv[NB];
+        if constexpr (D == 3) {
+            // K index s = 4(b) + q  <->  (b = s >> 2, c' = 4 (s & 3) + lk)
+            const int64_t base = ((int64_t)(tc[0] * T + li) * J.L[1] + tc[1] * T) * J.L[2] + tc[2] * T;
+#pragma unroll
+            for (int s = 0; s < 64; ++s)
+                Bv[s] = J.grid[base + (int64_t)(s >> 2) * J.L[2] + 4 * (s & 3) + lk];
+        } else if constexpr (D == 2) {
+            const int64_t base = (int64_t)(tc[0] * T + li) * J.L[1] + tc[1] * T;
+#pragma unroll
+            for (int s = 0; s < 4; ++s) Bv[s] = J.grid[base + 4 * s + lk];
+        } else {
+            if (l < 16) G1[l] = J.grid[tc[0] * T + l];
         }
         int e = *J.v_exp;
         if (e == INT32_MIN) e = 0;
+        load_poly_lds(J, cf_lds);
         const int p0 = J.tgt_chunk_start[itm.y], p1 = J.tgt_chunk_start[itm.y + 1];
+        RowData rd;
+        load_rows<D>(J.tgt_cell, J.tgt_frac, nullptr, p0, min(16, p1 - p0), rd);
         __syncthreads();
         for (int pb = p0; pb < p1; pb += 16) {
             const int np = min(16, p1 - pb);
-            shifted_windows<D>(J, J.tgt_cell, J.tgt_frac, pb, np, 1.0f, nullptr, 0, win);
+            shifted_windows<D>(J, cf_lds, rd, np, false, 0, win);
+            if (pb + 16 < p1) load_rows<D>(J.tgt_cell, J.tgt_frac, nullptr, pb + 16, min(16, p1 - pb - 16), rd);
             __syncthreads();
             if constexpr (D == 1) {
                 if (l < np) {
                     float s = 0.0f;
 #pragma unroll
-                    for (int a = 0; a < 16; ++a) s += G[a] * win[l][0][a];
+                    for (int a = 0; a < 16; ++a) s += G1[a] * win[l][0][a];
                     J.out[pb + l] = ldexp((double)s, e);
                 }
             } else {
@@ -423,16 +462,12 @@ __global__ __launch_bounds__(64) void interp_kernel(const ProdJob *__restrict__ 
 #pragma unroll
                     for (int q = 0; q < 4; ++q) wzk[q] = win[li][2][4 * q + lk];
 #pragma unroll
-                    for (int s = 0; s < 64; ++s) {
-                        const float A = wy[s >> 2] * wzk[s & 3];
-                        const float Bv = G[li * RS + (s >> 2) * 16 + 4 * (s & 3) + lk];
-                        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(A, Bv, acc, 0, 0, 0);
-                    }
+                    for (int s = 0; s < 64; ++s)
+                        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(wy[s >> 2] * wzk[s & 3], Bv[s], acc, 0, 0, 0);
                 } else {
 #pragma unroll
                     for (int s = 0; s < 4; ++s)
-                        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(win[li][1][4 * s + lk],
-                                                                  G[li * RS + 4 * s + lk], acc, 0, 0, 0);
+                        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(win[li][1][4 * s + lk], Bv[s], acc, 0, 0, 0);
                 }
                 // acc[r] = Z[p = 4 lk + r][a = li]; beta_p = sum_a w_0[a] Z[p][a]
 #pragma unroll

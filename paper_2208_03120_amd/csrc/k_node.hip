@@ -17,7 +17,7 @@
 
 namespace mot {
 
-constexpr int kNodeElems = 1024;  // elements per node item (4 per thread)
+constexpr int kNodeElems = 256;  // elements per node item (one per thread)
 constexpr int kRegChildren = 16;  // children held in registers
 
 __device__ __forceinline__ int exp_of(double v)
@@ -49,6 +49,7 @@ __global__ __launch_bounds__(256) void node_kernel(const NodeJob *__restrict__ j
                                                    const int2 *__restrict__ items, int n_items)
 {
     __shared__ double red[4];
+    __shared__ int emx[4][kRegChildren + 1];
     const int tid = threadIdx.x;
     for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
         const int2 itm = items[it];
@@ -127,16 +128,30 @@ __global__ __launch_bounds__(256) void node_kernel(const NodeJob *__restrict__ j
             }
         }
         if (bad) atomicOr(J.flag, 1);
-        if (usrc) {
-            const int m = wave_max_int(em_up);
-            if ((tid & 63) == 0 && m != INT32_MIN) atomicMax(J.up_exp, m);
-        }
-        if (dsrc && regs) {
+        // exponent maxima: wave max, then block max, then one atomic per block and vector
+        if (usrc || dsrc) {
+            const int wave = tid >> 6, lane = tid & 63;
+            __syncthreads();
+            if (usrc) {
+                const int m = wave_max_int(em_up);
+                if (lane == 0) emx[wave][kRegChildren] = m;
+            }
+            if (dsrc && regs) {
 #pragma unroll
-            for (int c = 0; c < kRegChildren; ++c) {
-                if (c < nch) {  // nch is uniform over the block
-                    const int m = wave_max_int(em[c]);
-                    if ((tid & 63) == 0 && m != INT32_MIN) atomicMax(J.down_exp[c], m);
+                for (int c = 0; c < kRegChildren; ++c) {
+                    if (c < nch) {  // nch is uniform over the block
+                        const int m = wave_max_int(em[c]);
+                        if (lane == 0) emx[wave][c] = m;
+                    }
+                }
+            }
+            __syncthreads();
+            if (tid <= kRegChildren) {
+                const bool is_up = tid == kRegChildren;
+                if ((is_up && usrc) || (!is_up && dsrc && regs && tid < nch)) {
+                    int m = emx[0][tid];
+                    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) m = max(m, emx[w][tid]);
+                    if (m != INT32_MIN) atomicMax(is_up ? J.up_exp : J.down_exp[tid], m);
                 }
             }
         }
@@ -195,13 +210,18 @@ __global__ __launch_bounds__(256) void finalize_kernel(const FinalJob *__restric
         __syncthreads();
         if (last) {
             __threadfence();
+            // every thread sums a fixed strided subset; block_sum combines them in a fixed
+            // order, so the result does not depend on timing
+            double s1 = 0.0, s2 = 0.0, e1 = 0.0;
+            for (int p = tid; p < J.n_partials; p += blockDim.x) {
+                s1 += J.s_partial[2 * p];
+                s2 += J.s_partial[2 * p + 1];
+            }
+            for (int p = tid; p < J.n_items; p += blockDim.x) e1 += J.l1_partial[p];
+            s1 = block_sum(s1, red);
+            s2 = block_sum(s2, red);
+            e1 = block_sum(e1, red);
             if (tid == 0) {
-                double s1 = 0.0, s2 = 0.0, e1 = 0.0;
-                for (int p = 0; p < J.n_partials; ++p) {
-                    s1 += J.s_partial[2 * p];
-                    s2 += J.s_partial[2 * p + 1];
-                }
-                for (int p = 0; p < J.n_items; ++p) e1 += J.l1_partial[p];
                 const int r = *J.sweep_ctr;
                 const int slot = r % J.hist_cap;
                 J.S_hist[slot] = J.eta * (s1 - s2);

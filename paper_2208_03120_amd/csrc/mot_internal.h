@@ -18,6 +18,7 @@ constexpr int kMaxD = 3;
 constexpr int kMaxTaps = 16;      // 2m taps per dimension, m <= 8
 constexpr int kMaxN = 512;        // FFT grid per dimension
 constexpr int kMinN = 16;
+constexpr int kWinDeg = 9;       // degree of the window polynomials
 constexpr int kMaxChildren = 64;  // children per tree node handled by the node kernels
 
 // ---------------------------------------------------------------------------------------
@@ -55,6 +56,7 @@ struct ProdJob {
     float kb_inv_den;  // 1 / (1 - exp(-2 b m))
     float kb_edge;     // window value at |s| = m
     const float *D;    // multiplier on the half spectrum, layout [A2][A1][2M+1]
+    const float *winpoly;  // [2m][kWinDeg+1] window polynomial coefficients
     const float2 *twiddle;  // exp(-2 pi i k / n), k < n/2
     // NFFT work buffers
     float *patches;    // src_nchunks * W^d
@@ -130,7 +132,7 @@ hipError_t launch_point_layout_s(int d, int64_t npts, const double *pts, const d
                                  hipStream_t st);
 
 // NFFT pipeline kernels (a2-a6).
-constexpr int kNodeItemElems = 1024;
+constexpr int kNodeItemElems = 256;
 constexpr int kFoldItemCells = 256;
 constexpr int kFftLinesPerItem = 16;
 hipError_t launch_spread(int d, const ProdJob *jobs, const int2 *items, int n_items,

@@ -678,6 +678,7 @@ static int make_prod_job(mot_plan_s *P, int t, int s, const double *v, int32_t *
     Q.kb_inv_den = (float)N.kb_inv_den;
     Q.kb_edge = (float)N.kb_edge;
     Q.D = P->D;
+    Q.winpoly = P->winpoly;
     Q.twiddle = device_twiddle(N.n);
     int64_t pe = 1, cells = 1;
     for (int c = 0; c < P->d; ++c) {
@@ -740,6 +741,10 @@ static int create_tree(mot_plan_s *P, const std::vector<double> &pts_h, const st
         build_multiplier(d, P->P, P->eta, D);
         MOT_TRY(P->arena.get_n(D.size(), &P->D));
         MOT_HIP(hipMemcpy(P->D, D.data(), D.size() * sizeof(float), hipMemcpyHostToDevice));
+        std::vector<float> wp;
+        build_window_poly(P->P, wp);
+        MOT_TRY(P->arena.get_n(wp.size(), &P->winpoly));
+        MOT_HIP(hipMemcpy(P->winpoly, wp.data(), wp.size() * sizeof(float), hipMemcpyHostToDevice));
         if (!device_twiddle(P->P.n)) return MOT_EDEVICE;
         log_msg("NFFT params: M=%d n=%d m=%d p=%d tau=%.6g eps_B=%.6g T=%d box=%dx%dx%d est_err=%.3g",
                 P->P.M, P->P.n, P->P.m, P->P.p, P->P.tau, P->P.eps_B, P->P.T, P->P.L[0], P->P.L[1],
