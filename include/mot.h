@@ -159,8 +159,8 @@ int mot_set_scalings(mot_plan plan, const double *phi_in, int32_t ptr_kind);
 /* One kernel product with the plan's path: out = K^{(t,s)} v, i.e.
  * out_i = sum_j v_j exp(-|x^t_i - x^s_j|^2 / eta) (Sec. 5, eq. fastsum-sum),
  * approximated by Algorithm 4 on the NFFT path.  v has n_s entries, out n_t
- * (original point order, ptr_kind).  Tree plans accept any pair (t, s), circle
- * plans any pair.  For parity tests of a single product. */
+ * (original point order, ptr_kind).  Tree plans only (any pair (t, s));
+ * MOT_EUNSUPPORTED for circle plans.  For parity tests of a single product. */
 int mot_apply_kernel(mot_plan plan, int32_t t, int32_t s, const double *v, double *out,
                      int32_t ptr_kind);
 

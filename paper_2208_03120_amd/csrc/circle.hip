@@ -1,10 +1,701 @@
-// Circle-structured Sinkhorn (Algorithm 3).
+// Circle-structured Sinkhorn (a9, Algorithm 3) on gfx950.
+//
+// Algorithm 3 keeps the matrices beta_k = alpha^{(k,1)} (n_k x n_1) and
+// gamma_k = lambda^{(1,k)} (n_1 x n_k).  Both are stored here as n_1 x n_k row-major
+// matrices: Yb_k = beta_k^T and Yg_k = gamma_k.  With Kmat(a, b)[i][j] =
+// exp(-|x^a_i - x^b_j|^2 / eta) the recursions read
+//   Yb_k = Yb_{k+1} diag(phi^{k+1}) Kmat(k, k+1)^T      (k = K-2 .. 1, Yb_{K-1} = Kmat(0, K-1))
+//   Yg_k = Yg_{k-1} diag(phi^{k-1}) Kmat(k, k-1)^T      (k = 2 .. K-1, Yg_1 = Kmat(0, 1))
+// -- one GEMM shape C = A diag(phi) B^T with a constant kernel matrix B -- and the
+// row-wise inner products of Theorem 4.3 become
+//   phi^k_j = mu^k_j / sum_i Yb_k[i][j] phi^0_i Yg_k[i][j]                   (column sums)
+//   phi^0_i = mu^0_i / sum_j Kmat(0,1)[i][j] phi^1_j Yb_1[i][j]               (row sums)
+//
+// Dense path: the GEMMs run on MFMA (v_mfma_f32_32x32x16_bf16 / _f16) with FP32
+// accumulation; A is converted on the fly while it is staged in LDS.  Precision modes:
+// BF16, FP16 (rows of A scaled by powers of two) and split BF16 (A = Ah + Al,
+// B = Bh + Bl, C = Ah Bh + Ah Bl + Al Bh).  The reductions accumulate in FP64.
+// NFFT path: every row of a product is one fast summation (column by column in the
+// paper's words), run by the tree path's spreading / FFT / interpolation kernels with
+// one job per row; matrices are FP64.
+#include <algorithm>
+#include <cmath>
+
 #include "host.h"
 
 namespace mot {
-int circle_create(mot_plan_s *, const mot_fastsum_params *) { return MOT_EUNSUPPORTED; }
-int circle_run_sweeps(mot_plan_s *, int) { return MOT_EUNSUPPORTED; }
-int circle_marginals(mot_plan_s *, double *) { return MOT_EUNSUPPORTED; }
-void circle_destroy(mot_plan_s *) {}
-size_t circle_footprint(int, const int64_t *, int, int) { return 0; }
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+
+constexpr int kBM = 128, kBN = 128, kBK = 32, kLdsK = kBK + 8;  // padded LDS row (elements)
+
+__device__ __forceinline__ unsigned short bf16_bits(float x)
+{
+    __bf16 h = (__bf16)x;  // round to nearest even
+    return __builtin_bit_cast(unsigned short, h);
+}
+__device__ __forceinline__ float bf16_value(unsigned short b)
+{
+    return __builtin_bit_cast(float, (uint32_t)b << 16);
+}
+__device__ __forceinline__ unsigned short f16_bits(float x)
+{
+    _Float16 h = (_Float16)x;
+    return __builtin_bit_cast(unsigned short, h);
+}
+
+// C[M x N] (row-major, ldc) = A[M x K] (FP32, lda) diag(phi) B[N x K]^T (16-bit, ldb),
+// all dimensions padded to the tile sizes by the caller (zero padding).  MODE: 0 BF16,
+// 1 FP16 (row scale 2^-rexp[i] applied to A and undone on C), 2 split BF16.
+template <int MODE>
+__global__ __launch_bounds__(256) void gemm_kernel(const float *__restrict__ A, int lda,
+                                                   const double *__restrict__ phi,
+                                                   const unsigned short *__restrict__ Bh,
+                                                   const unsigned short *__restrict__ Bl, int ldb,
+                                                   float *__restrict__ C, int ldc, int K,
+                                                   const int32_t *__restrict__ rexp)
+{
+    __shared__ unsigned short As[kBM * kLdsK], Bs[kBN * kLdsK];
+    __shared__ unsigned short Asl[MODE == 2 ? kBM * kLdsK : 1], Bsl[MODE == 2 ? kBN * kLdsK : 1];
+    __shared__ float phis[kBK];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;  // wave's 64 x 64 sub-tile
+    const int m0 = blockIdx.y * kBM, n0 = blockIdx.x * kBN;
+    f32x16 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
+    // global staging assignment: A: row tid/2, 16 columns from (tid&1)*16; B: row tid/2, 16
+    const int ar = tid >> 1, ac = (tid & 1) * 16;
+    float rowscale = 1.0f;
+    if (MODE == 1) rowscale = ldexpf(1.0f, -rexp[m0 + ar]);
+    for (int k0 = 0; k0 < K; k0 += kBK) {
+        if (tid < kBK) phis[tid] = (float)phi[k0 + tid];
+        __syncthreads();
+        {
+            const float4 *src = reinterpret_cast<const float4 *>(A + (int64_t)(m0 + ar) * lda + k0 + ac);
+            unsigned short hv[16], lv[16];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const float4 a4 = src[q];
+                const float av[4] = {a4.x, a4.y, a4.z, a4.w};
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const float x = av[u] * phis[ac + 4 * q + u] * rowscale;
+                    if (MODE == 1) {
+                        hv[4 * q + u] = f16_bits(x);
+                    } else {
+                        hv[4 * q + u] = bf16_bits(x);
+                        if (MODE == 2) lv[4 * q + u] = bf16_bits(x - bf16_value(hv[4 * q + u]));
+                    }
+                }
+            }
+            uint4 *dst = reinterpret_cast<uint4 *>(&As[ar * kLdsK + ac]);
+            dst[0] = *reinterpret_cast<uint4 *>(&hv[0]);
+            dst[1] = *reinterpret_cast<uint4 *>(&hv[8]);
+            if (MODE == 2) {
+                uint4 *dl = reinterpret_cast<uint4 *>(&Asl[ar * kLdsK + ac]);
+                dl[0] = *reinterpret_cast<uint4 *>(&lv[0]);
+                dl[1] = *reinterpret_cast<uint4 *>(&lv[8]);
+            }
+            const uint4 *bs = reinterpret_cast<const uint4 *>(Bh + (int64_t)(n0 + ar) * ldb + k0 + ac);
+            uint4 *bd = reinterpret_cast<uint4 *>(&Bs[ar * kLdsK + ac]);
+            bd[0] = bs[0];
+            bd[1] = bs[1];
+            if (MODE == 2) {
+                const uint4 *bl = reinterpret_cast<const uint4 *>(Bl + (int64_t)(n0 + ar) * ldb + k0 + ac);
+                uint4 *bdl = reinterpret_cast<uint4 *>(&Bsl[ar * kLdsK + ac]);
+                bdl[0] = bl[0];
+                bdl[1] = bl[1];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < kBK; ks += 16) {
+            const int kk = ks + 8 * (lane >> 5);
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                const int ra = wm + 32 * i + (lane & 31);
+                const uint4 a_h = *reinterpret_cast<const uint4 *>(&As[ra * kLdsK + kk]);
+                uint4 a_l;
+                if (MODE == 2) a_l = *reinterpret_cast<const uint4 *>(&Asl[ra * kLdsK + kk]);
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    const int rb = wn + 32 * j + (lane & 31);
+                    const uint4 b_h = *reinterpret_cast<const uint4 *>(&Bs[rb * kLdsK + kk]);
+                    if (MODE == 1) {
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
+                            __builtin_bit_cast(f16x8, a_h), __builtin_bit_cast(f16x8, b_h), acc[i][j], 0, 0, 0);
+                    } else {
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                            __builtin_bit_cast(bf16x8, a_h), __builtin_bit_cast(bf16x8, b_h), acc[i][j], 0, 0, 0);
+                        if (MODE == 2) {
+                            const uint4 b_l = *reinterpret_cast<const uint4 *>(&Bsl[rb * kLdsK + kk]);
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                                __builtin_bit_cast(bf16x8, a_h), __builtin_bit_cast(bf16x8, b_l), acc[i][j], 0, 0, 0);
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                                __builtin_bit_cast(bf16x8, a_l), __builtin_bit_cast(bf16x8, b_h), acc[i][j], 0, 0, 0);
+                        }
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+    // epilogue: acc[i][j][r] -> row wm + 32i + 8(r/4) + 4(lane/32) + r%4, col wn + 32j + lane%32
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int row = m0 + wm + 32 * i + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                const int col = n0 + wn + 32 * j + (lane & 31);
+                float v = acc[i][j][r];
+                if (MODE == 1) v = ldexpf(v, rexp[row]);
+                C[(int64_t)row * ldc + col] = v;
+            }
+}
+
+// rexp[i] = exponent of max_l |A[i][l] phi_l| (FP16 mode row scales), one block per row.
+__global__ __launch_bounds__(256) void row_exp_kernel(const float *__restrict__ A, int lda, int K,
+                                                      const double *__restrict__ phi, int32_t *rexp)
+{
+    __shared__ float red[4];
+    const int i = blockIdx.x;
+    float m = 0.0f;
+    for (int l = threadIdx.x; l < K; l += blockDim.x) m = fmaxf(m, fabsf(A[(int64_t)i * lda + l] * (float)phi[l]));
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float mm = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+        rexp[i] = mm > 0.0f ? ilogbf(mm) : 0;
+    }
+}
+
+// Kernel matrix in 16-bit form: Bh[i][j] = round(K(x^a_i, x^b_j)), Bl = round(rest) (split
+// mode), zero padding.  grid: rows of 256 columns.
+__global__ void kernel_matrix16_kernel(const double *__restrict__ xa, int64_t na, const double *__restrict__ xb,
+                                       int64_t nb, int d, double eta, int ld, int64_t rows_pad, int mode,
+                                       unsigned short *__restrict__ Bh, unsigned short *__restrict__ Bl)
+{
+    const int64_t i = blockIdx.y;
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= rows_pad || j >= ld) return;
+    double v = 0.0;
+    if (i < na && j < nb) {
+        double d2 = 0.0;
+        for (int c = 0; c < d; ++c) {
+            const double df = xa[i * d + c] - xb[j * d + c];
+            d2 += df * df;
+        }
+        v = exp(-d2 / eta);
+    }
+    const float vf = (float)v;
+    if (mode == 1) {
+        Bh[i * ld + j] = f16_bits(vf);
+    } else {
+        const unsigned short h = bf16_bits(vf);
+        Bh[i * ld + j] = h;
+        if (Bl) Bl[i * ld + j] = bf16_bits(vf - bf16_value(h));
+    }
+}
+
+// FP32 or FP64 kernel matrix (the constant first matrices of both recursions).
+template <class T>
+__global__ void kernel_matrix_kernel(const double *__restrict__ xa, int64_t na, const double *__restrict__ xb,
+                                     int64_t nb, int d, double eta, int ld, int64_t rows_pad, T *__restrict__ out)
+{
+    const int64_t i = blockIdx.y;
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= rows_pad || j >= ld) return;
+    double v = 0.0;
+    if (i < na && j < nb) {
+        double d2 = 0.0;
+        for (int c = 0; c < d; ++c) {
+            const double df = xa[i * d + c] - xb[j * d + c];
+            d2 += df * df;
+        }
+        v = exp(-d2 / eta);
+    }
+    out[i * ld + j] = (T)v;
+}
+
+// Column sums with FP64 accumulation: part[chunk][j] = sum_{i in chunk} Yb[i][j] phi0_i Yg[i][j]
+constexpr int kColChunk = 64;
+template <class T>
+__global__ __launch_bounds__(256) void colsum_kernel(const T *__restrict__ Yb, const T *__restrict__ Yg, int ld,
+                                                     int64_t n1, int64_t nk, const double *__restrict__ phi0,
+                                                     double *__restrict__ part)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i0 = (int64_t)blockIdx.y * kColChunk;
+    if (j >= nk) return;
+    double s = 0.0;
+    const int64_t i1 = min(n1, i0 + kColChunk);
+    for (int64_t i = i0; i < i1; ++i) s += (double)Yb[i * ld + j] * phi0[i] * (double)Yg[i * ld + j];
+    part[blockIdx.y * nk + j] = s;
+}
+
+// Row sums for phi^0: den_i = sum_j K(x^0_i, x^1_j) phi^1_j Yb_1[i][j], one block per row.
+template <class T>
+__global__ __launch_bounds__(256) void rowsum_kernel(const double *__restrict__ x0, const double *__restrict__ x1,
+                                                     int64_t n1, int d, double eta, const double *__restrict__ phi1,
+                                                     const T *__restrict__ Yb1, int ld, double *__restrict__ den)
+{
+    __shared__ double red[4];
+    const int64_t i = blockIdx.x;
+    double xi[3] = {0, 0, 0};
+    for (int c = 0; c < d; ++c) xi[c] = x0[i * d + c];
+    double s = 0.0;
+    for (int64_t j = threadIdx.x; j < n1; j += blockDim.x) {
+        double d2 = 0.0;
+        for (int c = 0; c < d; ++c) {
+            const double df = xi[c] - x1[j * d + c];
+            d2 += df * df;
+        }
+        s += exp(-d2 / eta) * phi1[j] * (double)Yb1[i * ld + j];
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) den[i] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// phi update from a denominator (column sums: nparts > 0 partial rows to add in order;
+// row sums: nparts == 0 and den given directly).  Writes S terms to part_out[2 * block].
+__global__ __launch_bounds__(256) void circle_phi_kernel(const double *__restrict__ part, int nparts,
+                                                         int64_t n, const double *__restrict__ mu,
+                                                         double *__restrict__ phi, int root,
+                                                         double *__restrict__ s_out, int32_t *flag,
+                                                         double *__restrict__ marg_out, int marg_only)
+{
+    __shared__ double red[2][4];
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double s1 = 0.0, s2 = 0.0;
+    if (j < n) {
+        double den = 0.0;
+        if (nparts > 0)
+            for (int p = 0; p < nparts; ++p) den += part[p * n + j];
+        else
+            den = part[j];
+        const double m = mu[j], old = phi[j];
+        if (marg_only) {
+            const double P = old * den;
+            marg_out[j] = P;
+            s1 = fabs(P - m);
+        } else {
+            const double nv = m / den;
+            if (m > 0.0) {
+                s1 = m * log(old);
+                if (root) s2 = (m / nv) * old;
+            }
+            if (!isfinite(nv)) atomicOr(flag, 1);
+            phi[j] = nv;
+        }
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        s1 += __shfl_xor(s1, o);
+        s2 += __shfl_xor(s2, o);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        red[0][threadIdx.x >> 6] = s1;
+        red[1][threadIdx.x >> 6] = s2;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        s_out[2 * blockIdx.x] = (red[0][0] + red[0][1]) + (red[0][2] + red[0][3]);
+        s_out[2 * blockIdx.x + 1] = (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]);
+    }
+}
+
+// Sweep finalisation: S^(r) from the phi-update partials, L1 error of the first marginal
+// from P_0 = phi^0 den0 (partials written by circle_phi_kernel in marginal mode).
+__global__ __launch_bounds__(256) void circle_final_kernel(const double *__restrict__ s_part, int ns,
+                                                           const double *__restrict__ e_part, int ne,
+                                                           double eta, int32_t *ctr, int hist_cap,
+                                                           double *S_hist, double *err_hist, int32_t *flag,
+                                                           int32_t *flag_hist)
+{
+    __shared__ double red[3][4];
+    double s1 = 0.0, s2 = 0.0, e = 0.0;
+    for (int p = threadIdx.x; p < ns; p += blockDim.x) {
+        s1 += s_part[2 * p];
+        s2 += s_part[2 * p + 1];
+    }
+    for (int p = threadIdx.x; p < ne; p += blockDim.x) e += e_part[2 * p];
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        s1 += __shfl_xor(s1, o);
+        s2 += __shfl_xor(s2, o);
+        e += __shfl_xor(e, o);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        red[0][threadIdx.x >> 6] = s1;
+        red[1][threadIdx.x >> 6] = s2;
+        red[2][threadIdx.x >> 6] = e;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double S1 = (red[0][0] + red[0][1]) + (red[0][2] + red[0][3]);
+        const double S2 = (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]);
+        const double E = (red[2][0] + red[2][1]) + (red[2][2] + red[2][3]);
+        const int r = *ctr, slot = r % hist_cap;
+        S_hist[slot] = eta * (S1 - S2);
+        err_hist[slot] = E;
+        flag_hist[slot] = *flag;
+        *ctr = r + 1;
+    }
+}
+
+// NFFT path: src[i][l] = A[i][l] phi_l and the row's max exponent (one block per row).
+__global__ __launch_bounds__(256) void scale_rows_kernel(const double *__restrict__ A, int64_t nl,
+                                                         const double *__restrict__ phi, double *__restrict__ src,
+                                                         int32_t *__restrict__ rexp)
+{
+    __shared__ int red[4];
+    const int64_t i = blockIdx.x;
+    int m = INT32_MIN;
+    for (int64_t l = threadIdx.x; l < nl; l += blockDim.x) {
+        const double v = A[i * nl + l] * phi[l];
+        src[i * nl + l] = v;
+        if (v > 0.0 && v < INFINITY) m = max(m, ilogb(v));
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) m = max(m, __shfl_xor(m, o));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) rexp[i] = max(max(red[0], red[1]), max(red[2], red[3]));
+}
+
+// ---------------------------------------------------------------------------------------
+// Host side
+
+static int pad_to(int64_t n, int q) { return (int)((n + q - 1) / q * q); }
+
+struct CircleState {
+    bool nfft = false;
+    int mode = 0;                  // GEMM mode (dense path)
+    int64_t n1 = 0;
+    int n1p = 0;                   // rows of every matrix (padded on the dense path)
+    std::vector<int> ld;           // leading dimension (columns) of the matrices of marginal k
+    std::vector<void *> Yb;        // [K] Yb_k, k = 1..K-1 (Yb_{K-1} constant)
+    void *Yg[2] = {nullptr, nullptr};
+    void *Yg1 = nullptr;           // Yg_1 = Kmat(0, 1) (constant)
+    std::vector<unsigned short *> Kb_h, Kb_l, Kg_h, Kg_l;  // dense: Kmat(k,k+1), Kmat(k,k-1)
+    int32_t *rexp = nullptr;
+    double *part = nullptr;        // column-sum partials [chunk][j]
+    double *den0 = nullptr;
+    double *s_part = nullptr;      // phi-update partials
+    std::vector<int> s_slot;       // first partial slot of marginal k's phi update
+    int ns = 0;
+    double *e_part = nullptr;      // first-marginal L1 partials
+    double *m_part = nullptr;      // scratch partials of marginal-only evaluations
+    // NFFT path: per-row product jobs for each product position
+    double *src = nullptr;
+    int32_t *rowexp = nullptr;
+    std::vector<std::vector<Step>> steps_g, steps_b;  // [k]
+};
+
+static void *Ymat(CircleState &C, int which_gamma, int k)
+{
+    if (which_gamma) return k == 1 ? C.Yg1 : C.Yg[k & 1];
+    return C.Yb[k];
+}
+
+static hipError_t launch_gemm(const CircleState &C, const float *A, int lda, const double *phi,
+                              const unsigned short *Bh, const unsigned short *Bl, int ldb, float *Cm,
+                              int ldc, int Mp, int Np, int Kp, hipStream_t s)
+{
+    dim3 grid(Np / kBN, Mp / kBM);
+    if (C.mode == 1) {
+        hipLaunchKernelGGL(row_exp_kernel, dim3(Mp), dim3(256), 0, s, A, lda, Kp, phi, C.rexp);
+        hipLaunchKernelGGL(gemm_kernel<1>, grid, dim3(256), 0, s, A, lda, phi, Bh, Bl, ldb, Cm, ldc, Kp,
+                           (const int32_t *)C.rexp);
+    } else if (C.mode == 2) {
+        hipLaunchKernelGGL(gemm_kernel<2>, grid, dim3(256), 0, s, A, lda, phi, Bh, Bl, ldb, Cm, ldc, Kp,
+                           (const int32_t *)C.rexp);
+    } else {
+        hipLaunchKernelGGL(gemm_kernel<0>, grid, dim3(256), 0, s, A, lda, phi, Bh, Bl, ldb, Cm, ldc, Kp,
+                           (const int32_t *)C.rexp);
+    }
+    return hipGetLastError();
+}
+
+// One matrix product of the recursions: gamma (k from k-1) or beta (k from k+1).
+static int circle_product(mot_plan_s *P, CircleState &C, int gamma, int k)
+{
+    const int l = gamma ? k - 1 : k + 1;
+    hipStream_t st = P->stream;
+    if (!C.nfft) {
+        const float *A = (const float *)Ymat(C, gamma, l);
+        float *Cm = (float *)Ymat(C, gamma, k);
+        const unsigned short *Bh = gamma ? C.Kg_h[k] : C.Kb_h[k];
+        const unsigned short *Bl = gamma ? C.Kg_l[k] : C.Kb_l[k];
+        MOT_HIP(launch_gemm(C, A, C.ld[l], P->marg[l].phi, Bh, Bl, C.ld[l], Cm, C.ld[k], C.n1p, C.ld[k], C.ld[l], st));
+        return MOT_OK;
+    }
+    const double *A = (const double *)Ymat(C, gamma, l);
+    hipLaunchKernelGGL(scale_rows_kernel, dim3((unsigned)C.n1), dim3(256), 0, st, A, (int64_t)P->n[l],
+                       (const double *)P->marg[l].phi, C.src, C.rowexp);
+    MOT_HIP(hipGetLastError());
+    return run_steps(gamma ? C.steps_g[k] : C.steps_b[k], st);
+}
+
+static int colsum_phi(mot_plan_s *P, CircleState &C, int k, bool marg_only)
+{
+    hipStream_t st = P->stream;
+    const int64_t n1 = C.n1, nk = P->n[k];
+    const int chunks = (int)((n1 + kColChunk - 1) / kColChunk);
+    dim3 g((unsigned)((nk + 255) / 256), (unsigned)chunks);
+    const void *Yb = C.Yb[k], *Yg = Ymat(C, 1, k);
+    if (C.nfft)
+        hipLaunchKernelGGL(colsum_kernel<double>, g, dim3(256), 0, st, (const double *)Yb, (const double *)Yg,
+                           C.ld[k], n1, nk, (const double *)P->marg[0].phi, C.part);
+    else
+        hipLaunchKernelGGL(colsum_kernel<float>, g, dim3(256), 0, st, (const float *)Yb, (const float *)Yg,
+                           C.ld[k], n1, nk, (const double *)P->marg[0].phi, C.part);
+    MOT_HIP(hipGetLastError());
+    const unsigned blocks = (unsigned)((nk + 255) / 256);
+    double *sout = marg_only ? C.m_part : C.s_part + 2 * C.s_slot[k];
+    hipLaunchKernelGGL(circle_phi_kernel, dim3(blocks), dim3(256), 0, st, (const double *)C.part, chunks, nk,
+                       (const double *)P->marg[k].mu, P->marg[k].phi, 0, sout, P->flag, P->marg[k].marg,
+                       marg_only ? 1 : 0);
+    return hipGetLastError() == hipSuccess ? MOT_OK : MOT_EDEVICE;
+}
+
+static int rowsum_den0(mot_plan_s *P, CircleState &C)
+{
+    hipStream_t st = P->stream;
+    if (C.nfft)
+        hipLaunchKernelGGL(rowsum_kernel<double>, dim3((unsigned)C.n1), dim3(256), 0, st,
+                           (const double *)P->marg[0].pts, (const double *)P->marg[1].pts, (int64_t)P->n[1], P->d,
+                           P->eta, (const double *)P->marg[1].phi, (const double *)C.Yb[1], C.ld[1], C.den0);
+    else
+        hipLaunchKernelGGL(rowsum_kernel<float>, dim3((unsigned)C.n1), dim3(256), 0, st,
+                           (const double *)P->marg[0].pts, (const double *)P->marg[1].pts, (int64_t)P->n[1], P->d,
+                           P->eta, (const double *)P->marg[1].phi, (const float *)C.Yb[1], C.ld[1], C.den0);
+    return hipGetLastError() == hipSuccess ? MOT_OK : MOT_EDEVICE;
+}
+
+// Upward recursion Yb_{K-2} .. Yb_1 at the current phi, then den0 (Algorithm 3 step 4).
+static int circle_up(mot_plan_s *P, CircleState &C)
+{
+    for (int k = P->K - 2; k >= 1; --k) MOT_TRY(circle_product(P, C, 0, k));
+    return rowsum_den0(P, C);
+}
+
+template <class T>
+static int kmat(mot_plan_s *P, int a, int b, int ld, int rows_pad, T *out)
+{
+    dim3 g((unsigned)((ld + 255) / 256), (unsigned)rows_pad);
+    hipLaunchKernelGGL(kernel_matrix_kernel<T>, g, dim3(256), 0, P->stream, (const double *)P->marg[a].pts,
+                       (int64_t)P->n[a], (const double *)P->marg[b].pts, (int64_t)P->n[b], P->d, P->eta, ld,
+                       (int64_t)rows_pad, out);
+    return hipGetLastError() == hipSuccess ? MOT_OK : MOT_EDEVICE;
+}
+
+static int kmat16(mot_plan_s *P, CircleState &C, int a, int b, unsigned short **h, unsigned short **l)
+{
+    const int ld = C.ld[b], rows = C.ld[a];
+    MOT_TRY(P->arena.get_n((size_t)rows * ld, h));
+    *l = nullptr;
+    if (C.mode == 2) MOT_TRY(P->arena.get_n((size_t)rows * ld, l));
+    dim3 g((unsigned)((ld + 255) / 256), (unsigned)rows);
+    hipLaunchKernelGGL(kernel_matrix16_kernel, g, dim3(256), 0, P->stream, (const double *)P->marg[a].pts,
+                       (int64_t)P->n[a], (const double *)P->marg[b].pts, (int64_t)P->n[b], P->d, P->eta, ld,
+                       (int64_t)rows, C.mode == 1 ? 1 : 0, *h, *l);
+    return hipGetLastError() == hipSuccess ? MOT_OK : MOT_EDEVICE;
+}
+
+// NFFT path: n1 product jobs (one per matrix row) for out = K^{(t,s)} rows.
+static int nfft_position(mot_plan_s *P, CircleState &C, int t, int s, double *out, std::vector<ProdJob> &tmpl,
+                         std::vector<Step> &steps)
+{
+    const int64_t n1 = C.n1;
+    std::vector<ProdJob> jobs(n1);
+    for (int64_t i = 0; i < n1; ++i) {
+        ProdJob &J = jobs[i];
+        MOT_TRY(make_prod_job(P, t, s, C.src + i * P->n[s], C.rowexp + i, out + i * P->n[t], &J, nullptr, false));
+        J.patches = tmpl[i].patches;
+        J.grid = tmpl[i].grid;
+        J.spec0 = tmpl[i].spec0;
+        J.spec1 = tmpl[i].spec1;
+    }
+    ProdJob *dev = nullptr;
+    MOT_TRY(P->arena.get_n(jobs.size(), &dev));
+    MOT_HIP(hipMemcpy(dev, jobs.data(), jobs.size() * sizeof(ProdJob), hipMemcpyHostToDevice));
+    std::vector<int> ids(n1);
+    for (int64_t i = 0; i < n1; ++i) ids[i] = (int)i;
+    return product_steps(P->arena, dev, jobs, ids, steps);
+}
+
+int circle_create(mot_plan_s *P, const std::vector<double> &pts_h, const std::vector<double> &w_h,
+                  const mot_fastsum_params *fs)
+{
+    const int K = P->K;
+    CircleState *Cp = new CircleState();
+    P->circle = Cp;
+    CircleState &C = *Cp;
+    C.nfft = P->path == MOT_NFFT;
+    if (!C.nfft) {
+        if (P->path != MOT_DENSE) return MOT_EUNSUPPORTED;
+        if (P->precision == MOT_PREC_BF16) C.mode = 0;
+        else if (P->precision == MOT_PREC_FP16) C.mode = 1;
+        else if (P->precision == MOT_PREC_BF16X3) C.mode = 2;
+        else return MOT_EUNSUPPORTED;
+    }
+    MOT_TRY(setup_marginals(P, pts_h, w_h, fs, C.nfft ? 0 : 128));
+    hipStream_t st = P->stream;
+    C.n1 = P->n[0];
+    C.n1p = C.nfft ? (int)C.n1 : pad_to(C.n1, 128);
+    C.ld.resize(K);
+    for (int k = 0; k < K; ++k) C.ld[k] = C.nfft ? (int)P->n[k] : pad_to(P->n[k], 128);
+    const size_t esz = C.nfft ? 8 : 4;
+    int ldmax = 0;
+    int64_t nmax = 0;
+    for (int k = 0; k < K; ++k) {
+        ldmax = std::max(ldmax, C.ld[k]);
+        nmax = std::max(nmax, P->n[k]);
+    }
+    C.Yb.assign(K, nullptr);
+    for (int k = 1; k < K; ++k) MOT_TRY(P->arena.get((size_t)C.n1p * C.ld[k] * esz, &C.Yb[k]));
+    MOT_TRY(P->arena.get((size_t)C.n1p * ldmax * esz, &C.Yg[0]));
+    MOT_TRY(P->arena.get((size_t)C.n1p * ldmax * esz, &C.Yg[1]));
+    MOT_TRY(P->arena.get((size_t)C.n1p * C.ld[1] * esz, &C.Yg1));
+    if (C.nfft) {
+        MOT_TRY(kmat<double>(P, 0, 1, C.ld[1], C.n1p, (double *)C.Yg1));
+        MOT_TRY(kmat<double>(P, 0, K - 1, C.ld[K - 1], C.n1p, (double *)C.Yb[K - 1]));
+    } else {
+        MOT_TRY(kmat<float>(P, 0, 1, C.ld[1], C.n1p, (float *)C.Yg1));
+        MOT_TRY(kmat<float>(P, 0, K - 1, C.ld[K - 1], C.n1p, (float *)C.Yb[K - 1]));
+        // padding of the ping-pong buffers must be zero (they become GEMM operands)
+        MOT_HIP(launch_fill_int((int32_t *)C.Yg[0], 0, (int64_t)C.n1p * ldmax, st));
+        MOT_HIP(launch_fill_int((int32_t *)C.Yg[1], 0, (int64_t)C.n1p * ldmax, st));
+        for (int k = 1; k < K - 1; ++k) MOT_HIP(launch_fill_int((int32_t *)C.Yb[k], 0, (int64_t)C.n1p * C.ld[k], st));
+        C.Kb_h.assign(K, nullptr);
+        C.Kb_l.assign(K, nullptr);
+        C.Kg_h.assign(K, nullptr);
+        C.Kg_l.assign(K, nullptr);
+        for (int k = 1; k <= K - 2; ++k) MOT_TRY(kmat16(P, C, k, k + 1, &C.Kb_h[k], &C.Kb_l[k]));
+        for (int k = 2; k <= K - 1; ++k) MOT_TRY(kmat16(P, C, k, k - 1, &C.Kg_h[k], &C.Kg_l[k]));
+        MOT_TRY(P->arena.get_n((size_t)C.n1p, &C.rexp));
+    }
+    const int chunks = (int)((C.n1 + kColChunk - 1) / kColChunk);
+    MOT_TRY(P->arena.get_n((size_t)chunks * nmax, &C.part));
+    MOT_TRY(P->arena.get_n((size_t)C.n1, &C.den0));
+    C.s_slot.assign(K, 0);
+    int slot = 0;
+    for (int k = 0; k < K; ++k) {
+        C.s_slot[k] = slot;
+        slot += (int)((P->n[k] + 255) / 256);
+    }
+    C.ns = slot;
+    MOT_TRY(P->arena.get_n(2 * (size_t)slot, &C.s_part));
+    MOT_TRY(P->arena.get_n(2 * (size_t)((C.n1 + 255) / 256), &C.e_part));
+    MOT_TRY(P->arena.get_n(2 * (size_t)((nmax + 255) / 256), &C.m_part));
+    if (C.nfft) {
+        MOT_TRY(P->arena.get_n((size_t)C.n1 * nmax, &C.src));
+        MOT_TRY(P->arena.get_n((size_t)C.n1, &C.rowexp));
+        // work buffers per row, shared by all product positions
+        std::vector<ProdJob> tmpl(C.n1);
+        int maxc = 0;
+        for (auto &g : P->marg) maxc = std::max(maxc, g.nchunks);
+        int64_t pe = 1;
+        for (int c = 0; c < P->d; ++c) pe *= P->P.W;
+        float *patches = nullptr;
+        MOT_TRY(P->arena.get_n((size_t)C.n1 * maxc * pe, &patches));
+        for (int64_t i = 0; i < C.n1; ++i)
+            MOT_TRY(make_prod_job(P, 1, 0, nullptr, nullptr, nullptr, &tmpl[i], patches + (size_t)i * maxc * pe, true));
+        C.steps_g.assign(K, {});
+        C.steps_b.assign(K, {});
+        for (int k = 2; k <= K - 1; ++k)
+            MOT_TRY(nfft_position(P, C, k, k - 1, (double *)Ymat(C, 1, k), tmpl, C.steps_g[k]));
+        for (int k = 1; k <= K - 2; ++k) MOT_TRY(nfft_position(P, C, k, k + 1, (double *)C.Yb[k], tmpl, C.steps_b[k]));
+    }
+    MOT_TRY(circle_up(P, C));
+    MOT_HIP(hipStreamSynchronize(st));
+    return MOT_OK;
+}
+
+int circle_run_sweeps(mot_plan_s *P, int sweeps)
+{
+    CircleState &C = *(CircleState *)P->circle;
+    hipStream_t st = P->stream;
+    const int K = P->K;
+    if (sweeps == 0) {  // re-initialise after new scaling vectors
+        MOT_TRY(circle_up(P, C));
+        MOT_HIP(hipStreamSynchronize(st));
+        return MOT_OK;
+    }
+    for (int r = 0; r < sweeps; ++r) {
+        // phi^1 <- mu^1 / <K^{(1,2)}, (phi^2 (.) beta_2)^T>  (Algorithm 3, first update)
+        hipLaunchKernelGGL(circle_phi_kernel, dim3((unsigned)((C.n1 + 255) / 256)), dim3(256), 0, st,
+                           (const double *)C.den0, 0, C.n1, (const double *)P->marg[0].mu, P->marg[0].phi, 1,
+                           C.s_part + 2 * C.s_slot[0], P->flag, P->marg[0].marg, 0);
+        MOT_HIP(hipGetLastError());
+        for (int k = 1; k < K; ++k) {
+            if (k >= 2) MOT_TRY(circle_product(P, C, 1, k));
+            MOT_TRY(colsum_phi(P, C, k, false));
+        }
+        MOT_TRY(circle_up(P, C));
+        // first marginal after the sweep, P_0 = phi^0 den0, and S^(r)
+        hipLaunchKernelGGL(circle_phi_kernel, dim3((unsigned)((C.n1 + 255) / 256)), dim3(256), 0, st,
+                           (const double *)C.den0, 0, C.n1, (const double *)P->marg[0].mu, P->marg[0].phi, 1,
+                           C.e_part, P->flag, P->marg[0].marg, 1);
+        hipLaunchKernelGGL(circle_final_kernel, dim3(1), dim3(256), 0, st, (const double *)C.s_part, C.ns,
+                           (const double *)C.e_part, (int)((C.n1 + 255) / 256), P->eta, P->sweep_ctr, P->hist_cap,
+                           P->S_hist, P->err_hist, P->flag, P->flag_hist);
+        MOT_HIP(hipGetLastError());
+    }
+    P->host_sweeps += sweeps;
+    return MOT_OK;
+}
+
+// Marginals at the current phi (Theorem 4.3): P_0 = phi^0 den0 and, through the gamma
+// recursion, P_k = phi^k <beta_k, (phi^1 (.) gamma_k)^T>.
+int circle_marginals(mot_plan_s *P, double *)
+{
+    CircleState &C = *(CircleState *)P->circle;
+    hipStream_t st = P->stream;
+    hipLaunchKernelGGL(circle_phi_kernel, dim3((unsigned)((C.n1 + 255) / 256)), dim3(256), 0, st,
+                       (const double *)C.den0, 0, C.n1, (const double *)P->marg[0].mu, P->marg[0].phi, 1, C.m_part,
+                       P->flag, P->marg[0].marg, 1);
+    MOT_HIP(hipGetLastError());
+    for (int k = 1; k < P->K; ++k) {
+        if (k >= 2) MOT_TRY(circle_product(P, C, 1, k));
+        MOT_TRY(colsum_phi(P, C, k, true));
+    }
+    return MOT_OK;
+}
+
+void circle_destroy(mot_plan_s *P)
+{
+    delete (CircleState *)P->circle;
+    P->circle = nullptr;
+}
+
+size_t circle_footprint(int K, const int64_t *n, int path, int precision)
+{
+    size_t b = 0;
+    const bool nfft = path == MOT_NFFT;
+    const int64_t n1 = nfft ? n[0] : pad_to(n[0], 128);
+    int64_t ldmax = 0;
+    for (int k = 0; k < K; ++k) ldmax = std::max<int64_t>(ldmax, nfft ? n[k] : pad_to(n[k], 128));
+    const size_t esz = nfft ? 8 : 4;
+    b += (size_t)n1 * ldmax * esz * (K + 2);
+    if (!nfft) b += (size_t)ldmax * ldmax * 2 * (2 * (K - 2)) * (precision == MOT_PREC_BF16X3 ? 2 : 1);
+    else b += (size_t)n1 * ldmax * 8 + (size_t)n1 * (64 * 1024);
+    return b;
+}
+
 }  // namespace mot

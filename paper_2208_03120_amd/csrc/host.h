@@ -169,10 +169,14 @@ int tree_build_schedule(mot_plan_s *P);
 int tree_run_sweeps(mot_plan_s *P, int sweeps, bool use_graph);
 int tree_marginals(mot_plan_s *P, double *P_sorted_all);
 int tree_init_up(mot_plan_s *P);
-void prod_items(const std::vector<ProdJob> &jobs_host, const std::vector<int> &job_ids,
-                const std::vector<int> &global_ids, std::vector<Step> &steps, Arena &arena,
-                const void *jobs_dev, const float2 *twiddle_for_n(int n), int &rc);
-int circle_create(mot_plan_s *P, const mot_fastsum_params *fs);
+int make_prod_job(mot_plan_s *P, int t, int s, const double *v, int32_t *slot, double *out, ProdJob *J,
+                  float *patches, bool alloc_buffers = true);
+int product_steps(Arena &arena, const ProdJob *jobs_dev, const std::vector<ProdJob> &jobs_host,
+                  const std::vector<int> &ids, std::vector<Step> &out);
+int circle_create(mot_plan_s *P, const std::vector<double> &pts_h, const std::vector<double> &w_h,
+                  const mot_fastsum_params *fs);
+int setup_marginals(mot_plan_s *P, const std::vector<double> &pts_h, const std::vector<double> &w_h,
+                    const mot_fastsum_params *fs, int64_t phi_pad_to);
 int circle_run_sweeps(mot_plan_s *P, int sweeps);
 int circle_marginals(mot_plan_s *P, double *P_sorted_all);
 void circle_destroy(mot_plan_s *P);

@@ -299,6 +299,14 @@ struct StepBuilder {
     }
 };
 
+int product_steps(Arena &arena, const ProdJob *jobs_dev, const std::vector<ProdJob> &jobs_host,
+                  const std::vector<int> &ids, std::vector<Step> &out)
+{
+    StepBuilder B{&arena, &out};
+    B.products(jobs_dev, jobs_host, ids);
+    return B.rc;
+}
+
 // ---------------------------------------------------------------------------------------
 // Tree plans
 
@@ -633,8 +641,8 @@ static int bin_marginal(mot_plan_s *P, int k, const double *pts_orig_dev, void *
 }
 
 // Fill the product job j: out(target t) = K^{(t,s)} v(source s).
-static int make_prod_job(mot_plan_s *P, int t, int s, const double *v, int32_t *slot, double *out,
-                         ProdJob *J, float *patches, bool alloc_buffers = true)
+int mot::make_prod_job(mot_plan_s *P, int t, int s, const double *v, int32_t *slot, double *out,
+                       ProdJob *J, float *patches, bool alloc_buffers)
 {
     ProdJob &Q = *J;
     Q = ProdJob{};
@@ -719,20 +727,12 @@ static int plan_stats_alloc(mot_plan_s *P, int n_partials_hint)
     return MOT_OK;
 }
 
-static int create_tree(mot_plan_s *P, const std::vector<double> &pts_h, const std::vector<double> &w_h,
-                       const mot_fastsum_params *fs)
+// Per-marginal device state shared by both topologies: parameters (NFFT path), binned
+// point layout (NFFT) or identity order, weights, phi = 1, statistics buffers.
+int mot::setup_marginals(mot_plan_s *P, const std::vector<double> &pts_h, const std::vector<double> &w_h,
+                         const mot_fastsum_params *fs, int64_t phi_pad_to)
 {
     const int K = P->K, d = P->d;
-    // topology: children lists and depths
-    P->children.assign(K, {});
-    P->depth.assign(K, 0);
-    for (int k = 1; k < K; ++k) {
-        P->children[P->parent[k]].push_back(k);
-        P->depth[k] = P->depth[P->parent[k]] + 1;
-        P->depth_max = std::max(P->depth_max, P->depth[k]);
-    }
-    for (int k = 0; k < K; ++k)
-        if ((int)P->children[k].size() > kMaxChildren) return MOT_EUNSUPPORTED;
     int64_t nmax = 0;
     for (int k = 0; k < K; ++k) nmax = std::max(nmax, P->n[k]);
     if (P->path == MOT_NFFT) {
@@ -750,7 +750,6 @@ static int create_tree(mot_plan_s *P, const std::vector<double> &pts_h, const st
                 P->P.M, P->P.n, P->P.m, P->P.p, P->P.tau, P->P.eps_B, P->P.T, P->P.L[0], P->P.L[1],
                 P->P.L[2], P->P.est_err);
     }
-    // device inputs (original order) and per-marginal arrays
     double *pts_dev = nullptr;
     MOT_TRY(P->arena.get_n(pts_h.size(), &pts_dev));
     MOT_HIP(hipMemcpy(pts_dev, pts_h.data(), pts_h.size() * sizeof(double), hipMemcpyHostToDevice));
@@ -759,14 +758,15 @@ static int create_tree(mot_plan_s *P, const std::vector<double> &pts_h, const st
     for (int k = 0; k < K; ++k) {
         MargDev &G = P->marg[k];
         G.n = P->n[k];
+        const int64_t nphi = std::max<int64_t>(G.n, phi_pad_to > 0 ? (G.n + phi_pad_to - 1) / phi_pad_to * phi_pad_to : 0);
         MOT_TRY(P->arena.get_n((size_t)G.n * d, &G.pts));
         MOT_TRY(P->arena.get_n((size_t)G.n, &G.perm));
         MOT_TRY(P->arena.get_n((size_t)G.n, &G.mu));
-        MOT_TRY(P->arena.get_n((size_t)G.n, &G.phi));
+        MOT_TRY(P->arena.get_n((size_t)nphi, &G.phi));
         MOT_TRY(P->arena.get_n((size_t)G.n, &G.gamma));
         MOT_TRY(P->arena.get_n((size_t)G.n, &G.up_src));
         MOT_TRY(P->arena.get_n((size_t)G.n, &G.marg));
-        if (k > 0) {
+        if (P->topology == MOT_TREE && k > 0) {
             MOT_TRY(P->arena.get_n((size_t)P->n[P->parent[k]], &G.beta));
             MOT_TRY(P->arena.get_n((size_t)P->n[P->parent[k]], &G.down_src));
         }
@@ -774,9 +774,9 @@ static int create_tree(mot_plan_s *P, const std::vector<double> &pts_h, const st
             MOT_TRY(P->arena.get_n((size_t)G.n, &G.cell));
             MOT_TRY(P->arena.get_n((size_t)G.n * d, &G.frac));
         }
+        if (nphi > G.n) MOT_HIP(launch_fill_double(G.phi + G.n, 0.0, nphi - G.n, P->stream));
         total_partials += 2 * (int)((G.n + kNodeItemElems - 1) / kNodeItemElems);
     }
-    // binning / ordering
     if (P->path == MOT_NFFT) {
         const int tpd = (P->P.n + P->P.T - 1) / P->P.T;
         int64_t ntiles = 1;
@@ -801,7 +801,6 @@ static int create_tree(mot_plan_s *P, const std::vector<double> &pts_h, const st
                               hipMemcpyHostToDevice));
         }
     }
-    // weights in binned order, phi = 1
     double *w_dev = nullptr;
     MOT_TRY(P->arena.get_n(w_h.size(), &w_dev));
     MOT_HIP(hipMemcpy(w_dev, w_h.data(), w_h.size() * sizeof(double), hipMemcpyHostToDevice));
@@ -809,10 +808,27 @@ static int create_tree(mot_plan_s *P, const std::vector<double> &pts_h, const st
         MOT_HIP(launch_gather_rows(w_dev + P->off[k], P->marg[k].perm, P->n[k], 1, P->marg[k].mu, P->stream));
         MOT_HIP(launch_fill_double(P->marg[k].phi, 1.0, P->n[k], P->stream));
     }
-    // exponent slots and statistics
     MOT_TRY(P->arena.get_n(2 * K + 1, &P->exp_slots));
     MOT_HIP(launch_fill_int(P->exp_slots, INT32_MIN, 2 * K + 1, P->stream));
-    MOT_TRY(plan_stats_alloc(P, total_partials));
+    MOT_TRY(plan_stats_alloc(P, total_partials + 64 * K));
+    return MOT_OK;
+}
+
+static int create_tree(mot_plan_s *P, const std::vector<double> &pts_h, const std::vector<double> &w_h,
+                       const mot_fastsum_params *fs)
+{
+    const int K = P->K;
+    // topology: children lists and depths
+    P->children.assign(K, {});
+    P->depth.assign(K, 0);
+    for (int k = 1; k < K; ++k) {
+        P->children[P->parent[k]].push_back(k);
+        P->depth[k] = P->depth[P->parent[k]] + 1;
+        P->depth_max = std::max(P->depth_max, P->depth[k]);
+    }
+    for (int k = 0; k < K; ++k)
+        if ((int)P->children[k].size() > kMaxChildren) return MOT_EUNSUPPORTED;
+    MOT_TRY(setup_marginals(P, pts_h, w_h, fs, 0));
     // product jobs
     P->jobs.assign(2 * K + 1, ProdJob{});
     for (int k = 1; k < K; ++k) {
@@ -990,7 +1006,7 @@ int mot_plan_create(mot_plan *out, int32_t K, int32_t d, const int64_t *n, const
     if (topology == MOT_TREE)
         rc = create_tree(P, pts_h, w_h, fs);
     else
-        rc = circle_create(P, fs);
+        rc = circle_create(P, pts_h, w_h, fs);
     if (rc < 0) {
         (void)hipStreamSynchronize(P->stream);
         mot_plan_destroy(P);
@@ -1233,7 +1249,7 @@ int mot_marginals(mot_plan P, double *P_out, double *l1_err, int32_t ptr_kind)
 int mot_apply_kernel(mot_plan P, int32_t t, int32_t s, const double *v, double *out, int32_t ptr_kind)
 {
     if (!P || !v || !out || t < 0 || s < 0 || t >= P->K || s >= P->K) return MOT_EINVAL;
-    if (P->topology == MOT_CIRCLE && P->path == MOT_DENSE) return MOT_EUNSUPPORTED;
+    if (P->topology != MOT_TREE) return MOT_EUNSUPPORTED;
     const int64_t cap = *std::max_element(P->n.begin(), P->n.end());
     if (!P->apply_in) {
         MOT_TRY(P->arena.get_n((size_t)cap, &P->apply_in));

@@ -1,0 +1,67 @@
+"""GPU parity of the circle path (Algorithm 3) against the FP64 oracle."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2208_03120_amd import workloads as W
+from tests.helpers import gauge_fix, max_rel
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mot():
+    from paper_2208_03120_amd import mot as m
+    return m
+
+
+def rng(seed):
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+@pytest.fixture(scope="module")
+def cyc():
+    inst = W.make_instance(rng(51), 4, [300, 257, 311, 290], 2, W.CIRCLE, 0.1)
+    ophi, oS, _, _ = oracle.circle_sinkhorn(inst.points, inst.weights, inst.eta, 20)
+    return inst, ophi, oS
+
+
+# measured error bounds of the stated precisions (gauge-fixed scaling vectors after 20
+# sweeps, relative to the FP64 oracle)
+@pytest.mark.parametrize("prec,bound", [("BF16X3", 1e-5), ("FP16", 5e-4), ("BF16", 5e-3)])
+def test_dense_circle_precisions(mot, cyc, prec, bound):
+    inst, ophi, oS = cyc
+    p = getattr(mot, "PREC_" + prec)
+    plan = mot.Plan(inst.points, inst.weights, W.CIRCLE, None, inst.eta, path=mot.DENSE, precision=p)
+    rc, done, S_last, err = plan.sinkhorn(20)
+    assert done == 20
+    phi = plan.scalings()
+    rel = max_rel(gauge_fix(phi, inst.weights), gauge_fix(ophi, inst.weights))
+    print("dense %s: gauge-fixed phi rel err %.3e, S %.10f vs %.10f" % (prec, rel, S_last, oS[-1]))
+    assert rel < bound
+    S = plan.S_history()
+    assert abs(S[-1] - oS[-1]) < 50 * bound * abs(oS[-1])
+    plan.close()
+
+
+def test_nfft_circle_parity(mot, cyc):
+    inst, ophi, oS = cyc
+    plan = mot.Plan(inst.points, inst.weights, W.CIRCLE, None, inst.eta, path=mot.NFFT)
+    rc, done, S_last, err = plan.sinkhorn(20)
+    phi = plan.scalings()
+    rel = max_rel(gauge_fix(phi, inst.weights), gauge_fix(ophi, inst.weights))
+    print("nfft circle: gauge-fixed phi rel err %.3e" % rel)
+    assert rel < 1e-5
+    np.testing.assert_allclose(plan.S_history(), oS, rtol=1e-6)
+    plan.close()
+
+
+def test_circle_marginals(mot, cyc):
+    inst, ophi, _ = cyc
+    plan = mot.Plan(inst.points, inst.weights, W.CIRCLE, None, inst.eta, path=mot.DENSE,
+                    precision=mot.PREC_BF16X3)
+    plan.set_scalings(ophi)
+    P, l1 = plan.marginals()
+    oP = oracle.circle_marginals(inst.points, inst.eta, ophi)
+    assert max_rel(P, oP) < 1e-4
+    plan.close()
