@@ -1,0 +1,107 @@
+// Batched form (a11): many tree plans advanced by shared launches.
+//
+// The product, node and finalisation jobs of all plans are concatenated into one set of
+// device job tables; the merged sweep runs, for every tree depth, one set of launches
+// covering the edges at that depth in every plan (grouped by dimension and FFT size),
+// and is captured once as a HIP graph.  Each plan keeps its own buffers, statistics
+// and exponent slots, so its results are those of running it alone.
+#include <algorithm>
+
+#include "host.h"
+
+struct mot_batch_s {
+    std::vector<mot_plan_s *> plans;
+    hipStream_t stream = nullptr;
+    mot::Arena arena;
+    std::vector<mot::Step> sweep, init_up, marg;
+    hipGraph_t graph_def = nullptr;
+    hipGraphExec_t graph = nullptr;
+};
+
+using namespace mot;
+
+extern "C" {
+
+int mot_batch_destroy(mot_batch B)
+{
+    if (!B) return MOT_EINVAL;
+    if (B->stream) (void)hipStreamSynchronize(B->stream);
+    if (B->graph) (void)hipGraphExecDestroy(B->graph);
+    if (B->graph_def) (void)hipGraphDestroy(B->graph_def);
+    B->arena.release();
+    delete B;
+    return MOT_OK;
+}
+
+int mot_batch_create(mot_batch *out, mot_plan *plans, int32_t count)
+{
+    if (!out || !plans || count < 1) return MOT_EINVAL;
+    *out = nullptr;
+    for (int i = 0; i < count; ++i) {
+        if (!plans[i] || plans[i]->topology != MOT_TREE) return MOT_EINVAL;
+        if (plans[i]->device != plans[0]->device) return MOT_EINVAL;
+    }
+    mot_batch_s *B = new mot_batch_s();
+    B->plans.assign(plans, plans + count);
+    B->stream = plans[0]->stream;
+    std::vector<ProdJob> pj;
+    std::vector<NodeJob> nj;
+    std::vector<FinalJob> fj;
+    std::vector<TreeRef> refs;
+    for (mot_plan_s *P : B->plans) {
+        TreeTables *T = tables_of(P);
+        if (!T) {
+            delete B;
+            return MOT_EINVAL;
+        }
+        refs.push_back({P, (int)pj.size(), (int)nj.size(), (int)fj.size()});
+        pj.insert(pj.end(), P->jobs.begin(), P->jobs.end());
+        nj.insert(nj.end(), T->njobs.begin(), T->njobs.end());
+        fj.insert(fj.end(), T->fjob.begin(), T->fjob.end());
+    }
+    ProdJob *pj_dev = nullptr;
+    NodeJob *nj_dev = nullptr;
+    FinalJob *fj_dev = nullptr;
+    int rc = B->arena.get_n(pj.size(), &pj_dev);
+    if (rc >= 0) rc = B->arena.get_n(nj.size(), &nj_dev);
+    if (rc >= 0) rc = B->arena.get_n(fj.size(), &fj_dev);
+    if (rc >= 0 && (hipMemcpy(pj_dev, pj.data(), pj.size() * sizeof(ProdJob), hipMemcpyHostToDevice) != hipSuccess ||
+                    hipMemcpy(nj_dev, nj.data(), nj.size() * sizeof(NodeJob), hipMemcpyHostToDevice) != hipSuccess ||
+                    hipMemcpy(fj_dev, fj.data(), fj.size() * sizeof(FinalJob), hipMemcpyHostToDevice) != hipSuccess))
+        rc = MOT_EDEVICE;
+    if (rc >= 0) rc = tree_steps(refs, pj, pj_dev, nj, nj_dev, fj, fj_dev, B->arena, B->sweep, B->init_up, B->marg);
+    if (rc < 0) {
+        mot_batch_destroy(B);
+        return rc;
+    }
+    *out = B;
+    return MOT_OK;
+}
+
+int mot_batch_sinkhorn(mot_batch B, int32_t sweeps, int32_t use_graph)
+{
+    if (!B || sweeps < 0) return MOT_EINVAL;
+    // work queued on the plans' own streams must finish first
+    for (mot_plan_s *P : B->plans)
+        if (P->stream != B->stream) MOT_HIP(hipStreamSynchronize(P->stream));
+    if (use_graph && !B->graph && sweeps > 0) {
+        MOT_HIP(hipStreamBeginCapture(B->stream, hipStreamCaptureModeThreadLocal));
+        int rc = run_steps(B->sweep, B->stream);
+        hipError_t e = hipStreamEndCapture(B->stream, &B->graph_def);
+        if (rc < 0) return rc;
+        MOT_HIP(e);
+        MOT_HIP(hipGraphInstantiate(&B->graph, B->graph_def, nullptr, nullptr, 0));
+    }
+    for (int r = 0; r < sweeps; ++r) {
+        if (use_graph) {
+            MOT_HIP(hipGraphLaunch(B->graph, B->stream));
+        } else {
+            MOT_TRY(run_steps(B->sweep, B->stream));
+        }
+    }
+    for (mot_plan_s *P : B->plans) P->host_sweeps += sweeps;
+    MOT_HIP(hipStreamSynchronize(B->stream));
+    return MOT_OK;
+}
+
+}  // extern "C"

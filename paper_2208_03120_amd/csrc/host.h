@@ -165,6 +165,26 @@ struct mot_plan_s {
 };
 
 namespace mot {
+// Per-plan host-side job tables of a tree plan (kept for batching).
+struct TreeTables {
+    std::vector<NodeJob> njobs;  // [0,K) down, [K,2K) up, [2K,3K) init-up, [3K,4K) marginal
+    std::vector<FinalJob> fjob;
+    NodeJob *njobs_dev = nullptr;
+    FinalJob *fjob_dev = nullptr;
+    int n_down_partials = 0, n_marg_partials = 0;
+    std::vector<int> marg_block0;  // first partial slot of each node's marginal job
+};
+TreeTables *tables_of(const mot_plan_s *P);
+
+// A plan inside a merged schedule: offsets of its product, node and final jobs.
+struct TreeRef {
+    mot_plan_s *P;
+    int pbase, nbase, fbase;
+};
+int tree_steps(const std::vector<TreeRef> &refs, const std::vector<ProdJob> &pj, const ProdJob *pj_dev,
+               const std::vector<NodeJob> &nj, const NodeJob *nj_dev, const std::vector<FinalJob> &fj,
+               const FinalJob *fj_dev, Arena &arena, std::vector<Step> &sweep, std::vector<Step> &init_up,
+               std::vector<Step> &marg);
 int tree_build_schedule(mot_plan_s *P);
 int tree_run_sweeps(mot_plan_s *P, int sweeps, bool use_graph);
 int tree_marginals(mot_plan_s *P, double *P_sorted_all);

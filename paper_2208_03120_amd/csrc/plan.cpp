@@ -318,16 +318,6 @@ struct TreeNodeJobs {
 
 using namespace mot;
 
-// Per-plan host-side job tables (kept with the plan for batching).
-struct TreeTables {
-    std::vector<NodeJob> njobs;  // [0,K) down, [K,2K) up, [2K,3K) init-up, [3K,4K) marginal
-    std::vector<FinalJob> fjob;
-    NodeJob *njobs_dev = nullptr;
-    FinalJob *fjob_dev = nullptr;
-    int n_down_partials = 0, n_marg_partials = 0;
-    std::vector<int> marg_block0;  // first partial slot of each node's marginal job
-};
-
 static std::map<const mot_plan_s *, TreeTables *> &tables_map()
 {
     static std::map<const mot_plan_s *, TreeTables *> m;
@@ -335,7 +325,7 @@ static std::map<const mot_plan_s *, TreeTables *> &tables_map()
 }
 static std::mutex g_tables_mu;
 
-static TreeTables *tables_of(const mot_plan_s *P)
+TreeTables *mot::tables_of(const mot_plan_s *P)
 {
     std::lock_guard<std::mutex> lk(g_tables_mu);
     auto it = tables_map().find(P);
@@ -453,11 +443,6 @@ int tree_build_schedule(mot_plan_s *P)
 // Steps of one sweep / the initial upward pass / the marginal pass for a set of tree
 // plans whose node, product and final jobs are concatenated in the given device
 // arrays (offsets per plan).
-struct TreeRef {
-    mot_plan_s *P;
-    int pbase, nbase, fbase;
-};
-
 int tree_steps(const std::vector<TreeRef> &refs, const std::vector<ProdJob> &pj,
                const ProdJob *pj_dev, const std::vector<NodeJob> &nj, const NodeJob *nj_dev,
                const std::vector<FinalJob> &fj, const FinalJob *fj_dev, Arena &arena,

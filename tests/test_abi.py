@@ -1,0 +1,75 @@
+"""The C ABI library loads and exports what include/mot.h declares; host-side argument
+validation and the footprint model work without a GPU."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def mot():
+    from paper_2208_03120_amd import mot as m
+    return m
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "mot.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mot_[A-Za-z0-9_]+)\s*\(", text)))
+
+
+def test_every_declared_function_is_exported(mot):
+    names = header_functions()
+    assert len(names) >= 20
+    lib = mot.lib()
+    for name in names:
+        assert hasattr(lib, name), name
+    assert sorted(mot.EXPORTED) == names
+
+
+def test_status_constants_match_header(mot):
+    text = open(os.path.join(ROOT, "include", "mot.h")).read()
+    vals = dict((k, int(v)) for k, v in re.findall(r"#define (MOT_[A-Z0-9_]+) \(?(-?\d+)\)?", text))
+    assert vals["MOT_OK"] == mot.OK and vals["MOT_MAXITER"] == mot.MAXITER
+    assert vals["MOT_EINVAL"] == mot.EINVAL and vals["MOT_ENUMERIC"] == mot.ENUMERIC
+    assert vals["MOT_ENOMEM"] == mot.ENOMEM and vals["MOT_EDOMAIN"] == mot.EDOMAIN
+    assert vals["MOT_NFFT"] == mot.NFFT and vals["MOT_DENSE"] == mot.DENSE
+    assert vals["MOT_PREC_BF16X3"] == mot.PREC_BF16X3
+    assert mot.strerror(mot.EINVAL) == "invalid argument"
+
+
+def _try_create(mot, pts, wts, topology=0, parent=(-1, 0), eta=0.1, path=0, precision=0):
+    try:
+        mot.Plan(pts, wts, topology, parent, eta, path=path, precision=precision, stream=0)
+    except mot.MotError as e:
+        return e.status
+    return mot.OK
+
+
+def test_invalid_arguments_rejected_before_device_work(mot):
+    r = np.random.default_rng(0)
+    pts = [r.uniform(-.25, .25, (5, 2)) for _ in range(2)]
+    good = [np.full(5, 0.2), np.full(5, 0.2)]
+    assert _try_create(mot, pts, [np.full(5, 0.3), np.full(5, 0.2)]) == mot.EINVAL   # sum != 1
+    neg = np.full(5, 0.2)
+    neg[0], neg[1] = -0.1, 0.5
+    assert _try_create(mot, pts, [neg, good[1]]) == mot.EINVAL                        # negative weight
+    assert _try_create(mot, pts, good, eta=0.0) == mot.EINVAL                          # eta <= 0
+    assert _try_create(mot, pts, good, parent=(-1, 1)) == mot.EINVAL                   # parent[k] >= k
+    assert _try_create(mot, pts, good, topology=1, parent=None) == mot.EINVAL          # circle with K < 3
+    assert _try_create(mot, pts, good, path=2) == mot.EUNSUPPORTED                     # dense tree
+    assert _try_create(mot, pts, good, path=1, precision=0) == mot.EUNSUPPORTED        # NFFT in FP64
+    bad = [p.copy() for p in pts]
+    bad[0][0, 0] = np.nan
+    assert _try_create(mot, bad, good) == mot.EINVAL                                   # non-finite point
+
+
+def test_footprint_model(mot):
+    small = mot.footprint([1000] * 4, 2, 0, mot.NFFT, mot.PREC_MIXED, 0.1)
+    big = mot.footprint([100000] * 10, 3, 0, mot.NFFT, mot.PREC_MIXED, 0.05)
+    circ = mot.footprint([4000] * 5, 2, 1, mot.DENSE, mot.PREC_BF16X3, 0.1)
+    assert 0 < small < big
+    assert circ > 5 * 4096 * 4096 * 4  # the n_1 x n_k FP32 matrices dominate

@@ -1,0 +1,105 @@
+"""Batched and serving forms: every problem's result equals its result alone (bitwise;
+all reductions run in a fixed order and no floating-point atomics are used)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2208_03120_amd import workloads as W
+from tests.helpers import gauge_fix, max_rel
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mot():
+    from paper_2208_03120_amd import mot as m
+    return m
+
+
+def small_batch_instances(count=6):
+    out = []
+    for i in range(count):
+        inst = W.batched_instance(i, n_range=(300, 3000))
+        out.append(inst)
+    return out
+
+
+@pytest.mark.parametrize("use_graph", [True, False])
+def test_batched_sweeps_equal_single_plans(mot, use_graph):
+    insts = small_batch_instances()
+    stream = mot.current_stream()
+    plans = [mot.Plan(x.points, x.weights, W.TREE, x.parent, x.eta, path=mot.NFFT, stream=stream)
+             for x in insts]
+    batch = mot.Batch(plans)
+    batch.sinkhorn(12, use_graph=use_graph)
+    for x, p in zip(insts, plans):
+        alone = mot.Plan(x.points, x.weights, W.TREE, x.parent, x.eta, path=mot.NFFT)
+        alone.sinkhorn(12)
+        for a, b in zip(p.scalings(), alone.scalings()):
+            np.testing.assert_array_equal(a, b)
+        np.testing.assert_array_equal(p.S_history(), alone.S_history())
+        alone.close()
+    batch.close()
+    for p in plans:
+        p.close()
+
+
+def test_batched_instance_matches_oracle(mot):
+    x = small_batch_instances(3)[2]
+    plan = mot.Plan(x.points, x.weights, W.TREE, x.parent, x.eta, path=mot.NFFT)
+    batch = mot.Batch([plan])
+    batch.sinkhorn(15)
+    ophi, _, _, _ = oracle.tree_sinkhorn(x.points, x.weights, x.parent, x.eta, 15)
+    assert max_rel(gauge_fix(plan.scalings(), x.weights), gauge_fix(ophi, x.weights)) < 1e-5
+    batch.close()
+    plan.close()
+
+
+def _requests():
+    stream = W.request_stream(seed=7, count=10, n_range=(300, 2500), circle_n_max=400)
+    return [inst for _, inst in stream]
+
+
+def test_server_results_alone_equal_in_mix(mot):
+    reqs = _requests()
+    srv = mot.Server(hbm_budget=8 << 30, max_slots=8)
+    tickets = [srv.submit(q, tol=1e-6, max_sweeps=400,
+                          path=(mot.DENSE if q.topology == W.CIRCLE else mot.NFFT))[1] for q in reqs]
+    while True:
+        srv.run(5.0, idle_exit=True)
+        res = [srv.fetch(t, want_phi=True) for t in tickets if t is not None]
+        if all(r is not None for r in res):
+            break
+    srv.close()
+    for i in (0, 3, 7):
+        q = reqs[i]
+        solo = mot.Server(hbm_budget=8 << 30, max_slots=8)
+        _, t = solo.submit(q, tol=1e-6, max_sweeps=400,
+                           path=(mot.DENSE if q.topology == W.CIRCLE else mot.NFFT))
+        solo.run(30.0, idle_exit=True)
+        r = solo.fetch(t, want_phi=True)
+        solo.close()
+        assert r["status"] == res[i]["status"] and r["sweeps"] == res[i]["sweeps"]
+        for a, b in zip(r["phi"], res[i]["phi"]):
+            np.testing.assert_array_equal(a, b)
+    assert sum(r["status"] == mot.OK for r in res) >= 8
+
+
+def test_server_admission_slots_and_footprint(mot):
+    reqs = _requests()[:4]
+    srv = mot.Server(hbm_budget=8 << 30, max_slots=1)   # one resident problem at a time
+    tk = [srv.submit(q, tol=1e-6, max_sweeps=200,
+                     path=(mot.DENSE if q.topology == W.CIRCLE else mot.NFFT))[1] for q in reqs]
+    srv.run(60.0, idle_exit=True)
+    res = [srv.fetch(t) for t in tk]
+    assert all(r is not None for r in res)
+    order = sorted(range(len(res)), key=lambda i: res[i]["t_admit"])
+    assert order == list(range(len(res)))               # FIFO admission
+    for a, b in zip(order, order[1:]):
+        assert res[b]["t_admit"] >= res[a]["t_done"]
+    srv.close()
+    # a problem whose device footprint exceeds the budget is refused at submission
+    tiny = mot.Server(hbm_budget=1 << 20, max_slots=2)
+    rc, t = tiny.submit(reqs[0])
+    assert rc == mot.ENOMEM and t is None
+    tiny.close()
