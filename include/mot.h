@@ -81,7 +81,8 @@ typedef struct {
 } mot_fastsum_params;
 
 /* Optional device-memory provider (e.g. PyTorch's caching allocator).  NULL
- * means hipMalloc/hipFree.  alloc returns NULL on failure. */
+ * means hipMalloc/hipFree.  alloc returns NULL on failure; a block it returns must be
+ * 256-byte aligned (plan creation fails with MOT_EINVAL otherwise). */
 typedef struct {
     void *(*alloc)(size_t bytes, void *ctx);
     void (*free)(void *ptr, void *ctx);

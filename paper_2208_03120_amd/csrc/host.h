@@ -56,7 +56,7 @@ struct NfftParams {
     double o[3] = {0, 0, 0};
     int lo[3] = {0, 0, 0}, L[3] = {1, 1, 1}, ntile[3] = {1, 1, 1}, tmin[3] = {0, 0, 0};
     int W = 0;
-    double kb_b = 0, kb_inv_den = 0, kb_edge = 0;
+    double kb_b = 0;
     double est_err = 0;   // autotuner's error estimate for one product (relative)
 };
 
@@ -76,7 +76,6 @@ void kappa_hat_even(int d, int M, double eta, double tau, double eps_B, int p,
                     std::vector<double> &khat);  // (M+1)^d entries, |k_c| = 0..M
 void build_multiplier(int d, const NfftParams &P, double eta, std::vector<float> &D);
 void build_twiddle(int n, std::vector<float2> &tw);
-void build_window_poly(const NfftParams &P, std::vector<float> &coef);
 double kb_fourier(double k, const NfftParams &P);  // normalised window transform
 
 // ---------------------------------------------------------------------------------------
@@ -107,8 +106,7 @@ struct MargDev {
     double *mu = nullptr, *phi = nullptr, *gamma = nullptr, *beta = nullptr;
     double *down_src = nullptr, *up_src = nullptr, *marg = nullptr;
     // NFFT layout
-    uint32_t *cell = nullptr;
-    float *frac = nullptr;
+    float *win = nullptr;    // window rows, n x d x 16
     int32_t *chunk_start = nullptr, *chunk_tile = nullptr, *tile_chunks = nullptr;
     int nchunks = 0;
     std::vector<int32_t> h_chunk_tile;
@@ -146,7 +144,6 @@ struct mot_plan_s {
     mot::ProdJob *jobs_dev = nullptr;
     int32_t *exp_slots = nullptr;  // [2K + 1]
     float *D = nullptr;
-    float *winpoly = nullptr;
     float2 *twiddle = nullptr;
     // statistics
     int32_t *sweep_ctr = nullptr, *flag = nullptr, *flag_hist = nullptr, *ticket = nullptr;

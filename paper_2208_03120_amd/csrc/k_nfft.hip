@@ -1,5 +1,5 @@
-// NFFT fast-summation kernels for gfx950: point binning, window spreading into LDS
-// patches, the deterministic patch fold, and grid-to-point interpolation.
+// NFFT fast-summation kernels for gfx950: point binning, window rows, spreading into
+// per-tile patches, the deterministic patch fold, and grid-to-point interpolation.
 //
 // Fast summation (Sec. 5, Algorithm 4) evaluates beta = F_t (kappa_hat (.) F*_s v).
 // The adjoint NDFT F*_s is approximated by spreading v onto an oversampled grid of n
@@ -15,8 +15,8 @@
 // overlapping patches of neighbouring tiles into the box grid in a fixed order -- no
 // atomics anywhere (gfx950 executes LDS float atomics lane by lane, far below LDS
 // read rates), and the grid does not depend on which other jobs share a launch.
-// Interpolation loads a tile's patch of the result grid into LDS and contracts it with
-// the points' windows, again on the MFMA units.
+// Interpolation keeps a tile's patch of the result grid in registers and contracts it
+// with the points' windows, again on the MFMA units.
 #include "mot_internal.h"
 
 namespace mot {
@@ -153,45 +153,84 @@ hipError_t stable_tile_sort(int64_t npts, const int32_t *tile, int64_t ntiles, i
     return hipGetLastError();
 }
 
-// Binned layout of sorted points: tile-relative cell (10 bits per dimension) and the
-// fractional offset u - cell as FP32.  u is recomputed with the binning's operations,
-// so the cell is the one the point was sorted by.
-__global__ void point_layout_kernel(int d, int64_t npts, const double *__restrict__ pts, double s0,
-                                    double s1, double s2, double o0, double o1, double o2, int T,
-                                    uint32_t *__restrict__ cellpk, float *__restrict__ frac)
-{
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= npts) return;
-    const double sc[3] = {s0, s1, s2}, oc[3] = {o0, o1, o2};
-    uint32_t pk = 0;
-    for (int c = 0; c < d; ++c) {
-        double u = __dadd_rn(__dmul_rn(pts[i * d + c], sc[c]), oc[c]);
-        double f = floor(u);
-        int ci = (int)f;
-        pk |= (uint32_t)(ci % T) << (10 * c);
-        frac[i * d + c] = (float)(u - f);
-    }
-    cellpk[i] = pk;
-}
+constexpr int kPatch = 16;  // patch edge T + 2m - 1 in cells
 
-hipError_t launch_point_layout_s(int d, int64_t npts, const double *pts, const double *s,
-                                 const double *o, int T, uint32_t *cellpk, float *frac,
-                                 hipStream_t st)
+// ---------------------------------------------------------------------------------------
+// Global-memory views of generic pointers: loads and stores through them are global
+// (vector-memory counter only), so waiting for LDS results never also waits for
+// outstanding global loads, as it would with flat instructions.
+#define MOT_GLOBAL __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ const MOT_GLOBAL T *gp(const T *p)
 {
-    if (npts == 0) return hipSuccess;
-    int blocks = (int)((npts + 255) / 256);
-    hipLaunchKernelGGL(point_layout_kernel, dim3(blocks), dim3(256), 0, st, d, npts, pts, s[0],
-                       d > 1 ? s[1] : 0.0, d > 2 ? s[2] : 0.0, o[0], d > 1 ? o[1] : 0.0,
-                       d > 2 ? o[2] : 0.0, T, cellpk, frac);
-    return hipGetLastError();
+    return (const MOT_GLOBAL T *)p;
+}
+template <class T>
+__device__ __forceinline__ MOT_GLOBAL T *gp(T *p)
+{
+    return (MOT_GLOBAL T *)p;
 }
 
 // ---------------------------------------------------------------------------------------
 // Kaiser-Bessel window in grid units, normalised to 1 at s = 0:
 //   psi(s) = (m / r) sinh(b r) / sinh(b m),  r = sqrt(m^2 - s^2),  |s| <= m,
-// b = pi (2 - 1/sigma).  Its Fourier transform is I0(m sqrt(b^2 - w^2)) (used on the host
-// for the spectral multiplier).  On the device it is evaluated from 2m degree-9
-// polynomials, one per unit interval of s, fitted on the host in FP64.
+// b = pi (2 - 1/sigma).  Its Fourier transform is I0(m sqrt(b^2 - w^2)), which the host
+// uses for the spectral multiplier.
+//
+// Window rows.  A tile holds T = 17 - 2m cells per dimension, so the patch of cells its
+// points touch is exactly 16 wide (T + 2m - 1).  For a point with tile-relative cell r
+// and fractional offset f in dimension c, its row is the 16-vector
+//   w_c[q] = psi(f + m - 1 + r - q)  if 0 <= q - r < 2m,  else 0,
+// the weights of patch cells q = 0..15.  The rows depend on the points only, so they are
+// evaluated once per plan in FP64 (rounded to FP32) and stored per point in binned
+// order, rows[(i d + c) 16 + q]: every later product reads them instead of
+// re-evaluating the window.
+__global__ void window_rows_kernel(int d, int64_t npts, const double *__restrict__ pts, double s,
+                                   double o0, double o1, double o2, int T, int m, double b,
+                                   double inv_sinh_bm, float *__restrict__ rows)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= npts * d) return;
+    const int64_t i = t / d;
+    const int c = (int)(t - i * d);
+    const double oc = c == 0 ? o0 : (c == 1 ? o1 : o2);
+    // the binning's operations, so the cell is the one the point was sorted by
+    const double u = __dadd_rn(__dmul_rn(pts[i * d + c], s), oc);
+    const double fl = floor(u);
+    const double f = u - fl;
+    const int r = (int)fl % T;
+    const double dm = m;
+    float w[kPatch];
+#pragma unroll
+    for (int q = 0; q < kPatch; ++q) {
+        const int j = q - r;
+        float val = 0.0f;
+        if (j >= 0 && j < 2 * m) {
+            const double a = f + (dm - 1.0 - j);
+            const double rr = sqrt(fmax(dm * dm - a * a, 0.0));
+            const double br = b * rr;
+            // sinh(b r) / r, with its series near r = 0 (the support edge)
+            const double sr = br < 1e-4 ? b * (1.0 + br * br / 6.0) : sinh(br) / rr;
+            val = (float)(dm * sr * inv_sinh_bm);
+        }
+        w[q] = val;
+    }
+    float4 *dst = reinterpret_cast<float4 *>(rows + t * kPatch);
+#pragma unroll
+    for (int q = 0; q < kPatch / 4; ++q) dst[q] = make_float4(w[4 * q], w[4 * q + 1], w[4 * q + 2], w[4 * q + 3]);
+}
+
+hipError_t launch_window_rows(int d, int64_t npts, const double *pts, double s, const double *o, int T,
+                              int m, double b, float *rows, hipStream_t st)
+{
+    if (npts == 0) return hipSuccess;
+    const int64_t work = npts * d;
+    const int blocks = (int)((work + 255) / 256);
+    hipLaunchKernelGGL(window_rows_kernel, dim3(blocks), dim3(256), 0, st, d, npts, pts, s, o[0],
+                       d > 1 ? o[1] : 0.0, d > 2 ? o[2] : 0.0, T, m, b, 1.0 / sinh(b * m), rows);
+    return hipGetLastError();
+}
+
 __device__ __forceinline__ int floor_div(int a, int b)  // floor(a / b) for b > 0
 {
     return a >= 0 ? a / b : -((-a + b - 1) / b);
@@ -199,149 +238,167 @@ __device__ __forceinline__ int floor_div(int a, int b)  // floor(a / b) for b > 
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-// ---------------------------------------------------------------------------------------
-// Spreading and interpolation as dense tile contractions on FP32 MFMA.
-//
-// A tile holds T = 17 - 2m cells per dimension, so the patch of cells its points touch
-// is exactly 16 wide (T + 2m - 1).  For a point p with tile-relative cell r and
-// fractional offset f, the "shifted window" of dimension c is the 16-vector
-//   w_c[q] = psi(f + m - 1 + r - q)  if 0 <= q - r < 2m,  else 0,
-// so that the point's contribution to patch cell (a, b, c') is v w_0[a] w_1[b] w_2[c'].
-// Spreading a chunk of points is then the contraction
-//   G[a][(b,c')] = sum_p X[a][p] Y[p][(b,c')],   X[a][p] = v_p w_0[a],
-//   Y[p][(b,c')] = w_1[b] w_2[c'],
-// a 16 x 256 x P matrix product done with v_mfma_f32_16x16x4_f32 (4 points per step,
-// 16 output tiles, one per b).  Interpolation contracts the other way:
-//   Z[p][a] = sum_{(b,c')} Y[p][(b,c')] G[a][(b,c')],  beta_p = sum_a w_0[a] Z[p][a].
-// No atomics: each chunk owns its patch (spreading), each point its sum (interpolation).
-// One wavefront per work item; points are taken 16 at a time.
-constexpr int kPatch = 16;
+__device__ __forceinline__ int source_exponent(const ProdJob &J)
+{
+    const int e = *gp(J.v_exp);
+    return e == INT32_MIN ? 0 : e;
+}
 
-// Per-lane data of one (point, dimension) row of a 16-point batch, prefetched a batch
-// ahead: lane t < 16 D holds row t = p D + c.
-struct RowData {
-    uint32_t cell;
-    float frac;
-    double v;
+// ---------------------------------------------------------------------------------------
+// Spreading (a2) as a dense tile contraction on FP32 MFMA.
+//
+// For a chunk of points of one tile, the patch is
+//   G[a][(b,c')] = sum_p X[a][p] Y[p][(b,c')],   X[a][p] = v_p w_0,p[a],
+//   Y[p][(b,c')] = w_1,p[b] w_2,p[c'],
+// a 16 x 256 x P product done with v_mfma_f32_16x16x4_f32: a step takes 4 points (the K
+// dimension), one MFMA per b (16 output tiles of 16 x 16 over (a, c')).  Lane l holds
+// A[a = l % 16][k = l / 16] and B[k = l / 16][c' = l % 16]; accumulator r of tile b holds
+// G[a = 4 (l / 16) + r][b][c' = l % 16].  In 2-D the product is one 16 x 16 tile per step,
+// in 1-D a plain sum over points.
+//
+// A block of kSpreadWaves wavefronts takes one chunk; wave w takes the 4-point steps
+// w, w + kSpreadWaves, ...  The wave partials are added through LDS in a fixed order
+// (pairwise halving), so a patch is the same whatever else shares the launch, and the
+// chunk owns its patch: no atomics.
+constexpr int kSpreadWaves = 4;
+constexpr int kInterpWaves = 4;
+
+// Points are staged through LDS kStage at a time: all threads of the block copy the
+// stage's window rows (contiguous in memory for consecutive points) with 16-byte loads,
+// one stage ahead of the MFMA work, so the row stream overlaps the contractions.
+constexpr int kStage = 64;
+
+template <int D, bool WITH_V>
+struct Stage {
+    static constexpr int kRow4 = kStage * D * kPatch / 4;  // 16-byte row pieces per stage
+    static constexpr int kPer = (kRow4 + 255) / 256;        // per thread (256 threads)
+    static constexpr int kBytes = kRow4 * 16 + (WITH_V ? kStage * 4 : 0);
+    f32x4 r[kPer];
+    float v;
+
+    // Registers <- global: points pb .. pb + kStage - 1 (zeros past p1).  For spreading,
+    // v is the source value scaled by 2^-e.
+    __device__ __forceinline__ void load(const float *rows, const double *vsrc, int64_t pb, int64_t p1, int e)
+    {
+        const MOT_GLOBAL f32x4 *g = reinterpret_cast<const MOT_GLOBAL f32x4 *>(gp(rows)) + pb * (D * 4);
+#pragma unroll
+        for (int i = 0; i < kPer; ++i) {
+            const int idx = threadIdx.x + 256 * i;
+            r[i] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+            if (idx < kRow4 && pb + idx / (D * 4) < p1) r[i] = g[idx];
+        }
+        if constexpr (WITH_V) {
+            v = 0.0f;
+            const int64_t p = pb + threadIdx.x;
+            if (threadIdx.x < kStage && p < p1) v = (float)ldexp(gp(vsrc)[p], -e);
+        }
+    }
+    // LDS <- registers
+    __device__ __forceinline__ void store(unsigned char *buf) const
+    {
+        f32x4 *rl = reinterpret_cast<f32x4 *>(buf);
+#pragma unroll
+        for (int i = 0; i < kPer; ++i) {
+            const int idx = threadIdx.x + 256 * i;
+            if (idx < kRow4) rl[idx] = r[i];
+        }
+        if constexpr (WITH_V)
+            if (threadIdx.x < kStage) reinterpret_cast<float *>(buf + kRow4 * 16)[threadIdx.x] = v;
+    }
 };
 
 template <int D>
-__device__ __forceinline__ void load_rows(const uint32_t *cellpk, const float *frac, const double *v,
-                                          int64_t pb, int np, RowData &rd)
+__global__ __launch_bounds__(64 * kSpreadWaves) void spread_kernel(const ProdJob *__restrict__ jobs,
+                                                                   const int2 *__restrict__ items,
+                                                                   int n_items)
 {
-    const int t = threadIdx.x, p = t / D, c = t - p * D;
-    rd.cell = 0u;
-    rd.frac = 0.0f;
-    rd.v = 0.0;
-    if (t < 16 * D && p < np) {
-        const int64_t gi = pb + p;
-        rd.cell = (cellpk[gi] >> (10 * c)) & 1023u;
-        rd.frac = frac[gi * D + c];
-        if (c == 0 && v) rd.v = v[gi];
-    }
-}
-
-// Fill win[p][c][0..15] with the shifted windows of the batch: lane t owns row t, zeroes
-// it and writes its 2m taps at positions r + j, tap j evaluated by Horner's rule at
-// t = f - 1/2 on interval 2m - 1 - j (coefficients read from LDS, the same address on
-// every lane).
-template <int D>
-__device__ __forceinline__ void shifted_windows(const ProdJob &J, const float *cf_lds, const RowData &rd,
-                                                int np, bool scale_v, int e, float (*win)[D][kPatch])
-{
-    const int t = threadIdx.x, p = t / D, c = t - p * D;
-    if (t < 16 * D) {
-        float4 *row4 = reinterpret_cast<float4 *>(&win[p][c][0]);
-#pragma unroll
-        for (int q = 0; q < kPatch / 4; ++q) row4[q] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        if (p < np) {
-            const int taps = 2 * J.m;
-            const float x = rd.frac - 0.5f;
-            const float sc = (c == 0 && scale_v) ? (float)ldexp(rd.v, -e) : 1.0f;
-            float *row = &win[p][c][rd.cell];
-            for (int j = 0; j < taps; ++j) {
-                const float *cf = cf_lds + (taps - 1 - j) * (kWinDeg + 1);
-                float w = cf[kWinDeg];
-#pragma unroll
-                for (int i = kWinDeg - 1; i >= 0; --i) w = fmaf(w, x, cf[i]);
-                row[j] = sc * w;
-            }
-        }
-    }
-}
-
-__device__ __forceinline__ void load_poly_lds(const ProdJob &J, float *cf_lds)
-{
-    const int n = 2 * J.m * (kWinDeg + 1);
-    for (int i = threadIdx.x; i < n; i += blockDim.x) cf_lds[i] = J.winpoly[i];
-}
-
-template <int D>
-__global__ __launch_bounds__(64) void spread_kernel(const ProdJob *__restrict__ jobs,
-                                                    const int2 *__restrict__ items, int n_items)
-{
-    __shared__ float win[16][D][kPatch];
-    __shared__ float cf_lds[2 * (kMaxTaps / 2) * (kWinDeg + 1)];
-    const int l = threadIdx.x, li = l & 15, lk = l >> 4;
+    static_assert(kSpreadWaves == 4, "staging assumes 256 threads");
+    constexpr int NT = D == 3 ? 16 : 1;  // accumulator tiles per lane
+    using St = Stage<D, true>;
+    constexpr int kRed = (kSpreadWaves / 2) * NT * 64 * 16;
+    constexpr int kSmem = 2 * St::kBytes > kRed ? 2 * St::kBytes : kRed;
+    __shared__ __align__(16) unsigned char smem[kSmem];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int li = lane & 15, lk = lane >> 4;
     for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
         const int2 itm = items[it];
         const ProdJob &J = jobs[itm.x];
-        const int p0 = J.src_chunk_start[itm.y], p1 = J.src_chunk_start[itm.y + 1];
-        int e = *J.v_exp;
-        if (e == INT32_MIN) e = 0;
-        load_poly_lds(J, cf_lds);
-        RowData rd;
-        load_rows<D>(J.src_cell, J.src_frac, J.v, p0, min(16, p1 - p0), rd);
-        __syncthreads();
-        constexpr int NT = D == 3 ? 16 : 1;
+        const int64_t p0 = gp(J.src_chunk_start)[itm.y], p1 = gp(J.src_chunk_start)[itm.y + 1];
+        const int e = source_exponent(J);
+        const int nstages = (int)((p1 - p0 + kStage - 1) / kStage);
         f32x4 acc[NT];
-        float acc1 = 0.0f;
 #pragma unroll
         for (int t = 0; t < NT; ++t) acc[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-        for (int pb = p0; pb < p1; pb += 16) {
-            const int np = min(16, p1 - pb);
-            shifted_windows<D>(J, cf_lds, rd, np, true, e, win);
-            if (pb + 16 < p1) load_rows<D>(J.src_cell, J.src_frac, J.v, pb + 16, min(16, p1 - pb - 16), rd);
-            __syncthreads();
-            if constexpr (D == 3) {
+        St stg;
+        stg.load(J.src_win, J.v, p0, p1, e);
+        stg.store(smem);
+        __syncthreads();
+        for (int k = 0; k < nstages; ++k) {
+            const bool more = k + 1 < nstages;
+            if (more) stg.load(J.src_win, J.v, p0 + (int64_t)(k + 1) * kStage, p1, e);
+            const unsigned char *buf = smem + (k & 1) * St::kBytes;
+            const float *rl = reinterpret_cast<const float *>(buf);
+            const float *vl = reinterpret_cast<const float *>(buf + St::kRow4 * 16);
+            // this wave's 4-point steps of the stage: points 4 j + lane group, j = wave + 4 i
 #pragma unroll
-                for (int s = 0; s < 4; ++s) {
-                    const int pk = 4 * s + lk;
-                    const float x = win[pk][0][li];
-                    const float wz = win[pk][2][li];
-                    float wy[16];
+            for (int i = 0; i < kStage / 16; ++i) {
+                const int pi = 4 * (wave + 4 * i) + lk;
+                const float *row = rl + pi * (D * kPatch);
+                const float x = vl[pi] * row[li];
+                if constexpr (D == 3) {
+                    const float w2 = row[2 * kPatch + li];
+                    const f32x4 *r1 = reinterpret_cast<const f32x4 *>(row + kPatch);
 #pragma unroll
-                    for (int q = 0; q < 16; ++q) wy[q] = win[pk][1][q];
+                    for (int q = 0; q < 4; ++q) {
+                        const f32x4 w1 = r1[q];
 #pragma unroll
-                    for (int bt = 0; bt < 16; ++bt)
-                        acc[bt] = __builtin_amdgcn_mfma_f32_16x16x4f32(x, wy[bt] * wz, acc[bt], 0, 0, 0);
+                        for (int u = 0; u < 4; ++u)
+                            acc[4 * q + u] = __builtin_amdgcn_mfma_f32_16x16x4f32(x, w1[u] * w2, acc[4 * q + u],
+                                                                                  0, 0, 0);
+                    }
+                } else if constexpr (D == 2) {
+                    acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(x, row[kPatch + li], acc[0], 0, 0, 0);
+                } else {
+                    acc[0][0] += x;
                 }
-            } else if constexpr (D == 2) {
-#pragma unroll
-                for (int s = 0; s < 4; ++s) {
-                    const int pk = 4 * s + lk;
-                    acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(win[pk][0][li], win[pk][1][li], acc[0],
-                                                                 0, 0, 0);
-                }
-            } else {
-#pragma unroll
-                for (int s = 0; s < 4; ++s) acc1 += win[4 * s + lk][0][li];
             }
+            if (more) stg.store(smem + ((k + 1) & 1) * St::kBytes);
             __syncthreads();
         }
-        float *out = J.patches + (int64_t)itm.y * (D == 3 ? 4096 : (D == 2 ? 256 : 16));
-        if constexpr (D == 3) {
+        if constexpr (D == 1) {
+            // sum over the four points of a step (lane groups), then over waves
+            float a1 = acc[0][0];
+            a1 += __shfl_xor(a1, 16);
+            a1 += __shfl_xor(a1, 32);
+            acc[0][0] = a1;
+        }
+        // wave partials: wave w < half adds wave w + half, halving until wave 0 holds the
+        // patch (the staging buffers are free: the last stage ended with a barrier)
+        f32x4(*red)[NT][64] = reinterpret_cast<f32x4(*)[NT][64]>(smem);
 #pragma unroll
-            for (int bt = 0; bt < 16; ++bt)
+        for (int half = kSpreadWaves / 2; half >= 1; half >>= 1) {
+            if (wave >= half && wave < 2 * half)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) out[((4 * lk + r) * 16 + bt) * 16 + li] = acc[bt][r];
-        } else if constexpr (D == 2) {
+                for (int t = 0; t < NT; ++t) red[wave - half][t][lane] = acc[t];
+            __syncthreads();
+            if (wave < half)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) out[(4 * lk + r) * 16 + li] = acc[0][r];
-        } else {
-            acc1 += __shfl_xor(acc1, 16);
-            acc1 += __shfl_xor(acc1, 32);
-            if (lk == 0) out[li] = acc1;
+                for (int t = 0; t < NT; ++t) acc[t] += red[wave][t][lane];
+            __syncthreads();
+        }
+        if (wave == 0) {
+            MOT_GLOBAL float *out = gp(J.patches) + (int64_t)itm.y * (D == 3 ? 4096 : (D == 2 ? 256 : 16));
+            if constexpr (D == 3) {
+#pragma unroll
+                for (int bt = 0; bt < 16; ++bt)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) out[((4 * lk + r) * 16 + bt) * 16 + li] = acc[bt][r];
+            } else if constexpr (D == 2) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) out[(4 * lk + r) * 16 + li] = acc[0][r];
+            } else {
+                if (lk == 0) out[li] = acc[0][0];
+            }
         }
     }
 }
@@ -387,101 +444,130 @@ __global__ __launch_bounds__(256) void fold_kernel(const ProdJob *__restrict__ j
                         tl = tl * J.ntile[2] + t2;
                         loc = loc * W + (gc[2] - t2 * T);
                     }
-                    const int c0 = J.src_tile_chunks[tl], c1 = J.src_tile_chunks[tl + 1];
-                    for (int ch = c0; ch < c1; ++ch) acc += J.patches[(int64_t)ch * patch_elems + loc];
+                    const int c0 = gp(J.src_tile_chunks)[tl], c1 = gp(J.src_tile_chunks)[tl + 1];
+                    for (int ch = c0; ch < c1; ++ch) acc += gp(J.patches)[(int64_t)ch * patch_elems + loc];
                 }
-        J.grid[g] = acc;
+        gp(J.grid)[g] = acc;
     }
 }
 
-// Interpolation (a6): item = (job, chunk of target points).  out = 2^e * beta with beta
-// the window-weighted sum of the grid around each point (FP32, written as FP64), where e
-// is the exponent the source vector was scaled by before spreading.
-// The MFMA B operand, G[a][(b,c')] for this lane's a = lane % 16 and c' = 4q + lane / 16,
-// is the same for every point of the chunk: it is loaded once into registers.
+// ---------------------------------------------------------------------------------------
+// Interpolation (a6) as the transposed contraction on FP32 MFMA.
+//
+// For 16 target points of one tile and the 16^d patch G of the result grid over the
+// tile, Z[p][a] = sum_{(b,c')} Y[p][(b,c')] G[a][(b,c')] with Y[p][(b,c')] =
+// w_1,p[b] w_2,p[c'], then beta_p = sum_a w_0,p[a] Z[p][a].  Step s of the 64-step MFMA
+// chain covers b = s / 4 and, for lane group g = l / 16, c' = 4 g + s % 4: lane l holds
+// A[p = l % 16][k] = w_1,p[b] w_2,p[c'] and B[k][a = l % 16] = G[a][b][c'].  The B values
+// are the same for every point of the tile, so they stay in registers for the whole
+// chunk.  Accumulator r holds Z[p = 4 g + r][a = l % 16]; the last contraction over a is
+// a 16-lane reduction.  In 2-D the chain has 4 steps (k = b = 4 g + s); in 1-D one lane
+// takes one point.  out = 2^e beta, e the exponent the source was scaled by.
+//
+// A block of kInterpWaves wavefronts takes one chunk; wave w takes the 16-point groups
+// (64 in 1-D) w, w + kInterpWaves, ...
 template <int D>
-__global__ __launch_bounds__(64) void interp_kernel(const ProdJob *__restrict__ jobs,
-                                                    const int2 *__restrict__ items, int n_items)
+__global__ __launch_bounds__(64 * kInterpWaves) void interp_kernel(const ProdJob *__restrict__ jobs,
+                                                                   const int2 *__restrict__ items,
+                                                                   int n_items)
 {
-    constexpr int NB = D == 3 ? 64 : (D == 2 ? 4 : 1);  // B values per lane
-    __shared__ float win[16][D][kPatch];
-    __shared__ float cf_lds[2 * (kMaxTaps / 2) * (kWinDeg + 1)];
-    __shared__ float G1[16];
-    const int l = threadIdx.x, li = l & 15, lk = l >> 4;
+    static_assert(kInterpWaves == 4 && kStage == 16 * kInterpWaves, "one 16-point group per wave and stage");
+    constexpr int NB = D == 3 ? 64 : (D == 2 ? 4 : 16);  // B values per lane
+    using St = Stage<D, false>;
+    __shared__ __align__(16) unsigned char smem[D == 1 ? 16 : 2 * St::kBytes];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int li = lane & 15, lk = lane >> 4;
     for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
         const int2 itm = items[it];
         const ProdJob &J = jobs[itm.x];
         const int T = J.T;
         int tc[3] = {0, 0, 0};
         {
-            int rem = J.tgt_chunk_tile[itm.y];
+            int rem = gp(J.tgt_chunk_tile)[itm.y];
             for (int c = D - 1; c >= 0; --c) {
                 tc[c] = rem % J.ntile[c];
                 rem /= J.ntile[c];
             }
         }
+        const MOT_GLOBAL float *grid = gp(J.grid);
         float Bv[NB];
         if constexpr (D == 3) {
-            // K index s = 4(b) + q  <->  (b = s >> 2, c' = 4 (s & 3) + lk)
-            const int64_t base = ((int64_t)(tc[0] * T + li) * J.L[1] + tc[1] * T) * J.L[2] + tc[2] * T;
+            const int64_t base = ((int64_t)(tc[0] * T + li) * J.L[1] + tc[1] * T) * J.L[2] + tc[2] * T + 4 * lk;
 #pragma unroll
-            for (int s = 0; s < 64; ++s)
-                Bv[s] = J.grid[base + (int64_t)(s >> 2) * J.L[2] + 4 * (s & 3) + lk];
+            for (int s = 0; s < 64; ++s) Bv[s] = grid[base + (int64_t)(s >> 2) * J.L[2] + (s & 3)];
         } else if constexpr (D == 2) {
-            const int64_t base = (int64_t)(tc[0] * T + li) * J.L[1] + tc[1] * T;
+            const int64_t base = (int64_t)(tc[0] * T + li) * J.L[1] + tc[1] * T + 4 * lk;
 #pragma unroll
-            for (int s = 0; s < 4; ++s) Bv[s] = J.grid[base + 4 * s + lk];
+            for (int s = 0; s < 4; ++s) Bv[s] = grid[base + s];
         } else {
-            if (l < 16) G1[l] = J.grid[tc[0] * T + l];
+#pragma unroll
+            for (int a = 0; a < 16; ++a) Bv[a] = grid[tc[0] * T + a];
         }
-        int e = *J.v_exp;
-        if (e == INT32_MIN) e = 0;
-        load_poly_lds(J, cf_lds);
-        const int p0 = J.tgt_chunk_start[itm.y], p1 = J.tgt_chunk_start[itm.y + 1];
-        RowData rd;
-        load_rows<D>(J.tgt_cell, J.tgt_frac, nullptr, p0, min(16, p1 - p0), rd);
-        __syncthreads();
-        for (int pb = p0; pb < p1; pb += 16) {
-            const int np = min(16, p1 - pb);
-            shifted_windows<D>(J, cf_lds, rd, np, false, 0, win);
-            if (pb + 16 < p1) load_rows<D>(J.tgt_cell, J.tgt_frac, nullptr, pb + 16, min(16, p1 - pb - 16), rd);
+        const int e = source_exponent(J);
+        const int64_t p0 = gp(J.tgt_chunk_start)[itm.y], p1 = gp(J.tgt_chunk_start)[itm.y + 1];
+        MOT_GLOBAL double *out = gp(J.out);
+        if constexpr (D == 1) {
+            const MOT_GLOBAL f32x4 *rows = reinterpret_cast<const MOT_GLOBAL f32x4 *>(gp(J.tgt_win));
+            for (int64_t p = p0 + threadIdx.x; p < p1; p += 64 * kInterpWaves) {
+                float s = 0.0f;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const f32x4 w = rows[p * 4 + q];
+                    s += w[0] * Bv[4 * q] + w[1] * Bv[4 * q + 1] + w[2] * Bv[4 * q + 2] + w[3] * Bv[4 * q + 3];
+                }
+                out[p] = ldexp((double)s, e);
+            }
+        } else {
+            const int nstages = (int)((p1 - p0 + kStage - 1) / kStage);
+            St stg;
+            stg.load(J.tgt_win, nullptr, p0, p1, 0);
+            stg.store(smem);
             __syncthreads();
-            if constexpr (D == 1) {
-                if (l < np) {
-                    float s = 0.0f;
-#pragma unroll
-                    for (int a = 0; a < 16; ++a) s += G1[a] * win[l][0][a];
-                    J.out[pb + l] = ldexp((double)s, e);
-                }
-            } else {
-                f32x4 acc = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+            for (int k = 0; k < nstages; ++k) {
+                const bool more = k + 1 < nstages;
+                if (more) stg.load(J.tgt_win, nullptr, p0 + (int64_t)(k + 1) * kStage, p1, 0);
+                const float *rl = reinterpret_cast<const float *>(smem + (k & 1) * St::kBytes);
+                // this wave's group: stage points 16 wave .. 16 wave + 15
+                const float *grow = rl + (16 * wave) * (D * kPatch);
+                const float *row = grow + li * (D * kPatch);  // point l % 16
+                f32x4 acc0 = f32x4{0.0f, 0.0f, 0.0f, 0.0f}, acc1 = acc0;
                 if constexpr (D == 3) {
-                    float wy[16], wzk[4];
+                    const f32x4 *r1 = reinterpret_cast<const f32x4 *>(row + kPatch);
+                    const f32x4 wz = reinterpret_cast<const f32x4 *>(row + 2 * kPatch)[lk];
 #pragma unroll
-                    for (int q = 0; q < 16; ++q) wy[q] = win[li][1][q];
+                    for (int q = 0; q < 4; ++q) {
+                        const f32x4 wy = r1[q];
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) wzk[q] = win[li][2][4 * q + lk];
-#pragma unroll
-                    for (int s = 0; s < 64; ++s)
-                        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(wy[s >> 2] * wzk[s & 3], Bv[s], acc, 0, 0, 0);
+                        for (int u = 0; u < 4; ++u) {
+                            const int s = 16 * q + 4 * u;  // b = 4 q + u, c' = 4 lk + 0..3
+                            acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(wy[u] * wz[0], Bv[s], acc0, 0, 0, 0);
+                            acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(wy[u] * wz[1], Bv[s + 1], acc1, 0, 0, 0);
+                            acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(wy[u] * wz[2], Bv[s + 2], acc0, 0, 0, 0);
+                            acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(wy[u] * wz[3], Bv[s + 3], acc1, 0, 0, 0);
+                        }
+                    }
                 } else {
-#pragma unroll
-                    for (int s = 0; s < 4; ++s)
-                        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(win[li][1][4 * s + lk], Bv[s], acc, 0, 0, 0);
+                    const f32x4 wb = reinterpret_cast<const f32x4 *>(row + kPatch)[lk];
+                    acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(wb[0], Bv[0], acc0, 0, 0, 0);
+                    acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(wb[1], Bv[1], acc1, 0, 0, 0);
+                    acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(wb[2], Bv[2], acc0, 0, 0, 0);
+                    acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(wb[3], Bv[3], acc1, 0, 0, 0);
                 }
-                // acc[r] = Z[p = 4 lk + r][a = li]; beta_p = sum_a w_0[a] Z[p][a]
+                // beta_p = sum_a w_0,p[a] Z[p][a] over the 16 lanes of a lane group
+                const int64_t pb = p0 + (int64_t)k * kStage + 16 * wave;
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const int p = 4 * lk + r;
-                    float z = acc[r] * win[p][0][li];
+                    float z = (acc0[r] + acc1[r]) * grow[(4 * lk + r) * (D * kPatch) + li];
                     z += __shfl_xor(z, 1);
                     z += __shfl_xor(z, 2);
                     z += __shfl_xor(z, 4);
                     z += __shfl_xor(z, 8);
-                    if (li == 0 && p < np) J.out[pb + p] = ldexp((double)z, e);
+                    const int64_t p = pb + 4 * lk + r;
+                    if (li == r && p < p1) out[p] = ldexp((double)z, e);
                 }
+                if (more) stg.store(smem + ((k + 1) & 1) * St::kBytes);
+                __syncthreads();
             }
-            __syncthreads();
         }
     }
 }
@@ -495,15 +581,13 @@ hipError_t launch_spread(int d, const ProdJob *jobs, const int2 *items, int n_it
                          int /*max_patch_elems*/, hipStream_t s)
 {
     if (n_items == 0) return hipSuccess;
+    const dim3 grid(nfft_grid(n_items)), block(64 * kSpreadWaves);
     if (d == 3)
-        hipLaunchKernelGGL(spread_kernel<3>, dim3(nfft_grid(n_items)), dim3(64), 0, s, jobs, items,
-                           n_items);
+        hipLaunchKernelGGL(spread_kernel<3>, grid, block, 0, s, jobs, items, n_items);
     else if (d == 2)
-        hipLaunchKernelGGL(spread_kernel<2>, dim3(nfft_grid(n_items)), dim3(64), 0, s, jobs, items,
-                           n_items);
+        hipLaunchKernelGGL(spread_kernel<2>, grid, block, 0, s, jobs, items, n_items);
     else
-        hipLaunchKernelGGL(spread_kernel<1>, dim3(nfft_grid(n_items)), dim3(64), 0, s, jobs, items,
-                           n_items);
+        hipLaunchKernelGGL(spread_kernel<1>, grid, block, 0, s, jobs, items, n_items);
     return hipGetLastError();
 }
 
@@ -526,15 +610,13 @@ hipError_t launch_interp(int d, const ProdJob *jobs, const int2 *items, int n_it
                          int /*max_patch_elems*/, hipStream_t s)
 {
     if (n_items == 0) return hipSuccess;
+    const dim3 grid(nfft_grid(n_items)), block(64 * kInterpWaves);
     if (d == 3)
-        hipLaunchKernelGGL(interp_kernel<3>, dim3(nfft_grid(n_items)), dim3(64), 0, s, jobs, items,
-                           n_items);
+        hipLaunchKernelGGL(interp_kernel<3>, grid, block, 0, s, jobs, items, n_items);
     else if (d == 2)
-        hipLaunchKernelGGL(interp_kernel<2>, dim3(nfft_grid(n_items)), dim3(64), 0, s, jobs, items,
-                           n_items);
+        hipLaunchKernelGGL(interp_kernel<2>, grid, block, 0, s, jobs, items, n_items);
     else
-        hipLaunchKernelGGL(interp_kernel<1>, dim3(nfft_grid(n_items)), dim3(64), 0, s, jobs, items,
-                           n_items);
+        hipLaunchKernelGGL(interp_kernel<1>, grid, block, 0, s, jobs, items, n_items);
     return hipGetLastError();
 }
 

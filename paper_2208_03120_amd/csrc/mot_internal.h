@@ -18,7 +18,6 @@ constexpr int kMaxD = 3;
 constexpr int kMaxTaps = 16;      // 2m taps per dimension, m <= 8
 constexpr int kMaxN = 512;        // FFT grid per dimension
 constexpr int kMinN = 16;
-constexpr int kWinDeg = 9;       // degree of the window polynomials
 constexpr int kMaxChildren = 64;  // children per tree node handled by the node kernels
 
 // ---------------------------------------------------------------------------------------
@@ -40,8 +39,7 @@ struct ProdJob {
     // direct path: sorted FP64 coordinates (n x d) of sources and targets
     const double *src_pts, *tgt_pts;
     // NFFT path, source and target binned layouts
-    const uint32_t *src_cell, *tgt_cell;  // tile-relative cell coordinates, 10 bits per dim
-    const float *src_frac, *tgt_frac;     // n x d offsets u - cell, in [0, 1]
+    const float *src_win, *tgt_win;       // window rows, n x d x 16 (see window_rows_kernel)
     const int32_t *src_chunk_start, *tgt_chunk_start;  // point range of each chunk
     const int32_t *src_chunk_tile, *tgt_chunk_tile;    // box-relative tile of each chunk
     const int32_t *src_tile_chunks;       // [ntiles+1] chunk range of each box tile
@@ -52,11 +50,7 @@ struct ProdJob {
     int32_t lo[3];     // active box first grid index per dimension
     int32_t ntile[3];  // box tiles per dimension
     int32_t W;         // patch edge T + 2m - 1
-    float kb_b;        // Kaiser-Bessel shape parameter b = pi (2 - 1/sigma)
-    float kb_inv_den;  // 1 / (1 - exp(-2 b m))
-    float kb_edge;     // window value at |s| = m
     const float *D;    // multiplier on the half spectrum, layout [A2][A1][2M+1]
-    const float *winpoly;  // [2m][kWinDeg+1] window polynomial coefficients
     const float2 *twiddle;  // exp(-2 pi i k / n), k < n/2
     // NFFT work buffers
     float *patches;    // src_nchunks * W^d
@@ -127,9 +121,9 @@ hipError_t launch_bin_cells(int d, int64_t npts, const double *x, double s0, dou
 size_t stable_tile_sort_scratch(int64_t npts, int64_t ntiles);
 hipError_t stable_tile_sort(int64_t npts, const int32_t *tile, int64_t ntiles, int32_t *perm,
                             int32_t *tile_off, void *scratch, size_t scratch_bytes, hipStream_t st);
-hipError_t launch_point_layout_s(int d, int64_t npts, const double *pts, const double *s,
-                                 const double *o, int T, uint32_t *cellpk, float *frac,
-                                 hipStream_t st);
+// Window rows of sorted points (n x d x 16 FP32), Kaiser-Bessel shape parameter b.
+hipError_t launch_window_rows(int d, int64_t npts, const double *pts, double s, const double *o, int T,
+                              int m, double b, float *rows, hipStream_t st);
 
 // NFFT pipeline kernels (a2-a6).
 constexpr int kNodeItemElems = 256;

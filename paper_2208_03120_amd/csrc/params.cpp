@@ -211,55 +211,6 @@ void build_multiplier(int d, const NfftParams &P, double eta, std::vector<float>
     }
 }
 
-// Normalised window psi(s)/psi(0) in FP64 (host reference of the device tables).
-static double kb_value(double s, const NfftParams &P)
-{
-    const double m = P.m, b = P.kb_b;
-    const double r = std::sqrt(std::max(m * m - s * s, 0.0));
-    if (r < 1e-12) return m * b / std::sinh(b * m);
-    return (m / r) * std::sinh(b * r) / std::sinh(b * m);
-}
-
-// Window as 2m polynomials: interval k covers s in [k - m, k - m + 1]; on it
-// psi(k - m + 1/2 + t) ~ sum_i c[k][i] t^i for t in [-1/2, 1/2] (degree kWinDeg,
-// interpolation at Chebyshev nodes, solved in FP64).  A point with fractional offset f
-// has taps s = f + m - 1 - j (j = 0 .. 2m-1), all at t = f - 1/2 on interval 2m - 1 - j.
-void build_window_poly(const NfftParams &P, std::vector<float> &coef)
-{
-    const int n = kWinDeg + 1;
-    coef.assign((size_t)2 * P.m * n, 0.0f);
-    for (int k = 0; k < 2 * P.m; ++k) {
-        std::vector<double> A((size_t)n * n), rhs(n), c(n);
-        for (int i = 0; i < n; ++i) {
-            const double t = 0.5 * std::cos(M_PI * (i + 0.5) / n);
-            double tp = 1.0;
-            for (int j = 0; j < n; ++j) {
-                A[(size_t)i * n + j] = tp;
-                tp *= t;
-            }
-            rhs[i] = kb_value(k - P.m + 0.5 + t, P);
-        }
-        for (int col = 0; col < n; ++col) {
-            int piv = col;
-            for (int r = col + 1; r < n; ++r)
-                if (std::fabs(A[(size_t)r * n + col]) > std::fabs(A[(size_t)piv * n + col])) piv = r;
-            for (int j = 0; j < n; ++j) std::swap(A[(size_t)col * n + j], A[(size_t)piv * n + j]);
-            std::swap(rhs[col], rhs[piv]);
-            for (int r = col + 1; r < n; ++r) {
-                const double f = A[(size_t)r * n + col] / A[(size_t)col * n + col];
-                for (int j = col; j < n; ++j) A[(size_t)r * n + j] -= f * A[(size_t)col * n + j];
-                rhs[r] -= f * rhs[col];
-            }
-        }
-        for (int r = n - 1; r >= 0; --r) {
-            double v = rhs[r];
-            for (int j = r + 1; j < n; ++j) v -= A[(size_t)r * n + j] * c[j];
-            c[r] = v / A[(size_t)r * n + r];
-        }
-        for (int i = 0; i < n; ++i) coef[(size_t)k * n + i] = (float)c[i];
-    }
-}
-
 void build_twiddle(int n, std::vector<float2> &tw)
 {
     tw.resize(n / 2);
@@ -410,8 +361,6 @@ int resolve_params(int d, double eta, const Extent &ext, const mot_fastsum_param
             }
         }
     if (best_cost < 0) return MOT_EDOMAIN;
-    best.kb_inv_den = 1.0 / (1.0 - std::exp(-2.0 * best.kb_b * best.m));
-    best.kb_edge = best.m * 2.0 * best.kb_b * std::exp(-best.kb_b * best.m) * best.kb_inv_den;
     int chunk = F.chunk > 0 ? F.chunk : (d == 3 ? 512 : 2048);
     best.chunk = chunk;
     *out = best;

@@ -56,6 +56,10 @@ int Arena::get(size_t nbytes, void **out)
     if (custom) {
         p = alloc.alloc(nbytes, alloc.ctx);
         if (!p) return MOT_ENOMEM;
+        if ((uintptr_t)p % 256 != 0) {  // kernels use 16-byte vector accesses
+            alloc.free(p, alloc.ctx);
+            return MOT_EINVAL;
+        }
     } else {
         hipError_t e = hipMalloc(&p, nbytes);
         if (e != hipSuccess) {
@@ -579,8 +583,7 @@ static int bin_marginal(mot_plan_s *P, int k, const double *pts_orig_dev, void *
     MOT_HIP(stable_tile_sort(G.n, tile_tmp, ntiles, G.perm, tile_off_dev, scratch, scratch_bytes,
                              P->stream));
     MOT_HIP(launch_gather_rows(pts_orig_dev, G.perm, G.n, d, G.pts, P->stream));
-    const double sv[3] = {Q.s, Q.s, Q.s};
-    MOT_HIP(launch_point_layout_s(d, G.n, G.pts, sv, Q.o, T, G.cell, G.frac, P->stream));
+    MOT_HIP(launch_window_rows(d, G.n, G.pts, Q.s, Q.o, T, Q.m, Q.kb_b, G.win, P->stream));
     tile_off_host.resize(ntiles + 1);
     MOT_HIP(hipMemcpyAsync(tile_off_host.data(), tile_off_dev, (ntiles + 1) * sizeof(int32_t),
                            hipMemcpyDeviceToHost, P->stream));
@@ -646,10 +649,8 @@ int mot::make_prod_job(mot_plan_s *P, int t, int s, const double *v, int32_t *sl
     if (P->path != MOT_NFFT) return MOT_OK;
     const NfftParams &N = P->P;
     const MargDev &S = P->marg[s], &Tm = P->marg[t];
-    Q.src_cell = S.cell;
-    Q.tgt_cell = Tm.cell;
-    Q.src_frac = S.frac;
-    Q.tgt_frac = Tm.frac;
+    Q.src_win = S.win;
+    Q.tgt_win = Tm.win;
     Q.src_chunk_start = S.chunk_start;
     Q.tgt_chunk_start = Tm.chunk_start;
     Q.src_chunk_tile = S.chunk_tile;
@@ -667,11 +668,7 @@ int mot::make_prod_job(mot_plan_s *P, int t, int s, const double *v, int32_t *sl
         Q.ntile[c] = N.ntile[c];
     }
     Q.W = N.W;
-    Q.kb_b = (float)N.kb_b;
-    Q.kb_inv_den = (float)N.kb_inv_den;
-    Q.kb_edge = (float)N.kb_edge;
     Q.D = P->D;
-    Q.winpoly = P->winpoly;
     Q.twiddle = device_twiddle(N.n);
     int64_t pe = 1, cells = 1;
     for (int c = 0; c < P->d; ++c) {
@@ -726,10 +723,6 @@ int mot::setup_marginals(mot_plan_s *P, const std::vector<double> &pts_h, const 
         build_multiplier(d, P->P, P->eta, D);
         MOT_TRY(P->arena.get_n(D.size(), &P->D));
         MOT_HIP(hipMemcpy(P->D, D.data(), D.size() * sizeof(float), hipMemcpyHostToDevice));
-        std::vector<float> wp;
-        build_window_poly(P->P, wp);
-        MOT_TRY(P->arena.get_n(wp.size(), &P->winpoly));
-        MOT_HIP(hipMemcpy(P->winpoly, wp.data(), wp.size() * sizeof(float), hipMemcpyHostToDevice));
         if (!device_twiddle(P->P.n)) return MOT_EDEVICE;
         log_msg("NFFT params: M=%d n=%d m=%d p=%d tau=%.6g eps_B=%.6g T=%d box=%dx%dx%d est_err=%.3g",
                 P->P.M, P->P.n, P->P.m, P->P.p, P->P.tau, P->P.eps_B, P->P.T, P->P.L[0], P->P.L[1],
@@ -756,8 +749,7 @@ int mot::setup_marginals(mot_plan_s *P, const std::vector<double> &pts_h, const 
             MOT_TRY(P->arena.get_n((size_t)P->n[P->parent[k]], &G.down_src));
         }
         if (P->path == MOT_NFFT) {
-            MOT_TRY(P->arena.get_n((size_t)G.n, &G.cell));
-            MOT_TRY(P->arena.get_n((size_t)G.n * d, &G.frac));
+            MOT_TRY(P->arena.get_n((size_t)G.n * d * 16, &G.win));
         }
         if (nphi > G.n) MOT_HIP(launch_fill_double(G.phi + G.n, 0.0, nphi - G.n, P->stream));
         total_partials += 2 * (int)((G.n + kNodeItemElems - 1) / kNodeItemElems);
@@ -1338,8 +1330,9 @@ int mot_plan_footprint(int32_t K, int32_t d, const int64_t *n, int32_t topology,
         nmax = std::max(nmax, n[k]);
     }
     size_t b = 0;
-    // per point: points, perm, mu, phi, gamma, up/down sources, beta, marginal, layout
-    b += (size_t)total * (8 * d + 4 + 8 * 7 + 4 + 4 * d);
+    // per point: points, perm, mu, phi, gamma, up/down sources, beta, marginal; window
+    // rows on the NFFT path
+    b += (size_t)total * (8 * d + 4 + 8 * 7 + (path == MOT_NFFT ? 64 * d : 0));
     if (topology == MOT_CIRCLE) {
         b += circle_footprint(K, n, path, precision);
     } else if (path == MOT_NFFT) {
