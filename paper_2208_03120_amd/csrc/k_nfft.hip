@@ -274,11 +274,11 @@ struct Stage {
     static constexpr int kPer = (kRow4 + 255) / 256;        // per thread (256 threads)
     static constexpr int kBytes = kRow4 * 16 + (WITH_V ? kStage * 4 : 0);
     f32x4 r[kPer];
-    float v;
+    double v;  // scaled only when stored, so that the loads stay in flight
 
-    // Registers <- global: points pb .. pb + kStage - 1 (zeros past p1).  For spreading,
-    // v is the source value scaled by 2^-e.
-    __device__ __forceinline__ void load(const float *rows, const double *vsrc, int64_t pb, int64_t p1, int e)
+    // Registers <- global: points pb .. pb + kStage - 1 (zeros past p1), and for
+    // spreading the source values.
+    __device__ __forceinline__ void load(const float *rows, const double *vsrc, int64_t pb, int64_t p1)
     {
         const MOT_GLOBAL f32x4 *g = reinterpret_cast<const MOT_GLOBAL f32x4 *>(gp(rows)) + pb * (D * 4);
 #pragma unroll
@@ -288,13 +288,13 @@ struct Stage {
             if (idx < kRow4 && pb + idx / (D * 4) < p1) r[i] = g[idx];
         }
         if constexpr (WITH_V) {
-            v = 0.0f;
+            v = 0.0;
             const int64_t p = pb + threadIdx.x;
-            if (threadIdx.x < kStage && p < p1) v = (float)ldexp(gp(vsrc)[p], -e);
+            if (threadIdx.x < kStage && p < p1) v = gp(vsrc)[p];
         }
     }
-    // LDS <- registers
-    __device__ __forceinline__ void store(unsigned char *buf) const
+    // LDS <- registers; source values are stored as FP32 v 2^-e.
+    __device__ __forceinline__ void store(unsigned char *buf, int e) const
     {
         f32x4 *rl = reinterpret_cast<f32x4 *>(buf);
 #pragma unroll
@@ -303,12 +303,12 @@ struct Stage {
             if (idx < kRow4) rl[idx] = r[i];
         }
         if constexpr (WITH_V)
-            if (threadIdx.x < kStage) reinterpret_cast<float *>(buf + kRow4 * 16)[threadIdx.x] = v;
+            if (threadIdx.x < kStage) reinterpret_cast<float *>(buf + kRow4 * 16)[threadIdx.x] = (float)ldexp(v, -e);
     }
 };
 
 template <int D>
-__global__ __launch_bounds__(64 * kSpreadWaves) void spread_kernel(const ProdJob *__restrict__ jobs,
+__global__ __launch_bounds__(64 * kSpreadWaves, 4) void spread_kernel(const ProdJob *__restrict__ jobs,
                                                                    const int2 *__restrict__ items,
                                                                    int n_items)
 {
@@ -330,17 +330,17 @@ __global__ __launch_bounds__(64 * kSpreadWaves) void spread_kernel(const ProdJob
 #pragma unroll
         for (int t = 0; t < NT; ++t) acc[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
         St stg;
-        stg.load(J.src_win, J.v, p0, p1, e);
-        stg.store(smem);
+        stg.load(J.src_win, J.v, p0, p1);
+        stg.store(smem, e);
         __syncthreads();
         for (int k = 0; k < nstages; ++k) {
             const bool more = k + 1 < nstages;
-            if (more) stg.load(J.src_win, J.v, p0 + (int64_t)(k + 1) * kStage, p1, e);
+            if (more) stg.load(J.src_win, J.v, p0 + (int64_t)(k + 1) * kStage, p1);
             const unsigned char *buf = smem + (k & 1) * St::kBytes;
             const float *rl = reinterpret_cast<const float *>(buf);
             const float *vl = reinterpret_cast<const float *>(buf + St::kRow4 * 16);
             // this wave's 4-point steps of the stage: points 4 j + lane group, j = wave + 4 i
-#pragma unroll
+#pragma unroll 1
             for (int i = 0; i < kStage / 16; ++i) {
                 const int pi = 4 * (wave + 4 * i) + lk;
                 const float *row = rl + pi * (D * kPatch);
@@ -362,7 +362,7 @@ __global__ __launch_bounds__(64 * kSpreadWaves) void spread_kernel(const ProdJob
                     acc[0][0] += x;
                 }
             }
-            if (more) stg.store(smem + ((k + 1) & 1) * St::kBytes);
+            if (more) stg.store(smem + ((k + 1) & 1) * St::kBytes, e);
             __syncthreads();
         }
         if constexpr (D == 1) {
@@ -467,7 +467,7 @@ __global__ __launch_bounds__(256) void fold_kernel(const ProdJob *__restrict__ j
 // A block of kInterpWaves wavefronts takes one chunk; wave w takes the 16-point groups
 // (64 in 1-D) w, w + kInterpWaves, ...
 template <int D>
-__global__ __launch_bounds__(64 * kInterpWaves) void interp_kernel(const ProdJob *__restrict__ jobs,
+__global__ __launch_bounds__(64 * kInterpWaves, 4) void interp_kernel(const ProdJob *__restrict__ jobs,
                                                                    const int2 *__restrict__ items,
                                                                    int n_items)
 {
@@ -520,12 +520,12 @@ __global__ __launch_bounds__(64 * kInterpWaves) void interp_kernel(const ProdJob
         } else {
             const int nstages = (int)((p1 - p0 + kStage - 1) / kStage);
             St stg;
-            stg.load(J.tgt_win, nullptr, p0, p1, 0);
-            stg.store(smem);
+            stg.load(J.tgt_win, nullptr, p0, p1);
+            stg.store(smem, 0);
             __syncthreads();
             for (int k = 0; k < nstages; ++k) {
                 const bool more = k + 1 < nstages;
-                if (more) stg.load(J.tgt_win, nullptr, p0 + (int64_t)(k + 1) * kStage, p1, 0);
+                if (more) stg.load(J.tgt_win, nullptr, p0 + (int64_t)(k + 1) * kStage, p1);
                 const float *rl = reinterpret_cast<const float *>(smem + (k & 1) * St::kBytes);
                 // this wave's group: stage points 16 wave .. 16 wave + 15
                 const float *grow = rl + (16 * wave) * (D * kPatch);
@@ -565,7 +565,7 @@ __global__ __launch_bounds__(64 * kInterpWaves) void interp_kernel(const ProdJob
                     const int64_t p = pb + 4 * lk + r;
                     if (li == r && p < p1) out[p] = ldexp((double)z, e);
                 }
-                if (more) stg.store(smem + ((k + 1) & 1) * St::kBytes);
+                if (more) stg.store(smem + ((k + 1) & 1) * St::kBytes, 0);
                 __syncthreads();
             }
         }
