@@ -403,51 +403,107 @@ __global__ __launch_bounds__(64 * kSpreadWaves, 4) void spread_kernel(const Prod
     }
 }
 
+constexpr int kFoldMaxCover = 4;
+
 // Fold (a2, second half): box grid cell g = sum of the patches covering it, tiles in
-// ascending order and chunks in ascending order within a tile.
-// item = (job, first cell of a run of 256 consecutive box cells).
+// ascending order and chunks in ascending order within a tile.  One wavefront folds one
+// line of cells along the last dimension, so the covering tiles of the leading
+// dimensions are the same on every lane; item = (job, first of kFoldLinesPerItem lines).
 template <int D>
-__global__ __launch_bounds__(256) void fold_kernel(const ProdJob *__restrict__ jobs,
-                                                   const int2 *__restrict__ items, int n_items)
+__global__ __launch_bounds__(64 * kFoldLinesPerItem) void fold_kernel(const ProdJob *__restrict__ jobs,
+                                                                      const int2 *__restrict__ items,
+                                                                      int n_items)
 {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
         const int2 itm = items[it];
         const ProdJob &J = jobs[itm.x];
-        int64_t total = J.L[0];
-        for (int c = 1; c < D; ++c) total *= J.L[c];
-        const int64_t g = (int64_t)itm.y + threadIdx.x;
-        if (g >= total) continue;
-        int gc[3] = {0, 0, 0};
-        int64_t rem = g;
-        for (int c = D - 1; c >= 0; --c) {
-            gc[c] = (int)(rem % J.L[c]);
-            rem /= J.L[c];
+        const int line = itm.y + wave;
+        const int nl = D == 3 ? J.L[0] * J.L[1] : (D == 2 ? J.L[0] : 1);
+        if (line >= nl) continue;
+        const int W = J.W, T = J.T, Ll = J.L[D - 1], ntl = J.ntile[D - 1];
+        int gu[2] = {0, 0};  // line coordinates in the leading dimensions
+        if (D == 3) {
+            gu[0] = line / J.L[1];
+            gu[1] = line - gu[0] * J.L[1];
+        } else if (D == 2) {
+            gu[0] = line;
         }
-        const int W = J.W, T = J.T;
-        int tlo[3] = {0, 0, 0}, thi[3] = {0, 0, 0};
-        for (int c = 0; c < D; ++c) {
-            tlo[c] = max(0, floor_div(gc[c] - W + T, T));  // ceil((g - W + 1) / T)
-            thi[c] = min(J.ntile[c] - 1, gc[c] / T);
+        int tlo[2] = {0, 0}, thi[2] = {0, 0};
+        for (int c = 0; c < D - 1; ++c) {
+            tlo[c] = max(0, floor_div(gu[c] - W + T, T));  // ceil((g - W + 1) / T)
+            thi[c] = min(J.ntile[c] - 1, gu[c] / T);
         }
-        int patch_elems = W;
-        for (int c = 1; c < D; ++c) patch_elems *= W;
-        float acc = 0.0f;
-        for (int t0 = tlo[0]; t0 <= thi[0]; ++t0)
-            for (int t1 = tlo[1]; t1 <= thi[1]; ++t1)
-                for (int t2 = tlo[2]; t2 <= thi[2]; ++t2) {
-                    int tl = t0, loc = gc[0] - t0 * T;
-                    if constexpr (D > 1) {
-                        tl = tl * J.ntile[1] + t1;
-                        loc = loc * W + (gc[1] - t1 * T);
-                    }
-                    if constexpr (D > 2) {
-                        tl = tl * J.ntile[2] + t2;
-                        loc = loc * W + (gc[2] - t2 * T);
-                    }
-                    const int c0 = gp(J.src_tile_chunks)[tl], c1 = gp(J.src_tile_chunks)[tl + 1];
-                    for (int ch = c0; ch < c1; ++ch) acc += gp(J.patches)[(int64_t)ch * patch_elems + loc];
+        const int pe = D == 3 ? W * W * W : (D == 2 ? W * W : W);
+        const MOT_GLOBAL int32_t *tch = gp(J.src_tile_chunks);
+        const MOT_GLOBAL float *pat = gp(J.patches);
+        MOT_GLOBAL float *out = gp(J.grid) + (int64_t)line * Ll;
+        for (int g = lane; g < Ll; g += 64) {
+            const int t2lo = max(0, floor_div(g - W + T, T)), t2hi = min(ntl - 1, g / T);
+            float acc = 0.0f;
+            if (W <= kFoldMaxCover * T) {
+                // at most kFoldMaxCover covering tiles per dimension: the chunk ranges and
+                // first patches of all (t1, t2) pairs of a t0 are loaded together, then
+                // added in the fixed order
+                constexpr int NU = D == 3 ? kFoldMaxCover : 1;
+                for (int t0 = tlo[0]; t0 <= thi[0]; ++t0) {
+                    int c0[NU][kFoldMaxCover], c1[NU][kFoldMaxCover], loc[NU][kFoldMaxCover];
+#pragma unroll
+                    for (int u = 0; u < NU; ++u)
+#pragma unroll
+                        for (int k = 0; k < kFoldMaxCover; ++k) {
+                            const int t1 = tlo[1] + u, t2 = t2lo + k;
+                            int lead_tile = 0, lead_loc = 0;
+                            if constexpr (D == 3) {
+                                lead_tile = t0 * J.ntile[1] + t1;
+                                lead_loc = (gu[0] - t0 * T) * W + (gu[1] - t1 * T);
+                            } else if constexpr (D == 2) {
+                                lead_tile = t0;
+                                lead_loc = gu[0] - t0 * T;
+                            }
+                            c0[u][k] = c1[u][k] = 0;
+                            loc[u][k] = lead_loc * W + (g - t2 * T);
+                            if ((D < 3 || t1 <= thi[1]) && t2 <= t2hi) {
+                                const int tl = lead_tile * ntl + t2;
+                                c0[u][k] = tch[tl];
+                                c1[u][k] = tch[tl + 1];
+                            }
+                        }
+                    float first[NU][kFoldMaxCover];
+#pragma unroll
+                    for (int u = 0; u < NU; ++u)
+#pragma unroll
+                        for (int k = 0; k < kFoldMaxCover; ++k)
+                            first[u][k] = c1[u][k] > c0[u][k] ? pat[(int64_t)c0[u][k] * pe + loc[u][k]] : 0.0f;
+#pragma unroll
+                    for (int u = 0; u < NU; ++u)
+#pragma unroll
+                        for (int k = 0; k < kFoldMaxCover; ++k) {
+                            if (c1[u][k] > c0[u][k]) acc += first[u][k];
+                            for (int ch = c0[u][k] + 1; ch < c1[u][k]; ++ch) acc += pat[(int64_t)ch * pe + loc[u][k]];
+                        }
                 }
-        gp(J.grid)[g] = acc;
+            } else {
+                for (int t0 = tlo[0]; t0 <= thi[0]; ++t0)
+                    for (int t1 = tlo[1]; t1 <= thi[1]; ++t1) {
+                        int lead_tile = 0, lead_loc = 0;
+                        if constexpr (D == 3) {
+                            lead_tile = t0 * J.ntile[1] + t1;
+                            lead_loc = (gu[0] - t0 * T) * W + (gu[1] - t1 * T);
+                        } else if constexpr (D == 2) {
+                            lead_tile = t0;
+                            lead_loc = gu[0] - t0 * T;
+                        }
+                        for (int t2 = t2lo; t2 <= t2hi; ++t2) {
+                            const int tl = lead_tile * ntl + t2;
+                            const int lc = lead_loc * W + (g - t2 * T);
+                            const int ca = tch[tl], cb = tch[tl + 1];
+                            for (int ch = ca; ch < cb; ++ch) acc += pat[(int64_t)ch * pe + lc];
+                        }
+                    }
+            }
+            out[g] = acc;
+        }
     }
 }
 
@@ -595,13 +651,13 @@ hipError_t launch_fold(int d, const ProdJob *jobs, const int2 *items, int n_item
 {
     if (n_items == 0) return hipSuccess;
     if (d == 3)
-        hipLaunchKernelGGL(fold_kernel<3>, dim3(nfft_grid(n_items)), dim3(256), 0, s, jobs, items,
+        hipLaunchKernelGGL(fold_kernel<3>, dim3(nfft_grid(n_items)), dim3(64 * kFoldLinesPerItem), 0, s, jobs, items,
                            n_items);
     else if (d == 2)
-        hipLaunchKernelGGL(fold_kernel<2>, dim3(nfft_grid(n_items)), dim3(256), 0, s, jobs, items,
+        hipLaunchKernelGGL(fold_kernel<2>, dim3(nfft_grid(n_items)), dim3(64 * kFoldLinesPerItem), 0, s, jobs, items,
                            n_items);
     else
-        hipLaunchKernelGGL(fold_kernel<1>, dim3(nfft_grid(n_items)), dim3(256), 0, s, jobs, items,
+        hipLaunchKernelGGL(fold_kernel<1>, dim3(nfft_grid(n_items)), dim3(64 * kFoldLinesPerItem), 0, s, jobs, items,
                            n_items);
     return hipGetLastError();
 }

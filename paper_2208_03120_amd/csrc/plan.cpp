@@ -234,9 +234,8 @@ struct StepBuilder {
                 continue;
             }
             for (int c = 0; c < J.src_nchunks; ++c) spread[J.d].push_back(make_int2(j, c));
-            int64_t cells = 1;
-            for (int c = 0; c < J.d; ++c) cells *= J.L[c];
-            for (int64_t g = 0; g < cells; g += kFoldItemCells) fold[J.d].push_back(make_int2(j, (int)g));
+            const int lines = J.d == 3 ? J.L[0] * J.L[1] : (J.d == 2 ? J.L[0] : 1);
+            for (int l = 0; l < lines; l += kFoldLinesPerItem) fold[J.d].push_back(make_int2(j, l));
             for (int c = 0; c < J.tgt_nchunks; ++c) interp[J.d].push_back(make_int2(j, c));
             int pe = 1;
             for (int c = 0; c < J.d; ++c) pe *= J.W;
