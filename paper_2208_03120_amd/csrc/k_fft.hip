@@ -160,7 +160,7 @@ __global__ __launch_bounds__(256) void fft_pass_kernel(const ProdJob *__restrict
     __shared__ float2 zl[KIND == 0 ? LPR : 1][KIND == 0 ? N : 1];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int g = lane % G, slot = wave * LW + lane / G;
-    for (int t = tid; t < N / 2; t += blockDim.x) tw[t] = twiddle[t];
+    for (int t = tid; t < N / 2; t += blockDim.x) tw[t] = ld2(twiddle, t);
     __syncthreads();
     for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
         const int4 itm = items[it];
@@ -186,27 +186,27 @@ __global__ __launch_bounds__(256) void fft_pass_kernel(const ProdJob *__restrict
                         const int i = q - P.lo_in;
                         if (i >= 0 && i < P.LA) {
                             const int la = a10 + 2 * li, lb = la + 1;
-                            v.x = P.in_r[((int64_t)a2 * P.A1 + la) * P.LA + i];
-                            if (lb < a10 + nl) v.y = P.in_r[((int64_t)a2 * P.A1 + lb) * P.LA + i];
+                            v.x = gp(P.in_r)[((int64_t)a2 * P.A1 + la) * P.LA + i];
+                            if (lb < a10 + nl) v.y = gp(P.in_r)[((int64_t)a2 * P.A1 + lb) * P.LA + i];
                         }
                     } else if (KIND == 1 || KIND == 2) {
                         const int i = q - P.lo_in;
-                        if (i >= 0 && i < P.LA) v = P.in_c[((int64_t)a2 * P.A1 + a10 + li) * P.LA + i];
+                        if (i >= 0 && i < P.LA) v = ld2(P.in_c, ((int64_t)a2 * P.A1 + a10 + li) * P.LA + i);
                     } else {
                         const int f = (int)(__brev((unsigned)q) >> (32 - LOG));
                         const int fs = f < N / 2 ? f : f - N;
                         if (KIND == 3) {
                             if (fs >= -M && fs <= M)
-                                v = P.in_c[((int64_t)a2 * P.A1 + a10 + li) * P.LA + fs + M];
+                                v = ld2(P.in_c, ((int64_t)a2 * P.A1 + a10 + li) * P.LA + fs + M);
                         } else {  // KIND 4: Hermitian half spectra of two real lines
                             const int la = a10 + 2 * li, lb = la + 1;
                             const int fa = fs >= 0 ? fs : -fs;
                             if (fa <= M) {
-                                float2 A = P.in_c[((int64_t)a2 * P.A1 + la) * P.LA + fa];
-                                float2 Bv = lb < a10 + nl ? P.in_c[((int64_t)a2 * P.A1 + lb) * P.LA + fa]
+                                float2 A = ld2(P.in_c, ((int64_t)a2 * P.A1 + la) * P.LA + fa);
+                                float2 Bv = lb < a10 + nl ? ld2(P.in_c, ((int64_t)a2 * P.A1 + lb) * P.LA + fa)
                                                           : make_float2(0.0f, 0.0f);
                                 if (J.d == 1) {
-                                    const float dm = J.D[fa];
+                                    const float dm = gp(J.D)[fa];
                                     A.x *= dm; A.y *= dm; Bv.x *= dm; Bv.y *= dm;
                                 }
                                 if (fa == 0) {
@@ -232,7 +232,7 @@ __global__ __launch_bounds__(256) void fft_pass_kernel(const ProdJob *__restrict
                     const int fs = f < N / 2 ? f : f - N;
                     float dm = 0.0f;
                     if (act && fs >= -M && fs <= M)
-                        dm = J.D[((int64_t)a2 * P.A1 + a10 + li) * B + fs + M];
+                        dm = gp(J.D)[((int64_t)a2 * P.A1 + a10 + li) * B + fs + M];
                     x[e].x *= dm;
                     x[e].y *= dm;
                 }
@@ -281,8 +281,8 @@ __global__ __launch_bounds__(256) void fft_pass_kernel(const ProdJob *__restrict
                     const int q = g + G * e;
                     const int i = q - P.lo_out;
                     if (act && i >= 0 && i < P.Kout) {
-                        P.out_r[((int64_t)a2 * P.A1 + la) * P.Kout + i] = x[e].x;
-                        if (lb < a10 + nl) P.out_r[((int64_t)a2 * P.A1 + lb) * P.Kout + i] = x[e].y;
+                        gp(P.out_r)[((int64_t)a2 * P.A1 + la) * P.Kout + i] = x[e].x;
+                        if (lb < a10 + nl) gp(P.out_r)[((int64_t)a2 * P.A1 + lb) * P.Kout + i] = x[e].y;
                     }
                 }
             }
@@ -297,7 +297,7 @@ __global__ __launch_bounds__(256) void fft_pass_kernel(const ProdJob *__restrict
                     o = ((int64_t)k * P.A2 + a2) * P.A1 + a10 + l;
                 else
                     o = ((int64_t)a2 * P.Kout + k) * P.A1 + a10 + l;
-                P.out_c[o] = stage[l][k];
+                st2(P.out_c, o, stage[l][k]);
             }
             __syncthreads();
         }

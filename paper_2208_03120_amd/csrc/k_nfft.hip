@@ -156,22 +156,6 @@ hipError_t stable_tile_sort(int64_t npts, const int32_t *tile, int64_t ntiles, i
 constexpr int kPatch = 16;  // patch edge T + 2m - 1 in cells
 
 // ---------------------------------------------------------------------------------------
-// Global-memory views of generic pointers: loads and stores through them are global
-// (vector-memory counter only), so waiting for LDS results never also waits for
-// outstanding global loads, as it would with flat instructions.
-#define MOT_GLOBAL __attribute__((address_space(1)))
-template <class T>
-__device__ __forceinline__ const MOT_GLOBAL T *gp(const T *p)
-{
-    return (const MOT_GLOBAL T *)p;
-}
-template <class T>
-__device__ __forceinline__ MOT_GLOBAL T *gp(T *p)
-{
-    return (MOT_GLOBAL T *)p;
-}
-
-// ---------------------------------------------------------------------------------------
 // Kaiser-Bessel window in grid units, normalised to 1 at s = 0:
 //   psi(s) = (m / r) sinh(b r) / sinh(b m),  r = sqrt(m^2 - s^2),  |s| <= m,
 // b = pi (2 - 1/sigma).  Its Fourier transform is I0(m sqrt(b^2 - w^2)), which the host

@@ -72,15 +72,15 @@ __global__ __launch_bounds__(256) void node_kernel(const NodeJob *__restrict__ j
             if (regs) {
 #pragma unroll
                 for (int t = 0; t < kRegChildren; ++t) {
-                    b[t] = t < nch ? J.beta[t][i] : 1.0;
+                    b[t] = t < nch ? gp(gp(J.beta)[t])[i] : 1.0;
                     if (t < nch) cp *= b[t];
                 }
             } else {
-                for (int t = 0; t < nch; ++t) cp *= J.beta[t][i];
+                for (int t = 0; t < nch; ++t) cp *= gp(gp(J.beta)[t])[i];
             }
-            const double g = root ? 1.0 : J.gamma[i];
-            const double mu = J.mu[i];
-            double ph = J.phi[i];
+            const double g = root ? 1.0 : gp(J.gamma)[i];
+            const double mu = gp(J.mu)[i];
+            double ph = gp(J.phi)[i];
             if (upd) {
                 const double nv = mu / (g * cp);
                 if (mu > 0.0) {
@@ -88,17 +88,17 @@ __global__ __launch_bounds__(256) void node_kernel(const NodeJob *__restrict__ j
                     if (root) s2 += (mu / nv) * ph;
                 }
                 if (!isfinite(nv)) bad = true;
-                J.phi[i] = nv;
+                gp(J.phi)[i] = nv;
                 ph = nv;
             }
             if (marg) {
                 const double P = (ph * g) * cp;
-                J.marg_out[i] = P;
+                gp(J.marg_out)[i] = P;
                 s1 += fabs(P - mu);
             }
             if (usrc) {
                 const double v = ph * cp;
-                J.up_src[i] = v;
+                gp(J.up_src)[i] = v;
                 em_up = max(em_up, exp_of(v));
             }
             if (dsrc) {
@@ -112,16 +112,16 @@ __global__ __launch_bounds__(256) void node_kernel(const NodeJob *__restrict__ j
                         for (int t = 0; t < kRegChildren; ++t)
                             if (t < nch && t != c) w *= b[t];
                         const double u = pg * w;
-                        J.down_src[c][i] = u;
+                        gp(gp(J.down_src)[c])[i] = u;
                         em[c] = max(em[c], exp_of(u));
                     }
                 } else {
                     for (int c = 0; c < nch; ++c) {
                         double w = 1.0;
                         for (int t = 0; t < nch; ++t)
-                            if (t != c) w *= J.beta[t][i];
+                            if (t != c) w *= gp(gp(J.beta)[t])[i];
                         const double u = pg * w;
-                        J.down_src[c][i] = u;
+                        gp(gp(J.down_src)[c])[i] = u;
                         atomicMax(J.down_exp[c], exp_of(u));
                     }
                 }
@@ -160,8 +160,8 @@ __global__ __launch_bounds__(256) void node_kernel(const NodeJob *__restrict__ j
             const double t2 = block_sum(s2, red);
             if (tid == 0) {
                 const int slot = J.block0 + (int)(itm.y / kNodeElems);
-                J.partial[2 * slot] = t1;
-                J.partial[2 * slot + 1] = t2;
+                gp(J.partial)[2 * slot] = t1;
+                gp(J.partial)[2 * slot + 1] = t2;
             }
         }
     }
@@ -196,8 +196,8 @@ __global__ __launch_bounds__(256) void finalize_kernel(const FinalJob *__restric
             const int64_t i = (int64_t)itm.y + tid + 256 * k;
             if (i >= J.n0) break;
             double cp = 1.0;
-            for (int t = 0; t < J.nchild; ++t) cp *= J.root_beta[t][i];
-            l1 += fabs(J.phi0[i] * cp - J.mu0[i]);
+            for (int t = 0; t < J.nchild; ++t) cp *= gp(gp(J.root_beta)[t])[i];
+            l1 += fabs(gp(J.phi0)[i] * cp - gp(J.mu0)[i]);
         }
         const double tot = block_sum(l1, red);
         const int blk = (int)(itm.y / kNodeElems);

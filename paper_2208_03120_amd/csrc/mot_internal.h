@@ -21,6 +21,33 @@ constexpr int kMinN = 16;
 constexpr int kMaxChildren = 64;  // children per tree node handled by the node kernels
 
 // ---------------------------------------------------------------------------------------
+// Global-memory views of generic pointers: loads and stores through them are global
+// (vector-memory counter only), so waiting for LDS results never also waits for
+// outstanding global loads, as it would with flat instructions.
+#define MOT_GLOBAL __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ const MOT_GLOBAL T *gp(const T *p)
+{
+    return (const MOT_GLOBAL T *)p;
+}
+template <class T>
+__device__ __forceinline__ MOT_GLOBAL T *gp(T *p)
+{
+    return (MOT_GLOBAL T *)p;
+}
+
+typedef float mot_f32x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ float2 ld2(const float2 *p, int64_t i)  // global load of p[i]
+{
+    const mot_f32x2 v = ((const MOT_GLOBAL mot_f32x2 *)(const void *)p)[i];
+    return make_float2(v[0], v[1]);
+}
+__device__ __forceinline__ void st2(float2 *p, int64_t i, float2 v)  // global store p[i] = v
+{
+    ((MOT_GLOBAL mot_f32x2 *)(void *)p)[i] = mot_f32x2{v.x, v.y};
+}
+
+// ---------------------------------------------------------------------------------------
 // Device-side job descriptors.  Plain structs copied to device memory once per plan
 // (or per batch); kernels read them through an item table of (job, sub-range) pairs.
 
