@@ -17,7 +17,8 @@
 
 namespace mot {
 
-constexpr int kNodeElems = 256;  // elements per node item (one per thread)
+constexpr int kNodeElems = kNodeItemElems;   // elements per node item
+constexpr int kNodeEPT = kNodeElems / 256;     // elements per thread (256 threads)
 constexpr int kRegChildren = 16;  // children held in registers
 
 __device__ __forceinline__ int exp_of(double v)
@@ -64,23 +65,42 @@ __global__ __launch_bounds__(256) void node_kernel(const NodeJob *__restrict__ j
 #pragma unroll
         for (int c = 0; c < kRegChildren; ++c) em[c] = INT32_MIN;
         bool bad = false;
-        for (int k = 0; k < kNodeElems / 256; ++k) {
+        // the inputs of all of this thread's elements (children's messages too, when they
+        // fit in registers) are loaded before any output is written, so that the loads
+        // are in flight together
+        double mu_k[kNodeEPT], ph_k[kNodeEPT], g_k[kNodeEPT];
+        double b[kRegChildren][kNodeEPT];
+#pragma unroll
+        for (int k = 0; k < kNodeEPT; ++k) {
+            const int64_t i = (int64_t)itm.y + tid + 256 * k;
+            mu_k[k] = ph_k[k] = g_k[k] = 1.0;
+#pragma unroll
+            for (int t = 0; t < kRegChildren; ++t) b[t][k] = 1.0;
+            if (i < J.n) {
+                mu_k[k] = gp(J.mu)[i];
+                ph_k[k] = gp(J.phi)[i];
+                if (!root) g_k[k] = gp(J.gamma)[i];
+                if (regs)
+#pragma unroll
+                    for (int t = 0; t < kRegChildren; ++t)
+                        if (t < nch) b[t][k] = gp(gp(J.beta)[t])[i];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < kNodeEPT; ++k) {
             const int64_t i = (int64_t)itm.y + tid + 256 * k;
             if (i >= J.n) break;
-            double b[kRegChildren];
             double cp = 1.0;
             if (regs) {
 #pragma unroll
-                for (int t = 0; t < kRegChildren; ++t) {
-                    b[t] = t < nch ? gp(gp(J.beta)[t])[i] : 1.0;
-                    if (t < nch) cp *= b[t];
-                }
+                for (int t = 0; t < kRegChildren; ++t)
+                    if (t < nch) cp *= b[t][k];
             } else {
                 for (int t = 0; t < nch; ++t) cp *= gp(gp(J.beta)[t])[i];
             }
-            const double g = root ? 1.0 : gp(J.gamma)[i];
-            const double mu = gp(J.mu)[i];
-            double ph = gp(J.phi)[i];
+            const double g = g_k[k];
+            const double mu = mu_k[k];
+            double ph = ph_k[k];
             if (upd) {
                 const double nv = mu / (g * cp);
                 if (mu > 0.0) {
@@ -110,7 +130,7 @@ __global__ __launch_bounds__(256) void node_kernel(const NodeJob *__restrict__ j
                         double w = 1.0;
 #pragma unroll
                         for (int t = 0; t < kRegChildren; ++t)
-                            if (t < nch && t != c) w *= b[t];
+                            if (t < nch && t != c) w *= b[t][k];
                         const double u = pg * w;
                         gp(gp(J.down_src)[c])[i] = u;
                         em[c] = max(em[c], exp_of(u));
@@ -192,12 +212,26 @@ __global__ __launch_bounds__(256) void finalize_kernel(const FinalJob *__restric
         const int2 itm = items[it];
         const FinalJob &J = jobs[itm.x];
         double l1 = 0.0;
-        for (int k = 0; k < kNodeElems / 256; ++k) {
-            const int64_t i = (int64_t)itm.y + tid + 256 * k;
-            if (i >= J.n0) break;
-            double cp = 1.0;
-            for (int t = 0; t < J.nchild; ++t) cp *= gp(gp(J.root_beta)[t])[i];
-            l1 += fabs(gp(J.phi0)[i] * cp - gp(J.mu0)[i]);
+        {
+            // child products of all of this thread's elements, children in ascending order
+            double cp[kNodeEPT];
+            bool ok[kNodeEPT];
+#pragma unroll
+            for (int k = 0; k < kNodeEPT; ++k) {
+                cp[k] = 1.0;
+                ok[k] = (int64_t)itm.y + tid + 256 * k < J.n0;
+            }
+            for (int t = 0; t < J.nchild; ++t) {
+                const MOT_GLOBAL double *bt = gp(gp(J.root_beta)[t]);
+#pragma unroll
+                for (int k = 0; k < kNodeEPT; ++k)
+                    if (ok[k]) cp[k] *= bt[(int64_t)itm.y + tid + 256 * k];
+            }
+#pragma unroll
+            for (int k = 0; k < kNodeEPT; ++k) {
+                const int64_t i = (int64_t)itm.y + tid + 256 * k;
+                if (ok[k]) l1 += fabs(gp(J.phi0)[i] * cp[k] - gp(J.mu0)[i]);
+            }
         }
         const double tot = block_sum(l1, red);
         const int blk = (int)(itm.y / kNodeElems);
