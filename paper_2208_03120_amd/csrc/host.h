@@ -110,6 +110,7 @@ struct MargDev {
     int32_t *chunk_start = nullptr, *chunk_tile = nullptr, *tile_chunks = nullptr;
     int nchunks = 0;
     std::vector<int32_t> h_chunk_tile;
+    std::vector<int32_t> h_chunk_start;  // chunk bounds, nchunks + 1 entries
 };
 
 struct Schedule {

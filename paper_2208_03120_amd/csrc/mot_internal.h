@@ -71,6 +71,9 @@ struct ProdJob {
     const int32_t *src_chunk_tile, *tgt_chunk_tile;    // box-relative tile of each chunk
     const int32_t *src_tile_chunks;       // [ntiles+1] chunk range of each box tile
     int32_t src_nchunks, tgt_nchunks;
+    // host copies of the chunk bounds, used when launch items are built (never read on
+    // the device)
+    const int32_t *h_src_chunk_start, *h_tgt_chunk_start;
     // NFFT geometry
     int32_t n, M, m, T;
     int32_t L[3];      // active box extent per dimension (grid cells)

@@ -223,6 +223,7 @@ struct StepBuilder {
     {
         std::map<std::pair<int, int>, std::vector<int4>> direct;  // (d, precision)
         std::map<int, std::vector<int2>> spread, fold, interp;   // d
+        std::map<int, std::vector<int32_t>> spread_pts, interp_pts;  // points of each item
         std::map<std::pair<int, int>, std::vector<int4>> fft[5]; // (d, n) per pass kind
         std::map<int, int> max_patch;
         for (int j : ids) {
@@ -234,9 +235,14 @@ struct StepBuilder {
                 continue;
             }
             for (int c = 0; c < J.src_nchunks; ++c) spread[J.d].push_back(make_int2(j, c));
+            for (int c = 0; c < J.src_nchunks; ++c)
+                spread_pts[J.d].push_back(J.h_src_chunk_start[c + 1] - J.h_src_chunk_start[c]);
             const int lines = J.d == 3 ? J.L[0] * J.L[1] : (J.d == 2 ? J.L[0] : 1);
             for (int l = 0; l < lines; l += kFoldLinesPerItem) fold[J.d].push_back(make_int2(j, l));
-            for (int c = 0; c < J.tgt_nchunks; ++c) interp[J.d].push_back(make_int2(j, c));
+            for (int c = 0; c < J.tgt_nchunks; ++c) {
+                interp[J.d].push_back(make_int2(j, c));
+                interp_pts[J.d].push_back(J.h_tgt_chunk_start[c + 1] - J.h_tgt_chunk_start[c]);
+            }
             int pe = 1;
             for (int c = 0; c < J.d; ++c) pe *= J.W;
             max_patch[J.d] = std::max(max_patch[J.d], pe);
@@ -260,6 +266,18 @@ struct StepBuilder {
             st.n_items = (int)kv.second.size();
             out->push_back(st);
         }
+        // largest chunks first: the blocks of a launch start roughly in item order, so the
+        // short boundary chunks fill in at the end instead of forming a tail
+        auto by_size = [](std::vector<int2> &v, const std::vector<int32_t> &npts) {
+            std::vector<int> ord(v.size());
+            for (size_t i = 0; i < ord.size(); ++i) ord[i] = (int)i;
+            std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return npts[a] > npts[b]; });
+            std::vector<int2> out(v.size());
+            for (size_t i = 0; i < ord.size(); ++i) out[i] = v[ord[i]];
+            v.swap(out);
+        };
+        for (auto &kv : spread) by_size(kv.second, spread_pts[kv.first]);
+        for (auto &kv : interp) by_size(kv.second, interp_pts[kv.first]);
         for (auto &kv : spread) {
             Step st{ST_SPREAD};
             st.d = kv.first;
@@ -618,6 +636,7 @@ static int bin_marginal(mot_plan_s *P, int k, const double *pts_orig_dev, void *
     bounds.push_back((int32_t)G.n);
     G.nchunks = (int)starts.size();
     G.h_chunk_tile = tiles;
+    G.h_chunk_start = bounds;
     MOT_TRY(P->arena.get_n(bounds.size() + 2, &G.chunk_start));
     MOT_TRY(P->arena.get_n(tiles.size() + 1, &G.chunk_tile));
     MOT_TRY(P->arena.get_n(tch2.size() + 1, &G.tile_chunks));
@@ -657,6 +676,8 @@ int mot::make_prod_job(mot_plan_s *P, int t, int s, const double *v, int32_t *sl
     Q.src_tile_chunks = S.tile_chunks;
     Q.src_nchunks = S.nchunks;
     Q.tgt_nchunks = Tm.nchunks;
+    Q.h_src_chunk_start = S.h_chunk_start.data();
+    Q.h_tgt_chunk_start = Tm.h_chunk_start.data();
     Q.n = N.n;
     Q.M = N.M;
     Q.m = N.m;
