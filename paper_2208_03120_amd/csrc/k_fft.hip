@@ -24,6 +24,11 @@
 //   3 INV  spec0[L0][H][B]       -> spec1[L0][L1][H]     (axis 1)
 //   4 C2R  spec1[L0][L1][H]      -> grid[L0][L1][L2]     (axis 2, Hermitian half spectrum)
 // 2-D uses 0, 2, 4 and 1-D uses 0 and 4 (which then applies the multiplier).
+//
+// When a box slab's half spectrum fits in LDS, 3-D uses three passes instead:
+//   6 SLAB grid[L0][L1][L2]  -> spec1[L0][H][B]   (per slab g0: R2C axis 2, FWD axis 1)
+//   5 FUSE spec1[L0][H][B]   -> spec0[L0][H][B]   (axis 0 as pass 2; 16 columns staged in LDS)
+//   7 SLAB spec0[L0][H][B]   -> grid[L0][L1][L2]  (per slab g0: INV axis 1, C2R axis 2)
 #include "mot_internal.h"
 
 namespace mot {
@@ -133,7 +138,7 @@ __device__ __forceinline__ PassGeom pass_geom(const ProdJob &J)
     if (J.d == 3) {
         if (KIND == 0) { P.A2 = J.L[0]; P.A1 = J.L[1]; P.LA = J.L[2]; P.lo_in = J.lo[2]; P.Kout = H; P.out_c = J.spec0; }
         if (KIND == 1) { P.A2 = H; P.A1 = J.L[0]; P.LA = J.L[1]; P.lo_in = J.lo[1]; P.Kout = B; P.in_c = J.spec0; P.out_c = J.spec1; }
-        if (KIND == 2) { P.A2 = H; P.A1 = B; P.LA = J.L[0]; P.lo_in = J.lo[0]; P.Kout = J.L[0]; P.lo_out = J.lo[0]; P.in_c = J.spec1; P.out_c = J.spec0; }
+        if (KIND == 2 || KIND == 5) { P.A2 = H; P.A1 = B; P.LA = J.L[0]; P.lo_in = J.lo[0]; P.Kout = J.L[0]; P.lo_out = J.lo[0]; P.in_c = J.spec1; P.out_c = J.spec0; }
         if (KIND == 3) { P.A2 = J.L[0]; P.A1 = H; P.LA = B; P.Kout = J.L[1]; P.lo_out = J.lo[1]; P.in_c = J.spec0; P.out_c = J.spec1; }
         if (KIND == 4) { P.A2 = J.L[0]; P.A1 = J.L[1]; P.LA = H; P.Kout = J.L[2]; P.lo_out = J.lo[2]; P.in_c = J.spec1; }
     } else if (J.d == 2) {
@@ -158,6 +163,8 @@ __global__ __launch_bounds__(256) void fft_pass_kernel(const ProdJob *__restrict
     __shared__ float2 tw[N / 2];
     __shared__ float2 stage[kTL][N];
     __shared__ float2 zl[KIND == 0 ? LPR : 1][KIND == 0 ? N : 1];
+    __shared__ float2 stin[KIND == 5 ? kTL : 1][KIND == 5 ? N : 1];  // staged input columns
+    constexpr bool FWD = KIND <= 2 || KIND == 5, MUL = KIND == 2 || KIND == 5, INV = KIND >= 2;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int g = lane % G, slot = wave * LW + lane / G;
     for (int t = tid; t < N / 2; t += blockDim.x) tw[t] = ld2(twiddle, t);
@@ -172,6 +179,15 @@ __global__ __launch_bounds__(256) void fft_pass_kernel(const ProdJob *__restrict
         const bool paired = (KIND == 0 || KIND == 4);
         const int ncl = paired ? (nl + 1) / 2 : nl;
         const int rounds = (ncl + LPR - 1) / LPR;
+        if constexpr (KIND == 5) {
+            // columns (k2, k1 = a10 .. a10 + nl - 1) of the g0-major input: each row g0 is
+            // nl consecutive complex values
+            for (int t = tid; t < P.LA * nl; t += blockDim.x) {
+                const int i = t / nl, l = t - i * nl;
+                stin[l][i] = ld2(P.in_c, ((int64_t)i * P.A2 + a2) * P.A1 + a10 + l);
+            }
+            __syncthreads();
+        }
         for (int r = 0; r < rounds; ++r) {
             const int li = r * LPR + slot;
             const bool act = li < ncl;
@@ -192,6 +208,9 @@ __global__ __launch_bounds__(256) void fft_pass_kernel(const ProdJob *__restrict
                     } else if (KIND == 1 || KIND == 2) {
                         const int i = q - P.lo_in;
                         if (i >= 0 && i < P.LA) v = ld2(P.in_c, ((int64_t)a2 * P.A1 + a10 + li) * P.LA + i);
+                    } else if (KIND == 5) {
+                        const int i = q - P.lo_in;
+                        if (i >= 0 && i < P.LA) v = stin[li][i];
                     } else {
                         const int f = (int)(__brev((unsigned)q) >> (32 - LOG));
                         const int fs = f < N / 2 ? f : f - N;
@@ -223,8 +242,8 @@ __global__ __launch_bounds__(256) void fft_pass_kernel(const ProdJob *__restrict
                 x[e] = v;
             }
             // ---- transform
-            if (KIND <= 2) fft_dif<N>(x, g, tw);
-            if (KIND == 2) {
+            if (FWD) fft_dif<N>(x, g, tw);
+            if (MUL) {
 #pragma unroll
                 for (int e = 0; e < E; ++e) {
                     const int q = g + G * e;
@@ -237,7 +256,7 @@ __global__ __launch_bounds__(256) void fft_pass_kernel(const ProdJob *__restrict
                     x[e].y *= dm;
                 }
             }
-            if (KIND >= 2) fft_dit_inv<N>(x, g, tw);
+            if (INV) fft_dit_inv<N>(x, g, tw);
             // ---- store
             if (KIND == 0) {
 #pragma unroll
@@ -267,7 +286,7 @@ __global__ __launch_bounds__(256) void fft_pass_kernel(const ProdJob *__restrict
                     const int fs = f < N / 2 ? f : f - N;
                     if (act && fs >= -M && fs <= M) stage[li][fs + M] = x[e];
                 }
-            } else if (KIND == 2 || KIND == 3) {
+            } else if (KIND == 2 || KIND == 3 || KIND == 5) {
 #pragma unroll
                 for (int e = 0; e < E; ++e) {
                     const int q = g + G * e;
@@ -287,17 +306,156 @@ __global__ __launch_bounds__(256) void fft_pass_kernel(const ProdJob *__restrict
                 }
             }
         }
-        if (KIND <= 3) {
+        if (KIND <= 3 || KIND == 5) {
             __syncthreads();
-            // out layout: KIND 0, 2: [k][a2][a1];  KIND 1, 3: [a2][k][a1]
+            // out layout: KIND 0, 2, 5: [k][a2][a1];  KIND 1, 3: [a2][k][a1]
             for (int t = tid; t < P.Kout * nl; t += blockDim.x) {
                 const int k = t / nl, l = t - k * nl;
                 int64_t o;
-                if (KIND == 0 || KIND == 2)
+                if (KIND == 0 || KIND == 2 || KIND == 5)
                     o = ((int64_t)k * P.A2 + a2) * P.A1 + a10 + l;
                 else
                     o = ((int64_t)a2 * P.Kout + k) * P.A1 + a10 + l;
                 st2(P.out_c, o, stage[l][k]);
+            }
+            __syncthreads();
+        }
+    }
+}
+
+
+// ---------------------------------------------------------------------------------------
+// Slab passes of the 3-D transform: one box slab g0 per work item, both in-slab axes, with
+// the slab's half spectrum X[L1][H] held in LDS between them.
+//   forward: grid[g0][L1][L2] --R2C axis 2--> X[L1][H] --FWD axis 1--> spec1[g0][H][B]
+//   inverse: spec0[g0][H][B] --INV axis 1--> X[L1][H] --C2R axis 2--> grid[g0][L1][L2]
+// Lines are transformed exactly as in passes 0, 1 (forward) and 3, 4 (inverse).
+template <int N, bool INVERSE>
+__global__ __launch_bounds__(kSlabThreads) void fft_slab_kernel(const ProdJob *__restrict__ jobs,
+                                                                const int4 *__restrict__ items, int n_items,
+                                                                const float2 *__restrict__ twiddle)
+{
+    using S = FftShape<N>;
+    constexpr int G = S::G, E = S::E, LW = S::LW, LOG = S::LOG;
+    constexpr int LPR = (kSlabThreads / 64) * LW;  // lines per round
+    __shared__ float2 tw[N / 2];
+    __shared__ float2 X[kSlabLds / 8];
+    __shared__ float2 zl[INVERSE ? 1 : LPR][INVERSE ? 1 : N];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int g = lane % G, slot = wave * LW + lane / G;
+    for (int t = tid; t < N / 2; t += blockDim.x) tw[t] = ld2(twiddle, t);
+    __syncthreads();
+    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const int4 itm = items[it];
+        const ProdJob &J = jobs[itm.x];
+        const int g0 = itm.y, M = J.M, H = M + 1, B = 2 * M + 1;
+        const int L1 = J.L[1], L2 = J.L[2], lo1 = J.lo[1], lo2 = J.lo[2];
+        const int ncl = (L1 + 1) / 2;  // complex lines carrying two real lines of axis 2
+        MOT_GLOBAL float *grid = gp(J.grid) + (int64_t)g0 * L1 * L2;
+        if constexpr (!INVERSE) {
+            for (int c0 = 0; c0 < ncl; c0 += LPR) {
+                const int c = c0 + slot, la = 2 * c, lb = la + 1;
+                const bool act = c < ncl;
+                float2 x[E];
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    const int i = g + G * e - lo2;
+                    float2 v = make_float2(0.0f, 0.0f);
+                    if (act && i >= 0 && i < L2) {
+                        v.x = grid[(int64_t)la * L2 + i];
+                        if (lb < L1) v.y = grid[(int64_t)lb * L2 + i];
+                    }
+                    x[e] = v;
+                }
+                fft_dif<N>(x, g, tw);
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    const int f = (int)(__brev((unsigned)(g + G * e)) >> (32 - LOG));
+                    const int fs = f < N / 2 ? f : f - N;
+                    if (act && fs >= -M && fs <= M) zl[slot][fs + M] = x[e];
+                }
+                __builtin_amdgcn_wave_barrier();  // the line's band is read back by its own wavefront
+                // unpack A(k) = (Z(k) + conj Z(-k)) / 2, B(k) = (Z(k) - conj Z(-k)) / (2i)
+                if (act)
+                    for (int k = g; k < H; k += G) {
+                        const float2 z = zl[slot][k + M], zm = zl[slot][M - k];
+                        X[la * H + k] = make_float2(0.5f * (z.x + zm.x), 0.5f * (z.y - zm.y));
+                        if (lb < L1) X[lb * H + k] = make_float2(0.5f * (z.y + zm.y), 0.5f * (zm.x - z.x));
+                    }
+                __builtin_amdgcn_wave_barrier();
+            }
+            __syncthreads();
+            for (int k0 = 0; k0 < H; k0 += LPR) {
+                const int k2 = k0 + slot;
+                const bool act = k2 < H;
+                float2 x[E];
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    const int i = g + G * e - lo1;
+                    x[e] = (act && i >= 0 && i < L1) ? X[i * H + k2] : make_float2(0.0f, 0.0f);
+                }
+                fft_dif<N>(x, g, tw);
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    const int f = (int)(__brev((unsigned)(g + G * e)) >> (32 - LOG));
+                    const int fs = f < N / 2 ? f : f - N;
+                    if (act && fs >= -M && fs <= M) st2(J.spec1, ((int64_t)g0 * H + k2) * B + fs + M, x[e]);
+                }
+            }
+            __syncthreads();  // X is rewritten by the next item
+        } else {
+            for (int k0 = 0; k0 < H; k0 += LPR) {
+                const int k2 = k0 + slot;
+                const bool act = k2 < H;
+                float2 x[E];
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    const int f = (int)(__brev((unsigned)(g + G * e)) >> (32 - LOG));
+                    const int fs = f < N / 2 ? f : f - N;
+                    x[e] = (act && fs >= -M && fs <= M) ? ld2(J.spec0, ((int64_t)g0 * H + k2) * B + fs + M)
+                                                        : make_float2(0.0f, 0.0f);
+                }
+                fft_dit_inv<N>(x, g, tw);
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    const int i = g + G * e - lo1;
+                    if (act && i >= 0 && i < L1) X[i * H + k2] = x[e];
+                }
+            }
+            __syncthreads();
+            for (int c0 = 0; c0 < ncl; c0 += LPR) {
+                const int c = c0 + slot, la = 2 * c, lb = la + 1;
+                const bool act = c < ncl;
+                float2 x[E];
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    const int f = (int)(__brev((unsigned)(g + G * e)) >> (32 - LOG));
+                    const int fs = f < N / 2 ? f : f - N;
+                    const int fa = fs >= 0 ? fs : -fs;
+                    float2 v = make_float2(0.0f, 0.0f);
+                    if (act && fa <= M) {
+                        // Hermitian half spectra of two real lines, combined as Z = A + i B
+                        const float2 A = X[la * H + fa];
+                        const float2 Bv = lb < L1 ? X[lb * H + fa] : make_float2(0.0f, 0.0f);
+                        if (fa == 0) {
+                            v = make_float2(A.x, Bv.x);
+                        } else if (fs > 0) {
+                            v = make_float2(A.x - Bv.y, A.y + Bv.x);
+                        } else {
+                            v = make_float2(A.x + Bv.y, Bv.x - A.y);
+                        }
+                    }
+                    x[e] = v;
+                }
+                fft_dit_inv<N>(x, g, tw);
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    const int i = g + G * e - lo2;
+                    if (act && i >= 0 && i < L2) {
+                        grid[(int64_t)la * L2 + i] = x[e].x;
+                        if (lb < L1) grid[(int64_t)lb * L2 + i] = x[e].y;
+                    }
+                }
             }
             __syncthreads();
         }
@@ -314,7 +472,11 @@ static hipError_t launch_n(int kind, const ProdJob *jobs, const int4 *items, int
     case 1: hipLaunchKernelGGL((fft_pass_kernel<N, 1>), dim3(grid), dim3(256), 0, s, jobs, items, n_items, tw); break;
     case 2: hipLaunchKernelGGL((fft_pass_kernel<N, 2>), dim3(grid), dim3(256), 0, s, jobs, items, n_items, tw); break;
     case 3: hipLaunchKernelGGL((fft_pass_kernel<N, 3>), dim3(grid), dim3(256), 0, s, jobs, items, n_items, tw); break;
-    default: hipLaunchKernelGGL((fft_pass_kernel<N, 4>), dim3(grid), dim3(256), 0, s, jobs, items, n_items, tw); break;
+    case 4: hipLaunchKernelGGL((fft_pass_kernel<N, 4>), dim3(grid), dim3(256), 0, s, jobs, items, n_items, tw); break;
+    case 5: hipLaunchKernelGGL((fft_pass_kernel<N, 5>), dim3(grid), dim3(256), 0, s, jobs, items, n_items, tw); break;
+    case 6: hipLaunchKernelGGL((fft_slab_kernel<N, false>), dim3(grid), dim3(kSlabThreads), 0, s, jobs, items, n_items, tw); break;
+    case 7: hipLaunchKernelGGL((fft_slab_kernel<N, true>), dim3(grid), dim3(kSlabThreads), 0, s, jobs, items, n_items, tw); break;
+    default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }

@@ -224,7 +224,7 @@ struct StepBuilder {
         std::map<std::pair<int, int>, std::vector<int4>> direct;  // (d, precision)
         std::map<int, std::vector<int2>> spread, fold, interp;   // d
         std::map<int, std::vector<int32_t>> spread_pts, interp_pts;  // points of each item
-        std::map<std::pair<int, int>, std::vector<int4>> fft[5]; // (d, n) per pass kind
+        std::map<std::pair<int, int>, std::vector<int4>> fft[8]; // (d, n) per pass kind
         std::map<int, int> max_patch;
         for (int j : ids) {
             const ProdJob &J = host_jobs[j];
@@ -246,15 +246,29 @@ struct StepBuilder {
             int pe = 1;
             for (int c = 0; c < J.d; ++c) pe *= J.W;
             max_patch[J.d] = std::max(max_patch[J.d], pe);
+            // 3-D boxes whose slab half spectrum fits in LDS take the three-pass chain
+            const bool slab = J.d == 3 && (int64_t)J.L[1] * (J.M + 1) * 8 <= kSlabLds;
             const int kinds3[5] = {0, 1, 2, 3, 4}, kinds2[3] = {0, 2, 4}, kinds1[2] = {0, 4};
             const int *kinds = J.d == 3 ? kinds3 : (J.d == 2 ? kinds2 : kinds1);
             const int nk = J.d == 3 ? 5 : (J.d == 2 ? 3 : 2);
-            for (int q = 0; q < nk; ++q) {
+            if (slab) {
+                for (int g0 = 0; g0 < J.L[0]; ++g0) {
+                    fft[6][{J.d, J.n}].push_back(make_int4(j, g0, 0, 0));
+                    fft[7][{J.d, J.n}].push_back(make_int4(j, g0, 0, 0));
+                }
                 int A2, A1;
-                fft_dims(J, kinds[q], &A2, &A1);
-                auto &v = fft[kinds[q]][{J.d, J.n}];
+                fft_dims(J, 2, &A2, &A1);
+                auto &v = fft[5][{J.d, J.n}];
                 for (int a2 = 0; a2 < A2; ++a2)
                     for (int a1 = 0; a1 < A1; a1 += kFftLinesPerItem) v.push_back(make_int4(j, a2, a1, 0));
+            } else {
+                for (int q = 0; q < nk; ++q) {
+                    int A2, A1;
+                    fft_dims(J, kinds[q], &A2, &A1);
+                    auto &v = fft[kinds[q]][{J.d, J.n}];
+                    for (int a2 = 0; a2 < A2; ++a2)
+                        for (int a1 = 0; a1 < A1; a1 += kFftLinesPerItem) v.push_back(make_int4(j, a2, a1, 0));
+                }
             }
         }
         for (auto &kv : direct) {
@@ -295,7 +309,8 @@ struct StepBuilder {
             st.n_items = (int)kv.second.size();
             out->push_back(st);
         }
-        for (int kind = 0; kind < 5; ++kind)
+        // per job the chain order holds: 0 < 1 < 2 < 3 < 4 and 6 < 5 < 7
+        for (int kind : {0, 6, 1, 2, 5, 3, 4, 7})
             for (auto &kv : fft[kind]) {
                 Step st{ST_FFT};
                 st.d = kv.first.first;
