@@ -27,7 +27,7 @@
 //
 // When a box slab's half spectrum fits in LDS, 3-D uses three passes instead:
 //   6 SLAB grid[L0][L1][L2]  -> spec1[L0][H][B]   (per slab g0: R2C axis 2, FWD axis 1)
-//   5 FUSE spec1[L0][H][B]   -> spec0[L0][H][B]   (axis 0 as pass 2; 16 columns staged in LDS)
+//   5 FUSE spec1[L0][H][B]   -> spec0[L0][H][B]   (axis 0 as pass 2, reading g0-major input)
 //   7 SLAB spec0[L0][H][B]   -> grid[L0][L1][L2]  (per slab g0: INV axis 1, C2R axis 2)
 #include "mot_internal.h"
 
@@ -163,7 +163,6 @@ __global__ __launch_bounds__(256) void fft_pass_kernel(const ProdJob *__restrict
     __shared__ float2 tw[N / 2];
     __shared__ float2 stage[kTL][N];
     __shared__ float2 zl[KIND == 0 ? LPR : 1][KIND == 0 ? N : 1];
-    __shared__ float2 stin[KIND == 5 ? kTL : 1][KIND == 5 ? N : 1];  // staged input columns
     constexpr bool FWD = KIND <= 2 || KIND == 5, MUL = KIND == 2 || KIND == 5, INV = KIND >= 2;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int g = lane % G, slot = wave * LW + lane / G;
@@ -179,15 +178,6 @@ __global__ __launch_bounds__(256) void fft_pass_kernel(const ProdJob *__restrict
         const bool paired = (KIND == 0 || KIND == 4);
         const int ncl = paired ? (nl + 1) / 2 : nl;
         const int rounds = (ncl + LPR - 1) / LPR;
-        if constexpr (KIND == 5) {
-            // columns (k2, k1 = a10 .. a10 + nl - 1) of the g0-major input: each row g0 is
-            // nl consecutive complex values
-            for (int t = tid; t < P.LA * nl; t += blockDim.x) {
-                const int i = t / nl, l = t - i * nl;
-                stin[l][i] = ld2(P.in_c, ((int64_t)i * P.A2 + a2) * P.A1 + a10 + l);
-            }
-            __syncthreads();
-        }
         for (int r = 0; r < rounds; ++r) {
             const int li = r * LPR + slot;
             const bool act = li < ncl;
@@ -208,9 +198,9 @@ __global__ __launch_bounds__(256) void fft_pass_kernel(const ProdJob *__restrict
                     } else if (KIND == 1 || KIND == 2) {
                         const int i = q - P.lo_in;
                         if (i >= 0 && i < P.LA) v = ld2(P.in_c, ((int64_t)a2 * P.A1 + a10 + li) * P.LA + i);
-                    } else if (KIND == 5) {
+                    } else if (KIND == 5) {  // g0-major input: line elements H B apart
                         const int i = q - P.lo_in;
-                        if (i >= 0 && i < P.LA) v = stin[li][i];
+                        if (i >= 0 && i < P.LA) v = ld2(P.in_c, ((int64_t)i * P.A2 + a2) * P.A1 + a10 + li);
                     } else {
                         const int f = (int)(__brev((unsigned)q) >> (32 - LOG));
                         const int fs = f < N / 2 ? f : f - N;
