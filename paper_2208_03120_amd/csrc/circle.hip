@@ -13,8 +13,11 @@
 //
 // Dense path: the GEMMs run on MFMA (v_mfma_f32_32x32x16_bf16 / _f16) with FP32
 // accumulation; A is converted on the fly while it is staged in LDS.  Precision modes:
-// BF16, FP16 (rows of A scaled by powers of two) and split BF16 (A = Ah + Al,
-// B = Bh + Bl, C = Ah Bh + Ah Bl + Al Bh).  The reductions accumulate in FP64.
+// BF16, FP16 and split BF16 (A = Ah + Al, B = Bh + Bl, C = Ah Bh + Ah Bl + Al Bh).  The
+// FP32 matrices carry a power-of-two scale per row: before each product the rows of
+// A diag(phi) are normalised (exponent of their largest entry, taken in FP64) and the
+// exponent is added to the row's scale, so long chains of products (K up to thousands of
+// times n_k growth per step) stay in range.  The reductions apply the scales in FP64.
 // NFFT path: every row of a product is one fast summation (column by column in the
 // paper's words), run by the tree path's spreading / FFT / interpolation kernels with
 // one job per row; matrices are FP64.
@@ -46,9 +49,10 @@ __device__ __forceinline__ unsigned short f16_bits(float x)
     return __builtin_bit_cast(unsigned short, h);
 }
 
-// C[M x N] (row-major, ldc) = A[M x K] (FP32, lda) diag(phi) B[N x K]^T (16-bit, ldb),
-// all dimensions padded to the tile sizes by the caller (zero padding).  MODE: 0 BF16,
-// 1 FP16 (row scale 2^-rexp[i] applied to A and undone on C), 2 split BF16.
+// C[M x N] (row-major, ldc) = diag(2^-rexp) A[M x K] (FP32, lda) diag(phi) B[N x K]^T
+// (16-bit, ldb), all dimensions padded to the tile sizes by the caller (zero padding);
+// the products A_il phi_l 2^-rexp_i are formed in FP64.  MODE: 0 BF16, 1 FP16,
+// 2 split BF16.
 template <int MODE>
 __global__ __launch_bounds__(256) void gemm_kernel(const float *__restrict__ A, int lda,
                                                    const double *__restrict__ phi,
@@ -59,7 +63,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(const float *__restrict__ A, 
 {
     __shared__ unsigned short As[kBM * kLdsK], Bs[kBN * kLdsK];
     __shared__ unsigned short Asl[MODE == 2 ? kBM * kLdsK : 1], Bsl[MODE == 2 ? kBN * kLdsK : 1];
-    __shared__ float phis[kBK];
+    __shared__ double phis[kBK];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;  // wave's 64 x 64 sub-tile
     const int m0 = blockIdx.y * kBM, n0 = blockIdx.x * kBN;
@@ -72,10 +76,9 @@ __global__ __launch_bounds__(256) void gemm_kernel(const float *__restrict__ A, 
             for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
     // global staging assignment: A: row tid/2, 16 columns from (tid&1)*16; B: row tid/2, 16
     const int ar = tid >> 1, ac = (tid & 1) * 16;
-    float rowscale = 1.0f;
-    if (MODE == 1) rowscale = ldexpf(1.0f, -rexp[m0 + ar]);
+    const double rowscale = ldexp(1.0, -rexp[m0 + ar]);
     for (int k0 = 0; k0 < K; k0 += kBK) {
-        if (tid < kBK) phis[tid] = (float)phi[k0 + tid];
+        if (tid < kBK) phis[tid] = phi[k0 + tid];
         __syncthreads();
         {
             const float4 *src = reinterpret_cast<const float4 *>(A + (int64_t)(m0 + ar) * lda + k0 + ac);
@@ -86,7 +89,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(const float *__restrict__ A, 
                 const float av[4] = {a4.x, a4.y, a4.z, a4.w};
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
-                    const float x = av[u] * phis[ac + 4 * q + u] * rowscale;
+                    const float x = (float)((double)av[u] * phis[ac + 4 * q + u] * rowscale);
                     if (MODE == 1) {
                         hv[4 * q + u] = f16_bits(x);
                     } else {
@@ -156,28 +159,39 @@ __global__ __launch_bounds__(256) void gemm_kernel(const float *__restrict__ A, 
             for (int r = 0; r < 16; ++r) {
                 const int row = m0 + wm + 32 * i + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
                 const int col = n0 + wn + 32 * j + (lane & 31);
-                float v = acc[i][j][r];
-                if (MODE == 1) v = ldexpf(v, rexp[row]);
-                C[(int64_t)row * ldc + col] = v;
+                C[(int64_t)row * ldc + col] = acc[i][j][r];
             }
 }
 
-// rexp[i] = exponent of max_l |A[i][l] phi_l| (FP16 mode row scales), one block per row.
+// rexp[i] = exponent of max_l |A[i][l] phi_l| (in FP64; 0 for a zero row), and the row
+// scale of the product: s_out[i] = s_in[i] + rexp[i].  One block per row.
 __global__ __launch_bounds__(256) void row_exp_kernel(const float *__restrict__ A, int lda, int K,
-                                                      const double *__restrict__ phi, int32_t *rexp)
+                                                      const double *__restrict__ phi, int32_t *rexp,
+                                                      const int32_t *__restrict__ s_in, int32_t *s_out)
 {
-    __shared__ float red[4];
+    __shared__ double red[4];
     const int i = blockIdx.x;
-    float m = 0.0f;
-    for (int l = threadIdx.x; l < K; l += blockDim.x) m = fmaxf(m, fabsf(A[(int64_t)i * lda + l] * (float)phi[l]));
+    double m = 0.0;
+    for (int l = threadIdx.x; l < K; l += blockDim.x) m = fmax(m, fabs((double)A[(int64_t)i * lda + l] * phi[l]));
 #pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+    for (int o = 32; o >= 1; o >>= 1) m = fmax(m, __shfl_xor(m, o));
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
     __syncthreads();
     if (threadIdx.x == 0) {
-        float mm = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
-        rexp[i] = mm > 0.0f ? ilogbf(mm) : 0;
+        const double mm = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+        const int e = (mm > 0.0 && mm < INFINITY) ? ilogb(mm) : 0;
+        rexp[i] = e;
+        s_out[i] = s_in[i] + e;
     }
+}
+
+// w[i] = phi0_i 2^(sb[i] + sg[i]): the first marginal's scaling times the row scales of
+// the two matrices of a column sum.
+__global__ void row_weight_kernel(const double *__restrict__ phi0, const int32_t *__restrict__ sb,
+                                  const int32_t *__restrict__ sg, int64_t n1, double *__restrict__ w)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n1) w[i] = ldexp(phi0[i], sb[i] + sg[i]);
 }
 
 // Kernel matrix in 16-bit form: Bh[i][j] = round(K(x^a_i, x^b_j)), Bl = round(rest) (split
@@ -248,7 +262,8 @@ __global__ __launch_bounds__(256) void colsum_kernel(const T *__restrict__ Yb, c
 template <class T>
 __global__ __launch_bounds__(256) void rowsum_kernel(const double *__restrict__ x0, const double *__restrict__ x1,
                                                      int64_t n1, int d, double eta, const double *__restrict__ phi1,
-                                                     const T *__restrict__ Yb1, int ld, double *__restrict__ den)
+                                                     const T *__restrict__ Yb1, int ld, const int32_t *__restrict__ rs,
+                                                     double *__restrict__ den)
 {
     __shared__ double red[4];
     const int64_t i = blockIdx.x;
@@ -267,7 +282,10 @@ __global__ __launch_bounds__(256) void rowsum_kernel(const double *__restrict__ 
     for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
     __syncthreads();
-    if (threadIdx.x == 0) den[i] = (red[0] + red[1]) + (red[2] + red[3]);
+    if (threadIdx.x == 0) {
+        const double t = (red[0] + red[1]) + (red[2] + red[3]);
+        den[i] = rs ? ldexp(t, rs[i]) : t;  // row scale of Yb_1 (dense path)
+    }
 }
 
 // phi update from a denominator (column sums: nparts > 0 partial rows to add in order;
@@ -393,6 +411,12 @@ struct CircleState {
     void *Yg1 = nullptr;           // Yg_1 = Kmat(0, 1) (constant)
     std::vector<unsigned short *> Kb_h, Kb_l, Kg_h, Kg_l;  // dense: Kmat(k,k+1), Kmat(k,k-1)
     int32_t *rexp = nullptr;
+    // dense path: power-of-two scale of every row of each matrix (see the file comment)
+    int K = 0;
+    std::vector<int32_t *> sb;     // [K] row scales of Yb_k
+    int32_t *sg[2] = {nullptr, nullptr};
+    int32_t *szero = nullptr;      // the constant matrices Yg_1, Yb_{K-1}
+    double *w = nullptr;           // row weights of a column sum
     double *part = nullptr;        // column-sum partials [chunk][j]
     double *den0 = nullptr;
     double *s_part = nullptr;      // phi-update partials
@@ -412,13 +436,20 @@ static void *Ymat(CircleState &C, int which_gamma, int k)
     return C.Yb[k];
 }
 
+static int32_t *Yscale(CircleState &C, int which_gamma, int k)  // dense path only
+{
+    if (which_gamma) return k == 1 ? C.szero : C.sg[k & 1];
+    return k == C.K - 1 ? C.szero : C.sb[k];
+}
+
 static hipError_t launch_gemm(const CircleState &C, const float *A, int lda, const double *phi,
                               const unsigned short *Bh, const unsigned short *Bl, int ldb, float *Cm,
-                              int ldc, int Mp, int Np, int Kp, hipStream_t s)
+                              int ldc, int Mp, int Np, int Kp, const int32_t *s_in, int32_t *s_out,
+                              hipStream_t s)
 {
     dim3 grid(Np / kBN, Mp / kBM);
+    hipLaunchKernelGGL(row_exp_kernel, dim3(Mp), dim3(256), 0, s, A, lda, Kp, phi, C.rexp, s_in, s_out);
     if (C.mode == 1) {
-        hipLaunchKernelGGL(row_exp_kernel, dim3(Mp), dim3(256), 0, s, A, lda, Kp, phi, C.rexp);
         hipLaunchKernelGGL(gemm_kernel<1>, grid, dim3(256), 0, s, A, lda, phi, Bh, Bl, ldb, Cm, ldc, Kp,
                            (const int32_t *)C.rexp);
     } else if (C.mode == 2) {
@@ -441,7 +472,8 @@ static int circle_product(mot_plan_s *P, CircleState &C, int gamma, int k)
         float *Cm = (float *)Ymat(C, gamma, k);
         const unsigned short *Bh = gamma ? C.Kg_h[k] : C.Kb_h[k];
         const unsigned short *Bl = gamma ? C.Kg_l[k] : C.Kb_l[k];
-        MOT_HIP(launch_gemm(C, A, C.ld[l], P->marg[l].phi, Bh, Bl, C.ld[l], Cm, C.ld[k], C.n1p, C.ld[k], C.ld[l], st));
+        MOT_HIP(launch_gemm(C, A, C.ld[l], P->marg[l].phi, Bh, Bl, C.ld[l], Cm, C.ld[k], C.n1p, C.ld[k], C.ld[l],
+                            Yscale(C, gamma, l), Yscale(C, gamma, k), st));
         return MOT_OK;
     }
     const double *A = (const double *)Ymat(C, gamma, l);
@@ -461,9 +493,13 @@ static int colsum_phi(mot_plan_s *P, CircleState &C, int k, bool marg_only)
     if (C.nfft)
         hipLaunchKernelGGL(colsum_kernel<double>, g, dim3(256), 0, st, (const double *)Yb, (const double *)Yg,
                            C.ld[k], n1, nk, (const double *)P->marg[0].phi, C.part);
-    else
+    else {
+        hipLaunchKernelGGL(row_weight_kernel, dim3((unsigned)((n1 + 255) / 256)), dim3(256), 0, st,
+                           (const double *)P->marg[0].phi, (const int32_t *)Yscale(C, 0, k),
+                           (const int32_t *)Yscale(C, 1, k), n1, C.w);
         hipLaunchKernelGGL(colsum_kernel<float>, g, dim3(256), 0, st, (const float *)Yb, (const float *)Yg,
-                           C.ld[k], n1, nk, (const double *)P->marg[0].phi, C.part);
+                           C.ld[k], n1, nk, (const double *)C.w, C.part);
+    }
     MOT_HIP(hipGetLastError());
     const unsigned blocks = (unsigned)((nk + 255) / 256);
     double *sout = marg_only ? C.m_part : C.s_part + 2 * C.s_slot[k];
@@ -479,11 +515,13 @@ static int rowsum_den0(mot_plan_s *P, CircleState &C)
     if (C.nfft)
         hipLaunchKernelGGL(rowsum_kernel<double>, dim3((unsigned)C.n1), dim3(256), 0, st,
                            (const double *)P->marg[0].pts, (const double *)P->marg[1].pts, (int64_t)P->n[1], P->d,
-                           P->eta, (const double *)P->marg[1].phi, (const double *)C.Yb[1], C.ld[1], C.den0);
+                           P->eta, (const double *)P->marg[1].phi, (const double *)C.Yb[1], C.ld[1],
+                           (const int32_t *)nullptr, C.den0);
     else
         hipLaunchKernelGGL(rowsum_kernel<float>, dim3((unsigned)C.n1), dim3(256), 0, st,
                            (const double *)P->marg[0].pts, (const double *)P->marg[1].pts, (int64_t)P->n[1], P->d,
-                           P->eta, (const double *)P->marg[1].phi, (const float *)C.Yb[1], C.ld[1], C.den0);
+                           P->eta, (const double *)P->marg[1].phi, (const float *)C.Yb[1], C.ld[1],
+                           (const int32_t *)Yscale(C, 0, 1), C.den0);
     return hipGetLastError() == hipSuccess ? MOT_OK : MOT_EDEVICE;
 }
 
@@ -589,6 +627,14 @@ int circle_create(mot_plan_s *P, const std::vector<double> &pts_h, const std::ve
         for (int k = 1; k <= K - 2; ++k) MOT_TRY(kmat16(P, C, k, k + 1, &C.Kb_h[k], &C.Kb_l[k]));
         for (int k = 2; k <= K - 1; ++k) MOT_TRY(kmat16(P, C, k, k - 1, &C.Kg_h[k], &C.Kg_l[k]));
         MOT_TRY(P->arena.get_n((size_t)C.n1p, &C.rexp));
+        C.K = K;
+        C.sb.assign(K, nullptr);
+        for (int k = 1; k < K - 1; ++k) MOT_TRY(P->arena.get_n((size_t)C.n1p, &C.sb[k]));
+        MOT_TRY(P->arena.get_n((size_t)C.n1p, &C.sg[0]));
+        MOT_TRY(P->arena.get_n((size_t)C.n1p, &C.sg[1]));
+        MOT_TRY(P->arena.get_n((size_t)C.n1p, &C.szero));
+        MOT_TRY(P->arena.get_n((size_t)C.n1p, &C.w));
+        MOT_HIP(launch_fill_int(C.szero, 0, C.n1p, st));
     }
     const int chunks = (int)((C.n1 + kColChunk - 1) / kColChunk);
     MOT_TRY(P->arena.get_n((size_t)chunks * nmax, &C.part));

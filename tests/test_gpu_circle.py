@@ -65,3 +65,27 @@ def test_circle_marginals(mot, cyc):
     oP = oracle.circle_marginals(inst.points, inst.eta, ophi)
     assert max_rel(P, oP) < 1e-4
     plan.close()
+
+
+@pytest.fixture(scope="module")
+def long_cycle():
+    """K = 16 with eta = 0.2: every product of the recursions grows the entries by about
+    n_k times the mean kernel value, so unscaled FP32 chains overflow after a few steps."""
+    inst = W.make_instance(rng(57), 16, 200, 2, W.CIRCLE, 0.2)
+    ophi, oS, _, _ = oracle.circle_sinkhorn(inst.points, inst.weights, inst.eta, 10)
+    return inst, ophi, oS
+
+
+@pytest.mark.parametrize("prec,bound", [("BF16X3", 1e-5), ("FP16", 5e-4), ("BF16", 5e-3)])
+def test_dense_long_cycle_stays_in_range(mot, long_cycle, prec, bound):
+    inst, ophi, oS = long_cycle
+    plan = mot.Plan(inst.points, inst.weights, W.CIRCLE, None, inst.eta, path=mot.DENSE,
+                    precision=getattr(mot, "PREC_" + prec))
+    rc, done, S_last, err = plan.sinkhorn(10)
+    assert rc >= 0 and done == 10
+    phi = plan.scalings()
+    assert all(np.all(np.isfinite(p)) for p in phi)
+    rel = max_rel(gauge_fix(phi, inst.weights), gauge_fix(ophi, inst.weights))
+    print("long cycle %s: gauge-fixed phi rel err %.3e" % (prec, rel))
+    assert rel < bound
+    plan.close()
