@@ -48,6 +48,17 @@ TRAFFIC = {
 }
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def source_sha(name):
     import hashlib
     path = os.path.join(ROOT, "paper_2208_03120_amd", "csrc", name)
@@ -218,7 +229,8 @@ def bench_serving(mot, W, count=300, rate=16.0, n_max=200000, circle_n_max=1500,
             break
     th.join()
     srv.close()
-    lat = np.array([r["t_done"] - r["t_submit"] for r in results.values()])
+    warm = count // 10  # the first tenth of the requests warms the server up
+    lat = np.array([r["t_done"] - r["t_submit"] for i, r in results.items() if i >= warm])
     ok = sum(1 for r in results.values() if r["status"] == mot.OK)
     maxit = sum(1 for r in results.values() if r["status"] == mot.MAXITER)
     span = max(r["t_done"] for r in results.values()) - min(r["t_submit"] for r in results.values())
@@ -234,6 +246,7 @@ def bench_serving(mot, W, count=300, rate=16.0, n_max=200000, circle_n_max=1500,
                         "N log-uniform [500,%d] (circle N <= %d), d in {2,3}, eta log-uniform "
                         "[0.01,0.3], tol 1e-6, at most %d sweeps" % (rate, count, n_max, circle_n_max,
                                                                      max_sweeps),
+            "rate_req_per_s": rate, "warmup_requests_excluded": warm,
             "completed": len(results), "converged": ok, "max_sweeps_reached": maxit,
             "failed": len(results) - ok - maxit, "failures": fails, "refused": refused,
             "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
@@ -269,6 +282,16 @@ def main():
     cal_dst = torch.empty_like(cal_src)
     cal_dst.copy_(cal_src)
     torch.cuda.synchronize()
+    # the same copy timed (HIP events, best of 5): the achievable HBM stream rate
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    copy_ms = []
+    for _ in range(5):
+        ev0.record()
+        cal_dst.copy_(cal_src)
+        ev1.record()
+        ev1.synchronize()
+        copy_ms.append(ev0.elapsed_time(ev1))
+    hbm_copy_gbs = 2.0 * (COPY_MIB << 20) / (min(copy_ms) * 1e-3) / 1e9
     del cal_src, cal_dst
 
     inst = W.star_nfft(seed=2, N=args.N)
@@ -384,7 +407,9 @@ def main():
         "roofline": roof,
         "kernel_ms_per_sweep": breakdown,
         "plan_seconds": t_plan,
+        "hbm_copy_GBps": hbm_copy_gbs,
         "cpu_baseline": {"value": cpu_sweeps, "unit": "sweeps/s", "cores": cores, "kind": "oracle",
+                         "cpu": cpu_model(),
                          "sample": "FP64 oracle direct product of %d of %d targets x %d sources "
                                    "(%.2f s), scaled to %d products per sweep"
                                    % (nt, inst.sizes[0], inst.sizes[1], dt, 2 * (K - 1))},
