@@ -121,6 +121,39 @@ def step_work(step, info, inst, n_jobs_level):
     return {"flops": 0.0, "bytes": 0.0}
 
 
+def bench_error_vs_M(mot, W, etas=(0.02, 0.05, 0.1, 0.2), Ms=(8, 12, 16, 24, 32, 48), samples=256):
+    """Error of one NFFT product against the FP64 direct sum as the half bandwidth M
+    grows (d = 2, two marginals of 2000 and 1800 uniform points, tau and eps_B and m
+    from the autotuner, grid n = the smallest power of two >= 4M): the measured maximum
+    relative error over sampled targets next to the autotuner's estimate."""
+    import oracle
+    rows = []
+    r = np.random.Generator(np.random.PCG64(8))
+    for eta in etas:
+        inst = W.make_instance(r, 2, [2000, 1800], 2, W.TREE, eta, parent=[-1, 0])
+        v = r.uniform(0.5, 1.5, 1800)
+        idx = r.choice(2000, samples, replace=False)
+        want = oracle.kernel_apply(inst.points[0][idx], inst.points[1], v, eta)
+        for M in Ms:
+            n = 16
+            while n < 4 * M:
+                n *= 2
+            fs = mot.fastsum_params(M=M, n=n, p=3)
+            try:
+                plan = mot.Plan(inst.points, inst.weights, W.TREE, inst.parent, eta, path=mot.NFFT,
+                                fastsum=fs)
+            except Exception as e:  # parameters outside the supported range
+                rows.append({"eta": eta, "M": M, "n": n, "error": repr(e)})
+                continue
+            info = plan.info()
+            got = plan.apply(0, 1, v)[idx]
+            plan.close()
+            rows.append({"eta": eta, "M": M, "n": n, "m": info["m"], "tau": round(info["tau"], 4),
+                         "eps_B": round(info["eps_B"], 4), "est_err": info["est_err"],
+                         "max_rel_err": float(np.max(np.abs(got - want) / want))})
+    return rows
+
+
 def bench_circle(mot, W, sweeps=20):
     """Cycle K=5, N=4000, d=2, eta=0.1: dense MFMA products in three precisions and the
     row-by-row NFFT products; errors of the gauge-fixed scaling vectors are stated
@@ -416,7 +449,8 @@ def main():
     }
     plan.close()
     if not args.no_extras:
-        for key, fn in [("circle", bench_circle), ("batched", bench_batched), ("serving", bench_serving)]:
+        for key, fn in [("circle", bench_circle), ("batched", bench_batched), ("serving", bench_serving),
+                        ("error_vs_M", bench_error_vs_M)]:
             try:
                 out[key] = fn(mot, W)
             except Exception as e:  # the headline measurement stands on its own

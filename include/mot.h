@@ -103,6 +103,10 @@ typedef struct {
     int32_t depth;       /* tree depth (levels below the root)                     */
     size_t device_bytes; /* device memory held by the plan                         */
     int32_t products_per_sweep;
+    double est_err;      /* autotuner's estimate of one product's relative error:
+                            Fourier truncation (d x the 1-D sup error of the
+                            truncated series of the regularised kernel) plus the
+                            Kaiser-Bessel window bound; 0 off the NFFT path      */
 } mot_plan_info;
 
 /* Create a plan: copy the problem to the device and precompute everything the

@@ -1055,6 +1055,7 @@ int mot_plan_get_info(mot_plan P, mot_plan_info *info)
     I.depth = P->depth_max;
     I.device_bytes = P->arena.bytes;
     I.products_per_sweep = P->topology == MOT_TREE ? 2 * (P->K - 1) : 2 * (P->K - 2);
+    I.est_err = P->path == MOT_NFFT ? P->P.est_err : 0.0;
     *info = I;
     return MOT_OK;
 }

@@ -46,7 +46,7 @@ class PlanInfo(ctypes.Structure):
                 ("scale", ctypes.c_double), ("offset", ctypes.c_double * 3),
                 ("box_lo", ctypes.c_int32 * 3), ("box_len", ctypes.c_int32 * 3),
                 ("depth", ctypes.c_int32), ("device_bytes", ctypes.c_size_t),
-                ("products_per_sweep", ctypes.c_int32)]
+                ("products_per_sweep", ctypes.c_int32), ("est_err", ctypes.c_double)]
 
 
 class Allocator(ctypes.Structure):

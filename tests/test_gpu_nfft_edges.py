@@ -146,3 +146,27 @@ def test_full_size_root_marginal_sampled(mot, full):
     for t in range(1, inst.K):
         want *= oracle.kernel_apply(inst.points[0][idx], inst.points[t], phi[t], inst.eta)
     assert float(np.max(np.abs(P[0][idx] - want) / want)) < 9 * 2e-6
+
+
+def test_error_vs_M_tracks_the_estimate(mot):
+    """One product's error against the direct sum falls as M grows until FP32 rounding
+    (a few 1e-7), and stays within a factor of the autotuner's estimate (d = 2)."""
+    inst = W.make_instance(rng(95), 2, [1200, 1000], 2, W.TREE, 0.05, parent=[-1, 0])
+    v = rng(96).uniform(0.5, 1.5, 1000)
+    want = oracle.kernel_apply(inst.points[0], inst.points[1], v, inst.eta)
+    errs, ests = [], []
+    for M in (6, 8, 12, 16, 24):
+        n = 16
+        while n < 4 * M:
+            n *= 2
+        plan = mot.Plan(inst.points, inst.weights, W.TREE, inst.parent, inst.eta, path=mot.NFFT,
+                        fastsum=mot.fastsum_params(M=M, n=n, p=3))
+        ests.append(plan.info()["est_err"])
+        errs.append(float(np.max(np.abs(plan.apply(0, 1, v) - want) / want)))
+        plan.close()
+    print("M errors", errs, "estimates", ests)
+    for a, b in zip(errs, errs[1:]):
+        assert b < a or b < 2e-6, errs
+    for e, est in zip(errs, ests):
+        assert e <= 10 * est + 2e-6, (errs, ests)
+    assert errs[-1] < 2e-6, errs
