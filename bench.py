@@ -154,6 +154,86 @@ def bench_error_vs_M(mot, W, etas=(0.02, 0.05, 0.1, 0.2), Ms=(8, 12, 16, 24, 32,
     return rows
 
 
+def trunc_pairs(info, x_t, x_s):
+    """Source-target pairs one truncated product evaluates: every target sums the sources
+    of the cells whose box distance to its own cell is at most r_c (cells of side
+    1 / scale from the grid origin, the plan's neighbour half-width)."""
+    from scipy import ndimage
+    d, nc, w = x_t.shape[1], info["n"], info["tile"]
+    sc = info["scale"]
+    q2 = (info["trunc_radius"] * sc) ** 2 * (1 + 1e-6)
+
+    def counts(x):
+        cell = np.clip(np.floor(x * sc + np.asarray(info["offset"][:d])), 0, nc - 1).astype(np.int64)
+        return np.bincount(np.ravel_multi_index(cell.T, (nc,) * d), minlength=nc ** d).reshape((nc,) * d)
+
+    grid = np.indices((2 * w + 1,) * d) - w
+    ex = np.maximum(np.abs(grid) - 1, 0)
+    mask = ((ex ** 2).sum(0) <= q2).astype(np.float64)
+    scanned = ndimage.convolve(counts(x_s).astype(np.float64), mask, mode="constant", cval=0.0)
+    return float(np.sum(counts(x_t) * scanned))
+
+
+def bench_truncated(mot, W, etas=(1e-3, 3e-4), N=100_000, sweeps=20, direct_sweeps=2, acc_sweeps=10):
+    """Small eta, star K=10, N=1e5 per marginal, d=3: the truncated direct path against
+    the full direct path and the autotuned NFFT path (which cannot represent the kernel
+    once eta is below its largest bandwidth).  Sweeps/s, gauge-fixed scaling error
+    against the direct path after the same sweeps from phi = 1, and the truncated
+    kernel's pair rate against the v_exp_f32 rate (16 per CU and clock)."""
+    import torch
+    res = []
+    for eta in etas:
+        inst = W.star_small_eta(seed=6, N=N, eta=eta)
+        row = {"workload": "star tree K=10, N=%d per marginal, d=3, eta=%g" % (N, eta)}
+        ones = [np.ones(n) for n in inst.sizes]
+        ref = None
+        for name, path, n_sw in [("direct", mot.DIRECT, direct_sweeps), ("trunc", mot.TRUNC, sweeps),
+                                 ("nfft", mot.NFFT, sweeps)]:
+            try:
+                plan = mot.Plan(inst.points, inst.weights, W.TREE, inst.parent, eta, path=path)
+            except Exception as e:
+                row[name] = {"error": repr(e)}
+                continue
+            plan.sinkhorn(1)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            plan.sinkhorn(n_sw)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / n_sw
+            entry = {"sweeps_per_s": 1.0 / dt, "ms_per_sweep": dt * 1e3}
+            info = plan.info()
+            if path == mot.TRUNC:
+                prof = plan.profile(3)
+                launches = [p for p in prof if p["kind"] == "trunc"]
+                ms = sum(p["ms"] for p in launches) / max(1, len(launches))
+                # one launch: the 9 products of one level (root -> leaves or leaves -> root)
+                pairs = 9 * trunc_pairs(info, inst.points[1], inst.points[0])
+                peak = 16 * 256 * 2.4e9
+                entry.update({"r_c": info["trunc_radius"], "cells_per_dim": info["n"],
+                              "neighbour_halfwidth": info["tile"],
+                              "pairs_per_launch": pairs,
+                              "pairs_frac_of_direct": pairs / (9.0 * N * N),
+                              "ms_per_launch": ms,
+                              "pairs_per_s": pairs / (ms * 1e-3),
+                              "exp_rate_frac": pairs / (ms * 1e-3) / peak})
+            if path == mot.NFFT:
+                entry.update({"M": info["M"], "n": info["n"], "m": info["m"], "est_err": info["est_err"]})
+            plan.set_scalings(ones)
+            plan.sinkhorn(acc_sweeps)
+            g = gauge_fix(plan.scalings(), inst.weights)
+            if ref is None:
+                ref = g
+            else:
+                entry["phi_rel_err_vs_direct"] = max(float(np.max(np.abs(a - b) / np.abs(b)))
+                                                     for a, b in zip(g, ref))
+            plan.close()
+            row[name] = entry
+        if "sweeps_per_s" in row.get("trunc", {}) and "sweeps_per_s" in row.get("direct", {}):
+            row["trunc_speedup_vs_direct"] = row["trunc"]["sweeps_per_s"] / row["direct"]["sweeps_per_s"]
+        res.append(row)
+    return res
+
+
 def bench_circle(mot, W, sweeps=20):
     """Cycle K=5, N=4000, d=2, eta=0.1: dense MFMA products in three precisions and the
     row-by-row NFFT products; errors of the gauge-fixed scaling vectors are stated
@@ -450,7 +530,7 @@ def main():
     plan.close()
     if not args.no_extras:
         for key, fn in [("circle", bench_circle), ("batched", bench_batched), ("serving", bench_serving),
-                        ("error_vs_M", bench_error_vs_M)]:
+                        ("error_vs_M", bench_error_vs_M), ("truncated", bench_truncated)]:
             try:
                 out[key] = fn(mot, W)
             except Exception as e:  # the headline measurement stands on its own

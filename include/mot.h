@@ -49,9 +49,21 @@ extern "C" {
 #define MOT_DIRECT 0       /* kernel products by direct O(N^2) summation, eq. (fastsum-sum) */
 #define MOT_NFFT 1         /* kernel products by NFFT fast summation, Algorithm 4         */
 #define MOT_DENSE 2        /* circle only: dense matrix products on MFMA                  */
+#define MOT_TRUNC 3        /* tree only: direct summation truncated to the sources within
+                              the kernel's cutoff radius r_c of each target, for small eta
+                              (the truncation the paper suggests at the end of Sec. 6.1).
+                              r_c = sqrt(eta ln(1 / eps_t)): dropped terms are below
+                              eps_t v_j each.  eps_t is set from fs->target_rel_err (default
+                              1e-7) times the fraction (pi eta)^(d/2) / (2^d V) of the
+                              sources a corner target of a uniform cloud of bounding-box
+                              volume V sees, so the relative error of such a cloud's
+                              products stays near the target.  Sources are found through
+                              a cell list: the a1 binning with cubic cells of side h and
+                              tile edge 1, cells within r_c of the target's cell summed. */
 
-#define MOT_PREC_FP64 0    /* direct path: FP64 exp and accumulation                      */
-#define MOT_PREC_MIXED 1   /* direct path: FP32 exp, FP32 tile sums, FP64 across tiles;
+#define MOT_PREC_FP64 0    /* direct and truncated paths: FP64 exp and accumulation       */
+#define MOT_PREC_MIXED 1   /* direct and truncated paths: FP32 exp, FP32 sums over 64
+                              sources, FP64 across them;
                               NFFT path: FP32 spread/FFT/interpolation                    */
 #define MOT_PREC_BF16 2    /* dense circle: BF16 operands, FP32 accumulation              */
 #define MOT_PREC_FP16 3    /* dense circle: FP16 operands (power-of-two scaled), FP32 acc. */
@@ -106,7 +118,13 @@ typedef struct {
     double est_err;      /* autotuner's estimate of one product's relative error:
                             Fourier truncation (d x the 1-D sup error of the
                             truncated series of the regularised kernel) plus the
-                            Kaiser-Bessel window bound; 0 off the NFFT path      */
+                            Kaiser-Bessel window bound (NFFT path); the target the
+                            cutoff was set for (truncated path); 0 otherwise     */
+    double trunc_radius; /* truncated path: cutoff radius r_c (0 otherwise); the
+                            cell side is 1 / scale, the cells per dimension n,
+                            the neighbour half-width in cells tile, and at the
+                            mean density the cells per work item chunk and the
+                            targets per lane m                                  */
 } mot_plan_info;
 
 /* Create a plan: copy the problem to the device and precompute everything the
@@ -120,8 +138,8 @@ typedef struct {
  *   parent   tree only: [K] host ints, parent[0] = -1, 0 <= parent[k] < k; NULL
  *            for a circle (edges {k, k+1 mod K}, K >= 3)
  *   eta      > 0
- *   path     MOT_DIRECT, MOT_NFFT or (circle) MOT_DENSE
- *   precision see MOT_PREC_*; MOT_PREC_FP64 only with MOT_DIRECT
+ *   path     MOT_DIRECT, MOT_NFFT, (tree) MOT_TRUNC or (circle) MOT_DENSE
+ *   precision see MOT_PREC_*; MOT_PREC_FP64 only with MOT_DIRECT and MOT_TRUNC
  *   fs       fast-summation parameters (NFFT path); NULL = all autotuned
  *   stream   hipStream_t to enqueue on; NULL = a stream the plan creates
  * Scaling vectors start at phi^(0) = 1.  On failure *out is NULL.           */
@@ -186,8 +204,8 @@ const char *mot_strerror(int status);
 /* Per-step device timing of the plan's sweep (tree plans): runs `sweeps` sweeps with a
  * HIP event pair around every launch of the sweep schedule on the plan's stream and
  * reports, per schedule position, the kernel kind and the mean duration.  kind:
- * 0 node update, 1 direct product, 2 spread, 3 fold, 4 FFT pass (fft_kind 0..4),
- * 5 interpolation, 6 sweep finalisation.  Returns the number of entries written
+ * 0 node update, 1 direct product, 2 spread, 3 fold, 4 FFT pass (fft_kind 0..7),
+ * 5 interpolation, 6 sweep finalisation, 7 fill, 8 truncated product.  Returns the number of entries written
  * (<= max_out) or an error.  The sweeps advance the plan like mot_sinkhorn. */
 typedef struct {
     int32_t kind, d, n, fft_kind, n_items, calls;
@@ -214,7 +232,7 @@ int mot_bin_points(int32_t d, int64_t npts, const double *x, const double *s, co
  * every plan's sweep is executed by shared launches (all edges at a tree depth
  * across all plans in one set of kernels), and the whole batched sweep is
  * captured once as a HIP graph and replayed.  All plans must share one stream
- * and use the NFFT or direct path.  Equivalent, plan by plan, to mot_sinkhorn
+ * and use the NFFT, direct or truncated path.  Equivalent, plan by plan, to mot_sinkhorn
  * with the same sweep count and no stopping tests. */
 typedef struct mot_batch_s *mot_batch;
 int mot_batch_create(mot_batch *out, mot_plan *plans, int32_t count);

@@ -15,6 +15,8 @@ Contents
     (eq. fastsum1) evaluated directly, without any NFFT.
   * ``brute.py``: full-tensor brute force for tiny K and n (Sec. 3,
     Algorithm 1, Theorem 3.1).
+  * ``kernel_apply_truncated`` (here, numpy): the direct sum restricted to the pairs
+    within a cutoff radius (the truncation for small eta, end of Sec. 6.1).
 
 Marginals are 0-based here: the paper's root / first marginal is index 0.
 """
@@ -115,6 +117,26 @@ def kernel_apply(xt, xs, v, eta):
     out = np.empty(xt.shape[0], dtype=np.float64)
     lib.orc_kernel_apply(d, xt.shape[0], _d(xt), xs.shape[0], _d(xs), _d(v), float(eta),
                          _d(out))
+    return out
+
+
+def kernel_apply_truncated(xt, xs, v, eta, r_c):
+    """out_i = sum over j with |xt_i - xs_j| <= r_c of v_j exp(-|xt_i - xs_j|^2 / eta):
+    the direct sum of eq. fastsum-sum with every term beyond the cutoff radius dropped,
+    the simple truncation the end of Sec. 6.1 suggests for small eta.  Targets in
+    blocks of 32, sources in their given order."""
+    xt = np.asarray(xt, dtype=np.float64)
+    xs = np.asarray(xs, dtype=np.float64)
+    v = np.asarray(v, dtype=np.float64)
+    d = xt.shape[1]
+    out = np.empty(xt.shape[0])
+    for i0 in range(0, xt.shape[0], 32):
+        i1 = min(i0 + 32, xt.shape[0])
+        d2 = np.zeros((i1 - i0, xs.shape[0]))
+        for c in range(d):
+            d2 += (xt[i0:i1, c, None] - xs[None, :, c]) ** 2
+        terms = np.where(d2 <= r_c * r_c, np.exp(-d2 / eta), 0.0)
+        out[i0:i1] = terms @ v
     return out
 
 

@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmot.so")
-SOURCES = ["k_nfft.hip", "k_fft.hip", "k_direct.hip", "k_node.hip", "circle.hip",
+SOURCES = ["k_nfft.hip", "k_fft.hip", "k_direct.hip", "k_trunc.hip", "k_node.hip", "circle.hip",
            "params.cpp", "plan.cpp", "batch.cpp", "server.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",

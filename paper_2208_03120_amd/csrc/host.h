@@ -60,6 +60,18 @@ struct NfftParams {
     double est_err = 0;   // autotuner's error estimate for one product (relative)
 };
 
+// Cell list of the truncated path.
+struct TruncParams {
+    double eps = 0;        // kernel values below eps are dropped
+    double rc = 0;         // cutoff radius sqrt(eta ln(1 / eps))
+    double h = 0;          // cell side
+    double q2 = 0;         // (rc / h)^2 (1 + 1e-6)
+    double glo[3] = {0, 0, 0};  // grid origin (lower corner of the bounding box)
+    int nc = 1, w = 1;     // cells per dimension; neighbour half-width in cells
+    int B = 1, R = 1;      // cells per run and targets per lane at the mean density
+    double est_err = 0;    // relative error the cutoff was set for
+};
+
 // Bounding box of all points.
 struct Extent {
     double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0}, ctr[3] = {0, 0, 0};
@@ -70,6 +82,15 @@ struct Extent {
 int resolve_params(int d, double eta, const Extent &ext, const mot_fastsum_params *fs,
                    int64_t n_max, NfftParams *out);
 int build_box(int d, const Extent &ext, NfftParams *P);
+int resolve_trunc(int d, double eta, const Extent &ext, const mot_fastsum_params *fs,
+                  double n_mean, TruncParams *out);
+int64_t trunc_cells(int d, const TruncParams &T);  // nc^d
+// host mirror of the kernel's neighbour rows of a run of B cells starting at cc
+int trunc_row_range(int d, const TruncParams &T, const int cc[3], int B, int ri, int64_t *row_base,
+                    int *xa, int *xb);
+double trunc_cost(int d, const TruncParams &T, double tpc, double spc, double occ, int B, int R);
+void trunc_choose_run(int d, const TruncParams &T, double tpc, double spc, double occ, int max_r, int *B,
+                      int *R);
 void kappa_B_shifted(double eta, double tau, double eps_B, int p, std::vector<double> &q);
 double kappa_R(double r, double eta, double tau, double eps_B, const std::vector<double> &q);
 void kappa_hat_even(int d, int M, double eta, double tau, double eps_B, int p,
@@ -81,11 +102,12 @@ double kb_fourier(double k, const NfftParams &P);  // normalised window transfor
 // ---------------------------------------------------------------------------------------
 // A launch step of a sweep schedule.  Steps reference device job and item arrays owned
 // by the schedule.
-enum StepKind { ST_NODE, ST_DIRECT, ST_SPREAD, ST_FOLD, ST_FFT, ST_INTERP, ST_FINAL, ST_FILL_INT };
+enum StepKind { ST_NODE, ST_DIRECT, ST_SPREAD, ST_FOLD, ST_FFT, ST_INTERP, ST_FINAL, ST_FILL_INT,
+                ST_TRUNC };
 
 struct Step {
     StepKind kind;
-    int d = 0, n = 0, fft_kind = 0, precision = 0, max_patch = 0;
+    int d = 0, n = 0, fft_kind = 0, precision = 0, max_patch = 0, trunc_r = 0, diff = 0;
     const void *jobs = nullptr;   // device ProdJob / NodeJob / FinalJob array
     const void *items = nullptr;  // device int2 / int4 array
     int n_items = 0;
@@ -111,6 +133,9 @@ struct MargDev {
     int nchunks = 0;
     std::vector<int32_t> h_chunk_tile;
     std::vector<int32_t> h_chunk_start;  // chunk bounds, nchunks + 1 entries
+    // truncated path: sorted point range of each cell
+    int32_t *cell_off = nullptr;
+    std::vector<int32_t> h_cell_off;
 };
 
 struct Schedule {
@@ -138,6 +163,7 @@ struct mot_plan_s {
     int depth_max = 0;
     mot::Extent ext;
     mot::NfftParams P;
+    mot::TruncParams TP;
     std::vector<mot::MargDev> marg;
     // product jobs: index 2k = down job of k (gamma_k), 2k+1 = up job of k (beta_k); slot
     // 2K is the stand-alone product used by mot_apply_kernel

@@ -8,10 +8,17 @@
 // c = log2(e) / eta and coordinates taken relative to the point cloud's centre,
 //   exp(-|x - y|^2 / eta) = exp2(a_x + a_y + x'.y'),  a_x = -c|x|^2, a_y = -c|y|^2,
 //   y' = 2 c y,
-// so each pair costs d FMAs, one add, one v_exp_f32 and one FMA.  Source values are
-// scaled by 2^-e (e = exponent of max v) so FP32 never under- or overflows; partial sums
-// over 64 sources are added into FP64 accumulators.  Each thread owns R targets to reuse
-// every LDS read R times.  This kernel is bound by the transcendental rate.
+// so each pair costs d FMAs, one add, one v_exp_f32 and one FMA.  The exponent is a sum
+// of terms up to c r^2 (r the cloud's radius) that cancel to -c|x - y|^2, so its FP32
+// rounding error grows like 6e-8 c r^2; when c r^2 exceeds 8 (small eta) the kernel
+// forms the same exponent in FP64 (gfx950 issues FP64 adds and FMAs at the unpacked FP32
+// rate) and rounds only the result to FP32 for v_exp_f32: one conversion more per pair,
+// and the error is the rounding of the exponent itself.  Source values are scaled by
+// 2^-e (e = exponent of max v) so FP32 never under- or overflows; partial sums over 64
+// sources are added into FP64 accumulators.  Each thread owns R targets to reuse every
+// LDS read R times.  This kernel is bound by the transcendental and vector issue rates.
+#include <type_traits>
+
 #include "mot_internal.h"
 
 namespace mot {
@@ -58,11 +65,24 @@ __global__ __launch_bounds__(256) void direct_fp64_kernel(const ProdJob *__restr
 
 constexpr int kDirectR = 4;
 
-template <int D>
+// Source staging of the mixed kernel: FP32 (2 c y, -c|y|^2) or the same in FP64.
+template <bool WIDE>
+struct DirectSrc;
+template <>
+struct DirectSrc<false> {
+    float4 y;
+};
+template <>
+struct DirectSrc<true> {
+    double y[4];
+};
+
+template <int D, bool WIDE>
 __global__ __launch_bounds__(256) void direct_mixed_kernel(const ProdJob *__restrict__ jobs,
                                                            const int4 *__restrict__ items, int n_items)
 {
-    __shared__ float4 sy[256];
+    typedef typename std::conditional<WIDE, double, float>::type real;
+    __shared__ DirectSrc<WIDE> sy[256];
     __shared__ float sv[256];
     const int tid = threadIdx.x;
     for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
@@ -71,7 +91,7 @@ __global__ __launch_bounds__(256) void direct_mixed_kernel(const ProdJob *__rest
         const double c2 = 1.4426950408889634 / J.eta;  // log2(e) / eta
         int e = *J.v_exp;
         if (e == INT32_MIN) e = 0;
-        float xs[kDirectR][3], ax[kDirectR];
+        real xs[kDirectR][3], ax[kDirectR];
         double acc[kDirectR];
 #pragma unroll
         for (int r = 0; r < kDirectR; ++r) {
@@ -81,10 +101,10 @@ __global__ __launch_bounds__(256) void direct_mixed_kernel(const ProdJob *__rest
             for (int c = 0; c < 3; ++c) {
                 double dx = 0.0;
                 if (c < D && i < J.nt) dx = J.tgt_pts[i * D + c] - J.ctr[c];
-                xs[r][c] = (float)dx;
+                xs[r][c] = (real)dx;
                 nrm += dx * dx;
             }
-            ax[r] = (float)(-c2 * nrm);
+            ax[r] = (real)(-c2 * nrm);
             acc[r] = 0.0;
         }
         for (int64_t j0 = 0; j0 < J.ns; j0 += 256) {
@@ -97,8 +117,15 @@ __global__ __launch_bounds__(256) void direct_mixed_kernel(const ProdJob *__rest
                     dy[c] = J.src_pts[(j0 + tid) * D + c] - J.ctr[c];
                     nrm += dy[c] * dy[c];
                 }
-                sy[tid] = make_float4((float)(2.0 * c2 * dy[0]), (float)(2.0 * c2 * dy[1]),
-                                      (float)(2.0 * c2 * dy[2]), (float)(-c2 * nrm));
+                if constexpr (WIDE) {
+                    sy[tid].y[0] = 2.0 * c2 * dy[0];
+                    sy[tid].y[1] = 2.0 * c2 * dy[1];
+                    sy[tid].y[2] = 2.0 * c2 * dy[2];
+                    sy[tid].y[3] = -c2 * nrm;
+                } else {
+                    sy[tid].y = make_float4((float)(2.0 * c2 * dy[0]), (float)(2.0 * c2 * dy[1]),
+                                            (float)(2.0 * c2 * dy[2]), (float)(-c2 * nrm));
+                }
                 sv[tid] = (float)ldexp(J.v[j0 + tid], -e);
             }
             __syncthreads();
@@ -108,15 +135,25 @@ __global__ __launch_bounds__(256) void direct_mixed_kernel(const ProdJob *__rest
 #pragma unroll
                 for (int r = 0; r < kDirectR; ++r) part[r] = 0.0f;
                 for (int jj = jb; jj < je; ++jj) {
-                    const float4 s = sy[jj];
+                    real s[4];
+                    if constexpr (WIDE) {
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) s[q] = sy[jj].y[q];
+                    } else {
+                        const float4 f = sy[jj].y;
+                        s[0] = f.x;
+                        s[1] = f.y;
+                        s[2] = f.z;
+                        s[3] = f.w;
+                    }
                     const float w = sv[jj];
 #pragma unroll
                     for (int r = 0; r < kDirectR; ++r) {
-                        float arg = ax[r] + s.w;
-                        arg = fmaf(xs[r][0], s.x, arg);
-                        if (D > 1) arg = fmaf(xs[r][1], s.y, arg);
-                        if (D > 2) arg = fmaf(xs[r][2], s.z, arg);
-                        part[r] = fmaf(w, __builtin_amdgcn_exp2f(arg), part[r]);
+                        real arg = ax[r] + s[3];
+                        arg = fma(xs[r][0], s[0], arg);
+                        if (D > 1) arg = fma(xs[r][1], s[1], arg);
+                        if (D > 2) arg = fma(xs[r][2], s[2], arg);
+                        part[r] = fmaf(w, __builtin_amdgcn_exp2f((float)arg), part[r]);
                     }
                 }
 #pragma unroll
@@ -134,7 +171,7 @@ __global__ __launch_bounds__(256) void direct_mixed_kernel(const ProdJob *__rest
 int direct_targets_per_item(int precision) { return precision == MOT_PREC_FP64 ? 256 : 256 * kDirectR; }
 
 hipError_t launch_direct(int d, const ProdJob *jobs_dev, const int4 *items, int n_items,
-                         int precision, hipStream_t s)
+                         int precision, int diff, hipStream_t s)
 {
     if (n_items == 0) return hipSuccess;
     const int grid = n_items < 16384 ? n_items : 16384;
@@ -142,10 +179,14 @@ hipError_t launch_direct(int d, const ProdJob *jobs_dev, const int4 *items, int 
         if (d == 1) hipLaunchKernelGGL(direct_fp64_kernel<1>, dim3(grid), dim3(256), 0, s, jobs_dev, items, n_items);
         if (d == 2) hipLaunchKernelGGL(direct_fp64_kernel<2>, dim3(grid), dim3(256), 0, s, jobs_dev, items, n_items);
         if (d == 3) hipLaunchKernelGGL(direct_fp64_kernel<3>, dim3(grid), dim3(256), 0, s, jobs_dev, items, n_items);
+    } else if (diff) {
+        if (d == 1) hipLaunchKernelGGL((direct_mixed_kernel<1, true>), dim3(grid), dim3(256), 0, s, jobs_dev, items, n_items);
+        if (d == 2) hipLaunchKernelGGL((direct_mixed_kernel<2, true>), dim3(grid), dim3(256), 0, s, jobs_dev, items, n_items);
+        if (d == 3) hipLaunchKernelGGL((direct_mixed_kernel<3, true>), dim3(grid), dim3(256), 0, s, jobs_dev, items, n_items);
     } else {
-        if (d == 1) hipLaunchKernelGGL(direct_mixed_kernel<1>, dim3(grid), dim3(256), 0, s, jobs_dev, items, n_items);
-        if (d == 2) hipLaunchKernelGGL(direct_mixed_kernel<2>, dim3(grid), dim3(256), 0, s, jobs_dev, items, n_items);
-        if (d == 3) hipLaunchKernelGGL(direct_mixed_kernel<3>, dim3(grid), dim3(256), 0, s, jobs_dev, items, n_items);
+        if (d == 1) hipLaunchKernelGGL((direct_mixed_kernel<1, false>), dim3(grid), dim3(256), 0, s, jobs_dev, items, n_items);
+        if (d == 2) hipLaunchKernelGGL((direct_mixed_kernel<2, false>), dim3(grid), dim3(256), 0, s, jobs_dev, items, n_items);
+        if (d == 3) hipLaunchKernelGGL((direct_mixed_kernel<3, false>), dim3(grid), dim3(256), 0, s, jobs_dev, items, n_items);
     }
     return hipGetLastError();
 }

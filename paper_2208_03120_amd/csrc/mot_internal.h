@@ -55,7 +55,8 @@ __device__ __forceinline__ void st2(float2 *p, int64_t i, float2 v)  // global s
 // or by NFFT fast summation (Algorithm 4).  Vectors are FP64 in the marginals' binned
 // (sorted) point order.
 struct ProdJob {
-    int32_t d, path, precision, pad0;
+    int32_t d, path, precision;
+    int32_t diff;      // direct mixed path: exponent formed in FP64 (small eta)
     // vectors
     const double *v;   // source vector, n_s entries
     int32_t *v_exp;    // slot holding max_j exponent(|v_j|) (atomicMax), reset per sweep
@@ -87,6 +88,14 @@ struct ProdJob {
     float *grid;       // L0*L1*L2 real (box grid, coordinate 0 slowest)
     float2 *spec0, *spec1;
     int64_t spec_elems;
+    // truncated path: cubic cells of side h from the origin glo, nc per dimension,
+    // linearised row-major (coordinate 0 slowest); points are sorted by cell
+    const int32_t *src_cell_off;            // [nc^d + 1] sorted source range of each cell
+    const int32_t *h_src_cell_off, *h_tgt_cell_off;  // host copies (launch items only)
+    int32_t nc, tw;    // cells per dimension; neighbour half-width in cells
+    int32_t trunc_r, trunc_b;  // targets per lane and cells per run of the launch items
+    double h, q2;      // cell side; (r_c / h)^2 enlarged by 1e-6 for cell rounding
+    double glo[3];
 };
 
 // Node update descriptors for the tree sweep (Algorithm 2), FP64.
@@ -132,8 +141,13 @@ struct FinalJob {
 // ---------------------------------------------------------------------------------------
 // Kernel launchers (implemented in the .hip files).
 int direct_targets_per_item(int precision);
+// Truncated products: items int4 (job, first cell of a run of B cells of one row, first
+// sorted target, count | B << 16), count <= 64 * R; R = 1, 2 or 4 (FP64: 1 or 2).
+hipError_t launch_trunc(int d, int precision, int R, const ProdJob *jobs_dev, const int4 *items,
+                        int n_items, hipStream_t s);
+// diff != 0: mixed-precision pairs with the exponent formed in FP64 (small eta)
 hipError_t launch_direct(int d, const ProdJob *jobs_dev, const int4 *items, int n_items,
-                         int precision, hipStream_t s);
+                         int precision, int diff, hipStream_t s);
 hipError_t launch_node(const NodeJob *jobs_dev, const int2 *items, int n_items, hipStream_t s);
 hipError_t launch_finalize(const FinalJob *jobs, const int2 *items, int n_items, hipStream_t s);
 hipError_t launch_fill_int(int32_t *p, int32_t value, int64_t count, hipStream_t s);

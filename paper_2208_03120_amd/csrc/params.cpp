@@ -367,4 +367,131 @@ int resolve_params(int d, double eta, const Extent &ext, const mot_fastsum_param
     return MOT_OK;
 }
 
+// ---------------------------------------------------------------------------------------
+// Truncated path.  Dropping the source terms with exp(-r^2 / eta) < eps changes a product
+// by at most eps sum_j v_j.  For a uniform cloud of bounding-box volume V, a target at a
+// corner of the box sums about (pi eta)^(d/2) / (2^d V) of the total source weight, so
+// eps = target (pi eta)^(d/2) / (2^d V) keeps the relative error of such products near
+// the target.  The cell side h = r_c / q is chosen by a cost model of the kernel: one
+// wavefront per item of at most 64 R targets from a run of B consecutive cells of a row,
+// scanning the rows of cells whose box distance to the run is at most r_c.
+int64_t trunc_cells(int d, const TruncParams &T)
+{
+    int64_t c = 1;
+    for (int k = 0; k < d; ++k) c *= T.nc;
+    return c;
+}
+
+int trunc_row_range(int d, const TruncParams &T, const int cc[3], int B, int ri, int64_t *row_base,
+                    int *xa, int *xb)
+{
+    const int w = T.w, span = 2 * w + 1;
+    int del[2] = {0, 0};
+    if (d == 3) {
+        del[0] = ri / span - w;
+        del[1] = ri % span - w;
+    } else if (d == 2) {
+        del[0] = ri - w;
+    }
+    double used = 0.0;
+    int64_t base = 0;
+    for (int c = 0; c < d - 1; ++c) {
+        const int x = cc[c] + del[c];
+        if (x < 0 || x >= T.nc) return 0;
+        const int e = std::abs(del[c]) - 1;
+        if (e > 0) used += (double)e * e;
+        base = base * T.nc + x;
+    }
+    const double rem = T.q2 - used;
+    if (rem < 0.0) return 0;
+    const int wl = std::min(w, 1 + (int)std::floor(std::sqrt(rem)));
+    *row_base = base * T.nc;
+    *xa = std::max(cc[d - 1] - wl, 0);
+    *xb = std::min(cc[d - 1] + B - 1 + wl, T.nc - 1);
+    return 1;
+}
+
+// Modelled wave cycles of one product: per row ~100, per 64-source stage ~200, per source
+// and target slot ~40.  tpc / spc: targets / sources per occupied cell; occ: occupied
+// target cells.
+double trunc_cost(int d, const TruncParams &T, double tpc, double spc, double occ, int B, int R)
+{
+    const int span = 2 * T.w + 1;
+    const int rows_total = d == 1 ? 1 : (d == 2 ? span : span * span);
+    TruncParams U = T;
+    U.nc = 1 << 20;  // no clipping at the grid edge
+    const int cc[3] = {1 << 19, 1 << 19, 1 << 19};
+    double cells = 0.0, rows = 0.0;
+    for (int ri = 0; ri < rows_total; ++ri) {
+        int64_t base;
+        int xa, xb;
+        if (!trunc_row_range(d, U, cc, B, ri, &base, &xa, &xb)) continue;
+        rows += 1.0;
+        cells += xb - xa + 1;
+    }
+    const double runs = std::max(1.0, occ / B);
+    const double items = runs * std::max(1.0, std::ceil(tpc * B / (64.0 * R)));
+    const double src = cells * spc;
+    return items * (rows * 100.0 + (src / 64.0 + rows) * 200.0 + src * R * 40.0);
+}
+
+void trunc_choose_run(int d, const TruncParams &T, double tpc, double spc, double occ, int max_r, int *B,
+                      int *R)
+{
+    double best = -1.0;
+    *B = 1;
+    *R = 1;
+    for (int b : {1, 2, 3, 4, 6, 8, 12, 16}) {
+        if (b > T.nc) break;
+        for (int r : {1, 2, 4}) {
+            if (r > max_r) break;
+            const double c = trunc_cost(d, T, tpc, spc, occ, b, r);
+            if (best < 0 || c < best) {
+                best = c;
+                *B = b;
+                *R = r;
+            }
+        }
+    }
+}
+
+int resolve_trunc(int d, double eta, const Extent &ext, const mot_fastsum_params *fs, double n_mean,
+                  TruncParams *out)
+{
+    const double target = fs && fs->target_rel_err > 0 ? fs->target_rel_err : 1e-7;
+    if (!(target < 1.0)) return MOT_EINVAL;
+    const double g0 = std::sqrt(M_PI * eta);
+    double V = 1.0;
+    for (int c = 0; c < d; ++c) V *= std::max(ext.hi[c] - ext.lo[c], g0);
+    const double frac = std::pow(M_PI * eta, 0.5 * d) / (std::pow(2.0, d) * V);
+    TruncParams T;
+    T.eps = target * std::min(1.0, frac);
+    T.rc = std::sqrt(eta * std::log(1.0 / T.eps));
+    T.est_err = target;
+    for (int c = 0; c < 3; ++c) T.glo[c] = c < d ? ext.lo[c] : 0.0;
+    const int nc_max = d == 1 ? (1 << 20) : (d == 2 ? 2048 : 128);
+    double best = -1.0;
+    for (double q : {0.5, 0.75, 1.0, 1.5, 2.0, 3.0, 4.0, 6.0, 8.0}) {
+        TruncParams C = T;
+        C.h = T.rc / q;
+        const double ncd = std::floor(ext.width_max / C.h) + 1.0;
+        if (ncd > nc_max) continue;
+        C.nc = (int)ncd;
+        C.q2 = q * q * (1.0 + 1e-6);
+        C.w = 1 + (int)std::floor(std::sqrt(C.q2));
+        double occupied = 1.0;
+        for (int c = 0; c < d; ++c) occupied *= std::ceil(std::max(ext.hi[c] - ext.lo[c], 1e-300) / C.h);
+        occupied = std::min(occupied, std::max(n_mean, 1.0));
+        const double pc = std::max(n_mean, 1.0) / occupied;  // points per occupied cell
+        trunc_choose_run(d, C, pc, pc, occupied, 4, &C.B, &C.R);
+        const double cost = trunc_cost(d, C, pc, pc, occupied, C.B, C.R);
+        if (best < 0 || cost < best) {
+            best = cost;
+            *out = C;
+        }
+    }
+    if (best < 0) return MOT_EDOMAIN;
+    return MOT_OK;
+}
+
 }  // namespace mot

@@ -19,6 +19,7 @@
 #include <cstdlib>
 #include <map>
 #include <mutex>
+#include <tuple>
 
 #include "host.h"
 
@@ -126,7 +127,7 @@ int run_steps(const std::vector<Step> &steps, hipStream_t s)
             break;
         case ST_DIRECT:
             MOT_HIP(launch_direct(st.d, (const ProdJob *)st.jobs, (const int4 *)st.items, st.n_items,
-                                  st.precision, s));
+                                  st.precision, st.diff, s));
             break;
         case ST_SPREAD:
             MOT_HIP(launch_spread(st.d, (const ProdJob *)st.jobs, (const int2 *)st.items, st.n_items,
@@ -148,6 +149,10 @@ int run_steps(const std::vector<Step> &steps, hipStream_t s)
             break;
         case ST_FILL_INT:
             MOT_HIP(launch_fill_int(st.fill_ptr, st.fill_value, st.fill_count, s));
+            break;
+        case ST_TRUNC:
+            MOT_HIP(launch_trunc(st.d, st.precision, st.trunc_r, (const ProdJob *)st.jobs,
+                                 (const int4 *)st.items, st.n_items, s));
             break;
         }
     }
@@ -221,7 +226,8 @@ struct StepBuilder {
     void products(const ProdJob *jobs_dev, const std::vector<ProdJob> &host_jobs,
                   const std::vector<int> &ids)
     {
-        std::map<std::pair<int, int>, std::vector<int4>> direct;  // (d, precision)
+        std::map<std::tuple<int, int, int>, std::vector<int4>> direct;  // (d, precision, diff)
+        std::map<std::tuple<int, int, int>, std::vector<std::pair<double, int4>>> trunc;  // (d, prec, R)
         std::map<int, std::vector<int2>> spread, fold, interp;   // d
         std::map<int, std::vector<int32_t>> spread_pts, interp_pts;  // points of each item
         std::map<std::pair<int, int>, std::vector<int4>> fft[8]; // (d, n) per pass kind
@@ -230,8 +236,45 @@ struct StepBuilder {
             const ProdJob &J = host_jobs[j];
             if (J.path == MOT_DIRECT) {
                 const int tpi = direct_targets_per_item(J.precision);
-                auto &v = direct[{J.d, J.precision}];
+                auto &v = direct[std::make_tuple(J.d, J.precision, J.diff)];
                 for (int64_t t = 0; t < J.nt; t += tpi) v.push_back(make_int4(j, (int)t, 0, 0));
+                continue;
+            }
+            if (J.path == MOT_TRUNC) {
+                // items of at most 64 R targets from a run of B consecutive cells of one
+                // row (contiguous in the sorted order), costed by the sources they scan
+                auto &v = trunc[std::make_tuple(J.d, J.precision, J.trunc_r)];
+                TruncParams TQ;
+                TQ.nc = J.nc;
+                TQ.w = J.tw;
+                TQ.q2 = J.q2;
+                int64_t nrow_cells = 1;
+                for (int c = 0; c < J.d - 1; ++c) nrow_cells *= J.nc;
+                const int cap = 64 * J.trunc_r;
+                const int span = 2 * J.tw + 1;
+                const int nrows = J.d == 1 ? 1 : (J.d == 2 ? span : span * span);
+                for (int64_t row = 0; row < nrow_cells; ++row)
+                    for (int x0 = 0; x0 < J.nc; x0 += J.trunc_b) {
+                        const int B = std::min(J.trunc_b, J.nc - x0);
+                        const int64_t cell = row * J.nc + x0;
+                        const int a = J.h_tgt_cell_off[cell], b = J.h_tgt_cell_off[cell + B];
+                        if (b <= a) continue;
+                        int cc[3] = {0, 0, 0};
+                        int64_t rem = cell;
+                        for (int c = J.d - 1; c >= 0; --c) {
+                            cc[c] = (int)(rem % J.nc);
+                            rem /= J.nc;
+                        }
+                        double srcs = 0.0;
+                        for (int ri = 0; ri < nrows; ++ri) {
+                            int64_t base;
+                            int xa, xb;
+                            if (!trunc_row_range(J.d, TQ, cc, B, ri, &base, &xa, &xb)) continue;
+                            srcs += J.h_src_cell_off[base + xb + 1] - J.h_src_cell_off[base + xa] + 64.0;
+                        }
+                        for (int s0 = a; s0 < b; s0 += cap)
+                            v.push_back({srcs, make_int4(j, (int)cell, s0, std::min(cap, b - s0) | (B << 16))});
+                    }
                 continue;
             }
             for (int c = 0; c < J.src_nchunks; ++c) spread[J.d].push_back(make_int2(j, c));
@@ -271,10 +314,28 @@ struct StepBuilder {
                 }
             }
         }
+        for (auto &kv : trunc) {
+            // costliest items first, so the cheap boundary cells fill in at the end
+            std::stable_sort(kv.second.begin(), kv.second.end(),
+                             [](const std::pair<double, int4> &x, const std::pair<double, int4> &y) {
+                                 return x.first > y.first;
+                             });
+            std::vector<int4> its(kv.second.size());
+            for (size_t i = 0; i < its.size(); ++i) its[i] = kv.second[i].second;
+            Step st{ST_TRUNC};
+            st.d = std::get<0>(kv.first);
+            st.precision = std::get<1>(kv.first);
+            st.trunc_r = std::get<2>(kv.first);
+            st.jobs = jobs_dev;
+            st.items = upload(its);
+            st.n_items = (int)its.size();
+            out->push_back(st);
+        }
         for (auto &kv : direct) {
             Step st{ST_DIRECT};
-            st.d = kv.first.first;
-            st.precision = kv.first.second;
+            st.d = std::get<0>(kv.first);
+            st.precision = std::get<1>(kv.first);
+            st.diff = std::get<2>(kv.first);
             st.jobs = jobs_dev;
             st.items = upload(kv.second);
             st.n_items = (int)kv.second.size();
@@ -677,8 +738,33 @@ int mot::make_prod_job(mot_plan_s *P, int t, int s, const double *v, int32_t *sl
     Q.nt = P->marg[t].n;
     Q.eta = P->eta;
     for (int c = 0; c < 3; ++c) Q.ctr[c] = P->ext.ctr[c];
+    // mixed direct sums: the expanded exponent cancels terms up to log2(e) r^2 / eta (r the
+    // cloud's radius about its centre); above 8 it is formed in FP64
+    const double half = 0.5 * P->ext.diag;
+    Q.diff = P->precision == MOT_PREC_MIXED && 1.4426950408889634 * half * half / P->eta > 8.0;
     Q.src_pts = P->marg[s].pts;
     Q.tgt_pts = P->marg[t].pts;
+    if (P->path == MOT_TRUNC) {
+        const TruncParams &T = P->TP;
+        Q.src_cell_off = P->marg[s].cell_off;
+        Q.h_src_cell_off = P->marg[s].h_cell_off.data();
+        Q.h_tgt_cell_off = P->marg[t].h_cell_off.data();
+        Q.nc = T.nc;
+        Q.tw = T.w;
+        Q.h = T.h;
+        Q.q2 = T.q2;
+        for (int c = 0; c < 3; ++c) Q.glo[c] = T.glo[c];
+        // run length and targets per lane from the cost model at this pair's occupancy
+        auto occupied = [](const std::vector<int32_t> &off) {
+            int64_t occ = 0;
+            for (size_t c = 0; c + 1 < off.size(); ++c) occ += off[c + 1] > off[c];
+            return (double)std::max<int64_t>(occ, 1);
+        };
+        const double occ_t = occupied(P->marg[t].h_cell_off), occ_s = occupied(P->marg[s].h_cell_off);
+        trunc_choose_run(P->d, T, (double)Q.nt / occ_t, (double)Q.ns / occ_s, occ_t,
+                         P->precision == MOT_PREC_FP64 ? 2 : 4, &Q.trunc_b, &Q.trunc_r);
+        return MOT_OK;
+    }
     if (P->path != MOT_NFFT) return MOT_OK;
     const NfftParams &N = P->P;
     const MargDev &S = P->marg[s], &Tm = P->marg[t];
@@ -763,6 +849,13 @@ int mot::setup_marginals(mot_plan_s *P, const std::vector<double> &pts_h, const 
                 P->P.M, P->P.n, P->P.m, P->P.p, P->P.tau, P->P.eps_B, P->P.T, P->P.L[0], P->P.L[1],
                 P->P.L[2], P->P.est_err);
     }
+    if (P->path == MOT_TRUNC) {
+        double nsum = 0.0;
+        for (int k = 0; k < K; ++k) nsum += (double)P->n[k];
+        MOT_TRY(resolve_trunc(d, P->eta, P->ext, fs, nsum / K, &P->TP));
+        log_msg("truncation: eps=%.3g r_c=%.6g h=%.6g cells=%d^%d w=%d", P->TP.eps, P->TP.rc, P->TP.h,
+                P->TP.nc, d, P->TP.w);
+    }
     double *pts_dev = nullptr;
     MOT_TRY(P->arena.get_n(pts_h.size(), &pts_dev));
     MOT_HIP(hipMemcpy(pts_dev, pts_h.data(), pts_h.size() * sizeof(double), hipMemcpyHostToDevice));
@@ -804,6 +897,32 @@ int mot::setup_marginals(mot_plan_s *P, const std::vector<double> &pts_h, const 
         for (int k = 0; k < K; ++k)
             MOT_TRY(bin_marginal(P, k, pts_dev + P->off[k] * d, scratch, sb, cell_tmp, tile_tmp, toff,
                                  toff_h));
+    } else if (P->path == MOT_TRUNC) {
+        // a1's binning with tile edge 1: points sorted by cell, cell ranges kept
+        const TruncParams &T = P->TP;
+        const int64_t ncell = trunc_cells(d, T);
+        const size_t sb = stable_tile_sort_scratch(nmax, ncell);
+        void *scratch = nullptr;
+        int32_t *cell_tmp = nullptr, *tile_tmp = nullptr;
+        MOT_TRY(P->arena.get(sb, &scratch));
+        MOT_TRY(P->arena.get_n((size_t)nmax * d, &cell_tmp));
+        MOT_TRY(P->arena.get_n((size_t)nmax, &tile_tmp));
+        const double sc = 1.0 / T.h;
+        double o[3] = {0.0, 0.0, 0.0};
+        for (int c = 0; c < d; ++c) o[c] = -T.glo[c] * sc;
+        for (int k = 0; k < K; ++k) {
+            MargDev &G = P->marg[k];
+            const double *src = pts_dev + P->off[k] * d;
+            MOT_TRY(P->arena.get_n((size_t)ncell + 1, &G.cell_off));
+            MOT_HIP(launch_bin_cells(d, G.n, src, sc, sc, sc, o[0], o[1], o[2], T.nc, 1, cell_tmp, tile_tmp,
+                                     P->stream));
+            MOT_HIP(stable_tile_sort(G.n, tile_tmp, ncell, G.perm, G.cell_off, scratch, sb, P->stream));
+            MOT_HIP(launch_gather_rows(src, G.perm, G.n, d, G.pts, P->stream));
+            G.h_cell_off.resize(ncell + 1);
+            MOT_HIP(hipMemcpyAsync(G.h_cell_off.data(), G.cell_off, (ncell + 1) * sizeof(int32_t),
+                                   hipMemcpyDeviceToHost, P->stream));
+        }
+        MOT_HIP(hipStreamSynchronize(P->stream));
     } else {
         for (int k = 0; k < K; ++k) {
             std::vector<int32_t> id(P->n[k]);
@@ -963,10 +1082,11 @@ int mot_plan_create(mot_plan *out, int32_t K, int32_t d, const int64_t *n, const
     *out = nullptr;
     if (!n || !points || !weights || K < 2 || d < 1 || d > 3) return MOT_EINVAL;
     if (topology != MOT_TREE && topology != MOT_CIRCLE) return MOT_EINVAL;
-    if (path != MOT_DIRECT && path != MOT_NFFT && path != MOT_DENSE) return MOT_EINVAL;
+    if (path != MOT_DIRECT && path != MOT_NFFT && path != MOT_DENSE && path != MOT_TRUNC) return MOT_EINVAL;
     if (path == MOT_DENSE && topology != MOT_CIRCLE) return MOT_EUNSUPPORTED;
-    if (precision == MOT_PREC_FP64 && path != MOT_DIRECT) return MOT_EUNSUPPORTED;
-    if (path == MOT_DIRECT && precision != MOT_PREC_FP64 && precision != MOT_PREC_MIXED)
+    if (path == MOT_TRUNC && topology != MOT_TREE) return MOT_EUNSUPPORTED;
+    if (precision == MOT_PREC_FP64 && path != MOT_DIRECT && path != MOT_TRUNC) return MOT_EUNSUPPORTED;
+    if ((path == MOT_DIRECT || path == MOT_TRUNC) && precision != MOT_PREC_FP64 && precision != MOT_PREC_MIXED)
         return MOT_EUNSUPPORTED;
     if (path == MOT_NFFT && precision != MOT_PREC_MIXED) return MOT_EUNSUPPORTED;
     if (topology == MOT_TREE) {
@@ -1056,6 +1176,17 @@ int mot_plan_get_info(mot_plan P, mot_plan_info *info)
     I.device_bytes = P->arena.bytes;
     I.products_per_sweep = P->topology == MOT_TREE ? 2 * (P->K - 1) : 2 * (P->K - 2);
     I.est_err = P->path == MOT_NFFT ? P->P.est_err : 0.0;
+    if (P->path == MOT_TRUNC) {
+        const TruncParams &T = P->TP;
+        I.est_err = T.est_err;
+        I.trunc_radius = T.rc;
+        I.n = T.nc;
+        I.tile = T.w;
+        I.chunk = T.B;
+        I.m = T.R;
+        I.scale = 1.0 / T.h;
+        for (int c = 0; c < 3; ++c) I.offset[c] = c < P->d ? -T.glo[c] / T.h : 0.0;
+    }
     *info = I;
     return MOT_OK;
 }
@@ -1134,7 +1265,7 @@ int mot_plan_profile(mot_plan P, int32_t sweeps, mot_step_timing *out, int32_t m
     P->host_sweeps += sweeps;
     for (auto &e : ev) (void)hipEventDestroy(e);
     const int nout = std::min((int)ns, (int)max_out);
-    static const int kind_code[] = {0, 1, 2, 3, 4, 5, 6, 7};
+    static const int kind_code[] = {0, 1, 2, 3, 4, 5, 6, 7, 8};
     for (int i = 0; i < nout; ++i) {
         mot_step_timing t{};
         t.kind = kind_code[steps[i].kind];
@@ -1396,6 +1527,19 @@ int mot_plan_footprint(int32_t K, int32_t d, const int64_t *n, int32_t topology,
         b += (size_t)(2 * (K - 1) + 1) * (cells * 4 + spec * 16);
         b += (size_t)2 * chunks * pe * 4;
         b += (size_t)H * B * B * 4;
+    } else if (path == MOT_TRUNC) {
+        Extent E;
+        for (int c = 0; c < d; ++c) {
+            E.lo[c] = -half_width;
+            E.hi[c] = half_width;
+        }
+        E.width_max = 2.0 * half_width;
+        E.diag = 2.0 * half_width * std::sqrt((double)d);
+        TruncParams T;
+        int rc = resolve_trunc(d, eta, E, fs, (double)total / K, &T);
+        if (rc < 0) return rc;
+        const int64_t ncell = trunc_cells(d, T);
+        b += (size_t)(K + 1) * (ncell + 1) * 4 + stable_tile_sort_scratch(nmax, ncell);
     }
     b += (size_t)(1 << 16) * 20 + (1 << 20);
     *bytes = b;

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libmot.so")
 OK, MAXITER = 0, 1
 EINVAL, EDOMAIN, ENOMEM, EDEVICE, ENUMERIC, EUNSUPPORTED = -1, -2, -3, -4, -6, -7
 TREE, CIRCLE = 0, 1
-DIRECT, NFFT, DENSE = 0, 1, 2
+DIRECT, NFFT, DENSE, TRUNC = 0, 1, 2, 3
 PREC_FP64, PREC_MIXED, PREC_BF16, PREC_FP16, PREC_BF16X3 = 0, 1, 2, 3, 4
 HOST, DEVICE = 0, 1
 
@@ -46,7 +46,8 @@ class PlanInfo(ctypes.Structure):
                 ("scale", ctypes.c_double), ("offset", ctypes.c_double * 3),
                 ("box_lo", ctypes.c_int32 * 3), ("box_len", ctypes.c_int32 * 3),
                 ("depth", ctypes.c_int32), ("device_bytes", ctypes.c_size_t),
-                ("products_per_sweep", ctypes.c_int32), ("est_err", ctypes.c_double)]
+                ("products_per_sweep", ctypes.c_int32), ("est_err", ctypes.c_double),
+                ("trunc_radius", ctypes.c_double)]
 
 
 class Allocator(ctypes.Structure):
@@ -62,7 +63,7 @@ class StepTiming(ctypes.Structure):
 
 
 STEP_KIND = {0: "node", 1: "direct", 2: "spread", 3: "fold", 4: "fft", 5: "interp", 6: "final",
-             7: "fill"}
+             7: "fill", 8: "trunc"}
 
 
 class Request(ctypes.Structure):

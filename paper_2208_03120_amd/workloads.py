@@ -127,6 +127,14 @@ def star_nfft(seed=2, N=100_000):
                                "grid": 128, "m": 6})
 
 
+def star_small_eta(seed=6, N=100_000, eta=1e-3):
+    """Star tree K=10, N points in d=3 with a small eta (kernel radius well below the
+    cloud's extent), for the truncated direct path."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return make_instance(rng, 10, N, 3, TREE, eta, parent=star_parent(10),
+                         meta={"name": "star_K10_N%d_d3_eta%g" % (N, eta), "sweeps": 200})
+
+
 def cycle(seed=3, N=4000):
     """Cycle K=5, N points in d=2, eta=0.1, 100 sweeps."""
     rng = np.random.Generator(np.random.PCG64(seed))

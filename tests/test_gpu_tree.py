@@ -130,3 +130,18 @@ def test_nfft_star_sinkhorn_parity(mot):
     viol = max(float(np.sum(np.abs(a - b))) for a, b in zip(P, oP))
     assert viol < 1e-6
     plan.close()
+
+
+@pytest.mark.parametrize("d,eta", [(3, 1e-3), (2, 3e-4), (1, 1e-4), (3, 0.05)])
+def test_direct_mixed_product_accuracy_over_eta(mot, d, eta):
+    """The mixed direct product stays at FP32 accuracy for small eta (where the expanded
+    exponent would cancel large terms, the kernel works with scaled coordinate
+    differences) and at the benchmark's eta."""
+    inst = W.make_instance(rng(300 + d), 2, [2000, 1700], d, W.TREE, eta, parent=[-1, 0])
+    plan = mot.Plan(inst.points, inst.weights, W.TREE, inst.parent, eta, path=mot.DIRECT,
+                    precision=mot.PREC_MIXED)
+    v = rng(310 + d).uniform(0.5, 1.5, 1700)
+    got = plan.apply(0, 1, v)
+    want = oracle.kernel_apply(inst.points[0], inst.points[1], v, eta)
+    assert float(np.max(np.abs(got - want) / want)) < 1e-6
+    plan.close()

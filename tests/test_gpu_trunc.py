@@ -1,0 +1,200 @@
+"""GPU truncated direct products (small eta; the truncation suggested at the end of
+Sec. 6.1) against the FP64 oracle, through the C ABI.
+
+The cutoff is part of the interface: r_c = sqrt(eta ln(1 / eps)) with
+eps = target (pi eta)^(d/2) / (2^d V), V the bounding-box volume of all points (each side
+at least sqrt(pi eta)).  The tests recompute r_c from that formula and check:
+* the plan reports it;
+* the product brackets: truncated oracle sum at r_c <= GPU <= full direct sum (the GPU
+  sums every source of the cells near the target's cell, a superset of the ball);
+* the product is within eps sum_j v_j of the full direct sum (FP64: plus 1e-12 relative;
+  mixed: plus 2e-6 relative) and within 1e-5 relative;
+* Sinkhorn sweeps on the truncated path against the oracle's Algorithm 2.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2208_03120_amd import workloads as W
+from tests.helpers import gauge_fix, max_rel
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mot():
+    from paper_2208_03120_amd import mot as m
+    return m
+
+
+def rng(seed):
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def cutoff(points, eta, target=1e-7):
+    allp = np.concatenate(points)
+    d = allp.shape[1]
+    V = 1.0
+    for c in range(d):
+        V *= max(allp[:, c].max() - allp[:, c].min(), math.sqrt(math.pi * eta))
+    eps = target * min(1.0, (math.pi * eta) ** (d / 2) / (2 ** d * V))
+    return eps, math.sqrt(eta * math.log(1.0 / eps))
+
+
+def check_product(got, x_t, x_s, v, eta, eps, rc, rel):
+    full = oracle.kernel_apply(x_t, x_s, v, eta)
+    trunc = oracle.kernel_apply_truncated(x_t, x_s, v, eta, rc)
+    assert np.all(got >= trunc * (1 - rel)), "a source within r_c was left out"
+    assert np.all(got <= full * (1 + rel) + 1e-300)
+    assert np.all(np.abs(got - full) <= eps * np.abs(v).sum() + rel * full)
+    return float(np.max(np.abs(got - full) / full))
+
+
+@pytest.mark.parametrize("d,sizes,eta", [(1, [4000, 3500], 1e-4), (2, [3000, 2600], 1e-3),
+                                         (3, [5000, 4100], 2e-3), (3, [700, 1300], 5e-4)])
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_product_small_eta(mot, d, sizes, eta, prec):
+    inst = W.make_instance(rng(200 + d), 2, sizes, d, W.TREE, eta, parent=[-1, 0])
+    precision = mot.PREC_FP64 if prec == "fp64" else mot.PREC_MIXED
+    plan = mot.Plan(inst.points, inst.weights, W.TREE, inst.parent, eta, path=mot.TRUNC,
+                    precision=precision)
+    eps, rc = cutoff(inst.points, eta)
+    info = plan.info()
+    assert abs(info["trunc_radius"] - rc) <= 1e-12 * rc
+    assert info["n"] >= 2, "the cloud should span several cells at this eta"
+    rel = 1e-12 if prec == "fp64" else 2e-6
+    for t, s in [(0, 1), (1, 0)]:
+        v = rng(210 + t).uniform(0.5, 1.5, sizes[s])
+        got = plan.apply(t, s, v)
+        err = check_product(got, inst.points[t], inst.points[s], v, eta, eps, rc, rel)
+        assert err < 1e-5, err
+    plan.close()
+
+
+def test_one_cell_equals_direct(mot):
+    """A large eta: the cutoff exceeds the cloud, one cell holds everything and the
+    truncated product is the direct sum."""
+    inst = W.make_instance(rng(220), 2, [900, 1000], 2, W.TREE, 0.5, parent=[-1, 0])
+    plan = mot.Plan(inst.points, inst.weights, W.TREE, inst.parent, 0.5, path=mot.TRUNC,
+                    precision=mot.PREC_FP64)
+    assert plan.info()["n"] == 1
+    v = rng(221).uniform(0, 1, 1000)
+    np.testing.assert_allclose(plan.apply(0, 1, v),
+                               oracle.kernel_apply(inst.points[0], inst.points[1], v, 0.5),
+                               rtol=1e-13)
+    plan.close()
+
+
+def test_clustered_and_tiny_marginals(mot):
+    """Two far-apart clusters (empty cells between them), a single-point marginal and
+    points on cell boundaries."""
+    r = rng(230)
+    a = np.concatenate([r.normal(-0.2, 0.01, (600, 2)), r.normal(0.2, 0.01, (500, 2))])
+    b = np.concatenate([r.normal(-0.2, 0.01, (400, 2)), r.normal(0.2, 0.01, (450, 2))])
+    c = np.array([[0.2, 0.2]])
+    pts = [a, b, c]
+    # a lattice of points exactly on multiples of 1/64 in the first marginal
+    a[:50] = np.round(a[:50] * 64) / 64
+    wts = [np.full(len(p), 1.0 / len(p)) for p in pts]
+    eta = 2e-4
+    plan = mot.Plan(pts, wts, W.TREE, [-1, 0, 0], eta, path=mot.TRUNC, precision=mot.PREC_FP64)
+    eps, rc = cutoff(pts, eta)
+    for t, s in [(0, 1), (1, 0), (2, 0), (0, 2)]:
+        v = r.uniform(0.5, 1.5, len(pts[s]))
+        got = plan.apply(t, s, v)
+        full = oracle.kernel_apply(pts[t], pts[s], v, eta)
+        trunc = oracle.kernel_apply_truncated(pts[t], pts[s], v, eta, rc)
+        assert np.all(got >= trunc * (1 - 1e-12))
+        assert np.all(np.abs(got - full) <= eps * v.sum() + 1e-12 * full)
+    plan.close()
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_tree_sinkhorn_truncated(mot, prec):
+    """A branching tree, d = 2, eta = 2e-3: sweeps on the truncated path against the
+    oracle's Algorithm 2 with full direct products.  FP64 with a 1e-12 target."""
+    r = rng(240)
+    parent = [-1, 0, 0, 1, 1, 2]
+    inst = W.make_instance(r, 6, [800, 700, 900, 650, 720, 810], 2, W.TREE, 2e-3, parent=parent)
+    precision = mot.PREC_FP64 if prec == "fp64" else mot.PREC_MIXED
+    fs = mot.fastsum_params(target=1e-12) if prec == "fp64" else None
+    plan = mot.Plan(inst.points, inst.weights, W.TREE, inst.parent, inst.eta, path=mot.TRUNC,
+                    precision=precision, fastsum=fs)
+    plan.sinkhorn(30)
+    phi = plan.scalings()
+    ophi, oS, _, _ = oracle.tree_sinkhorn(inst.points, inst.weights, inst.parent, inst.eta, 30)
+    err = max_rel(gauge_fix(phi, inst.weights), gauge_fix(ophi, inst.weights))
+    assert err < (1e-9 if prec == "fp64" else 1e-5), err
+    np.testing.assert_allclose(plan.S_history(), oS, rtol=1e-9 if prec == "fp64" else 1e-5)
+    plan.close()
+
+
+def test_batched_truncated_plan_equals_alone(mot):
+    """A truncated-path plan batched with an NFFT plan gives bitwise its stand-alone result."""
+    a = W.make_instance(rng(250), 3, [1500, 1200, 1300], 3, W.TREE, 1e-3, parent=[-1, 0, 0])
+    b = W.make_instance(rng(251), 3, [900, 800, 1000], 2, W.TREE, 0.05, parent=[-1, 0, 1])
+    pa = mot.Plan(a.points, a.weights, W.TREE, a.parent, a.eta, path=mot.TRUNC)
+    pb = mot.Plan(b.points, b.weights, W.TREE, b.parent, b.eta, path=mot.NFFT)
+    alone = mot.Plan(a.points, a.weights, W.TREE, a.parent, a.eta, path=mot.TRUNC)
+    batch = mot.Batch([pa, pb])
+    batch.sinkhorn(12)
+    alone.sinkhorn(12)
+    for x, y in zip(pa.scalings(), alone.scalings()):
+        np.testing.assert_array_equal(x, y)
+    batch.close()
+    for p in (pa, pb, alone):
+        p.close()
+
+
+@pytest.fixture(scope="module")
+def full(mot):
+    inst = W.star_small_eta(seed=6, N=100_000, eta=1e-3)
+    plan = mot.Plan(inst.points, inst.weights, W.TREE, inst.parent, inst.eta, path=mot.TRUNC)
+    yield inst, plan
+    plan.close()
+
+
+def test_full_size_product_sampled(mot, full):
+    """Star K = 10, N = 100000, d = 3, eta = 1e-3: one product (root -> leaf 4), 512
+    sampled targets against the full direct sum and the truncated oracle."""
+    inst, plan = full
+    eps, rc = cutoff(inst.points, inst.eta)
+    assert abs(plan.info()["trunc_radius"] - rc) <= 1e-12 * rc
+    v = rng(261).uniform(0.5, 1.5, 100_000)
+    got = plan.apply(4, 0, v)
+    idx = rng(262).choice(100_000, 512, replace=False)
+    err = check_product(got[idx], inst.points[4][idx], inst.points[0], v, inst.eta, eps, rc, 2e-6)
+    assert err < 2e-6, err
+
+
+def test_full_size_root_marginal_sampled(mot, full):
+    """After sweeps at full size, the root marginal P_0 = phi^0 prod_t beta_t at 256
+    sampled root points (Theorem 4.1) against full direct sums."""
+    inst, plan = full
+    plan.set_scalings([np.ones(n) for n in inst.sizes])
+    plan.sinkhorn(3)
+    phi = plan.scalings()
+    P, _ = plan.marginals()
+    idx = rng(263).choice(100_000, 256, replace=False)
+    want = phi[0][idx].copy()
+    for t in range(1, inst.K):
+        want *= oracle.kernel_apply(inst.points[0][idx], inst.points[t], phi[t], inst.eta)
+    assert float(np.max(np.abs(P[0][idx] - want) / want)) < 9 * 2e-6
+
+
+def test_runs_of_cells_fill_lanes(mot):
+    """Sparse cells (few points per cell at this eta): work items take runs of several
+    cells of a row; the products still bracket correctly, in both directions."""
+    inst = W.make_instance(rng(270), 2, [2500, 2200], 2, W.TREE, 1e-4, parent=[-1, 0])
+    plan = mot.Plan(inst.points, inst.weights, W.TREE, inst.parent, 1e-4, path=mot.TRUNC)
+    info = plan.info()
+    assert info["chunk"] > 1, info
+    eps, rc = cutoff(inst.points, 1e-4)
+    for t, s in [(0, 1), (1, 0)]:
+        v = rng(271 + t).uniform(0.5, 1.5, inst.sizes[s])
+        got = plan.apply(t, s, v)
+        err = check_product(got, inst.points[t], inst.points[s], v, 1e-4, eps, rc, 2e-6)
+        assert err < 1e-5, err
+    plan.close()

@@ -378,3 +378,53 @@ def test_binning_boundaries_and_clamping():
     assert tile.tolist() == [1, 1, 0, 1, 1, 0, 1]
     assert perm.tolist() == [2, 5, 0, 1, 3, 4, 6]
     assert toff.tolist() == [0, 2, 7]
+
+
+# ---- truncated direct sum (small eta, end of Sec. 6.1) -----------------------------------
+
+def test_truncated_sum_hand_values():
+    """1-D, eta = 0.01, r_c = 0.25: sources at distances 0.1, 0.3, 0.2 and exactly 0.25.
+    The terms kept are e^-1 (0.1^2 / 0.01 = 1), 4 e^-4 and, on the radius, 8 e^-6.25; the
+    source at 0.3 is dropped."""
+    x = np.array([[0.0]])
+    y = np.array([[0.1], [0.3], [-0.2], [0.25]])
+    v = np.array([1.0, 2.0, 4.0, 8.0])
+    got = oracle.kernel_apply_truncated(x, y, v, 0.01, 0.25)
+    want = math.exp(-1.0) + 4.0 * math.exp(-4.0) + 8.0 * math.exp(-6.25)
+    assert abs(got[0] - want) <= 1e-15 * want
+    # a radius below every distance keeps nothing; a radius of 0 keeps a coincident source
+    assert oracle.kernel_apply_truncated(x, y, v, 0.01, 0.05)[0] == 0.0
+    y0 = np.array([[0.0], [0.1]])
+    assert oracle.kernel_apply_truncated(x, y0, np.array([3.0, 5.0]), 0.01, 0.0)[0] == 3.0
+
+
+def test_truncated_sum_large_radius_is_the_direct_sum():
+    """A radius above the diameter keeps every pair: the numpy truncated sum equals the C
+    direct sum (two independent codes of eq. fastsum-sum)."""
+    r = np.random.Generator(np.random.PCG64(7))
+    for d in (1, 2, 3):
+        x = r.uniform(-0.25, 0.25, (40, d))
+        y = r.uniform(-0.25, 0.25, (55, d))
+        v = r.uniform(0, 1, 55)
+        a = oracle.kernel_apply_truncated(x, y, v, 0.003, 10.0)
+        b = oracle.kernel_apply(x, y, v, 0.003)
+        np.testing.assert_allclose(a, b, rtol=1e-13, atol=0)
+
+
+def test_truncated_sum_error_bound_and_monotone_radius():
+    """Every dropped term is below exp(-r_c^2 / eta) v_j, so 0 <= full - truncated <=
+    exp(-r_c^2 / eta) sum_j v_j, and the truncated sum grows with r_c."""
+    r = np.random.Generator(np.random.PCG64(8))
+    x = r.uniform(-0.25, 0.25, (60, 2))
+    y = r.uniform(-0.25, 0.25, (300, 2))
+    v = r.uniform(0, 1, 300)
+    eta = 2e-3
+    full = oracle.kernel_apply(x, y, v, eta)
+    prev = np.zeros(60)
+    for rc in (0.02, 0.05, 0.08, 0.12, 0.2):
+        t = oracle.kernel_apply_truncated(x, y, v, eta, rc)
+        assert np.all(t >= prev - 1e-15)
+        gap = full - t
+        assert np.all(gap >= -1e-15 * full)
+        assert np.all(gap <= math.exp(-rc * rc / eta) * v.sum() * (1 + 1e-12))
+        prev = t
