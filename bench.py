@@ -234,6 +234,40 @@ def bench_truncated(mot, W, etas=(1e-3, 3e-4), N=100_000, sweeps=20, direct_swee
     return res
 
 
+def bench_barycenter(mot, W, N=5000, sweeps=150, eta=5e-3):
+    """Generalised barycenter on the H-shaped tree of Sec. 6.2 (K = 7, four leaves of N
+    points on synthetic planar shapes, three free nodes on their 4N-point union, leaf
+    edges weighted 1/4, eta = 5e-3, 150 sweeps as in the paper): NFFT and direct sweeps/s,
+    the barycenters (free-node marginals) of the two paths against each other, and the
+    leaves' marginal errors."""
+    import torch
+    inst, ew, free = W.h_tree_barycenter(seed=7, N=N, eta=eta)
+    res = {"workload": "H-shaped tree K=7, 4 leaves x %d points (2-D shapes), 3 free nodes x %d points, "
+                       "leaf edges weighted 1/4, eta=%g" % (N, 4 * N, eta), "sweeps": sweeps}
+    margs = {}
+    for name, path in [("nfft", mot.NFFT), ("direct", mot.DIRECT)]:
+        plan = mot.Plan(inst.points, inst.weights, W.TREE, inst.parent, eta, path=path,
+                        edge_weight=ew, free=free)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.sinkhorn(sweeps)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / sweeps
+        P, l1 = plan.marginals()
+        info = plan.info()
+        entry = {"sweeps_per_s": 1.0 / dt, "ms_per_sweep": dt * 1e3,
+                 "leaf_marginal_l1_max": float(max(l1[k] for k in range(inst.K) if not free[k]))}
+        if path == mot.NFFT:
+            entry.update({"M": info["M"], "n": info["n"], "m": info["m"], "est_err": info["est_err"]})
+        res[name] = entry
+        margs[name] = P
+        plan.close()
+    res["barycenter_l1_nfft_vs_direct"] = float(max(np.sum(np.abs(margs["nfft"][k] - margs["direct"][k]))
+                                                    for k in range(inst.K) if free[k]))
+    res["speedup_nfft_vs_direct"] = res["nfft"]["sweeps_per_s"] / res["direct"]["sweeps_per_s"]
+    return res
+
+
 def bench_circle(mot, W, sweeps=20):
     """Cycle K=5, N=4000, d=2, eta=0.1: dense MFMA products in three precisions and the
     row-by-row NFFT products; errors of the gauge-fixed scaling vectors are stated
@@ -530,7 +564,8 @@ def main():
     plan.close()
     if not args.no_extras:
         for key, fn in [("circle", bench_circle), ("batched", bench_batched), ("serving", bench_serving),
-                        ("error_vs_M", bench_error_vs_M), ("truncated", bench_truncated)]:
+                        ("error_vs_M", bench_error_vs_M), ("truncated", bench_truncated),
+                        ("barycenter", bench_barycenter)]:
             try:
                 out[key] = fn(mot, W)
             except Exception as e:  # the headline measurement stands on its own

@@ -148,6 +148,30 @@ int mot_plan_create(mot_plan *out, int32_t K, int32_t d, const int64_t *n, const
                     int32_t path, int32_t precision, const mot_fastsum_params *fs,
                     int32_t ptr_kind, void *stream, const mot_allocator *alloc);
 
+/* ---- generalised barycenters on trees (Sec. 6.2) -----------------------------------
+ * Tree problems with weighted edge costs and nodes without a marginal constraint.  The
+ * cost of the edge {parent[k], k} is edge_weight[k] |x - y|^2, so its kernel is
+ * exp(-|x - y|^2 / (eta / edge_weight[k])).  A node k with free_node[k] != 0 has no given
+ * marginal: its scaling vector is 1 in every sweep (the barycenter form of Algorithm 2's
+ * phi update), and its marginal after the solve (mot_marginals) is the barycenter on the
+ * node's support.  The weights passed for free nodes are not read.  The root (node 0)
+ * must be constrained (MOT_EINVAL otherwise): its update fixes the common scale of the
+ * scalings, without which the stale sibling messages of Algorithm 2 oscillate or grow.
+ * mot_marginals reports an L1 error of 0 for free nodes.  On the NFFT path the plan's
+ * grid and bandwidth serve every edge (chosen for the smallest and largest eta / w),
+ * with one multiplier per distinct edge weight; on the truncated path the cutoff is
+ * the one of the largest eta / w.  Other arguments as for mot_plan_create (tree). */
+typedef struct {
+    const double *edge_weight; /* [K] host or NULL (all 1): entry k >= 1 finite and > 0;
+                                  entry 0 is not read                                  */
+    const int32_t *free_node;  /* [K] host or NULL (none)                              */
+} mot_tree_options;
+
+int mot_plan_create_tree(mot_plan *out, int32_t K, int32_t d, const int64_t *n, const double *points,
+                         const double *weights, const int32_t *parent, const mot_tree_options *opt,
+                         double eta, int32_t path, int32_t precision, const mot_fastsum_params *fs,
+                         int32_t ptr_kind, void *stream, const mot_allocator *alloc);
+
 /* Run Sinkhorn sweeps: Algorithm 2 (tree) or Algorithm 3 (circle).  One sweep
  * updates every scaling vector once and recomputes the messages; it costs
  * 2(K-1) kernel products (tree) or 2(K-2) matrix products (circle).

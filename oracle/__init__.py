@@ -62,6 +62,13 @@ def _load():
                                           ctypes.c_double, ctypes.c_int, ctypes.c_double,
                                           dp, dp, ip]
         lib.orc_tree_sinkhorn.restype = ctypes.c_int
+        lib.orc_tree_sinkhorn_ex.argtypes = [ctypes.c_int, ctypes.c_int, lp, dp, dp, ip, dp, ip,
+                                             ctypes.c_double, ctypes.c_int, ctypes.c_double,
+                                             dp, dp, ip]
+        lib.orc_tree_sinkhorn_ex.restype = ctypes.c_int
+        lib.orc_tree_marginals_ex.argtypes = [ctypes.c_int, ctypes.c_int, lp, dp, ip, dp,
+                                              ctypes.c_double, dp, dp]
+        lib.orc_tree_marginals_ex.restype = ctypes.c_int
         lib.orc_tree_marginals.argtypes = [ctypes.c_int, ctypes.c_int, lp, dp, ip,
                                            ctypes.c_double, dp, dp]
         lib.orc_tree_marginals.restype = ctypes.c_int
@@ -140,31 +147,48 @@ def kernel_apply_truncated(xt, xs, v, eta, r_c):
     return out
 
 
-def tree_sinkhorn(points, weights, parent, eta, sweeps, delta=0.0, phi0=None):
-    """Algorithm 2.  Returns (phi list, S history, sweeps done, status)."""
+def tree_sinkhorn(points, weights, parent, eta, sweeps, delta=0.0, phi0=None, edge_weight=None,
+                  free=None):
+    """Algorithm 2.  Returns (phi list, S history, sweeps done, status).
+
+    ``edge_weight`` ([K], entry k for the edge {parent[k], k}) and ``free`` ([K] booleans)
+    give the generalised barycenter problem of Sec. 6.2: weighted edge costs, and nodes
+    without a marginal constraint whose scaling vector is 1 in every sweep."""
     lib = _load()
     K = len(points)
+    weights = [np.zeros(len(p)) if w is None else w for p, w in zip(points, weights)]
     d, off, pts, mu = _cat(points, weights)
     par = np.ascontiguousarray(parent, dtype=np.int32)
     phi = np.ones(off[-1]) if phi0 is None else np.concatenate(phi0).astype(np.float64)
     phi = np.ascontiguousarray(phi)
     S = np.zeros(max(sweeps, 1))
     done = ctypes.c_int(0)
-    rc = lib.orc_tree_sinkhorn(K, d, _l(off), _d(pts), _d(mu), _i(par), float(eta),
-                               int(sweeps), float(delta), _d(phi), _d(S),
-                               ctypes.byref(done))
+    if edge_weight is None and free is None:
+        rc = lib.orc_tree_sinkhorn(K, d, _l(off), _d(pts), _d(mu), _i(par), float(eta),
+                                   int(sweeps), float(delta), _d(phi), _d(S),
+                                   ctypes.byref(done))
+    else:
+        ew = None if edge_weight is None else np.ascontiguousarray(edge_weight, dtype=np.float64)
+        fr = None if free is None else np.ascontiguousarray(np.asarray(free, dtype=bool), dtype=np.int32)
+        rc = lib.orc_tree_sinkhorn_ex(K, d, _l(off), _d(pts), _d(mu), _i(par),
+                                      _d(ew) if ew is not None else None,
+                                      _i(fr) if fr is not None else None, float(eta),
+                                      int(sweeps), float(delta), _d(phi), _d(S),
+                                      ctypes.byref(done))
     return _split(phi, off), S[:done.value].copy(), done.value, rc
 
 
-def tree_marginals(points, parent, eta, phi):
-    """P_k(K (.) Phi) of Theorem 4.1 at fixed phi."""
+def tree_marginals(points, parent, eta, phi, edge_weight=None):
+    """P_k(K (.) Phi) of Theorem 4.1 at fixed phi (edge costs weighted by edge_weight)."""
     lib = _load()
     K = len(points)
     d, off, pts, _ = _cat(points)
     par = np.ascontiguousarray(parent, dtype=np.int32)
     ph = np.ascontiguousarray(np.concatenate(phi), dtype=np.float64)
     P = np.empty(off[-1])
-    rc = lib.orc_tree_marginals(K, d, _l(off), _d(pts), _i(par), float(eta), _d(ph), _d(P))
+    ew = None if edge_weight is None else np.ascontiguousarray(edge_weight, dtype=np.float64)
+    rc = lib.orc_tree_marginals_ex(K, d, _l(off), _d(pts), _i(par),
+                                   _d(ew) if ew is not None else None, float(eta), _d(ph), _d(P))
     assert rc == OK, rc
     return _split(P, off)
 

@@ -18,13 +18,16 @@ def circle_edges(K):
     return [(k, (k + 1) % K) for k in range(K)]
 
 
-def cost_tensor(points, edges):
-    """C_i = sum_{(a,b) in edges} |x^a_{i_a} - x^b_{i_b}|^2, eq. (cost_sparse)."""
+def cost_tensor(points, edges, edge_weights=None):
+    """C_i = sum_{(a,b) in edges} w_(a,b) |x^a_{i_a} - x^b_{i_b}|^2, eq. (cost_sparse), with
+    the edge weights of eq. (cost_function_barycenter_tree) (default 1)."""
     K = len(points)
     shape = tuple(p.shape[0] for p in points)
     C = np.zeros(shape)
-    for a, b in edges:
+    for e, (a, b) in enumerate(edges):
         D = np.sum((points[a][:, None, :] - points[b][None, :, :]) ** 2, axis=-1)
+        if edge_weights is not None:
+            D = edge_weights[e] * D
         idx = [None] * K
         idx[a] = slice(None)
         idx[b] = slice(None)
@@ -54,25 +57,31 @@ def outer(vectors):
     return out
 
 
-def algorithm1(Kt, weights, sweeps, phi0=None):
+def algorithm1(Kt, weights, sweeps, phi0=None, constrained=None):
     """Algorithm 1: phi^k <- (mu^k (.) phi^k) / P_k(K (.) Phi~), k = 1..K per sweep.
 
     One sweep updates every marginal once in order, each update using the
-    newest values of the others.  Returns the list of phi after each sweep."""
+    newest values of the others.  Marginals without a constraint (``constrained[k]``
+    false; the barycenter nodes of Sec. 6.2) keep phi^k = 1.  Returns the list of phi
+    after each sweep."""
     K = Kt.ndim
     phi = [np.ones(Kt.shape[k]) for k in range(K)] if phi0 is None else [p.copy() for p in phi0]
     hist = []
     for _ in range(sweeps):
         for k in range(K):
+            if constrained is not None and not constrained[k]:
+                continue
             Pk = marginal(Kt * outer(phi), k)
             phi[k] = (weights[k] * phi[k]) / Pk
         hist.append([p.copy() for p in phi])
     return hist
 
 
-def sinkhorn_S(Kt, weights, phi, eta):
-    """S(phi) = eta sum_k mu^k . log phi^k - eta sum_i K_i Phi_i (Theorem 3.1)."""
-    s = sum(float(np.sum(w[w > 0] * np.log(p[w > 0]))) for w, p in zip(weights, phi))
+def sinkhorn_S(Kt, weights, phi, eta, constrained=None):
+    """S(phi) = eta sum_k mu^k . log phi^k - eta sum_i K_i Phi_i (Theorem 3.1); the sum
+    over k runs over the constrained marginals only."""
+    s = sum(float(np.sum(w[w > 0] * np.log(p[w > 0]))) for k, (w, p) in enumerate(zip(weights, phi))
+            if constrained is None or constrained[k])
     return eta * (s - float(np.sum(Kt * outer(phi))))
 
 

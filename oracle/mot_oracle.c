@@ -88,7 +88,14 @@ typedef struct {
     double **beta;  /* beta[k] (k >= 1) has length n_{p(k)}: alpha^{(p(k),k)} */
     double **gamma; /* gamma[k] has length n_k: alpha^{(k,p(k))}, gamma[0] = 1  */
     double *work;   /* scratch vector of length max n_k                        */
+    const double *edge_w; /* NULL or [K]: weight w_k of the edge {p(k), k}, Sec. 6.2 */
+    const int *free_node; /* NULL or [K]: nonzero = no marginal constraint at k    */
 } tree_t;
+
+/* The edge {p(k), k} has cost w_k |x - y|^2 (eq. cost_function_barycenter_tree), so its
+ * kernel is exp(-|x - y|^2 / (eta / w_k)). */
+static double edge_eta(const tree_t *T, int k) { return T->edge_w ? T->eta / T->edge_w[k] : T->eta; }
+static int is_free(const tree_t *T, int k) { return T->free_node && T->free_node[k]; }
 
 static long tn(const tree_t *T, int k) { return T->off[k + 1] - T->off[k]; }
 static const double *tpts(const tree_t *T, int k) { return T->pts + T->off[k] * T->d; }
@@ -112,7 +119,7 @@ static void compute_beta(tree_t *T, const double *const *phi, int k)
     long nk = tn(T, k);
     child_product(T, k, -1, T->work);
     for (long i = 0; i < nk; ++i) T->work[i] = phi[k][i] * T->work[i];
-    orc_kernel_apply(T->d, tn(T, p), tpts(T, p), nk, tpts(T, k), T->work, T->eta,
+    orc_kernel_apply(T->d, tn(T, p), tpts(T, p), nk, tpts(T, k), T->work, edge_eta(T, k),
                      T->beta[k]);
 }
 
@@ -127,7 +134,7 @@ static void compute_gamma(tree_t *T, const double *const *phi, int k)
     long np_ = tn(T, p);
     child_product(T, p, k, T->work);
     for (long i = 0; i < np_; ++i) T->work[i] = (phi[p][i] * T->gamma[p][i]) * T->work[i];
-    orc_kernel_apply(T->d, tn(T, k), tpts(T, k), np_, tpts(T, p), T->work, T->eta,
+    orc_kernel_apply(T->d, tn(T, k), tpts(T, k), np_, tpts(T, p), T->work, edge_eta(T, k),
                      T->gamma[k]);
 }
 
@@ -174,13 +181,24 @@ static int tree_check(int K, const int *parent)
 /* Sinkhorn for tree structure, Algorithm 2.
  *   phi    in: initial scaling vectors (phi^(0)); out: the last computed ones.
  *   S_hist receives S^(r) for every completed sweep r (length >= max_sweeps).
- * Stops when |S^(r) - S^(r-1)| < delta (delta > 0) or after max_sweeps sweeps. */
-int orc_tree_sinkhorn(int K, int d, const long *off, const double *pts, const double *mu,
-                      const int *parent, double eta, int max_sweeps, double delta,
-                      double *phi_cat, double *S_hist, int *sweeps_done)
+ * Stops when |S^(r) - S^(r-1)| < delta (delta > 0) or after max_sweeps sweeps.
+ * Generalised barycenters (Sec. 6.2): edge_w (NULL = all 1) weights the edge costs and
+ * free_node (NULL = none) marks nodes without a marginal constraint; their phi is 1 in
+ * every sweep (the modified update of the phi step) and their mu is not read.  The root
+ * must be constrained: its update is the one that fixes the common scale of the
+ * scalings, and without it the stale sibling messages of Algorithm 2 oscillate (two
+ * children) or grow geometrically (more). */
+int orc_tree_sinkhorn_ex(int K, int d, const long *off, const double *pts, const double *mu,
+                         const int *parent, const double *edge_w, const int *free_node, double eta,
+                         int max_sweeps, double delta, double *phi_cat, double *S_hist,
+                         int *sweeps_done)
 {
     if (tree_check(K, parent) != ORC_OK || eta <= 0.0 || d < 1) return ORC_EINVAL;
-    tree_t T = {K, d, off, pts, parent, eta, NULL, NULL, NULL};
+    if (edge_w)
+        for (int k = 1; k < K; ++k)
+            if (!(edge_w[k] > 0.0)) return ORC_EINVAL;
+    if (free_node && free_node[0]) return ORC_EINVAL;
+    tree_t T = {K, d, off, pts, parent, eta, NULL, NULL, NULL, edge_w, free_node};
     int rc = tree_alloc(&T);
     double **phi = (double **)malloc((size_t)K * sizeof(double *));
     double *phi_old = (double *)malloc((size_t)off[K] * sizeof(double));
@@ -205,16 +223,20 @@ int orc_tree_sinkhorn(int K, int d, const long *off, const double *pts, const do
             long nk = tn(&T, k);
             child_product(&T, k, -1, T.work);
             const double *muk = mu + off[k];
-            for (long i = 0; i < nk; ++i) phi[k][i] = muk[i] / (T.gamma[k][i] * T.work[i]);
+            for (long i = 0; i < nk; ++i)
+                phi[k][i] = is_free(&T, k) ? 1.0 : muk[i] / (T.gamma[k][i] * T.work[i]);
         }
         /* Upward pass with the new phi, k = K..2. */
         for (int k = K - 1; k >= 1; --k) compute_beta(&T, (const double *const *)phi, k);
 
         /* S^(r) = eta (sum_k mu^k . log phi^k(r) - (mu^1 / phi^1(r+1)) . phi^1(r)).
-         * Terms with mu = 0 contribute nothing (0 log 0 := 0). */
+         * Terms with mu = 0 contribute nothing (0 log 0 := 0); free nodes have none. */
         double s1 = 0.0, s2 = 0.0;
-        for (long i = 0; i < off[K]; ++i)
-            if (mu[i] > 0.0) s1 += mu[i] * log(phi_old[i]);
+        for (int k = 0; k < K; ++k) {
+            if (is_free(&T, k)) continue;
+            for (long i = off[k]; i < off[k + 1]; ++i)
+                if (mu[i] > 0.0) s1 += mu[i] * log(phi_old[i]);
+        }
         for (long i = 0; i < tn(&T, 0); ++i)
             if (mu[i] > 0.0) s2 += (mu[i] / phi[0][i]) * phi_old[i];
         S_hist[r] = eta * (s1 - s2);
@@ -241,13 +263,19 @@ int orc_tree_sinkhorn(int K, int d, const long *off, const double *pts, const do
     return rc;
 }
 
-/* Marginals of K (.) Phi at fixed phi, Theorem 4.1 written with the beta/gamma
- * vectors: P_k = phi^k (.) gamma_k (.) beta^{(.)C_k}.  P is concatenated. */
-int orc_tree_marginals(int K, int d, const long *off, const double *pts, const int *parent,
-                       double eta, const double *phi_cat, double *P)
+int orc_tree_sinkhorn(int K, int d, const long *off, const double *pts, const double *mu,
+                      const int *parent, double eta, int max_sweeps, double delta,
+                      double *phi_cat, double *S_hist, int *sweeps_done)
+{
+    return orc_tree_sinkhorn_ex(K, d, off, pts, mu, parent, NULL, NULL, eta, max_sweeps, delta,
+                                phi_cat, S_hist, sweeps_done);
+}
+
+int orc_tree_marginals_ex(int K, int d, const long *off, const double *pts, const int *parent,
+                          const double *edge_w, double eta, const double *phi_cat, double *P)
 {
     if (tree_check(K, parent) != ORC_OK || eta <= 0.0) return ORC_EINVAL;
-    tree_t T = {K, d, off, pts, parent, eta, NULL, NULL, NULL};
+    tree_t T = {K, d, off, pts, parent, eta, NULL, NULL, NULL, edge_w, NULL};
     if (tree_alloc(&T) != ORC_OK) {
         tree_free(&T);
         return ORC_ENOMEM;
@@ -264,6 +292,12 @@ int orc_tree_marginals(int K, int d, const long *off, const double *pts, const i
     free(phi);
     tree_free(&T);
     return ORC_OK;
+}
+
+int orc_tree_marginals(int K, int d, const long *off, const double *pts, const int *parent,
+                       double eta, const double *phi_cat, double *P)
+{
+    return orc_tree_marginals_ex(K, d, off, pts, parent, NULL, eta, phi_cat, P);
 }
 
 /* ------------------------------------------------------------------------ */

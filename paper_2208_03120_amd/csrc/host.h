@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <cstring>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -79,8 +80,9 @@ struct Extent {
 };
 
 // params.cpp
+// eta_hi > eta: the parameters must also serve kernels up to eta_hi (weighted edges)
 int resolve_params(int d, double eta, const Extent &ext, const mot_fastsum_params *fs,
-                   int64_t n_max, NfftParams *out);
+                   int64_t n_max, NfftParams *out, double eta_hi = 0.0);
 int build_box(int d, const Extent &ext, NfftParams *P);
 int resolve_trunc(int d, double eta, const Extent &ext, const mot_fastsum_params *fs,
                   double n_mean, TruncParams *out);
@@ -153,6 +155,10 @@ struct Schedule {
 struct mot_plan_s {
     int K = 0, d = 0, topology = 0, path = 0, precision = 0;
     double eta = 0;
+    // generalised barycenters (tree): edge weight of {parent[k], k} and free nodes
+    std::vector<double> edge_w;
+    std::vector<int> free_node;
+    std::map<double, float *> D_of_eta;  // NFFT multiplier per distinct eta / w
     hipStream_t stream = nullptr;
     bool own_stream = false;
     int device = 0;

@@ -9,6 +9,8 @@
 //              (the vector whose transposed kernel product gives gamma_c, eq. gamma_tree)
 //   up src:    v_k = phi^k * cp                             (beta_k = K^{(p,k)} v_k)
 //   marginal:  P_k = (phi^k * gamma_k) * cp               (Theorem 4.1), and |P_k - mu^k|
+//   free node (generalised barycenter, Sec. 6.2): phi^k = 1 instead of the update, no S
+//              term and no marginal error (mu^k is not given)
 // Every product vector also records max_i exponent(value) in the job's slot so the
 // product kernels can scale it into FP32 range without loss.
 // Per-item partial sums go to distinct slots (no floating-point atomics): reductions
@@ -57,6 +59,7 @@ __global__ __launch_bounds__(256) void node_kernel(const NodeJob *__restrict__ j
         const NodeJob &J = jobs[itm.x];
         const int op = J.op;
         const bool upd = op & 1, dsrc = op & 2, usrc = op & 4, root = op & 8, marg = op & 16;
+        const bool freen = op & 32;
         const int nch = J.nchild;
         const bool regs = nch <= kRegChildren;
         double s1 = 0.0, s2 = 0.0;
@@ -101,7 +104,10 @@ __global__ __launch_bounds__(256) void node_kernel(const NodeJob *__restrict__ j
             const double g = g_k[k];
             const double mu = mu_k[k];
             double ph = ph_k[k];
-            if (upd) {
+            if (upd && freen) {
+                gp(J.phi)[i] = 1.0;  // no marginal constraint: phi^k = 1 in every sweep
+                ph = 1.0;
+            } else if (upd) {
                 const double nv = mu / (g * cp);
                 if (mu > 0.0) {
                     s1 += mu * log(ph);
@@ -114,7 +120,7 @@ __global__ __launch_bounds__(256) void node_kernel(const NodeJob *__restrict__ j
             if (marg) {
                 const double P = (ph * g) * cp;
                 gp(J.marg_out)[i] = P;
-                s1 += fabs(P - mu);
+                if (!freen) s1 += fabs(P - mu);
             }
             if (usrc) {
                 const double v = ph * cp;

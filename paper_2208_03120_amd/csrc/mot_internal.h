@@ -104,7 +104,8 @@ struct ProdJob {
 // UP:   v_k = phi^k (.) prod_{t in C_k} beta_t (source of beta_k's product).
 struct NodeJob {
     int32_t op;          // bit 0: down update, bit 1: down sources, bit 2: up source,
-                         // bit 3: root (gamma = 1, extra S term), bit 4: marginal only
+                         // bit 3: root (gamma = 1, extra S term), bit 4: marginal only,
+                         // bit 5: free node (phi = 1, no S or error terms; Sec. 6.2)
     int32_t nchild;
     int64_t n;
     const double *mu;

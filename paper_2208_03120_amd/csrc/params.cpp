@@ -283,7 +283,7 @@ static double kb_err(int m, double sigma)
 static int tile_for(int m) { return 17 - 2 * m; }
 
 int resolve_params(int d, double eta, const Extent &ext, const mot_fastsum_params *fs,
-                   int64_t n_max, NfftParams *out)
+                   int64_t n_max, NfftParams *out, double eta_hi)
 {
     mot_fastsum_params F{};
     if (fs) F = *fs;
@@ -316,6 +316,7 @@ int resolve_params(int d, double eta, const Extent &ext, const mot_fastsum_param
             double ferr = 0.0;
             for (int M : M_list) {
                 ferr = d * fourier_err_1d(M, eta, tau, eb, p, ext.diag);
+                if (eta_hi > eta) ferr = std::max(ferr, d * fourier_err_1d(M, eta_hi, tau, eb, p, ext.diag));
                 if (F.M > 0 || ferr <= 0.5 * target) {
                     Mfound = M;
                     break;

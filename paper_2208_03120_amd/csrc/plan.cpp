@@ -481,7 +481,8 @@ int tree_build_schedule(mot_plan_s *P)
         const int items = (int)((base.n + kNodeItemElems - 1) / kNodeItemElems);
         // DOWN: update (+ root) + down sources (+ up source for leaves)
         NodeJob dn = base;
-        dn.op = 1 | (ch.empty() ? 0 : 2) | ((ch.empty() && k > 0) ? 4 : 0) | (k == 0 ? 8 : 0);
+        const int fr = (!P->free_node.empty() && P->free_node[k]) ? 32 : 0;
+        dn.op = 1 | (ch.empty() ? 0 : 2) | ((ch.empty() && k > 0) ? 4 : 0) | (k == 0 ? 8 : 0) | fr;
         dn.block0 = slot;
         slot += items;
         T->njobs[k] = dn;
@@ -498,7 +499,8 @@ int tree_build_schedule(mot_plan_s *P)
     T->n_down_partials = slot;
     for (int k = 0; k < K; ++k) {
         NodeJob mg = T->njobs[k];
-        mg.op = 16 | (P->children[k].empty() ? 0 : 2) | (k == 0 ? 8 : 0);
+        mg.op = 16 | (P->children[k].empty() ? 0 : 2) | (k == 0 ? 8 : 0) |
+                ((!P->free_node.empty() && P->free_node[k]) ? 32 : 0);
         mg.block0 = slot;
         T->marg_block0[k] = slot;
         slot += (int)((mg.n + kNodeItemElems - 1) / kNodeItemElems);
@@ -617,12 +619,16 @@ static int copy_in(const double *src, size_t count, int ptr_kind, std::vector<do
 }
 
 static int validate_common(int K, int d, const int64_t *n, double eta, const std::vector<double> &w,
-                           const std::vector<double> &pts, int64_t total)
+                           const std::vector<double> &pts, int64_t total, const std::vector<int> &free_node)
 {
     if (K < 2 || d < 1 || d > 3 || !(eta > 0.0) || !std::isfinite(eta)) return MOT_EINVAL;
     int64_t off = 0;
     for (int k = 0; k < K; ++k) {
         if (n[k] < 1 || n[k] > (int64_t)1 << 30) return MOT_EINVAL;
+        if (!free_node.empty() && free_node[k]) {  // weights of a free node are not read
+            off += n[k];
+            continue;
+        }
         double s = 0.0;
         for (int64_t i = 0; i < n[k]; ++i) {
             const double v = w[off + i];
@@ -722,6 +728,16 @@ static int bin_marginal(mot_plan_s *P, int k, const double *pts_orig_dev, void *
     return MOT_OK;
 }
 
+// eta of the kernel between marginals t and s: eta / w for a weighted tree edge
+// (Sec. 6.2), eta otherwise.
+static double pair_eta(const mot_plan_s *P, int t, int s)
+{
+    if (P->topology != MOT_TREE || P->edge_w.empty()) return P->eta;
+    if (t > 0 && P->parent[t] == s) return P->eta / P->edge_w[t];
+    if (s > 0 && P->parent[s] == t) return P->eta / P->edge_w[s];
+    return P->eta;
+}
+
 // Fill the product job j: out(target t) = K^{(t,s)} v(source s).
 int mot::make_prod_job(mot_plan_s *P, int t, int s, const double *v, int32_t *slot, double *out,
                        ProdJob *J, float *patches, bool alloc_buffers)
@@ -736,12 +752,12 @@ int mot::make_prod_job(mot_plan_s *P, int t, int s, const double *v, int32_t *sl
     Q.out = out;
     Q.ns = P->marg[s].n;
     Q.nt = P->marg[t].n;
-    Q.eta = P->eta;
+    Q.eta = pair_eta(P, t, s);
     for (int c = 0; c < 3; ++c) Q.ctr[c] = P->ext.ctr[c];
     // mixed direct sums: the expanded exponent cancels terms up to log2(e) r^2 / eta (r the
     // cloud's radius about its centre); above 8 it is formed in FP64
     const double half = 0.5 * P->ext.diag;
-    Q.diff = P->precision == MOT_PREC_MIXED && 1.4426950408889634 * half * half / P->eta > 8.0;
+    Q.diff = P->precision == MOT_PREC_MIXED && 1.4426950408889634 * half * half / Q.eta > 8.0;
     Q.src_pts = P->marg[s].pts;
     Q.tgt_pts = P->marg[t].pts;
     if (P->path == MOT_TRUNC) {
@@ -789,7 +805,10 @@ int mot::make_prod_job(mot_plan_s *P, int t, int s, const double *v, int32_t *sl
         Q.ntile[c] = N.ntile[c];
     }
     Q.W = N.W;
-    Q.D = P->D;
+    {
+        auto it = P->D_of_eta.find(Q.eta);
+        Q.D = it != P->D_of_eta.end() ? it->second : P->D;
+    }
     Q.twiddle = device_twiddle(N.n);
     int64_t pe = 1, cells = 1;
     for (int c = 0; c < P->d; ++c) {
@@ -838,12 +857,22 @@ int mot::setup_marginals(mot_plan_s *P, const std::vector<double> &pts_h, const 
     const int K = P->K, d = P->d;
     int64_t nmax = 0;
     for (int k = 0; k < K; ++k) nmax = std::max(nmax, P->n[k]);
+    // the kernels' eta: eta itself and eta / w of every weighted tree edge
+    std::vector<double> etas{P->eta};
+    for (size_t k = 1; k < P->edge_w.size(); ++k) etas.push_back(P->eta / P->edge_w[k]);
+    std::sort(etas.begin(), etas.end());
+    etas.erase(std::unique(etas.begin(), etas.end()), etas.end());
     if (P->path == MOT_NFFT) {
-        MOT_TRY(resolve_params(d, P->eta, P->ext, fs, nmax, &P->P));
-        std::vector<float> D;
-        build_multiplier(d, P->P, P->eta, D);
-        MOT_TRY(P->arena.get_n(D.size(), &P->D));
-        MOT_HIP(hipMemcpy(P->D, D.data(), D.size() * sizeof(float), hipMemcpyHostToDevice));
+        MOT_TRY(resolve_params(d, etas.front(), P->ext, fs, nmax, &P->P, etas.back()));
+        for (double e : etas) {
+            std::vector<float> D;
+            build_multiplier(d, P->P, e, D);
+            float *Dd = nullptr;
+            MOT_TRY(P->arena.get_n(D.size(), &Dd));
+            MOT_HIP(hipMemcpy(Dd, D.data(), D.size() * sizeof(float), hipMemcpyHostToDevice));
+            P->D_of_eta[e] = Dd;
+        }
+        P->D = P->D_of_eta[P->eta];
         if (!device_twiddle(P->P.n)) return MOT_EDEVICE;
         log_msg("NFFT params: M=%d n=%d m=%d p=%d tau=%.6g eps_B=%.6g T=%d box=%dx%dx%d est_err=%.3g",
                 P->P.M, P->P.n, P->P.m, P->P.p, P->P.tau, P->P.eps_B, P->P.T, P->P.L[0], P->P.L[1],
@@ -852,7 +881,7 @@ int mot::setup_marginals(mot_plan_s *P, const std::vector<double> &pts_h, const 
     if (P->path == MOT_TRUNC) {
         double nsum = 0.0;
         for (int k = 0; k < K; ++k) nsum += (double)P->n[k];
-        MOT_TRY(resolve_trunc(d, P->eta, P->ext, fs, nsum / K, &P->TP));
+        MOT_TRY(resolve_trunc(d, etas.back(), P->ext, fs, nsum / K, &P->TP));
         log_msg("truncation: eps=%.3g r_c=%.6g h=%.6g cells=%d^%d w=%d", P->TP.eps, P->TP.rc, P->TP.h,
                 P->TP.nc, d, P->TP.w);
     }
@@ -1073,10 +1102,11 @@ int mot_plan_destroy(mot_plan P)
     return MOT_OK;
 }
 
-int mot_plan_create(mot_plan *out, int32_t K, int32_t d, const int64_t *n, const double *points,
-                    const double *weights, int32_t topology, const int32_t *parent, double eta,
-                    int32_t path, int32_t precision, const mot_fastsum_params *fs, int32_t ptr_kind,
-                    void *stream, const mot_allocator *alloc)
+static int create_plan(mot_plan *out, int32_t K, int32_t d, const int64_t *n, const double *points,
+                       const double *weights, int32_t topology, const int32_t *parent,
+                       const mot_tree_options *opt, double eta, int32_t path, int32_t precision,
+                       const mot_fastsum_params *fs, int32_t ptr_kind, void *stream,
+                       const mot_allocator *alloc)
 {
     if (!out) return MOT_EINVAL;
     *out = nullptr;
@@ -1101,13 +1131,37 @@ int mot_plan_create(mot_plan *out, int32_t K, int32_t d, const int64_t *n, const
         if (n[k] < 1) return MOT_EINVAL;
         total += n[k];
     }
+    std::vector<double> edge_w;
+    std::vector<int> free_node;
+    if (opt) {
+        if (topology != MOT_TREE) return MOT_EINVAL;
+        if (opt->edge_weight) {
+            edge_w.assign(opt->edge_weight, opt->edge_weight + K);
+            edge_w[0] = 1.0;
+            for (int k = 1; k < K; ++k)
+                if (!(edge_w[k] > 0.0) || !std::isfinite(edge_w[k]) || !std::isfinite(eta / edge_w[k]))
+                    return MOT_EINVAL;
+        }
+        if (opt->free_node) {
+            free_node.assign(K, 0);
+            for (int k = 0; k < K; ++k) free_node[k] = opt->free_node[k] != 0;
+            if (free_node[0]) return MOT_EINVAL;  // the root's update fixes the common scale
+        }
+    }
     std::vector<double> pts_h, w_h;
     int rc = copy_in(points, (size_t)total * d, ptr_kind, pts_h);
     if (rc < 0) return rc;
     rc = copy_in(weights, (size_t)total, ptr_kind, w_h);
     if (rc < 0) return rc;
-    rc = validate_common(K, d, n, eta, w_h, pts_h, total);
+    rc = validate_common(K, d, n, eta, w_h, pts_h, total, free_node);
     if (rc < 0) return rc;
+    {  // free nodes carry no weights: zero them (no S term, mu is never divided)
+        int64_t o = 0;
+        for (int k = 0; k < K; ++k) {
+            if (!free_node.empty() && free_node[k]) std::fill(w_h.begin() + o, w_h.begin() + o + n[k], 0.0);
+            o += n[k];
+        }
+    }
 
     mot_plan_s *P = new mot_plan_s();
     P->K = K;
@@ -1116,6 +1170,8 @@ int mot_plan_create(mot_plan *out, int32_t K, int32_t d, const int64_t *n, const
     P->path = path;
     P->precision = precision;
     P->eta = eta;
+    P->edge_w = edge_w;
+    P->free_node = free_node;
     (void)hipGetDevice(&P->device);
     if (alloc && alloc->alloc && alloc->free) {
         P->arena.alloc = *alloc;
@@ -1146,6 +1202,24 @@ int mot_plan_create(mot_plan *out, int32_t K, int32_t d, const int64_t *n, const
     }
     *out = P;
     return MOT_OK;
+}
+
+int mot_plan_create(mot_plan *out, int32_t K, int32_t d, const int64_t *n, const double *points,
+                    const double *weights, int32_t topology, const int32_t *parent, double eta,
+                    int32_t path, int32_t precision, const mot_fastsum_params *fs, int32_t ptr_kind,
+                    void *stream, const mot_allocator *alloc)
+{
+    return create_plan(out, K, d, n, points, weights, topology, parent, nullptr, eta, path, precision, fs,
+                       ptr_kind, stream, alloc);
+}
+
+int mot_plan_create_tree(mot_plan *out, int32_t K, int32_t d, const int64_t *n, const double *points,
+                         const double *weights, const int32_t *parent, const mot_tree_options *opt,
+                         double eta, int32_t path, int32_t precision, const mot_fastsum_params *fs,
+                         int32_t ptr_kind, void *stream, const mot_allocator *alloc)
+{
+    return create_plan(out, K, d, n, points, weights, MOT_TREE, parent, opt, eta, path, precision, fs,
+                       ptr_kind, stream, alloc);
 }
 
 int mot_plan_get_info(mot_plan P, mot_plan_info *info)

@@ -37,6 +37,11 @@ class FastsumParams(ctypes.Structure):
                 ("target_rel_err", ctypes.c_double)]
 
 
+class TreeOptions(ctypes.Structure):
+    _fields_ = [("edge_weight", ctypes.POINTER(ctypes.c_double)),
+                ("free_node", ctypes.POINTER(ctypes.c_int32))]
+
+
 class PlanInfo(ctypes.Structure):
     _fields_ = [("K", ctypes.c_int32), ("d", ctypes.c_int32), ("topology", ctypes.c_int32),
                 ("path", ctypes.c_int32), ("precision", ctypes.c_int32),
@@ -83,7 +88,7 @@ class Result(ctypes.Structure):
 
 
 # names declared in include/mot.h, used by the ABI export test
-EXPORTED = ["mot_plan_create", "mot_sinkhorn", "mot_get_S_history", "mot_marginals",
+EXPORTED = ["mot_plan_create", "mot_plan_create_tree", "mot_sinkhorn", "mot_get_S_history", "mot_marginals",
             "mot_get_scalings", "mot_set_scalings", "mot_apply_kernel", "mot_plan_get_info",
             "mot_plan_footprint", "mot_plan_destroy", "mot_strerror", "mot_bin_points",
             "mot_plan_profile",
@@ -115,6 +120,10 @@ def _load():
                                            ctypes.c_int32, _ip, ctypes.c_double, ctypes.c_int32,
                                            ctypes.c_int32, _P(FastsumParams), ctypes.c_int32, _vp,
                                            _P(Allocator)]),
+        "mot_plan_create_tree": (ctypes.c_int, [_P(_vp), ctypes.c_int32, ctypes.c_int32, _lp, _dp, _dp,
+                                                _ip, _P(TreeOptions), ctypes.c_double, ctypes.c_int32,
+                                                ctypes.c_int32, _P(FastsumParams), ctypes.c_int32, _vp,
+                                                _P(Allocator)]),
         "mot_sinkhorn": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
                                         ctypes.c_int32, _ip, _dp, _dp]),
         "mot_get_S_history": (ctypes.c_int, [_vp, _dp, ctypes.c_int32]),
@@ -181,7 +190,9 @@ def _concat(points, weights):
     d = int(points[0].shape[1])
     sizes = np.array([p.shape[0] for p in points], dtype=np.int64)
     pts = _f64(np.concatenate([np.asarray(p, dtype=np.float64).reshape(-1, d) for p in points]))
-    w = _f64(np.concatenate([np.asarray(x, dtype=np.float64) for x in weights]))
+    # None: a free node's weights (not read by the library)
+    w = _f64(np.concatenate([np.zeros(len(p)) if x is None else np.asarray(x, dtype=np.float64)
+                             for p, x in zip(points, weights)]))
     return d, sizes, pts, w
 
 
@@ -209,7 +220,9 @@ class Plan:
     """One multi-marginal OT problem resident on the GPU (mot_plan_create)."""
 
     def __init__(self, points, weights, topology=TREE, parent=None, eta=0.1, path=NFFT,
-                 precision=None, fastsum=None, stream=None):
+                 precision=None, fastsum=None, stream=None, edge_weight=None, free=None):
+        """edge_weight ([K], entry k for the edge {parent[k], k}) and free ([K] booleans)
+        pose the generalised barycenter problem of Sec. 6.2 (mot_plan_create_tree)."""
         if precision is None:
             precision = PREC_MIXED if path != DENSE else PREC_BF16
         d, sizes, pts, w = _concat(points, weights)
@@ -222,10 +235,21 @@ class Plan:
             par = np.ascontiguousarray(parent, dtype=np.int32)
         fs = ctypes.byref(fastsum) if fastsum is not None else None
         st = stream if stream is not None else current_stream()
-        rc = _lib.mot_plan_create(ctypes.byref(self._h), self.K, d, sizes.ctypes.data_as(_lp),
-                                  _dptr(pts), _dptr(w), topology,
-                                  par.ctypes.data_as(_ip) if par is not None else None,
-                                  float(eta), path, precision, fs, HOST, st, None)
+        if edge_weight is None and free is None:
+            rc = _lib.mot_plan_create(ctypes.byref(self._h), self.K, d, sizes.ctypes.data_as(_lp),
+                                      _dptr(pts), _dptr(w), topology,
+                                      par.ctypes.data_as(_ip) if par is not None else None,
+                                      float(eta), path, precision, fs, HOST, st, None)
+        else:
+            if topology != TREE:
+                raise ValueError("edge weights and free nodes are tree options")
+            ew = None if edge_weight is None else _f64(edge_weight)
+            fr = None if free is None else np.ascontiguousarray(np.asarray(free, dtype=bool), dtype=np.int32)
+            opt = TreeOptions(_dptr(ew) if ew is not None else None,
+                              fr.ctypes.data_as(_ip) if fr is not None else None)
+            rc = _lib.mot_plan_create_tree(ctypes.byref(self._h), self.K, d, sizes.ctypes.data_as(_lp),
+                                           _dptr(pts), _dptr(w), par.ctypes.data_as(_ip), ctypes.byref(opt),
+                                           float(eta), path, precision, fs, HOST, st, None)
         _check(rc, "mot_plan_create")
 
     def close(self):

@@ -135,6 +135,64 @@ def star_small_eta(seed=6, N=100_000, eta=1e-3):
                          meta={"name": "star_K10_N%d_d3_eta%g" % (N, eta), "sweeps": 200})
 
 
+def shape_points(rng, n, shape, half_width=0.25):
+    """n points drawn uniformly from a planar shape inside [-half_width, half_width)^2:
+    'disk', 'ring' (annulus), 'square' (a square's frame) or 'blobs' (two discs)."""
+    h = half_width
+    out = np.empty((0, 2))
+    while out.shape[0] < n:
+        p = rng.uniform(-h, h, size=(4 * n, 2))
+        r = np.hypot(p[:, 0], p[:, 1])
+        if shape == "disk":
+            keep = r < 0.8 * h
+        elif shape == "ring":
+            keep = (r > 0.5 * h) & (r < 0.8 * h)
+        elif shape == "square":
+            m = np.maximum(np.abs(p[:, 0]), np.abs(p[:, 1]))
+            keep = (m > 0.55 * h) & (m < 0.8 * h)
+        elif shape == "blobs":
+            keep = (np.hypot(p[:, 0] - 0.4 * h, p[:, 1] - 0.4 * h) < 0.35 * h) | \
+                   (np.hypot(p[:, 0] + 0.4 * h, p[:, 1] + 0.4 * h) < 0.35 * h)
+        else:
+            raise ValueError(shape)
+        out = np.concatenate([out, p[keep]])
+    return out[:n]
+
+
+H_TREE_PARENT = np.array([-1, 0, 1, 1, 2, 4, 4], dtype=np.int32)
+H_TREE_LEAVES = (0, 3, 5, 6)
+
+
+def h_tree_barycenter(seed=7, N=2500, eta=5e-3, leaf_weight=0.25):
+    """Generalised barycenter on the H-shaped tree of Sec. 6.2 (K = 7): leaves 0, 3, 5, 6
+    carry given measures with uniform weights 1/N on synthetic planar shapes (disk,
+    ring, square frame, two discs: stand-ins for the paper's dithered images); the
+    inner nodes 1, 2, 4 are free, supported on the union of the leaves' points.  Edge
+    {p, k} has weight leaf_weight when it touches a leaf and 1 otherwise.  Returns
+    (Instance, edge weights [K], free flags [K])."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    leaves = {k: shape_points(rng, N, s) for k, s in zip(H_TREE_LEAVES, ("disk", "ring", "square", "blobs"))}
+    union = np.concatenate([leaves[k] for k in H_TREE_LEAVES])
+    K = len(H_TREE_PARENT)
+    pts, wts, free = [], [], []
+    for k in range(K):
+        if k in leaves:
+            pts.append(leaves[k])
+            wts.append(np.full(N, 1.0 / N))
+            free.append(False)
+        else:
+            pts.append(union.copy())
+            wts.append(None)
+            free.append(True)
+    ew = np.ones(K)
+    for k in range(1, K):
+        if (k in leaves) != (int(H_TREE_PARENT[k]) in leaves):
+            ew[k] = leaf_weight
+    inst = Instance(pts, wts, TREE, H_TREE_PARENT.copy(), float(eta),
+                    {"name": "h_tree_barycenter_N%d" % N, "sweeps": 150})
+    return inst, ew, np.array(free)
+
+
 def cycle(seed=3, N=4000):
     """Cycle K=5, N points in d=2, eta=0.1, 100 sweeps."""
     rng = np.random.Generator(np.random.PCG64(seed))

@@ -428,3 +428,88 @@ def test_truncated_sum_error_bound_and_monotone_radius():
         assert np.all(gap >= -1e-15 * full)
         assert np.all(gap <= math.exp(-rc * rc / eta) * v.sum() * (1 + 1e-12))
         prev = t
+
+
+# ---- generalised barycenters on trees (Sec. 6.2) -------------------------------------------
+
+def _dense_kernel(xa, xb, eta):
+    d2 = np.sum((xa[:, None, :] - xb[None, :, :]) ** 2, axis=-1)
+    return np.exp(-d2 / eta)
+
+
+def test_barycenter_chain_is_textbook_sinkhorn_on_the_composed_kernel():
+    """Chain 0 - 1 - 2 with node 1 free and edge weights w1, w2: summing the free index
+    out gives the two-marginal problem with kernel K' = K_01(eta / w1) K_12(eta / w2), and
+    Algorithm 2 with the barycenter update is textbook Sinkhorn on it, iterate for iterate:
+    a = mu0 / (K' b), b = mu2 / (K'^T a).  S^(r) is its dual eta (mu0 log a + mu2 log b -
+    a^T K' b) at the previous iterate."""
+    r = rng(41)
+    pts = [r.uniform(-0.25, 0.25, (n, 2)) for n in (9, 14, 11)]
+    mu = [W.uniform_weights(r, 9), None, W.uniform_weights(r, 11)]
+    w1, w2, eta = 0.25, 0.6, 0.02
+    Kp = _dense_kernel(pts[0], pts[1], eta / w1) @ _dense_kernel(pts[1], pts[2], eta / w2)
+    a, b = np.ones(9), np.ones(11)
+    for sweeps in range(1, 6):
+        a_old, b_old = a, b
+        a = mu[0] / (Kp @ b)
+        b = mu[2] / (Kp.T @ a)
+        phi, S, _, _ = oracle.tree_sinkhorn(pts, mu, [-1, 0, 1], eta, sweeps,
+                                            edge_weight=[0.0, w1, w2], free=[False, True, False])
+        np.testing.assert_allclose(phi[0], a, rtol=1e-12)
+        np.testing.assert_allclose(phi[2], b, rtol=1e-12)
+        np.testing.assert_array_equal(phi[1], np.ones(14))
+        dual = eta * (mu[0] @ np.log(a_old) + mu[2] @ np.log(b_old) - a_old @ Kp @ b_old)
+        assert abs(S[-1] - dual) < 1e-13 * max(1.0, abs(dual))
+
+
+def test_barycenter_free_root_is_rejected():
+    """The root's update fixes the common scale of the scalings; a free root is refused."""
+    r = rng(42)
+    pts = [r.uniform(-0.25, 0.25, (n, 2)) for n in (5, 4, 6)]
+    mu = [None, W.uniform_weights(r, 4), W.uniform_weights(r, 6)]
+    _, _, _, rc = oracle.tree_sinkhorn(pts, mu, [-1, 0, 0], 0.1, 3, free=[True, False, False])
+    assert rc == oracle.EINVAL
+
+
+@pytest.mark.parametrize("parent,free", [([-1, 0, 1, 1], [False, True, False, False]),
+                                         ([-1, 0, 0, 0], [False, False, True, False]),
+                                         ([-1, 0, 1, 2], [False, True, True, False])])
+def test_barycenter_fixed_point_matches_brute_force(parent, free):
+    """Weighted edge costs and free nodes on the full tensor: Algorithm 1 updating only the
+    constrained marginals and the oracle's Algorithm 2 reach the same plan; the
+    constrained marginals equal mu and primal = dual (S over the constrained marginals)."""
+    r = rng(43)
+    K = len(parent)
+    pts = [r.uniform(-0.25, 0.25, (n, 2)) for n in (6, 7, 5, 6)[:K]]
+    mu = [None if free[k] else W.uniform_weights(r, len(pts[k])) for k in range(K)]
+    ew = [0.0] + [float(x) for x in r.uniform(0.25, 1.0, K - 1)]
+    eta = 0.1
+    edges = brute.tree_edges(parent)
+    C = brute.cost_tensor(pts, edges, [ew[k] for _, k in edges])
+    Kt = brute.kernel_tensor(C, eta)
+    phi, S, _, _ = oracle.tree_sinkhorn(pts, mu, parent, eta, 600, edge_weight=ew, free=free)
+    Pi = Kt * brute.outer(phi)
+    for k in range(K):
+        if not free[k]:
+            np.testing.assert_allclose(brute.marginal(Pi, k), mu[k], rtol=0, atol=1e-13)
+    mus = [np.zeros(len(p)) if m is None else m for p, m in zip(pts, mu)]
+    cons = [not f for f in free]
+    ref = brute.algorithm1(Kt, mus, 600, constrained=cons)[-1]
+    np.testing.assert_allclose(Pi, Kt * brute.outer(ref), rtol=1e-9, atol=1e-16)
+    primal = brute.primal_value(Pi, C, eta)
+    dual = brute.sinkhorn_S(Kt, mus, phi, eta, constrained=cons)
+    assert abs(primal - dual) < 1e-11 * max(1.0, abs(primal))
+    # the barycenters are the free marginals of the plan, which the marginal pass gives
+    P = oracle.tree_marginals(pts, parent, eta, phi, edge_weight=ew)
+    for k in range(K):
+        np.testing.assert_allclose(P[k], brute.marginal(Pi, k), rtol=1e-12)
+
+
+def test_unit_edge_weights_and_no_free_nodes_change_nothing():
+    inst = tiny(44, 4, 12, 2, W.TREE, 0.1, parent=np.array([-1, 0, 0, 1], np.int32))
+    a = oracle.tree_sinkhorn(inst.points, inst.weights, inst.parent, inst.eta, 7)
+    b = oracle.tree_sinkhorn(inst.points, inst.weights, inst.parent, inst.eta, 7,
+                             edge_weight=[0.0, 1.0, 1.0, 1.0], free=[False] * 4)
+    for x, y in zip(a[0], b[0]):
+        np.testing.assert_array_equal(x, y)
+    np.testing.assert_array_equal(a[1], b[1])
