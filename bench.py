@@ -125,15 +125,19 @@ def bench_error_vs_M(mot, W, etas=(0.02, 0.05, 0.1, 0.2), Ms=(8, 12, 16, 24, 32,
     """Error of one NFFT product against the FP64 direct sum as the half bandwidth M
     grows (d = 2, two marginals of 2000 and 1800 uniform points, tau and eps_B and m
     from the autotuner, grid n = the smallest power of two >= 4M): the measured maximum
-    relative error over sampled targets next to the autotuner's estimate."""
-    import oracle
+    relative error over sampled targets next to the autotuner's estimate.  The
+    reference is the library's FP64 direct product (equal to the definition to 1e-13 in
+    the parity tests)."""
     rows = []
     r = np.random.Generator(np.random.PCG64(8))
     for eta in etas:
         inst = W.make_instance(r, 2, [2000, 1800], 2, W.TREE, eta, parent=[-1, 0])
         v = r.uniform(0.5, 1.5, 1800)
         idx = r.choice(2000, samples, replace=False)
-        want = oracle.kernel_apply(inst.points[0][idx], inst.points[1], v, eta)
+        ref = mot.Plan(inst.points, inst.weights, W.TREE, inst.parent, eta, path=mot.DIRECT,
+                       precision=mot.PREC_FP64)
+        want = ref.apply(0, 1, v)[idx]
+        ref.close()
         for M in Ms:
             n = 16
             while n < 4 * M:
@@ -265,6 +269,37 @@ def bench_barycenter(mot, W, N=5000, sweeps=150, eta=5e-3):
     res["barycenter_l1_nfft_vs_direct"] = float(max(np.sum(np.abs(margs["nfft"][k] - margs["direct"][k]))
                                                     for k in range(inst.K) if free[k]))
     res["speedup_nfft_vs_direct"] = res["nfft"]["sweeps_per_s"] / res["direct"]["sweeps_per_s"]
+    return res
+
+
+def bench_euler_flow(mot, W, N=400, K=6, eta=0.05, sweeps=50):
+    """Generalised Euler flows (Sec. 6.3): N uniform points on [0, 1], K time steps, eta =
+    0.05, 50 sweeps, sigma(x) = 1 - x and the tent map.  Sweeps/s of the row-by-row NFFT
+    and dense split-BF16 circle paths, the pair marginals Pi_{1,k}, k = 2..K, of each path
+    (with the time for all of them), and their largest difference between the paths
+    relative to each matrix's largest entry."""
+    import torch
+    res = []
+    for sig in ("reverse", "tent"):
+        inst, closing = W.euler_flow(seed=8, N=N, K=K, eta=eta, sigma=sig)
+        row = {"workload": "Euler flow, sigma=%s, K=%d, N=%d on [0,1], eta=%g" % (sig, K, N, eta),
+               "sweeps": sweeps}
+        pairs = {}
+        for name, path, prec in [("nfft", mot.NFFT, mot.PREC_MIXED), ("dense_bf16x3", mot.DENSE, mot.PREC_BF16X3)]:
+            plan = mot.Plan(inst.points, inst.weights, W.CIRCLE, None, eta, path=path, precision=prec,
+                            closing_points=closing)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            plan.sinkhorn(sweeps)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            pairs[name] = [plan.pair_marginal(k) for k in range(1, K)]
+            t2 = time.perf_counter()
+            row[name] = {"sweeps_per_s": sweeps / (t1 - t0), "ms_pair_marginals": (t2 - t1) * 1e3}
+            plan.close()
+        row["pair_marginal_rel_diff_nfft_vs_dense"] = max(
+            float(np.max(np.abs(a - b)) / np.max(np.abs(b))) for a, b in zip(pairs["nfft"], pairs["dense_bf16x3"]))
+        res.append(row)
     return res
 
 
@@ -565,7 +600,7 @@ def main():
     if not args.no_extras:
         for key, fn in [("circle", bench_circle), ("batched", bench_batched), ("serving", bench_serving),
                         ("error_vs_M", bench_error_vs_M), ("truncated", bench_truncated),
-                        ("barycenter", bench_barycenter)]:
+                        ("barycenter", bench_barycenter), ("euler_flow", bench_euler_flow)]:
             try:
                 out[key] = fn(mot, W)
             except Exception as e:  # the headline measurement stands on its own

@@ -172,6 +172,32 @@ int mot_plan_create_tree(mot_plan *out, int32_t K, int32_t d, const int64_t *n, 
                          double eta, int32_t path, int32_t precision, const mot_fastsum_params *fs,
                          int32_t ptr_kind, void *stream, const mot_allocator *alloc);
 
+/* ---- generalised Euler flows (Sec. 6.3) ---------------------------------------------
+ * A circle whose closing edge {K, 1} compares x^K with sigma(x^1) instead of x^1: the
+ * cost |x^K_{i_K} - sigma(x^1_{i_1})|^2 + sum_k |x^{k+1} - x^k|^2.  closing_points
+ * (n_0 x d, ptr_kind, copied) are the mapped points sigma(x^1_i) in marginal 0's order;
+ * NULL gives the plain circle.  The closing edge enters Algorithm 3 only through the
+ * constant matrix beta_K = K^{(K,1)}, which is built from them.  Other arguments as for
+ * mot_plan_create (circle). */
+int mot_plan_create_circle(mot_plan *out, int32_t K, int32_t d, const int64_t *n, const double *points,
+                           const double *weights, const double *closing_points, double eta, int32_t path,
+                           int32_t precision, const mot_fastsum_params *fs, int32_t ptr_kind, void *stream,
+                           const mot_allocator *alloc);
+
+/* Pair marginal at the current scaling vectors: the sum of K (.) Phi over every index
+ * but two.  Circle: Pi_{1,k} of Sec. 6.3 (marginals 0 and k, 1 <= k < K),
+ *   Pi[i][j] = phi^1_i lambda^{(1,k)}[i][j] alpha^{(k,1)}[j][i] phi^k_j
+ * (the matrices of Theorem 4.3, recomputed at the current phi).  Tree: the edge
+ * {parent[k], k} (1 <= k < K),
+ *   Pi[i][j] = (phi^p gamma_p prod_{t in C_p, t != k} beta_t)_i K^{(p,k)}[i][j]
+ *              (phi^k prod_{t in C_k} beta_t)_j
+ * after a consistent pass as in mot_marginals.  out: n_a x n_k doubles, row-major, rows
+ * = the points of marginal a (0 for the circle, parent[k] for the tree) and columns =
+ * those of marginal k, both in the original order (ptr_kind).  The matrix is formed on
+ * the device in FP64 from the plan's factors (FP32 with power-of-two row scales on the
+ * dense circle path). */
+int mot_pair_marginal(mot_plan plan, int32_t k, double *out, int32_t ptr_kind);
+
 /* Run Sinkhorn sweeps: Algorithm 2 (tree) or Algorithm 3 (circle).  One sweep
  * updates every scaling vector once and recomputes the messages; it costs
  * 2(K-1) kernel products (tree) or 2(K-2) matrix products (circle).

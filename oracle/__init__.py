@@ -76,6 +76,19 @@ def _load():
                                             ctypes.c_double, ctypes.c_int, ctypes.c_double,
                                             dp, dp, ip]
         lib.orc_circle_sinkhorn.restype = ctypes.c_int
+        lib.orc_circle_sinkhorn_ex.argtypes = [ctypes.c_int, ctypes.c_int, lp, dp, dp, dp,
+                                               ctypes.c_double, ctypes.c_int, ctypes.c_double,
+                                               dp, dp, ip]
+        lib.orc_circle_sinkhorn_ex.restype = ctypes.c_int
+        lib.orc_circle_marginals_ex.argtypes = [ctypes.c_int, ctypes.c_int, lp, dp, dp,
+                                                ctypes.c_double, dp, dp]
+        lib.orc_circle_marginals_ex.restype = ctypes.c_int
+        lib.orc_circle_pair_marginal.argtypes = [ctypes.c_int, ctypes.c_int, lp, dp, dp,
+                                                 ctypes.c_double, dp, ctypes.c_int, dp]
+        lib.orc_circle_pair_marginal.restype = ctypes.c_int
+        lib.orc_tree_pair_marginal.argtypes = [ctypes.c_int, ctypes.c_int, lp, dp, ip, dp,
+                                               ctypes.c_double, dp, ctypes.c_int, dp]
+        lib.orc_tree_pair_marginal.restype = ctypes.c_int
         lib.orc_circle_marginals.argtypes = [ctypes.c_int, ctypes.c_int, lp, dp,
                                              ctypes.c_double, dp, dp]
         lib.orc_circle_marginals.restype = ctypes.c_int
@@ -193,8 +206,18 @@ def tree_marginals(points, parent, eta, phi, edge_weight=None):
     return _split(P, off)
 
 
-def circle_sinkhorn(points, weights, eta, sweeps, delta=0.0, phi0=None):
-    """Algorithm 3.  Returns (phi list, S history, sweeps done, status)."""
+def _closing(closing, n0, d):
+    if closing is None:
+        return None
+    c = np.ascontiguousarray(np.asarray(closing, dtype=np.float64).reshape(n0, d))
+    return c
+
+
+def circle_sinkhorn(points, weights, eta, sweeps, delta=0.0, phi0=None, closing=None):
+    """Algorithm 3.  Returns (phi list, S history, sweeps done, status).
+
+    ``closing`` (n_0 x d): the points sigma(x^1) marginal 0 takes on the closing edge
+    {K, 1} (generalised Euler flows, Sec. 6.3); None = x^1 itself."""
     lib = _load()
     K = len(points)
     d, off, pts, mu = _cat(points, weights)
@@ -202,21 +225,55 @@ def circle_sinkhorn(points, weights, eta, sweeps, delta=0.0, phi0=None):
     phi = np.ascontiguousarray(phi)
     S = np.zeros(max(sweeps, 1))
     done = ctypes.c_int(0)
-    rc = lib.orc_circle_sinkhorn(K, d, _l(off), _d(pts), _d(mu), float(eta), int(sweeps),
-                                 float(delta), _d(phi), _d(S), ctypes.byref(done))
+    cl = _closing(closing, off[1], d)
+    rc = lib.orc_circle_sinkhorn_ex(K, d, _l(off), _d(pts), _d(cl) if cl is not None else None, _d(mu),
+                                    float(eta), int(sweeps), float(delta), _d(phi), _d(S),
+                                    ctypes.byref(done))
     return _split(phi, off), S[:done.value].copy(), done.value, rc
 
 
-def circle_marginals(points, eta, phi):
+def circle_marginals(points, eta, phi, closing=None):
     """P_k(K (.) Phi) of Theorem 4.3 at fixed phi."""
     lib = _load()
     K = len(points)
     d, off, pts, _ = _cat(points)
     ph = np.ascontiguousarray(np.concatenate(phi), dtype=np.float64)
     P = np.empty(off[-1])
-    rc = lib.orc_circle_marginals(K, d, _l(off), _d(pts), float(eta), _d(ph), _d(P))
+    cl = _closing(closing, off[1], d)
+    rc = lib.orc_circle_marginals_ex(K, d, _l(off), _d(pts), _d(cl) if cl is not None else None,
+                                     float(eta), _d(ph), _d(P))
     assert rc == OK, rc
     return _split(P, off)
+
+
+def circle_pair_marginal(points, eta, phi, k, closing=None):
+    """Pi_{1,k} of the circle (Sec. 6.3) at fixed phi, n_0 x n_k (k = 1..K-1, 0-based)."""
+    lib = _load()
+    K = len(points)
+    d, off, pts, _ = _cat(points)
+    ph = np.ascontiguousarray(np.concatenate(phi), dtype=np.float64)
+    out = np.empty((off[1], off[k + 1] - off[k]))
+    cl = _closing(closing, off[1], d)
+    rc = lib.orc_circle_pair_marginal(K, d, _l(off), _d(pts), _d(cl) if cl is not None else None,
+                                      float(eta), _d(ph), int(k), _d(out))
+    assert rc == OK, rc
+    return out
+
+
+def tree_pair_marginal(points, parent, eta, phi, k, edge_weight=None):
+    """Pi_{p(k),k} of a tree edge at fixed phi, n_{p(k)} x n_k."""
+    lib = _load()
+    K = len(points)
+    d, off, pts, _ = _cat(points)
+    par = np.ascontiguousarray(parent, dtype=np.int32)
+    ph = np.ascontiguousarray(np.concatenate(phi), dtype=np.float64)
+    p = int(par[k])
+    out = np.empty((off[p + 1] - off[p], off[k + 1] - off[k]))
+    ew = None if edge_weight is None else np.ascontiguousarray(edge_weight, dtype=np.float64)
+    rc = lib.orc_tree_pair_marginal(K, d, _l(off), _d(pts), _i(par), _d(ew) if ew is not None else None,
+                                    float(eta), _d(ph), int(k), _d(out))
+    assert rc == OK, rc
+    return out
 
 
 def sinkhorn_function(weights, phi, total_mass, eta):

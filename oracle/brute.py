@@ -18,14 +18,19 @@ def circle_edges(K):
     return [(k, (k + 1) % K) for k in range(K)]
 
 
-def cost_tensor(points, edges, edge_weights=None):
+def cost_tensor(points, edges, edge_weights=None, closing=None):
     """C_i = sum_{(a,b) in edges} w_(a,b) |x^a_{i_a} - x^b_{i_b}|^2, eq. (cost_sparse), with
-    the edge weights of eq. (cost_function_barycenter_tree) (default 1)."""
+    the edge weights of eq. (cost_function_barycenter_tree) (default 1).  ``closing``:
+    the Euler-flow cost of Sec. 6.3, where the edge between the last marginal and marginal
+    0 compares x^K with sigma(x^1) = closing[i_1]."""
     K = len(points)
     shape = tuple(p.shape[0] for p in points)
     C = np.zeros(shape)
     for e, (a, b) in enumerate(edges):
-        D = np.sum((points[a][:, None, :] - points[b][None, :, :]) ** 2, axis=-1)
+        xa, xb = points[a], points[b]
+        if closing is not None and {a, b} == {K - 1, 0}:
+            xa, xb = (closing, xb) if a == 0 else (xa, closing)
+        D = np.sum((xa[:, None, :] - xb[None, :, :]) ** 2, axis=-1)
         if edge_weights is not None:
             D = edge_weights[e] * D
         idx = [None] * K
@@ -46,6 +51,12 @@ def kernel_tensor(C, eta):
 def marginal(T, k):
     """P_k(T): sum over every index except the k-th, eq. (Pk)."""
     axes = tuple(a for a in range(T.ndim) if a != k)
+    return T.sum(axis=axes)
+
+
+def pair_marginal(T, a, b):
+    """The sum of T over every index except the a-th and b-th (a < b), an n_a x n_b matrix."""
+    axes = tuple(x for x in range(T.ndim) if x not in (a, b))
     return T.sum(axis=axes)
 
 

@@ -312,6 +312,8 @@ typedef struct {
     double **beta;  /* beta[k] = alpha^{(k,1)}, n_k x n_1, k = 1..K-1 (0-based) */
     double *gam;    /* current gamma_k = lambda^{(1,k)}, n_1 x n_k             */
     double *gam_next;
+    const double *closing; /* NULL or n_1 x d: the points sigma(x^1) that marginal 1 takes
+                              on the closing edge {K, 1} (generalised Euler flows, Sec. 6.3) */
 } circ_t;
 
 static long cn(const circ_t *C, int k) { return C->off[k + 1] - C->off[k]; }
@@ -411,7 +413,9 @@ static int circ_alloc(circ_t *C)
         int k1 = (k + 1) % C->K;
         C->Kedge[k] = (double *)malloc((size_t)(cn(C, k) * cn(C, k1)) * sizeof(double));
         if (!C->Kedge[k]) return ORC_ENOMEM;
-        kernel_matrix(C->d, cn(C, k), cpts(C, k), cn(C, k1), cpts(C, k1), C->eta, C->Kedge[k]);
+        /* the closing edge compares x^K with sigma(x^1) when a map is given */
+        const double *xb = (k1 == 0 && C->closing) ? C->closing : cpts(C, k1);
+        kernel_matrix(C->d, cn(C, k), cpts(C, k), cn(C, k1), xb, C->eta, C->Kedge[k]);
         if (k >= 1) {
             C->beta[k] = (double *)malloc((size_t)(cn(C, k) * n1) * sizeof(double));
             if (!C->beta[k]) return ORC_ENOMEM;
@@ -446,12 +450,12 @@ static void circ_gamma_first(circ_t *C)
 }
 
 /* Sinkhorn for circle structure, Algorithm 3 (same stopping rule as the tree). */
-int orc_circle_sinkhorn(int K, int d, const long *off, const double *pts, const double *mu,
-                        double eta, int max_sweeps, double delta, double *phi_cat,
-                        double *S_hist, int *sweeps_done)
+int orc_circle_sinkhorn_ex(int K, int d, const long *off, const double *pts, const double *closing,
+                           const double *mu, double eta, int max_sweeps, double delta, double *phi_cat,
+                           double *S_hist, int *sweeps_done)
 {
     if (K < 3 || eta <= 0.0 || d < 1) return ORC_EINVAL;
-    circ_t C = {K, d, off, pts, eta, NULL, NULL, NULL, NULL};
+    circ_t C = {K, d, off, pts, eta, NULL, NULL, NULL, NULL, closing};
     int rc = circ_alloc(&C);
     double **phi = (double **)malloc((size_t)K * sizeof(double *));
     double *phi_old = (double *)malloc((size_t)off[K] * sizeof(double));
@@ -522,11 +526,11 @@ int orc_circle_sinkhorn(int K, int d, const long *off, const double *pts, const 
 /* Marginals at fixed phi, Theorem 4.3:
  *   P_1 = phi^1 (.) <K^{(1,2)}, (phi^2 (.) alpha^{(2,1)})^T>,
  *   P_k = phi^k (.) <alpha^{(k,1)}, (phi^1 (.) lambda^{(1,k)})^T>. */
-int orc_circle_marginals(int K, int d, const long *off, const double *pts, double eta,
-                         const double *phi_cat, double *P)
+int orc_circle_marginals_ex(int K, int d, const long *off, const double *pts, const double *closing,
+                            double eta, const double *phi_cat, double *P)
 {
     if (K < 3 || eta <= 0.0) return ORC_EINVAL;
-    circ_t C = {K, d, off, pts, eta, NULL, NULL, NULL, NULL};
+    circ_t C = {K, d, off, pts, eta, NULL, NULL, NULL, NULL, closing};
     long nmax = 0;
     for (int k = 0; k < K; ++k)
         if (cn(&C, k) > nmax) nmax = cn(&C, k);
@@ -555,6 +559,89 @@ int orc_circle_marginals(int K, int d, const long *off, const double *pts, doubl
     circ_free(&C);
     free(den);
     free(phi);
+    return ORC_OK;
+}
+
+int orc_circle_sinkhorn(int K, int d, const long *off, const double *pts, const double *mu,
+                        double eta, int max_sweeps, double delta, double *phi_cat,
+                        double *S_hist, int *sweeps_done)
+{
+    return orc_circle_sinkhorn_ex(K, d, off, pts, NULL, mu, eta, max_sweeps, delta, phi_cat, S_hist,
+                                  sweeps_done);
+}
+
+int orc_circle_marginals(int K, int d, const long *off, const double *pts, double eta,
+                         const double *phi_cat, double *P)
+{
+    return orc_circle_marginals_ex(K, d, off, pts, NULL, eta, phi_cat, P);
+}
+
+/* Pair marginal Pi_{1,k} of the circle at fixed phi (Sec. 6.3): the sum of K (.) Phi over
+ * every index but i_1 and i_k.  Summing the circle's chain on both sides of the pair,
+ *   Pi_{1,k}[i][j] = phi^1_i lambda^{(1,k)}[i][j] alpha^{(k,1)}[j][i] phi^k_j,
+ * with lambda^{(1,2)} = K^{(1,2)} (Theorem 4.3's matrices; out is n_1 x n_k row-major,
+ * k = 2..K in the paper's numbering, 1..K-1 here). */
+int orc_circle_pair_marginal(int K, int d, const long *off, const double *pts, const double *closing,
+                             double eta, const double *phi_cat, int k, double *out)
+{
+    if (K < 3 || eta <= 0.0 || k < 1 || k >= K) return ORC_EINVAL;
+    circ_t C = {K, d, off, pts, eta, NULL, NULL, NULL, NULL, closing};
+    const double **phi = (const double **)malloc((size_t)K * sizeof(double *));
+    if (circ_alloc(&C) != ORC_OK || !phi) {
+        circ_free(&C);
+        free(phi);
+        return ORC_ENOMEM;
+    }
+    for (int q = 0; q < K; ++q) phi[q] = phi_cat + off[q];
+    for (int q = K - 1; q >= 1; --q) circ_beta(&C, phi, q);
+    circ_gamma_first(&C);
+    for (int q = 2; q <= k; ++q) {
+        circ_gamma_step(&C, phi, q);
+        circ_swap_gamma(&C);
+    }
+    const long n1 = cn(&C, 0), nk = cn(&C, k);
+    for (long i = 0; i < n1; ++i)
+        for (long j = 0; j < nk; ++j)
+            out[i * nk + j] = ((phi[0][i] * C.gam[i * nk + j]) * C.beta[k][j * n1 + i]) * phi[k][j];
+    circ_free(&C);
+    free(phi);
+    return ORC_OK;
+}
+
+/* Pair marginal of a tree edge {p(k), k} at fixed phi (Theorem 4.1 applied to the pair):
+ *   Pi_{p,k}[i][j] = (phi^p gamma_p prod_{t in C_p, t != k} beta_t)_i K^{(p,k)}[i][j]
+ *                    (phi^k prod_{t in C_k} beta_t)_j,
+ * out is n_p x n_k row-major; edge costs weighted by edge_w (NULL = 1). */
+int orc_tree_pair_marginal(int K, int d, const long *off, const double *pts, const int *parent,
+                           const double *edge_w, double eta, const double *phi_cat, int k, double *out)
+{
+    if (tree_check(K, parent) != ORC_OK || eta <= 0.0 || k < 1 || k >= K) return ORC_EINVAL;
+    tree_t T = {K, d, off, pts, parent, eta, NULL, NULL, NULL, edge_w, NULL};
+    if (tree_alloc(&T) != ORC_OK) {
+        tree_free(&T);
+        return ORC_ENOMEM;
+    }
+    const double **phi = (const double **)malloc((size_t)K * sizeof(double *));
+    for (int q = 0; q < K; ++q) phi[q] = phi_cat + off[q];
+    for (int q = K - 1; q >= 1; --q) compute_beta(&T, phi, q);
+    for (int q = 0; q < K; ++q) compute_gamma(&T, phi, q);
+    const int p = parent[k];
+    const long np_ = tn(&T, p), nk = tn(&T, k);
+    double *u = (double *)malloc((size_t)np_ * sizeof(double));
+    double *w = (double *)malloc((size_t)nk * sizeof(double));
+    double *Kpk = (double *)malloc((size_t)(np_ * nk) * sizeof(double));
+    child_product(&T, p, k, u);
+    for (long i = 0; i < np_; ++i) u[i] = (phi[p][i] * T.gamma[p][i]) * u[i];
+    child_product(&T, k, -1, w);
+    for (long j = 0; j < nk; ++j) w[j] = phi[k][j] * w[j];
+    kernel_matrix(d, np_, tpts(&T, p), nk, tpts(&T, k), edge_eta(&T, k), Kpk);
+    for (long i = 0; i < np_; ++i)
+        for (long j = 0; j < nk; ++j) out[i * nk + j] = (u[i] * Kpk[i * nk + j]) * w[j];
+    free(u);
+    free(w);
+    free(Kpk);
+    free(phi);
+    tree_free(&T);
     return ORC_OK;
 }
 

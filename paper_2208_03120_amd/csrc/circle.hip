@@ -375,6 +375,25 @@ __global__ __launch_bounds__(256) void circle_final_kernel(const double *__restr
     }
 }
 
+// Pair marginal Pi_{1,k}[i][j] = phi^0_i Yg_k[i][j] Yb_k[i][j] phi^k_j (times the rows'
+// power-of-two scales on the dense path), written in the original orders of both
+// marginals.  Rows strided over blockIdx.y, columns across threads.
+template <class T>
+__global__ void circle_pair_kernel(const T *__restrict__ Yg, const T *__restrict__ Yb, int ld, int64_t n1,
+                                   int64_t nk, const double *__restrict__ phi0, const double *__restrict__ phik,
+                                   const int32_t *__restrict__ sg, const int32_t *__restrict__ sb,
+                                   const int32_t *__restrict__ perm0, const int32_t *__restrict__ permk,
+                                   double *__restrict__ out)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= nk) return;
+    for (int64_t i = blockIdx.y; i < n1; i += gridDim.y) {
+        double v = ((phi0[i] * (double)Yg[i * ld + j]) * (double)Yb[i * ld + j]) * phik[j];
+        if (sg) v = ldexp(v, sg[i] + sb[i]);
+        out[(int64_t)perm0[i] * nk + permk[j]] = v;
+    }
+}
+
 // NFFT path: src[i][l] = A[i][l] phi_l and the row's max exponent (one block per row).
 __global__ __launch_bounds__(256) void scale_rows_kernel(const double *__restrict__ A, int64_t nl,
                                                          const double *__restrict__ phi, double *__restrict__ src,
@@ -533,12 +552,12 @@ static int circle_up(mot_plan_s *P, CircleState &C)
 }
 
 template <class T>
-static int kmat(mot_plan_s *P, int a, int b, int ld, int rows_pad, T *out)
+static int kmat(mot_plan_s *P, int a, int b, int ld, int rows_pad, T *out, const double *xa = nullptr)
 {
     dim3 g((unsigned)((ld + 255) / 256), (unsigned)rows_pad);
-    hipLaunchKernelGGL(kernel_matrix_kernel<T>, g, dim3(256), 0, P->stream, (const double *)P->marg[a].pts,
-                       (int64_t)P->n[a], (const double *)P->marg[b].pts, (int64_t)P->n[b], P->d, P->eta, ld,
-                       (int64_t)rows_pad, out);
+    hipLaunchKernelGGL(kernel_matrix_kernel<T>, g, dim3(256), 0, P->stream,
+                       xa ? xa : (const double *)P->marg[a].pts, (int64_t)P->n[a], (const double *)P->marg[b].pts,
+                       (int64_t)P->n[b], P->d, P->eta, ld, (int64_t)rows_pad, out);
     return hipGetLastError() == hipSuccess ? MOT_OK : MOT_EDEVICE;
 }
 
@@ -610,12 +629,23 @@ int circle_create(mot_plan_s *P, const std::vector<double> &pts_h, const std::ve
     MOT_TRY(P->arena.get((size_t)C.n1p * ldmax * esz, &C.Yg[0]));
     MOT_TRY(P->arena.get((size_t)C.n1p * ldmax * esz, &C.Yg[1]));
     MOT_TRY(P->arena.get((size_t)C.n1p * C.ld[1] * esz, &C.Yg1));
+    // the closing edge {K, 1}: x^1 or, for a generalised Euler flow, sigma(x^1) in
+    // marginal 0's binned order
+    const double *xclose = nullptr;
+    if (!P->closing.empty()) {
+        double *orig = nullptr, *sorted = nullptr;
+        MOT_TRY(P->arena.get_n(P->closing.size(), &orig));
+        MOT_TRY(P->arena.get_n(P->closing.size(), &sorted));
+        MOT_HIP(hipMemcpy(orig, P->closing.data(), P->closing.size() * sizeof(double), hipMemcpyHostToDevice));
+        MOT_HIP(launch_gather_rows(orig, P->marg[0].perm, P->n[0], P->d, sorted, st));
+        xclose = sorted;
+    }
     if (C.nfft) {
         MOT_TRY(kmat<double>(P, 0, 1, C.ld[1], C.n1p, (double *)C.Yg1));
-        MOT_TRY(kmat<double>(P, 0, K - 1, C.ld[K - 1], C.n1p, (double *)C.Yb[K - 1]));
+        MOT_TRY(kmat<double>(P, 0, K - 1, C.ld[K - 1], C.n1p, (double *)C.Yb[K - 1], xclose));
     } else {
         MOT_TRY(kmat<float>(P, 0, 1, C.ld[1], C.n1p, (float *)C.Yg1));
-        MOT_TRY(kmat<float>(P, 0, K - 1, C.ld[K - 1], C.n1p, (float *)C.Yb[K - 1]));
+        MOT_TRY(kmat<float>(P, 0, K - 1, C.ld[K - 1], C.n1p, (float *)C.Yb[K - 1], xclose));
         // padding of the ping-pong buffers must be zero (they become GEMM operands)
         MOT_HIP(launch_fill_int((int32_t *)C.Yg[0], 0, (int64_t)C.n1p * ldmax, st));
         MOT_HIP(launch_fill_int((int32_t *)C.Yg[1], 0, (int64_t)C.n1p * ldmax, st));
@@ -722,6 +752,30 @@ int circle_marginals(mot_plan_s *P, double *)
         MOT_TRY(colsum_phi(P, C, k, true));
     }
     return MOT_OK;
+}
+
+// Pi_{1,k} at the current phi: the gamma recursion up to k (beta is current after every
+// sweep and after new scaling vectors), then the elementwise product of Theorem 4.3's
+// factors.
+int circle_pair_marginal(mot_plan_s *P, int k, double *out)
+{
+    CircleState &C = *(CircleState *)P->circle;
+    hipStream_t st = P->stream;
+    for (int q = 2; q <= k; ++q) MOT_TRY(circle_product(P, C, 1, q));
+    const int64_t n1 = C.n1, nk = P->n[k];
+    const dim3 g((unsigned)((nk + 255) / 256), (unsigned)(n1 < 32768 ? n1 : 32768));
+    if (C.nfft)
+        hipLaunchKernelGGL(circle_pair_kernel<double>, g, dim3(256), 0, st, (const double *)Ymat(C, 1, k),
+                           (const double *)C.Yb[k], C.ld[k], n1, nk, (const double *)P->marg[0].phi,
+                           (const double *)P->marg[k].phi, (const int32_t *)nullptr, (const int32_t *)nullptr,
+                           (const int32_t *)P->marg[0].perm, (const int32_t *)P->marg[k].perm, out);
+    else
+        hipLaunchKernelGGL(circle_pair_kernel<float>, g, dim3(256), 0, st, (const float *)Ymat(C, 1, k),
+                           (const float *)C.Yb[k], C.ld[k], n1, nk, (const double *)P->marg[0].phi,
+                           (const double *)P->marg[k].phi, (const int32_t *)Yscale(C, 1, k),
+                           (const int32_t *)Yscale(C, 0, k), (const int32_t *)P->marg[0].perm,
+                           (const int32_t *)P->marg[k].perm, out);
+    return hipGetLastError() == hipSuccess ? MOT_OK : MOT_EDEVICE;
 }
 
 void circle_destroy(mot_plan_s *P)

@@ -159,6 +159,8 @@ struct mot_plan_s {
     std::vector<double> edge_w;
     std::vector<int> free_node;
     std::map<double, float *> D_of_eta;  // NFFT multiplier per distinct eta / w
+    // generalised Euler flow (circle): sigma(x^1) for the closing edge, original order
+    std::vector<double> closing;
     hipStream_t stream = nullptr;
     bool own_stream = false;
     int device = 0;
@@ -229,6 +231,8 @@ int setup_marginals(mot_plan_s *P, const std::vector<double> &pts_h, const std::
                     const mot_fastsum_params *fs, int64_t phi_pad_to);
 int circle_run_sweeps(mot_plan_s *P, int sweeps);
 int circle_marginals(mot_plan_s *P, double *P_sorted_all);
+// Pi_{1,k} into out (n_0 x n_k device doubles, original orders of both marginals)
+int circle_pair_marginal(mot_plan_s *P, int k, double *out);
 void circle_destroy(mot_plan_s *P);
 size_t circle_footprint(int K, const int64_t *n, int path, int precision);
 const float2 *device_twiddle(int n);

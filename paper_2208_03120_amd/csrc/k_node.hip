@@ -344,6 +344,36 @@ hipError_t launch_scatter_vec(const double *src, const int32_t *perm, int64_t n,
     return hipGetLastError();
 }
 
+// Pair marginal of a tree edge (Theorem 4.1 applied to two adjacent marginals): one
+// row i of the parent per block, columns across the threads; written in original order.
+__global__ void tree_pair_kernel(const double *__restrict__ u, const double *__restrict__ xa,
+                                 const int32_t *__restrict__ perm_a, const double *__restrict__ w,
+                                 const double *__restrict__ xb, const int32_t *__restrict__ perm_b,
+                                 int64_t na, int64_t nb, int d, double inv_eta, double *__restrict__ out)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= nb) return;
+    for (int64_t i = blockIdx.y; i < na; i += gridDim.y) {
+        double d2 = 0.0;
+        for (int c = 0; c < d; ++c) {
+            const double df = xa[i * d + c] - xb[j * d + c];
+            d2 += df * df;
+        }
+        out[(int64_t)perm_a[i] * nb + perm_b[j]] = (u[i] * exp(-d2 * inv_eta)) * w[j];
+    }
+}
+
+hipError_t launch_tree_pair(const double *u, const double *xa, const int32_t *perm_a, int64_t na,
+                            const double *w, const double *xb, const int32_t *perm_b, int64_t nb, int d,
+                            double eta, double *out, hipStream_t s)
+{
+    if (na <= 0 || nb <= 0) return hipSuccess;
+    const unsigned gy = (unsigned)(na < 32768 ? na : 32768);
+    hipLaunchKernelGGL(tree_pair_kernel, dim3((unsigned)((nb + 255) / 256), gy), dim3(256), 0, s, u, xa, perm_a,
+                       w, xb, perm_b, na, nb, d, 1.0 / eta, out);
+    return hipGetLastError();
+}
+
 // max exponent of a vector into a slot (for products requested outside a sweep)
 __global__ void vec_exp_kernel(const double *__restrict__ v, int64_t n, int32_t *slot)
 {

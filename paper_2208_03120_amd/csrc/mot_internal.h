@@ -154,6 +154,10 @@ hipError_t launch_finalize(const FinalJob *jobs, const int2 *items, int n_items,
 hipError_t launch_fill_int(int32_t *p, int32_t value, int64_t count, hipStream_t s);
 hipError_t launch_fill_double(double *p, double value, int64_t count, hipStream_t s);
 hipError_t launch_vec_exp(const double *v, int64_t n, int32_t *slot, hipStream_t s);
+// Tree edge pair marginal: out[perm_a[i] * nb + perm_b[j]] = u_i exp(-|x_i - y_j|^2 / eta) w_j
+hipError_t launch_tree_pair(const double *u, const double *xa, const int32_t *perm_a, int64_t na,
+                            const double *w, const double *xb, const int32_t *perm_b, int64_t nb, int d,
+                            double eta, double *out, hipStream_t s);
 hipError_t launch_gather_rows(const double *src, const int32_t *perm, int64_t n, int d, double *dst,
                               hipStream_t s);
 hipError_t launch_scatter_vec(const double *src, const int32_t *perm, int64_t n, double *dst,

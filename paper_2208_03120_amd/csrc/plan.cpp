@@ -1104,8 +1104,8 @@ int mot_plan_destroy(mot_plan P)
 
 static int create_plan(mot_plan *out, int32_t K, int32_t d, const int64_t *n, const double *points,
                        const double *weights, int32_t topology, const int32_t *parent,
-                       const mot_tree_options *opt, double eta, int32_t path, int32_t precision,
-                       const mot_fastsum_params *fs, int32_t ptr_kind, void *stream,
+                       const mot_tree_options *opt, const double *closing, double eta, int32_t path,
+                       int32_t precision, const mot_fastsum_params *fs, int32_t ptr_kind, void *stream,
                        const mot_allocator *alloc)
 {
     if (!out) return MOT_EINVAL;
@@ -1155,6 +1155,14 @@ static int create_plan(mot_plan *out, int32_t K, int32_t d, const int64_t *n, co
     if (rc < 0) return rc;
     rc = validate_common(K, d, n, eta, w_h, pts_h, total, free_node);
     if (rc < 0) return rc;
+    std::vector<double> closing_h;
+    if (closing) {
+        if (topology != MOT_CIRCLE) return MOT_EINVAL;
+        rc = copy_in(closing, (size_t)n[0] * d, ptr_kind, closing_h);
+        if (rc < 0) return rc;
+        for (double v : closing_h)
+            if (!std::isfinite(v)) return MOT_EINVAL;
+    }
     {  // free nodes carry no weights: zero them (no S term, mu is never divided)
         int64_t o = 0;
         for (int k = 0; k < K; ++k) {
@@ -1172,6 +1180,7 @@ static int create_plan(mot_plan *out, int32_t K, int32_t d, const int64_t *n, co
     P->eta = eta;
     P->edge_w = edge_w;
     P->free_node = free_node;
+    P->closing = closing_h;
     (void)hipGetDevice(&P->device);
     if (alloc && alloc->alloc && alloc->free) {
         P->arena.alloc = *alloc;
@@ -1209,8 +1218,51 @@ int mot_plan_create(mot_plan *out, int32_t K, int32_t d, const int64_t *n, const
                     int32_t path, int32_t precision, const mot_fastsum_params *fs, int32_t ptr_kind,
                     void *stream, const mot_allocator *alloc)
 {
-    return create_plan(out, K, d, n, points, weights, topology, parent, nullptr, eta, path, precision, fs,
-                       ptr_kind, stream, alloc);
+    return create_plan(out, K, d, n, points, weights, topology, parent, nullptr, nullptr, eta, path, precision,
+                       fs, ptr_kind, stream, alloc);
+}
+
+int mot_plan_create_circle(mot_plan *out, int32_t K, int32_t d, const int64_t *n, const double *points,
+                           const double *weights, const double *closing_points, double eta, int32_t path,
+                           int32_t precision, const mot_fastsum_params *fs, int32_t ptr_kind, void *stream,
+                           const mot_allocator *alloc)
+{
+    return create_plan(out, K, d, n, points, weights, MOT_CIRCLE, nullptr, nullptr, closing_points, eta, path,
+                       precision, fs, ptr_kind, stream, alloc);
+}
+
+int mot_pair_marginal(mot_plan P, int32_t k, double *out, int32_t ptr_kind)
+{
+    if (!P || !out || k < 1 || k >= P->K) return MOT_EINVAL;
+    const int a = P->topology == MOT_CIRCLE ? 0 : P->parent[k];
+    const size_t count = (size_t)P->n[a] * (size_t)P->n[k];
+    double *dst = nullptr;
+    if (ptr_kind == MOT_DEVICE) {
+        dst = out;
+    } else if (hipMalloc(&dst, count * sizeof(double)) != hipSuccess) {
+        (void)hipGetLastError();
+        return MOT_ENOMEM;
+    }
+    int rc = MOT_OK;
+    if (P->topology == MOT_CIRCLE) {
+        rc = circle_pair_marginal(P, k, dst);
+    } else {
+        // a consistent pass at the current phi (as in mot_marginals): the down source of
+        // k at its parent and the up source of k are then the two outer factors
+        MOT_HIP(launch_fill_int(P->exp_slots, INT32_MIN, 2 * P->K + 1, P->stream));
+        rc = run_steps(P->sched.marg_pass, P->stream);
+        if (rc >= 0) {
+            MOT_HIP(launch_fill_int(P->exp_slots, INT32_MIN, 2 * P->K + 1, P->stream));
+            MOT_HIP(launch_tree_pair(P->marg[k].down_src, P->marg[a].pts, P->marg[a].perm, P->n[a],
+                                     P->marg[k].up_src, P->marg[k].pts, P->marg[k].perm, P->n[k], P->d,
+                                     P->jobs[2 * k + 1].eta, dst, P->stream));
+        }
+    }
+    if (rc >= 0 && ptr_kind != MOT_DEVICE)
+        MOT_HIP(hipMemcpyAsync(out, dst, count * sizeof(double), hipMemcpyDeviceToHost, P->stream));
+    MOT_HIP(hipStreamSynchronize(P->stream));
+    if (ptr_kind != MOT_DEVICE) (void)hipFree(dst);
+    return rc;
 }
 
 int mot_plan_create_tree(mot_plan *out, int32_t K, int32_t d, const int64_t *n, const double *points,
@@ -1218,7 +1270,7 @@ int mot_plan_create_tree(mot_plan *out, int32_t K, int32_t d, const int64_t *n, 
                          double eta, int32_t path, int32_t precision, const mot_fastsum_params *fs,
                          int32_t ptr_kind, void *stream, const mot_allocator *alloc)
 {
-    return create_plan(out, K, d, n, points, weights, MOT_TREE, parent, opt, eta, path, precision, fs,
+    return create_plan(out, K, d, n, points, weights, MOT_TREE, parent, opt, nullptr, eta, path, precision, fs,
                        ptr_kind, stream, alloc);
 }
 

@@ -88,7 +88,7 @@ class Result(ctypes.Structure):
 
 
 # names declared in include/mot.h, used by the ABI export test
-EXPORTED = ["mot_plan_create", "mot_plan_create_tree", "mot_sinkhorn", "mot_get_S_history", "mot_marginals",
+EXPORTED = ["mot_plan_create", "mot_plan_create_tree", "mot_plan_create_circle", "mot_pair_marginal", "mot_sinkhorn", "mot_get_S_history", "mot_marginals",
             "mot_get_scalings", "mot_set_scalings", "mot_apply_kernel", "mot_plan_get_info",
             "mot_plan_footprint", "mot_plan_destroy", "mot_strerror", "mot_bin_points",
             "mot_plan_profile",
@@ -124,6 +124,10 @@ def _load():
                                                 _ip, _P(TreeOptions), ctypes.c_double, ctypes.c_int32,
                                                 ctypes.c_int32, _P(FastsumParams), ctypes.c_int32, _vp,
                                                 _P(Allocator)]),
+        "mot_plan_create_circle": (ctypes.c_int, [_P(_vp), ctypes.c_int32, ctypes.c_int32, _lp, _dp, _dp,
+                                                  _dp, ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
+                                                  _P(FastsumParams), ctypes.c_int32, _vp, _P(Allocator)]),
+        "mot_pair_marginal": (ctypes.c_int, [_vp, ctypes.c_int32, _dp, ctypes.c_int32]),
         "mot_sinkhorn": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
                                         ctypes.c_int32, _ip, _dp, _dp]),
         "mot_get_S_history": (ctypes.c_int, [_vp, _dp, ctypes.c_int32]),
@@ -220,9 +224,12 @@ class Plan:
     """One multi-marginal OT problem resident on the GPU (mot_plan_create)."""
 
     def __init__(self, points, weights, topology=TREE, parent=None, eta=0.1, path=NFFT,
-                 precision=None, fastsum=None, stream=None, edge_weight=None, free=None):
+                 precision=None, fastsum=None, stream=None, edge_weight=None, free=None,
+                 closing_points=None):
         """edge_weight ([K], entry k for the edge {parent[k], k}) and free ([K] booleans)
-        pose the generalised barycenter problem of Sec. 6.2 (mot_plan_create_tree)."""
+        pose the generalised barycenter problem of Sec. 6.2 (mot_plan_create_tree);
+        closing_points (n_0 x d, sigma(x^1)) the generalised Euler flow of Sec. 6.3 on a
+        circle (mot_plan_create_circle)."""
         if precision is None:
             precision = PREC_MIXED if path != DENSE else PREC_BF16
         d, sizes, pts, w = _concat(points, weights)
@@ -233,9 +240,17 @@ class Plan:
         par = None
         if topology == TREE:
             par = np.ascontiguousarray(parent, dtype=np.int32)
+        self._parent = par
         fs = ctypes.byref(fastsum) if fastsum is not None else None
         st = stream if stream is not None else current_stream()
-        if edge_weight is None and free is None:
+        if closing_points is not None:
+            if topology != CIRCLE:
+                raise ValueError("closing points are a circle option")
+            cl = _f64(np.asarray(closing_points, dtype=np.float64).reshape(int(sizes[0]), d))
+            rc = _lib.mot_plan_create_circle(ctypes.byref(self._h), self.K, d, sizes.ctypes.data_as(_lp),
+                                             _dptr(pts), _dptr(w), _dptr(cl), float(eta), path, precision, fs,
+                                             HOST, st, None)
+        elif edge_weight is None and free is None:
             rc = _lib.mot_plan_create(ctypes.byref(self._h), self.K, d, sizes.ctypes.data_as(_lp),
                                       _dptr(pts), _dptr(w), topology,
                                       par.ctypes.data_as(_ip) if par is not None else None,
@@ -296,6 +311,13 @@ class Plan:
         l1 = np.zeros(self.K)
         _check(_lib.mot_marginals(self._h, _dptr(out), _dptr(l1), HOST), "mot_marginals")
         return _split(out, self.sizes), l1
+
+    def pair_marginal(self, k):
+        """Pi between marginal a and k (circle: a = 0; tree: a = parent[k]), n_a x n_k."""
+        a = 0 if self._parent is None else int(self._parent[k])
+        out = np.zeros((int(self.sizes[a]), int(self.sizes[k])))
+        _check(_lib.mot_pair_marginal(self._h, int(k), _dptr(out), HOST), "mot_pair_marginal")
+        return out
 
     def apply(self, t, s, v):
         v = _f64(v)

@@ -193,6 +193,28 @@ def h_tree_barycenter(seed=7, N=2500, eta=5e-3, leaf_weight=0.25):
     return inst, ew, np.array(free)
 
 
+def sigma_map(name, x):
+    """Connection maps of [0, 1] for generalised Euler flows (Sec. 6.3): 'reverse'
+    x -> 1 - x and 'tent' x -> min(2x, 2 - 2x)."""
+    if name == "reverse":
+        return 1.0 - x
+    if name == "tent":
+        return np.minimum(2.0 * x, 2.0 - 2.0 * x)
+    raise ValueError(name)
+
+
+def euler_flow(seed=8, N=400, K=6, eta=0.05, sigma="reverse"):
+    """Generalised Euler flow of Sec. 6.3: K marginals of N uniform points on [0, 1]
+    (d = 1) with uniform weights 1/N, circle cost whose closing edge compares x^K with
+    sigma(x^1).  Returns (Instance, closing points sigma(x^1))."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    pts = [rng.uniform(0.0, 1.0, size=(N, 1)) for _ in range(K)]
+    wts = [np.full(N, 1.0 / N) for _ in range(K)]
+    inst = Instance(pts, wts, CIRCLE, None, float(eta),
+                    {"name": "euler_flow_%s_K%d_N%d" % (sigma, K, N), "sweeps": 50})
+    return inst, sigma_map(sigma, pts[0])
+
+
 def cycle(seed=3, N=4000):
     """Cycle K=5, N points in d=2, eta=0.1, 100 sweeps."""
     rng = np.random.Generator(np.random.PCG64(seed))

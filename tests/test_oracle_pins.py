@@ -513,3 +513,66 @@ def test_unit_edge_weights_and_no_free_nodes_change_nothing():
     for x, y in zip(a[0], b[0]):
         np.testing.assert_array_equal(x, y)
     np.testing.assert_array_equal(a[1], b[1])
+
+
+# ---- generalised Euler flows and pair marginals (Sec. 6.3) ---------------------------------
+
+def _sigma_tent(x):
+    """A connection map of [0, 1] onto itself (the tent map min(2x, 2 - 2x))."""
+    return np.minimum(2.0 * x, 2.0 - 2.0 * x)
+
+
+@pytest.mark.parametrize("sigma", ["reverse", "tent"])
+def test_circle_with_closing_map_iterates_equal_algorithm1(sigma):
+    """The Euler-flow cost |x^K - sigma(x^1)|^2 on the closing edge: Algorithm 3 with the
+    mapped points equals Algorithm 1 on the full tensor of that cost, iterate for
+    iterate, with S^(r) = S(phi^(r))."""
+    r = rng(51)
+    K, n = 4, 6
+    pts = [r.uniform(0.0, 1.0, (n, 1)) for _ in range(K)]
+    mu = [np.full(n, 1.0 / n) for _ in range(K)]
+    closing = 1.0 - pts[0] if sigma == "reverse" else _sigma_tent(pts[0])
+    C = brute.cost_tensor(pts, brute.circle_edges(K), closing=closing)
+    Kt = brute.kernel_tensor(C, 0.05)
+    hist = brute.algorithm1(Kt, mu, 5)
+    for sweeps in range(1, 6):
+        phi, S, _, _ = oracle.circle_sinkhorn(pts, mu, 0.05, sweeps, closing=closing)
+        for k in range(K):
+            np.testing.assert_allclose(phi[k], hist[sweeps - 1][k], rtol=1e-12)
+        prev = [np.ones(n) for _ in range(K)] if sweeps == 1 else hist[sweeps - 2]
+        assert abs(S[-1] - brute.sinkhorn_S(Kt, mu, prev, 0.05)) < 1e-13
+
+
+@pytest.mark.parametrize("closing", [False, True])
+def test_circle_pair_marginals_match_brute_force(closing):
+    """Pi_{1,k} = phi^1_i lambda^{(1,k)}_ij alpha^{(k,1)}_ji phi^k_j equals the full tensor
+    K (.) Phi summed over every other index, for every k, at arbitrary phi."""
+    r = rng(52)
+    K = 5
+    pts = [r.uniform(0.0, 1.0, (n, 1)) for n in (5, 4, 6, 3, 5)]
+    cl = _sigma_tent(pts[0]) if closing else None
+    C = brute.cost_tensor(pts, brute.circle_edges(K), closing=cl)
+    Kt = brute.kernel_tensor(C, 0.08)
+    phi = [r.uniform(0.5, 2.0, len(p)) for p in pts]
+    T = Kt * brute.outer(phi)
+    for k in range(1, K):
+        got = oracle.circle_pair_marginal(pts, 0.08, phi, k, closing=cl)
+        np.testing.assert_allclose(got, brute.pair_marginal(T, 0, k), rtol=1e-12)
+    P = oracle.circle_marginals(pts, 0.08, phi, closing=cl)
+    for k in range(K):
+        np.testing.assert_allclose(P[k], brute.marginal(T, k), rtol=1e-12)
+
+
+def test_tree_pair_marginals_match_brute_force():
+    """Pi_{p(k),k} of every edge of a weighted tree against the full tensor."""
+    r = rng(53)
+    parent = [-1, 0, 0, 1]
+    pts = [r.uniform(-0.25, 0.25, (n, 2)) for n in (5, 4, 6, 3)]
+    ew = [0.0, 0.5, 1.5, 0.8]
+    edges = brute.tree_edges(parent)
+    Kt = brute.kernel_tensor(brute.cost_tensor(pts, edges, [ew[k] for _, k in edges]), 0.1)
+    phi = [r.uniform(0.5, 2.0, len(p)) for p in pts]
+    T = Kt * brute.outer(phi)
+    for k in range(1, 4):
+        got = oracle.tree_pair_marginal(pts, parent, 0.1, phi, k, edge_weight=ew)
+        np.testing.assert_allclose(got, brute.pair_marginal(T, parent[k], k), rtol=1e-12)
