@@ -447,6 +447,9 @@ def main():
     ap.add_argument("--profile-sweeps", type=int, default=5)
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the circle, batched and serving measurements")
+    ap.add_argument("--only", default="",
+                    help="comma-separated extra sections to run alone (no headline line), e.g. "
+                         "truncated,barycenter,euler_flow; for profiling them")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -457,6 +460,19 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     from paper_2208_03120_amd import mot, workloads as W
+
+    extras = [("circle", bench_circle), ("batched", bench_batched), ("serving", bench_serving),
+              ("error_vs_M", bench_error_vs_M), ("truncated", bench_truncated),
+              ("barycenter", bench_barycenter), ("euler_flow", bench_euler_flow)]
+    if args.only:
+        want = [x for x in args.only.split(",") if x]
+        known = dict(extras)
+        unknown = [x for x in want if x not in known]
+        if unknown:
+            print("unknown sections: %s (known: %s)" % (unknown, sorted(known)), file=sys.stderr)
+            sys.exit(2)
+        print(json.dumps({x: known[x](mot, W) for x in want}))
+        return
 
     # plain device-to-device copy of known size: the reference for a profiler's HBM
     # byte counters (its kernel is the runtime's buffer copy)
@@ -598,9 +614,7 @@ def main():
     }
     plan.close()
     if not args.no_extras:
-        for key, fn in [("circle", bench_circle), ("batched", bench_batched), ("serving", bench_serving),
-                        ("error_vs_M", bench_error_vs_M), ("truncated", bench_truncated),
-                        ("barycenter", bench_barycenter), ("euler_flow", bench_euler_flow)]:
+        for key, fn in extras:
             try:
                 out[key] = fn(mot, W)
             except Exception as e:  # the headline measurement stands on its own
