@@ -70,6 +70,7 @@ struct TruncParams {
     double glo[3] = {0, 0, 0};  // grid origin (lower corner of the bounding box)
     int nc = 1, w = 1;     // cells per dimension; neighbour half-width in cells
     int B = 1, R = 1;      // cells per run and targets per lane at the mean density
+    double box_cells[3] = {1, 1, 1};  // cells spanned by the cloud's box per dimension
     double est_err = 0;    // relative error the cutoff was set for
 };
 
@@ -90,9 +91,12 @@ int64_t trunc_cells(int d, const TruncParams &T);  // nc^d
 // host mirror of the kernel's neighbour rows of a run of B cells starting at cc
 int trunc_row_range(int d, const TruncParams &T, const int cc[3], int B, int ri, int64_t *row_base,
                     int *xa, int *xb);
-double trunc_cost(int d, const TruncParams &T, double tpc, double spc, double occ, int B, int R);
-void trunc_choose_run(int d, const TruncParams &T, double tpc, double spc, double occ, int max_r, int *B,
-                      int *R);
+double trunc_cost(int d, const TruncParams &T, double lam_t, double lam_s, int B, int R, bool wide);
+// cells per run B, targets per lane R and exponent form (wide: FP64) of the cheapest launch
+// shape; lam_t / lam_s: targets / sources per grid cell; sch = sqrt(log2(e) / eta) h;
+// fp64: the FP64 kernel (form fixed)
+void trunc_choose_run(int d, const TruncParams &T, double lam_t, double lam_s, int max_r, double sch, bool fp64,
+                      int *B, int *R, int *wide);
 void kappa_B_shifted(double eta, double tau, double eps_B, int p, std::vector<double> &q);
 double kappa_R(double r, double eta, double tau, double eps_B, const std::vector<double> &q);
 void kappa_hat_even(int d, int M, double eta, double tau, double eps_B, int p,

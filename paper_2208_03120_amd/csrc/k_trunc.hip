@@ -11,18 +11,28 @@
 // One wavefront takes one item: up to 64 R targets, R per lane, from a run of B
 // consecutive cells of one row (consecutive in the sorted order; B > 1 fills the lanes
 // when cells hold few points).  The neighbourhood rows of a run are those of its first
-// cell, widened by B - 1 cells along the row.  The wave stages the sources of its rows 64
-// at a time through its own LDS slice and every lane sums them against its R targets;
-// the next stage's sources are loaded into registers while the current one is summed.
-// The waves of a block take different items and synchronise only within themselves.
+// cell, widened by B - 1 cells along the row.  The wave first lists the item's non-empty
+// rows in LDS with the prefix sum of their lengths, so its sources form one list; it then
+// stages that list 64 entries at a time through its own LDS slice (every stage full but
+// the last), and every lane sums a stage against its R targets while the next stage's
+// sources are loaded.  The waves of a block take different items and synchronise only
+// within themselves.
 //
-// Mixed precision: with c = log2(e) / eta and coordinates relative to the cloud's centre,
-// the exponent -c|x - y|^2 = -c|x|^2 - c|y|^2 + 2c x.y is formed in FP64 (gfx950 issues
-// FP64 adds and FMAs at the unpacked FP32 rate; at small eta the terms reach thousands and
-// cancel, which FP32 could not resolve), rounded to FP32 and passed to v_exp_f32.  Values
-// are scaled by 2^-e (e = exponent of max v); sums over 64 sources are FP32 and are added
-// into FP64 accumulators.
+// Mixed precision, two forms of the exponent (c = log2(e) / eta):
+//  * short runs: coordinates relative to the centre of the item's run of cells (in FP64),
+//    scaled by sqrt(c) and rounded to FP32; a term is exp2(-|x'' - y''|^2).  The host takes
+//    this form only when sqrt(c) times the run's half-diagonal is at most 3, so the targets
+//    and every source that contributes more than a rounding error have |x''|, |y''| of a
+//    few units and their FP32 rounding moves the exponent by ~1e-7;
+//  * long runs (sparse cells): -c|x|^2 - c|y|^2 + 2c x.y formed in FP64 (coordinates
+//    relative to the cloud's centre), rounded to FP32 for v_exp_f32.  On gfx950 the FP64
+//    adds and FMAs issue at half the FP32 rate, so this form costs ~1.6x per pair.
+// (The expanded form in FP32 would cancel terms of size c r^2.)  Values are scaled by
+// 2^-e (e = exponent of max v); sums over 64 sources are FP32 and are added into FP64
+// accumulators.
 // FP64: plain exp(-|x - y|^2 / eta) with FP64 sums in source order.
+#include <type_traits>
+
 #include "mot_internal.h"
 
 namespace mot {
@@ -89,36 +99,34 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// The stages of an item: consecutive blocks of at most 64 sources of its neighbour rows.
-template <int D>
-struct StageCursor {
-    int ri = -1, nrows = 0;
-    int64_t ja = 0, jb = 0;
-    __device__ __forceinline__ bool next(const ProdJob &J, const int cc[3], int B, int64_t &j0, int &nj)
-    {
-        while (ja >= jb) {
-            if (++ri >= nrows) return false;
-            if (!trunc_row<D>(J, cc, B, ri, ja, jb)) ja = jb = 0;
-        }
-        j0 = ja;
-        nj = (int)min((int64_t)64, jb - ja);
-        ja += nj;
-        return true;
-    }
-};
-
 constexpr int kTruncWaves = 4;  // independent wavefronts per block, one item each
 
-template <int D, int R>
+__device__ __forceinline__ int wave_incl_scan(int v, int lane)
+{
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int t = __shfl_up(v, o);
+        if (lane >= o) v += t;
+    }
+    return v;
+}
+
+template <int D, int R, bool WIDE>
 __global__ __launch_bounds__(64 * kTruncWaves) void trunc_mixed_kernel(const ProdJob *__restrict__ jobs,
                                                                        const int4 *__restrict__ items,
                                                                        int n_items)
 {
-    __shared__ double sy_all[kTruncWaves][64][4];  // 2 c y (centred), -c |y|^2
+    // FP32 form: float4 sqrt(c) (y - run centre), 2^-e v;  FP64 form: 2c (y - cloud
+    // centre), -c |y - cloud centre|^2 and the value in its own array
+    __shared__ double sbuf_all[kTruncWaves][64][4];
     __shared__ float sv_all[kTruncWaves][64];
+    __shared__ int32_t ra_all[kTruncWaves][kMaxTruncRows];      // first sorted source of each row
+    __shared__ int32_t rp_all[kTruncWaves][kMaxTruncRows + 1];  // sources before each row
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    double(*sy)[4] = sy_all[wave];
+    float4 *sy = reinterpret_cast<float4 *>(sbuf_all[wave]);
+    double(*sw)[4] = sbuf_all[wave];
     float *sv = sv_all[wave];
+    int32_t *ra = ra_all[wave], *rp = rp_all[wave];
     for (int it = blockIdx.x * kTruncWaves + wave; it < n_items; it += gridDim.x * kTruncWaves) {
         const int4 itm = items[it];
         const ProdJob &J = jobs[itm.x];
@@ -126,12 +134,39 @@ __global__ __launch_bounds__(64 * kTruncWaves) void trunc_mixed_kernel(const Pro
         int cc[3];
         trunc_cell<D>(J, itm.y, cc);
         const double c2 = 1.4426950408889634 / J.eta;  // log2(e) / eta
+        const double sc = sqrt(c2);
+        double ctr[3] = {0.0, 0.0, 0.0};  // centre of the run (FP32 form), of the cloud (FP64)
+#pragma unroll
+        for (int c = 0; c < D; ++c)
+            ctr[c] = WIDE ? J.ctr[c] : J.glo[c] + (cc[c] + (c == D - 1 ? 0.5 * B : 0.5)) * J.h;
         int e = *gp(J.v_exp);
         if (e == INT32_MIN) e = 0;
         const MOT_GLOBAL double *tgt = gp(J.tgt_pts);
         const MOT_GLOBAL double *src = gp(J.src_pts);
         const MOT_GLOBAL double *vv = gp(J.v);
-        double xs[R][3], ax[R], acc[R];
+        // the item's non-empty neighbour rows, compacted in row order with the prefix of
+        // their lengths: the sources to sum are one list of `total` entries
+        int nr = 0, total = 0;
+        const int nrows = trunc_rows(D, J.tw);
+        wave_sync();
+        for (int r0 = 0; r0 < nrows; r0 += 64) {
+            int64_t a = 0, b = 0;
+            const bool ok = r0 + lane < nrows && trunc_row<D>(J, cc, B, r0 + lane, a, b);
+            const int len = ok ? (int)(b - a) : 0;
+            const int f = len > 0 ? 1 : 0;
+            const int fpos = wave_incl_scan(f, lane), lpos = wave_incl_scan(len, lane);
+            if (f) {
+                ra[nr + fpos - 1] = (int32_t)a;
+                rp[nr + fpos - 1] = total + lpos - len;
+            }
+            nr += __shfl(fpos, 63);
+            total += __shfl(lpos, 63);
+        }
+        if (lane == 0) rp[nr] = total;
+        wave_sync();
+        typedef typename std::conditional<WIDE, double, float>::type real;
+        real xs[R][3];
+        double ax[R], acc[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const bool act = lane + 64 * r < cnt;
@@ -139,69 +174,90 @@ __global__ __launch_bounds__(64 * kTruncWaves) void trunc_mixed_kernel(const Pro
             double nrm = 0.0;
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                const double dx = (c < D && act) ? tgt[i * D + c] - J.ctr[c] : 0.0;
-                xs[r][c] = dx;
+                const double dx = (c < D && act) ? tgt[i * D + c] - ctr[c] : 0.0;
+                xs[r][c] = WIDE ? (real)dx : (real)(dx * sc);
                 nrm += dx * dx;
             }
             ax[r] = -c2 * nrm;
             acc[r] = 0.0;
         }
-        StageCursor<D> cur;
-        cur.nrows = trunc_rows(D, J.tw);
-        int64_t j0 = 0;
-        int nj = 0;
-        bool have = cur.next(J, cc, B, j0, nj);
-        // registers holding the next stage's source (loaded one stage ahead)
+        // stages of 64 consecutive list entries; each lane follows its entry's row with a
+        // pointer that only moves forward, and loads its source one stage ahead
+        int row = 0;
         double ly[3] = {0.0, 0.0, 0.0}, lv = 0.0;
-        if (have && lane < nj) {
+        auto fetch = [&](int q) {
+            if (q < total) {
+                while (rp[row + 1] <= q) ++row;
+                const int64_t j = (int64_t)ra[row] + (q - rp[row]);
 #pragma unroll
-            for (int c = 0; c < D; ++c) ly[c] = src[(j0 + lane) * D + c];
-            lv = vv[j0 + lane];
-        }
-        while (have) {
+                for (int c = 0; c < D; ++c) ly[c] = src[j * D + c];
+                lv = vv[j];
+            }
+        };
+        fetch(lane);
+        for (int s0 = 0; s0 < total; s0 += 64) {
+            const int nj = min(64, total - s0);
             wave_sync();
             if (lane < nj) {
-                double nrm = 0.0;
-                sy[lane][0] = sy[lane][1] = sy[lane][2] = 0.0;
+                if constexpr (WIDE) {
+                    double nrm = 0.0;
+                    sw[lane][0] = sw[lane][1] = sw[lane][2] = 0.0;
 #pragma unroll
-                for (int c = 0; c < D; ++c) {
-                    const double dy = ly[c] - J.ctr[c];
-                    sy[lane][c] = 2.0 * c2 * dy;
-                    nrm += dy * dy;
+                    for (int c = 0; c < D; ++c) {
+                        const double dy = ly[c] - ctr[c];
+                        sw[lane][c] = 2.0 * c2 * dy;
+                        nrm += dy * dy;
+                    }
+                    sw[lane][3] = -c2 * nrm;
+                    sv[lane] = (float)ldexp(lv, -e);
+                } else {
+                    float y[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+                    for (int c = 0; c < D; ++c) y[c] = (float)((ly[c] - ctr[c]) * sc);
+                    sy[lane] = make_float4(y[0], y[1], y[2], (float)ldexp(lv, -e));
                 }
-                sy[lane][3] = -c2 * nrm;
-                sv[lane] = (float)ldexp(lv, -e);
             }
             wave_sync();
-            int64_t j1 = 0;
-            int nj1 = 0;
-            const bool have1 = cur.next(J, cc, B, j1, nj1);
-            if (have1 && lane < nj1) {
-#pragma unroll
-                for (int c = 0; c < D; ++c) ly[c] = src[(j1 + lane) * D + c];
-                lv = vv[j1 + lane];
-            }
+            fetch(s0 + 64 + lane);
             float part[R];
 #pragma unroll
             for (int r = 0; r < R; ++r) part[r] = 0.0f;
+            if constexpr (WIDE) {
 #pragma unroll 2
-            for (int jj = 0; jj < nj; ++jj) {
-                const double s0 = sy[jj][0], s1 = sy[jj][1], s2 = sy[jj][2], s3 = sy[jj][3];
-                const float w = sv[jj];
+                for (int jj = 0; jj < nj; ++jj) {
+                    const double s0v = sw[jj][0], s1 = sw[jj][1], s2 = sw[jj][2], s3 = sw[jj][3];
+                    const float w = sv[jj];
 #pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    double arg = ax[r] + s3;
-                    arg = fma(xs[r][0], s0, arg);
-                    if (D > 1) arg = fma(xs[r][1], s1, arg);
-                    if (D > 2) arg = fma(xs[r][2], s2, arg);
-                    part[r] = fmaf(w, __builtin_amdgcn_exp2f((float)arg), part[r]);
+                    for (int r = 0; r < R; ++r) {
+                        double arg = ax[r] + s3;
+                        arg = fma(xs[r][0], s0v, arg);
+                        if (D > 1) arg = fma(xs[r][1], s1, arg);
+                        if (D > 2) arg = fma(xs[r][2], s2, arg);
+                        part[r] = fmaf(w, __builtin_amdgcn_exp2f((float)arg), part[r]);
+                    }
+                }
+            } else {
+#pragma unroll 2
+                for (int jj = 0; jj < nj; ++jj) {
+                    const float4 y = sy[jj];
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        const float dx = xs[r][0] - y.x;
+                        float q = dx * dx;
+                        if (D > 1) {
+                            const float dy = xs[r][1] - y.y;
+                            q = fmaf(dy, dy, q);
+                        }
+                        if (D > 2) {
+                            const float dz = xs[r][2] - y.z;
+                            q = fmaf(dz, dz, q);
+                        }
+                        part[r] = fmaf(y.w, __builtin_amdgcn_exp2f(-q), part[r]);
+                    }
                 }
             }
 #pragma unroll
             for (int r = 0; r < R; ++r) acc[r] += (double)part[r];
-            j0 = j1;
-            nj = nj1;
-            have = have1;
         }
         MOT_GLOBAL double *out = gp(J.out);
 #pragma unroll
@@ -275,7 +331,7 @@ __global__ __launch_bounds__(64) void trunc_fp64_kernel(const ProdJob *__restric
 }
 
 template <int D>
-static void launch_trunc_d(int precision, int R, const ProdJob *jobs, const int4 *items, int n_items,
+static void launch_trunc_d(int precision, int R, int wide, const ProdJob *jobs, const int4 *items, int n_items,
                            hipStream_t s)
 {
     if (precision == MOT_PREC_FP64) {
@@ -285,21 +341,27 @@ static void launch_trunc_d(int precision, int R, const ProdJob *jobs, const int4
     } else {
         const int blocks = (n_items + kTruncWaves - 1) / kTruncWaves;
         const dim3 grid(blocks < (1 << 20) ? blocks : (1 << 20)), block(64 * kTruncWaves);
-        if (R == 1) hipLaunchKernelGGL((trunc_mixed_kernel<D, 1>), grid, block, 0, s, jobs, items, n_items);
-        if (R == 2) hipLaunchKernelGGL((trunc_mixed_kernel<D, 2>), grid, block, 0, s, jobs, items, n_items);
-        if (R == 4) hipLaunchKernelGGL((trunc_mixed_kernel<D, 4>), grid, block, 0, s, jobs, items, n_items);
+        if (wide) {
+            if (R == 1) hipLaunchKernelGGL((trunc_mixed_kernel<D, 1, true>), grid, block, 0, s, jobs, items, n_items);
+            if (R == 2) hipLaunchKernelGGL((trunc_mixed_kernel<D, 2, true>), grid, block, 0, s, jobs, items, n_items);
+            if (R == 4) hipLaunchKernelGGL((trunc_mixed_kernel<D, 4, true>), grid, block, 0, s, jobs, items, n_items);
+        } else {
+            if (R == 1) hipLaunchKernelGGL((trunc_mixed_kernel<D, 1, false>), grid, block, 0, s, jobs, items, n_items);
+            if (R == 2) hipLaunchKernelGGL((trunc_mixed_kernel<D, 2, false>), grid, block, 0, s, jobs, items, n_items);
+            if (R == 4) hipLaunchKernelGGL((trunc_mixed_kernel<D, 4, false>), grid, block, 0, s, jobs, items, n_items);
+        }
     }
 }
 
-hipError_t launch_trunc(int d, int precision, int R, const ProdJob *jobs_dev, const int4 *items, int n_items,
-                        hipStream_t s)
+hipError_t launch_trunc(int d, int precision, int R, int wide, const ProdJob *jobs_dev, const int4 *items,
+                        int n_items, hipStream_t s)
 {
     if (n_items == 0) return hipSuccess;
     if (R != 1 && R != 2 && R != 4) return hipErrorInvalidValue;
     if (precision == MOT_PREC_FP64 && R == 4) return hipErrorInvalidValue;
-    if (d == 1) launch_trunc_d<1>(precision, R, jobs_dev, items, n_items, s);
-    if (d == 2) launch_trunc_d<2>(precision, R, jobs_dev, items, n_items, s);
-    if (d == 3) launch_trunc_d<3>(precision, R, jobs_dev, items, n_items, s);
+    if (d == 1) launch_trunc_d<1>(precision, R, wide, jobs_dev, items, n_items, s);
+    if (d == 2) launch_trunc_d<2>(precision, R, wide, jobs_dev, items, n_items, s);
+    if (d == 3) launch_trunc_d<3>(precision, R, wide, jobs_dev, items, n_items, s);
     return hipGetLastError();
 }
 

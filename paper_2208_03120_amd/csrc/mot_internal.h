@@ -56,7 +56,7 @@ __device__ __forceinline__ void st2(float2 *p, int64_t i, float2 v)  // global s
 // (sorted) point order.
 struct ProdJob {
     int32_t d, path, precision;
-    int32_t diff;      // direct mixed path: exponent formed in FP64 (small eta)
+    int32_t diff;      // mixed direct / truncated paths: exponent formed in FP64
     // vectors
     const double *v;   // source vector, n_s entries
     int32_t *v_exp;    // slot holding max_j exponent(|v_j|) (atomicMax), reset per sweep
@@ -142,9 +142,11 @@ struct FinalJob {
 // ---------------------------------------------------------------------------------------
 // Kernel launchers (implemented in the .hip files).
 int direct_targets_per_item(int precision);
+constexpr int kMaxTruncRows = 400;  // neighbour rows per truncated work item, (2w + 1)^(d-1)
 // Truncated products: items int4 (job, first cell of a run of B cells of one row, first
 // sorted target, count | B << 16), count <= 64 * R; R = 1, 2 or 4 (FP64: 1 or 2).
-hipError_t launch_trunc(int d, int precision, int R, const ProdJob *jobs_dev, const int4 *items,
+// wide != 0 (mixed precision): exponent formed in FP64 instead of FP32 coordinate differences
+hipError_t launch_trunc(int d, int precision, int R, int wide, const ProdJob *jobs_dev, const int4 *items,
                         int n_items, hipStream_t s);
 // diff != 0: mixed-precision pairs with the exponent formed in FP64 (small eta)
 hipError_t launch_direct(int d, const ProdJob *jobs_dev, const int4 *items, int n_items,

@@ -412,10 +412,26 @@ int trunc_row_range(int d, const TruncParams &T, const int cc[3], int B, int ri,
     return 1;
 }
 
+// E[ceil(X / cap)] for a Poisson count X with mean lam (pmf in log space).
+static double expected_chunks(double lam, int cap)
+{
+    if (lam <= 0.0) return 0.0;
+    if (lam > 1e4) return lam / cap + 0.5;  // concentrated: ceil adds half an item on average
+    const double sd = std::sqrt(lam);
+    const int k0 = std::max(0, (int)std::floor(lam - 12.0 * sd - 5.0));
+    const int k1 = (int)std::ceil(lam + 12.0 * sd + 20.0);
+    double s = 0.0;
+    for (int k = std::max(k0, 1); k <= k1; ++k)
+        s += std::exp(k * std::log(lam) - lam - std::lgamma(k + 1.0)) * std::ceil((double)k / cap);
+    return s;
+}
+
 // Modelled wave cycles of one product: per row ~100, per 64-source stage ~200, per source
-// and target slot ~40.  tpc / spc: targets / sources per occupied cell; occ: occupied
-// target cells.
-double trunc_cost(int d, const TruncParams &T, double tpc, double spc, double occ, int B, int R)
+// and target slot ~40 (FP32 coordinate differences) or ~66 (FP64 exponent).  Points are
+// taken as Poisson counts per cell: lam_t / lam_s targets / sources per full cell (the
+// cloud's density times h^d).  A run of B cells holding k targets takes ceil(k / 64R)
+// items; the runs are those of the cells covering the cloud's box.
+double trunc_cost(int d, const TruncParams &T, double lam_t, double lam_s, int B, int R, bool wide)
 {
     const int span = 2 * T.w + 1;
     const int rows_total = d == 1 ? 1 : (d == 2 ? span : span * span);
@@ -430,27 +446,41 @@ double trunc_cost(int d, const TruncParams &T, double tpc, double spc, double oc
         rows += 1.0;
         cells += xb - xa + 1;
     }
-    const double runs = std::max(1.0, occ / B);
-    const double items = runs * std::max(1.0, std::ceil(tpc * B / (64.0 * R)));
-    const double src = cells * spc;
-    return items * (rows * 100.0 + (src / 64.0 + rows) * 200.0 + src * R * 40.0);
+    double runs = 1.0;
+    for (int c = 0; c < d - 1; ++c) runs *= T.box_cells[c];
+    runs *= std::ceil(T.box_cells[d - 1] / B);
+    const double items = runs * expected_chunks(lam_t * B, 64 * R);
+    const double src = cells * lam_s;
+    return items * (rows * 100.0 + (src / 64.0 + rows) * 200.0 + src * R * (wide ? 66.0 : 40.0));
 }
 
-void trunc_choose_run(int d, const TruncParams &T, double tpc, double spc, double occ, int max_r, int *B,
-                      int *R)
+// sqrt(log2(e) / eta) times the half-diagonal of a run of B cells: the largest scaled
+// coordinate of a target relative to the run's centre.  The FP32 form is used up to 3.
+static double run_extent(int d, const TruncParams &T, double sch, int B)
+{
+    return sch * std::sqrt(0.25 * B * B + 0.25 * (d - 1));
+}
+
+void trunc_choose_run(int d, const TruncParams &T, double lam_t, double lam_s, int max_r, double sch, bool fp64,
+                      int *B, int *R, int *wide)
 {
     double best = -1.0;
     *B = 1;
     *R = 1;
+    *wide = 0;
     for (int b : {1, 2, 3, 4, 6, 8, 12, 16}) {
         if (b > T.nc) break;
         for (int r : {1, 2, 4}) {
             if (r > max_r) break;
-            const double c = trunc_cost(d, T, tpc, spc, occ, b, r);
-            if (best < 0 || c < best) {
-                best = c;
-                *B = b;
-                *R = r;
+            for (int w = 0; w < 2; ++w) {
+                if (!fp64 && w == 0 && run_extent(d, T, sch, b) > 3.0) continue;
+                const double c = trunc_cost(d, T, lam_t, lam_s, b, r, fp64 || w == 1);
+                if (best < 0 || c < best) {
+                    best = c;
+                    *B = b;
+                    *R = r;
+                    *wide = fp64 ? 0 : w;
+                }
             }
         }
     }
@@ -480,12 +510,21 @@ int resolve_trunc(int d, double eta, const Extent &ext, const mot_fastsum_params
         C.nc = (int)ncd;
         C.q2 = q * q * (1.0 + 1e-6);
         C.w = 1 + (int)std::floor(std::sqrt(C.q2));
-        double occupied = 1.0;
-        for (int c = 0; c < d; ++c) occupied *= std::ceil(std::max(ext.hi[c] - ext.lo[c], 1e-300) / C.h);
-        occupied = std::min(occupied, std::max(n_mean, 1.0));
-        const double pc = std::max(n_mean, 1.0) / occupied;  // points per occupied cell
-        trunc_choose_run(d, C, pc, pc, occupied, 4, &C.B, &C.R);
-        const double cost = trunc_cost(d, C, pc, pc, occupied, C.B, C.R);
+        {
+            const int span = 2 * C.w + 1;
+            if ((d == 3 ? span * span : (d == 2 ? span : 1)) > kMaxTruncRows) continue;
+        }
+        double Vb = 1.0;
+        for (int c = 0; c < d; ++c) {
+            const double wc = std::max(ext.hi[c] - ext.lo[c], C.h);
+            C.box_cells[c] = wc / C.h;
+            Vb *= wc;
+        }
+        const double lam = std::max(n_mean, 1.0) * std::pow(C.h, d) / Vb;  // points per full cell
+        const double sch = std::sqrt(1.4426950408889634 / eta) * C.h;
+        int wide = 0;
+        trunc_choose_run(d, C, lam, lam, 4, sch, false, &C.B, &C.R, &wide);
+        const double cost = trunc_cost(d, C, lam, lam, C.B, C.R, wide != 0);
         if (best < 0 || cost < best) {
             best = cost;
             *out = C;

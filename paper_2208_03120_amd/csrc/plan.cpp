@@ -151,7 +151,7 @@ int run_steps(const std::vector<Step> &steps, hipStream_t s)
             MOT_HIP(launch_fill_int(st.fill_ptr, st.fill_value, st.fill_count, s));
             break;
         case ST_TRUNC:
-            MOT_HIP(launch_trunc(st.d, st.precision, st.trunc_r, (const ProdJob *)st.jobs,
+            MOT_HIP(launch_trunc(st.d, st.precision, st.trunc_r, st.diff, (const ProdJob *)st.jobs,
                                  (const int4 *)st.items, st.n_items, s));
             break;
         }
@@ -227,7 +227,7 @@ struct StepBuilder {
                   const std::vector<int> &ids)
     {
         std::map<std::tuple<int, int, int>, std::vector<int4>> direct;  // (d, precision, diff)
-        std::map<std::tuple<int, int, int>, std::vector<std::pair<double, int4>>> trunc;  // (d, prec, R)
+        std::map<std::tuple<int, int, int, int>, std::vector<std::pair<double, int4>>> trunc;  // (d, prec, R, wide)
         std::map<int, std::vector<int2>> spread, fold, interp;   // d
         std::map<int, std::vector<int32_t>> spread_pts, interp_pts;  // points of each item
         std::map<std::pair<int, int>, std::vector<int4>> fft[8]; // (d, n) per pass kind
@@ -243,7 +243,7 @@ struct StepBuilder {
             if (J.path == MOT_TRUNC) {
                 // items of at most 64 R targets from a run of B consecutive cells of one
                 // row (contiguous in the sorted order), costed by the sources they scan
-                auto &v = trunc[std::make_tuple(J.d, J.precision, J.trunc_r)];
+                auto &v = trunc[std::make_tuple(J.d, J.precision, J.trunc_r, J.diff)];
                 TruncParams TQ;
                 TQ.nc = J.nc;
                 TQ.w = J.tw;
@@ -326,6 +326,7 @@ struct StepBuilder {
             st.d = std::get<0>(kv.first);
             st.precision = std::get<1>(kv.first);
             st.trunc_r = std::get<2>(kv.first);
+            st.diff = std::get<3>(kv.first);
             st.jobs = jobs_dev;
             st.items = upload(its);
             st.n_items = (int)its.size();
@@ -770,15 +771,13 @@ int mot::make_prod_job(mot_plan_s *P, int t, int s, const double *v, int32_t *sl
         Q.h = T.h;
         Q.q2 = T.q2;
         for (int c = 0; c < 3; ++c) Q.glo[c] = T.glo[c];
-        // run length and targets per lane from the cost model at this pair's occupancy
-        auto occupied = [](const std::vector<int32_t> &off) {
-            int64_t occ = 0;
-            for (size_t c = 0; c + 1 < off.size(); ++c) occ += off[c + 1] > off[c];
-            return (double)std::max<int64_t>(occ, 1);
-        };
-        const double occ_t = occupied(P->marg[t].h_cell_off), occ_s = occupied(P->marg[s].h_cell_off);
-        trunc_choose_run(P->d, T, (double)Q.nt / occ_t, (double)Q.ns / occ_s, occ_t,
-                         P->precision == MOT_PREC_FP64 ? 2 : 4, &Q.trunc_b, &Q.trunc_r);
+        // run length, targets per lane and exponent form from the cost model at this pair's
+        // densities (points per grid cell)
+        double cells = 1.0;  // full cells covering the cloud's box
+        for (int c = 0; c < P->d; ++c) cells *= T.box_cells[c];
+        const bool fp64 = P->precision == MOT_PREC_FP64;
+        trunc_choose_run(P->d, T, (double)Q.nt / cells, (double)Q.ns / cells, fp64 ? 2 : 4,
+                         std::sqrt(1.4426950408889634 / Q.eta) * T.h, fp64, &Q.trunc_b, &Q.trunc_r, &Q.diff);
         return MOT_OK;
     }
     if (P->path != MOT_NFFT) return MOT_OK;

@@ -185,16 +185,19 @@ def test_full_size_root_marginal_sampled(mot, full):
 
 
 def test_runs_of_cells_fill_lanes(mot):
-    """Sparse cells (few points per cell at this eta): work items take runs of several
-    cells of a row; the products still bracket correctly, in both directions."""
+    """Sparse cells (few points per cell at small eta): the cost model takes runs of several
+    cells of a row per work item for at least one of these eta; the products bracket
+    correctly in both directions for all of them."""
     inst = W.make_instance(rng(270), 2, [2500, 2200], 2, W.TREE, 1e-4, parent=[-1, 0])
-    plan = mot.Plan(inst.points, inst.weights, W.TREE, inst.parent, 1e-4, path=mot.TRUNC)
-    info = plan.info()
-    assert info["chunk"] > 1, info
-    eps, rc = cutoff(inst.points, 1e-4)
-    for t, s in [(0, 1), (1, 0)]:
-        v = rng(271 + t).uniform(0.5, 1.5, inst.sizes[s])
-        got = plan.apply(t, s, v)
-        err = check_product(got, inst.points[t], inst.points[s], v, 1e-4, eps, rc, 2e-6)
-        assert err < 1e-5, err
-    plan.close()
+    runs = []
+    for eta in (1e-4, 3e-5, 1e-5):
+        plan = mot.Plan(inst.points, inst.weights, W.TREE, inst.parent, eta, path=mot.TRUNC)
+        runs.append(plan.info()["chunk"])
+        eps, rc = cutoff(inst.points, eta)
+        for t, s in [(0, 1), (1, 0)]:
+            v = rng(271 + t).uniform(0.5, 1.5, inst.sizes[s])
+            got = plan.apply(t, s, v)
+            err = check_product(got, inst.points[t], inst.points[s], v, eta, eps, rc, 2e-6)
+            assert err < 1e-5, (eta, err)
+        plan.close()
+    assert max(runs) > 1, runs
