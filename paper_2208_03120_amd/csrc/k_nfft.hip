@@ -390,22 +390,22 @@ __global__ __launch_bounds__(64 * kSpreadWaves, 4) void spread_kernel(const Prod
 constexpr int kFoldMaxCover = 4;
 
 // Fold (a2, second half): box grid cell g = sum of the patches covering it, tiles in
-// ascending order and chunks in ascending order within a tile.  One wavefront folds one
-// line of cells along the last dimension, so the covering tiles of the leading
-// dimensions are the same on every lane; item = (job, first of kFoldLinesPerItem lines).
+// ascending order and chunks in ascending order within a tile.  One thread folds one
+// cell; an item is kFoldCellsPerItem consecutive cells of the box in row-major order
+// (lines of the last dimension back to back, so every lane has a cell even when a line
+// is shorter than a wavefront); item = (job, first cell).
 template <int D>
-__global__ __launch_bounds__(64 * kFoldLinesPerItem) void fold_kernel(const ProdJob *__restrict__ jobs,
-                                                                      const int2 *__restrict__ items,
-                                                                      int n_items)
+__global__ __launch_bounds__(kFoldCellsPerItem) void fold_kernel(const ProdJob *__restrict__ jobs,
+                                                                 const int2 *__restrict__ items, int n_items)
 {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
         const int2 itm = items[it];
         const ProdJob &J = jobs[itm.x];
-        const int line = itm.y + wave;
-        const int nl = D == 3 ? J.L[0] * J.L[1] : (D == 2 ? J.L[0] : 1);
-        if (line >= nl) continue;
         const int W = J.W, T = J.T, Ll = J.L[D - 1], ntl = J.ntile[D - 1];
+        const int nl = D == 3 ? J.L[0] * J.L[1] : (D == 2 ? J.L[0] : 1);
+        const int f = itm.y + (int)threadIdx.x;
+        if (f >= nl * Ll) continue;
+        const int line = f / Ll, g = f - line * Ll;
         int gu[2] = {0, 0};  // line coordinates in the leading dimensions
         if (D == 3) {
             gu[0] = line / J.L[1];
@@ -421,55 +421,20 @@ __global__ __launch_bounds__(64 * kFoldLinesPerItem) void fold_kernel(const Prod
         const int pe = D == 3 ? W * W * W : (D == 2 ? W * W : W);
         const MOT_GLOBAL int32_t *tch = gp(J.src_tile_chunks);
         const MOT_GLOBAL float *pat = gp(J.patches);
-        MOT_GLOBAL float *out = gp(J.grid) + (int64_t)line * Ll;
-        for (int g = lane; g < Ll; g += 64) {
-            const int t2lo = max(0, floor_div(g - W + T, T)), t2hi = min(ntl - 1, g / T);
-            float acc = 0.0f;
-            if (W <= kFoldMaxCover * T) {
-                // at most kFoldMaxCover covering tiles per dimension: the chunk ranges and
-                // first patches of all (t1, t2) pairs of a t0 are loaded together, then
-                // added in the fixed order
-                constexpr int NU = D == 3 ? kFoldMaxCover : 1;
-                for (int t0 = tlo[0]; t0 <= thi[0]; ++t0) {
-                    int c0[NU][kFoldMaxCover], c1[NU][kFoldMaxCover], loc[NU][kFoldMaxCover];
+        const int t2lo = max(0, floor_div(g - W + T, T)), t2hi = min(ntl - 1, g / T);
+        float acc = 0.0f;
+        if (W <= kFoldMaxCover * T) {
+            // at most kFoldMaxCover covering tiles per dimension: the chunk ranges and first
+            // patches of all (t1, t2) pairs of a t0 are loaded together, then added in the
+            // fixed order
+            constexpr int NU = D == 3 ? kFoldMaxCover : 1;
+            for (int t0 = tlo[0]; t0 <= thi[0]; ++t0) {
+                int c0[NU][kFoldMaxCover], c1[NU][kFoldMaxCover], loc[NU][kFoldMaxCover];
 #pragma unroll
-                    for (int u = 0; u < NU; ++u)
+                for (int u = 0; u < NU; ++u)
 #pragma unroll
-                        for (int k = 0; k < kFoldMaxCover; ++k) {
-                            const int t1 = tlo[1] + u, t2 = t2lo + k;
-                            int lead_tile = 0, lead_loc = 0;
-                            if constexpr (D == 3) {
-                                lead_tile = t0 * J.ntile[1] + t1;
-                                lead_loc = (gu[0] - t0 * T) * W + (gu[1] - t1 * T);
-                            } else if constexpr (D == 2) {
-                                lead_tile = t0;
-                                lead_loc = gu[0] - t0 * T;
-                            }
-                            c0[u][k] = c1[u][k] = 0;
-                            loc[u][k] = lead_loc * W + (g - t2 * T);
-                            if ((D < 3 || t1 <= thi[1]) && t2 <= t2hi) {
-                                const int tl = lead_tile * ntl + t2;
-                                c0[u][k] = tch[tl];
-                                c1[u][k] = tch[tl + 1];
-                            }
-                        }
-                    float first[NU][kFoldMaxCover];
-#pragma unroll
-                    for (int u = 0; u < NU; ++u)
-#pragma unroll
-                        for (int k = 0; k < kFoldMaxCover; ++k)
-                            first[u][k] = c1[u][k] > c0[u][k] ? pat[(int64_t)c0[u][k] * pe + loc[u][k]] : 0.0f;
-#pragma unroll
-                    for (int u = 0; u < NU; ++u)
-#pragma unroll
-                        for (int k = 0; k < kFoldMaxCover; ++k) {
-                            if (c1[u][k] > c0[u][k]) acc += first[u][k];
-                            for (int ch = c0[u][k] + 1; ch < c1[u][k]; ++ch) acc += pat[(int64_t)ch * pe + loc[u][k]];
-                        }
-                }
-            } else {
-                for (int t0 = tlo[0]; t0 <= thi[0]; ++t0)
-                    for (int t1 = tlo[1]; t1 <= thi[1]; ++t1) {
+                    for (int k = 0; k < kFoldMaxCover; ++k) {
+                        const int t1 = tlo[1] + u, t2 = t2lo + k;
                         int lead_tile = 0, lead_loc = 0;
                         if constexpr (D == 3) {
                             lead_tile = t0 * J.ntile[1] + t1;
@@ -478,16 +443,48 @@ __global__ __launch_bounds__(64 * kFoldLinesPerItem) void fold_kernel(const Prod
                             lead_tile = t0;
                             lead_loc = gu[0] - t0 * T;
                         }
-                        for (int t2 = t2lo; t2 <= t2hi; ++t2) {
+                        c0[u][k] = c1[u][k] = 0;
+                        loc[u][k] = lead_loc * W + (g - t2 * T);
+                        if ((D < 3 || t1 <= thi[1]) && t2 <= t2hi) {
                             const int tl = lead_tile * ntl + t2;
-                            const int lc = lead_loc * W + (g - t2 * T);
-                            const int ca = tch[tl], cb = tch[tl + 1];
-                            for (int ch = ca; ch < cb; ++ch) acc += pat[(int64_t)ch * pe + lc];
+                            c0[u][k] = tch[tl];
+                            c1[u][k] = tch[tl + 1];
                         }
                     }
+                float first[NU][kFoldMaxCover];
+#pragma unroll
+                for (int u = 0; u < NU; ++u)
+#pragma unroll
+                    for (int k = 0; k < kFoldMaxCover; ++k)
+                        first[u][k] = c1[u][k] > c0[u][k] ? pat[(int64_t)c0[u][k] * pe + loc[u][k]] : 0.0f;
+#pragma unroll
+                for (int u = 0; u < NU; ++u)
+#pragma unroll
+                    for (int k = 0; k < kFoldMaxCover; ++k) {
+                        if (c1[u][k] > c0[u][k]) acc += first[u][k];
+                        for (int ch = c0[u][k] + 1; ch < c1[u][k]; ++ch) acc += pat[(int64_t)ch * pe + loc[u][k]];
+                    }
             }
-            out[g] = acc;
+        } else {
+            for (int t0 = tlo[0]; t0 <= thi[0]; ++t0)
+                for (int t1 = tlo[1]; t1 <= thi[1]; ++t1) {
+                    int lead_tile = 0, lead_loc = 0;
+                    if constexpr (D == 3) {
+                        lead_tile = t0 * J.ntile[1] + t1;
+                        lead_loc = (gu[0] - t0 * T) * W + (gu[1] - t1 * T);
+                    } else if constexpr (D == 2) {
+                        lead_tile = t0;
+                        lead_loc = gu[0] - t0 * T;
+                    }
+                    for (int t2 = t2lo; t2 <= t2hi; ++t2) {
+                        const int tl = lead_tile * ntl + t2;
+                        const int lc = lead_loc * W + (g - t2 * T);
+                        const int ca = tch[tl], cb = tch[tl + 1];
+                        for (int ch = ca; ch < cb; ++ch) acc += pat[(int64_t)ch * pe + lc];
+                    }
+                }
         }
+        gp(J.grid)[(int64_t)line * Ll + g] = acc;
     }
 }
 
@@ -635,13 +632,13 @@ hipError_t launch_fold(int d, const ProdJob *jobs, const int2 *items, int n_item
 {
     if (n_items == 0) return hipSuccess;
     if (d == 3)
-        hipLaunchKernelGGL(fold_kernel<3>, dim3(nfft_grid(n_items)), dim3(64 * kFoldLinesPerItem), 0, s, jobs, items,
+        hipLaunchKernelGGL(fold_kernel<3>, dim3(nfft_grid(n_items)), dim3(kFoldCellsPerItem), 0, s, jobs, items,
                            n_items);
     else if (d == 2)
-        hipLaunchKernelGGL(fold_kernel<2>, dim3(nfft_grid(n_items)), dim3(64 * kFoldLinesPerItem), 0, s, jobs, items,
+        hipLaunchKernelGGL(fold_kernel<2>, dim3(nfft_grid(n_items)), dim3(kFoldCellsPerItem), 0, s, jobs, items,
                            n_items);
     else
-        hipLaunchKernelGGL(fold_kernel<1>, dim3(nfft_grid(n_items)), dim3(64 * kFoldLinesPerItem), 0, s, jobs, items,
+        hipLaunchKernelGGL(fold_kernel<1>, dim3(nfft_grid(n_items)), dim3(kFoldCellsPerItem), 0, s, jobs, items,
                            n_items);
     return hipGetLastError();
 }

@@ -281,7 +281,8 @@ struct StepBuilder {
             for (int c = 0; c < J.src_nchunks; ++c)
                 spread_pts[J.d].push_back(J.h_src_chunk_start[c + 1] - J.h_src_chunk_start[c]);
             const int lines = J.d == 3 ? J.L[0] * J.L[1] : (J.d == 2 ? J.L[0] : 1);
-            for (int l = 0; l < lines; l += kFoldLinesPerItem) fold[J.d].push_back(make_int2(j, l));
+            const int cells = lines * J.L[J.d - 1];
+            for (int f = 0; f < cells; f += kFoldCellsPerItem) fold[J.d].push_back(make_int2(j, f));
             for (int c = 0; c < J.tgt_nchunks; ++c) {
                 interp[J.d].push_back(make_int2(j, c));
                 interp_pts[J.d].push_back(J.h_tgt_chunk_start[c + 1] - J.h_tgt_chunk_start[c]);

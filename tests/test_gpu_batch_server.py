@@ -116,3 +116,36 @@ def test_server_admission_slots_and_footprint(mot):
     rc, t = tiny.submit(reqs[0])
     assert rc == mot.ENOMEM and t is None
     tiny.close()
+
+
+def test_server_serves_truncated_path_requests(mot):
+    """Small-eta tree requests on the truncated path served in a mix with NFFT requests:
+    each equals its stand-alone result bitwise and the oracle's Algorithm 2 for the same
+    sweeps (gauge-fixed, 1e-5)."""
+    r = np.random.Generator(np.random.PCG64(77))
+    reqs, paths = [], []
+    for i in range(6):
+        small = i % 2 == 0
+        eta = 2e-3 if small else 0.05
+        inst = W.make_instance(r, 3, [int(x) for x in r.integers(300, 700, 3)], 2, W.TREE, eta,
+                               parent=[-1, 0, 0])
+        reqs.append(inst)
+        paths.append(mot.TRUNC if small else mot.NFFT)
+    srv = mot.Server(hbm_budget=8 << 30, max_slots=8)
+    tickets = [srv.submit(q, tol=1e-6, max_sweeps=400, path=p)[1] for q, p in zip(reqs, paths)]
+    srv.run(60.0, idle_exit=True)
+    res = [srv.fetch(t, want_phi=True) for t in tickets]
+    srv.close()
+    assert all(x is not None and x["status"] in (mot.OK, mot.MAXITER) for x in res)
+    for q, p, x in zip(reqs, paths, res):
+        solo = mot.Server(hbm_budget=8 << 30, max_slots=1)
+        _, t = solo.submit(q, tol=1e-6, max_sweeps=400, path=p)
+        solo.run(60.0, idle_exit=True)
+        y = solo.fetch(t, want_phi=True)
+        solo.close()
+        assert y["sweeps"] == x["sweeps"]
+        for a, b in zip(y["phi"], x["phi"]):
+            np.testing.assert_array_equal(a, b)
+        if p == mot.TRUNC:
+            ophi, _, _, _ = oracle.tree_sinkhorn(q.points, q.weights, q.parent, q.eta, x["sweeps"])
+            assert max_rel(gauge_fix(x["phi"], q.weights), gauge_fix(ophi, q.weights)) < 1e-5
