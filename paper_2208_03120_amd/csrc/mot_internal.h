@@ -178,7 +178,7 @@ hipError_t launch_window_rows(int d, int64_t npts, const double *pts, double s, 
 
 // NFFT pipeline kernels (a2-a6).
 constexpr int kNodeItemElems = 512;  // elements per node / finalisation item
-constexpr int kFoldCellsPerItem = 256;  // box cells per fold item (one per thread)
+constexpr int kFoldCellsPerItem = 128;  // box cells per fold item (one per thread)
 constexpr int kFftLinesPerItem = 16;
 hipError_t launch_spread(int d, const ProdJob *jobs, const int2 *items, int n_items,
                          int max_patch_elems, hipStream_t s);
