@@ -33,12 +33,12 @@ PEAK_FP32_TFLOPS = 157.3  # dense FP32 MFMA
 # only for the kernel source it was measured on (SHA-256 of the file that holds it).
 COPY_MIB = 256
 TRAFFIC = {
-    "spread": {"bytes_per_launch": 204200850, "source": "k_nfft.hip",
-               "sha256": "de160639622eb225878cd7f4df77f6ce6df143988eee2bd556251e2555fe3630"},
-    "fold": {"bytes_per_launch": 65736700, "source": "k_nfft.hip",
-               "sha256": "de160639622eb225878cd7f4df77f6ce6df143988eee2bd556251e2555fe3630"},
-    "interp": {"bytes_per_launch": 205178665, "source": "k_nfft.hip",
-               "sha256": "de160639622eb225878cd7f4df77f6ce6df143988eee2bd556251e2555fe3630"},
+    "spread": {"bytes_per_launch": 204197063, "source": "k_nfft.hip",
+               "sha256": "bdb0c66f19102ceb9bf9d51090cbe94651896c0248c6a244c16f5f5b8a692749"},
+    "fold": {"bytes_per_launch": 79191056, "source": "k_nfft.hip",
+               "sha256": "bdb0c66f19102ceb9bf9d51090cbe94651896c0248c6a244c16f5f5b8a692749"},
+    "interp": {"bytes_per_launch": 205204893, "source": "k_nfft.hip",
+               "sha256": "bdb0c66f19102ceb9bf9d51090cbe94651896c0248c6a244c16f5f5b8a692749"},
     "fft6": {"bytes_per_launch": 10832544, "source": "k_fft.hip",
              "sha256": "0fdb613e3aa356b695e37243d8a0803c82e512974bd0f3a4f21196a7c2e62e6f"},
     "fft5": {"bytes_per_launch": 28822253, "source": "k_fft.hip",

@@ -29,6 +29,28 @@ int hip_fail(hipError_t e, const char *what, const char *file, int line);
 void log_msg(const char *fmt, ...);
 
 // ---------------------------------------------------------------------------------------
+// A temporary device buffer of one C-ABI call, released on every return path (hipFree
+// waits for the work still using it).
+struct DevTmp {
+    void *p = nullptr;
+    int alloc(size_t bytes)
+    {
+        if (hipMalloc(&p, bytes ? bytes : 1) != hipSuccess) {
+            (void)hipGetLastError();
+            p = nullptr;
+            return MOT_ENOMEM;
+        }
+        return MOT_OK;
+    }
+    template <class T>
+    T *as() const { return (T *)p; }
+    ~DevTmp()
+    {
+        if (p) (void)hipFree(p);
+    }
+};
+
+// ---------------------------------------------------------------------------------------
 // Device memory owned by a plan (through the caller's allocator or hipMalloc).
 struct Arena {
     mot_allocator alloc{};

@@ -1236,32 +1236,29 @@ int mot_pair_marginal(mot_plan P, int32_t k, double *out, int32_t ptr_kind)
     if (!P || !out || k < 1 || k >= P->K) return MOT_EINVAL;
     const int a = P->topology == MOT_CIRCLE ? 0 : P->parent[k];
     const size_t count = (size_t)P->n[a] * (size_t)P->n[k];
-    double *dst = nullptr;
-    if (ptr_kind == MOT_DEVICE) {
-        dst = out;
-    } else if (hipMalloc(&dst, count * sizeof(double)) != hipSuccess) {
-        (void)hipGetLastError();
-        return MOT_ENOMEM;
+    DevTmp buf;
+    double *dst = out;
+    if (ptr_kind != MOT_DEVICE) {
+        MOT_TRY(buf.alloc(count * sizeof(double)));
+        dst = buf.as<double>();
     }
-    int rc = MOT_OK;
-    if (P->topology == MOT_CIRCLE) {
-        rc = circle_pair_marginal(P, k, dst);
-    } else {
-        // a consistent pass at the current phi (as in mot_marginals): the down source of
-        // k at its parent and the up source of k are then the two outer factors
+    auto body = [&]() -> int {
+        if (P->topology == MOT_CIRCLE) return circle_pair_marginal(P, k, dst);
+        // a consistent pass at the current phi (as in mot_marginals): the down source of k
+        // at its parent and the up source of k are then the two outer factors
         MOT_HIP(launch_fill_int(P->exp_slots, INT32_MIN, 2 * P->K + 1, P->stream));
-        rc = run_steps(P->sched.marg_pass, P->stream);
-        if (rc >= 0) {
-            MOT_HIP(launch_fill_int(P->exp_slots, INT32_MIN, 2 * P->K + 1, P->stream));
-            MOT_HIP(launch_tree_pair(P->marg[k].down_src, P->marg[a].pts, P->marg[a].perm, P->n[a],
-                                     P->marg[k].up_src, P->marg[k].pts, P->marg[k].perm, P->n[k], P->d,
-                                     P->jobs[2 * k + 1].eta, dst, P->stream));
-        }
-    }
-    if (rc >= 0 && ptr_kind != MOT_DEVICE)
-        MOT_HIP(hipMemcpyAsync(out, dst, count * sizeof(double), hipMemcpyDeviceToHost, P->stream));
-    MOT_HIP(hipStreamSynchronize(P->stream));
-    if (ptr_kind != MOT_DEVICE) (void)hipFree(dst);
+        MOT_TRY(run_steps(P->sched.marg_pass, P->stream));
+        MOT_HIP(launch_fill_int(P->exp_slots, INT32_MIN, 2 * P->K + 1, P->stream));
+        MOT_HIP(launch_tree_pair(P->marg[k].down_src, P->marg[a].pts, P->marg[a].perm, P->n[a], P->marg[k].up_src,
+                                 P->marg[k].pts, P->marg[k].perm, P->n[k], P->d, P->jobs[2 * k + 1].eta, dst,
+                                 P->stream));
+        return MOT_OK;
+    };
+    int rc = body();
+    if (rc >= 0 && ptr_kind != MOT_DEVICE &&
+        hipMemcpyAsync(out, dst, count * sizeof(double), hipMemcpyDeviceToHost, P->stream) != hipSuccess)
+        rc = MOT_EDEVICE;
+    if (hipStreamSynchronize(P->stream) != hipSuccess && rc >= 0) rc = MOT_EDEVICE;
     return rc;
 }
 
@@ -1426,22 +1423,18 @@ int mot_get_S_history(mot_plan P, double *S_out, int32_t count)
 static int scatter_out(mot_plan P, double *const *src_sorted, double *dst, int ptr_kind)
 {
     // binned order -> original order, concatenated
-    double *tmp = nullptr;
     const int64_t total = P->off[P->K];
-    if (ptr_kind == MOT_DEVICE) {
-        tmp = dst;
-    } else {
-        if (hipMalloc(&tmp, total * sizeof(double)) != hipSuccess) return MOT_ENOMEM;
+    DevTmp buf;
+    double *tmp = dst;
+    if (ptr_kind != MOT_DEVICE) {
+        MOT_TRY(buf.alloc(total * sizeof(double)));
+        tmp = buf.as<double>();
     }
     for (int k = 0; k < P->K; ++k)
         MOT_HIP(launch_scatter_vec(src_sorted[k], P->marg[k].perm, P->n[k], tmp + P->off[k], P->stream));
-    if (ptr_kind != MOT_DEVICE) {
+    if (ptr_kind != MOT_DEVICE)
         MOT_HIP(hipMemcpyAsync(dst, tmp, total * sizeof(double), hipMemcpyDeviceToHost, P->stream));
-        MOT_HIP(hipStreamSynchronize(P->stream));
-        (void)hipFree(tmp);
-    } else {
-        MOT_HIP(hipStreamSynchronize(P->stream));
-    }
+    MOT_HIP(hipStreamSynchronize(P->stream));
     return MOT_OK;
 }
 
@@ -1457,18 +1450,16 @@ int mot_set_scalings(mot_plan P, const double *phi_in, int32_t ptr_kind)
 {
     if (!P || !phi_in) return MOT_EINVAL;
     const int64_t total = P->off[P->K];
-    double *tmp = nullptr;
-    if (hipMalloc(&tmp, total * sizeof(double)) != hipSuccess) return MOT_ENOMEM;
+    DevTmp buf;
+    MOT_TRY(buf.alloc(total * sizeof(double)));
+    double *tmp = buf.as<double>();
     MOT_HIP(hipMemcpyAsync(tmp, phi_in, total * sizeof(double),
                            ptr_kind == MOT_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
                            P->stream));
     for (int k = 0; k < P->K; ++k)
         MOT_HIP(launch_gather_rows(tmp + P->off[k], P->marg[k].perm, P->n[k], 1, P->marg[k].phi, P->stream));
-    int rc = MOT_OK;
-    if (P->topology == MOT_TREE) rc = tree_init_up(P);
+    if (P->topology == MOT_TREE) MOT_TRY(tree_init_up(P));
     MOT_HIP(hipStreamSynchronize(P->stream));
-    (void)hipFree(tmp);
-    if (rc < 0) return rc;
     if (P->topology == MOT_CIRCLE) return circle_run_sweeps(P, 0);
     return MOT_OK;
 }
@@ -1527,8 +1518,9 @@ int mot_apply_kernel(mot_plan P, int32_t t, int32_t s, const double *v, double *
         P->apply_cap = cap;
     }
     // v (original order) -> binned order of s
-    double *tmp = nullptr;
-    if (hipMalloc(&tmp, (P->n[s] + P->n[t]) * sizeof(double)) != hipSuccess) return MOT_ENOMEM;
+    DevTmp buf;
+    MOT_TRY(buf.alloc((P->n[s] + P->n[t]) * sizeof(double)));
+    double *tmp = buf.as<double>();
     MOT_HIP(hipMemcpyAsync(tmp, v, P->n[s] * sizeof(double),
                            ptr_kind == MOT_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
                            P->stream));
@@ -1566,7 +1558,6 @@ int mot_apply_kernel(mot_plan P, int32_t t, int32_t s, const double *v, double *
                            ptr_kind == MOT_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
                            P->stream));
     MOT_HIP(hipStreamSynchronize(P->stream));
-    (void)hipFree(tmp);
     return MOT_OK;
 }
 
@@ -1582,15 +1573,16 @@ int mot_bin_points(int32_t d, int64_t npts, const double *x, const double *s, co
     for (int c = 0; c < d; ++c) ntiles *= tpd;
     if (ntiles > ((int64_t)1 << 30)) return MOT_EINVAL;
     const size_t sb = stable_tile_sort_scratch(npts, ntiles);
-    double *xd = nullptr;
-    int32_t *cd = nullptr, *td = nullptr, *pd = nullptr, *od = nullptr;
-    void *scratch = nullptr;
-    MOT_HIP(hipMalloc(&xd, std::max<int64_t>(npts, 1) * d * sizeof(double)));
-    MOT_HIP(hipMalloc(&cd, std::max<int64_t>(npts, 1) * d * sizeof(int32_t)));
-    MOT_HIP(hipMalloc(&td, std::max<int64_t>(npts, 1) * sizeof(int32_t)));
-    MOT_HIP(hipMalloc(&pd, std::max<int64_t>(npts, 1) * sizeof(int32_t)));
-    MOT_HIP(hipMalloc(&od, (ntiles + 1) * sizeof(int32_t)));
-    MOT_HIP(hipMalloc(&scratch, sb));
+    DevTmp bx, bc, bt, bp, bo, bs;
+    MOT_TRY(bx.alloc(std::max<int64_t>(npts, 1) * d * sizeof(double)));
+    MOT_TRY(bc.alloc(std::max<int64_t>(npts, 1) * d * sizeof(int32_t)));
+    MOT_TRY(bt.alloc(std::max<int64_t>(npts, 1) * sizeof(int32_t)));
+    MOT_TRY(bp.alloc(std::max<int64_t>(npts, 1) * sizeof(int32_t)));
+    MOT_TRY(bo.alloc((ntiles + 1) * sizeof(int32_t)));
+    MOT_TRY(bs.alloc(sb));
+    double *xd = bx.as<double>();
+    int32_t *cd = bc.as<int32_t>(), *td = bt.as<int32_t>(), *pd = bp.as<int32_t>(), *od = bo.as<int32_t>();
+    void *scratch = bs.p;
     const hipMemcpyKind kin = ptr_kind == MOT_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
     const hipMemcpyKind kout = ptr_kind == MOT_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
     if (npts > 0) MOT_HIP(hipMemcpyAsync(xd, x, npts * d * sizeof(double), kin, st));
@@ -1603,12 +1595,6 @@ int mot_bin_points(int32_t d, int64_t npts, const double *x, const double *s, co
     }
     MOT_HIP(hipMemcpyAsync(tile_off, od, (ntiles + 1) * sizeof(int32_t), kout, st));
     MOT_HIP(hipStreamSynchronize(st));
-    (void)hipFree(xd);
-    (void)hipFree(cd);
-    (void)hipFree(td);
-    (void)hipFree(pd);
-    (void)hipFree(od);
-    (void)hipFree(scratch);
     return MOT_OK;
 }
 
