@@ -227,11 +227,28 @@ __global__ __launch_bounds__(256) void finalize_kernel(const FinalJob *__restric
                 cp[k] = 1.0;
                 ok[k] = (int64_t)itm.y + tid + 256 * k < J.n0;
             }
-            for (int t = 0; t < J.nchild; ++t) {
-                const MOT_GLOBAL double *bt = gp(gp(J.root_beta)[t]);
+            if (J.nchild <= kRegChildren) {
+                // all children's messages loaded before the products, so the loads are in
+                // flight together; multiplied in ascending child order
+                double b[kRegChildren][kNodeEPT];
 #pragma unroll
-                for (int k = 0; k < kNodeEPT; ++k)
-                    if (ok[k]) cp[k] *= bt[(int64_t)itm.y + tid + 256 * k];
+                for (int t = 0; t < kRegChildren; ++t)
+#pragma unroll
+                    for (int k = 0; k < kNodeEPT; ++k)
+                        b[t][k] = (t < J.nchild && ok[k]) ? gp(gp(J.root_beta)[t])[(int64_t)itm.y + tid + 256 * k]
+                                                          : 1.0;
+#pragma unroll
+                for (int t = 0; t < kRegChildren; ++t)
+#pragma unroll
+                    for (int k = 0; k < kNodeEPT; ++k)
+                        if (t < J.nchild) cp[k] *= b[t][k];
+            } else {
+                for (int t = 0; t < J.nchild; ++t) {
+                    const MOT_GLOBAL double *bt = gp(gp(J.root_beta)[t]);
+#pragma unroll
+                    for (int k = 0; k < kNodeEPT; ++k)
+                        if (ok[k]) cp[k] *= bt[(int64_t)itm.y + tid + 256 * k];
+                }
             }
 #pragma unroll
             for (int k = 0; k < kNodeEPT; ++k) {
