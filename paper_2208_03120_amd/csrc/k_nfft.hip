@@ -55,13 +55,21 @@ hipError_t launch_bin_cells(int d, int64_t npts, const double *x, double s0, dou
     return hipGetLastError();
 }
 
-// Stable sort by tile: bitonic sort of the unique 64-bit keys (tile << 32 | index).
+// Stable sort by tile: bitonic sort of the unique 64-bit keys (tile << 32 | index).  With
+// a sub-key (cell != nullptr) the key is ((tile << kSubBits | r) << 32 | index), where r
+// is the point's tile-relative cell in dimension sub_dim: points of a tile then come in
+// ascending r, ties in index order.
+constexpr int kSubBits = 4;
+
 __global__ void make_keys_kernel(int64_t npts, int64_t npad, const int32_t *__restrict__ tile,
+                                 const int32_t *__restrict__ cell, int d, int sub_dim, int T,
                                  uint64_t *__restrict__ keys)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= npad) return;
-    keys[i] = i < npts ? (((uint64_t)(uint32_t)tile[i]) << 32) | (uint64_t)i : ~0ull;
+    uint64_t hi = i < npts ? (uint64_t)(uint32_t)tile[i] : 0;
+    if (cell != nullptr && i < npts) hi = (hi << kSubBits) | (uint64_t)(cell[i * d + sub_dim] % T);
+    keys[i] = i < npts ? (hi << 32) | (uint64_t)i : ~0ull;
 }
 
 // One global compare-exchange step (k, j) of the bitonic network.
@@ -112,12 +120,12 @@ __global__ __launch_bounds__(512) void bitonic_local_kernel(uint64_t *keys, int6
 }
 
 __global__ void keys_to_perm_kernel(int64_t npts, int64_t ntiles, const uint64_t *__restrict__ keys,
-                                    int32_t *__restrict__ perm, int32_t *__restrict__ tile_off)
+                                    int shift, int32_t *__restrict__ perm, int32_t *__restrict__ tile_off)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i > npts) return;
-    int64_t t_prev = i == 0 ? -1 : (int64_t)(keys[i - 1] >> 32);
-    int64_t t_cur = i == npts ? ntiles : (int64_t)(keys[i] >> 32);
+    int64_t t_prev = i == 0 ? -1 : (int64_t)(keys[i - 1] >> shift);
+    int64_t t_cur = i == npts ? ntiles : (int64_t)(keys[i] >> shift);
     if (i < npts) perm[i] = (int32_t)(keys[i] & 0xffffffffull);
     for (int64_t t = t_prev + 1; t <= t_cur; ++t) tile_off[t] = (int32_t)i;
 }
@@ -130,14 +138,19 @@ size_t stable_tile_sort_scratch(int64_t npts, int64_t /*ntiles*/)
 }
 
 hipError_t stable_tile_sort(int64_t npts, const int32_t *tile, int64_t ntiles, int32_t *perm,
-                            int32_t *tile_off, void *scratch, size_t scratch_bytes, hipStream_t st)
+                            int32_t *tile_off, void *scratch, size_t scratch_bytes, hipStream_t st,
+                            const int32_t *cell, int d, int sub_dim, int T)
 {
     int64_t npad = 1024;
     while (npad < npts) npad <<= 1;
     if (scratch_bytes < (size_t)npad * sizeof(uint64_t)) return hipErrorInvalidValue;
+    if (cell != nullptr && (T > (1 << kSubBits) || sub_dim < 0 || sub_dim >= d ||
+                            ntiles >= ((int64_t)1 << (32 - kSubBits))))
+        return hipErrorInvalidValue;
     uint64_t *keys = (uint64_t *)scratch;
     int blocks = (int)((npad + 255) / 256);
-    hipLaunchKernelGGL(make_keys_kernel, dim3(blocks), dim3(256), 0, st, npts, npad, tile, keys);
+    hipLaunchKernelGGL(make_keys_kernel, dim3(blocks), dim3(256), 0, st, npts, npad, tile, cell, d, sub_dim,
+                       T, keys);
     int lblocks = (int)(npad / 1024);
     hipLaunchKernelGGL(bitonic_local_kernel, dim3(lblocks), dim3(512), 0, st, keys, npad,
                        (int64_t)0, 1);
@@ -149,7 +162,7 @@ hipError_t stable_tile_sort(int64_t npts, const int32_t *tile, int64_t ntiles, i
     }
     int pblocks = (int)((npts + 1 + 255) / 256);
     hipLaunchKernelGGL(keys_to_perm_kernel, dim3(pblocks), dim3(256), 0, st, npts, ntiles, keys,
-                       perm, tile_off);
+                       cell != nullptr ? 32 + kSubBits : 32, perm, tile_off);
     return hipGetLastError();
 }
 
@@ -337,8 +350,11 @@ __global__ __launch_bounds__(64 * kSpreadWaves, 4) void spread_kernel(const Prod
                         const f32x4 w1 = r1[q];
 #pragma unroll
                         for (int u = 0; u < 4; ++u)
-                            acc[4 * q + u] = __builtin_amdgcn_mfma_f32_16x16x4f32(x, w1[u] * w2, acc[4 * q + u],
-                                                                                  0, 0, 0);
+                            // B is zero when b = 4 q + u is outside the window of all four
+                            // points: the product would add exact zeros
+                            if (__any(w1[u] != 0.0f))
+                                acc[4 * q + u] = __builtin_amdgcn_mfma_f32_16x16x4f32(x, w1[u] * w2,
+                                                                                      acc[4 * q + u], 0, 0, 0);
                     }
                 } else if constexpr (D == 2) {
                     acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(x, row[kPatch + li], acc[0], 0, 0, 0);
@@ -576,6 +592,9 @@ __global__ __launch_bounds__(64 * kInterpWaves, 4) void interp_kernel(const Prod
                         const f32x4 wy = r1[q];
 #pragma unroll
                         for (int u = 0; u < 4; ++u) {
+                            // A is zero when b is outside the window of all 16 points: the
+                            // four products would add exact zeros
+                            if (!__any(wy[u] != 0.0f)) continue;
                             const int s = 16 * q + 4 * u;  // b = 4 q + u, c' = 4 lk + 0..3
                             acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(wy[u] * wz[0], Bv[s], acc0, 0, 0, 0);
                             acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(wy[u] * wz[1], Bv[s + 1], acc1, 0, 0, 0);

@@ -170,8 +170,11 @@ hipError_t launch_bin_cells(int d, int64_t npts, const double *x, double s0, dou
                             double o0, double o1, double o2, int n, int T, int32_t *cell,
                             int32_t *tile, hipStream_t st);
 size_t stable_tile_sort_scratch(int64_t npts, int64_t ntiles);
+// Stable sort of points by tile; with cell != nullptr points of one tile are further
+// ordered by their tile-relative cell (cell % T, T <= 16) in dimension sub_dim.
 hipError_t stable_tile_sort(int64_t npts, const int32_t *tile, int64_t ntiles, int32_t *perm,
-                            int32_t *tile_off, void *scratch, size_t scratch_bytes, hipStream_t st);
+                            int32_t *tile_off, void *scratch, size_t scratch_bytes, hipStream_t st,
+                            const int32_t *cell = nullptr, int d = 0, int sub_dim = 0, int T = 1);
 // Window rows of sorted points (n x d x 16 FP32), Kaiser-Bessel shape parameter b.
 hipError_t launch_window_rows(int d, int64_t npts, const double *pts, double s, const double *o, int T,
                               int m, double b, float *rows, hipStream_t st);

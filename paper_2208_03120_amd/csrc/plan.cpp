@@ -681,8 +681,12 @@ static int bin_marginal(mot_plan_s *P, int k, const double *pts_orig_dev, void *
     for (int c = 0; c < d; ++c) ntiles *= tpd;
     MOT_HIP(launch_bin_cells(d, G.n, pts_orig_dev, Q.s, Q.s, Q.s, Q.o[0], Q.o[1], Q.o[2], n, T,
                              cell_tmp, tile_tmp, P->stream));
+    // In 3-D the points of a tile are ordered by their cell in dimension 1: the MFMA steps
+    // of spreading and interpolation then mostly hold points with the same window support
+    // in that dimension, and the steps outside it are skipped.
+    const bool sub = d == 3 && T > 1 && ntiles < ((int64_t)1 << 28);
     MOT_HIP(stable_tile_sort(G.n, tile_tmp, ntiles, G.perm, tile_off_dev, scratch, scratch_bytes,
-                             P->stream));
+                             P->stream, sub ? cell_tmp : nullptr, d, 1, T));
     MOT_HIP(launch_gather_rows(pts_orig_dev, G.perm, G.n, d, G.pts, P->stream));
     MOT_HIP(launch_window_rows(d, G.n, G.pts, Q.s, Q.o, T, Q.m, Q.kb_b, G.win, P->stream));
     tile_off_host.resize(ntiles + 1);
