@@ -409,98 +409,119 @@ constexpr int kFoldMaxCover = 4;
 // ascending order and chunks in ascending order within a tile.  One thread folds one
 // cell; an item is kFoldCellsPerItem consecutive cells of the box in row-major order
 // (lines of the last dimension back to back, so every lane has a cell even when a line
-// is shorter than a wavefront); item = (job, first cell).
+// is shorter than a wavefront); item = (job, first cell).  The job's tile -> chunk table
+// is staged in LDS when it fits, so the chunk lookups of a thread's covering tiles cost
+// LDS rather than global latency.
+constexpr int kFoldTab = 2048;  // tile -> chunk table entries staged in LDS
+
+// One item of the fold; tch is the job's tile -> chunk table (in LDS when it fits).
+template <int D, class Tab>
+__device__ __forceinline__ void fold_item(const ProdJob &J, int f0, Tab tch)
+{
+    const int W = J.W, T = J.T, Ll = J.L[D - 1], ntl = J.ntile[D - 1];
+    const int nl = D == 3 ? J.L[0] * J.L[1] : (D == 2 ? J.L[0] : 1);
+    const int f = f0 + (int)threadIdx.x;
+    if (f >= nl * Ll) return;
+    const int line = f / Ll, g = f - line * Ll;
+    int gu[2] = {0, 0};  // line coordinates in the leading dimensions
+    if (D == 3) {
+        gu[0] = line / J.L[1];
+        gu[1] = line - gu[0] * J.L[1];
+    } else if (D == 2) {
+        gu[0] = line;
+    }
+    int tlo[2] = {0, 0}, thi[2] = {0, 0};
+    for (int c = 0; c < D - 1; ++c) {
+        tlo[c] = max(0, floor_div(gu[c] - W + T, T));  // ceil((g - W + 1) / T)
+        thi[c] = min(J.ntile[c] - 1, gu[c] / T);
+    }
+    const int pe = D == 3 ? W * W * W : (D == 2 ? W * W : W);
+    const MOT_GLOBAL float *pat = gp(J.patches);
+    const int t2lo = max(0, floor_div(g - W + T, T)), t2hi = min(ntl - 1, g / T);
+    float acc = 0.0f;
+    if (W <= kFoldMaxCover * T) {
+        // at most kFoldMaxCover covering tiles per dimension: the chunk ranges and first
+        // patches of all (t1, t2) pairs of a t0 are loaded together, then added in the
+        // fixed order
+        constexpr int NU = D == 3 ? kFoldMaxCover : 1;
+        // t0-invariant parts of the tile index and patch offset of candidate (u, k):
+        //   tile = t0 nt1 ntl + tl_b + u ntl + k,
+        //   loc  = (gu0 - t0 T) W^2 + loc_b - u T W - k T
+        const int nt1 = D == 3 ? J.ntile[1] : 1;
+        const int vu = D == 3 ? thi[1] - tlo[1] : 0, vk = t2hi - t2lo;
+        const int tl_b = (D == 3 ? tlo[1] * ntl : 0) + t2lo;
+        const int loc_b = (D == 3 ? (gu[1] - tlo[1] * T) * W : 0) + (g - t2lo * T);
+        const int W2 = D == 1 ? 0 : (D == 2 ? W : W * W);
+        for (int t0 = tlo[0]; t0 <= thi[0]; ++t0) {
+            const int tl0 = t0 * nt1 * ntl + tl_b;
+            const int loc0 = (gu[0] - t0 * T) * W2 + loc_b;
+            int c0[NU][kFoldMaxCover], c1[NU][kFoldMaxCover];
+#pragma unroll
+            for (int u = 0; u < NU; ++u)
+#pragma unroll
+                for (int k = 0; k < kFoldMaxCover; ++k) {
+                    const bool ok = u <= vu && k <= vk;
+                    const int tl = tl0 + u * ntl + k;
+                    c0[u][k] = ok ? tch[tl] : 0;
+                    c1[u][k] = ok ? tch[tl + 1] : 0;
+                }
+            float first[NU][kFoldMaxCover];
+#pragma unroll
+            for (int u = 0; u < NU; ++u)
+#pragma unroll
+                for (int k = 0; k < kFoldMaxCover; ++k)
+                    first[u][k] = c1[u][k] > c0[u][k] ? pat[(int64_t)c0[u][k] * pe + (loc0 - u * T * W - k * T)] : 0.0f;
+#pragma unroll
+            for (int u = 0; u < NU; ++u)
+#pragma unroll
+                for (int k = 0; k < kFoldMaxCover; ++k) {
+                    acc += first[u][k];  // +0 for an absent tile leaves the sum unchanged
+                    for (int ch = c0[u][k] + 1; ch < c1[u][k]; ++ch)
+                        acc += pat[(int64_t)ch * pe + (loc0 - u * T * W - k * T)];
+                }
+        }
+    } else {
+        for (int t0 = tlo[0]; t0 <= thi[0]; ++t0)
+            for (int t1 = tlo[1]; t1 <= thi[1]; ++t1) {
+                int lead_tile = 0, lead_loc = 0;
+                if constexpr (D == 3) {
+                    lead_tile = t0 * J.ntile[1] + t1;
+                    lead_loc = (gu[0] - t0 * T) * W + (gu[1] - t1 * T);
+                } else if constexpr (D == 2) {
+                    lead_tile = t0;
+                    lead_loc = gu[0] - t0 * T;
+                }
+                for (int t2 = t2lo; t2 <= t2hi; ++t2) {
+                    const int tl = lead_tile * ntl + t2;
+                    const int lc = lead_loc * W + (g - t2 * T);
+                    const int ca = tch[tl], cb = tch[tl + 1];
+                    for (int ch = ca; ch < cb; ++ch) acc += pat[(int64_t)ch * pe + lc];
+                }
+            }
+    }
+    gp(J.grid)[(int64_t)line * Ll + g] = acc;
+}
+
 template <int D>
 __global__ __launch_bounds__(kFoldCellsPerItem) void fold_kernel(const ProdJob *__restrict__ jobs,
                                                                  const int2 *__restrict__ items, int n_items)
 {
+    __shared__ int32_t s_tab[kFoldTab];
     for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
         const int2 itm = items[it];
         const ProdJob &J = jobs[itm.x];
-        const int W = J.W, T = J.T, Ll = J.L[D - 1], ntl = J.ntile[D - 1];
-        const int nl = D == 3 ? J.L[0] * J.L[1] : (D == 2 ? J.L[0] : 1);
-        const int f = itm.y + (int)threadIdx.x;
-        if (f >= nl * Ll) continue;
-        const int line = f / Ll, g = f - line * Ll;
-        int gu[2] = {0, 0};  // line coordinates in the leading dimensions
-        if (D == 3) {
-            gu[0] = line / J.L[1];
-            gu[1] = line - gu[0] * J.L[1];
-        } else if (D == 2) {
-            gu[0] = line;
-        }
-        int tlo[2] = {0, 0}, thi[2] = {0, 0};
-        for (int c = 0; c < D - 1; ++c) {
-            tlo[c] = max(0, floor_div(gu[c] - W + T, T));  // ceil((g - W + 1) / T)
-            thi[c] = min(J.ntile[c] - 1, gu[c] / T);
-        }
-        const int pe = D == 3 ? W * W * W : (D == 2 ? W * W : W);
-        const MOT_GLOBAL int32_t *tch = gp(J.src_tile_chunks);
-        const MOT_GLOBAL float *pat = gp(J.patches);
-        const int t2lo = max(0, floor_div(g - W + T, T)), t2hi = min(ntl - 1, g / T);
-        float acc = 0.0f;
-        if (W <= kFoldMaxCover * T) {
-            // at most kFoldMaxCover covering tiles per dimension: the chunk ranges and first
-            // patches of all (t1, t2) pairs of a t0 are loaded together, then added in the
-            // fixed order
-            constexpr int NU = D == 3 ? kFoldMaxCover : 1;
-            for (int t0 = tlo[0]; t0 <= thi[0]; ++t0) {
-                int c0[NU][kFoldMaxCover], c1[NU][kFoldMaxCover], loc[NU][kFoldMaxCover];
-#pragma unroll
-                for (int u = 0; u < NU; ++u)
-#pragma unroll
-                    for (int k = 0; k < kFoldMaxCover; ++k) {
-                        const int t1 = tlo[1] + u, t2 = t2lo + k;
-                        int lead_tile = 0, lead_loc = 0;
-                        if constexpr (D == 3) {
-                            lead_tile = t0 * J.ntile[1] + t1;
-                            lead_loc = (gu[0] - t0 * T) * W + (gu[1] - t1 * T);
-                        } else if constexpr (D == 2) {
-                            lead_tile = t0;
-                            lead_loc = gu[0] - t0 * T;
-                        }
-                        c0[u][k] = c1[u][k] = 0;
-                        loc[u][k] = lead_loc * W + (g - t2 * T);
-                        if ((D < 3 || t1 <= thi[1]) && t2 <= t2hi) {
-                            const int tl = lead_tile * ntl + t2;
-                            c0[u][k] = tch[tl];
-                            c1[u][k] = tch[tl + 1];
-                        }
-                    }
-                float first[NU][kFoldMaxCover];
-#pragma unroll
-                for (int u = 0; u < NU; ++u)
-#pragma unroll
-                    for (int k = 0; k < kFoldMaxCover; ++k)
-                        first[u][k] = c1[u][k] > c0[u][k] ? pat[(int64_t)c0[u][k] * pe + loc[u][k]] : 0.0f;
-#pragma unroll
-                for (int u = 0; u < NU; ++u)
-#pragma unroll
-                    for (int k = 0; k < kFoldMaxCover; ++k) {
-                        if (c1[u][k] > c0[u][k]) acc += first[u][k];
-                        for (int ch = c0[u][k] + 1; ch < c1[u][k]; ++ch) acc += pat[(int64_t)ch * pe + loc[u][k]];
-                    }
-            }
+        int ntab = 1;
+        for (int c = 0; c < D; ++c) ntab *= J.ntile[c];
+        ++ntab;
+        if (ntab <= kFoldTab) {
+            __syncthreads();  // the previous item's reads of the table are done
+            const MOT_GLOBAL int32_t *tg = gp(J.src_tile_chunks);
+            for (int i = threadIdx.x; i < ntab; i += blockDim.x) s_tab[i] = tg[i];
+            __syncthreads();
+            fold_item<D>(J, itm.y, static_cast<const int32_t *>(s_tab));
         } else {
-            for (int t0 = tlo[0]; t0 <= thi[0]; ++t0)
-                for (int t1 = tlo[1]; t1 <= thi[1]; ++t1) {
-                    int lead_tile = 0, lead_loc = 0;
-                    if constexpr (D == 3) {
-                        lead_tile = t0 * J.ntile[1] + t1;
-                        lead_loc = (gu[0] - t0 * T) * W + (gu[1] - t1 * T);
-                    } else if constexpr (D == 2) {
-                        lead_tile = t0;
-                        lead_loc = gu[0] - t0 * T;
-                    }
-                    for (int t2 = t2lo; t2 <= t2hi; ++t2) {
-                        const int tl = lead_tile * ntl + t2;
-                        const int lc = lead_loc * W + (g - t2 * T);
-                        const int ca = tch[tl], cb = tch[tl + 1];
-                        for (int ch = ca; ch < cb; ++ch) acc += pat[(int64_t)ch * pe + lc];
-                    }
-                }
+            fold_item<D>(J, itm.y, gp(J.src_tile_chunks));
         }
-        gp(J.grid)[(int64_t)line * Ll + g] = acc;
     }
 }
 
