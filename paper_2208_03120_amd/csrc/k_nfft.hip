@@ -253,10 +253,11 @@ __device__ __forceinline__ int source_exponent(const ProdJob &J)
 // G[a = 4 (l / 16) + r][b][c' = l % 16].  In 2-D the product is one 16 x 16 tile per step,
 // in 1-D a plain sum over points.
 //
-// A block of kSpreadWaves wavefronts takes one chunk; wave w takes the 4-point steps
-// w, w + kSpreadWaves, ...  The wave partials are added through LDS in a fixed order
-// (pairwise halving), so a patch is the same whatever else shares the launch, and the
-// chunk owns its patch: no atomics.
+// A block of kSpreadWaves wavefronts takes one chunk, which owns its patch: no atomics.
+// In 1-D and 2-D wave w takes the 4-point steps w, w + kSpreadWaves, ... and the wave
+// partials are added through LDS in a fixed order (pairwise halving); in 3-D the waves
+// split the b tiles instead (spread3_kernel).  Either way a patch is the same whatever
+// else shares the launch.
 constexpr int kSpreadWaves = 4;
 constexpr int kInterpWaves = 4;
 
@@ -310,9 +311,9 @@ __global__ __launch_bounds__(64 * kSpreadWaves, 4) void spread_kernel(const Prod
                                                                    int n_items)
 {
     static_assert(kSpreadWaves == 4, "staging assumes 256 threads");
-    constexpr int NT = D == 3 ? 16 : 1;  // accumulator tiles per lane
+    static_assert(D < 3, "3-D spreading is spread3_kernel");
     using St = Stage<D, true>;
-    constexpr int kRed = (kSpreadWaves / 2) * NT * 64 * 16;
+    constexpr int kRed = (kSpreadWaves / 2) * 64 * 16;
     constexpr int kSmem = 2 * St::kBytes > kRed ? 2 * St::kBytes : kRed;
     __shared__ __align__(16) unsigned char smem[kSmem];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -323,9 +324,7 @@ __global__ __launch_bounds__(64 * kSpreadWaves, 4) void spread_kernel(const Prod
         const int64_t p0 = gp(J.src_chunk_start)[itm.y], p1 = gp(J.src_chunk_start)[itm.y + 1];
         const int e = source_exponent(J);
         const int nstages = (int)((p1 - p0 + kStage - 1) / kStage);
-        f32x4 acc[NT];
-#pragma unroll
-        for (int t = 0; t < NT; ++t) acc[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+        f32x4 acc = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
         St stg;
         stg.load(J.src_win, J.v, p0, p1);
         stg.store(smem, e);
@@ -342,64 +341,98 @@ __global__ __launch_bounds__(64 * kSpreadWaves, 4) void spread_kernel(const Prod
                 const int pi = 4 * (wave + 4 * i) + lk;
                 const float *row = rl + pi * (D * kPatch);
                 const float x = vl[pi] * row[li];
-                if constexpr (D == 3) {
-                    const float w2 = row[2 * kPatch + li];
-                    const f32x4 *r1 = reinterpret_cast<const f32x4 *>(row + kPatch);
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const f32x4 w1 = r1[q];
-#pragma unroll
-                        for (int u = 0; u < 4; ++u)
-                            // B is zero when b = 4 q + u is outside the window of all four
-                            // points: the product would add exact zeros
-                            if (__any(w1[u] != 0.0f))
-                                acc[4 * q + u] = __builtin_amdgcn_mfma_f32_16x16x4f32(x, w1[u] * w2,
-                                                                                      acc[4 * q + u], 0, 0, 0);
-                    }
-                } else if constexpr (D == 2) {
-                    acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(x, row[kPatch + li], acc[0], 0, 0, 0);
-                } else {
-                    acc[0][0] += x;
-                }
+                if constexpr (D == 2)
+                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(x, row[kPatch + li], acc, 0, 0, 0);
+                else
+                    acc[0] += x;
             }
             if (more) stg.store(smem + ((k + 1) & 1) * St::kBytes, e);
             __syncthreads();
         }
         if constexpr (D == 1) {
             // sum over the four points of a step (lane groups), then over waves
-            float a1 = acc[0][0];
+            float a1 = acc[0];
             a1 += __shfl_xor(a1, 16);
             a1 += __shfl_xor(a1, 32);
-            acc[0][0] = a1;
+            acc[0] = a1;
         }
         // wave partials: wave w < half adds wave w + half, halving until wave 0 holds the
         // patch (the staging buffers are free: the last stage ended with a barrier)
-        f32x4(*red)[NT][64] = reinterpret_cast<f32x4(*)[NT][64]>(smem);
+        f32x4(*red)[64] = reinterpret_cast<f32x4(*)[64]>(smem);
 #pragma unroll
         for (int half = kSpreadWaves / 2; half >= 1; half >>= 1) {
-            if (wave >= half && wave < 2 * half)
-#pragma unroll
-                for (int t = 0; t < NT; ++t) red[wave - half][t][lane] = acc[t];
+            if (wave >= half && wave < 2 * half) red[wave - half][lane] = acc;
             __syncthreads();
-            if (wave < half)
-#pragma unroll
-                for (int t = 0; t < NT; ++t) acc[t] += red[wave][t][lane];
+            if (wave < half) acc += red[wave][lane];
             __syncthreads();
         }
         if (wave == 0) {
-            MOT_GLOBAL float *out = gp(J.patches) + (int64_t)itm.y * (D == 3 ? 4096 : (D == 2 ? 256 : 16));
-            if constexpr (D == 3) {
+            MOT_GLOBAL float *out = gp(J.patches) + (int64_t)itm.y * (D == 2 ? 256 : 16);
+            if constexpr (D == 2) {
 #pragma unroll
-                for (int bt = 0; bt < 16; ++bt)
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) out[((4 * lk + r) * 16 + bt) * 16 + li] = acc[bt][r];
-            } else if constexpr (D == 2) {
-#pragma unroll
-                for (int r = 0; r < 4; ++r) out[(4 * lk + r) * 16 + li] = acc[0][r];
+                for (int r = 0; r < 4; ++r) out[(4 * lk + r) * 16 + li] = acc[r];
             } else {
-                if (lk == 0) out[li] = acc[0][0];
+                if (lk == 0) out[li] = acc[0];
             }
         }
+    }
+}
+
+// 3-D spreading: the 16 b tiles are split over the block's waves.  Wave w accumulates
+// tiles b = 4 w .. 4 w + 3 over every point of the chunk (one MFMA per tile and 4-point
+// step, in point order), so a wave holds 4 accumulators rather than 16, no partial patches
+// are combined, and every wave writes its own quarter of the patch.  At about 60 VGPRs six
+// blocks fit a CU (the LDS of their double-buffered stages bounds it too).
+__global__ __launch_bounds__(64 * kSpreadWaves, 6) void spread3_kernel(const ProdJob *__restrict__ jobs,
+                                                                   const int2 *__restrict__ items,
+                                                                   int n_items)
+{
+    static_assert(kSpreadWaves == 4, "one wave per group of 4 b tiles");
+    using St = Stage<3, true>;
+    __shared__ __align__(16) unsigned char smem[2 * St::kBytes];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const int2 itm = items[it];
+        const ProdJob &J = jobs[itm.x];
+        const int64_t p0 = gp(J.src_chunk_start)[itm.y], p1 = gp(J.src_chunk_start)[itm.y + 1];
+        const int e = source_exponent(J);
+        const int nstages = (int)((p1 - p0 + kStage - 1) / kStage);
+        f32x4 acc[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+        St stg;
+        stg.load(J.src_win, J.v, p0, p1);
+        stg.store(smem, e);
+        __syncthreads();
+        for (int k = 0; k < nstages; ++k) {
+            const bool more = k + 1 < nstages;
+            if (more) stg.load(J.src_win, J.v, p0 + (int64_t)(k + 1) * kStage, p1);
+            const unsigned char *buf = smem + (k & 1) * St::kBytes;
+            const float *rl = reinterpret_cast<const float *>(buf);
+            const float *vl = reinterpret_cast<const float *>(buf + St::kRow4 * 16);
+#pragma unroll 2
+            for (int j = 0; j < kStage / 4; ++j) {
+                const int pi = 4 * j + lk;  // point of lane group lk in step j
+                const float *row = rl + pi * (3 * kPatch);
+                const float x = vl[pi] * row[li];
+                const float w2 = row[2 * kPatch + li];
+                const f32x4 w1 = reinterpret_cast<const f32x4 *>(row + kPatch)[wave];
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    // B is zero when b = 4 w + u is outside the window of all four points:
+                    // the product would add exact zeros
+                    if (__any(w1[u] != 0.0f))
+                        acc[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(x, w1[u] * w2, acc[u], 0, 0, 0);
+            }
+            if (more) stg.store(smem + ((k + 1) & 1) * St::kBytes, e);
+            __syncthreads();
+        }
+        MOT_GLOBAL float *out = gp(J.patches) + (int64_t)itm.y * 4096;
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) out[((4 * lk + r) * 16 + 4 * wave + u) * 16 + li] = acc[u][r];
     }
 }
 
@@ -660,7 +693,7 @@ hipError_t launch_spread(int d, const ProdJob *jobs, const int2 *items, int n_it
     if (n_items == 0) return hipSuccess;
     const dim3 grid(nfft_grid(n_items)), block(64 * kSpreadWaves);
     if (d == 3)
-        hipLaunchKernelGGL(spread_kernel<3>, grid, block, 0, s, jobs, items, n_items);
+        hipLaunchKernelGGL(spread3_kernel, grid, block, 0, s, jobs, items, n_items);
     else if (d == 2)
         hipLaunchKernelGGL(spread_kernel<2>, grid, block, 0, s, jobs, items, n_items);
     else
