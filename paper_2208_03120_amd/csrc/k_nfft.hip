@@ -571,15 +571,17 @@ __global__ __launch_bounds__(kFoldCellsPerItem) void fold_kernel(const ProdJob *
 // a 16-lane reduction.  In 2-D the chain has 4 steps (k = b = 4 g + s); in 1-D one lane
 // takes one point.  out = 2^e beta, e the exponent the source was scaled by.
 //
-// A block of kInterpWaves wavefronts takes one chunk; wave w takes the 16-point groups
-// (64 in 1-D) w, w + kInterpWaves, ...
+// A block of kInterpWaves wavefronts takes one chunk.  In 2-D wave w takes the 16-point
+// groups w, w + kInterpWaves, ... (one per stage), in 1-D 64-point groups; 3-D
+// interpolation splits the b values over the waves instead (interp3_kernel).
 template <int D>
 __global__ __launch_bounds__(64 * kInterpWaves, 4) void interp_kernel(const ProdJob *__restrict__ jobs,
                                                                    const int2 *__restrict__ items,
                                                                    int n_items)
 {
     static_assert(kInterpWaves == 4 && kStage == 16 * kInterpWaves, "one 16-point group per wave and stage");
-    constexpr int NB = D == 3 ? 64 : (D == 2 ? 4 : 16);  // B values per lane
+    static_assert(D < 3, "3-D interpolation is interp3_kernel");
+    constexpr int NB = D == 2 ? 4 : 16;  // B values per lane
     using St = Stage<D, false>;
     __shared__ __align__(16) unsigned char smem[D == 1 ? 16 : 2 * St::kBytes];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -598,11 +600,7 @@ __global__ __launch_bounds__(64 * kInterpWaves, 4) void interp_kernel(const Prod
         }
         const MOT_GLOBAL float *grid = gp(J.grid);
         float Bv[NB];
-        if constexpr (D == 3) {
-            const int64_t base = ((int64_t)(tc[0] * T + li) * J.L[1] + tc[1] * T) * J.L[2] + tc[2] * T + 4 * lk;
-#pragma unroll
-            for (int s = 0; s < 64; ++s) Bv[s] = grid[base + (int64_t)(s >> 2) * J.L[2] + (s & 3)];
-        } else if constexpr (D == 2) {
+        if constexpr (D == 2) {
             const int64_t base = (int64_t)(tc[0] * T + li) * J.L[1] + tc[1] * T + 4 * lk;
 #pragma unroll
             for (int s = 0; s < 4; ++s) Bv[s] = grid[base + s];
@@ -638,31 +636,11 @@ __global__ __launch_bounds__(64 * kInterpWaves, 4) void interp_kernel(const Prod
                 const float *grow = rl + (16 * wave) * (D * kPatch);
                 const float *row = grow + li * (D * kPatch);  // point l % 16
                 f32x4 acc0 = f32x4{0.0f, 0.0f, 0.0f, 0.0f}, acc1 = acc0;
-                if constexpr (D == 3) {
-                    const f32x4 *r1 = reinterpret_cast<const f32x4 *>(row + kPatch);
-                    const f32x4 wz = reinterpret_cast<const f32x4 *>(row + 2 * kPatch)[lk];
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const f32x4 wy = r1[q];
-#pragma unroll
-                        for (int u = 0; u < 4; ++u) {
-                            // A is zero when b is outside the window of all 16 points: the
-                            // four products would add exact zeros
-                            if (!__any(wy[u] != 0.0f)) continue;
-                            const int s = 16 * q + 4 * u;  // b = 4 q + u, c' = 4 lk + 0..3
-                            acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(wy[u] * wz[0], Bv[s], acc0, 0, 0, 0);
-                            acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(wy[u] * wz[1], Bv[s + 1], acc1, 0, 0, 0);
-                            acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(wy[u] * wz[2], Bv[s + 2], acc0, 0, 0, 0);
-                            acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(wy[u] * wz[3], Bv[s + 3], acc1, 0, 0, 0);
-                        }
-                    }
-                } else {
-                    const f32x4 wb = reinterpret_cast<const f32x4 *>(row + kPatch)[lk];
-                    acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(wb[0], Bv[0], acc0, 0, 0, 0);
-                    acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(wb[1], Bv[1], acc1, 0, 0, 0);
-                    acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(wb[2], Bv[2], acc0, 0, 0, 0);
-                    acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(wb[3], Bv[3], acc1, 0, 0, 0);
-                }
+                const f32x4 wb = reinterpret_cast<const f32x4 *>(row + kPatch)[lk];
+                acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(wb[0], Bv[0], acc0, 0, 0, 0);
+                acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(wb[1], Bv[1], acc1, 0, 0, 0);
+                acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(wb[2], Bv[2], acc0, 0, 0, 0);
+                acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(wb[3], Bv[3], acc1, 0, 0, 0);
                 // beta_p = sum_a w_0,p[a] Z[p][a] over the 16 lanes of a lane group
                 const int64_t pb = p0 + (int64_t)k * kStage + 16 * wave;
 #pragma unroll
@@ -677,6 +655,109 @@ __global__ __launch_bounds__(64 * kInterpWaves, 4) void interp_kernel(const Prod
                 }
                 if (more) stg.store(smem + ((k + 1) & 1) * St::kBytes, 0);
                 __syncthreads();
+            }
+        }
+    }
+}
+
+// 3-D interpolation with the 16 b values of the contraction split over the block's waves.
+// Wave w holds B only for b = 4 w .. 4 w + 3 (16 registers rather than 64) and takes all
+// four 16-point groups of a stage: for group g and lane group lk its accumulators give
+// Z_w[p = 16 g + 4 lk + r][a = l % 16], the part of Z from its b values.  The lane
+// products w_0,p[a] Z_w[p][a] of the four points 16 g + 4 lk + r of a group are summed
+// over the 16 lanes of the lane group, the four waves' partial sums of a point are added in
+// wave order through LDS after the stage's barrier, and wave 0 stores out = 2^e beta.
+__global__ __launch_bounds__(64 * kInterpWaves, 6) void interp3_kernel(const ProdJob *__restrict__ jobs,
+                                                                   const int2 *__restrict__ items,
+                                                                   int n_items)
+{
+    static_assert(kInterpWaves == 4 && kStage == 64, "four 16-point groups and four b quarters per stage");
+    using St = Stage<3, false>;
+    __shared__ __align__(16) unsigned char smem[2 * St::kBytes];
+    __shared__ float zb[2][kInterpWaves][kStage];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const int2 itm = items[it];
+        const ProdJob &J = jobs[itm.x];
+        const int T = J.T;
+        int tc[3] = {0, 0, 0};
+        {
+            int rem = gp(J.tgt_chunk_tile)[itm.y];
+            for (int c = 2; c >= 0; --c) {
+                tc[c] = rem % J.ntile[c];
+                rem /= J.ntile[c];
+            }
+        }
+        // B[k = (b, c')][a = l % 16] = G[a][b][c'] for b = 4 wave + bb, c' = 4 lk + s
+        const MOT_GLOBAL float *grid = gp(J.grid);
+        float Bv[16];
+        {
+            const int64_t base =
+                ((int64_t)(tc[0] * T + li) * J.L[1] + tc[1] * T + 4 * wave) * J.L[2] + tc[2] * T + 4 * lk;
+#pragma unroll
+            for (int bb = 0; bb < 4; ++bb)
+#pragma unroll
+                for (int s = 0; s < 4; ++s) Bv[4 * bb + s] = grid[base + (int64_t)bb * J.L[2] + s];
+        }
+        const int e = source_exponent(J);
+        const int64_t p0 = gp(J.tgt_chunk_start)[itm.y], p1 = gp(J.tgt_chunk_start)[itm.y + 1];
+        MOT_GLOBAL double *out = gp(J.out);
+        const int nstages = (int)((p1 - p0 + kStage - 1) / kStage);
+        St stg;
+        stg.load(J.tgt_win, nullptr, p0, p1);
+        stg.store(smem, 0);
+        __syncthreads();
+        for (int k = 0; k < nstages; ++k) {
+            const bool more = k + 1 < nstages;
+            if (more) stg.load(J.tgt_win, nullptr, p0 + (int64_t)(k + 1) * kStage, p1);
+            const float *rl = reinterpret_cast<const float *>(smem + (k & 1) * St::kBytes);
+#pragma unroll 1
+            for (int g = 0; g < 4; ++g) {
+                const float *row = rl + (16 * g + li) * (3 * kPatch);  // point 16 g + l % 16
+                const f32x4 wy = reinterpret_cast<const f32x4 *>(row + kPatch)[wave];
+                const f32x4 wz = reinterpret_cast<const f32x4 *>(row + 2 * kPatch)[lk];
+                f32x4 acc0 = f32x4{0.0f, 0.0f, 0.0f, 0.0f}, acc1 = acc0;
+#pragma unroll
+                for (int bb = 0; bb < 4; ++bb) {
+                    // A is zero when b is outside the window of all 16 points: the four
+                    // products would add exact zeros
+                    if (!__any(wy[bb] != 0.0f)) continue;
+                    acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(wy[bb] * wz[0], Bv[4 * bb], acc0, 0, 0, 0);
+                    acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(wy[bb] * wz[1], Bv[4 * bb + 1], acc1, 0, 0, 0);
+                    acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(wy[bb] * wz[2], Bv[4 * bb + 2], acc0, 0, 0, 0);
+                    acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(wy[bb] * wz[3], Bv[4 * bb + 3], acc1, 0, 0, 0);
+                }
+                // z[r]: this lane's product for point 16 g + 4 lk + r
+                float z[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    z[r] = (acc0[r] + acc1[r]) * rl[(16 * g + 4 * lk + r) * (3 * kPatch) + li];
+                // sum over the 16 lanes of the lane group: halving over lane masks 8 and 4
+                // (lane l keeps r = l / 4), then full sums over masks 2 and 1
+                {
+                    const bool hi = (li & 8) != 0;
+#pragma unroll
+                    for (int q = 0; q < 2; ++q) {
+                        const float mine = hi ? z[q + 2] : z[q], other = hi ? z[q] : z[q + 2];
+                        z[q] = mine + __shfl_xor(other, 8);
+                    }
+                }
+                {
+                    const bool hi = (li & 4) != 0;
+                    const float mine = hi ? z[1] : z[0], other = hi ? z[0] : z[1];
+                    z[0] = mine + __shfl_xor(other, 4);
+                }
+                z[0] += __shfl_xor(z[0], 2);
+                z[0] += __shfl_xor(z[0], 1);
+                if ((li & 3) == 0) zb[k & 1][wave][16 * g + 4 * lk + (li >> 2)] = z[0];
+            }
+            if (more) stg.store(smem + ((k + 1) & 1) * St::kBytes, 0);
+            __syncthreads();
+            if (wave == 0) {
+                const int64_t p = p0 + (int64_t)k * kStage + lane;
+                const float s = ((zb[k & 1][0][lane] + zb[k & 1][1][lane]) + zb[k & 1][2][lane]) + zb[k & 1][3][lane];
+                if (p < p1) out[p] = ldexp((double)s, e);
             }
         }
     }
@@ -722,7 +803,7 @@ hipError_t launch_interp(int d, const ProdJob *jobs, const int2 *items, int n_it
     if (n_items == 0) return hipSuccess;
     const dim3 grid(nfft_grid(n_items)), block(64 * kInterpWaves);
     if (d == 3)
-        hipLaunchKernelGGL(interp_kernel<3>, grid, block, 0, s, jobs, items, n_items);
+        hipLaunchKernelGGL(interp3_kernel, grid, block, 0, s, jobs, items, n_items);
     else if (d == 2)
         hipLaunchKernelGGL(interp_kernel<2>, grid, block, 0, s, jobs, items, n_items);
     else
