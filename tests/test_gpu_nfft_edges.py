@@ -56,6 +56,34 @@ def test_window_cutoff_range(mot):
     assert max(errs[m] for m in (4, 5, 6, 7, 8)) < 1e-6, errs
 
 
+def test_window_cutoff_range_3d(mot):
+    """d = 3, M = 16, n = 64 (sigma = 4): every tile edge T = 17 - 2m the 3-D spreading and
+    interpolation meet (11, 9, 7, 5, 3), with several chunks per tile, against the exact
+    trigonometric sums of eq. (fastsum1).  The points of a tile are ordered by their cell in
+    dimension 1 and the MFMA steps outside every point's window are skipped, so this also
+    covers tiles whose points start at every offset."""
+    inst = _pair(55, [1500, 1400], 3)
+    v = rng(56).uniform(0, 1, 1400)
+    chain = fastsum.fastsum(inst.points[0], inst.points[1], v, 0.05, 1.0, 0.125, 3, 16)
+    errs = {}
+    for m in (3, 4, 5, 6, 7):
+        fs = mot.fastsum_params(M=16, n=64, m=m, p=3, tau=1.0, eps_B=0.125, chunk=40)
+        plan = mot.Plan(inst.points, inst.weights, W.TREE, inst.parent, inst.eta, path=mot.NFFT,
+                        fastsum=fs)
+        assert plan.info()["tile"] == 17 - 2 * m
+        errs[m] = rel_to_max(plan.apply(0, 1, v), chain)
+        # the reverse direction: sources are the 1500-point marginal
+        u = rng(57).uniform(0, 1, 1500)
+        back = fastsum.fastsum(inst.points[1], inst.points[0], u, 0.05, 1.0, 0.125, 3, 16)
+        errs[-m] = rel_to_max(plan.apply(1, 0, u), back)
+        plan.close()
+    print("3-D window errors", errs)
+    # the window's truncation error is ~1e-5 at m = 3 and below the FP32 rounding of the
+    # pipeline (a few 1e-7) from m = 4 on, in both directions
+    assert 1e-6 < errs[3] < 1e-4 and 1e-6 < errs[-3] < 1e-4, errs
+    assert max(e for m, e in errs.items() if abs(m) >= 4) < 1e-6, errs
+
+
 @pytest.mark.parametrize("chunk", [8, 24, 100])
 def test_tiles_split_into_chunks(mot, chunk):
     """Chunks far smaller than a tile's points: several patches per tile, folded in order.
