@@ -269,10 +269,24 @@ __global__ __launch_bounds__(256) void finalize_kernel(const FinalJob *__restric
             __threadfence();
             // every thread sums a fixed strided subset; block_sum combines them in a fixed
             // order, so the result does not depend on timing
+            // eight strided partials are loaded before they are added (in the same order), so
+            // the loads of a thread are in flight together
+            constexpr int U = 8;
             double s1 = 0.0, s2 = 0.0, e1 = 0.0;
-            for (int p = tid; p < J.n_partials; p += blockDim.x) {
-                s1 += J.s_partial[2 * p];
-                s2 += J.s_partial[2 * p + 1];
+            for (int p0 = tid; p0 < J.n_partials; p0 += U * (int)blockDim.x) {
+                double a[U], b[U];
+#pragma unroll
+                for (int q = 0; q < U; ++q) {
+                    const int p = p0 + q * (int)blockDim.x;
+                    a[q] = p < J.n_partials ? J.s_partial[2 * p] : 0.0;
+                    b[q] = p < J.n_partials ? J.s_partial[2 * p + 1] : 0.0;
+                }
+#pragma unroll
+                for (int q = 0; q < U; ++q)
+                    if (p0 + q * (int)blockDim.x < J.n_partials) {
+                        s1 += a[q];
+                        s2 += b[q];
+                    }
             }
             for (int p = tid; p < J.n_items; p += blockDim.x) e1 += J.l1_partial[p];
             s1 = block_sum(s1, red);
