@@ -136,6 +136,7 @@ enum StepKind { ST_NODE, ST_DIRECT, ST_SPREAD, ST_FOLD, ST_FFT, ST_INTERP, ST_FI
 struct Step {
     StepKind kind;
     int d = 0, n = 0, fft_kind = 0, precision = 0, max_patch = 0, trunc_r = 0, diff = 0;
+    int group = 0;                // 3-D spreading: jobs per item (items int4)
     const void *jobs = nullptr;   // device ProdJob / NodeJob / FinalJob array
     const void *items = nullptr;  // device int2 / int4 array
     int n_items = 0;

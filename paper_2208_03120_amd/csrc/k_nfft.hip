@@ -380,34 +380,84 @@ __global__ __launch_bounds__(64 * kSpreadWaves, 4) void spread_kernel(const Prod
 
 // 3-D spreading: the 16 b tiles are split over the block's waves.  Wave w accumulates
 // tiles b = 4 w .. 4 w + 3 over every point of the chunk (one MFMA per tile and 4-point
-// step, in point order), so a wave holds 4 accumulators rather than 16, no partial patches
-// are combined, and every wave writes its own quarter of the patch.  At about 60 VGPRs six
-// blocks fit a CU (the LDS of their double-buffered stages bounds it too).
-__global__ __launch_bounds__(64 * kSpreadWaves, 6) void spread3_kernel(const ProdJob *__restrict__ jobs,
-                                                                   const int2 *__restrict__ items,
-                                                                   int n_items)
+// step, in point order), so a wave holds 4 accumulators per job rather than 16, no partial
+// patches are combined, and every wave writes its own quarter of the patch.
+//
+// An item is (job_0, .., job_{G-1}, chunk): G jobs that spread different values from the
+// same points (the down products of a node's children).  They share the chunk's window
+// rows, so the rows are staged once, and the B operand w_1,p[b] w_2,p[c'] and the test for
+// a zero step are formed once for G MFMAs.  Each job's patch is accumulated exactly as it
+// would be on its own.
+template <int G>
+struct SpreadStage3 {
+    static constexpr int kRow4 = kStage * 3 * kPatch / 4;  // 16-byte row pieces per stage
+    static constexpr int kPer = (kRow4 + 255) / 256;        // per thread (256 threads)
+    static constexpr int kBytes = kRow4 * 16 + G * kStage * 4;
+    f32x4 r[kPer];
+    double v;  // value of job q = threadIdx.x / kStage (the wave), scaled only when stored
+
+    // Registers <- global: points pb .. pb + kStage - 1 (zeros past p1); wave q < G loads
+    // job q's values from vq (the job's pointer, selected by the caller).
+    __device__ __forceinline__ void load(const float *rows, const double *vq, int64_t pb, int64_t p1)
+    {
+        const MOT_GLOBAL f32x4 *g = reinterpret_cast<const MOT_GLOBAL f32x4 *>(gp(rows)) + pb * 12;
+#pragma unroll
+        for (int i = 0; i < kPer; ++i) {
+            const int idx = threadIdx.x + 256 * i;
+            r[i] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+            if (idx < kRow4 && pb + idx / 12 < p1) r[i] = g[idx];
+        }
+        v = 0.0;
+        const int64_t p = pb + (threadIdx.x % kStage);
+        if (threadIdx.x / kStage < G && p < p1) v = gp(vq)[p];
+    }
+    // LDS <- registers; job q's values are stored as FP32 v 2^-eq.
+    __device__ __forceinline__ void store(unsigned char *buf, int eq) const
+    {
+        f32x4 *rl = reinterpret_cast<f32x4 *>(buf);
+#pragma unroll
+        for (int i = 0; i < kPer; ++i) {
+            const int idx = threadIdx.x + 256 * i;
+            if (idx < kRow4) rl[idx] = r[i];
+        }
+        if (threadIdx.x / kStage < G) reinterpret_cast<float *>(buf + kRow4 * 16)[threadIdx.x] = (float)ldexp(v, -eq);
+    }
+};
+
+template <int G>
+__global__ __launch_bounds__(64 * kSpreadWaves, G == 1 ? 6 : (G == 2 ? 5 : 4)) void spread3_kernel(const ProdJob *__restrict__ jobs,
+                                                                                 const int4 *__restrict__ items,
+                                                                                 int n_items)
 {
-    static_assert(kSpreadWaves == 4, "one wave per group of 4 b tiles");
-    using St = Stage<3, true>;
+    static_assert(kSpreadWaves == 4 && kStage == 64 && G >= 1 && G <= 3,
+                  "one wave per group of 4 b tiles and per job's stage values; up to 3 jobs");
+    using St = SpreadStage3<G>;
     __shared__ __align__(16) unsigned char smem[2 * St::kBytes];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int li = lane & 15, lk = lane >> 4;
     for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
-        const int2 itm = items[it];
-        const ProdJob &J = jobs[itm.x];
-        const int64_t p0 = gp(J.src_chunk_start)[itm.y], p1 = gp(J.src_chunk_start)[itm.y + 1];
-        const int e = source_exponent(J);
+        const int4 itm = items[it];
+        const int c = itm.w;
+        const ProdJob &J = jobs[itm.x];  // the points, shared by the item's jobs
+        const int64_t p0 = gp(J.src_chunk_start)[c], p1 = gp(J.src_chunk_start)[c + 1];
+        // wave q < G stages job q's values: its pointer and exponent, selected by wave
+        const int jq = wave == 0 ? itm.x : (wave == 1 ? itm.y : itm.z);
+        const int q_job = wave < G ? jq : itm.x;
+        const double *vq = jobs[q_job].v;
+        const int eq = source_exponent(jobs[q_job]);
         const int nstages = (int)((p1 - p0 + kStage - 1) / kStage);
-        f32x4 acc[4];
+        f32x4 acc[G][4];
 #pragma unroll
-        for (int t = 0; t < 4; ++t) acc[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+        for (int g = 0; g < G; ++g)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) acc[g][t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
         St stg;
-        stg.load(J.src_win, J.v, p0, p1);
-        stg.store(smem, e);
+        stg.load(J.src_win, vq, p0, p1);
+        stg.store(smem, eq);
         __syncthreads();
         for (int k = 0; k < nstages; ++k) {
             const bool more = k + 1 < nstages;
-            if (more) stg.load(J.src_win, J.v, p0 + (int64_t)(k + 1) * kStage, p1);
+            if (more) stg.load(J.src_win, vq, p0 + (int64_t)(k + 1) * kStage, p1);
             const unsigned char *buf = smem + (k & 1) * St::kBytes;
             const float *rl = reinterpret_cast<const float *>(buf);
             const float *vl = reinterpret_cast<const float *>(buf + St::kRow4 * 16);
@@ -415,24 +465,35 @@ __global__ __launch_bounds__(64 * kSpreadWaves, 6) void spread3_kernel(const Pro
             for (int j = 0; j < kStage / 4; ++j) {
                 const int pi = 4 * j + lk;  // point of lane group lk in step j
                 const float *row = rl + pi * (3 * kPatch);
-                const float x = vl[pi] * row[li];
+                const float w0 = row[li];
+                float x[G];
+#pragma unroll
+                for (int g = 0; g < G; ++g) x[g] = vl[g * kStage + pi] * w0;
                 const float w2 = row[2 * kPatch + li];
                 const f32x4 w1 = reinterpret_cast<const f32x4 *>(row + kPatch)[wave];
 #pragma unroll
                 for (int u = 0; u < 4; ++u)
                     // B is zero when b = 4 w + u is outside the window of all four points:
-                    // the product would add exact zeros
-                    if (__any(w1[u] != 0.0f))
-                        acc[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(x, w1[u] * w2, acc[u], 0, 0, 0);
+                    // the products would add exact zeros
+                    if (__any(w1[u] != 0.0f)) {
+                        const float bu = w1[u] * w2;
+#pragma unroll
+                        for (int g = 0; g < G; ++g)
+                            acc[g][u] = __builtin_amdgcn_mfma_f32_16x16x4f32(x[g], bu, acc[g][u], 0, 0, 0);
+                    }
             }
-            if (more) stg.store(smem + ((k + 1) & 1) * St::kBytes, e);
+            if (more) stg.store(smem + ((k + 1) & 1) * St::kBytes, eq);
             __syncthreads();
         }
-        MOT_GLOBAL float *out = gp(J.patches) + (int64_t)itm.y * 4096;
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
+        for (int g = 0; g < G; ++g) {
+            const int jg = g == 0 ? itm.x : (g == 1 ? itm.y : itm.z);
+            MOT_GLOBAL float *out = gp(jobs[jg].patches) + (int64_t)c * 4096;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) out[((4 * lk + r) * 16 + 4 * wave + u) * 16 + li] = acc[u][r];
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) out[((4 * lk + r) * 16 + 4 * wave + u) * 16 + li] = acc[g][u][r];
+        }
     }
 }
 
@@ -768,13 +829,28 @@ static int nfft_grid(int n_items)
     return n_items < 65535 ? n_items : 65535;
 }
 
+hipError_t launch_spread3(int group, const ProdJob *jobs, const int4 *items, int n_items, hipStream_t s)
+{
+    if (n_items == 0) return hipSuccess;
+    const dim3 grid(nfft_grid(n_items)), block(64 * kSpreadWaves);
+    if (group == 3)
+        hipLaunchKernelGGL(spread3_kernel<3>, grid, block, 0, s, jobs, items, n_items);
+    else if (group == 2)
+        hipLaunchKernelGGL(spread3_kernel<2>, grid, block, 0, s, jobs, items, n_items);
+    else if (group == 1)
+        hipLaunchKernelGGL(spread3_kernel<1>, grid, block, 0, s, jobs, items, n_items);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
 hipError_t launch_spread(int d, const ProdJob *jobs, const int2 *items, int n_items,
                          int /*max_patch_elems*/, hipStream_t s)
 {
     if (n_items == 0) return hipSuccess;
     const dim3 grid(nfft_grid(n_items)), block(64 * kSpreadWaves);
     if (d == 3)
-        hipLaunchKernelGGL(spread3_kernel, grid, block, 0, s, jobs, items, n_items);
+        return hipErrorInvalidValue;  // 3-D items are grouped: launch_spread3
     else if (d == 2)
         hipLaunchKernelGGL(spread_kernel<2>, grid, block, 0, s, jobs, items, n_items);
     else

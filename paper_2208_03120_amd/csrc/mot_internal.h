@@ -184,7 +184,10 @@ constexpr int kNodeItemElems = 512;  // elements per node / finalisation item
 constexpr int kFoldCellsPerItem = 128;  // box cells per fold item (one per thread)
 constexpr int kFftLinesPerItem = 16;
 hipError_t launch_spread(int d, const ProdJob *jobs, const int2 *items, int n_items,
-                         int max_patch_elems, hipStream_t s);
+                         int max_patch_elems, hipStream_t s);  // d = 1, 2
+// 3-D spreading; items int4 (job_0, .., job_{group-1}, chunk): group jobs (1..3) that spread
+// from the same points.
+hipError_t launch_spread3(int group, const ProdJob *jobs, const int4 *items, int n_items, hipStream_t s);
 hipError_t launch_fold(int d, const ProdJob *jobs, const int2 *items, int n_items, hipStream_t s);
 hipError_t launch_interp(int d, const ProdJob *jobs, const int2 *items, int n_items,
                          int max_patch_elems, hipStream_t s);

@@ -130,8 +130,11 @@ int run_steps(const std::vector<Step> &steps, hipStream_t s)
                                   st.precision, st.diff, s));
             break;
         case ST_SPREAD:
-            MOT_HIP(launch_spread(st.d, (const ProdJob *)st.jobs, (const int2 *)st.items, st.n_items,
-                                  st.max_patch, s));
+            if (st.group > 0)
+                MOT_HIP(launch_spread3(st.group, (const ProdJob *)st.jobs, (const int4 *)st.items, st.n_items, s));
+            else
+                MOT_HIP(launch_spread(st.d, (const ProdJob *)st.jobs, (const int2 *)st.items, st.n_items,
+                                      st.max_patch, s));
             break;
         case ST_FOLD:
             MOT_HIP(launch_fold(st.d, (const ProdJob *)st.jobs, (const int2 *)st.items, st.n_items, s));
@@ -229,6 +232,8 @@ struct StepBuilder {
         std::map<std::tuple<int, int, int>, std::vector<int4>> direct;  // (d, precision, diff)
         std::map<std::tuple<int, int, int, int>, std::vector<std::pair<double, int4>>> trunc;  // (d, prec, R, wide)
         std::map<int, std::vector<int2>> spread, fold, interp;   // d
+        // 3-D spreading: jobs by the points they spread from (a binned marginal's rows)
+        std::map<const float *, std::vector<int>> spread3_src;
         std::map<int, std::vector<int32_t>> spread_pts, interp_pts;  // points of each item
         std::map<std::pair<int, int>, std::vector<int4>> fft[8]; // (d, n) per pass kind
         std::map<int, int> max_patch;
@@ -277,9 +282,13 @@ struct StepBuilder {
                     }
                 continue;
             }
-            for (int c = 0; c < J.src_nchunks; ++c) spread[J.d].push_back(make_int2(j, c));
-            for (int c = 0; c < J.src_nchunks; ++c)
-                spread_pts[J.d].push_back(J.h_src_chunk_start[c + 1] - J.h_src_chunk_start[c]);
+            if (J.d == 3) {
+                spread3_src[J.src_win].push_back(j);
+            } else {
+                for (int c = 0; c < J.src_nchunks; ++c) spread[J.d].push_back(make_int2(j, c));
+                for (int c = 0; c < J.src_nchunks; ++c)
+                    spread_pts[J.d].push_back(J.h_src_chunk_start[c + 1] - J.h_src_chunk_start[c]);
+            }
             const int lines = J.d == 3 ? J.L[0] * J.L[1] : (J.d == 2 ? J.L[0] : 1);
             const int cells = lines * J.L[J.d - 1];
             for (int f = 0; f < cells; f += kFoldCellsPerItem) fold[J.d].push_back(make_int2(j, f));
@@ -354,6 +363,40 @@ struct StepBuilder {
             v.swap(out);
         };
         for (auto &kv : spread) by_size(kv.second, spread_pts[kv.first]);
+        // 3-D: jobs spreading from the same points go three (or the remaining two) to an
+        // item, which stages the chunk's rows once for all of them
+        {
+            std::vector<std::pair<int32_t, int4>> g3[4];
+            for (auto &kv : spread3_src) {
+                const std::vector<int> &js = kv.second;
+                for (size_t a = 0; a < js.size();) {
+                    const int G = (int)std::min<size_t>(3, js.size() - a);
+                    const ProdJob &J = host_jobs[js[a]];
+                    for (int c = 0; c < J.src_nchunks; ++c) {
+                        const int4 it = make_int4(js[a], G > 1 ? js[a + 1] : -1, G > 2 ? js[a + 2] : -1, c);
+                        g3[G].push_back({G * (J.h_src_chunk_start[c + 1] - J.h_src_chunk_start[c]), it});
+                    }
+                    a += G;
+                }
+            }
+            for (int G = 3; G >= 1; --G) {
+                if (g3[G].empty()) continue;
+                std::stable_sort(g3[G].begin(), g3[G].end(),
+                                 [](const std::pair<int32_t, int4> &x, const std::pair<int32_t, int4> &y) {
+                                     return x.first > y.first;
+                                 });
+                std::vector<int4> its(g3[G].size());
+                for (size_t i = 0; i < its.size(); ++i) its[i] = g3[G][i].second;
+                Step st{ST_SPREAD};
+                st.d = 3;
+                st.group = G;
+                st.max_patch = max_patch[3];
+                st.jobs = jobs_dev;
+                st.items = upload(its);
+                st.n_items = (int)its.size();
+                out->push_back(st);
+            }
+        }
         for (auto &kv : interp) by_size(kv.second, interp_pts[kv.first]);
         for (auto &kv : spread) {
             Step st{ST_SPREAD};
