@@ -29,21 +29,25 @@ PEAK_FP32_TFLOPS = 157.3  # dense FP32 MFMA
 # HBM bytes per launch of a kernel on the default workload (N = 100000), from the
 # FETCH_SIZE and WRITE_SIZE counters of a profiler run of this script (one pass each),
 # scaled by what the same counters read for the plain device-to-device copy of COPY_MIB
-# this script performs first (launches averaged over the down and up products).  Valid
-# only for the kernel source it was measured on (SHA-256 of the file that holds it).
+# this script performs first (fold, FFT and interpolation launches averaged over the down
+# and up products; spread per item grouping: "spread" is the up launch, one job per item,
+# "spread_g3" the down launch, whose items take three jobs spreading from the root's
+# points).  Valid only for the kernel source it was measured on (SHA-256 of its file).
 COPY_MIB = 256
 TRAFFIC = {
-    "spread": {"bytes_per_launch": 204079020, "source": "k_nfft.hip",
-               "sha256": "9f33b9d7f7df2645170786d486e08c4c1409b67dada1a1950593f66123b00659"},
-    "fold": {"bytes_per_launch": 79215445, "source": "k_nfft.hip",
-               "sha256": "9f33b9d7f7df2645170786d486e08c4c1409b67dada1a1950593f66123b00659"},
-    "interp": {"bytes_per_launch": 214518636, "source": "k_nfft.hip",
-               "sha256": "9f33b9d7f7df2645170786d486e08c4c1409b67dada1a1950593f66123b00659"},
-    "fft6": {"bytes_per_launch": 10833021, "source": "k_fft.hip",
+    "spread": {"bytes_per_launch": 231938537, "source": "k_nfft.hip",
+               "sha256": "4a3d65dc994f2c9d7597694c7d512f07c22e6e56fe7a20ae8175d93d03c18f21"},
+    "spread_g3": {"bytes_per_launch": 110918615, "source": "k_nfft.hip",
+                  "sha256": "4a3d65dc994f2c9d7597694c7d512f07c22e6e56fe7a20ae8175d93d03c18f21"},
+    "fold": {"bytes_per_launch": 79216365, "source": "k_nfft.hip",
+             "sha256": "4a3d65dc994f2c9d7597694c7d512f07c22e6e56fe7a20ae8175d93d03c18f21"},
+    "interp": {"bytes_per_launch": 213898443, "source": "k_nfft.hip",
+               "sha256": "4a3d65dc994f2c9d7597694c7d512f07c22e6e56fe7a20ae8175d93d03c18f21"},
+    "fft6": {"bytes_per_launch": 10832367, "source": "k_fft.hip",
              "sha256": "0fdb613e3aa356b695e37243d8a0803c82e512974bd0f3a4f21196a7c2e62e6f"},
-    "fft5": {"bytes_per_launch": 28822698, "source": "k_fft.hip",
+    "fft5": {"bytes_per_launch": 28823763, "source": "k_fft.hip",
              "sha256": "0fdb613e3aa356b695e37243d8a0803c82e512974bd0f3a4f21196a7c2e62e6f"},
-    "fft7": {"bytes_per_launch": 10842967, "source": "k_fft.hip",
+    "fft7": {"bytes_per_launch": 10842988, "source": "k_fft.hip",
              "sha256": "0fdb613e3aa356b695e37243d8a0803c82e512974bd0f3a4f21196a7c2e62e6f"},
 }
 
@@ -542,6 +546,9 @@ def main():
     K = inst.K
     dom = max(prof, key=lambda s: s["ms"])
     wk = step_work(dom, info, inst, K - 1)
+    # 3-D spreading launches whose items group jobs that spread from the same points are
+    # named with their group size (the root's down products: spread_g3)
+    kname = dom["kind"] + ("_g%d" % dom["group"] if dom.get("group", 0) > 1 else "")
     if dom["kind"] in ("spread", "interp"):
         # FP32 MFMA contractions over 16-wide patches; algorithmic work counts only the
         # (2m)^d window taps of each point, not the padding to 16^d
@@ -551,8 +558,8 @@ def main():
         # actually issued lies between the two figures)
         dense16 = achieved * (16.0 / (2 * info["m"])) ** info["d"]
         roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic_of(dom["kind"], args.N),
-                "kernel": dom["kind"], "ms_per_launch": dom["ms"],
+                "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic_of(kname, args.N),
+                "kernel": kname, "ms_per_launch": dom["ms"],
                 "work": "2 flop per window tap, (2m)^d taps per point, 9 products per launch",
                 "dense16_frac": dense16 / PEAK_FP32_TFLOPS}
     else:

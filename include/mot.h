@@ -255,10 +255,12 @@ const char *mot_strerror(int status);
  * HIP event pair around every launch of the sweep schedule on the plan's stream and
  * reports, per schedule position, the kernel kind and the mean duration.  kind:
  * 0 node update, 1 direct product, 2 spread, 3 fold, 4 FFT pass (fft_kind 0..7),
- * 5 interpolation, 6 sweep finalisation, 7 fill, 8 truncated product.  Returns the number of entries written
- * (<= max_out) or an error.  The sweeps advance the plan like mot_sinkhorn. */
+ * 5 interpolation, 6 sweep finalisation, 7 fill, 8 truncated product.  group: jobs per
+ * item of a 3-D spreading launch (jobs spreading from the same points share items), else 0.
+ * Returns the number of entries written (<= max_out) or an error.  The sweeps advance the
+ * plan like mot_sinkhorn. */
 typedef struct {
-    int32_t kind, d, n, fft_kind, n_items, calls;
+    int32_t kind, d, n, fft_kind, n_items, calls, group, reserved;
     double ms_mean;
 } mot_step_timing;
 int mot_plan_profile(mot_plan plan, int32_t sweeps, mot_step_timing *out, int32_t max_out);

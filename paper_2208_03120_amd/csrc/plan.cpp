@@ -1443,6 +1443,7 @@ int mot_plan_profile(mot_plan P, int32_t sweeps, mot_step_timing *out, int32_t m
         t.n = steps[i].n;
         t.fft_kind = steps[i].fft_kind;
         t.n_items = steps[i].n_items;
+        t.group = steps[i].group;
         t.calls = sweeps;
         t.ms_mean = acc[i] / sweeps;
         out[i] = t;

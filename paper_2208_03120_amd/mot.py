@@ -64,7 +64,7 @@ class Allocator(ctypes.Structure):
 class StepTiming(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("d", ctypes.c_int32), ("n", ctypes.c_int32),
                 ("fft_kind", ctypes.c_int32), ("n_items", ctypes.c_int32), ("calls", ctypes.c_int32),
-                ("ms_mean", ctypes.c_double)]
+                ("group", ctypes.c_int32), ("reserved", ctypes.c_int32), ("ms_mean", ctypes.c_double)]
 
 
 STEP_KIND = {0: "node", 1: "direct", 2: "spread", 3: "fold", 4: "fft", 5: "interp", 6: "final",
@@ -331,7 +331,8 @@ class Plan:
         arr = (StepTiming * 512)()
         n = _check(_lib.mot_plan_profile(self._h, int(sweeps), arr, 512), "mot_plan_profile")
         return [{"kind": STEP_KIND.get(arr[i].kind, "?"), "d": arr[i].d, "n": arr[i].n,
-                 "fft_kind": arr[i].fft_kind, "n_items": arr[i].n_items, "ms": arr[i].ms_mean}
+                 "fft_kind": arr[i].fft_kind, "n_items": arr[i].n_items, "group": arr[i].group,
+                 "ms": arr[i].ms_mean}
                 for i in range(n)]
 
     def info(self):
