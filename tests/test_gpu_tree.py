@@ -132,6 +132,32 @@ def test_nfft_star_sinkhorn_parity(mot):
     plan.close()
 
 
+def test_nfft_tree_sibling_groups_parity(mot):
+    """3-D tree whose nodes have 2 and 4 children: the down products of siblings spread
+    from their parent's points in shared items of two, and of three plus one.  NFFT sweeps
+    against the FP64 direct oracle as in the star test; the marginals at the plan's own
+    phi (one pass of grouped down products) against the oracle's at that phi; and the
+    single-product call (one job per item) from node 1 to each of its children."""
+    r = rng(43)
+    parent = [-1, 0, 0, 1, 1, 1, 1, 2]
+    inst = W.make_instance(r, 8, [900, 800, 850, 700, 750, 720, 680, 760], 3, W.TREE, 0.05,
+                           parent=parent)
+    plan = mot.Plan(inst.points, inst.weights, W.TREE, inst.parent, inst.eta, path=mot.NFFT)
+    plan.sinkhorn(40)
+    phi = plan.scalings()
+    ophi, oS, _, _ = oracle.tree_sinkhorn(inst.points, inst.weights, inst.parent, inst.eta, 40)
+    assert max_rel(gauge_fix(phi, inst.weights), gauge_fix(ophi, inst.weights)) < 1e-5
+    np.testing.assert_allclose(plan.S_history(), oS, rtol=1e-5)
+    P, _ = plan.marginals()
+    oP = oracle.tree_marginals(inst.points, inst.parent, inst.eta, phi)
+    assert max(float(np.sum(np.abs(a - b))) for a, b in zip(P, oP)) < 1e-6
+    for c in (3, 4, 5, 6):
+        v = r.uniform(0.5, 1.5, inst.sizes[1])
+        want = oracle.kernel_apply(inst.points[c], inst.points[1], v, inst.eta)
+        assert float(np.max(np.abs(plan.apply(c, 1, v) - want) / want)) < 2e-6
+    plan.close()
+
+
 @pytest.mark.parametrize("d,eta", [(3, 1e-3), (2, 3e-4), (1, 1e-4), (3, 0.05)])
 def test_direct_mixed_product_accuracy_over_eta(mot, d, eta):
     """The mixed direct product stays at FP32 accuracy for small eta (where the expanded
