@@ -379,9 +379,13 @@ __global__ __launch_bounds__(64 * kSpreadWaves, 4) void spread_kernel(const Prod
 }
 
 // 3-D spreading: the 16 b tiles are split over the block's waves.  Wave w accumulates
-// tiles b = 4 w .. 4 w + 3 over every point of the chunk (one MFMA per tile and 4-point
-// step, in point order), so a wave holds 4 accumulators per job rather than 16, no partial
-// patches are combined, and every wave writes its own quarter of the patch.
+// tiles b = w, w + 4, w + 8, w + 12 over every point of the chunk (one MFMA per tile and
+// 4-point step, in point order), so a wave holds 4 accumulators per job rather than 16, no
+// partial patches are combined, and every wave writes its own quarter of the patch.  Any
+// 2m = 12 consecutive b values hold three of each wave's four, so when the points of a step
+// share their window support every wave skips one step and none waits at the stage
+// barrier for the others (with quarters of consecutive b values the two middle waves
+// never skip).
 //
 // An item is (job_0, .., job_{G-1}, chunk): G jobs that spread different values from the
 // same points (the down products of a node's children).  They share the chunk's window
@@ -470,10 +474,12 @@ __global__ __launch_bounds__(64 * kSpreadWaves, G == 1 ? 6 : (G == 2 ? 5 : 4)) v
 #pragma unroll
                 for (int g = 0; g < G; ++g) x[g] = vl[g * kStage + pi] * w0;
                 const float w2 = row[2 * kPatch + li];
-                const f32x4 w1 = reinterpret_cast<const f32x4 *>(row + kPatch)[wave];
+                // w_1,p[b] for the wave's b = wave + 4 u
+                const f32x4 w1 = f32x4{row[kPatch + wave], row[kPatch + wave + 4], row[kPatch + wave + 8],
+                                       row[kPatch + wave + 12]};
 #pragma unroll
                 for (int u = 0; u < 4; ++u)
-                    // B is zero when b = 4 w + u is outside the window of all four points:
+                    // B is zero when b = w + 4 u is outside the window of all four points:
                     // the products would add exact zeros
                     if (__any(w1[u] != 0.0f)) {
                         const float bu = w1[u] * w2;
@@ -492,7 +498,7 @@ __global__ __launch_bounds__(64 * kSpreadWaves, G == 1 ? 6 : (G == 2 ? 5 : 4)) v
 #pragma unroll
             for (int u = 0; u < 4; ++u)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) out[((4 * lk + r) * 16 + 4 * wave + u) * 16 + li] = acc[g][u][r];
+                for (int r = 0; r < 4; ++r) out[((4 * lk + r) * 16 + wave + 4 * u) * 16 + li] = acc[g][u][r];
         }
     }
 }
