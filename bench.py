@@ -35,17 +35,17 @@ PEAK_FP32_TFLOPS = 157.3  # dense FP32 MFMA
 # points).  Valid only for the kernel source it was measured on (SHA-256 of its file).
 COPY_MIB = 256
 TRAFFIC = {
-    "spread": {"bytes_per_launch": 231938537, "source": "k_nfft.hip",
-               "sha256": "4a3d65dc994f2c9d7597694c7d512f07c22e6e56fe7a20ae8175d93d03c18f21"},
-    "spread_g3": {"bytes_per_launch": 110918615, "source": "k_nfft.hip",
-                  "sha256": "4a3d65dc994f2c9d7597694c7d512f07c22e6e56fe7a20ae8175d93d03c18f21"},
-    "fold": {"bytes_per_launch": 79216365, "source": "k_nfft.hip",
-             "sha256": "4a3d65dc994f2c9d7597694c7d512f07c22e6e56fe7a20ae8175d93d03c18f21"},
-    "interp": {"bytes_per_launch": 213898443, "source": "k_nfft.hip",
-               "sha256": "4a3d65dc994f2c9d7597694c7d512f07c22e6e56fe7a20ae8175d93d03c18f21"},
+    "spread": {"bytes_per_launch": 231910438, "source": "k_nfft.hip",
+               "sha256": "48ac8a42222f48a3f26efe18f287341582c166c5417d40eae4fb22af96445a8c"},
+    "spread_g3": {"bytes_per_launch": 110922436, "source": "k_nfft.hip",
+                  "sha256": "48ac8a42222f48a3f26efe18f287341582c166c5417d40eae4fb22af96445a8c"},
+    "fold": {"bytes_per_launch": 79214317, "source": "k_nfft.hip",
+             "sha256": "48ac8a42222f48a3f26efe18f287341582c166c5417d40eae4fb22af96445a8c"},
+    "interp": {"bytes_per_launch": 214426965, "source": "k_nfft.hip",
+               "sha256": "48ac8a42222f48a3f26efe18f287341582c166c5417d40eae4fb22af96445a8c"},
     "fft6": {"bytes_per_launch": 10832367, "source": "k_fft.hip",
              "sha256": "0fdb613e3aa356b695e37243d8a0803c82e512974bd0f3a4f21196a7c2e62e6f"},
-    "fft5": {"bytes_per_launch": 28823763, "source": "k_fft.hip",
+    "fft5": {"bytes_per_launch": 28822691, "source": "k_fft.hip",
              "sha256": "0fdb613e3aa356b695e37243d8a0803c82e512974bd0f3a4f21196a7c2e62e6f"},
     "fft7": {"bytes_per_launch": 10842988, "source": "k_fft.hip",
              "sha256": "0fdb613e3aa356b695e37243d8a0803c82e512974bd0f3a4f21196a7c2e62e6f"},
