@@ -204,7 +204,7 @@ struct mot_plan_s {
     // 2K is the stand-alone product used by mot_apply_kernel
     std::vector<mot::ProdJob> jobs;
     mot::ProdJob *jobs_dev = nullptr;
-    int32_t *exp_slots = nullptr;  // [2K + 1]
+    int32_t *exp_slots = nullptr;  // [2K + 1] slots, kExpSlotStride ints apart
     float *D = nullptr;
     float2 *twiddle = nullptr;
     // statistics

@@ -19,6 +19,10 @@ constexpr int kMaxTaps = 16;      // 2m taps per dimension, m <= 8
 constexpr int kMaxN = 512;        // FFT grid per dimension
 constexpr int kMinN = 16;
 constexpr int kMaxChildren = 64;  // children per tree node handled by the node kernels
+// Exponent slots (one int each, raised by atomicMax from every block of a node launch) sit
+// one 128-byte line apart, so the atomics on different slots go to different L2 lines
+// instead of queueing on one.
+constexpr int kExpSlotStride = 32;
 
 // ---------------------------------------------------------------------------------------
 // Global-memory views of generic pointers: loads and stores through them are global

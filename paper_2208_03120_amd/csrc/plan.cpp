@@ -496,7 +496,7 @@ int tree_build_schedule(mot_plan_s *P)
         for (int c : ch) {
             bptr.push_back(P->marg[c].beta);
             dptr.push_back(P->marg[c].down_src);
-            eptr.push_back(P->exp_slots + 2 * c);
+            eptr.push_back(P->exp_slots + (size_t)(2 * c) * kExpSlotStride);
         }
         const double **bdev = nullptr;
         double **ddev = nullptr;
@@ -519,7 +519,7 @@ int tree_build_schedule(mot_plan_s *P)
         base.down_src = ddev;
         base.down_exp = edev;
         base.up_src = P->marg[k].up_src;
-        base.up_exp = P->exp_slots + 2 * k + 1;
+        base.up_exp = P->exp_slots + (size_t)(2 * k + 1) * kExpSlotStride;
         base.marg_out = P->marg[k].marg;
         base.partial = P->s_partial;
         base.flag = P->flag;
@@ -572,7 +572,7 @@ int tree_build_schedule(mot_plan_s *P)
         F.S_hist = P->S_hist;
         F.err_hist = P->err_hist;
         F.exp_slots = P->exp_slots;
-        F.n_exp_slots = 2 * K + 1;
+        F.n_exp_slots = (2 * K + 1) * kExpSlotStride;
         F.eta = P->eta;
         T->fjob.push_back(F);
     }
@@ -1015,8 +1015,8 @@ int mot::setup_marginals(mot_plan_s *P, const std::vector<double> &pts_h, const 
         MOT_HIP(launch_gather_rows(w_dev + P->off[k], P->marg[k].perm, P->n[k], 1, P->marg[k].mu, P->stream));
         MOT_HIP(launch_fill_double(P->marg[k].phi, 1.0, P->n[k], P->stream));
     }
-    MOT_TRY(P->arena.get_n(2 * K + 1, &P->exp_slots));
-    MOT_HIP(launch_fill_int(P->exp_slots, INT32_MIN, 2 * K + 1, P->stream));
+    MOT_TRY(P->arena.get_n((size_t)(2 * K + 1) * kExpSlotStride, &P->exp_slots));
+    MOT_HIP(launch_fill_int(P->exp_slots, INT32_MIN, (2 * K + 1) * kExpSlotStride, P->stream));
     MOT_TRY(plan_stats_alloc(P, total_partials + 64 * K));
     return MOT_OK;
 }
@@ -1041,10 +1041,10 @@ static int create_tree(mot_plan_s *P, const std::vector<double> &pts_h, const st
     for (int k = 1; k < K; ++k) {
         const int p = P->parent[k];
         // down: gamma_k = K^{(k,p)} u_k  (targets k, sources p)
-        MOT_TRY(make_prod_job(P, k, p, P->marg[k].down_src, P->exp_slots + 2 * k, P->marg[k].gamma,
+        MOT_TRY(make_prod_job(P, k, p, P->marg[k].down_src, P->exp_slots + (size_t)(2 * k) * kExpSlotStride, P->marg[k].gamma,
                               &P->jobs[2 * k], nullptr));
         // up: beta_k = K^{(p,k)} v_k  (targets p, sources k)
-        MOT_TRY(make_prod_job(P, p, k, P->marg[k].up_src, P->exp_slots + 2 * k + 1, P->marg[k].beta,
+        MOT_TRY(make_prod_job(P, p, k, P->marg[k].up_src, P->exp_slots + (size_t)(2 * k + 1) * kExpSlotStride, P->marg[k].beta,
                               &P->jobs[2 * k + 1], nullptr));
     }
     MOT_TRY(P->arena.get_n(P->jobs.size(), &P->jobs_dev));
@@ -1055,7 +1055,7 @@ static int create_tree(mot_plan_s *P, const std::vector<double> &pts_h, const st
     MOT_TRY(tree_steps(refs, P->jobs, P->jobs_dev, T->njobs, T->njobs_dev, T->fjob, T->fjob_dev,
                        P->arena, P->sched.sweep, P->sched.init_up, P->sched.marg_pass));
     MOT_TRY(run_steps(P->sched.init_up, P->stream));
-    MOT_HIP(launch_fill_int(P->exp_slots, INT32_MIN, 2 * K + 1, P->stream));
+    MOT_HIP(launch_fill_int(P->exp_slots, INT32_MIN, (2 * K + 1) * kExpSlotStride, P->stream));
     MOT_HIP(hipStreamSynchronize(P->stream));
     return MOT_OK;
 }
@@ -1091,9 +1091,9 @@ int tree_run_sweeps(mot_plan_s *P, int sweeps, bool use_graph)
 
 int tree_init_up(mot_plan_s *P)
 {
-    MOT_HIP(launch_fill_int(P->exp_slots, INT32_MIN, 2 * P->K + 1, P->stream));
+    MOT_HIP(launch_fill_int(P->exp_slots, INT32_MIN, (2 * P->K + 1) * kExpSlotStride, P->stream));
     MOT_TRY(run_steps(P->sched.init_up, P->stream));
-    MOT_HIP(launch_fill_int(P->exp_slots, INT32_MIN, 2 * P->K + 1, P->stream));
+    MOT_HIP(launch_fill_int(P->exp_slots, INT32_MIN, (2 * P->K + 1) * kExpSlotStride, P->stream));
     return MOT_OK;
 }
 
@@ -1293,9 +1293,9 @@ int mot_pair_marginal(mot_plan P, int32_t k, double *out, int32_t ptr_kind)
         if (P->topology == MOT_CIRCLE) return circle_pair_marginal(P, k, dst);
         // a consistent pass at the current phi (as in mot_marginals): the down source of k
         // at its parent and the up source of k are then the two outer factors
-        MOT_HIP(launch_fill_int(P->exp_slots, INT32_MIN, 2 * P->K + 1, P->stream));
+        MOT_HIP(launch_fill_int(P->exp_slots, INT32_MIN, (2 * P->K + 1) * kExpSlotStride, P->stream));
         MOT_TRY(run_steps(P->sched.marg_pass, P->stream));
-        MOT_HIP(launch_fill_int(P->exp_slots, INT32_MIN, 2 * P->K + 1, P->stream));
+        MOT_HIP(launch_fill_int(P->exp_slots, INT32_MIN, (2 * P->K + 1) * kExpSlotStride, P->stream));
         MOT_HIP(launch_tree_pair(P->marg[k].down_src, P->marg[a].pts, P->marg[a].perm, P->n[a], P->marg[k].up_src,
                                  P->marg[k].pts, P->marg[k].perm, P->n[k], P->d, P->jobs[2 * k + 1].eta, dst,
                                  P->stream));
@@ -1518,9 +1518,9 @@ int mot_marginals(mot_plan P, double *P_out, double *l1_err, int32_t ptr_kind)
     if (P->topology == MOT_CIRCLE) {
         MOT_TRY(circle_marginals(P, nullptr));
     } else {
-        MOT_HIP(launch_fill_int(P->exp_slots, INT32_MIN, 2 * P->K + 1, P->stream));
+        MOT_HIP(launch_fill_int(P->exp_slots, INT32_MIN, (2 * P->K + 1) * kExpSlotStride, P->stream));
         MOT_TRY(run_steps(P->sched.marg_pass, P->stream));
-        MOT_HIP(launch_fill_int(P->exp_slots, INT32_MIN, 2 * P->K + 1, P->stream));
+        MOT_HIP(launch_fill_int(P->exp_slots, INT32_MIN, (2 * P->K + 1) * kExpSlotStride, P->stream));
         // the marginal pass overwrote beta with values at the current phi (the same
         // values a following sweep expects), and gamma with consistent values
     }
@@ -1573,7 +1573,7 @@ int mot_apply_kernel(mot_plan P, int32_t t, int32_t s, const double *v, double *
                            ptr_kind == MOT_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
                            P->stream));
     MOT_HIP(launch_gather_rows(tmp, P->marg[s].perm, P->n[s], 1, P->apply_in, P->stream));
-    int32_t *slot = P->exp_slots + 2 * P->K;
+    int32_t *slot = P->exp_slots + (size_t)(2 * P->K) * kExpSlotStride;
     MOT_HIP(launch_fill_int(slot, INT32_MIN, 1, P->stream));
     MOT_HIP(launch_vec_exp(P->apply_in, P->n[s], slot, P->stream));
     // job slot 2K: buffers sized for the largest chunk count, allocated on first use
