@@ -1415,7 +1415,17 @@ int mot_plan_profile(mot_plan P, int32_t sweeps, mot_step_timing *out, int32_t m
     if (P->topology != MOT_TREE) return MOT_EUNSUPPORTED;
     const auto &steps = P->sched.sweep;
     const size_t ns = steps.size();
-    std::vector<hipEvent_t> ev(2 * ns);
+    // events destroyed on every return path
+    struct Events {
+        std::vector<hipEvent_t> e;
+        ~Events()
+        {
+            for (hipEvent_t x : e)
+                if (x) (void)hipEventDestroy(x);
+        }
+    } evs;
+    evs.e.assign(2 * ns, nullptr);
+    std::vector<hipEvent_t> &ev = evs.e;
     for (auto &e : ev) MOT_HIP(hipEventCreate(&e));
     std::vector<double> acc(ns, 0.0);
     for (int r = 0; r < sweeps; ++r) {
@@ -1433,7 +1443,6 @@ int mot_plan_profile(mot_plan P, int32_t sweeps, mot_step_timing *out, int32_t m
         }
     }
     P->host_sweeps += sweeps;
-    for (auto &e : ev) (void)hipEventDestroy(e);
     const int nout = std::min((int)ns, (int)max_out);
     static const int kind_code[] = {0, 1, 2, 3, 4, 5, 6, 7, 8};
     for (int i = 0; i < nout; ++i) {

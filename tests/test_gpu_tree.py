@@ -158,6 +158,32 @@ def test_nfft_tree_sibling_groups_parity(mot):
     plan.close()
 
 
+def test_sweep_schedule_and_step_timings(mot):
+    """The NFFT sweep schedule of a 3-D star (K = 5, four leaves): one node launch before
+    the down products, the leaves' launch before the up products, the finalisation last;
+    the down products' spread takes its four jobs as one item group of three and one of
+    one, the up products' spread one job per item; every step is timed (mean > 0) and
+    profiling advances the plan like sweeps (its S history grows by the profiled sweeps)."""
+    r = rng(45)
+    inst = W.make_instance(r, 5, [1200, 900, 950, 1000, 880], 3, W.TREE, 0.05, parent=W.star_parent(5))
+    plan = mot.Plan(inst.points, inst.weights, W.TREE, inst.parent, inst.eta, path=mot.NFFT)
+    plan.sinkhorn(2)
+    before = len(plan.S_history())
+    steps = plan.profile(3)
+    assert len(plan.S_history()) == before + 3
+    kinds = [s["kind"] for s in steps]
+    assert kinds[0] == "node" and kinds[-1] == "final"
+    assert all(s["ms"] > 0 for s in steps)
+    spreads = [s for s in steps if s["kind"] == "spread"]
+    # down products: root -> 4 leaves from the root's points (groups 3 + 1); up products:
+    # 4 leaves -> root, each from its own points (group 1)
+    assert sorted(s["group"] for s in spreads) == [1, 1, 3]
+    # the group-of-three launch and the root's group-of-one launch cover the same chunks
+    root_groups = [s for s in spreads if s["kind"] == "spread"][:2]
+    assert root_groups[0]["n_items"] == root_groups[1]["n_items"]
+    plan.close()
+
+
 @pytest.mark.parametrize("d,eta", [(3, 1e-3), (2, 3e-4), (1, 1e-4), (3, 0.05)])
 def test_direct_mixed_product_accuracy_over_eta(mot, d, eta):
     """The mixed direct product stays at FP32 accuracy for small eta (where the expanded
