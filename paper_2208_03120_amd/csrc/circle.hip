@@ -49,21 +49,55 @@ __device__ __forceinline__ unsigned short f16_bits(float x)
     return __builtin_bit_cast(unsigned short, h);
 }
 
-// C[M x N] (row-major, ldc) = diag(2^-rexp) A[M x K] (FP32, lda) diag(phi) B[N x K]^T
-// (16-bit, ldb), all dimensions padded to the tile sizes by the caller (zero padding);
-// the products A_il phi_l 2^-rexp_i are formed in FP64.  MODE: 0 BF16, 1 FP16,
-// 2 split BF16.
+// A' = diag(2^-rexp) A diag(phi) in the GEMM's 16-bit form: the products A_il phi_l
+// 2^-rexp_i are formed in FP64 and rounded to FP32, then to FP16 (MODE 1) or BF16 (MODE 0),
+// or split into BF16 high and low parts (MODE 2: lo = bf16(x - hi)).  Formed once per
+// product rather than in every column block of the GEMM.  grid: (Kp / 2048 rounded up,
+// rows); a thread converts 8 consecutive entries (Kp is a multiple of 8).
 template <int MODE>
-__global__ __launch_bounds__(256) void gemm_kernel(const float *__restrict__ A, int lda,
-                                                   const double *__restrict__ phi,
+__global__ __launch_bounds__(256) void scale_split_kernel(const float *__restrict__ A, int lda,
+                                                          const double *__restrict__ phi,
+                                                          const int32_t *__restrict__ rexp, int Kp,
+                                                          unsigned short *__restrict__ Ah,
+                                                          unsigned short *__restrict__ Al)
+{
+    const int i = blockIdx.y;
+    const int l0 = (blockIdx.x * 256 + threadIdx.x) * 8;
+    if (l0 >= Kp) return;
+    const double rowscale = ldexp(1.0, -rexp[i]);
+    const float4 *src = reinterpret_cast<const float4 *>(A + (int64_t)i * lda + l0);
+    unsigned short hv[8], lv[8];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const float4 a4 = src[q];
+        const float av[4] = {a4.x, a4.y, a4.z, a4.w};
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const float x = (float)((double)av[u] * phi[l0 + 4 * q + u] * rowscale);
+            if (MODE == 1) {
+                hv[4 * q + u] = f16_bits(x);
+            } else {
+                hv[4 * q + u] = bf16_bits(x);
+                if (MODE == 2) lv[4 * q + u] = bf16_bits(x - bf16_value(hv[4 * q + u]));
+            }
+        }
+    }
+    *reinterpret_cast<uint4 *>(Ah + (int64_t)i * lda + l0) = *reinterpret_cast<uint4 *>(&hv[0]);
+    if (MODE == 2) *reinterpret_cast<uint4 *>(Al + (int64_t)i * lda + l0) = *reinterpret_cast<uint4 *>(&lv[0]);
+}
+
+// C[M x N] (row-major, ldc) = A'[M x K] B[N x K]^T with A' from scale_split_kernel (lda)
+// and B the 16-bit kernel matrix (ldb), all dimensions padded to the tile sizes by the
+// caller (zero padding).  MODE: 0 BF16, 1 FP16, 2 split BF16 (hi hi + hi lo + lo hi).
+template <int MODE>
+__global__ __launch_bounds__(256) void gemm_kernel(const unsigned short *__restrict__ Ah,
+                                                   const unsigned short *__restrict__ Al, int lda,
                                                    const unsigned short *__restrict__ Bh,
                                                    const unsigned short *__restrict__ Bl, int ldb,
-                                                   float *__restrict__ C, int ldc, int K,
-                                                   const int32_t *__restrict__ rexp)
+                                                   float *__restrict__ C, int ldc, int K)
 {
     __shared__ unsigned short As[kBM * kLdsK], Bs[kBN * kLdsK];
     __shared__ unsigned short Asl[MODE == 2 ? kBM * kLdsK : 1], Bsl[MODE == 2 ? kBN * kLdsK : 1];
-    __shared__ double phis[kBK];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;  // wave's 64 x 64 sub-tile
     const int m0 = blockIdx.y * kBM, n0 = blockIdx.x * kBN;
@@ -76,35 +110,17 @@ __global__ __launch_bounds__(256) void gemm_kernel(const float *__restrict__ A, 
             for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
     // global staging assignment: A: row tid/2, 16 columns from (tid&1)*16; B: row tid/2, 16
     const int ar = tid >> 1, ac = (tid & 1) * 16;
-    const double rowscale = ldexp(1.0, -rexp[m0 + ar]);
     for (int k0 = 0; k0 < K; k0 += kBK) {
-        if (tid < kBK) phis[tid] = phi[k0 + tid];
-        __syncthreads();
         {
-            const float4 *src = reinterpret_cast<const float4 *>(A + (int64_t)(m0 + ar) * lda + k0 + ac);
-            unsigned short hv[16], lv[16];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const float4 a4 = src[q];
-                const float av[4] = {a4.x, a4.y, a4.z, a4.w};
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const float x = (float)((double)av[u] * phis[ac + 4 * q + u] * rowscale);
-                    if (MODE == 1) {
-                        hv[4 * q + u] = f16_bits(x);
-                    } else {
-                        hv[4 * q + u] = bf16_bits(x);
-                        if (MODE == 2) lv[4 * q + u] = bf16_bits(x - bf16_value(hv[4 * q + u]));
-                    }
-                }
-            }
-            uint4 *dst = reinterpret_cast<uint4 *>(&As[ar * kLdsK + ac]);
-            dst[0] = *reinterpret_cast<uint4 *>(&hv[0]);
-            dst[1] = *reinterpret_cast<uint4 *>(&hv[8]);
+            const uint4 *as = reinterpret_cast<const uint4 *>(Ah + (int64_t)(m0 + ar) * lda + k0 + ac);
+            uint4 *ad = reinterpret_cast<uint4 *>(&As[ar * kLdsK + ac]);
+            ad[0] = as[0];
+            ad[1] = as[1];
             if (MODE == 2) {
-                uint4 *dl = reinterpret_cast<uint4 *>(&Asl[ar * kLdsK + ac]);
-                dl[0] = *reinterpret_cast<uint4 *>(&lv[0]);
-                dl[1] = *reinterpret_cast<uint4 *>(&lv[8]);
+                const uint4 *asl = reinterpret_cast<const uint4 *>(Al + (int64_t)(m0 + ar) * lda + k0 + ac);
+                uint4 *adl = reinterpret_cast<uint4 *>(&Asl[ar * kLdsK + ac]);
+                adl[0] = asl[0];
+                adl[1] = asl[1];
             }
             const uint4 *bs = reinterpret_cast<const uint4 *>(Bh + (int64_t)(n0 + ar) * ldb + k0 + ac);
             uint4 *bd = reinterpret_cast<uint4 *>(&Bs[ar * kLdsK + ac]);
@@ -430,6 +446,9 @@ struct CircleState {
     void *Yg1 = nullptr;           // Yg_1 = Kmat(0, 1) (constant)
     std::vector<unsigned short *> Kb_h, Kb_l, Kg_h, Kg_l;  // dense: Kmat(k,k+1), Kmat(k,k-1)
     int32_t *rexp = nullptr;
+    // dense path: the scaled left operand of a product in 16-bit form (n1p x ldmax each;
+    // Al only for split BF16)
+    unsigned short *Ah = nullptr, *Al = nullptr;
     // dense path: power-of-two scale of every row of each matrix (see the file comment)
     int K = 0;
     std::vector<int32_t *> sb;     // [K] row scales of Yb_k
@@ -467,16 +486,23 @@ static hipError_t launch_gemm(const CircleState &C, const float *A, int lda, con
                               hipStream_t s)
 {
     dim3 grid(Np / kBN, Mp / kBM);
+    const dim3 sgrid((unsigned)((Kp + 2047) / 2048), (unsigned)Mp);
     hipLaunchKernelGGL(row_exp_kernel, dim3(Mp), dim3(256), 0, s, A, lda, Kp, phi, C.rexp, s_in, s_out);
     if (C.mode == 1) {
-        hipLaunchKernelGGL(gemm_kernel<1>, grid, dim3(256), 0, s, A, lda, phi, Bh, Bl, ldb, Cm, ldc, Kp,
-                           (const int32_t *)C.rexp);
+        hipLaunchKernelGGL(scale_split_kernel<1>, sgrid, dim3(256), 0, s, A, lda, phi, (const int32_t *)C.rexp, Kp,
+                           C.Ah, C.Al);
+        hipLaunchKernelGGL(gemm_kernel<1>, grid, dim3(256), 0, s, (const unsigned short *)C.Ah,
+                           (const unsigned short *)C.Al, lda, Bh, Bl, ldb, Cm, ldc, Kp);
     } else if (C.mode == 2) {
-        hipLaunchKernelGGL(gemm_kernel<2>, grid, dim3(256), 0, s, A, lda, phi, Bh, Bl, ldb, Cm, ldc, Kp,
-                           (const int32_t *)C.rexp);
+        hipLaunchKernelGGL(scale_split_kernel<2>, sgrid, dim3(256), 0, s, A, lda, phi, (const int32_t *)C.rexp, Kp,
+                           C.Ah, C.Al);
+        hipLaunchKernelGGL(gemm_kernel<2>, grid, dim3(256), 0, s, (const unsigned short *)C.Ah,
+                           (const unsigned short *)C.Al, lda, Bh, Bl, ldb, Cm, ldc, Kp);
     } else {
-        hipLaunchKernelGGL(gemm_kernel<0>, grid, dim3(256), 0, s, A, lda, phi, Bh, Bl, ldb, Cm, ldc, Kp,
-                           (const int32_t *)C.rexp);
+        hipLaunchKernelGGL(scale_split_kernel<0>, sgrid, dim3(256), 0, s, A, lda, phi, (const int32_t *)C.rexp, Kp,
+                           C.Ah, C.Al);
+        hipLaunchKernelGGL(gemm_kernel<0>, grid, dim3(256), 0, s, (const unsigned short *)C.Ah,
+                           (const unsigned short *)C.Al, lda, Bh, Bl, ldb, Cm, ldc, Kp);
     }
     return hipGetLastError();
 }
@@ -657,6 +683,8 @@ int circle_create(mot_plan_s *P, const std::vector<double> &pts_h, const std::ve
         for (int k = 1; k <= K - 2; ++k) MOT_TRY(kmat16(P, C, k, k + 1, &C.Kb_h[k], &C.Kb_l[k]));
         for (int k = 2; k <= K - 1; ++k) MOT_TRY(kmat16(P, C, k, k - 1, &C.Kg_h[k], &C.Kg_l[k]));
         MOT_TRY(P->arena.get_n((size_t)C.n1p, &C.rexp));
+        MOT_TRY(P->arena.get_n((size_t)C.n1p * ldmax, &C.Ah));
+        if (C.mode == 2) MOT_TRY(P->arena.get_n((size_t)C.n1p * ldmax, &C.Al));
         C.K = K;
         C.sb.assign(K, nullptr);
         for (int k = 1; k < K - 1; ++k) MOT_TRY(P->arena.get_n((size_t)C.n1p, &C.sb[k]));
@@ -793,7 +821,11 @@ size_t circle_footprint(int K, const int64_t *n, int path, int precision)
     for (int k = 0; k < K; ++k) ldmax = std::max<int64_t>(ldmax, nfft ? n[k] : pad_to(n[k], 128));
     const size_t esz = nfft ? 8 : 4;
     b += (size_t)n1 * ldmax * esz * (K + 2);
-    if (!nfft) b += (size_t)ldmax * ldmax * 2 * (2 * (K - 2)) * (precision == MOT_PREC_BF16X3 ? 2 : 1);
+    if (!nfft) {
+        const size_t parts = precision == MOT_PREC_BF16X3 ? 2 : 1;
+        b += (size_t)ldmax * ldmax * 2 * (2 * (K - 2)) * parts;  // kernel matrices
+        b += (size_t)n1 * ldmax * 2 * parts;                       // scaled left operand
+    }
     else b += (size_t)n1 * ldmax * 8 + (size_t)n1 * (64 * 1024);
     return b;
 }
