@@ -110,30 +110,50 @@ __global__ __launch_bounds__(256) void gemm_kernel(const unsigned short *__restr
             for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
     // global staging assignment: A: row tid/2, 16 columns from (tid&1)*16; B: row tid/2, 16
     const int ar = tid >> 1, ac = (tid & 1) * 16;
+    // the next K step's tiles are fetched into registers while the current one is multiplied
+    const unsigned short *pa = Ah + (int64_t)(m0 + ar) * lda + ac, *pb = Bh + (int64_t)(n0 + ar) * ldb + ac;
+    const unsigned short *pal = MODE == 2 ? Al + (int64_t)(m0 + ar) * lda + ac : nullptr;
+    const unsigned short *pbl = MODE == 2 ? Bl + (int64_t)(n0 + ar) * ldb + ac : nullptr;
+    uint4 ga0 = reinterpret_cast<const uint4 *>(pa)[0], ga1 = reinterpret_cast<const uint4 *>(pa)[1];
+    uint4 gb0 = reinterpret_cast<const uint4 *>(pb)[0], gb1 = reinterpret_cast<const uint4 *>(pb)[1];
+    uint4 gal0 = ga0, gal1 = ga1, gbl0 = gb0, gbl1 = gb1;
+    if (MODE == 2) {
+        gal0 = reinterpret_cast<const uint4 *>(pal)[0];
+        gal1 = reinterpret_cast<const uint4 *>(pal)[1];
+        gbl0 = reinterpret_cast<const uint4 *>(pbl)[0];
+        gbl1 = reinterpret_cast<const uint4 *>(pbl)[1];
+    }
     for (int k0 = 0; k0 < K; k0 += kBK) {
         {
-            const uint4 *as = reinterpret_cast<const uint4 *>(Ah + (int64_t)(m0 + ar) * lda + k0 + ac);
             uint4 *ad = reinterpret_cast<uint4 *>(&As[ar * kLdsK + ac]);
-            ad[0] = as[0];
-            ad[1] = as[1];
-            if (MODE == 2) {
-                const uint4 *asl = reinterpret_cast<const uint4 *>(Al + (int64_t)(m0 + ar) * lda + k0 + ac);
-                uint4 *adl = reinterpret_cast<uint4 *>(&Asl[ar * kLdsK + ac]);
-                adl[0] = asl[0];
-                adl[1] = asl[1];
-            }
-            const uint4 *bs = reinterpret_cast<const uint4 *>(Bh + (int64_t)(n0 + ar) * ldb + k0 + ac);
             uint4 *bd = reinterpret_cast<uint4 *>(&Bs[ar * kLdsK + ac]);
-            bd[0] = bs[0];
-            bd[1] = bs[1];
+            ad[0] = ga0;
+            ad[1] = ga1;
+            bd[0] = gb0;
+            bd[1] = gb1;
             if (MODE == 2) {
-                const uint4 *bl = reinterpret_cast<const uint4 *>(Bl + (int64_t)(n0 + ar) * ldb + k0 + ac);
+                uint4 *adl = reinterpret_cast<uint4 *>(&Asl[ar * kLdsK + ac]);
                 uint4 *bdl = reinterpret_cast<uint4 *>(&Bsl[ar * kLdsK + ac]);
-                bdl[0] = bl[0];
-                bdl[1] = bl[1];
+                adl[0] = gal0;
+                adl[1] = gal1;
+                bdl[0] = gbl0;
+                bdl[1] = gbl1;
             }
         }
         __syncthreads();
+        if (k0 + kBK < K) {
+            const int kn = k0 + kBK;
+            ga0 = reinterpret_cast<const uint4 *>(pa + kn)[0];
+            ga1 = reinterpret_cast<const uint4 *>(pa + kn)[1];
+            gb0 = reinterpret_cast<const uint4 *>(pb + kn)[0];
+            gb1 = reinterpret_cast<const uint4 *>(pb + kn)[1];
+            if (MODE == 2) {
+                gal0 = reinterpret_cast<const uint4 *>(pal + kn)[0];
+                gal1 = reinterpret_cast<const uint4 *>(pal + kn)[1];
+                gbl0 = reinterpret_cast<const uint4 *>(pbl + kn)[0];
+                gbl1 = reinterpret_cast<const uint4 *>(pbl + kn)[1];
+            }
+        }
 #pragma unroll
         for (int ks = 0; ks < kBK; ks += 16) {
             const int kk = ks + 8 * (lane >> 5);
