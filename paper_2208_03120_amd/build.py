@@ -59,10 +59,12 @@ def build(verbose=False) -> str:
     tmp = LIB + ".tmp"
     tl = _torch_lib_dir()
     if tl:
+        # the HIP runtime and rocBLAS of the process's PyTorch, so that one runtime serves both
         cmd = (["g++", "-shared", "-fPIC", "-o", tmp] + [o for o, _ in results] +
-               ["-L" + tl, "-l:libamdhip64.so", "-Wl,-rpath," + tl, "-Wl,--no-undefined"])
+               ["-L" + tl, "-l:libamdhip64.so", "-l:librocblas.so", "-Wl,-rpath," + tl, "-Wl,--no-undefined"])
     else:
-        cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + [o for o, _ in results]
+        cmd = ([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + [o for o, _ in results] +
+               ["-lrocblas"])
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed:\n" + r.stdout + r.stderr)
