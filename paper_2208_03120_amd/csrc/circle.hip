@@ -13,7 +13,8 @@
 //
 // Dense path: each product forms A' = diag(2^-rexp) A diag(phi) in FP64 and rounds it to
 // the 16-bit operand (scale_split_kernel); C = A' B^T is then a plain 16-bit GEMM with FP32
-// accumulation and output, run by rocBLAS (MFMA).  Precision modes: BF16, FP16 and split
+// accumulation and output, run by rocBLAS (MFMA), or for small products by gemm_kernel
+// (v_mfma_f32_32x32x16_bf16 / _f16).  Precision modes: BF16, FP16 and split
 // BF16 (A' = Ah + Al, B = Bh + Bl, C = Ah Bh + Ah Bl + Al Bh).  The
 // FP32 matrices carry a power-of-two scale per row: before each product the rows of
 // A diag(phi) are normalised (exponent of their largest entry, taken in FP64) and the
@@ -30,6 +31,12 @@
 #include "host.h"
 
 namespace mot {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+
+constexpr int kBM = 128, kBN = 128, kBK = 32, kLdsK = kBK + 8;  // padded LDS row (elements)
 
 __device__ __forceinline__ unsigned short bf16_bits(float x)
 {
@@ -83,6 +90,121 @@ __global__ __launch_bounds__(256) void scale_split_kernel(const float *__restric
     if (MODE == 2) *reinterpret_cast<uint4 *>(Al + (int64_t)i * lda + l0) = *reinterpret_cast<uint4 *>(&lv[0]);
 }
 
+
+// C[M x N] (row-major, ldc) = A'[M x K] B[N x K]^T with A' from scale_split_kernel (lda)
+// and B the 16-bit kernel matrix (ldb), all dimensions padded to the tile sizes by the
+// caller (zero padding).  MODE: 0 BF16, 1 FP16, 2 split BF16 (hi hi + hi lo + lo hi), the
+// three products accumulated in one FP32 accumulator.  Used for small products, where one
+// fused launch beats the library's calls.
+template <int MODE>
+__global__ __launch_bounds__(256) void gemm_kernel(const unsigned short *__restrict__ Ah,
+                                                   const unsigned short *__restrict__ Al, int lda,
+                                                   const unsigned short *__restrict__ Bh,
+                                                   const unsigned short *__restrict__ Bl, int ldb,
+                                                   float *__restrict__ C, int ldc, int K)
+{
+    __shared__ unsigned short As[kBM * kLdsK], Bs[kBN * kLdsK];
+    __shared__ unsigned short Asl[MODE == 2 ? kBM * kLdsK : 1], Bsl[MODE == 2 ? kBN * kLdsK : 1];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;  // wave's 64 x 64 sub-tile
+    const int m0 = blockIdx.y * kBM, n0 = blockIdx.x * kBN;
+    f32x16 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
+    // global staging assignment: A: row tid/2, 16 columns from (tid&1)*16; B: row tid/2, 16
+    const int ar = tid >> 1, ac = (tid & 1) * 16;
+    // the next K step's tiles are fetched into registers while the current one is multiplied
+    const unsigned short *pa = Ah + (int64_t)(m0 + ar) * lda + ac, *pb = Bh + (int64_t)(n0 + ar) * ldb + ac;
+    const unsigned short *pal = MODE == 2 ? Al + (int64_t)(m0 + ar) * lda + ac : nullptr;
+    const unsigned short *pbl = MODE == 2 ? Bl + (int64_t)(n0 + ar) * ldb + ac : nullptr;
+    uint4 ga0 = reinterpret_cast<const uint4 *>(pa)[0], ga1 = reinterpret_cast<const uint4 *>(pa)[1];
+    uint4 gb0 = reinterpret_cast<const uint4 *>(pb)[0], gb1 = reinterpret_cast<const uint4 *>(pb)[1];
+    uint4 gal0 = ga0, gal1 = ga1, gbl0 = gb0, gbl1 = gb1;
+    if (MODE == 2) {
+        gal0 = reinterpret_cast<const uint4 *>(pal)[0];
+        gal1 = reinterpret_cast<const uint4 *>(pal)[1];
+        gbl0 = reinterpret_cast<const uint4 *>(pbl)[0];
+        gbl1 = reinterpret_cast<const uint4 *>(pbl)[1];
+    }
+    for (int k0 = 0; k0 < K; k0 += kBK) {
+        {
+            uint4 *ad = reinterpret_cast<uint4 *>(&As[ar * kLdsK + ac]);
+            uint4 *bd = reinterpret_cast<uint4 *>(&Bs[ar * kLdsK + ac]);
+            ad[0] = ga0;
+            ad[1] = ga1;
+            bd[0] = gb0;
+            bd[1] = gb1;
+            if (MODE == 2) {
+                uint4 *adl = reinterpret_cast<uint4 *>(&Asl[ar * kLdsK + ac]);
+                uint4 *bdl = reinterpret_cast<uint4 *>(&Bsl[ar * kLdsK + ac]);
+                adl[0] = gal0;
+                adl[1] = gal1;
+                bdl[0] = gbl0;
+                bdl[1] = gbl1;
+            }
+        }
+        __syncthreads();
+        if (k0 + kBK < K) {
+            const int kn = k0 + kBK;
+            ga0 = reinterpret_cast<const uint4 *>(pa + kn)[0];
+            ga1 = reinterpret_cast<const uint4 *>(pa + kn)[1];
+            gb0 = reinterpret_cast<const uint4 *>(pb + kn)[0];
+            gb1 = reinterpret_cast<const uint4 *>(pb + kn)[1];
+            if (MODE == 2) {
+                gal0 = reinterpret_cast<const uint4 *>(pal + kn)[0];
+                gal1 = reinterpret_cast<const uint4 *>(pal + kn)[1];
+                gbl0 = reinterpret_cast<const uint4 *>(pbl + kn)[0];
+                gbl1 = reinterpret_cast<const uint4 *>(pbl + kn)[1];
+            }
+        }
+#pragma unroll
+        for (int ks = 0; ks < kBK; ks += 16) {
+            const int kk = ks + 8 * (lane >> 5);
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                const int ra = wm + 32 * i + (lane & 31);
+                const uint4 a_h = *reinterpret_cast<const uint4 *>(&As[ra * kLdsK + kk]);
+                uint4 a_l;
+                if (MODE == 2) a_l = *reinterpret_cast<const uint4 *>(&Asl[ra * kLdsK + kk]);
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    const int rb = wn + 32 * j + (lane & 31);
+                    const uint4 b_h = *reinterpret_cast<const uint4 *>(&Bs[rb * kLdsK + kk]);
+                    if (MODE == 1) {
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
+                            __builtin_bit_cast(f16x8, a_h), __builtin_bit_cast(f16x8, b_h), acc[i][j], 0, 0, 0);
+                    } else {
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                            __builtin_bit_cast(bf16x8, a_h), __builtin_bit_cast(bf16x8, b_h), acc[i][j], 0, 0, 0);
+                        if (MODE == 2) {
+                            const uint4 b_l = *reinterpret_cast<const uint4 *>(&Bsl[rb * kLdsK + kk]);
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                                __builtin_bit_cast(bf16x8, a_h), __builtin_bit_cast(bf16x8, b_l), acc[i][j], 0, 0, 0);
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                                __builtin_bit_cast(bf16x8, a_l), __builtin_bit_cast(bf16x8, b_h), acc[i][j], 0, 0, 0);
+                        }
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+    // epilogue: acc[i][j][r] -> row wm + 32i + 8(r/4) + 4(lane/32) + r%4, col wn + 32j + lane%32
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int row = m0 + wm + 32 * i + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                const int col = n0 + wn + 32 * j + (lane & 31);
+                C[(int64_t)row * ldc + col] = acc[i][j][r];
+            }
+}
 
 // rexp[i] = exponent of max_l |A[i][l] phi_l| (in FP64; 0 for a zero row), and the row
 // scale of the product: s_out[i] = s_in[i] + rexp[i].  One block per row.
@@ -391,10 +513,15 @@ static int32_t *Yscale(CircleState &C, int which_gamma, int k)  // dense path on
     return k == C.K - 1 ? C.szero : C.sb[k];
 }
 
+// Products of at least this many multiply-adds go to the library GEMM; smaller ones (the
+// Euler flows' N = 400, for instance) to the one fused launch of gemm_kernel.
+constexpr double kLibraryGemmMin = 2147483648.0;
+
 // One product of the recursions on the dense path: rexp and the row scales, the scaled
 // left operand A' = diag(2^-rexp) A diag(phi) in 16-bit form, then C = A' B^T as a plain
-// 16-bit GEMM with FP32 accumulation and output (rocBLAS); split BF16 accumulates
-// A'_hi B_hi^T + A'_hi B_lo^T + A'_lo B_hi^T in three calls.  Row-major C (M x N, ldc) is
+// 16-bit GEMM with FP32 accumulation and output (rocBLAS, or gemm_kernel for small
+// products); split BF16 accumulates A'_hi B_hi^T + A'_hi B_lo^T + A'_lo B_hi^T (three
+// library calls).  Row-major C (M x N, ldc) is
 // the column-major N x M matrix B A'^T, so the call multiplies B (transposed view of the
 // row-major N x K array) by A'.
 static hipError_t launch_gemm(const CircleState &C, const float *A, int lda, const double *phi,
@@ -415,6 +542,19 @@ static hipError_t launch_gemm(const CircleState &C, const float *A, int lda, con
                            C.Ah, C.Al);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    if ((double)Mp * Np * Kp < kLibraryGemmMin) {
+        const dim3 grid(Np / kBN, Mp / kBM);
+        if (C.mode == 1)
+            hipLaunchKernelGGL(gemm_kernel<1>, grid, dim3(256), 0, s, (const unsigned short *)C.Ah,
+                               (const unsigned short *)C.Al, lda, Bh, Bl, ldb, Cm, ldc, Kp);
+        else if (C.mode == 2)
+            hipLaunchKernelGGL(gemm_kernel<2>, grid, dim3(256), 0, s, (const unsigned short *)C.Ah,
+                               (const unsigned short *)C.Al, lda, Bh, Bl, ldb, Cm, ldc, Kp);
+        else
+            hipLaunchKernelGGL(gemm_kernel<0>, grid, dim3(256), 0, s, (const unsigned short *)C.Ah,
+                               (const unsigned short *)C.Al, lda, Bh, Bl, ldb, Cm, ldc, Kp);
+        return hipGetLastError();
+    }
     const rocblas_datatype t16 = C.mode == 1 ? rocblas_datatype_f16_r : rocblas_datatype_bf16_r;
     const float one = 1.0f, zero = 0.0f;
     auto gemm = [&](const unsigned short *Bx, const unsigned short *Ax, const float *beta) {
