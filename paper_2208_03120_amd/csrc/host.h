@@ -52,11 +52,19 @@ struct DevTmp {
 
 // ---------------------------------------------------------------------------------------
 // Device memory owned by a plan (through the caller's allocator or hipMalloc).
+// Device memory of a plan.  With the caller's allocator every request is one block of
+// it; otherwise requests are carved, 256-byte aligned, from slabs of hipMalloc memory that
+// grow geometrically (at least kSlabMin, at least a quarter of what is held already), so a plan
+// makes a handful of hipMalloc calls and, when destroyed, as many hipFree calls (each of
+// which waits for the device) rather than one per buffer.
 struct Arena {
+    static constexpr size_t kSlabMin = (size_t)4 << 20;
     mot_allocator alloc{};
     bool custom = false;
     std::vector<void *> blocks;
-    size_t bytes = 0;
+    size_t bytes = 0;             // device bytes held (blocks or slabs)
+    char *slab = nullptr;         // current slab and its free range
+    size_t slab_used = 0, slab_size = 0;
     int get(size_t nbytes, void **out);
     template <class T>
     int get_n(size_t count, T **out)

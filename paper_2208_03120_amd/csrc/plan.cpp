@@ -61,16 +61,28 @@ int Arena::get(size_t nbytes, void **out)
             alloc.free(p, alloc.ctx);
             return MOT_EINVAL;
         }
-    } else {
-        hipError_t e = hipMalloc(&p, nbytes);
+        blocks.push_back(p);
+        bytes += nbytes;
+        *out = p;
+        return MOT_OK;
+    }
+    nbytes = (nbytes + 255) / 256 * 256;
+    if (!slab || slab_size - slab_used < nbytes) {
+        const size_t size = std::max(nbytes, std::max(kSlabMin, bytes / 4));
+        void *q = nullptr;
+        hipError_t e = hipMalloc(&q, size);
         if (e != hipSuccess) {
             (void)hipGetLastError();
             return MOT_ENOMEM;
         }
+        blocks.push_back(q);
+        bytes += size;
+        slab = (char *)q;
+        slab_used = 0;
+        slab_size = size;
     }
-    blocks.push_back(p);
-    bytes += nbytes;
-    *out = p;
+    *out = slab + slab_used;
+    slab_used += nbytes;
     return MOT_OK;
 }
 
@@ -84,6 +96,8 @@ void Arena::release()
     }
     blocks.clear();
     bytes = 0;
+    slab = nullptr;
+    slab_used = slab_size = 0;
 }
 
 void Schedule::destroy()
