@@ -51,7 +51,6 @@ struct DevTmp {
 };
 
 // ---------------------------------------------------------------------------------------
-// Device memory owned by a plan (through the caller's allocator or hipMalloc).
 // Device memory of a plan.  With the caller's allocator every request is one block of
 // it; otherwise requests are carved, 256-byte aligned, from slabs of hipMalloc memory that
 // grow geometrically (at least kSlabMin, at least a quarter of what is held already), so a plan
@@ -226,6 +225,10 @@ struct mot_plan_s {
     void *circle = nullptr;
     // stand-alone product buffers (lazily sized)
     double *apply_in = nullptr, *apply_out = nullptr;
+    // device staging of the C-ABI transfers (max(sum n_k, 2 max n_k) doubles, allocated at
+    // first use): scalings in and out and the one-product call, without a hipMalloc and a
+    // device-synchronising hipFree per call
+    double *stage = nullptr;
     int64_t apply_cap = 0;
     float *apply_patches = nullptr;
     int apply_patch_cap = 0;

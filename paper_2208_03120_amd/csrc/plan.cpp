@@ -1491,16 +1491,24 @@ int mot_get_S_history(mot_plan P, double *S_out, int32_t count)
     return nout;
 }
 
+// The plan's staging buffer (see mot_plan_s::stage), allocated at first use.
+static int plan_stage(mot_plan P, double **out)
+{
+    if (!P->stage) {
+        int64_t nmax = 0;
+        for (int k = 0; k < P->K; ++k) nmax = std::max<int64_t>(nmax, P->n[k]);
+        MOT_TRY(P->arena.get_n((size_t)std::max<int64_t>(P->off[P->K], 2 * nmax), &P->stage));
+    }
+    *out = P->stage;
+    return MOT_OK;
+}
+
 static int scatter_out(mot_plan P, double *const *src_sorted, double *dst, int ptr_kind)
 {
     // binned order -> original order, concatenated
     const int64_t total = P->off[P->K];
-    DevTmp buf;
     double *tmp = dst;
-    if (ptr_kind != MOT_DEVICE) {
-        MOT_TRY(buf.alloc(total * sizeof(double)));
-        tmp = buf.as<double>();
-    }
+    if (ptr_kind != MOT_DEVICE) MOT_TRY(plan_stage(P, &tmp));
     for (int k = 0; k < P->K; ++k)
         MOT_HIP(launch_scatter_vec(src_sorted[k], P->marg[k].perm, P->n[k], tmp + P->off[k], P->stream));
     if (ptr_kind != MOT_DEVICE)
@@ -1521,9 +1529,8 @@ int mot_set_scalings(mot_plan P, const double *phi_in, int32_t ptr_kind)
 {
     if (!P || !phi_in) return MOT_EINVAL;
     const int64_t total = P->off[P->K];
-    DevTmp buf;
-    MOT_TRY(buf.alloc(total * sizeof(double)));
-    double *tmp = buf.as<double>();
+    double *tmp = nullptr;
+    MOT_TRY(plan_stage(P, &tmp));
     MOT_HIP(hipMemcpyAsync(tmp, phi_in, total * sizeof(double),
                            ptr_kind == MOT_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
                            P->stream));
@@ -1589,9 +1596,8 @@ int mot_apply_kernel(mot_plan P, int32_t t, int32_t s, const double *v, double *
         P->apply_cap = cap;
     }
     // v (original order) -> binned order of s
-    DevTmp buf;
-    MOT_TRY(buf.alloc((P->n[s] + P->n[t]) * sizeof(double)));
-    double *tmp = buf.as<double>();
+    double *tmp = nullptr;
+    MOT_TRY(plan_stage(P, &tmp));  // n[s] + n[t] <= 2 max n_k doubles
     MOT_HIP(hipMemcpyAsync(tmp, v, P->n[s] * sizeof(double),
                            ptr_kind == MOT_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
                            P->stream));
