@@ -119,15 +119,25 @@ __global__ __launch_bounds__(512) void bitonic_local_kernel(uint64_t *keys, int6
     for (int t = threadIdx.x; t < 1024; t += blockDim.x) keys[base + t] = sk[t];
 }
 
+// perm[i] = index of the i-th sorted key (i < npts); tile_off[t] = first sorted position
+// whose tile is >= t (t <= ntiles), by binary search over the sorted keys, so empty
+// stretches of tiles cost nothing extra.
 __global__ void keys_to_perm_kernel(int64_t npts, int64_t ntiles, const uint64_t *__restrict__ keys,
                                     int shift, int32_t *__restrict__ perm, int32_t *__restrict__ tile_off)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i > npts) return;
-    int64_t t_prev = i == 0 ? -1 : (int64_t)(keys[i - 1] >> shift);
-    int64_t t_cur = i == npts ? ntiles : (int64_t)(keys[i] >> shift);
     if (i < npts) perm[i] = (int32_t)(keys[i] & 0xffffffffull);
-    for (int64_t t = t_prev + 1; t <= t_cur; ++t) tile_off[t] = (int32_t)i;
+    if (i <= ntiles) {
+        int64_t lo = 0, hi = npts;  // first position with tile >= i in [lo, hi]
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if ((int64_t)(keys[mid] >> shift) < i)
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+        tile_off[i] = (int32_t)lo;
+    }
 }
 
 size_t stable_tile_sort_scratch(int64_t npts, int64_t /*ntiles*/)
@@ -160,7 +170,8 @@ hipError_t stable_tile_sort(int64_t npts, const int32_t *tile, int64_t ntiles, i
                                k, j);
         hipLaunchKernelGGL(bitonic_local_kernel, dim3(lblocks), dim3(512), 0, st, keys, npad, k, 0);
     }
-    int pblocks = (int)((npts + 1 + 255) / 256);
+    const int64_t nthr = std::max<int64_t>(npts, ntiles + 1);
+    int pblocks = (int)((nthr + 255) / 256);
     hipLaunchKernelGGL(keys_to_perm_kernel, dim3(pblocks), dim3(256), 0, st, npts, ntiles, keys,
                        cell != nullptr ? 32 + kSubBits : 32, perm, tile_off);
     return hipGetLastError();
