@@ -35,19 +35,19 @@ PEAK_FP32_TFLOPS = 157.3  # dense FP32 MFMA
 # points).  Valid only for the kernel source it was measured on (SHA-256 of its file).
 COPY_MIB = 256
 TRAFFIC = {
-    "spread": {"bytes_per_launch": 231910438, "source": "k_nfft.hip",
-               "sha256": "48ac8a42222f48a3f26efe18f287341582c166c5417d40eae4fb22af96445a8c"},
-    "spread_g3": {"bytes_per_launch": 110922436, "source": "k_nfft.hip",
-                  "sha256": "48ac8a42222f48a3f26efe18f287341582c166c5417d40eae4fb22af96445a8c"},
-    "fold": {"bytes_per_launch": 79214317, "source": "k_nfft.hip",
-             "sha256": "48ac8a42222f48a3f26efe18f287341582c166c5417d40eae4fb22af96445a8c"},
-    "interp": {"bytes_per_launch": 214426965, "source": "k_nfft.hip",
-               "sha256": "48ac8a42222f48a3f26efe18f287341582c166c5417d40eae4fb22af96445a8c"},
-    "fft6": {"bytes_per_launch": 10832367, "source": "k_fft.hip",
+    "spread": {"bytes_per_launch": 231931452, "source": "k_nfft.hip",
+               "sha256": "90eac38017085dd7447509cd1cd96781db142b8b3ac5132e8b7084febd01ee9e"},
+    "spread_g3": {"bytes_per_launch": 110931912, "source": "k_nfft.hip",
+                  "sha256": "90eac38017085dd7447509cd1cd96781db142b8b3ac5132e8b7084febd01ee9e"},
+    "fold": {"bytes_per_launch": 79214209, "source": "k_nfft.hip",
+             "sha256": "90eac38017085dd7447509cd1cd96781db142b8b3ac5132e8b7084febd01ee9e"},
+    "interp": {"bytes_per_launch": 214089317, "source": "k_nfft.hip",
+               "sha256": "90eac38017085dd7447509cd1cd96781db142b8b3ac5132e8b7084febd01ee9e"},
+    "fft6": {"bytes_per_launch": 10832426, "source": "k_fft.hip",
              "sha256": "0fdb613e3aa356b695e37243d8a0803c82e512974bd0f3a4f21196a7c2e62e6f"},
-    "fft5": {"bytes_per_launch": 28822691, "source": "k_fft.hip",
+    "fft5": {"bytes_per_launch": 28823967, "source": "k_fft.hip",
              "sha256": "0fdb613e3aa356b695e37243d8a0803c82e512974bd0f3a4f21196a7c2e62e6f"},
-    "fft7": {"bytes_per_launch": 10842988, "source": "k_fft.hip",
+    "fft7": {"bytes_per_launch": 10842977, "source": "k_fft.hip",
              "sha256": "0fdb613e3aa356b695e37243d8a0803c82e512974bd0f3a4f21196a7c2e62e6f"},
 }
 
