@@ -439,6 +439,14 @@ struct SpreadStage3 {
     }
 };
 
+// x from another lane of the same row of 16 lanes, by a DPP permutation (CTRL: 0x140 row
+// mirror, 0x141 row half mirror, quad_perm patterns below 0x100).
+template <int CTRL>
+__device__ __forceinline__ float dpp_f32(float x)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), CTRL, 0xF, 0xF, false));
+}
+
 template <int G>
 __global__ __launch_bounds__(64 * kSpreadWaves, G == 1 ? 6 : (G == 2 ? 5 : 4)) void spread3_kernel(const ProdJob *__restrict__ jobs,
                                                                                  const int4 *__restrict__ items,
@@ -811,23 +819,25 @@ __global__ __launch_bounds__(64 * kInterpWaves, 6) void interp3_kernel(const Pro
 #pragma unroll
                 for (int r = 0; r < 4; ++r)
                     z[r] = (acc0[r] + acc1[r]) * rl[(16 * g + 4 * lk + r) * (3 * kPatch) + li];
-                // sum over the 16 lanes of the lane group: halving over lane masks 8 and 4
-                // (lane l keeps r = l / 4), then full sums over masks 2 and 1
+                // sum over the 16 lanes of the lane group (a DPP row) by lane permutations:
+                // halving with the partner 15 - l (row mirror; lane l keeps r by bit 3), then
+                // with 7 - l within its half (half mirror; by bit 2), so lane l keeps
+                // r = l / 4; then full sums over the quad (partners l ^ 2, l ^ 1)
                 {
                     const bool hi = (li & 8) != 0;
 #pragma unroll
                     for (int q = 0; q < 2; ++q) {
                         const float mine = hi ? z[q + 2] : z[q], other = hi ? z[q] : z[q + 2];
-                        z[q] = mine + __shfl_xor(other, 8);
+                        z[q] = mine + dpp_f32<0x140>(other);
                     }
                 }
                 {
                     const bool hi = (li & 4) != 0;
                     const float mine = hi ? z[1] : z[0], other = hi ? z[0] : z[1];
-                    z[0] = mine + __shfl_xor(other, 4);
+                    z[0] = mine + dpp_f32<0x141>(other);
                 }
-                z[0] += __shfl_xor(z[0], 2);
-                z[0] += __shfl_xor(z[0], 1);
+                z[0] += dpp_f32<0x4E>(z[0]);
+                z[0] += dpp_f32<0xB1>(z[0]);
                 if ((li & 3) == 0) zb[k & 1][wave][16 * g + 4 * lk + (li >> 2)] = z[0];
             }
             if (more) stg.store(smem + ((k + 1) & 1) * St::kBytes, 0);
