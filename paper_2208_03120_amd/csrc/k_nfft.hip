@@ -440,11 +440,12 @@ struct SpreadStage3 {
 };
 
 // x from another lane of the same row of 16 lanes, by a DPP permutation (CTRL: 0x140 row
-// mirror, 0x141 row half mirror, quad_perm patterns below 0x100).
+// mirror, 0x141 row half mirror, quad_perm patterns below 0x100).  Every lane's source lies
+// in its row; the zero old value lets the compiler fold the move into the add that uses it.
 template <int CTRL>
 __device__ __forceinline__ float dpp_f32(float x)
 {
-    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), CTRL, 0xF, 0xF, false));
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), CTRL, 0xF, 0xF, true));
 }
 
 template <int G>
@@ -747,8 +748,9 @@ __global__ __launch_bounds__(64 * kInterpWaves, 4) void interp_kernel(const Prod
 }
 
 // 3-D interpolation with the 16 b values of the contraction split over the block's waves.
-// Wave w holds B only for b = 4 w .. 4 w + 3 (16 registers rather than 64) and takes all
-// four 16-point groups of a stage: for group g and lane group lk its accumulators give
+// Wave w holds B only for b = w, w + 4, w + 8, w + 12 (16 registers rather than 64; a
+// twelve-wide window covers three of each wave's four b, so the waves skip alike) and takes
+// all four 16-point groups of a stage: for group g and lane group lk its accumulators give
 // Z_w[p = 16 g + 4 lk + r][a = l % 16], the part of Z from its b values.  The lane
 // products w_0,p[a] Z_w[p][a] of the four points 16 g + 4 lk + r of a group are summed
 // over the 16 lanes of the lane group, the four waves' partial sums of a point are added in
@@ -775,16 +777,16 @@ __global__ __launch_bounds__(64 * kInterpWaves, 6) void interp3_kernel(const Pro
                 rem /= J.ntile[c];
             }
         }
-        // B[k = (b, c')][a = l % 16] = G[a][b][c'] for b = 4 wave + bb, c' = 4 lk + s
+        // B[k = (b, c')][a = l % 16] = G[a][b][c'] for b = wave + 4 bb, c' = 4 lk + s
         const MOT_GLOBAL float *grid = gp(J.grid);
         float Bv[16];
         {
             const int64_t base =
-                ((int64_t)(tc[0] * T + li) * J.L[1] + tc[1] * T + 4 * wave) * J.L[2] + tc[2] * T + 4 * lk;
+                ((int64_t)(tc[0] * T + li) * J.L[1] + tc[1] * T + wave) * J.L[2] + tc[2] * T + 4 * lk;
 #pragma unroll
             for (int bb = 0; bb < 4; ++bb)
 #pragma unroll
-                for (int s = 0; s < 4; ++s) Bv[4 * bb + s] = grid[base + (int64_t)bb * J.L[2] + s];
+                for (int s = 0; s < 4; ++s) Bv[4 * bb + s] = grid[base + (int64_t)(4 * bb) * J.L[2] + s];
         }
         const int e = source_exponent(J);
         const int64_t p0 = gp(J.tgt_chunk_start)[itm.y], p1 = gp(J.tgt_chunk_start)[itm.y + 1];
@@ -801,24 +803,25 @@ __global__ __launch_bounds__(64 * kInterpWaves, 6) void interp3_kernel(const Pro
 #pragma unroll 1
             for (int g = 0; g < 4; ++g) {
                 const float *row = rl + (16 * g + li) * (3 * kPatch);  // point 16 g + l % 16
-                const f32x4 wy = reinterpret_cast<const f32x4 *>(row + kPatch)[wave];
+                const f32x4 wy = f32x4{row[kPatch + wave], row[kPatch + wave + 4], row[kPatch + wave + 8],
+                                       row[kPatch + wave + 12]};
                 const f32x4 wz = reinterpret_cast<const f32x4 *>(row + 2 * kPatch)[lk];
-                f32x4 acc0 = f32x4{0.0f, 0.0f, 0.0f, 0.0f}, acc1 = acc0;
+                f32x4 acc = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
                 for (int bb = 0; bb < 4; ++bb) {
                     // A is zero when b is outside the window of all 16 points: the four
                     // products would add exact zeros
                     if (!__any(wy[bb] != 0.0f)) continue;
-                    acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(wy[bb] * wz[0], Bv[4 * bb], acc0, 0, 0, 0);
-                    acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(wy[bb] * wz[1], Bv[4 * bb + 1], acc1, 0, 0, 0);
-                    acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(wy[bb] * wz[2], Bv[4 * bb + 2], acc0, 0, 0, 0);
-                    acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(wy[bb] * wz[3], Bv[4 * bb + 3], acc1, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(wy[bb] * wz[0], Bv[4 * bb], acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(wy[bb] * wz[1], Bv[4 * bb + 1], acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(wy[bb] * wz[2], Bv[4 * bb + 2], acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(wy[bb] * wz[3], Bv[4 * bb + 3], acc, 0, 0, 0);
                 }
                 // z[r]: this lane's product for point 16 g + 4 lk + r
                 float z[4];
 #pragma unroll
                 for (int r = 0; r < 4; ++r)
-                    z[r] = (acc0[r] + acc1[r]) * rl[(16 * g + 4 * lk + r) * (3 * kPatch) + li];
+                    z[r] = acc[r] * rl[(16 * g + 4 * lk + r) * (3 * kPatch) + li];
                 // sum over the 16 lanes of the lane group (a DPP row) by lane permutations:
                 // halving with the partner 15 - l (row mirror; lane l keeps r by bit 3), then
                 // with 7 - l within its half (half mirror; by bit 2), so lane l keeps
