@@ -35,19 +35,19 @@ PEAK_FP32_TFLOPS = 157.3  # dense FP32 MFMA
 # points).  Valid only for the kernel source it was measured on (SHA-256 of its file).
 COPY_MIB = 256
 TRAFFIC = {
-    "spread": {"bytes_per_launch": 231918185, "source": "k_nfft.hip",
-               "sha256": "ab9bb4fe6f19194d03d640cfc06eb46c70f24904419bf325a3148029d776cda5"},
-    "spread_g3": {"bytes_per_launch": 110933403, "source": "k_nfft.hip",
-                  "sha256": "ab9bb4fe6f19194d03d640cfc06eb46c70f24904419bf325a3148029d776cda5"},
-    "fold": {"bytes_per_launch": 79214017, "source": "k_nfft.hip",
-             "sha256": "ab9bb4fe6f19194d03d640cfc06eb46c70f24904419bf325a3148029d776cda5"},
-    "interp": {"bytes_per_launch": 202271963, "source": "k_nfft.hip",
-               "sha256": "ab9bb4fe6f19194d03d640cfc06eb46c70f24904419bf325a3148029d776cda5"},
-    "fft6": {"bytes_per_launch": 10832416, "source": "k_fft.hip",
+    "spread": {"bytes_per_launch": 231934872, "source": "k_nfft.hip",
+               "sha256": "289d42b4630e8d1caee4f5983fd19678c15a00aa68318c34595c4e449eb59302"},
+    "spread_g3": {"bytes_per_launch": 110932424, "source": "k_nfft.hip",
+                  "sha256": "289d42b4630e8d1caee4f5983fd19678c15a00aa68318c34595c4e449eb59302"},
+    "fold": {"bytes_per_launch": 79214217, "source": "k_nfft.hip",
+             "sha256": "289d42b4630e8d1caee4f5983fd19678c15a00aa68318c34595c4e449eb59302"},
+    "interp": {"bytes_per_launch": 200356962, "source": "k_nfft.hip",
+               "sha256": "289d42b4630e8d1caee4f5983fd19678c15a00aa68318c34595c4e449eb59302"},
+    "fft6": {"bytes_per_launch": 10832426, "source": "k_fft.hip",
              "sha256": "0fdb613e3aa356b695e37243d8a0803c82e512974bd0f3a4f21196a7c2e62e6f"},
-    "fft5": {"bytes_per_launch": 28824429, "source": "k_fft.hip",
+    "fft5": {"bytes_per_launch": 28823967, "source": "k_fft.hip",
              "sha256": "0fdb613e3aa356b695e37243d8a0803c82e512974bd0f3a4f21196a7c2e62e6f"},
-    "fft7": {"bytes_per_launch": 10842957, "source": "k_fft.hip",
+    "fft7": {"bytes_per_launch": 10842977, "source": "k_fft.hip",
              "sha256": "0fdb613e3aa356b695e37243d8a0803c82e512974bd0f3a4f21196a7c2e62e6f"},
 }
 
