@@ -439,15 +439,6 @@ struct SpreadStage3 {
     }
 };
 
-// x from another lane of the same row of 16 lanes, by a DPP permutation (CTRL: 0x140 row
-// mirror, 0x141 row half mirror, quad_perm patterns below 0x100).  Every lane's source lies
-// in its row; the zero old value lets the compiler fold the move into the add that uses it.
-template <int CTRL>
-__device__ __forceinline__ float dpp_f32(float x)
-{
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), CTRL, 0xF, 0xF, true));
-}
-
 template <int G>
 __global__ __launch_bounds__(64 * kSpreadWaves, G == 1 ? 6 : (G == 2 ? 5 : 4)) void spread3_kernel(const ProdJob *__restrict__ jobs,
                                                                                  const int4 *__restrict__ items,
@@ -750,11 +741,13 @@ __global__ __launch_bounds__(64 * kInterpWaves, 4) void interp_kernel(const Prod
 // 3-D interpolation with the 16 b values of the contraction split over the block's waves.
 // Wave w holds B only for b = w, w + 4, w + 8, w + 12 (16 registers rather than 64; a
 // twelve-wide window covers three of each wave's four b, so the waves skip alike) and takes
-// all four 16-point groups of a stage: for group g and lane group lk its accumulators give
-// Z_w[p = 16 g + 4 lk + r][a = l % 16], the part of Z from its b values.  The lane
-// products w_0,p[a] Z_w[p][a] of the four points 16 g + 4 lk + r of a group are summed
-// over the 16 lanes of the lane group, the four waves' partial sums of a point are added in
-// wave order through LDS after the stage's barrier, and wave 0 stores out = 2^e beta.
+// all four 16-point groups of a stage.  The grid values are the MFMA's A operand and the
+// window products its B operand, so for group g lane l's accumulators give
+// Z_w[a = 4 (l / 16) + r][p = 16 g + l % 16], the part of Z from the wave's b values, with
+// the point along the lanes.  Each lane weights its four a by the point's w_0,p[a] and the
+// four lane groups are added by two lane exchanges; the four waves' partial sums of a
+// point are added in wave order through LDS after the stage's barrier, and wave 0 stores
+// out = 2^e beta.
 __global__ __launch_bounds__(64 * kInterpWaves, 6) void interp3_kernel(const ProdJob *__restrict__ jobs,
                                                                    const int2 *__restrict__ items,
                                                                    int n_items)
@@ -777,7 +770,7 @@ __global__ __launch_bounds__(64 * kInterpWaves, 6) void interp3_kernel(const Pro
                 rem /= J.ntile[c];
             }
         }
-        // B[k = (b, c')][a = l % 16] = G[a][b][c'] for b = wave + 4 bb, c' = 4 lk + s
+        // A[a = l % 16][k = (b, c')] = G[a][b][c'] for b = wave + 4 bb, c' = 4 lk + s
         const MOT_GLOBAL float *grid = gp(J.grid);
         float Bv[16];
         {
@@ -809,39 +802,21 @@ __global__ __launch_bounds__(64 * kInterpWaves, 6) void interp3_kernel(const Pro
                 f32x4 acc = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
                 for (int bb = 0; bb < 4; ++bb) {
-                    // A is zero when b is outside the window of all 16 points: the four
+                    // B is zero when b is outside the window of all 16 points: the four
                     // products would add exact zeros
                     if (!__any(wy[bb] != 0.0f)) continue;
-                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(wy[bb] * wz[0], Bv[4 * bb], acc, 0, 0, 0);
-                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(wy[bb] * wz[1], Bv[4 * bb + 1], acc, 0, 0, 0);
-                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(wy[bb] * wz[2], Bv[4 * bb + 2], acc, 0, 0, 0);
-                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(wy[bb] * wz[3], Bv[4 * bb + 3], acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(Bv[4 * bb], wy[bb] * wz[0], acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(Bv[4 * bb + 1], wy[bb] * wz[1], acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(Bv[4 * bb + 2], wy[bb] * wz[2], acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(Bv[4 * bb + 3], wy[bb] * wz[3], acc, 0, 0, 0);
                 }
-                // z[r]: this lane's product for point 16 g + 4 lk + r
-                float z[4];
-#pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    z[r] = acc[r] * rl[(16 * g + 4 * lk + r) * (3 * kPatch) + li];
-                // sum over the 16 lanes of the lane group (a DPP row) by lane permutations:
-                // halving with the partner 15 - l (row mirror; lane l keeps r by bit 3), then
-                // with 7 - l within its half (half mirror; by bit 2), so lane l keeps
-                // r = l / 4; then full sums over the quad (partners l ^ 2, l ^ 1)
-                {
-                    const bool hi = (li & 8) != 0;
-#pragma unroll
-                    for (int q = 0; q < 2; ++q) {
-                        const float mine = hi ? z[q + 2] : z[q], other = hi ? z[q] : z[q + 2];
-                        z[q] = mine + dpp_f32<0x140>(other);
-                    }
-                }
-                {
-                    const bool hi = (li & 4) != 0;
-                    const float mine = hi ? z[1] : z[0], other = hi ? z[0] : z[1];
-                    z[0] = mine + dpp_f32<0x141>(other);
-                }
-                z[0] += dpp_f32<0x4E>(z[0]);
-                z[0] += dpp_f32<0xB1>(z[0]);
-                if ((li & 3) == 0) zb[k & 1][wave][16 * g + 4 * lk + (li >> 2)] = z[0];
+                // acc[r] = Z_w[a = 4 lk + r][p = 16 g + l % 16]: weight by the point's own
+                // w_0,p[4 lk .. 4 lk + 3], then add the four lane groups (lanes l ^ 16, l ^ 32)
+                const f32x4 wx = reinterpret_cast<const f32x4 *>(row)[lk];
+                float z = (acc[0] * wx[0] + acc[1] * wx[1]) + (acc[2] * wx[2] + acc[3] * wx[3]);
+                z += __shfl_xor(z, 16);
+                z += __shfl_xor(z, 32);
+                if (lk == 0) zb[k & 1][wave][16 * g + li] = z;
             }
             if (more) stg.store(smem + ((k + 1) & 1) * St::kBytes, 0);
             __syncthreads();
