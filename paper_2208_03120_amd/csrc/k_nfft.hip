@@ -640,14 +640,15 @@ __global__ __launch_bounds__(kFoldCellsPerItem) void fold_kernel(const ProdJob *
 // Interpolation (a6) as the transposed contraction on FP32 MFMA.
 //
 // For 16 target points of one tile and the 16^d patch G of the result grid over the
-// tile, Z[p][a] = sum_{(b,c')} Y[p][(b,c')] G[a][(b,c')] with Y[p][(b,c')] =
-// w_1,p[b] w_2,p[c'], then beta_p = sum_a w_0,p[a] Z[p][a].  Step s of the 64-step MFMA
+// tile, Z[a][p] = sum_{(b,c')} G[a][(b,c')] Y[(b,c')][p] with Y[(b,c')][p] =
+// w_1,p[b] w_2,p[c'], then beta_p = sum_a w_0,p[a] Z[a][p].  Step s of the 64-step MFMA
 // chain covers b = s / 4 and, for lane group g = l / 16, c' = 4 g + s % 4: lane l holds
-// A[p = l % 16][k] = w_1,p[b] w_2,p[c'] and B[k][a = l % 16] = G[a][b][c'].  The B values
-// are the same for every point of the tile, so they stay in registers for the whole
-// chunk.  Accumulator r holds Z[p = 4 g + r][a = l % 16]; the last contraction over a is
-// a 16-lane reduction.  In 2-D the chain has 4 steps (k = b = 4 g + s); in 1-D one lane
-// takes one point.  out = 2^e beta, e the exponent the source was scaled by.
+// A[a = l % 16][k] = G[a][b][c'] and B[k][p = l % 16] = w_1,p[b] w_2,p[c'].  The grid
+// values are the same for every point of the tile, so they stay in registers for the whole
+// chunk.  Accumulator r holds Z[a = 4 g + r][p = l % 16], so each lane owns one point: the
+// last contraction over a takes the lane's four a and then adds the four lane groups.  In
+// 2-D the chain has 4 steps (k = b = 4 g + s); in 1-D one lane takes one point.
+// out = 2^e beta, e the exponent the source was scaled by.
 //
 // A block of kInterpWaves wavefronts takes one chunk.  In 2-D wave w takes the 16-point
 // groups w, w + kInterpWaves, ... (one per stage), in 1-D 64-point groups; 3-D
@@ -713,24 +714,21 @@ __global__ __launch_bounds__(64 * kInterpWaves, 4) void interp_kernel(const Prod
                 // this wave's group: stage points 16 wave .. 16 wave + 15
                 const float *grow = rl + (16 * wave) * (D * kPatch);
                 const float *row = grow + li * (D * kPatch);  // point l % 16
-                f32x4 acc0 = f32x4{0.0f, 0.0f, 0.0f, 0.0f}, acc1 = acc0;
+                // grid values as the A operand, window values as B: acc[r] = Z[a = 4 lk + r][p]
+                // for the lane's point p = l % 16
+                f32x4 acc = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
                 const f32x4 wb = reinterpret_cast<const f32x4 *>(row + kPatch)[lk];
-                acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(wb[0], Bv[0], acc0, 0, 0, 0);
-                acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(wb[1], Bv[1], acc1, 0, 0, 0);
-                acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(wb[2], Bv[2], acc0, 0, 0, 0);
-                acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(wb[3], Bv[3], acc1, 0, 0, 0);
-                // beta_p = sum_a w_0,p[a] Z[p][a] over the 16 lanes of a lane group
-                const int64_t pb = p0 + (int64_t)k * kStage + 16 * wave;
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    float z = (acc0[r] + acc1[r]) * grow[(4 * lk + r) * (D * kPatch) + li];
-                    z += __shfl_xor(z, 1);
-                    z += __shfl_xor(z, 2);
-                    z += __shfl_xor(z, 4);
-                    z += __shfl_xor(z, 8);
-                    const int64_t p = pb + 4 * lk + r;
-                    if (li == r && p < p1) out[p] = ldexp((double)z, e);
-                }
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(Bv[0], wb[0], acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(Bv[1], wb[1], acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(Bv[2], wb[2], acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(Bv[3], wb[3], acc, 0, 0, 0);
+                // beta_p = sum_a w_0,p[a] Z[a][p]: the lane's four a, then the four lane groups
+                const f32x4 wx = reinterpret_cast<const f32x4 *>(row)[lk];
+                float z = (acc[0] * wx[0] + acc[1] * wx[1]) + (acc[2] * wx[2] + acc[3] * wx[3]);
+                z += __shfl_xor(z, 16);
+                z += __shfl_xor(z, 32);
+                const int64_t p = p0 + (int64_t)k * kStage + 16 * wave + li;
+                if (lk == 0 && p < p1) out[p] = ldexp((double)z, e);
                 if (more) stg.store(smem + ((k + 1) & 1) * St::kBytes, 0);
                 __syncthreads();
             }
