@@ -199,7 +199,9 @@ hipError_t launch_interp(int d, const ProdJob *jobs, const int2 *items, int n_it
 // forward + multiply + inverse, 3 = inverse C2C, 4 = C2R (with multiply when d == 1);
 // 3-D slab chain: 6 = forward slab (R2C + C2C), 5 = fused pass on g0-major input,
 // 7 = inverse slab (C2C + C2R).  Items: int4 (job, a2, a1, 0); slab items (job, g0, 0, 0).
-constexpr int kSlabThreads = 512;
+// Twelve wavefronts per slab: a 128-point line takes one wavefront, so a slab of 46 box
+// lines (23 complex) is two rounds and its 33 half-spectrum lines (M = 32) three.
+constexpr int kSlabThreads = 768;
 constexpr int kSlabLds = 48 * 1024;  // bytes of LDS for a slab's half spectrum L1 x (M+1)
 hipError_t launch_fft_pass(int kind, int n, const ProdJob *jobs, const int4 *items, int n_items,
                            const float2 *twiddle, hipStream_t s);
