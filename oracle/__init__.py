@@ -95,6 +95,9 @@ def _load():
         lib.orc_bin_points.argtypes = [ctypes.c_int, ctypes.c_long, dp, dp, dp, ctypes.c_int,
                                        ctypes.c_int, ip, ip, ip, ip]
         lib.orc_bin_points.restype = ctypes.c_int
+        lib.orc_bin_points_sub.argtypes = [ctypes.c_int, ctypes.c_long, dp, dp, dp, ctypes.c_int,
+                                           ctypes.c_int, ctypes.c_int, ip, ip, ip, ip]
+        lib.orc_bin_points_sub.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -288,8 +291,11 @@ def sinkhorn_function(weights, phi, total_mass, eta):
     return eta * (s - total_mass)
 
 
-def bin_points(x, s, o, n, T):
-    """Point binning: cells, tile ids, stable tile-sorted permutation and tile offsets."""
+def bin_points(x, s, o, n, T, sub_dim=-1):
+    """Point binning: cells, tile ids, stable tile-sorted permutation and tile offsets.
+
+    ``sub_dim`` >= 0 orders the points of a tile by their tile-relative cell in that
+    dimension (cell mod T), ties by index: the sort key (tile, cell mod T, index)."""
     lib = _load()
     x = np.ascontiguousarray(x, dtype=np.float64)
     npts, d = x.shape
@@ -300,7 +306,7 @@ def bin_points(x, s, o, n, T):
     tile = np.empty(npts, dtype=np.int32)
     perm = np.empty(npts, dtype=np.int32)
     tile_off = np.empty(tpd ** d + 1, dtype=np.int32)
-    rc = lib.orc_bin_points(d, npts, _d(x), _d(s), _d(o), int(n), int(T), _i(cell), _i(tile),
-                            _i(perm), _i(tile_off))
+    rc = lib.orc_bin_points_sub(d, npts, _d(x), _d(s), _d(o), int(n), int(T), int(sub_dim),
+                                _i(cell), _i(tile), _i(perm), _i(tile_off))
     assert rc == OK, rc
     return cell, tile, perm, tile_off

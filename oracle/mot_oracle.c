@@ -653,11 +653,17 @@ int orc_tree_pair_marginal(int K, int d, const long *off, const double *pts, con
  *   tile   = row-major linearisation with coordinate 0 slowest
  * perm lists point indices sorted by tile, ties in ascending original index
  * (a stable counting sort); tile_off[t] is the first sorted position of tile
- * t, tile_off[ntiles] = n_pts.  cell is n_pts x d in original order. */
-int orc_bin_points(int d, long n_pts, const double *x, const double *s, const double *o,
-                   int n, int T, int *cell, int *tile, int *perm, int *tile_off)
+ * t, tile_off[ntiles] = n_pts.  cell is n_pts x d in original order.
+ *
+ * With 0 <= sub_dim < d the points of one tile are further ordered by their
+ * tile-relative cell in dimension sub_dim, r = cell_{sub_dim} mod T, ties again
+ * in ascending original index: the sort key is (tile, r, index).  This is the
+ * order the 3-D fast-summation path keeps its points in; tile_off is unchanged
+ * (a tile's points stay contiguous).  sub_dim < 0 gives the plain tile order. */
+int orc_bin_points_sub(int d, long n_pts, const double *x, const double *s, const double *o,
+                       int n, int T, int sub_dim, int *cell, int *tile, int *perm, int *tile_off)
 {
-    if (d < 1 || d > 3 || n < 1 || T < 1) return ORC_EINVAL;
+    if (d < 1 || d > 3 || n < 1 || T < 1 || sub_dim >= d) return ORC_EINVAL;
     int tpd = (n + T - 1) / T;
     long ntiles = 1;
     for (int c = 0; c < d; ++c) ntiles *= tpd;
@@ -683,10 +689,26 @@ int orc_bin_points(int d, long n_pts, const double *x, const double *s, const do
     for (long t = 0; t <= ntiles; ++t) tile_off[t] = 0;
     for (long i = 0; i < n_pts; ++i) tile_off[tile[i] + 1] += 1;
     for (long t = 0; t < ntiles; ++t) tile_off[t + 1] += tile_off[t];
-    int *cursor = (int *)malloc((size_t)ntiles * sizeof(int));
-    if (!cursor) return ORC_ENOMEM;
-    for (long t = 0; t < ntiles; ++t) cursor[t] = tile_off[t];
-    for (long i = 0; i < n_pts; ++i) perm[cursor[tile[i]]++] = (int)i;
-    free(cursor);
+    /* stable counting sort by the bucket (tile, r): ntiles * R buckets, R = T with a
+     * sub-key and 1 without; points enter their bucket in ascending index order */
+    const long R = sub_dim >= 0 ? T : 1;
+    long *bucket_off = (long *)calloc((size_t)(ntiles * R + 1), sizeof(long));
+    if (!bucket_off) return ORC_ENOMEM;
+    for (long i = 0; i < n_pts; ++i) {
+        long b = (long)tile[i] * R + (sub_dim >= 0 ? cell[i * d + sub_dim] % T : 0);
+        bucket_off[b + 1] += 1;
+    }
+    for (long b = 0; b < ntiles * R; ++b) bucket_off[b + 1] += bucket_off[b];
+    for (long i = 0; i < n_pts; ++i) {
+        long b = (long)tile[i] * R + (sub_dim >= 0 ? cell[i * d + sub_dim] % T : 0);
+        perm[bucket_off[b]++] = (int)i;
+    }
+    free(bucket_off);
     return ORC_OK;
+}
+
+int orc_bin_points(int d, long n_pts, const double *x, const double *s, const double *o,
+                   int n, int T, int *cell, int *tile, int *perm, int *tile_off)
+{
+    return orc_bin_points_sub(d, n_pts, x, s, o, n, T, -1, cell, tile, perm, tile_off);
 }

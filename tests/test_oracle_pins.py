@@ -380,6 +380,86 @@ def test_binning_boundaries_and_clamping():
     assert toff.tolist() == [0, 2, 7]
 
 
+@pytest.mark.parametrize("d,n,T,sub_dim", [(3, 128, 5, 1), (3, 64, 8, 0), (3, 32, 3, 2), (2, 64, 7, 1),
+                                            (1, 16, 4, 0)])
+def test_binning_sub_keyed_order_is_a_lexicographic_sort(d, n, T, sub_dim):
+    """With a sub-key the points of a tile are ordered by their tile-relative cell in one
+    dimension, ties by index: perm equals numpy's lexicographic sort of the keys
+    (tile, cell mod T, index), a library sort independent of the oracle's counting sort;
+    tile offsets and cells are those of the plain order."""
+    r = rng(42 + d + T)
+    x = W.uniform_points(r, 4000, d)
+    x[:7] = np.round(x[:7] * 64) / 64  # points on cell boundaries
+    s = np.full(d, n / 2.0)
+    o = n / 2.0 + r.uniform(-0.5, 0.5, size=d)
+    cell, tile, perm, toff = oracle.bin_points(x, s, o, n, T, sub_dim=sub_dim)
+    pcell, ptile, pperm, ptoff = oracle.bin_points(x, s, o, n, T)
+    np.testing.assert_array_equal(cell, pcell)
+    np.testing.assert_array_equal(tile, ptile)
+    np.testing.assert_array_equal(toff, ptoff)
+    want = np.lexsort((np.arange(4000), cell[:, sub_dim] % T, tile))
+    np.testing.assert_array_equal(perm, want)
+    # the plain order is the same lexicographic sort without the sub-key
+    np.testing.assert_array_equal(pperm, np.lexsort((np.arange(4000), tile)))
+    # a tile's points are the same set in both orders
+    for t in np.unique(tile)[::7]:
+        assert sorted(perm[toff[t]:toff[t + 1]]) == sorted(pperm[toff[t]:toff[t + 1]])
+
+
+def _first_delta_stop(S, delta):
+    """1-based sweep count at which |S^(r) - S^(r-1)| < delta first holds (r >= 1)."""
+    for r in range(1, len(S)):
+        if abs(S[r] - S[r - 1]) < delta:
+            return r + 1
+    return None
+
+
+def _delta_between(S, r_stop):
+    """A delta strictly between |dS| at sweep r_stop (to stop there) and the smallest
+    earlier |dS| (to pass them), away from both by a factor."""
+    diffs = np.abs(np.diff(S))
+    lo = diffs[r_stop - 2]
+    hi = np.min(diffs[:r_stop - 2]) if r_stop > 2 else 100.0 * lo
+    assert lo < 0.5 * hi, (lo, hi)
+    return float(np.sqrt(lo * hi))
+
+
+@pytest.mark.parametrize("topology", ["chain", "circle"])
+def test_delta_stop_on_the_brute_force_S_history(topology):
+    """The stopping rule of Algorithms 2 and 3: stop after the first sweep r >= 1 with
+    |S^(r) - S^(r-1)| < delta.  The S history is taken from Algorithm 1 on the full tensor
+    (S(phi) of Theorem 3.1 at the iterates, which the chain rooted at an end and the
+    circle reproduce iterate for iterate); the oracle must stop at the same sweep with
+    status OK, and with delta = 0 it runs to the limit."""
+    if topology == "chain":
+        inst = tiny(28, 3, 8, 2, W.TREE, 0.1, parent=W.chain_parent(3))
+        edges = brute.tree_edges(inst.parent)
+    else:
+        inst = tiny(29, 4, 6, 2, W.CIRCLE, 0.1)
+        edges = brute.circle_edges(4)
+    _, Kt = brute_setup(inst, edges)
+    hist = brute.algorithm1(Kt, inst.weights, 30)
+    phis = [[np.ones(len(w)) for w in inst.weights]] + hist
+    S_b = np.array([brute.sinkhorn_S(Kt, inst.weights, p, inst.eta) for p in phis[:30]])
+    for r_stop in (2, 4, 7):
+        delta = _delta_between(S_b, r_stop)
+        assert _first_delta_stop(S_b, delta) == r_stop
+        if topology == "chain":
+            phi, S, done, rc = oracle.tree_sinkhorn(inst.points, inst.weights, inst.parent, inst.eta, 30,
+                                                    delta=delta)
+        else:
+            phi, S, done, rc = oracle.circle_sinkhorn(inst.points, inst.weights, inst.eta, 30, delta=delta)
+        assert rc == oracle.OK and done == r_stop, (rc, done, r_stop)
+        np.testing.assert_allclose(S, S_b[:r_stop], rtol=1e-12)
+        for k in range(inst.K):
+            np.testing.assert_allclose(phi[k], hist[r_stop - 1][k], rtol=1e-12)
+    if topology == "chain":
+        _, _, done, rc = oracle.tree_sinkhorn(inst.points, inst.weights, inst.parent, inst.eta, 30)
+    else:
+        _, _, done, rc = oracle.circle_sinkhorn(inst.points, inst.weights, inst.eta, 30)
+    assert rc == oracle.MAXITER and done == 30
+
+
 # ---- truncated direct sum (small eta, end of Sec. 6.1) -----------------------------------
 
 def test_truncated_sum_hand_values():
