@@ -270,14 +270,26 @@ int mot_plan_profile(mot_plan plan, int32_t sweeps, mot_step_timing *out, int32_
  *   u_c = x_c * s_c + o_c   (FP64, product rounded before the add, no FMA)
  *   cell_c = clamp(floor(u_c), 0, n - 1),  tile_c = cell_c / T
  *   tile = row-major linearisation over ceil(n/T)^d tiles, coordinate 0 slowest
- *   perm = stable sort of the point indices by tile (ties by ascending index)
+ *   perm = stable sort of the point indices by tile (ties by ascending index); with
+ *          0 <= sub_dim < d the points of a tile are further ordered by their
+ *          tile-relative cell r = cell_{sub_dim} mod T, i.e. the sort key is
+ *          (tile, r, index) (requires T <= 16); sub_dim = -1 gives the plain order
  *   tile_off[t] = first sorted position of tile t; tile_off[ntiles] = npts
+ * The 3-D NFFT path sorts its points with sub_dim = 1 (1-D and 2-D: -1).
  * x is npts x d (ptr_kind), s and o are [d] host arrays; cell (npts x d), perm
  * (npts) and tile_off (ceil(n/T)^d + 1) are written to ptr_kind memory.  Runs on
- * the GPU (stream may be NULL = default stream) and synchronises. */
+ * the GPU (stream may be NULL = default stream) and synchronises.  Temporary device
+ * buffers are allocated and freed inside the call. */
 int mot_bin_points(int32_t d, int64_t npts, const double *x, const double *s, const double *o,
-                   int32_t n, int32_t T, int32_t *cell, int32_t *perm, int32_t *tile_off,
-                   int32_t ptr_kind, void *stream);
+                   int32_t n, int32_t T, int32_t sub_dim, int32_t *cell, int32_t *perm,
+                   int32_t *tile_off, int32_t ptr_kind, void *stream);
+
+/* The binned order a plan keeps marginal k's points in (NFFT and truncated paths; the
+ * identity otherwise): perm_out[i] = original index of the point at binned position i
+ * (n_k int32, ptr_kind).  With the plan's grid scale s, offset o, grid n and tile T
+ * (mot_plan_get_info) it equals mot_bin_points on the marginal's points, sub_dim 1 in
+ * 3-D and -1 otherwise (truncated path: the cell grid of mot_plan_get_info, T = 1). */
+int mot_plan_get_order(mot_plan plan, int32_t k, int32_t *perm_out, int32_t ptr_kind);
 
 /* ---- batched form ------------------------------------------------------------------
  * Run `sweeps` Sinkhorn sweeps on `count` tree plans at once: every level of

@@ -1368,8 +1368,9 @@ int mot_plan_get_info(mot_plan P, mot_plan_info *info)
         I.tile = T.w;
         I.chunk = T.B;
         I.m = T.R;
+        // the scale and offsets the cell binning used (setup_marginals), bit for bit
         I.scale = 1.0 / T.h;
-        for (int c = 0; c < 3; ++c) I.offset[c] = c < P->d ? -T.glo[c] / T.h : 0.0;
+        for (int c = 0; c < 3; ++c) I.offset[c] = c < P->d ? -T.glo[c] * I.scale : 0.0;
     }
     *info = I;
     return MOT_OK;
@@ -1639,16 +1640,17 @@ int mot_apply_kernel(mot_plan P, int32_t t, int32_t s, const double *v, double *
 }
 
 int mot_bin_points(int32_t d, int64_t npts, const double *x, const double *s, const double *o,
-                   int32_t n, int32_t T, int32_t *cell, int32_t *perm, int32_t *tile_off,
+                   int32_t n, int32_t T, int32_t sub_dim, int32_t *cell, int32_t *perm, int32_t *tile_off,
                    int32_t ptr_kind, void *stream)
 {
     if (d < 1 || d > 3 || npts < 0 || !x || !s || !o || n < 1 || T < 1 || !cell || !perm || !tile_off)
         return MOT_EINVAL;
+    if (sub_dim < -1 || sub_dim >= d || (sub_dim >= 0 && T > 16)) return MOT_EINVAL;
     hipStream_t st = (hipStream_t)stream;
     const int tpd = (n + T - 1) / T;
     int64_t ntiles = 1;
     for (int c = 0; c < d; ++c) ntiles *= tpd;
-    if (ntiles > ((int64_t)1 << 30)) return MOT_EINVAL;
+    if (ntiles > ((int64_t)1 << 30) || (sub_dim >= 0 && ntiles >= ((int64_t)1 << 28))) return MOT_EINVAL;
     const size_t sb = stable_tile_sort_scratch(npts, ntiles);
     DevTmp bx, bc, bt, bp, bo, bs;
     MOT_TRY(bx.alloc(std::max<int64_t>(npts, 1) * d * sizeof(double)));
@@ -1665,13 +1667,24 @@ int mot_bin_points(int32_t d, int64_t npts, const double *x, const double *s, co
     if (npts > 0) MOT_HIP(hipMemcpyAsync(xd, x, npts * d * sizeof(double), kin, st));
     MOT_HIP(launch_bin_cells(d, npts, xd, s[0], d > 1 ? s[1] : 0.0, d > 2 ? s[2] : 0.0, o[0],
                              d > 1 ? o[1] : 0.0, d > 2 ? o[2] : 0.0, n, T, cd, td, st));
-    MOT_HIP(stable_tile_sort(npts, td, ntiles, pd, od, scratch, sb, st));
+    // the plan's binning (bin_marginal) calls the same sort with the same sub-key
+    MOT_HIP(stable_tile_sort(npts, td, ntiles, pd, od, scratch, sb, st, sub_dim >= 0 ? cd : nullptr, d,
+                             sub_dim >= 0 ? sub_dim : 0, T));
     if (npts > 0) {
         MOT_HIP(hipMemcpyAsync(cell, cd, npts * d * sizeof(int32_t), kout, st));
         MOT_HIP(hipMemcpyAsync(perm, pd, npts * sizeof(int32_t), kout, st));
     }
     MOT_HIP(hipMemcpyAsync(tile_off, od, (ntiles + 1) * sizeof(int32_t), kout, st));
     MOT_HIP(hipStreamSynchronize(st));
+    return MOT_OK;
+}
+
+int mot_plan_get_order(mot_plan P, int32_t k, int32_t *perm_out, int32_t ptr_kind)
+{
+    if (!P || !perm_out || k < 0 || k >= P->K) return MOT_EINVAL;
+    MOT_HIP(hipMemcpyAsync(perm_out, P->marg[k].perm, P->n[k] * sizeof(int32_t),
+                           ptr_kind == MOT_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, P->stream));
+    MOT_HIP(hipStreamSynchronize(P->stream));
     return MOT_OK;
 }
 

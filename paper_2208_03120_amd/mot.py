@@ -91,7 +91,7 @@ class Result(ctypes.Structure):
 EXPORTED = ["mot_plan_create", "mot_plan_create_tree", "mot_plan_create_circle", "mot_pair_marginal", "mot_sinkhorn", "mot_get_S_history", "mot_marginals",
             "mot_get_scalings", "mot_set_scalings", "mot_apply_kernel", "mot_plan_get_info",
             "mot_plan_footprint", "mot_plan_destroy", "mot_strerror", "mot_bin_points",
-            "mot_plan_profile",
+            "mot_plan_profile", "mot_plan_get_order",
             "mot_batch_create", "mot_batch_sinkhorn", "mot_batch_destroy", "mot_server_create",
             "mot_server_submit", "mot_server_run", "mot_server_fetch", "mot_server_clock",
             "mot_server_destroy"]
@@ -145,8 +145,9 @@ def _load():
         "mot_plan_profile": (ctypes.c_int, [_vp, ctypes.c_int32, _P(StepTiming), ctypes.c_int32]),
         "mot_strerror": (ctypes.c_char_p, [ctypes.c_int]),
         "mot_bin_points": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int64, _dp, _dp, _dp,
-                                          ctypes.c_int32, ctypes.c_int32, _ip, _ip, _ip,
-                                          ctypes.c_int32, _vp]),
+                                          ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _ip, _ip,
+                                          _ip, ctypes.c_int32, _vp]),
+        "mot_plan_get_order": (ctypes.c_int, [_vp, ctypes.c_int32, _ip, ctypes.c_int32]),
         "mot_batch_create": (ctypes.c_int, [_P(_vp), _P(_vp), ctypes.c_int32]),
         "mot_batch_sinkhorn": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32]),
         "mot_batch_destroy": (ctypes.c_int, [_vp]),
@@ -220,19 +221,78 @@ def current_stream():
     return None
 
 
+_ALLOC_FN = Allocator._fields_[0][1]
+_FREE_FN = Allocator._fields_[1][1]
+
+
+def _torch_alloc(nbytes, ctx):
+    import torch
+    try:
+        return torch.cuda.caching_allocator_alloc(int(nbytes), torch.cuda.current_device(),
+                                                  torch.cuda.current_stream())
+    except Exception:  # out of memory: the library reports MOT_ENOMEM
+        return None
+
+
+def _torch_free(ptr, ctx):
+    try:
+        import torch
+        torch.cuda.caching_allocator_delete(ptr)
+    except Exception:  # interpreter shutdown: the process releases the memory
+        pass
+
+
+_TORCH_ALLOCATOR = None
+
+
+def torch_allocator():
+    """A mot_allocator whose blocks come from PyTorch's caching allocator (so PyTorch
+    owns the plan's device memory), or None when no GPU is visible.  The library frees
+    a plan's blocks only after synchronising the plan's stream."""
+    global _TORCH_ALLOCATOR
+    if _TORCH_ALLOCATOR is None:
+        try:
+            import torch
+            if not torch.cuda.is_available():
+                return None
+        except Exception:
+            return None
+        _TORCH_ALLOCATOR = Allocator(_ALLOC_FN(_torch_alloc), _FREE_FN(_torch_free), None)
+    return _TORCH_ALLOCATOR
+
+
+def _is_device_tensor(a):
+    return type(a).__module__.startswith("torch") and getattr(a, "is_cuda", False)
+
+
 class Plan:
     """One multi-marginal OT problem resident on the GPU (mot_plan_create)."""
 
     def __init__(self, points, weights, topology=TREE, parent=None, eta=0.1, path=NFFT,
                  precision=None, fastsum=None, stream=None, edge_weight=None, free=None,
-                 closing_points=None):
-        """edge_weight ([K], entry k for the edge {parent[k], k}) and free ([K] booleans)
-        pose the generalised barycenter problem of Sec. 6.2 (mot_plan_create_tree);
-        closing_points (n_0 x d, sigma(x^1)) the generalised Euler flow of Sec. 6.3 on a
-        circle (mot_plan_create_circle)."""
+                 closing_points=None, allocator="torch"):
+        """points / weights: K host arrays (n_k x d, n_k), or K device tensors (float64 on
+        the plan's GPU), which are passed as MOT_DEVICE pointers.  edge_weight ([K], entry
+        k for the edge {parent[k], k}) and free ([K] booleans) pose the generalised
+        barycenter problem of Sec. 6.2 (mot_plan_create_tree); closing_points (n_0 x d,
+        sigma(x^1)) the generalised Euler flow of Sec. 6.3 on a circle
+        (mot_plan_create_circle).  allocator: "torch" (default) takes the plan's device
+        memory from PyTorch's caching allocator, None lets the library use hipMalloc."""
         if precision is None:
             precision = PREC_MIXED if path != DENSE else PREC_BF16
-        d, sizes, pts, w = _concat(points, weights)
+        kind = HOST
+        if _is_device_tensor(points[0]):
+            import torch
+            kind = DEVICE
+            d = int(points[0].shape[1])
+            sizes = np.array([int(p.shape[0]) for p in points], dtype=np.int64)
+            self._dev_in = (torch.cat([p.reshape(-1, d) for p in points]).to(torch.float64).contiguous(),
+                            torch.cat([x for x in weights]).to(torch.float64).contiguous())
+            pts_p = ctypes.cast(self._dev_in[0].data_ptr(), _dp)
+            w_p = ctypes.cast(self._dev_in[1].data_ptr(), _dp)
+        else:
+            d, sizes, pts, w = _concat(points, weights)
+            pts_p, w_p = _dptr(pts), _dptr(w)
         self.sizes = sizes
         self.K = len(sizes)
         self.d = d
@@ -243,18 +303,25 @@ class Plan:
         self._parent = par
         fs = ctypes.byref(fastsum) if fastsum is not None else None
         st = stream if stream is not None else current_stream()
+        self._alloc = torch_allocator() if allocator == "torch" else None
+        al = ctypes.byref(self._alloc) if self._alloc is not None else None
         if closing_points is not None:
             if topology != CIRCLE:
                 raise ValueError("closing points are a circle option")
-            cl = _f64(np.asarray(closing_points, dtype=np.float64).reshape(int(sizes[0]), d))
+            if kind == DEVICE:
+                self._dev_cl = closing_points.reshape(int(sizes[0]), d).to(closing_points.device,
+                                                                             dtype=self._dev_in[0].dtype).contiguous()
+                cl_p = ctypes.cast(self._dev_cl.data_ptr(), _dp)
+            else:
+                cl = _f64(np.asarray(closing_points, dtype=np.float64).reshape(int(sizes[0]), d))
+                cl_p = _dptr(cl)
             rc = _lib.mot_plan_create_circle(ctypes.byref(self._h), self.K, d, sizes.ctypes.data_as(_lp),
-                                             _dptr(pts), _dptr(w), _dptr(cl), float(eta), path, precision, fs,
-                                             HOST, st, None)
+                                             pts_p, w_p, cl_p, float(eta), path, precision, fs, kind, st, al)
         elif edge_weight is None and free is None:
             rc = _lib.mot_plan_create(ctypes.byref(self._h), self.K, d, sizes.ctypes.data_as(_lp),
-                                      _dptr(pts), _dptr(w), topology,
+                                      pts_p, w_p, topology,
                                       par.ctypes.data_as(_ip) if par is not None else None,
-                                      float(eta), path, precision, fs, HOST, st, None)
+                                      float(eta), path, precision, fs, kind, st, al)
         else:
             if topology != TREE:
                 raise ValueError("edge weights and free nodes are tree options")
@@ -263,8 +330,9 @@ class Plan:
             opt = TreeOptions(_dptr(ew) if ew is not None else None,
                               fr.ctypes.data_as(_ip) if fr is not None else None)
             rc = _lib.mot_plan_create_tree(ctypes.byref(self._h), self.K, d, sizes.ctypes.data_as(_lp),
-                                           _dptr(pts), _dptr(w), par.ctypes.data_as(_ip), ctypes.byref(opt),
-                                           float(eta), path, precision, fs, HOST, st, None)
+                                           pts_p, w_p, par.ctypes.data_as(_ip), ctypes.byref(opt),
+                                           float(eta), path, precision, fs, kind, st, al)
+        self._dev_in = None
         _check(rc, "mot_plan_create")
 
     def close(self):
@@ -312,6 +380,28 @@ class Plan:
         _check(_lib.mot_marginals(self._h, _dptr(out), _dptr(l1), HOST), "mot_marginals")
         return _split(out, self.sizes), l1
 
+    def scalings_device(self, out):
+        """Concatenated scaling vectors into a float64 device tensor (MOT_DEVICE)."""
+        _check(_lib.mot_get_scalings(self._h, ctypes.cast(out.data_ptr(), _dp), DEVICE), "mot_get_scalings")
+        return out
+
+    def set_scalings_device(self, phi):
+        _check(_lib.mot_set_scalings(self._h, ctypes.cast(phi.data_ptr(), _dp), DEVICE), "mot_set_scalings")
+
+    def marginals_device(self, out):
+        """Concatenated marginals into a float64 device tensor (MOT_DEVICE) and the L1
+        errors (host)."""
+        l1 = np.zeros(self.K)
+        _check(_lib.mot_marginals(self._h, ctypes.cast(out.data_ptr(), _dp), _dptr(l1), DEVICE),
+               "mot_marginals")
+        return out, l1
+
+    def order(self, k):
+        """The binned order of marginal k's points (mot_plan_get_order)."""
+        out = np.zeros(int(self.sizes[k]), dtype=np.int32)
+        _check(_lib.mot_plan_get_order(self._h, int(k), out.ctypes.data_as(_ip), HOST), "mot_plan_get_order")
+        return out
+
     def pair_marginal(self, k):
         """Pi between marginal a and k (circle: a = 0; tree: a = parent[k]), n_a x n_k."""
         a = 0 if self._parent is None else int(self._parent[k])
@@ -342,8 +432,9 @@ class Plan:
                 for f, _ in PlanInfo._fields_}
 
 
-def bin_points(x, s, o, n, T, stream=None):
-    """GPU point binning (mot_bin_points): cells, stable tile permutation, tile offsets."""
+def bin_points(x, s, o, n, T, sub_dim=-1, stream=None):
+    """GPU point binning (mot_bin_points): cells, stable tile permutation (sub-keyed by
+    the tile-relative cell in dimension sub_dim when sub_dim >= 0), tile offsets."""
     x = _f64(x)
     npts, d = x.shape
     s = _f64(np.broadcast_to(np.asarray(s, dtype=np.float64), (d,)))
@@ -353,7 +444,7 @@ def bin_points(x, s, o, n, T, stream=None):
     perm = np.zeros(npts, dtype=np.int32)
     toff = np.zeros(tpd ** d + 1, dtype=np.int32)
     st = stream if stream is not None else current_stream()
-    _check(_lib.mot_bin_points(d, npts, _dptr(x), _dptr(s), _dptr(o), int(n), int(T),
+    _check(_lib.mot_bin_points(d, npts, _dptr(x), _dptr(s), _dptr(o), int(n), int(T), int(sub_dim),
                                cell.ctypes.data_as(_ip), perm.ctypes.data_as(_ip),
                                toff.ctypes.data_as(_ip), HOST, st), "mot_bin_points")
     return cell, perm, toff

@@ -107,3 +107,34 @@ def test_dense_circle_library_gemm(mot, prec, bound):
     print("dense %s at N = 1400: marginal rel err %.3e" % (prec, rel))
     assert rel < bound
     plan.close()
+
+
+@pytest.fixture(scope="module")
+def cycle_4000():
+    """The circle benchmark (cycle K = 5, N = 4000, d = 2, eta = 0.1) over 5 sweeps of the
+    FP64 oracle's Algorithm 3."""
+    inst = W.cycle(seed=3, N=4000)
+    ophi, oS, done, rc = oracle.circle_sinkhorn(inst.points, inst.weights, inst.eta, 5)
+    assert done == 5
+    return inst, ophi, oS
+
+
+# NFFT (FP32 products, FP64 updates) and split BF16 meet the 1e-5 gate; FP16 and BF16 carry
+# their operand rounding (measured errors printed, bounded by what these precisions can reach)
+@pytest.mark.timeout(1200)
+@pytest.mark.parametrize("name,path,prec,bound", [("nfft", "NFFT", "MIXED", 1e-5),
+                                                  ("bf16x3", "DENSE", "BF16X3", 1e-5),
+                                                  ("fp16", "DENSE", "FP16", 5e-4),
+                                                  ("bf16", "DENSE", "BF16", 5e-3)])
+def test_circle_benchmark_against_oracle(mot, cycle_4000, name, path, prec, bound):
+    inst, ophi, oS = cycle_4000
+    plan = mot.Plan(inst.points, inst.weights, W.CIRCLE, None, inst.eta, path=getattr(mot, path),
+                    precision=getattr(mot, "PREC_" + prec))
+    rc, done, S_last, err = plan.sinkhorn(5)
+    assert done == 5
+    rel = max_rel(gauge_fix(plan.scalings(), inst.weights), gauge_fix(ophi, inst.weights))
+    s_rel = float(np.max(np.abs(plan.S_history() - oS) / np.abs(oS)))
+    print("cycle K=5 N=4000 %s, 5 sweeps: gauge-fixed phi rel err %.3e, S rel err %.3e" % (name, rel, s_rel))
+    assert rel < bound
+    assert s_rel < 10 * bound
+    plan.close()

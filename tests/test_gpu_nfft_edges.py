@@ -176,6 +176,34 @@ def test_full_size_root_marginal_sampled(mot, full):
     assert float(np.max(np.abs(P[0][idx] - want) / want)) < 9 * 2e-6
 
 
+@pytest.mark.timeout(900)
+def test_full_size_leaf_marginals_sampled(mot, full):
+    """The down products at N = 100000, whose spreading takes three of the root's children
+    per work item: leaf marginals P_k = phi^k gamma_k with gamma_k = K^{(k,0)} (phi^0
+    prod_{t != k} beta_t) (Theorem 4.1; gamma_0 = 1 at the root of the star), at 256
+    sampled points of leaves 1, 5 and 9, against the oracle's direct sums at the plan's own
+    phi.  The oracle's beta_t = K^{(0,t)} phi^t are full products over all root points.
+    Each of the 9 products on the way carries the product error of the sampled product
+    test, so the marginal's relative error is at most 9 times it."""
+    inst, plan = full
+    plan.set_scalings([np.ones(n) for n in inst.sizes])
+    plan.sinkhorn(3)
+    phi = plan.scalings()
+    P, _ = plan.marginals()
+    beta = [None] + [oracle.kernel_apply(inst.points[0], inst.points[t], phi[t], inst.eta)
+                     for t in range(1, inst.K)]
+    for k in (1, 5, 9):
+        u = phi[0].copy()
+        for t in range(1, inst.K):
+            if t != k:
+                u *= beta[t]
+        idx = rng(97 + k).choice(100_000, 256, replace=False)
+        want = phi[k][idx] * oracle.kernel_apply(inst.points[k][idx], inst.points[0], u, inst.eta)
+        err = float(np.max(np.abs(P[k][idx] - want) / want))
+        print("leaf %d marginal, sampled: max rel err %.3e" % (k, err))
+        assert err < 9 * 2e-6
+
+
 def test_error_vs_M_tracks_the_estimate(mot):
     """One product's error against the direct sum falls as M grows until FP32 rounding
     (a few 1e-7), and stays within a factor of the autotuner's estimate (d = 2)."""
