@@ -123,16 +123,22 @@ def test_headline_star_200_sweeps_against_oracle(mot, star_1e4):
     phi = plan.scalings()
     rel = max_rel(gauge_fix(phi, inst.weights), gauge_fix(ophi, inst.weights))
     S = plan.S_history()
-    s_abs = float(np.max(np.abs(S - oS)))
+    s0_rel = abs(S[0] - oS[0]) / abs(oS[0])
+    s_abs = float(np.max(np.abs(S[1:] - oS[1:])))
     P, l1 = plan.marginals()
     viol = max(float(np.sum(np.abs(a - b))) for a, b in zip(P, oP))
-    print("N=1e4, 200 sweeps: gauge-fixed phi %.3e, S abs %.3e (rel %.3e), marginal L1 vs oracle "
-          "%.3e, own marginal L1 %.3e" % (rel, s_abs, s_abs / float(np.min(np.abs(oS))), viol, max(l1)))
+    print("N=1e4, 200 sweeps: gauge-fixed phi %.3e, S^(0) rel %.3e, S^(r>=1) abs %.3e, marginal L1 vs "
+          "oracle %.3e, own marginal L1 %.3e" % (rel, s0_rel, s_abs, viol, max(l1)))
     assert rel < 1e-5
-    # S^(r) = eta (sum_k mu^k . log phi^k - (mu^1 / phi^1_new) . phi^1_old) is gauge invariant;
-    # scalings within eps relative move each of its K sums by at most eps and the last one
-    # (a ratio of two scalings, weights summing to one) by at most 2 eps
-    assert s_abs < inst.eta * (inst.K + 2) * 1e-5
+    # S^(r) = eta (sum_k mu^k . log phi^k(r) - (mu^1 / phi^1(r+1)) . phi^1(r)) is gauge invariant.
+    # At phi = 1 (r = 0) its last sum is the unnormalised mass of the kernel tensor, the sum
+    # over root points of a product of K - 1 kernel products: relative error at most K - 1
+    # times a product's (2e-6, the sampled product bound).  From r = 1 on the mass is that
+    # of a plan whose last-updated marginals are close to mu (the oracle gives 1.07 after the
+    # first sweep of this star and 1 + 2e-4 after the third): scalings within eps move each
+    # of the K log sums by at most eps and the mass term by at most 2 eps times the mass.
+    assert s0_rel < (inst.K - 1) * 2e-6
+    assert s_abs < inst.eta * (inst.K + 2 * 1.1) * 1e-5
     assert viol < 1e-6
     plan.close()
 
