@@ -41,6 +41,7 @@ extern "C" {
 #define MOT_EDEVICE (-4)   /* HIP runtime error                                          */
 #define MOT_ENUMERIC (-6)  /* a scaling vector became Inf/NaN (kernel underflow)         */
 #define MOT_EUNSUPPORTED (-7) /* combination of options not provided                      */
+#define MOT_ELIMIT (-8)    /* size beyond a fixed limit of an allocation-free entry point  */
 
 /* ---- enumerations ---------------------------------------------------------------- */
 #define MOT_TREE 0         /* cost decouples along a tree (Sec. 4.1)                      */
@@ -283,6 +284,22 @@ int mot_plan_profile(mot_plan plan, int32_t sweeps, mot_step_timing *out, int32_
 int mot_bin_points(int32_t d, int64_t npts, const double *x, const double *s, const double *o,
                    int32_t n, int32_t T, int32_t sub_dim, int32_t *cell, int32_t *perm,
                    int32_t *tile_off, int32_t ptr_kind, void *stream);
+
+/* Allocation-free variant of mot_bin_points, for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation.  Same arguments and results as mot_bin_points with ptr_kind = MOT_DEVICE
+ * (x, cell, perm and tile_off are device pointers of the current GPU; s and o host
+ * arrays of d doubles), but nothing is allocated or freed: the tile ids and the sort
+ * keys live in a static device array of the library (12 MiB per GPU, held until the
+ * process ends), and the call only enqueues kernels on `stream` (NULL = default stream)
+ * without synchronising -- the outputs are ready when the stream reaches that point.
+ * Limit: npts <= 2^20 (MOT_ELIMIT beyond it).  Every call on one GPU uses that GPU's one
+ * array: calls whose work overlaps on the device (different streams, or threads without
+ * ordering) race and give undefined results; calls ordered on one stream are safe.  The
+ * first call on a device looks up the array's device address (outside graph capture). */
+int mot_bin_points_noalloc(int32_t d, int64_t npts, const double *x, const double *s, const double *o,
+                           int32_t n, int32_t T, int32_t sub_dim, int32_t *cell, int32_t *perm,
+                           int32_t *tile_off, void *stream);
 
 /* The binned order a plan keeps marginal k's points in (NFFT and truncated paths; the
  * identity otherwise): perm_out[i] = original index of the point at binned position i

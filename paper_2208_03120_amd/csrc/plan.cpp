@@ -1139,6 +1139,7 @@ const char *mot_strerror(int s)
     case MOT_EDEVICE: return "HIP runtime error";
     case MOT_ENUMERIC: return "a scaling vector became Inf/NaN";
     case MOT_EUNSUPPORTED: return "unsupported combination of options";
+    case MOT_ELIMIT: return "size beyond the fixed limit of an allocation-free entry point";
     default: return "unknown status";
     }
 }

@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmot.so")
 
 OK, MAXITER = 0, 1
-EINVAL, EDOMAIN, ENOMEM, EDEVICE, ENUMERIC, EUNSUPPORTED = -1, -2, -3, -4, -6, -7
+EINVAL, EDOMAIN, ENOMEM, EDEVICE, ENUMERIC, EUNSUPPORTED, ELIMIT = -1, -2, -3, -4, -6, -7, -8
 TREE, CIRCLE = 0, 1
 DIRECT, NFFT, DENSE, TRUNC = 0, 1, 2, 3
 PREC_FP64, PREC_MIXED, PREC_BF16, PREC_FP16, PREC_BF16X3 = 0, 1, 2, 3, 4
@@ -91,7 +91,7 @@ class Result(ctypes.Structure):
 EXPORTED = ["mot_plan_create", "mot_plan_create_tree", "mot_plan_create_circle", "mot_pair_marginal", "mot_sinkhorn", "mot_get_S_history", "mot_marginals",
             "mot_get_scalings", "mot_set_scalings", "mot_apply_kernel", "mot_plan_get_info",
             "mot_plan_footprint", "mot_plan_destroy", "mot_strerror", "mot_bin_points",
-            "mot_plan_profile", "mot_plan_get_order",
+            "mot_plan_profile", "mot_plan_get_order", "mot_bin_points_noalloc",
             "mot_batch_create", "mot_batch_sinkhorn", "mot_batch_destroy", "mot_server_create",
             "mot_server_submit", "mot_server_run", "mot_server_fetch", "mot_server_clock",
             "mot_server_destroy"]
@@ -148,6 +148,9 @@ def _load():
                                           ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _ip, _ip,
                                           _ip, ctypes.c_int32, _vp]),
         "mot_plan_get_order": (ctypes.c_int, [_vp, ctypes.c_int32, _ip, ctypes.c_int32]),
+        "mot_bin_points_noalloc": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int64, _dp, _dp, _dp,
+                                                  ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _ip, _ip,
+                                                  _ip, _vp]),
         "mot_batch_create": (ctypes.c_int, [_P(_vp), _P(_vp), ctypes.c_int32]),
         "mot_batch_sinkhorn": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32]),
         "mot_batch_destroy": (ctypes.c_int, [_vp]),

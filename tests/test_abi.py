@@ -73,3 +73,17 @@ def test_footprint_model(mot):
     circ = mot.footprint([4000] * 5, 2, 1, mot.DENSE, mot.PREC_BF16X3, 0.1)
     assert 0 < small < big
     assert circ > 5 * 4096 * 4096 * 4  # the n_1 x n_k FP32 matrices dominate
+
+
+def test_noalloc_binning_limit_refused_on_the_host(mot):
+    """The allocation-free binning refuses sizes beyond its static scratch before touching
+    any pointer or the device."""
+    import ctypes
+    dp = ctypes.POINTER(ctypes.c_double)
+    ip = ctypes.POINTER(ctypes.c_int32)
+    one = np.ones(3)
+    rc = mot.lib().mot_bin_points_noalloc(3, (1 << 20) + 1, ctypes.cast(1, dp), one.ctypes.data_as(dp),
+                                          one.ctypes.data_as(dp), 64, 5, 1, ctypes.cast(1, ip),
+                                          ctypes.cast(1, ip), ctypes.cast(1, ip), None)
+    assert rc == mot.ELIMIT
+    assert mot.strerror(mot.ELIMIT).startswith("size beyond")
