@@ -59,12 +59,11 @@ def build(verbose=False) -> str:
     tmp = LIB + ".tmp"
     tl = _torch_lib_dir()
     if tl:
-        # the HIP runtime and rocBLAS of the process's PyTorch, so that one runtime serves both
+        # the HIP runtime of the process's PyTorch, so that one runtime serves both
         cmd = (["g++", "-shared", "-fPIC", "-o", tmp] + [o for o, _ in results] +
-               ["-L" + tl, "-l:libamdhip64.so", "-l:librocblas.so", "-Wl,-rpath," + tl, "-Wl,--no-undefined"])
+               ["-L" + tl, "-l:libamdhip64.so", "-Wl,-rpath," + tl, "-Wl,--no-undefined"])
     else:
-        cmd = ([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + [o for o, _ in results] +
-               ["-lrocblas"])
+        cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + [o for o, _ in results]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed:\n" + r.stdout + r.stderr)

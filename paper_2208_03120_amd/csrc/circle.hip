@@ -12,9 +12,10 @@
 //   phi^0_i = mu^0_i / sum_j Kmat(0,1)[i][j] phi^1_j Yb_1[i][j]               (row sums)
 //
 // Dense path: each product forms A' = diag(2^-rexp) A diag(phi) in FP64 and rounds it to
-// the 16-bit operand (scale_split_kernel); C = A' B^T is then a plain 16-bit GEMM with FP32
-// accumulation and output, run by rocBLAS (MFMA), or for small products by gemm_kernel
-// (v_mfma_f32_32x32x16_bf16 / _f16).  Precision modes: BF16, FP16 and split
+// the 16-bit operand (scale_rows16_kernel); C = A' B^T is then a 16-bit GEMM with FP32
+// accumulation and output on the MFMA units (v_mfma_f32_32x32x16_bf16 / _f16):
+// gemm_big_kernel / gemm_big_split_kernel for products whose dimensions are multiples of
+// 256, gemm_kernel otherwise.  Precision modes: BF16, FP16 and split
 // BF16 (A' = Ah + Al, B = Bh + Bl, C = Ah Bh + Ah Bl + Al Bh).  The
 // FP32 matrices carry a power-of-two scale per row: before each product the rows of
 // A diag(phi) are normalised (exponent of their largest entry, taken in FP64) and the
@@ -25,8 +26,6 @@
 // one job per row; matrices are FP64.
 #include <algorithm>
 #include <cmath>
-
-#include <rocblas/rocblas.h>
 
 #include "host.h"
 
@@ -53,45 +52,8 @@ __device__ __forceinline__ unsigned short f16_bits(float x)
     return __builtin_bit_cast(unsigned short, h);
 }
 
-// A' = diag(2^-rexp) A diag(phi) in the GEMM's 16-bit form: the products A_il phi_l
-// 2^-rexp_i are formed in FP64 and rounded to FP32, then to FP16 (MODE 1) or BF16 (MODE 0),
-// or split into BF16 high and low parts (MODE 2: lo = bf16(x - hi)).  Formed once per
-// product.  grid: (Kp / 2048 rounded up,
-// rows); a thread converts 8 consecutive entries (Kp is a multiple of 8).
-template <int MODE>
-__global__ __launch_bounds__(256) void scale_split_kernel(const float *__restrict__ A, int lda,
-                                                          const double *__restrict__ phi,
-                                                          const int32_t *__restrict__ rexp, int Kp,
-                                                          unsigned short *__restrict__ Ah,
-                                                          unsigned short *__restrict__ Al)
-{
-    const int i = blockIdx.y;
-    const int l0 = (blockIdx.x * 256 + threadIdx.x) * 8;
-    if (l0 >= Kp) return;
-    const double rowscale = ldexp(1.0, -rexp[i]);
-    const float4 *src = reinterpret_cast<const float4 *>(A + (int64_t)i * lda + l0);
-    unsigned short hv[8], lv[8];
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-        const float4 a4 = src[q];
-        const float av[4] = {a4.x, a4.y, a4.z, a4.w};
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const float x = (float)((double)av[u] * phi[l0 + 4 * q + u] * rowscale);
-            if (MODE == 1) {
-                hv[4 * q + u] = f16_bits(x);
-            } else {
-                hv[4 * q + u] = bf16_bits(x);
-                if (MODE == 2) lv[4 * q + u] = bf16_bits(x - bf16_value(hv[4 * q + u]));
-            }
-        }
-    }
-    *reinterpret_cast<uint4 *>(Ah + (int64_t)i * lda + l0) = *reinterpret_cast<uint4 *>(&hv[0]);
-    if (MODE == 2) *reinterpret_cast<uint4 *>(Al + (int64_t)i * lda + l0) = *reinterpret_cast<uint4 *>(&lv[0]);
-}
 
-
-// C[M x N] (row-major, ldc) = A'[M x K] B[N x K]^T with A' from scale_split_kernel (lda)
+// C[M x N] (row-major, ldc) = A'[M x K] B[N x K]^T with A' from scale_rows16_kernel (lda)
 // and B the 16-bit kernel matrix (ldb), all dimensions padded to the tile sizes by the
 // caller (zero padding).  MODE: 0 BF16, 1 FP16, 2 split BF16 (hi hi + hi lo + lo hi), the
 // three products accumulated in one FP32 accumulator.  Used for small products, where one
@@ -206,35 +168,248 @@ __global__ __launch_bounds__(256) void gemm_kernel(const unsigned short *__restr
             }
 }
 
-// rexp[i] = exponent of max_l |A[i][l] phi_l| (in FP64; 0 for a zero row), and the row
-// scale of the product: s_out[i] = s_in[i] + rexp[i].  One block per row.
-__global__ __launch_bounds__(256) void row_exp_kernel(const float *__restrict__ A, int lda, int K,
-                                                      const double *__restrict__ phi, int32_t *rexp,
-                                                      const int32_t *__restrict__ s_in, int32_t *s_out)
+// ---------------------------------------------------------------------------------------
+// Large products, C[M x N] = A'[M x K] B[N x K]^T with M and N multiples of 256 and K of
+// 128 (the dense matrices of at least 1024 points are padded to 256).  A workgroup of 16
+// wavefronts owns a 256 x 256 tile of C, wave w the 64 x 64 block (w / 4, w % 4): per k16
+// step two A and two B fragments from LDS and four 32x32x16 MFMAs.  Operand tiles of 256
+// rows x 32 k move from global memory straight into LDS with global_load_lds_dwordx4 (no
+// register staging): one such instruction writes each lane's 16 bytes at LDS base + 16 lane,
+// so a wavefront fills 16 rows of 64 bytes.  Rows are not padded; the 16-byte chunk c of
+// row r is stored at chunk c ^ ((r >> 1) & 3), which puts the 8 lanes of an LDS read phase
+// (8 consecutive rows, one chunk) on 8 different bank groups.
+typedef __attribute__((address_space(3))) void lds_void;
+constexpr int kBigT = 256, kBigK = 32, kBigWaves = 16;
+
+__device__ __forceinline__ int big_swizzle(int r) { return (r >> 1) & 3; }
+
+// Tile (m0, n0) of block b: groups of four tile rows, consecutive blocks down a group's
+// columns, so the blocks running together share A rows and B rows in L2.
+__device__ __forceinline__ void big_tile(int b, int tiles_m, int tiles_n, int *m0, int *n0)
+{
+    const int group = b / (4 * tiles_n), first = group * 4;
+    const int gm = min(4, tiles_m - first);
+    const int rem = b % (4 * tiles_n);
+    *m0 = (first + rem % gm) * kBigT;
+    *n0 = (rem / gm) * kBigT;
+}
+
+// Loads of one operand part for k step kt into a stage: wave w fills row group w (rows
+// 16 w .. 16 w + 15 of the A tile and of the B tile).
+__device__ __forceinline__ void big_issue(const unsigned short *A, int lda, const unsigned short *B, int ldb, int m0,
+                                          int n0, int k0, unsigned short *sA, unsigned short *sB, int wave, int lane)
+{
+    const int r = 16 * wave + (lane >> 2);
+    const int c = (lane & 3) ^ big_swizzle(r);
+    __builtin_amdgcn_global_load_lds((const void *)(A + (int64_t)(m0 + r) * lda + k0 + 8 * c),
+                                     (lds_void *)(sA + wave * 512), 16, 0, 0);
+    __builtin_amdgcn_global_load_lds((const void *)(B + (int64_t)(n0 + r) * ldb + k0 + 8 * c),
+                                     (lds_void *)(sB + wave * 512), 16, 0, 0);
+}
+
+// Fragment of the lane for rows (base + lane % 32) and the lane's 8 k values of step ks.
+__device__ __forceinline__ uint4 big_frag(const unsigned short *s, int base, int ks, int lane)
+{
+    const int r = base + (lane & 31);
+    const int cl = ks / 8 + (lane >> 5);
+    return *reinterpret_cast<const uint4 *>(s + r * kBigK + 8 * (cl ^ big_swizzle(r)));
+}
+
+__device__ __forceinline__ void big_store(const f32x16 (&acc)[2][2], float *C, int ldc, int m0, int n0, int wm,
+                                          int wn, int lane)
+{
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int row = m0 + wm + 32 * i + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                const int col = n0 + wn + 32 * j + (lane & 31);
+                C[(int64_t)row * ldc + col] = acc[i][j][r];
+            }
+}
+
+// BF16 (MODE 0) and FP16 (MODE 1).  Four stages, each its own LDS object: the compiler
+// then sees that the stage being loaded is not the stage being read and does not wait for
+// the loads in flight before reading LDS.  Stages are taken two per barrier: after the
+// barrier of pair (s0, s1) every wavefront has finished reading (s2, s3), whose next tiles
+// are requested while (s0, s1) are multiplied.
+template <int MODE>
+__global__ __launch_bounds__(64 * kBigWaves, 1) void gemm_big_kernel(const unsigned short *__restrict__ A, int lda,
+                                                                      const unsigned short *__restrict__ B, int ldb,
+                                                                      float *__restrict__ C, int ldc, int K, int tiles_m,
+                                                                      int tiles_n)
+{
+    constexpr int TILE = kBigT * kBigK;
+    __shared__ __align__(16) unsigned short s0[2 * TILE], s1[2 * TILE], s2[2 * TILE], s3[2 * TILE];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wm = (wave >> 2) * 64, wn = (wave & 3) * 64;
+    int m0, n0;
+    big_tile(blockIdx.x, tiles_m, tiles_n, &m0, &n0);
+    f32x16 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
+    auto mult = [&](const unsigned short *sA) {
+        const unsigned short *sB = sA + TILE;
+#pragma unroll
+        for (int ks = 0; ks < kBigK; ks += 16) {
+            const uint4 a0 = big_frag(sA, wm, ks, lane), a1 = big_frag(sA, wm + 32, ks, lane);
+            const uint4 b0 = big_frag(sB, wn, ks, lane), b1 = big_frag(sB, wn + 32, ks, lane);
+            if constexpr (MODE == 1) {
+                acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, a0), __builtin_bit_cast(f16x8, b0), acc[0][0], 0, 0, 0);
+                acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, a0), __builtin_bit_cast(f16x8, b1), acc[0][1], 0, 0, 0);
+                acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, a1), __builtin_bit_cast(f16x8, b0), acc[1][0], 0, 0, 0);
+                acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, a1), __builtin_bit_cast(f16x8, b1), acc[1][1], 0, 0, 0);
+            } else {
+                acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a0), __builtin_bit_cast(bf16x8, b0), acc[0][0], 0, 0, 0);
+                acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a0), __builtin_bit_cast(bf16x8, b1), acc[0][1], 0, 0, 0);
+                acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a1), __builtin_bit_cast(bf16x8, b0), acc[1][0], 0, 0, 0);
+                acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a1), __builtin_bit_cast(bf16x8, b1), acc[1][1], 0, 0, 0);
+            }
+        }
+    };
+    // s_waitcnt with vmcnt(0) only (expcnt and lgkmcnt left at their maxima)
+    constexpr int kWaitLoads = (7 << 4) | (15 << 8);
+    const int nk = K / kBigK;  // a multiple of 4
+    big_issue(A, lda, B, ldb, m0, n0, 0, s0, s0 + TILE, wave, lane);
+    big_issue(A, lda, B, ldb, m0, n0, kBigK, s1, s1 + TILE, wave, lane);
+    for (int kt = 0; kt < nk; kt += 4) {
+        __builtin_amdgcn_s_waitcnt(kWaitLoads);  // this wave's part of tiles kt, kt + 1
+        __builtin_amdgcn_s_barrier();            // everybody's part; (s2, s3) no longer read
+        if (kt + 2 < nk) {
+            big_issue(A, lda, B, ldb, m0, n0, (kt + 2) * kBigK, s2, s2 + TILE, wave, lane);
+            big_issue(A, lda, B, ldb, m0, n0, (kt + 3) * kBigK, s3, s3 + TILE, wave, lane);
+        }
+        mult(s0);
+        mult(s1);
+        if (kt + 2 < nk) {
+            __builtin_amdgcn_s_waitcnt(kWaitLoads);
+            __builtin_amdgcn_s_barrier();
+            if (kt + 4 < nk) {
+                big_issue(A, lda, B, ldb, m0, n0, (kt + 4) * kBigK, s0, s0 + TILE, wave, lane);
+                big_issue(A, lda, B, ldb, m0, n0, (kt + 5) * kBigK, s1, s1 + TILE, wave, lane);
+            }
+            mult(s2);
+            mult(s3);
+        }
+    }
+    big_store(acc, C, ldc, m0, n0, wm, wn, lane);
+}
+
+// Split BF16: Ah Bh + Ah Bl + Al Bh in one accumulator per block (three MFMAs per fragment
+// pair).  A stage holds four operand tiles (64 KB), so two stages in one dynamic LDS
+// buffer: tile kt + 1 is requested while tile kt is multiplied, and the barrier (with its
+// wait for every load of the wave) separates the steps.
+__global__ __launch_bounds__(64 * kBigWaves, 1) void gemm_big_split_kernel(
+    const unsigned short *__restrict__ Ah, const unsigned short *__restrict__ Al, int lda,
+    const unsigned short *__restrict__ Bh, const unsigned short *__restrict__ Bl, int ldb, float *__restrict__ C,
+    int ldc, int K, int tiles_m, int tiles_n)
+{
+    constexpr int TILE = kBigT * kBigK, STAGE = 4 * TILE;  // Ah, Bh, Al, Bl
+    extern __shared__ __align__(16) unsigned short big_lds[];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wm = (wave >> 2) * 64, wn = (wave & 3) * 64;
+    int m0, n0;
+    big_tile(blockIdx.x, tiles_m, tiles_n, &m0, &n0);
+    f32x16 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
+    auto issue = [&](int kt, int st) {
+        unsigned short *s = big_lds + st * STAGE;
+        big_issue(Ah, lda, Bh, ldb, m0, n0, kt * kBigK, s, s + TILE, wave, lane);
+        big_issue(Al, lda, Bl, ldb, m0, n0, kt * kBigK, s + 2 * TILE, s + 3 * TILE, wave, lane);
+    };
+    const int nk = K / kBigK;
+    issue(0, 0);
+    for (int kt = 0; kt < nk; ++kt) {
+        __syncthreads();  // tile kt in LDS for every wave; tile kt - 1 no longer read
+        if (kt + 1 < nk) issue(kt + 1, (kt + 1) & 1);
+        const unsigned short *sAh = big_lds + (kt & 1) * STAGE, *sBh = sAh + TILE, *sAl = sAh + 2 * TILE,
+                             *sBl = sAh + 3 * TILE;
+#pragma unroll
+        for (int ks = 0; ks < kBigK; ks += 16) {
+            uint4 ah[2], al[2], bh[2], bl[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                ah[i] = big_frag(sAh, wm + 32 * i, ks, lane);
+                al[i] = big_frag(sAl, wm + 32 * i, ks, lane);
+                bh[i] = big_frag(sBh, wn + 32 * i, ks, lane);
+                bl[i] = big_frag(sBl, wn + 32 * i, ks, lane);
+            }
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, ah[i]), __builtin_bit_cast(bf16x8, bh[j]), acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, ah[i]), __builtin_bit_cast(bf16x8, bl[j]), acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, al[i]), __builtin_bit_cast(bf16x8, bh[j]), acc[i][j], 0, 0, 0);
+                }
+        }
+    }
+    big_store(acc, C, ldc, m0, n0, wm, wn, lane);
+}
+
+// One row of a product's left operand per block: rexp = exponent of max_l |A[i][l] phi_l|
+// (in FP64; 0 for a zero row), the row scale s_out[i] = s_in[i] + rexp, and the 16-bit
+// operand A'[i][l] = A[i][l] phi_l 2^-rexp (formed in FP64, rounded to FP32, then to FP16
+// (MODE 1) or BF16 (MODE 0), or split into BF16 high and low parts (MODE 2)).  The row is
+// read twice, the second time from cache.  Kp is a multiple of 8.
+template <int MODE>
+__global__ __launch_bounds__(256) void scale_rows16_kernel(const float *__restrict__ A, int lda, int Kp,
+                                                           const double *__restrict__ phi,
+                                                           const int32_t *__restrict__ s_in, int32_t *s_out,
+                                                           unsigned short *__restrict__ Ah,
+                                                           unsigned short *__restrict__ Al)
 {
     __shared__ double red[4];
     const int i = blockIdx.x;
+    const float *row = A + (int64_t)i * lda;
     double m = 0.0;
-    for (int l = threadIdx.x; l < K; l += blockDim.x) m = fmax(m, fabs((double)A[(int64_t)i * lda + l] * phi[l]));
+    for (int l = 4 * (int)threadIdx.x; l < Kp; l += 4 * 256) {
+        const float4 a4 = *reinterpret_cast<const float4 *>(row + l);
+        m = fmax(m, fabs((double)a4.x * phi[l]));
+        m = fmax(m, fabs((double)a4.y * phi[l + 1]));
+        m = fmax(m, fabs((double)a4.z * phi[l + 2]));
+        m = fmax(m, fabs((double)a4.w * phi[l + 3]));
+    }
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) m = fmax(m, __shfl_xor(m, o));
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        const double mm = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
-        const int e = (mm > 0.0 && mm < INFINITY) ? ilogb(mm) : 0;
-        rexp[i] = e;
-        s_out[i] = s_in[i] + e;
+    const double mm = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    const int e = (mm > 0.0 && mm < INFINITY) ? ilogb(mm) : 0;
+    if (threadIdx.x == 0) s_out[i] = s_in[i] + e;
+    const double rowscale = ldexp(1.0, -e);
+    for (int l0 = 8 * (int)threadIdx.x; l0 < Kp; l0 += 8 * 256) {
+        const float4 *src = reinterpret_cast<const float4 *>(row + l0);
+        unsigned short hv[8], lv[8];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const float4 a4 = src[q];
+            const float av[4] = {a4.x, a4.y, a4.z, a4.w};
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const float x = (float)((double)av[u] * phi[l0 + 4 * q + u] * rowscale);
+                if (MODE == 1) {
+                    hv[4 * q + u] = f16_bits(x);
+                } else {
+                    hv[4 * q + u] = bf16_bits(x);
+                    if (MODE == 2) lv[4 * q + u] = bf16_bits(x - bf16_value(hv[4 * q + u]));
+                }
+            }
+        }
+        *reinterpret_cast<uint4 *>(Ah + (int64_t)i * lda + l0) = *reinterpret_cast<uint4 *>(&hv[0]);
+        if (MODE == 2) *reinterpret_cast<uint4 *>(Al + (int64_t)i * lda + l0) = *reinterpret_cast<uint4 *>(&lv[0]);
     }
-}
-
-// w[i] = phi0_i 2^(sb[i] + sg[i]): the first marginal's scaling times the row scales of
-// the two matrices of a column sum.
-__global__ void row_weight_kernel(const double *__restrict__ phi0, const int32_t *__restrict__ sb,
-                                  const int32_t *__restrict__ sg, int64_t n1, double *__restrict__ w)
-{
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n1) w[i] = ldexp(phi0[i], sb[i] + sg[i]);
 }
 
 // Kernel matrix in 16-bit form: Bh[i][j] = round(K(x^a_i, x^b_j)), Bl = round(rest) (split
@@ -285,49 +460,54 @@ __global__ void kernel_matrix_kernel(const double *__restrict__ xa, int64_t na, 
     out[i * ld + j] = (T)v;
 }
 
-// Column sums with FP64 accumulation: part[chunk][j] = sum_{i in chunk} Yb[i][j] phi0_i Yg[i][j]
-constexpr int kColChunk = 64;
+// Column sums with FP64 accumulation (Theorem 4.3's row-wise inner products, stored
+// transposed): part[ch][j] = sum_{i in chunk ch} Yb[i][j] w_i Yg[i][j] over kColRows rows,
+// ascending, with w_i = phi^0_i 2^(sb[i] + sg[i]) formed here (sb, sg: the two matrices'
+// row scales on the dense path; NULL on the NFFT path).  One column per thread.
+constexpr int kColRows = 64;
 template <class T>
 __global__ __launch_bounds__(256) void colsum_kernel(const T *__restrict__ Yb, const T *__restrict__ Yg, int ld,
                                                      int64_t n1, int64_t nk, const double *__restrict__ phi0,
+                                                     const int32_t *__restrict__ sb, const int32_t *__restrict__ sg,
                                                      double *__restrict__ part)
 {
+    __shared__ double w[kColRows];
+    const int64_t i0 = (int64_t)blockIdx.y * kColRows;
+    const int rows = (int)min((int64_t)kColRows, n1 - i0);
+    if ((int)threadIdx.x < rows) {
+        const int64_t i = i0 + threadIdx.x;
+        w[threadIdx.x] = sb ? ldexp(phi0[i], sb[i] + sg[i]) : phi0[i];
+    }
+    __syncthreads();
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t i0 = (int64_t)blockIdx.y * kColChunk;
     if (j >= nk) return;
-    double s = 0.0;
-    const int64_t i1 = min(n1, i0 + kColChunk);
-    for (int64_t i = i0; i < i1; ++i) s += (double)Yb[i * ld + j] * phi0[i] * (double)Yg[i * ld + j];
-    part[blockIdx.y * nk + j] = s;
+    const T *yb = Yb + i0 * ld + j, *yg = Yg + i0 * ld + j;
+    double acc = 0.0;
+#pragma unroll 8
+    for (int r = 0; r < rows; ++r) acc += (double)yb[(int64_t)r * ld] * w[r] * (double)yg[(int64_t)r * ld];
+    part[blockIdx.y * nk + j] = acc;
 }
 
-// Row sums for phi^0: den_i = sum_j K(x^0_i, x^1_j) phi^1_j Yb_1[i][j], one block per row.
+// Row sums for phi^0 from the resident kernel matrix Yg_1 = K^{(1,2)}:
+// den_i = 2^rs[i] sum_j Yg_1[i][j] phi^1_j Yb_1[i][j] (Theorem 4.3's first inner product;
+// rs: Yb_1's row scale on the dense path, NULL on the NFFT path), one block per row.
 template <class T>
-__global__ __launch_bounds__(256) void rowsum_kernel(const double *__restrict__ x0, const double *__restrict__ x1,
-                                                     int64_t n1, int d, double eta, const double *__restrict__ phi1,
-                                                     const T *__restrict__ Yb1, int ld, const int32_t *__restrict__ rs,
-                                                     double *__restrict__ den)
+__global__ __launch_bounds__(256) void rowsum_k_kernel(const T *__restrict__ Yg1, const T *__restrict__ Yb1, int ld,
+                                                       int64_t n1c, const double *__restrict__ phi1,
+                                                       const int32_t *__restrict__ rs, double *__restrict__ den)
 {
     __shared__ double red[4];
     const int64_t i = blockIdx.x;
-    double xi[3] = {0, 0, 0};
-    for (int c = 0; c < d; ++c) xi[c] = x0[i * d + c];
     double s = 0.0;
-    for (int64_t j = threadIdx.x; j < n1; j += blockDim.x) {
-        double d2 = 0.0;
-        for (int c = 0; c < d; ++c) {
-            const double df = xi[c] - x1[j * d + c];
-            d2 += df * df;
-        }
-        s += exp(-d2 / eta) * phi1[j] * (double)Yb1[i * ld + j];
-    }
+    for (int64_t j = threadIdx.x; j < n1c; j += blockDim.x)
+        s += (double)Yg1[i * ld + j] * phi1[j] * (double)Yb1[i * ld + j];
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
     __syncthreads();
     if (threadIdx.x == 0) {
         const double t = (red[0] + red[1]) + (red[2] + red[3]);
-        den[i] = rs ? ldexp(t, rs[i]) : t;  // row scale of Yb_1 (dense path)
+        den[i] = rs ? ldexp(t, rs[i]) : t;
     }
 }
 
@@ -344,9 +524,10 @@ __global__ __launch_bounds__(256) void circle_phi_kernel(const double *__restric
     double s1 = 0.0, s2 = 0.0;
     if (j < n) {
         double den = 0.0;
-        if (nparts > 0)
+        if (nparts > 0) {
+#pragma unroll 8
             for (int p = 0; p < nparts; ++p) den += part[p * n + j];
-        else
+        } else
             den = part[j];
         const double m = mu[j], old = phi[j];
         if (marg_only) {
@@ -474,20 +655,13 @@ struct CircleState {
     std::vector<unsigned short *> Kb_h, Kb_l, Kg_h, Kg_l;  // dense: Kmat(k,k+1), Kmat(k,k-1)
     int32_t *rexp = nullptr;
     // dense path: the scaled left operand of a product in 16-bit form (n1p x ldmax each;
-    // Al only for split BF16), and the rocBLAS handle (on the plan's stream) that
-    // multiplies it with the 16-bit kernel matrix
+    // Al only for split BF16)
     unsigned short *Ah = nullptr, *Al = nullptr;
-    rocblas_handle blas = nullptr;
-    ~CircleState()
-    {
-        if (blas) (void)rocblas_destroy_handle(blas);
-    }
     // dense path: power-of-two scale of every row of each matrix (see the file comment)
     int K = 0;
     std::vector<int32_t *> sb;     // [K] row scales of Yb_k
     int32_t *sg[2] = {nullptr, nullptr};
     int32_t *szero = nullptr;      // the constant matrices Yg_1, Yb_{K-1}
-    double *w = nullptr;           // row weights of a column sum
     double *part = nullptr;        // column-sum partials [chunk][j]
     double *den0 = nullptr;
     double *s_part = nullptr;      // phi-update partials
@@ -513,59 +687,49 @@ static int32_t *Yscale(CircleState &C, int which_gamma, int k)  // dense path on
     return k == C.K - 1 ? C.szero : C.sb[k];
 }
 
-// Products of at least this many multiply-adds go to the library GEMM; smaller ones (the
-// Euler flows' N = 400, for instance) to the one fused launch of gemm_kernel.
-constexpr double kLibraryGemmMin = 2147483648.0;
+// Rows and columns of the dense path's matrices: multiples of 256 from 1024 points on (so
+// the products take gemm_big_kernel), of 128 below.
+static int dense_pad(int64_t n) { return n >= 1024 ? pad_to(n, 256) : pad_to(n, 128); }
 
-// One product of the recursions on the dense path: rexp and the row scales, the scaled
-// left operand A' = diag(2^-rexp) A diag(phi) in 16-bit form, then C = A' B^T as a plain
-// 16-bit GEMM with FP32 accumulation and output (rocBLAS, or gemm_kernel for small
-// products); split BF16 accumulates A'_hi B_hi^T + A'_hi B_lo^T + A'_lo B_hi^T (three
-// library calls).  Row-major C (M x N, ldc) is
-// the column-major N x M matrix B A'^T, so the call multiplies B (transposed view of the
-// row-major N x K array) by A'.
+// One product of the recursions on the dense path: the row scales and the scaled left
+// operand A' = diag(2^-rexp) A diag(phi) in 16-bit form in one pass, then C = A' B^T with 16-bit
+// operands and FP32 accumulation and output: one launch of gemm_big_kernel /
+// gemm_big_split_kernel when M, N and K are multiples of 256, 256 and 128, else of the
+// 128 x 128-tile gemm_kernel.
 static hipError_t launch_gemm(const CircleState &C, const float *A, int lda, const double *phi,
                               const unsigned short *Bh, const unsigned short *Bl, int ldb, float *Cm,
                               int ldc, int Mp, int Np, int Kp, const int32_t *s_in, int32_t *s_out,
                               hipStream_t s)
 {
-    const dim3 sgrid((unsigned)((Kp + 2047) / 2048), (unsigned)Mp);
-    hipLaunchKernelGGL(row_exp_kernel, dim3(Mp), dim3(256), 0, s, A, lda, Kp, phi, C.rexp, s_in, s_out);
     if (C.mode == 1)
-        hipLaunchKernelGGL(scale_split_kernel<1>, sgrid, dim3(256), 0, s, A, lda, phi, (const int32_t *)C.rexp, Kp,
-                           C.Ah, C.Al);
+        hipLaunchKernelGGL(scale_rows16_kernel<1>, dim3(Mp), dim3(256), 0, s, A, lda, Kp, phi, s_in, s_out, C.Ah, C.Al);
     else if (C.mode == 2)
-        hipLaunchKernelGGL(scale_split_kernel<2>, sgrid, dim3(256), 0, s, A, lda, phi, (const int32_t *)C.rexp, Kp,
-                           C.Ah, C.Al);
+        hipLaunchKernelGGL(scale_rows16_kernel<2>, dim3(Mp), dim3(256), 0, s, A, lda, Kp, phi, s_in, s_out, C.Ah, C.Al);
     else
-        hipLaunchKernelGGL(scale_split_kernel<0>, sgrid, dim3(256), 0, s, A, lda, phi, (const int32_t *)C.rexp, Kp,
-                           C.Ah, C.Al);
+        hipLaunchKernelGGL(scale_rows16_kernel<0>, dim3(Mp), dim3(256), 0, s, A, lda, Kp, phi, s_in, s_out, C.Ah, C.Al);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if ((double)Mp * Np * Kp < kLibraryGemmMin) {
-        const dim3 grid(Np / kBN, Mp / kBM);
-        if (C.mode == 1)
-            hipLaunchKernelGGL(gemm_kernel<1>, grid, dim3(256), 0, s, (const unsigned short *)C.Ah,
-                               (const unsigned short *)C.Al, lda, Bh, Bl, ldb, Cm, ldc, Kp);
-        else if (C.mode == 2)
-            hipLaunchKernelGGL(gemm_kernel<2>, grid, dim3(256), 0, s, (const unsigned short *)C.Ah,
-                               (const unsigned short *)C.Al, lda, Bh, Bl, ldb, Cm, ldc, Kp);
+    const unsigned short *Ah = C.Ah, *Al = C.Al;
+    if (Mp % kBigT == 0 && Np % kBigT == 0 && Kp % (4 * kBigK) == 0) {
+        const int tm = Mp / kBigT, tn = Np / kBigT;
+        const dim3 grid((unsigned)(tm * tn)), block(64 * kBigWaves);
+        if (C.mode == 2)
+            hipLaunchKernelGGL(gemm_big_split_kernel, grid, block, 2 * 4 * kBigT * kBigK * sizeof(unsigned short), s,
+                               Ah, Al, lda, Bh, Bl, ldb, Cm, ldc, Kp, tm, tn);
+        else if (C.mode == 1)
+            hipLaunchKernelGGL(gemm_big_kernel<1>, grid, block, 0, s, Ah, lda, Bh, ldb, Cm, ldc, Kp, tm, tn);
         else
-            hipLaunchKernelGGL(gemm_kernel<0>, grid, dim3(256), 0, s, (const unsigned short *)C.Ah,
-                               (const unsigned short *)C.Al, lda, Bh, Bl, ldb, Cm, ldc, Kp);
+            hipLaunchKernelGGL(gemm_big_kernel<0>, grid, block, 0, s, Ah, lda, Bh, ldb, Cm, ldc, Kp, tm, tn);
         return hipGetLastError();
     }
-    const rocblas_datatype t16 = C.mode == 1 ? rocblas_datatype_f16_r : rocblas_datatype_bf16_r;
-    const float one = 1.0f, zero = 0.0f;
-    auto gemm = [&](const unsigned short *Bx, const unsigned short *Ax, const float *beta) {
-        return rocblas_gemm_ex(C.blas, rocblas_operation_transpose, rocblas_operation_none, Np, Mp, Kp, &one, Bx,
-                               t16, ldb, Ax, t16, lda, beta, Cm, rocblas_datatype_f32_r, ldc, Cm,
-                               rocblas_datatype_f32_r, ldc, rocblas_datatype_f32_r, rocblas_gemm_algo_standard, 0, 0);
-    };
-    rocblas_status st = gemm(Bh, C.Ah, &zero);
-    if (st == rocblas_status_success && C.mode == 2) st = gemm(Bl, C.Ah, &one);
-    if (st == rocblas_status_success && C.mode == 2) st = gemm(Bh, C.Al, &one);
-    return st == rocblas_status_success ? hipSuccess : hipErrorLaunchFailure;
+    const dim3 grid(Np / kBN, Mp / kBM);
+    if (C.mode == 1)
+        hipLaunchKernelGGL(gemm_kernel<1>, grid, dim3(256), 0, s, Ah, Al, lda, Bh, Bl, ldb, Cm, ldc, Kp);
+    else if (C.mode == 2)
+        hipLaunchKernelGGL(gemm_kernel<2>, grid, dim3(256), 0, s, Ah, Al, lda, Bh, Bl, ldb, Cm, ldc, Kp);
+    else
+        hipLaunchKernelGGL(gemm_kernel<0>, grid, dim3(256), 0, s, Ah, Al, lda, Bh, Bl, ldb, Cm, ldc, Kp);
+    return hipGetLastError();
 }
 
 // One matrix product of the recursions: gamma (k from k-1) or beta (k from k+1).
@@ -593,19 +757,17 @@ static int colsum_phi(mot_plan_s *P, CircleState &C, int k, bool marg_only)
 {
     hipStream_t st = P->stream;
     const int64_t n1 = C.n1, nk = P->n[k];
-    const int chunks = (int)((n1 + kColChunk - 1) / kColChunk);
-    dim3 g((unsigned)((nk + 255) / 256), (unsigned)chunks);
+    const int chunks = (int)((n1 + kColRows - 1) / kColRows);
+    const dim3 g((unsigned)((nk + 255) / 256), (unsigned)chunks);
     const void *Yb = C.Yb[k], *Yg = Ymat(C, 1, k);
     if (C.nfft)
-        hipLaunchKernelGGL(colsum_kernel<double>, g, dim3(256), 0, st, (const double *)Yb, (const double *)Yg,
-                           C.ld[k], n1, nk, (const double *)P->marg[0].phi, C.part);
-    else {
-        hipLaunchKernelGGL(row_weight_kernel, dim3((unsigned)((n1 + 255) / 256)), dim3(256), 0, st,
-                           (const double *)P->marg[0].phi, (const int32_t *)Yscale(C, 0, k),
-                           (const int32_t *)Yscale(C, 1, k), n1, C.w);
-        hipLaunchKernelGGL(colsum_kernel<float>, g, dim3(256), 0, st, (const float *)Yb, (const float *)Yg,
-                           C.ld[k], n1, nk, (const double *)C.w, C.part);
-    }
+        hipLaunchKernelGGL(colsum_kernel<double>, g, dim3(256), 0, st, (const double *)Yb, (const double *)Yg, C.ld[k],
+                           n1, nk, (const double *)P->marg[0].phi, (const int32_t *)nullptr, (const int32_t *)nullptr,
+                           C.part);
+    else
+        hipLaunchKernelGGL(colsum_kernel<float>, g, dim3(256), 0, st, (const float *)Yb, (const float *)Yg, C.ld[k],
+                           n1, nk, (const double *)P->marg[0].phi, (const int32_t *)Yscale(C, 0, k),
+                           (const int32_t *)Yscale(C, 1, k), C.part);
     MOT_HIP(hipGetLastError());
     const unsigned blocks = (unsigned)((nk + 255) / 256);
     double *sout = marg_only ? C.m_part : C.s_part + 2 * C.s_slot[k];
@@ -619,14 +781,12 @@ static int rowsum_den0(mot_plan_s *P, CircleState &C)
 {
     hipStream_t st = P->stream;
     if (C.nfft)
-        hipLaunchKernelGGL(rowsum_kernel<double>, dim3((unsigned)C.n1), dim3(256), 0, st,
-                           (const double *)P->marg[0].pts, (const double *)P->marg[1].pts, (int64_t)P->n[1], P->d,
-                           P->eta, (const double *)P->marg[1].phi, (const double *)C.Yb[1], C.ld[1],
+        hipLaunchKernelGGL(rowsum_k_kernel<double>, dim3((unsigned)C.n1), dim3(256), 0, st, (const double *)C.Yg1,
+                           (const double *)C.Yb[1], C.ld[1], (int64_t)P->n[1], (const double *)P->marg[1].phi,
                            (const int32_t *)nullptr, C.den0);
     else
-        hipLaunchKernelGGL(rowsum_kernel<float>, dim3((unsigned)C.n1), dim3(256), 0, st,
-                           (const double *)P->marg[0].pts, (const double *)P->marg[1].pts, (int64_t)P->n[1], P->d,
-                           P->eta, (const double *)P->marg[1].phi, (const float *)C.Yb[1], C.ld[1],
+        hipLaunchKernelGGL(rowsum_k_kernel<float>, dim3((unsigned)C.n1), dim3(256), 0, st, (const float *)C.Yg1,
+                           (const float *)C.Yb[1], C.ld[1], (int64_t)P->n[1], (const double *)P->marg[1].phi,
                            (const int32_t *)Yscale(C, 0, 1), C.den0);
     return hipGetLastError() == hipSuccess ? MOT_OK : MOT_EDEVICE;
 }
@@ -698,12 +858,12 @@ int circle_create(mot_plan_s *P, const std::vector<double> &pts_h, const std::ve
         else if (P->precision == MOT_PREC_BF16X3) C.mode = 2;
         else return MOT_EUNSUPPORTED;
     }
-    MOT_TRY(setup_marginals(P, pts_h, w_h, fs, C.nfft ? 0 : 128));
+    MOT_TRY(setup_marginals(P, pts_h, w_h, fs, C.nfft ? 0 : 256));
     hipStream_t st = P->stream;
     C.n1 = P->n[0];
-    C.n1p = C.nfft ? (int)C.n1 : pad_to(C.n1, 128);
+    C.n1p = C.nfft ? (int)C.n1 : dense_pad(C.n1);
     C.ld.resize(K);
-    for (int k = 0; k < K; ++k) C.ld[k] = C.nfft ? (int)P->n[k] : pad_to(P->n[k], 128);
+    for (int k = 0; k < K; ++k) C.ld[k] = C.nfft ? (int)P->n[k] : dense_pad(P->n[k]);
     const size_t esz = C.nfft ? 8 : 4;
     int ldmax = 0;
     int64_t nmax = 0;
@@ -746,18 +906,18 @@ int circle_create(mot_plan_s *P, const std::vector<double> &pts_h, const std::ve
         MOT_TRY(P->arena.get_n((size_t)C.n1p, &C.rexp));
         MOT_TRY(P->arena.get_n((size_t)C.n1p * ldmax, &C.Ah));
         if (C.mode == 2) MOT_TRY(P->arena.get_n((size_t)C.n1p * ldmax, &C.Al));
-        if (rocblas_create_handle(&C.blas) != rocblas_status_success) return MOT_EDEVICE;
-        if (rocblas_set_stream(C.blas, st) != rocblas_status_success) return MOT_EDEVICE;
+        // the split kernel's two stages of four operand tiles live in dynamic LDS (128 KB)
+        MOT_HIP(hipFuncSetAttribute((const void *)gemm_big_split_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    2 * 4 * kBigT * kBigK * (int)sizeof(unsigned short)));
         C.K = K;
         C.sb.assign(K, nullptr);
         for (int k = 1; k < K - 1; ++k) MOT_TRY(P->arena.get_n((size_t)C.n1p, &C.sb[k]));
         MOT_TRY(P->arena.get_n((size_t)C.n1p, &C.sg[0]));
         MOT_TRY(P->arena.get_n((size_t)C.n1p, &C.sg[1]));
         MOT_TRY(P->arena.get_n((size_t)C.n1p, &C.szero));
-        MOT_TRY(P->arena.get_n((size_t)C.n1p, &C.w));
         MOT_HIP(launch_fill_int(C.szero, 0, C.n1p, st));
     }
-    const int chunks = (int)((C.n1 + kColChunk - 1) / kColChunk);
+    const int chunks = (int)((C.n1 + kColRows - 1) / kColRows);
     MOT_TRY(P->arena.get_n((size_t)chunks * nmax, &C.part));
     MOT_TRY(P->arena.get_n((size_t)C.n1, &C.den0));
     C.s_slot.assign(K, 0);
@@ -879,9 +1039,9 @@ size_t circle_footprint(int K, const int64_t *n, int path, int precision)
 {
     size_t b = 0;
     const bool nfft = path == MOT_NFFT;
-    const int64_t n1 = nfft ? n[0] : pad_to(n[0], 128);
+    const int64_t n1 = nfft ? n[0] : dense_pad(n[0]);
     int64_t ldmax = 0;
-    for (int k = 0; k < K; ++k) ldmax = std::max<int64_t>(ldmax, nfft ? n[k] : pad_to(n[k], 128));
+    for (int k = 0; k < K; ++k) ldmax = std::max<int64_t>(ldmax, nfft ? n[k] : dense_pad(n[k]));
     const size_t esz = nfft ? 8 : 4;
     b += (size_t)n1 * ldmax * esz * (K + 2);
     if (!nfft) {

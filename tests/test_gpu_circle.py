@@ -92,11 +92,14 @@ def test_dense_long_cycle_stays_in_range(mot, long_cycle, prec, bound):
 
 
 @pytest.mark.parametrize("prec,bound", [("BF16X3", 1e-5), ("FP16", 5e-4), ("BF16", 5e-3)])
-def test_dense_circle_library_gemm(mot, prec, bound):
-    """K = 3 with N = 1400 (padded 1408): the product 1408^3 goes to the library GEMM
-    rather than the fused kernel.  Marginals at the plan's own scaling vectors after 3
-    sweeps against the FP64 oracle's at the same phi (one 1400^3 product in FP64)."""
-    inst = W.make_instance(rng(59), 3, [1400, 1380, 1410], 2, W.CIRCLE, 0.1)
+@pytest.mark.parametrize("sizes", [[1400, 1380, 1410], [1100, 600, 1300]])
+def test_dense_circle_large_gemm(mot, prec, bound, sizes):
+    """K = 3 with matrices of 1400 points (padded to 1536): every product runs on the
+    256 x 256-tile kernel; with 1100 / 600 / 1300 points (1280, 640, 1536) the products
+    whose dimensions are not all multiples of 256 take the 128 x 128-tile kernel and the
+    others the large one.  Marginals at the plan's own scaling vectors after 3 sweeps
+    against the FP64 oracle's at the same phi."""
+    inst = W.make_instance(rng(59), 3, sizes, 2, W.CIRCLE, 0.1)
     p = getattr(mot, "PREC_" + prec)
     plan = mot.Plan(inst.points, inst.weights, W.CIRCLE, None, inst.eta, path=mot.DENSE, precision=p)
     plan.sinkhorn(3)
@@ -104,7 +107,7 @@ def test_dense_circle_library_gemm(mot, prec, bound):
     P, _ = plan.marginals()
     oP = oracle.circle_marginals(inst.points, inst.eta, phi)
     rel = max(float(np.max(np.abs(a - b)) / np.max(np.abs(b))) for a, b in zip(P, oP))
-    print("dense %s at N = 1400: marginal rel err %.3e" % (prec, rel))
+    print("dense %s at %s: marginal rel err %.3e" % (prec, sizes, rel))
     assert rel < bound
     plan.close()
 
