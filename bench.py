@@ -307,44 +307,103 @@ def bench_euler_flow(mot, W, N=400, K=6, eta=0.05, sweeps=50):
     return res
 
 
-def bench_circle(mot, W, sweeps=20):
-    """Cycle K=5, N=4000, d=2, eta=0.1: dense MFMA products in three precisions and the
-    row-by-row NFFT products; errors of the gauge-fixed scaling vectors are stated
-    against the NFFT (FP32, FP64 updates) result after the same sweeps."""
+def _oracle_threads(n):
+    """Set the OpenMP thread count of the oracle's parallel loops (libgomp, loaded with
+    the oracle library); returns the previous count."""
+    import ctypes
+    gomp = ctypes.CDLL("libgomp.so.1")
+    prev = gomp.omp_get_max_threads()
+    gomp.omp_set_num_threads(int(n))
+    return prev
+
+
+def bench_config1(mot, W, sweeps=100, warmup=10):
+    """Plain method: path K=3, N=500, d=2, eta=0.1, FP64 direct summation, 100 sweeps.
+    GPU sweeps/s, the gauge-fixed scaling error against the FP64 oracle after the same 100
+    sweeps from phi = 1, and the oracle's full run timed on one host thread and on all."""
     import torch
+    import oracle
+    inst = W.path_fp64_direct(seed=1, N=500)
+    plan = mot.Plan(inst.points, inst.weights, W.TREE, inst.parent, inst.eta, path=mot.DIRECT,
+                    precision=mot.PREC_FP64)
+    plan.sinkhorn(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.sinkhorn(sweeps)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / sweeps
+    plan.set_scalings([np.ones(n) for n in inst.sizes])
+    plan.sinkhorn(sweeps)
+    g = gauge_fix(plan.scalings(), inst.weights)
+    plan.close()
+    res = {"workload": "path tree K=3, N=500 per marginal, d=2, eta=0.1, FP64 direct, %d sweeps" % sweeps,
+           "sweeps_per_s": 1.0 / dt, "ms_per_sweep": dt * 1e3}
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    prev = _oracle_threads(cores)
+    try:
+        for name, nt in [("oracle_all_cores", cores), ("oracle_1_thread", 1)]:
+            _oracle_threads(nt)
+            c0 = time.perf_counter()
+            ophi, oS, _, _ = oracle.tree_sinkhorn(inst.points, inst.weights, inst.parent, inst.eta, sweeps)
+            c1 = time.perf_counter() - c0
+            res[name] = {"sweeps_per_s": sweeps / c1, "threads": nt, "seconds": c1}
+    finally:
+        _oracle_threads(prev)
+    res["phi_gauge_fixed_max_rel_err_vs_oracle"] = max(float(np.max(np.abs(a - b) / np.abs(b)))
+                                                       for a, b in zip(g, gauge_fix(ophi, inst.weights)))
+    res["speedup_vs_oracle_all_cores"] = res["sweeps_per_s"] / res["oracle_all_cores"]["sweeps_per_s"]
+    return res
+
+
+def bench_circle(mot, W, sweeps=20, acc_sweeps=5):
+    """Cycle K=5, N=4000, d=2, eta=0.1: dense MFMA products in three precisions and the
+    row-by-row NFFT products, each timed over the same sweeps.  Every variant's error is
+    stated against the FP64 oracle's Algorithm 3: gauge-fixed scaling vectors and S after
+    acc_sweeps sweeps from phi = 1 on both sides.  The oracle run's time (on all host cores,
+    including its kernel matrices and initial upward pass) is the CPU baseline."""
+    import torch
+    import oracle
     inst = W.cycle(seed=3, N=4000)
-    res = {"workload": "cycle K=5, N=4000 per marginal, d=2, eta=0.1", "sweeps": sweeps}
-    ref = None
-    for name, path, prec, n_sw in [("nfft_f32", mot.NFFT, mot.PREC_MIXED, 3),
-                                   ("dense_bf16x3", mot.DENSE, mot.PREC_BF16X3, sweeps),
-                                   ("dense_fp16", mot.DENSE, mot.PREC_FP16, sweeps),
-                                   ("dense_bf16", mot.DENSE, mot.PREC_BF16, sweeps)]:
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    c0 = time.perf_counter()
+    ophi, oS, _, _ = oracle.circle_sinkhorn(inst.points, inst.weights, inst.eta, acc_sweeps)
+    c1 = time.perf_counter() - c0
+    og = gauge_fix(ophi, inst.weights)
+    res = {"workload": "cycle K=5, N=4000 per marginal, d=2, eta=0.1", "sweeps": sweeps,
+           "oracle": {"sweeps": acc_sweeps, "seconds": c1, "cores": cores,
+                      "sweeps_per_s_incl_setup": acc_sweeps / c1}}
+    for name, path, prec in [("nfft_f32", mot.NFFT, mot.PREC_MIXED),
+                             ("dense_bf16x3", mot.DENSE, mot.PREC_BF16X3),
+                             ("dense_fp16", mot.DENSE, mot.PREC_FP16),
+                             ("dense_bf16", mot.DENSE, mot.PREC_BF16)]:
         plan = mot.Plan(inst.points, inst.weights, W.CIRCLE, None, inst.eta, path=path, precision=prec)
+        plan.sinkhorn(acc_sweeps)
+        g = gauge_fix(plan.scalings(), inst.weights)
+        S = plan.S_history()
+        entry = {"phi_rel_err_vs_oracle": max(float(np.max(np.abs(a - b) / np.abs(b))) for a, b in zip(g, og)),
+                 "S_rel_err_vs_oracle": float(np.max(np.abs(S - oS) / np.abs(oS)))}
         plan.sinkhorn(1)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        plan.sinkhorn(n_sw)
+        plan.sinkhorn(sweeps)
         torch.cuda.synchronize()
-        dt = (time.perf_counter() - t0) / n_sw
-        entry = {"sweeps_per_s": 1.0 / dt, "ms_per_sweep": dt * 1e3}
-        # accuracy after 10 sweeps from phi = 1
-        plan.set_scalings([np.ones(n) for n in inst.sizes])
-        plan.sinkhorn(10)
-        g = gauge_fix(plan.scalings(), inst.weights)
-        if ref is None:
-            ref = g
-        else:
-            entry["phi_rel_err_vs_nfft"] = max(float(np.max(np.abs(a - b) / np.abs(b))) for a, b in zip(g, ref))
+        dt = (time.perf_counter() - t0) / sweeps
+        entry.update({"sweeps_per_s": 1.0 / dt, "ms_per_sweep": dt * 1e3})
         res[name] = entry
         plan.close()
     return res
 
 
-def bench_batched(mot, W, count=256, sweeps=20):
+def bench_batched(mot, W, count=256, sweeps=20, parity_count=16, parity_sweeps=20):
     """256 independent tree instances (K ~ U{3..12}, N log-uniform [1e3, 5e4], d ~ U{1,2,3},
     random Pruefer trees, eta ~ U(0.02, 0.2), Dirichlet weights), autotuned NFFT
-    parameters, one captured graph per batched sweep."""
+    parameters, one captured graph per batched sweep.  Beside the rate: the launches of a
+    batched sweep, the spreading and interpolation work of the sweep (2 flop per window
+    tap, (2m)^d taps per point, both per product) against the FP32 MFMA peak, and the
+    gauge-fixed scaling error of the 16 cheapest instances against the FP64 oracle after
+    20 sweeps from phi = 1 (those plans restarted inside the batch)."""
     import torch
+    import oracle
     insts = [W.batched_instance(i) for i in range(count)]
     stream = mot.current_stream()
     t0 = time.perf_counter()
@@ -358,6 +417,10 @@ def bench_batched(mot, W, count=256, sweeps=20):
     batch.sinkhorn(sweeps)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t1) / sweeps
+    flops = 0.0
+    for x, p in zip(insts, plans):
+        info = p.info()
+        flops += 2 * (x.K - 1) * 2 * 2.0 * (2 * info["m"]) ** info["d"] * x.sizes[0]
     # the same plans one after another (each with its own captured graph)
     for p in plans[:32]:
         p.sinkhorn(1)
@@ -368,14 +431,31 @@ def bench_batched(mot, W, count=256, sweeps=20):
     torch.cuda.synchronize()
     seq = (time.perf_counter() - t2) / 5 * count / 32
     products = sum(2 * (x.K - 1) for x in insts)
+    # oracle parity on the cheapest instances (pairs per sweep ~ (K - 1) N^2)
+    cheap = sorted(range(count), key=lambda i: (insts[i].K - 1) * insts[i].sizes[0] ** 2)[:parity_count]
+    for i in cheap:
+        plans[i].set_scalings([np.ones(n) for n in insts[i].sizes])
+    batch.sinkhorn(parity_sweeps)
+    errs = []
+    for i in cheap:
+        x = insts[i]
+        ophi, _, _, _ = oracle.tree_sinkhorn(x.points, x.weights, x.parent, x.eta, parity_sweeps)
+        g, og = gauge_fix(plans[i].scalings(), x.weights), gauge_fix(ophi, x.weights)
+        errs.append(max(float(np.max(np.abs(a - b) / np.abs(b))) for a, b in zip(g, og)))
+    launches = batch.launches()
     batch.close()
     for p in plans:
         p.close()
+    achieved = flops / dt / 1e12
     return {"workload": "%d tree instances, K~U{3..12}, N log-uniform [1e3,5e4], d~U{1,2,3}, "
                         "eta~U(0.02,0.2), Pruefer trees, Dirichlet(1) weights" % count,
             "instance_sweeps_per_s": count / dt, "ms_per_batched_sweep": dt * 1e3,
-            "products_per_batched_sweep": products,
-            "sequential_instance_sweeps_per_s_est": count / seq, "plan_create_s": t_plans}
+            "products_per_batched_sweep": products, "launches_per_batched_sweep": launches,
+            "spread_interp_TFLOPs_per_s": achieved, "spread_interp_frac_of_fp32_mfma_peak": achieved / PEAK_FP32_TFLOPS,
+            "sequential_instance_sweeps_per_s_est": count / seq, "plan_create_s": t_plans,
+            "oracle_parity": {"instances": cheap, "sweeps": parity_sweeps,
+                              "phi_gauge_fixed_max_rel_err": max(errs),
+                              "per_instance": [round(e, 10) for e in errs]}}
 
 
 def bench_serving(mot, W, count=300, rate=16.0, n_max=200000, circle_n_max=1500, max_sweeps=20000):
@@ -465,7 +545,8 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     from paper_2208_03120_amd import mot, workloads as W
 
-    extras = [("circle", bench_circle), ("batched", bench_batched), ("serving", bench_serving),
+    extras = [("config1", bench_config1), ("circle", bench_circle), ("batched", bench_batched),
+              ("serving", bench_serving),
               ("error_vs_M", bench_error_vs_M), ("truncated", bench_truncated),
               ("barycenter", bench_barycenter), ("euler_flow", bench_euler_flow)]
     if args.only:

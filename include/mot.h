@@ -318,6 +318,8 @@ int mot_plan_get_order(mot_plan plan, int32_t k, int32_t *perm_out, int32_t ptr_
 typedef struct mot_batch_s *mot_batch;
 int mot_batch_create(mot_batch *out, mot_plan *plans, int32_t count);
 int mot_batch_sinkhorn(mot_batch batch, int32_t sweeps, int32_t use_graph);
+/* Kernel launches of one batched sweep (the nodes of its graph), for reporting. */
+int mot_batch_launches(mot_batch batch);
 int mot_batch_destroy(mot_batch batch);
 
 /* ---- serving form ------------------------------------------------------------------

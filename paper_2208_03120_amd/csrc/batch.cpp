@@ -78,6 +78,12 @@ int mot_batch_create(mot_batch *out, mot_plan *plans, int32_t count)
     return MOT_OK;
 }
 
+int mot_batch_launches(mot_batch B)
+{
+    if (!B) return MOT_EINVAL;
+    return (int)B->sweep.size();
+}
+
 int mot_batch_sinkhorn(mot_batch B, int32_t sweeps, int32_t use_graph)
 {
     if (!B || sweeps < 0) return MOT_EINVAL;

@@ -92,7 +92,7 @@ EXPORTED = ["mot_plan_create", "mot_plan_create_tree", "mot_plan_create_circle",
             "mot_get_scalings", "mot_set_scalings", "mot_apply_kernel", "mot_plan_get_info",
             "mot_plan_footprint", "mot_plan_destroy", "mot_strerror", "mot_bin_points",
             "mot_plan_profile", "mot_plan_get_order", "mot_bin_points_noalloc",
-            "mot_batch_create", "mot_batch_sinkhorn", "mot_batch_destroy", "mot_server_create",
+            "mot_batch_create", "mot_batch_sinkhorn", "mot_batch_launches", "mot_batch_destroy", "mot_server_create",
             "mot_server_submit", "mot_server_run", "mot_server_fetch", "mot_server_clock",
             "mot_server_destroy"]
 
@@ -153,6 +153,7 @@ def _load():
                                                   _ip, _vp]),
         "mot_batch_create": (ctypes.c_int, [_P(_vp), _P(_vp), ctypes.c_int32]),
         "mot_batch_sinkhorn": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32]),
+        "mot_batch_launches": (ctypes.c_int, [_vp]),
         "mot_batch_destroy": (ctypes.c_int, [_vp]),
         "mot_server_create": (ctypes.c_int, [_P(_vp), ctypes.c_size_t, ctypes.c_int32, _vp]),
         "mot_server_submit": (ctypes.c_int, [_vp, _P(Request), _P(ctypes.c_uint64)]),
@@ -476,6 +477,10 @@ class Batch:
     def sinkhorn(self, sweeps, use_graph=True):
         return _check(_lib.mot_batch_sinkhorn(self._h, int(sweeps), int(bool(use_graph))),
                       "mot_batch_sinkhorn")
+
+    def launches(self):
+        """Kernel launches of one batched sweep."""
+        return _check(_lib.mot_batch_launches(self._h), "mot_batch_launches")
 
     def close(self):
         if self._h:
