@@ -458,65 +458,110 @@ def bench_batched(mot, W, count=256, sweeps=20, parity_count=16, parity_sweeps=2
                               "per_instance": [round(e, 10) for e in errs]}}
 
 
-def bench_serving(mot, W, count=300, rate=16.0, n_max=200000, circle_n_max=1500, max_sweeps=20000):
-    """Poisson request stream (80 % tree NFFT / 20 % circle dense split-BF16), K ~ U{3..16},
-    N log-uniform [500, n_max] (circles capped at circle_n_max: their products are N x N),
-    d in {2,3}, eta log-uniform [0.01, 0.3]; each request is solved until the L1 error of
-    its first marginal is <= 1e-6 (at most max_sweeps sweeps).  The rate is below the
-    server's capacity, so latencies are solve times plus short admission waits."""
+def bench_serving(mot, W, count=2000, warmup=200, load=0.7, n_max=200000, max_sweeps=20000,
+                  budget=64 << 30, request_cap=2 << 30, deadline_s=420.0):
+    """Serving: 80 % tree (NFFT) / 20 % circle (dense split BF16) requests, K ~ U{3..16},
+    N log-uniform [500, n_max] for both, d in {2,3}, eta log-uniform [0.01, 0.3], Dirichlet
+    weights; each solved until the L1 error of its first marginal is <= 1e-6 (at most
+    max_sweeps sweeps).  Admission by device footprint: 64 GiB for the resident problems
+    together, 2 GiB per request (circles hold K N^2 matrices, so large circles are refused
+    with MOT_ENOMEM and counted).  The first `warmup` requests are submitted at once; their
+    completion rate is the measured capacity.  The remaining requests then arrive as a
+    Poisson stream at `load` times that capacity (the seeded stream's unit-rate gaps scaled
+    by the rate); latencies (completion - submission) and throughput are taken over them."""
     import threading
-    stream = W.request_stream(seed=5, count=count, rate=rate, n_range=(500, n_max),
-                              circle_n_max=circle_n_max)
-    srv = mot.Server(hbm_budget=64 << 30, max_slots=64)
+    stream = W.request_stream(seed=5, count=count, rate=1.0, n_range=(500, n_max))
+    srv = mot.Server(hbm_budget=budget, max_slots=64, max_request_bytes=request_cap)
     tickets = [None] * count
-    t_start = srv.clock()
-
-    def feeder():
-        for i, (t_arr, inst) in enumerate(stream):
-            wait = t_start + t_arr - srv.clock()
-            if wait > 0:
-                time.sleep(wait)
-            path = mot.DENSE if inst.topology == W.CIRCLE else mot.NFFT
-            rc, t = srv.submit(inst, path=path, tol=1e-6, max_sweeps=max_sweeps)
-            tickets[i] = t if rc == mot.OK else rc
-
-    th = threading.Thread(target=feeder)
-    th.start()
     results = {}
-    deadline = time.time() + 240
-    while time.time() < deadline:
-        srv.run(0.05, idle_exit=False)
+    t_start = time.time()
+
+    def submit(i):
+        inst = stream[i][1]
+        path = mot.DENSE if inst.topology == W.CIRCLE else mot.NFFT
+        rc, t = srv.submit(inst, path=path, tol=1e-6, max_sweeps=max_sweeps)
+        tickets[i] = t if rc == mot.OK else rc
+
+    def collect():
         for i, t in enumerate(tickets):
             if t is not None and t > 0 and i not in results:
                 r = srv.fetch(t)
                 if r is not None:
                     results[i] = r
-        if not th.is_alive() and len(results) == sum(1 for t in tickets if t is not None and t > 0):
+
+    def accepted(lo, hi):
+        return [i for i in range(lo, hi) if tickets[i] is not None and tickets[i] > 0]
+
+    last_note = [time.time()]
+
+    def progress(phase):
+        if time.time() - last_note[0] > 15.0:
+            last_note[0] = time.time()
+            print("serving %s: %d of %d requests done, %.0f s" % (phase, len(results), count, time.time() - t_start),
+                  file=sys.stderr, flush=True)
+
+    for i in range(warmup):
+        submit(i)
+    while time.time() - t_start < deadline_s:
+        srv.run(0.05, idle_exit=False)
+        collect()
+        progress("warm-up")
+        if all(i in results for i in accepted(0, warmup)):
+            break
+    warm = [results[i] for i in accepted(0, warmup) if i in results]
+    capacity = len(warm) / (max(r["t_done"] for r in warm) - min(r["t_submit"] for r in warm))
+    rate = load * capacity
+    base = srv.clock()
+    t_prev = stream[warmup - 1][0]
+
+    def feeder():
+        for i in range(warmup, count):
+            wait = base + (stream[i][0] - t_prev) / rate - srv.clock()
+            if wait > 0:
+                time.sleep(wait)
+            submit(i)
+
+    th = threading.Thread(target=feeder)
+    th.start()
+    while time.time() - t_start < deadline_s:
+        srv.run(0.05, idle_exit=False)
+        collect()
+        progress("stream")
+        if not th.is_alive() and all(i in results for i in accepted(warmup, count)):
             break
     th.join()
+    collect()
     srv.close()
-    warm = count // 10  # the first tenth of the requests warms the server up
-    lat = np.array([r["t_done"] - r["t_submit"] for i, r in results.items() if i >= warm])
-    ok = sum(1 for r in results.values() if r["status"] == mot.OK)
-    maxit = sum(1 for r in results.values() if r["status"] == mot.MAXITER)
-    span = max(r["t_done"] for r in results.values()) - min(r["t_submit"] for r in results.values())
-    refused = sum(1 for t in tickets if t is not None and t < 0)
+    meas = [i for i in accepted(warmup, count) if i in results]
+    lat = np.array([results[i]["t_done"] - results[i]["t_submit"] for i in meas])
+    span = max(results[i]["t_done"] for i in meas) - min(results[i]["t_submit"] for i in meas)
+    st = [results[i]["status"] for i in meas]
+    refused = [i for i in range(count) if tickets[i] is not None and tickets[i] < 0]
+    circ = [i for i in range(count) if stream[i][1].topology == W.CIRCLE]
     fails = []
-    for i, r in sorted(results.items()):
+    for i in meas:
+        r = results[i]
         if r["status"] not in (mot.OK, mot.MAXITER):
             inst = stream[i][1]
             fails.append({"request": i, "K": inst.K, "N": int(inst.sizes[0]), "d": int(inst.points[0].shape[1]),
                           "eta": round(inst.eta, 5), "circle": inst.topology == W.CIRCLE,
                           "status": int(r["status"]), "sweeps": int(r["sweeps"])})
-    return {"workload": "Poisson %.0f req/s, %d requests, 80%% tree / 20%% circle, K~U{3..16}, "
-                        "N log-uniform [500,%d] (circle N <= %d), d in {2,3}, eta log-uniform "
-                        "[0.01,0.3], tol 1e-6, at most %d sweeps" % (rate, count, n_max, circle_n_max,
-                                                                     max_sweeps),
-            "rate_req_per_s": rate, "warmup_requests_excluded": warm,
-            "completed": len(results), "converged": ok, "max_sweeps_reached": maxit,
-            "failed": len(results) - ok - maxit, "failures": fails, "refused": refused,
+    return {"workload": "%d requests (first %d warm-up, submitted at once), 80%% tree NFFT / 20%% circle dense "
+                        "split BF16, K~U{3..16}, N log-uniform [500,%d], d in {2,3}, eta log-uniform [0.01,0.3], "
+                        "tol 1e-6, at most %d sweeps; budget %d GiB, %d GiB per request"
+                        % (count, warmup, n_max, max_sweeps, budget >> 30, request_cap >> 30),
+            "measured_capacity_solves_per_s": capacity, "load": load, "rate_req_per_s": rate,
+            "warmup_requests_excluded": warmup, "measured_requests": count - warmup,
+            "completed": len(meas), "converged": st.count(mot.OK), "max_sweeps_reached": st.count(mot.MAXITER),
+            "failed": len(meas) - st.count(mot.OK) - st.count(mot.MAXITER), "failures": fails[:20],
+            "refused": len(refused), "refused_circles": sum(1 for i in refused if i in circ),
+            "circles_submitted": len(circ),
+            "largest_circle_n_admitted": max([int(stream[i][1].sizes[0]) for i in circ if tickets[i] is not None
+                                              and tickets[i] > 0] or [0]),
+            "smallest_circle_n_refused": min([int(stream[i][1].sizes[0]) for i in refused if i in circ] or [0]),
+            "unfinished_at_deadline": len(accepted(warmup, count)) - len(meas),
             "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
-            "solves_per_s": len(results) / span}
+            "solves_per_s": len(meas) / span, "wall_s": time.time() - t_start}
 
 
 def main():

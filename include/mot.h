@@ -324,11 +324,17 @@ int mot_batch_destroy(mot_batch batch);
 
 /* ---- serving form ------------------------------------------------------------------
  * A continuous-batching solver service on one GPU.  Requests (complete MOT
- * problems) are admitted when their device footprint fits the HBM budget and a
- * slot is free; admitted problems stay resident and advance together, one
- * batched sweep at a time, until each meets its stopping test; finished ones
- * leave and waiting ones enter between sweeps.  Requests that can never fit
- * are refused with MOT_ENOMEM at submission. */
+ * problems) are admitted in FIFO order when their device footprint fits the HBM budget
+ * and a slot is free; a preparation thread builds their plans (on a stream of its own)
+ * while the resident problems keep sweeping.  Resident problems stay on the device and
+ * advance a few sweeps per service step -- tree problems together through one batched
+ * schedule (rebuilt by the preparation thread when the resident set changes), each
+ * circle problem on a stream of its own, overlapping the tree launches -- until each
+ * meets its stopping test; finished ones leave and waiting ones enter between steps.
+ * Plans and schedules take device memory from a pool of the server's, so finishing a
+ * request frees nothing back to the runtime while others run.  A request's results do not
+ * depend on which others share the device.  Requests whose footprint exceeds the
+ * per-request limit are refused with MOT_ENOMEM at submission. */
 typedef struct mot_server_s *mot_server;
 typedef struct {
     int32_t K, d, topology;
@@ -349,7 +355,12 @@ typedef struct {
     double t_submit, t_admit, t_done; /* seconds on the server's monotonic clock       */
 } mot_result;
 
-int mot_server_create(mot_server *out, size_t hbm_budget, int32_t max_slots, void *stream);
+/* hbm_budget: device bytes the resident problems may hold together (admission);
+ * max_request_bytes: largest footprint a single request may have (0 = hbm_budget);
+ * max_slots: resident problems at most; stream: the tree batch's stream (NULL = a
+ * non-blocking stream the server creates). */
+int mot_server_create(mot_server *out, size_t hbm_budget, size_t max_request_bytes, int32_t max_slots,
+                      void *stream);
 /* Queue a request (copied).  *ticket identifies it.  Thread-safe. */
 int mot_server_submit(mot_server srv, const mot_request *req, uint64_t *ticket);
 /* Run the service loop for at most `seconds` (or until idle when idle_exit != 0).

@@ -33,7 +33,10 @@ int mot_batch_destroy(mot_batch B)
     return MOT_OK;
 }
 
-int mot_batch_create(mot_batch *out, mot_plan *plans, int32_t count)
+}  // extern "C"
+
+// A batch whose device memory comes from alloc (NULL: hipMalloc slabs).
+int mot::batch_create(mot_batch *out, mot_plan *plans, int32_t count, const mot_allocator *alloc)
 {
     if (!out || !plans || count < 1) return MOT_EINVAL;
     *out = nullptr;
@@ -42,6 +45,10 @@ int mot_batch_create(mot_batch *out, mot_plan *plans, int32_t count)
         if (plans[i]->device != plans[0]->device) return MOT_EINVAL;
     }
     mot_batch_s *B = new mot_batch_s();
+    if (alloc && alloc->alloc && alloc->free) {
+        B->arena.alloc = *alloc;
+        B->arena.custom = true;
+    }
     B->plans.assign(plans, plans + count);
     B->stream = plans[0]->stream;
     std::vector<ProdJob> pj;
@@ -76,6 +83,21 @@ int mot_batch_create(mot_batch *out, mot_plan *plans, int32_t count)
     }
     *out = B;
     return MOT_OK;
+}
+
+// Enqueue sweeps of the batch on its stream without waiting for them (no graph).
+int mot::batch_enqueue(mot_batch B, int sweeps)
+{
+    for (int r = 0; r < sweeps; ++r) MOT_TRY(run_steps(B->sweep, B->stream));
+    for (mot_plan_s *P : B->plans) P->host_sweeps += sweeps;
+    return MOT_OK;
+}
+
+extern "C" {
+
+int mot_batch_create(mot_batch *out, mot_plan *plans, int32_t count)
+{
+    return batch_create(out, plans, count, nullptr);
 }
 
 int mot_batch_launches(mot_batch B)

@@ -1049,7 +1049,7 @@ size_t circle_footprint(int K, const int64_t *n, int path, int precision)
         b += (size_t)ldmax * ldmax * 2 * (2 * (K - 2)) * parts;  // kernel matrices
         b += (size_t)n1 * ldmax * 2 * parts;                       // scaled left operand
     }
-    else b += (size_t)n1 * ldmax * 8 + (size_t)n1 * (64 * 1024);
+    else b += (size_t)n1 * ldmax * 8 + (size_t)n1 * 8;  // product sources, row exponents
     return b;
 }
 

@@ -273,5 +273,8 @@ int circle_marginals(mot_plan_s *P, double *P_sorted_all);
 int circle_pair_marginal(mot_plan_s *P, int k, double *out);
 void circle_destroy(mot_plan_s *P);
 size_t circle_footprint(int K, const int64_t *n, int path, int precision);
+// batch.cpp: a batch on an allocator of the caller's; sweeps enqueued without a wait
+int batch_create(mot_batch *out, mot_plan *plans, int32_t count, const mot_allocator *alloc);
+int batch_enqueue(mot_batch B, int sweeps);
 const float2 *device_twiddle(int n);
 }  // namespace mot

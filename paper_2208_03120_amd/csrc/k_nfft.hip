@@ -127,7 +127,7 @@ __global__ void keys_to_perm_kernel(int64_t npts, int64_t ntiles, const uint64_t
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < npts) perm[i] = (int32_t)(keys[i] & 0xffffffffull);
-    if (i <= ntiles) {
+    if (tile_off != nullptr && i <= ntiles) {
         int64_t lo = 0, hi = npts;  // first position with tile >= i in [lo, hi]
         while (lo < hi) {
             const int64_t mid = (lo + hi) >> 1;
@@ -138,6 +138,53 @@ __global__ void keys_to_perm_kernel(int64_t npts, int64_t ntiles, const uint64_t
         }
         tile_off[i] = (int32_t)lo;
     }
+}
+
+// Sorted ranges of the tiles of an active box after stable_tile_sort (whose sorted keys are
+// still in the scratch buffer): box tile b (row-major over nt[0] x nt[1] x nt[2] tiles,
+// coordinate 0 slowest, offset by t0 in the grid of tpd tiles per dimension) holds sorted
+// positions [lo[b], hi[b]).  Binary searches as in keys_to_perm_kernel.
+__global__ void box_tile_ranges_kernel(int64_t npts, const uint64_t *__restrict__ keys, int shift, int d, int tpd,
+                                       int t00, int t01, int t02, int nt0, int nt1, int nt2, int64_t nbox,
+                                       int32_t *__restrict__ lo, int32_t *__restrict__ hi)
+{
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nbox) return;
+    const int t0[3] = {t00, t01, t02}, nt[3] = {nt0, nt1, nt2};
+    int tc[3] = {0, 0, 0};
+    int64_t rem = b;
+    for (int c = d - 1; c >= 0; --c) {
+        tc[c] = (int)(rem % nt[c]);
+        rem /= nt[c];
+    }
+    int64_t gt = 0;
+    for (int c = 0; c < d; ++c) gt = gt * tpd + (t0[c] + tc[c]);
+    int64_t out[2];
+    for (int q = 0; q < 2; ++q) {
+        int64_t a = 0, e = npts;
+        while (a < e) {
+            const int64_t mid = (a + e) >> 1;
+            if ((int64_t)(keys[mid] >> shift) < gt + q)
+                a = mid + 1;
+            else
+                e = mid;
+        }
+        out[q] = a;
+    }
+    lo[b] = (int32_t)out[0];
+    hi[b] = (int32_t)out[1];
+}
+
+hipError_t launch_box_tile_ranges(int64_t npts, const void *scratch, bool sub_keyed, int d, int tpd, const int *t0,
+                                  const int *nt, int32_t *lo, int32_t *hi, hipStream_t st)
+{
+    int64_t nbox = 1;
+    for (int c = 0; c < d; ++c) nbox *= nt[c];
+    if (nbox == 0) return hipSuccess;
+    hipLaunchKernelGGL(box_tile_ranges_kernel, dim3((unsigned)((nbox + 255) / 256)), dim3(256), 0, st, npts,
+                       (const uint64_t *)scratch, sub_keyed ? 32 + kSubBits : 32, d, tpd, t0[0], d > 1 ? t0[1] : 0,
+                       d > 2 ? t0[2] : 0, nt[0], d > 1 ? nt[1] : 1, d > 2 ? nt[2] : 1, nbox, lo, hi);
+    return hipGetLastError();
 }
 
 size_t stable_tile_sort_scratch(int64_t npts, int64_t /*ntiles*/)

@@ -179,6 +179,11 @@ size_t stable_tile_sort_scratch(int64_t npts, int64_t ntiles);
 hipError_t stable_tile_sort(int64_t npts, const int32_t *tile, int64_t ntiles, int32_t *perm,
                             int32_t *tile_off, void *scratch, size_t scratch_bytes, hipStream_t st,
                             const int32_t *cell = nullptr, int d = 0, int sub_dim = 0, int T = 1);
+// tile_off may be NULL (only perm is written).  After the sort, the sorted ranges of the
+// tiles of an active box (t0 first tile, nt tiles per dimension, row-major) from the keys
+// still in the scratch buffer: [lo[b], hi[b]).
+hipError_t launch_box_tile_ranges(int64_t npts, const void *scratch, bool sub_keyed, int d, int tpd, const int *t0,
+                                  const int *nt, int32_t *lo, int32_t *hi, hipStream_t st);
 // Window rows of sorted points (n x d x 16 FP32), Kaiser-Bessel shape parameter b.
 hipError_t launch_window_rows(int d, int64_t npts, const double *pts, double s, const double *o, int T,
                               int m, double b, float *rows, hipStream_t st);

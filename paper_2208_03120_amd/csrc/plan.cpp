@@ -725,10 +725,11 @@ static Extent extent_of(int d, const std::vector<double> &pts, int64_t total)
     return E;
 }
 
-// Bin one marginal's points (original order, device) and build its binned layout.
+// Bin one marginal's points (original order, device) and build its binned layout.  The
+// temporaries (sort keys in scratch, cells, tile ids, box tile ranges) belong to the caller.
 static int bin_marginal(mot_plan_s *P, int k, const double *pts_orig_dev, void *scratch,
                         size_t scratch_bytes, int32_t *cell_tmp, int32_t *tile_tmp,
-                        int32_t *tile_off_dev, std::vector<int32_t> &tile_off_host)
+                        int32_t *box_lo, int32_t *box_hi)
 {
     MargDev &G = P->marg[k];
     const NfftParams &Q = P->P;
@@ -742,32 +743,27 @@ static int bin_marginal(mot_plan_s *P, int k, const double *pts_orig_dev, void *
     // of spreading and interpolation then mostly hold points with the same window support
     // in that dimension, and the steps outside it are skipped.
     const bool sub = d == 3 && T > 1 && ntiles < ((int64_t)1 << 28);
-    MOT_HIP(stable_tile_sort(G.n, tile_tmp, ntiles, G.perm, tile_off_dev, scratch, scratch_bytes,
+    MOT_HIP(stable_tile_sort(G.n, tile_tmp, ntiles, G.perm, nullptr, scratch, scratch_bytes,
                              P->stream, sub ? cell_tmp : nullptr, d, 1, T));
     MOT_HIP(launch_gather_rows(pts_orig_dev, G.perm, G.n, d, G.pts, P->stream));
     MOT_HIP(launch_window_rows(d, G.n, G.pts, Q.s, Q.o, T, Q.m, Q.kb_b, G.win, P->stream));
-    tile_off_host.resize(ntiles + 1);
-    MOT_HIP(hipMemcpyAsync(tile_off_host.data(), tile_off_dev, (ntiles + 1) * sizeof(int32_t),
-                           hipMemcpyDeviceToHost, P->stream));
+    // sorted ranges of the active box's tiles only (the box is a small part of the grid)
+    int64_t nbox = 1;
+    for (int c = 0; c < d; ++c) nbox *= Q.ntile[c];
+    MOT_HIP(launch_box_tile_ranges(G.n, scratch, sub, d, tpd, Q.tmin, Q.ntile, box_lo, box_hi, P->stream));
+    std::vector<int32_t> lo_h(nbox), hi_h(nbox);
+    MOT_HIP(hipMemcpyAsync(lo_h.data(), box_lo, nbox * sizeof(int32_t), hipMemcpyDeviceToHost, P->stream));
+    MOT_HIP(hipMemcpyAsync(hi_h.data(), box_hi, nbox * sizeof(int32_t), hipMemcpyDeviceToHost, P->stream));
     MOT_HIP(hipStreamSynchronize(P->stream));
     // Chunks over the box tiles in row-major order (coordinate 0 slowest).  Box tiles in
     // that order are a monotone subsequence of the global tile order the points are
     // sorted by, and every point lies in a box tile, so consecutive chunks are
     // consecutive ranges of the sorted points: chunk c = [starts[c], starts[c+1]).
-    int64_t nbox = 1;
-    for (int c = 0; c < d; ++c) nbox *= Q.ntile[c];
     std::vector<int32_t> starts, tiles, tch2;
     tch2.push_back(0);
     int64_t covered = 0;
     for (int64_t bt = 0; bt < nbox; ++bt) {
-        int64_t rem = bt, gt = 0;
-        int tc[3] = {0, 0, 0};
-        for (int c = d - 1; c >= 0; --c) {
-            tc[c] = (int)(rem % Q.ntile[c]);
-            rem /= Q.ntile[c];
-        }
-        for (int c = 0; c < d; ++c) gt = gt * tpd + (Q.tmin[c] + tc[c]);
-        const int a = tile_off_host[gt], b = tile_off_host[gt + 1];
+        const int a = lo_h[bt], b = hi_h[bt];
         if (a != covered && b > a) return MOT_EDOMAIN;
         for (int s = a; s < b; s += Q.chunk) {
             starts.push_back(s);
@@ -946,8 +942,23 @@ int mot::setup_marginals(mot_plan_s *P, const std::vector<double> &pts_h, const 
         log_msg("truncation: eps=%.3g r_c=%.6g h=%.6g cells=%d^%d w=%d", P->TP.eps, P->TP.rc, P->TP.h,
                 P->TP.nc, d, P->TP.w);
     }
+    // temporaries of plan creation (points and weights in the caller's order, binning
+    // scratch) come from an arena of their own: with the plan's allocator, released once
+    // the plan's stream has finished with them, on every return path
+    struct TmpArena {
+        Arena a;
+        hipStream_t st = nullptr;
+        ~TmpArena()
+        {
+            if (st) (void)hipStreamSynchronize(st);
+            a.release();
+        }
+    } tmp;
+    tmp.a.alloc = P->arena.alloc;
+    tmp.a.custom = P->arena.custom;
+    tmp.st = P->stream;
     double *pts_dev = nullptr;
-    MOT_TRY(P->arena.get_n(pts_h.size(), &pts_dev));
+    MOT_TRY(tmp.a.get_n(pts_h.size(), &pts_dev));
     MOT_HIP(hipMemcpy(pts_dev, pts_h.data(), pts_h.size() * sizeof(double), hipMemcpyHostToDevice));
     P->marg.resize(K);
     int total_partials = 0;
@@ -974,19 +985,21 @@ int mot::setup_marginals(mot_plan_s *P, const std::vector<double> &pts_h, const 
     }
     if (P->path == MOT_NFFT) {
         const int tpd = (P->P.n + P->P.T - 1) / P->P.T;
-        int64_t ntiles = 1;
-        for (int c = 0; c < d; ++c) ntiles *= tpd;
+        int64_t ntiles = 1, nbox = 1;
+        for (int c = 0; c < d; ++c) {
+            ntiles *= tpd;
+            nbox *= P->P.ntile[c];
+        }
         const size_t sb = stable_tile_sort_scratch(nmax, ntiles);
         void *scratch = nullptr;
-        int32_t *cell_tmp = nullptr, *tile_tmp = nullptr, *toff = nullptr;
-        MOT_TRY(P->arena.get(sb, &scratch));
-        MOT_TRY(P->arena.get_n((size_t)nmax * d, &cell_tmp));
-        MOT_TRY(P->arena.get_n((size_t)nmax, &tile_tmp));
-        MOT_TRY(P->arena.get_n((size_t)ntiles + 1, &toff));
-        std::vector<int32_t> toff_h;
+        int32_t *cell_tmp = nullptr, *tile_tmp = nullptr, *blo = nullptr, *bhi = nullptr;
+        MOT_TRY(tmp.a.get(sb, &scratch));
+        MOT_TRY(tmp.a.get_n((size_t)nmax * d, &cell_tmp));
+        MOT_TRY(tmp.a.get_n((size_t)nmax, &tile_tmp));
+        MOT_TRY(tmp.a.get_n((size_t)nbox, &blo));
+        MOT_TRY(tmp.a.get_n((size_t)nbox, &bhi));
         for (int k = 0; k < K; ++k)
-            MOT_TRY(bin_marginal(P, k, pts_dev + P->off[k] * d, scratch, sb, cell_tmp, tile_tmp, toff,
-                                 toff_h));
+            MOT_TRY(bin_marginal(P, k, pts_dev + P->off[k] * d, scratch, sb, cell_tmp, tile_tmp, blo, bhi));
     } else if (P->path == MOT_TRUNC) {
         // a1's binning with tile edge 1: points sorted by cell, cell ranges kept
         const TruncParams &T = P->TP;
@@ -994,9 +1007,9 @@ int mot::setup_marginals(mot_plan_s *P, const std::vector<double> &pts_h, const 
         const size_t sb = stable_tile_sort_scratch(nmax, ncell);
         void *scratch = nullptr;
         int32_t *cell_tmp = nullptr, *tile_tmp = nullptr;
-        MOT_TRY(P->arena.get(sb, &scratch));
-        MOT_TRY(P->arena.get_n((size_t)nmax * d, &cell_tmp));
-        MOT_TRY(P->arena.get_n((size_t)nmax, &tile_tmp));
+        MOT_TRY(tmp.a.get(sb, &scratch));
+        MOT_TRY(tmp.a.get_n((size_t)nmax * d, &cell_tmp));
+        MOT_TRY(tmp.a.get_n((size_t)nmax, &tile_tmp));
         const double sc = 1.0 / T.h;
         double o[3] = {0.0, 0.0, 0.0};
         for (int c = 0; c < d; ++c) o[c] = -T.glo[c] * sc;
@@ -1023,7 +1036,7 @@ int mot::setup_marginals(mot_plan_s *P, const std::vector<double> &pts_h, const 
         }
     }
     double *w_dev = nullptr;
-    MOT_TRY(P->arena.get_n(w_h.size(), &w_dev));
+    MOT_TRY(tmp.a.get_n(w_h.size(), &w_dev));
     MOT_HIP(hipMemcpy(w_dev, w_h.data(), w_h.size() * sizeof(double), hipMemcpyHostToDevice));
     for (int k = 0; k < K; ++k) {
         MOT_HIP(launch_gather_rows(w_dev + P->off[k], P->marg[k].perm, P->n[k], 1, P->marg[k].mu, P->stream));
@@ -1705,6 +1718,38 @@ int mot_plan_footprint(int32_t K, int32_t d, const int64_t *n, int32_t topology,
     b += (size_t)total * (8 * d + 4 + 8 * 7 + (path == MOT_NFFT ? 64 * d : 0));
     if (topology == MOT_CIRCLE) {
         b += circle_footprint(K, n, path, precision);
+        if (path == MOT_NFFT) {
+            // row-by-row fast sums: every row of a product is one job with its own patches,
+            // grid and spectra (shared by the product positions), and every position has
+            // its job table and launch item arrays
+            Extent E;
+            for (int c = 0; c < d; ++c) {
+                E.lo[c] = -half_width;
+                E.hi[c] = half_width;
+            }
+            E.diag = 2.0 * half_width * std::sqrt((double)d);
+            NfftParams Q;
+            int rc = resolve_params(d, eta, E, fs, nmax, &Q);
+            if (rc < 0) return rc;
+            int64_t cells = 1, pe = 1, tiles = 1;
+            for (int c = 0; c < d; ++c) {
+                cells *= Q.L[c];
+                pe *= Q.W;
+                tiles *= Q.ntile[c];
+            }
+            const int H = Q.M + 1, B = 2 * Q.M + 1;
+            int64_t spec = H;
+            if (d == 2) spec = (int64_t)H * Q.L[0];
+            if (d == 3) spec = (int64_t)H * Q.L[0] * std::max(Q.L[1], B);
+            const int64_t maxc = tiles + nmax / std::max(1, Q.chunk) + 1;
+            const int64_t n1 = n[0];
+            b += (size_t)n1 * ((size_t)maxc * pe * 4 + (size_t)cells * 4 + (size_t)spec * 16 + 3 * 256);
+            const int64_t fft_items = 3 * (int64_t)Q.L[0] + 2 * H + B + 8;
+            const int64_t per_job = (int64_t)sizeof(ProdJob) + 8 * 2 * maxc + 8 * (cells / kFoldCellsPerItem + 1) +
+                                    16 * fft_items;
+            b += (size_t)(2 * (K - 2)) * ((size_t)n1 * per_job + 16 * 256);
+            b += (size_t)(2 * (K - 2) + 1) * (64 * 1024);
+        }
     } else if (path == MOT_NFFT) {
         Extent E;
         for (int c = 0; c < d; ++c) {
@@ -1726,9 +1771,11 @@ int mot_plan_footprint(int32_t K, int32_t d, const int64_t *n, int32_t topology,
         if (d == 3) spec = (int64_t)H * Q.L[0] * std::max(Q.L[1], B);
         int64_t tiles = 1;
         for (int c = 0; c < d; ++c) tiles *= Q.ntile[c];
-        const int64_t chunks = tiles + total / std::max(1, Q.chunk) + K;
+        // every product job holds one patch per chunk of its source marginal: at most one
+        // chunk per non-empty tile plus one per Q.chunk points
+        const int64_t chunks_per_job = std::min(tiles, nmax) + nmax / std::max(1, Q.chunk) + 1;
         b += (size_t)(2 * (K - 1) + 1) * (cells * 4 + spec * 16);
-        b += (size_t)2 * chunks * pe * 4;
+        b += (size_t)(2 * (K - 1) + 1) * chunks_per_job * pe * 4;
         b += (size_t)H * B * B * 4;
     } else if (path == MOT_TRUNC) {
         Extent E;

@@ -155,7 +155,7 @@ def _load():
         "mot_batch_sinkhorn": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32]),
         "mot_batch_launches": (ctypes.c_int, [_vp]),
         "mot_batch_destroy": (ctypes.c_int, [_vp]),
-        "mot_server_create": (ctypes.c_int, [_P(_vp), ctypes.c_size_t, ctypes.c_int32, _vp]),
+        "mot_server_create": (ctypes.c_int, [_P(_vp), ctypes.c_size_t, ctypes.c_size_t, ctypes.c_int32, _vp]),
         "mot_server_submit": (ctypes.c_int, [_vp, _P(Request), _P(ctypes.c_uint64)]),
         "mot_server_run": (ctypes.c_int, [_vp, ctypes.c_double, ctypes.c_int32]),
         "mot_server_fetch": (ctypes.c_int, [_vp, ctypes.c_uint64, _P(Result), _dp]),
@@ -497,11 +497,11 @@ class Batch:
 class Server:
     """Continuous-batching solver service (mot_server_*)."""
 
-    def __init__(self, hbm_budget, max_slots=64, stream=None):
+    def __init__(self, hbm_budget, max_slots=64, stream=None, max_request_bytes=0):
+        """stream None: the server works on non-blocking streams of its own."""
         self._h = ctypes.c_void_p()
-        st = stream if stream is not None else current_stream()
-        _check(_lib.mot_server_create(ctypes.byref(self._h), int(hbm_budget), int(max_slots), st),
-               "mot_server_create")
+        _check(_lib.mot_server_create(ctypes.byref(self._h), int(hbm_budget), int(max_request_bytes),
+                                      int(max_slots), stream), "mot_server_create")
         self._keep = {}
 
     def submit(self, inst, path=NFFT, precision=None, tol=1e-6, max_sweeps=2000):

@@ -149,3 +149,43 @@ def test_server_serves_truncated_path_requests(mot):
         if p == mot.TRUNC:
             ophi, _, _, _ = oracle.tree_sinkhorn(q.points, q.weights, q.parent, q.eta, x["sweeps"])
             assert max_rel(gauge_fix(x["phi"], q.weights), gauge_fix(ophi, q.weights)) < 1e-5
+
+
+def test_footprint_bounds_plan_memory_across_the_serving_mix(mot):
+    """The footprint the server admits by is at least the device memory a plan holds once
+    built (plan memory from PyTorch's allocator, counted block by block), over request shapes
+    of the serving mix: trees through NFFT, direct and truncated paths, circles dense and
+    NFFT, d = 2 and 3, small and large eta."""
+    stream = W.request_stream(seed=13, count=24, n_range=(300, 6000), circle_n_max=900)
+    for _, q in stream:
+        circle = q.topology == W.CIRCLE
+        for path in ((mot.DENSE, mot.NFFT) if circle else (mot.NFFT, mot.DIRECT, mot.TRUNC)):
+            prec = mot.PREC_BF16X3 if path == mot.DENSE else mot.PREC_MIXED
+            hw = max(float(np.max(np.concatenate(q.points)[:, c]) - np.min(np.concatenate(q.points)[:, c])) / 2
+                     for c in range(q.d))
+            fp = mot.footprint(q.sizes, q.d, q.topology, path, prec, q.eta, half_width=hw)
+            try:
+                plan = mot.Plan(q.points, q.weights, q.topology, q.parent, q.eta, path=path, precision=prec)
+            except mot.MotError as e:  # e.g. a bandwidth the fast summation cannot reach
+                assert e.status in (mot.EDOMAIN, mot.EUNSUPPORTED), e
+                continue
+            held = plan.info()["device_bytes"]
+            plan.close()
+            assert held <= fp, (q.K, q.sizes[0], q.d, q.eta, circle, path, held, fp)
+
+
+def test_server_refuses_requests_above_the_per_request_limit(mot):
+    reqs = _requests()[:3]
+    fps = [mot.footprint(q.sizes, q.d, q.topology, mot.DENSE if q.topology == W.CIRCLE else mot.NFFT,
+                         mot.PREC_BF16X3 if q.topology == W.CIRCLE else mot.PREC_MIXED, q.eta) for q in reqs]
+    cap = sorted(fps)[1]  # admits the two smallest, refuses the largest
+    srv = mot.Server(hbm_budget=64 << 30, max_slots=8, max_request_bytes=cap)
+    out = [srv.submit(q, tol=1e-6, max_sweeps=100, path=(mot.DENSE if q.topology == W.CIRCLE else mot.NFFT))
+           for q in reqs]
+    for (rc, t), fp in zip(out, fps):
+        assert (rc == mot.ENOMEM) == (fp > cap)
+    srv.run(60.0, idle_exit=True)
+    for rc, t in out:
+        if rc == mot.OK:
+            assert srv.fetch(t) is not None
+    srv.close()
