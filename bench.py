@@ -394,18 +394,9 @@ def bench_circle(mot, W, sweeps=20, acc_sweeps=5):
     return res
 
 
-def bench_batched(mot, W, count=256, sweeps=20, parity_count=16, parity_sweeps=20):
-    """256 independent tree instances (K ~ U{3..12}, N log-uniform [1e3, 5e4], d ~ U{1,2,3},
-    random Pruefer trees, eta ~ U(0.02, 0.2), Dirichlet weights), autotuned NFFT
-    parameters, one captured graph per batched sweep.  Beside the rate: the launches of a
-    batched sweep, the spreading and interpolation work of the sweep (2 flop per window
-    tap, (2m)^d taps per point, both per product) against the FP32 MFMA peak, and the
-    gauge-fixed scaling error of the 16 cheapest instances against the FP64 oracle after
-    20 sweeps from phi = 1 (those plans restarted inside the batch)."""
+def _batched_sweeps(mot, W, insts, sweeps, stream):
+    """Plans for every instance, one batch, `sweeps` timed graph-launched batched sweeps."""
     import torch
-    import oracle
-    insts = [W.batched_instance(i) for i in range(count)]
-    stream = mot.current_stream()
     t0 = time.perf_counter()
     plans = [mot.Plan(x.points, x.weights, W.TREE, x.parent, x.eta, path=mot.NFFT, stream=stream)
              for x in insts]
@@ -418,9 +409,43 @@ def bench_batched(mot, W, count=256, sweeps=20, parity_count=16, parity_sweeps=2
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t1) / sweeps
     flops = 0.0
+    grids = {}
     for x, p in zip(insts, plans):
         info = p.info()
         flops += 2 * (x.K - 1) * 2 * 2.0 * (2 * info["m"]) ** info["d"] * x.sizes[0]
+        key = "d%d_n%d_m%d" % (info["d"], info["n"], info["m"])
+        grids[key] = grids.get(key, 0) + 1
+    return plans, batch, dt, flops, t_plans, dict(sorted(grids.items()))
+
+
+def bench_batched(mot, W, count=256, sweeps=20, parity_count=16, parity_sweeps=20):
+    """256 independent tree instances (K ~ U{3..12}, N log-uniform [1e3, 5e4], d ~ U{1,2,3},
+    random Pruefer trees, eta ~ U(0.02, 0.2), Dirichlet weights), autotuned NFFT
+    parameters, one captured graph per batched sweep.  The batch is timed twice: with the
+    autotuner's analytic cost model and with the cost table measured on this GPU
+    (mot_tune_measure), which then stays the reported configuration.  Beside the rate: the
+    launches of a batched sweep, the spreading and interpolation work of the sweep (2 flop
+    per window tap, (2m)^d taps per point, both per product) against the FP32 MFMA peak,
+    the (d, n, m) the tuner chose, and the gauge-fixed scaling error of the 16 cheapest
+    instances against the FP64 oracle after 20 sweeps from phi = 1 (those plans restarted
+    inside the batch)."""
+    import torch
+    import oracle
+    insts = [W.batched_instance(i) for i in range(count)]
+    stream = mot.current_stream()
+    # analytic cost model
+    mot.tune_install(None)
+    plans, batch, dt_model, flops_model, _, grids_model = _batched_sweeps(mot, W, insts, sweeps, stream)
+    batch.close()
+    for p in plans:
+        p.close()
+    # measured cost table
+    table = mot.tune_measure()
+    mot.tune_install(table)
+    try:
+        plans, batch, dt, flops, t_plans, grids = _batched_sweeps(mot, W, insts, sweeps, stream)
+    finally:
+        mot.tune_install(None)
     # the same plans one after another (each with its own captured graph)
     for p in plans[:32]:
         p.sinkhorn(1)
@@ -450,8 +475,19 @@ def bench_batched(mot, W, count=256, sweeps=20, parity_count=16, parity_sweeps=2
     return {"workload": "%d tree instances, K~U{3..12}, N log-uniform [1e3,5e4], d~U{1,2,3}, "
                         "eta~U(0.02,0.2), Pruefer trees, Dirichlet(1) weights" % count,
             "instance_sweeps_per_s": count / dt, "ms_per_batched_sweep": dt * 1e3,
+            "tuner": "measured cost table",
             "products_per_batched_sweep": products, "launches_per_batched_sweep": launches,
             "spread_interp_TFLOPs_per_s": achieved, "spread_interp_frac_of_fp32_mfma_peak": achieved / PEAK_FP32_TFLOPS,
+            "grids_chosen": grids,
+            "analytic_model": {"instance_sweeps_per_s": count / dt_model, "ms_per_batched_sweep": dt_model * 1e3,
+                               "spread_interp_TFLOPs_per_s": flops_model / dt_model / 1e12,
+                               "grids_chosen": grids_model},
+            "tune_table": {"seconds": table.seconds,
+                           "point_ns_per_d_m2to8": [[round(table.point_ns[d][i], 3) for i in range(7)]
+                                                    for d in range(3)],
+                           "grid_us_per_d_n16to512": [[round(table.grid_us[d][k], 3) for k in range(6)]
+                                                      for d in range(3)],
+                           "box_cells": [[table.box_cells[d][k] for k in range(6)] for d in range(3)]},
             "sequential_instance_sweeps_per_s_est": count / seq, "plan_create_s": t_plans,
             "oracle_parity": {"instances": cheap, "sweeps": parity_sweeps,
                               "phi_gauge_fixed_max_rel_err": max(errs),

@@ -266,6 +266,47 @@ typedef struct {
 } mot_step_timing;
 int mot_plan_profile(mot_plan plan, int32_t sweeps, mot_step_timing *out, int32_t max_out);
 
+/* ---- measured autotuner (Sec. 5 parameters) -----------------------------------------
+ * With no fields fixed, the fast-summation parameters are chosen among the candidates
+ * (p, eps_B, M, n, m) that meet the accuracy target by the lowest cost of one product.
+ * By default that cost is an analytic model; after mot_tune_install it is read from a
+ * table measured on the device:
+ *   cost = n_max point_ns[d-1][m-2] / 1000 + grid_us[d-1][log2(n)-4] box / box_cells[..]
+ * (microseconds; box = cells of the candidate's active box).
+ * mot_tune_measure fills the table on the current GPU by creating calibration plans with
+ * fixed parameters on synthetic uniform points and timing their launches
+ * (mot_plan_profile):
+ *   point_ns[d-1][m-2]  spreading + interpolation of one product per point, m = 2..8
+ *                       (a two-marginal path of 2^15 points per marginal);
+ *   grid_us[d-1][k]     fold + FFT passes of one product at n = 16 << k, k = 0..5
+ *                       (a 17-marginal star of 256 points per marginal, M = n / 4),
+ *                       measured on a box of box_cells[d-1][k] cells (a grid that
+ *                       admits no box for that cloud, n = 16, repeats the next
+ *                       grid's entry: the tuner never chooses it for such clouds).
+ * It takes a few seconds, allocates and frees its own device memory, and does not install
+ * the table.  mot_tune_install(table) makes every later plan creation, footprint and
+ * mot_tune_resolve call of the process use it (entries must be finite and > 0, else
+ * MOT_EINVAL); mot_tune_install(NULL) returns to the analytic model.  Plans already
+ * created keep their parameters. */
+#define MOT_TUNE_M 7 /* m = 2..8     */
+#define MOT_TUNE_N 6 /* n = 16..512  */
+typedef struct {
+    int32_t measured, device;
+    double point_ns[3][MOT_TUNE_M];
+    double grid_us[3][MOT_TUNE_N];
+    double box_cells[3][MOT_TUNE_N];
+    double seconds; /* wall time of the measurement */
+} mot_tune_table;
+int mot_tune_measure(mot_tune_table *out);
+int mot_tune_install(const mot_tune_table *table);
+
+/* The parameters a plan would get (host only, no device work): d, eta, points assumed in
+ * [-half_width, half_width)^d, n_max points in the largest marginal, fs as in
+ * mot_plan_create (NULL = all tuned).  out receives M, n, m, p, tau, eps_B, tile, chunk
+ * and the accuracy target; est_err (may be NULL) the estimate of mot_plan_info. */
+int mot_tune_resolve(int32_t d, double eta, double half_width, int64_t n_max, const mot_fastsum_params *fs,
+                     mot_fastsum_params *out, double *est_err);
+
 /* ---- building block: point binning ------------------------------------------------
  * The node ordering the NFFT path uses (not in the paper):
  *   u_c = x_c * s_c + o_c   (FP64, product rounded before the add, no FMA)

@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmot.so")
 SOURCES = ["k_nfft.hip", "k_fft.hip", "k_direct.hip", "k_trunc.hip", "k_node.hip", "circle.hip",
-           "params.cpp", "plan.cpp", "batch.cpp", "server.cpp", "noalloc.hip"]
+           "params.cpp", "plan.cpp", "batch.cpp", "server.cpp", "tune.cpp", "noalloc.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
          "-Wno-unused-result", "-Wno-pass-failed",

@@ -110,6 +110,8 @@ struct Extent {
 };
 
 // params.cpp
+constexpr int kTuneM = MOT_TUNE_M, kTuneN = MOT_TUNE_N;
+int install_tune_table(const mot_tune_table *t);
 // eta_hi > eta: the parameters must also serve kernels up to eta_hi (weighted edges)
 int resolve_params(int d, double eta, const Extent &ext, const mot_fastsum_params *fs,
                    int64_t n_max, NfftParams *out, double eta_hi = 0.0);

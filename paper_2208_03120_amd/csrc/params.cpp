@@ -8,6 +8,7 @@
 // its derivatives 1..p vanish at tau (this reproduces the worked example of Fig. 1).
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 
 #include "host.h"
 
@@ -282,6 +283,45 @@ static double kb_err(int m, double sigma)
 // Spreading and interpolation work on 16-cell patches: tiles of T = 17 - 2m cells.
 static int tile_for(int m) { return 17 - 2 * m; }
 
+// Cost of one product for a candidate: the measured table when one is installed, else the
+// analytic model (window taps of the points plus the box's line transforms).
+static std::mutex g_tune_mu;
+static mot_tune_table g_tune{};  // measured == 0: analytic model
+
+int install_tune_table(const mot_tune_table *t)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    if (!t) {
+        g_tune = mot_tune_table{};
+        return MOT_OK;
+    }
+    for (int d = 0; d < 3; ++d) {
+        for (int m = 0; m < kTuneM; ++m)
+            if (!(std::isfinite(t->point_ns[d][m]) && t->point_ns[d][m] > 0)) return MOT_EINVAL;
+        for (int k = 0; k < kTuneN; ++k)
+            if (!(std::isfinite(t->grid_us[d][k]) && t->grid_us[d][k] > 0 && std::isfinite(t->box_cells[d][k]) &&
+                  t->box_cells[d][k] >= 1))
+                return MOT_EINVAL;
+    }
+    g_tune = *t;
+    g_tune.measured = 1;
+    return MOT_OK;
+}
+
+static double product_cost(int d, int64_t n_max, int n, int m, double box)
+{
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        if (g_tune.measured) {
+            const int k = (int)std::lround(std::log2((double)n)) - 4;  // n = 16 << k
+            const int mi = std::min(std::max(m - 2, 0), kTuneM - 1);
+            return (double)n_max * g_tune.point_ns[d - 1][mi] * 1e-3 +
+                   g_tune.grid_us[d - 1][k] * box / g_tune.box_cells[d - 1][k];
+        }
+    }
+    return 2.0 * (double)n_max * std::pow(2.0 * m, d) + 10.0 * box * std::log2((double)n) * d;
+}
+
 int resolve_params(int d, double eta, const Extent &ext, const mot_fastsum_params *fs,
                    int64_t n_max, NfftParams *out, double eta_hi)
 {
@@ -352,8 +392,7 @@ int resolve_params(int d, double eta, const Extent &ext, const mot_fastsum_param
                 P.kb_b = M_PI * (2.0 - 1.0 / sigma);
                 double box = 1.0;
                 for (int c = 0; c < d; ++c) box *= P.L[c];
-                const double cost = 2.0 * (double)n_max * std::pow(2.0 * m, d) +
-                                    10.0 * box * std::log2((double)n) * d;
+                const double cost = product_cost(d, n_max, n, m, box);
                 if (best_cost < 0 || cost < best_cost) {
                     best_cost = cost;
                     best = P;

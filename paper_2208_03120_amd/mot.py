@@ -71,6 +71,12 @@ STEP_KIND = {0: "node", 1: "direct", 2: "spread", 3: "fold", 4: "fft", 5: "inter
              7: "fill", 8: "trunc"}
 
 
+class TuneTable(ctypes.Structure):
+    _fields_ = [("measured", ctypes.c_int32), ("device", ctypes.c_int32),
+                ("point_ns", (ctypes.c_double * 7) * 3), ("grid_us", (ctypes.c_double * 6) * 3),
+                ("box_cells", (ctypes.c_double * 6) * 3), ("seconds", ctypes.c_double)]
+
+
 class Request(ctypes.Structure):
     _fields_ = [("K", ctypes.c_int32), ("d", ctypes.c_int32), ("topology", ctypes.c_int32),
                 ("n", ctypes.POINTER(ctypes.c_int64)), ("points", ctypes.POINTER(ctypes.c_double)),
@@ -94,7 +100,7 @@ EXPORTED = ["mot_plan_create", "mot_plan_create_tree", "mot_plan_create_circle",
             "mot_plan_profile", "mot_plan_get_order", "mot_bin_points_noalloc",
             "mot_batch_create", "mot_batch_sinkhorn", "mot_batch_launches", "mot_batch_destroy", "mot_server_create",
             "mot_server_submit", "mot_server_run", "mot_server_fetch", "mot_server_clock",
-            "mot_server_destroy"]
+            "mot_server_destroy", "mot_tune_measure", "mot_tune_install", "mot_tune_resolve"]
 
 _P = ctypes.POINTER
 _dp = _P(ctypes.c_double)
@@ -161,6 +167,10 @@ def _load():
         "mot_server_fetch": (ctypes.c_int, [_vp, ctypes.c_uint64, _P(Result), _dp]),
         "mot_server_clock": (ctypes.c_double, [_vp]),
         "mot_server_destroy": (ctypes.c_int, [_vp]),
+        "mot_tune_measure": (ctypes.c_int, [_P(TuneTable)]),
+        "mot_tune_install": (ctypes.c_int, [_P(TuneTable)]),
+        "mot_tune_resolve": (ctypes.c_int, [ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_int64,
+                                            _P(FastsumParams), _P(FastsumParams), _dp]),
     }
     for name, (res, args) in sig.items():
         if hasattr(lib, name):
@@ -462,6 +472,43 @@ def footprint(sizes, d, topology, path, precision, eta, half_width=0.25, fastsum
                                    precision, float(eta), float(half_width), fs,
                                    ctypes.byref(out)), "mot_plan_footprint")
     return out.value
+
+
+def tune_measure():
+    """Measure the autotuner's cost table on the current GPU (mot_tune_measure)."""
+    t = TuneTable()
+    _check(_lib.mot_tune_measure(ctypes.byref(t)), "mot_tune_measure")
+    return t
+
+
+def tune_install(table):
+    """Make later plans use `table` (a TuneTable); None returns to the analytic model."""
+    _check(_lib.mot_tune_install(ctypes.byref(table) if table is not None else None), "mot_tune_install")
+
+
+def tune_table(point_ns, grid_us, box_cells):
+    """A TuneTable from nested lists: point_ns [3][7], grid_us [3][6], box_cells [3][6]."""
+    t = TuneTable()
+    for d in range(3):
+        for i in range(7):
+            t.point_ns[d][i] = float(point_ns[d][i])
+        for i in range(6):
+            t.grid_us[d][i] = float(grid_us[d][i])
+            t.box_cells[d][i] = float(box_cells[d][i])
+    return t
+
+
+def tune_resolve(d, eta, n_max, half_width=0.25, fastsum=None):
+    """Parameters a plan would get (mot_tune_resolve): dict of M, n, m, p, tau, eps_B,
+    tile, chunk, target_rel_err and est_err."""
+    out = FastsumParams()
+    err = ctypes.c_double(0.0)
+    fs = ctypes.byref(fastsum) if fastsum is not None else None
+    _check(_lib.mot_tune_resolve(d, float(eta), float(half_width), int(n_max), fs, ctypes.byref(out),
+                                 ctypes.byref(err)), "mot_tune_resolve")
+    r = {f: getattr(out, f) for f, _ in FastsumParams._fields_}
+    r["est_err"] = err.value
+    return r
 
 
 class Batch:
