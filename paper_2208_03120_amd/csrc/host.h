@@ -149,6 +149,7 @@ struct Step {
     const void *jobs = nullptr;   // device ProdJob / NodeJob / FinalJob array
     const void *items = nullptr;  // device int2 / int4 array
     int n_items = 0;
+    int n_jobs = 0;               // finalisation: jobs (plans) of the launch
     const float2 *twiddle = nullptr;
     int32_t *fill_ptr = nullptr;
     int32_t fill_value = 0;
@@ -217,7 +218,7 @@ struct mot_plan_s {
     float *D = nullptr;
     float2 *twiddle = nullptr;
     // statistics
-    int32_t *sweep_ctr = nullptr, *flag = nullptr, *flag_hist = nullptr, *ticket = nullptr;
+    int32_t *sweep_ctr = nullptr, *flag = nullptr, *flag_hist = nullptr;
     double *S_hist = nullptr, *err_hist = nullptr;
     double *s_partial = nullptr, *l1_partial = nullptr;
     int hist_cap = 0;

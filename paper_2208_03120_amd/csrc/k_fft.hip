@@ -54,7 +54,8 @@ __device__ __forceinline__ float2 cmulc(float2 a, float2 b)  // a * conj(b)
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
 
-template <int N>
+// tw holds the twiddles of a TWS N-point transform: exp(-2 pi i j / N) = tw[j TWS]
+template <int N, int TWS>
 __device__ __forceinline__ void fft_dif(float2 (&x)[FftShape<N>::E], int g, const float2 *tw)
 {
     constexpr int G = FftShape<N>::G, E = FftShape<N>::E;
@@ -67,13 +68,13 @@ __device__ __forceinline__ void fft_dif(float2 (&x)[FftShape<N>::E], int g, cons
             for (int e = 0; e < E; ++e) {
                 if (e & eb) continue;
                 const int q = g + G * e;
-                const float2 w = tw[(q & (h - 1)) * tstride];
+                const float2 w = tw[(q & (h - 1)) * tstride * TWS];
                 const float2 a = x[e], b = x[e + eb];
                 x[e] = cadd(a, b);
                 x[e + eb] = cmul(csub(a, b), w);
             }
         } else {
-            const float2 w = tw[(g & (h - 1)) * tstride];
+            const float2 w = tw[(g & (h - 1)) * tstride * TWS];
             const bool bottom = (g & h) != 0;
 #pragma unroll
             for (int e = 0; e < E; ++e) {
@@ -86,7 +87,7 @@ __device__ __forceinline__ void fft_dif(float2 (&x)[FftShape<N>::E], int g, cons
     }
 }
 
-template <int N>
+template <int N, int TWS>
 __device__ __forceinline__ void fft_dit_inv(float2 (&x)[FftShape<N>::E], int g, const float2 *tw)
 {
     constexpr int G = FftShape<N>::G, E = FftShape<N>::E;
@@ -99,13 +100,13 @@ __device__ __forceinline__ void fft_dit_inv(float2 (&x)[FftShape<N>::E], int g, 
             for (int e = 0; e < E; ++e) {
                 if (e & eb) continue;
                 const int q = g + G * e;
-                const float2 w = tw[(q & (h - 1)) * tstride];
+                const float2 w = tw[(q & (h - 1)) * tstride * TWS];
                 const float2 a = x[e], b = cmulc(x[e + eb], w);
                 x[e] = cadd(a, b);
                 x[e + eb] = csub(a, b);
             }
         } else {
-            const float2 w = tw[(g & (h - 1)) * tstride];
+            const float2 w = tw[(g & (h - 1)) * tstride * TWS];
             const bool bottom = (g & h) != 0;
 #pragma unroll
             for (int e = 0; e < E; ++e) {
@@ -152,25 +153,19 @@ __device__ __forceinline__ PassGeom pass_geom(const ProdJob &J)
     return P;
 }
 
-template <int N, int KIND>
-__global__ __launch_bounds__(256) void fft_pass_kernel(const ProdJob *__restrict__ jobs,
-                                                       const int4 *__restrict__ items, int n_items,
-                                                       const float2 *__restrict__ twiddle)
+// One work item of a pass (kTL lines of one job), all threads of the block.  stage holds
+// kTL rows of N and zl (KIND 0) 4 LW rows of N; tw the twiddles (stride TWS).
+template <int N, int KIND, int TWS>
+__device__ __forceinline__ void fft_pass_item(const ProdJob &J, const int4 itm, const float2 *tw,
+                                              float2 (*stage)[N], float2 (*zl)[N])
 {
     using S = FftShape<N>;
     constexpr int G = S::G, E = S::E, LW = S::LW, LOG = S::LOG;
     constexpr int LPR = 4 * LW;  // complex lines per round (4 waves)
-    __shared__ float2 tw[N / 2];
-    __shared__ float2 stage[kTL][N];
-    __shared__ float2 zl[KIND == 0 ? LPR : 1][KIND == 0 ? N : 1];
     constexpr bool FWD = KIND <= 2 || KIND == 5, MUL = KIND == 2 || KIND == 5, INV = KIND >= 2;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int g = lane % G, slot = wave * LW + lane / G;
-    for (int t = tid; t < N / 2; t += blockDim.x) tw[t] = ld2(twiddle, t);
-    __syncthreads();
-    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
-        const int4 itm = items[it];
-        const ProdJob &J = jobs[itm.x];
+    {
         const PassGeom P = pass_geom<KIND>(J);
         const int M = J.M, B = 2 * M + 1;
         const int a2 = itm.y, a10 = itm.z;
@@ -232,7 +227,7 @@ __global__ __launch_bounds__(256) void fft_pass_kernel(const ProdJob *__restrict
                 x[e] = v;
             }
             // ---- transform
-            if (FWD) fft_dif<N>(x, g, tw);
+            if (FWD) fft_dif<N, TWS>(x, g, tw);
             if (MUL) {
 #pragma unroll
                 for (int e = 0; e < E; ++e) {
@@ -246,7 +241,7 @@ __global__ __launch_bounds__(256) void fft_pass_kernel(const ProdJob *__restrict
                     x[e].y *= dm;
                 }
             }
-            if (INV) fft_dit_inv<N>(x, g, tw);
+            if (INV) fft_dit_inv<N, TWS>(x, g, tw);
             // ---- store
             if (KIND == 0) {
 #pragma unroll
@@ -313,6 +308,58 @@ __global__ __launch_bounds__(256) void fft_pass_kernel(const ProdJob *__restrict
     }
 }
 
+template <int N, int KIND>
+__global__ __launch_bounds__(256) void fft_pass_kernel(const ProdJob *__restrict__ jobs,
+                                                       const int4 *__restrict__ items, int n_items,
+                                                       const float2 *__restrict__ twiddle)
+{
+    constexpr int LPR = 4 * FftShape<N>::LW;
+    __shared__ float2 tw[N / 2];
+    __shared__ float2 stage[kTL][N];
+    __shared__ float2 zl[KIND == 0 ? LPR : 1][N];
+    for (int t = threadIdx.x; t < N / 2; t += blockDim.x) tw[t] = ld2(twiddle, t);
+    __syncthreads();
+    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const int4 itm = items[it];
+        fft_pass_item<N, KIND, 1>(jobs[itm.x], itm, tw, stage, zl);
+    }
+}
+
+// Mixed grid sizes n <= 128 in one launch (batches of plans): each item runs the pass of
+// its job's n with the 128-point twiddles at stride 128 / n, so its values are those of
+// fft_pass_kernel<n>.  LDS is that of the 128-point kernel (stage and zl hold kTL x 128
+// and 512 complex values for every n <= 128).
+constexpr int kMixedN = 128;
+
+template <int KIND>
+__global__ __launch_bounds__(256) void fft_pass_mixed_kernel(const ProdJob *__restrict__ jobs,
+                                                             const int4 *__restrict__ items, int n_items,
+                                                             const float2 *__restrict__ twiddle128)
+{
+    __shared__ float2 tw[kMixedN / 2];
+    __shared__ float2 stage[kTL * kMixedN];
+    __shared__ float2 zl[KIND == 0 ? 512 : kMixedN];
+    for (int t = threadIdx.x; t < kMixedN / 2; t += blockDim.x) tw[t] = ld2(twiddle128, t);
+    __syncthreads();
+    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const int4 itm = items[it];
+        const ProdJob &J = jobs[itm.x];
+        switch (J.n) {
+#define MOT_MIXED_PASS(NN)                                                                                   \
+    case NN:                                                                                                 \
+        fft_pass_item<NN, KIND, kMixedN / NN>(J, itm, tw, reinterpret_cast<float2(*)[NN]>(stage),            \
+                                              reinterpret_cast<float2(*)[NN]>(zl));                          \
+        break;
+            MOT_MIXED_PASS(16)
+            MOT_MIXED_PASS(32)
+            MOT_MIXED_PASS(64)
+            MOT_MIXED_PASS(128)
+#undef MOT_MIXED_PASS
+        default: break;
+        }
+    }
+}
+
 
 // ---------------------------------------------------------------------------------------
 // Slab passes of the 3-D transform: one box slab g0 per work item, both in-slab axes, with
@@ -320,24 +367,18 @@ __global__ __launch_bounds__(256) void fft_pass_kernel(const ProdJob *__restrict
 //   forward: grid[g0][L1][L2] --R2C axis 2--> X[L1][H] --FWD axis 1--> spec1[g0][H][B]
 //   inverse: spec0[g0][H][B] --INV axis 1--> X[L1][H] --C2R axis 2--> grid[g0][L1][L2]
 // Lines are transformed exactly as in passes 0, 1 (forward) and 3, 4 (inverse).
-template <int N, bool INVERSE>
-__global__ __launch_bounds__(kSlabThreads) void fft_slab_kernel(const ProdJob *__restrict__ jobs,
-                                                                const int4 *__restrict__ items, int n_items,
-                                                                const float2 *__restrict__ twiddle)
+// One slab item, all threads of the block: X holds the slab's half spectrum (kSlabLds
+// bytes), zl (forward) 12 LW rows of N, tw the twiddles (stride TWS).
+template <int N, bool INVERSE, int TWS>
+__device__ __forceinline__ void fft_slab_item(const ProdJob &J, const int4 itm, const float2 *tw,
+                                              float2 *X, float2 (*zl)[N])
 {
     using S = FftShape<N>;
     constexpr int G = S::G, E = S::E, LW = S::LW, LOG = S::LOG;
     constexpr int LPR = (kSlabThreads / 64) * LW;  // lines per round
-    __shared__ float2 tw[N / 2];
-    __shared__ float2 X[kSlabLds / 8];
-    __shared__ float2 zl[INVERSE ? 1 : LPR][INVERSE ? 1 : N];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int g = lane % G, slot = wave * LW + lane / G;
-    for (int t = tid; t < N / 2; t += blockDim.x) tw[t] = ld2(twiddle, t);
-    __syncthreads();
-    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
-        const int4 itm = items[it];
-        const ProdJob &J = jobs[itm.x];
+    {
         const int g0 = itm.y, M = J.M, H = M + 1, B = 2 * M + 1;
         const int L1 = J.L[1], L2 = J.L[2], lo1 = J.lo[1], lo2 = J.lo[2];
         const int ncl = (L1 + 1) / 2;  // complex lines carrying two real lines of axis 2
@@ -357,7 +398,7 @@ __global__ __launch_bounds__(kSlabThreads) void fft_slab_kernel(const ProdJob *_
                     }
                     x[e] = v;
                 }
-                fft_dif<N>(x, g, tw);
+                fft_dif<N, TWS>(x, g, tw);
 #pragma unroll
                 for (int e = 0; e < E; ++e) {
                     const int f = (int)(__brev((unsigned)(g + G * e)) >> (32 - LOG));
@@ -384,7 +425,7 @@ __global__ __launch_bounds__(kSlabThreads) void fft_slab_kernel(const ProdJob *_
                     const int i = g + G * e - lo1;
                     x[e] = (act && i >= 0 && i < L1) ? X[i * H + k2] : make_float2(0.0f, 0.0f);
                 }
-                fft_dif<N>(x, g, tw);
+                fft_dif<N, TWS>(x, g, tw);
 #pragma unroll
                 for (int e = 0; e < E; ++e) {
                     const int f = (int)(__brev((unsigned)(g + G * e)) >> (32 - LOG));
@@ -405,7 +446,7 @@ __global__ __launch_bounds__(kSlabThreads) void fft_slab_kernel(const ProdJob *_
                     x[e] = (act && fs >= -M && fs <= M) ? ld2(J.spec0, ((int64_t)g0 * H + k2) * B + fs + M)
                                                         : make_float2(0.0f, 0.0f);
                 }
-                fft_dit_inv<N>(x, g, tw);
+                fft_dit_inv<N, TWS>(x, g, tw);
 #pragma unroll
                 for (int e = 0; e < E; ++e) {
                     const int i = g + G * e - lo1;
@@ -437,7 +478,7 @@ __global__ __launch_bounds__(kSlabThreads) void fft_slab_kernel(const ProdJob *_
                     }
                     x[e] = v;
                 }
-                fft_dit_inv<N>(x, g, tw);
+                fft_dit_inv<N, TWS>(x, g, tw);
 #pragma unroll
                 for (int e = 0; e < E; ++e) {
                     const int i = g + G * e - lo2;
@@ -448,6 +489,53 @@ __global__ __launch_bounds__(kSlabThreads) void fft_slab_kernel(const ProdJob *_
                 }
             }
             __syncthreads();
+        }
+    }
+}
+
+template <int N, bool INVERSE>
+__global__ __launch_bounds__(kSlabThreads) void fft_slab_kernel(const ProdJob *__restrict__ jobs,
+                                                                const int4 *__restrict__ items, int n_items,
+                                                                const float2 *__restrict__ twiddle)
+{
+    constexpr int LPR = (kSlabThreads / 64) * FftShape<N>::LW;
+    __shared__ float2 tw[N / 2];
+    __shared__ float2 X[kSlabLds / 8];
+    __shared__ float2 zl[INVERSE ? 1 : LPR][N];
+    for (int t = threadIdx.x; t < N / 2; t += blockDim.x) tw[t] = ld2(twiddle, t);
+    __syncthreads();
+    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const int4 itm = items[it];
+        fft_slab_item<N, INVERSE, 1>(jobs[itm.x], itm, tw, X, zl);
+    }
+}
+
+// Mixed grid sizes n <= 128 in one slab launch, as fft_pass_mixed_kernel (zl: 12 LW rows
+// of n are 1536 complex values for every n <= 128).
+template <bool INVERSE>
+__global__ __launch_bounds__(kSlabThreads) void fft_slab_mixed_kernel(const ProdJob *__restrict__ jobs,
+                                                                      const int4 *__restrict__ items, int n_items,
+                                                                      const float2 *__restrict__ twiddle128)
+{
+    __shared__ float2 tw[kMixedN / 2];
+    __shared__ float2 X[kSlabLds / 8];
+    __shared__ float2 zl[INVERSE ? kMixedN : (kSlabThreads / 64) * kMixedN];
+    for (int t = threadIdx.x; t < kMixedN / 2; t += blockDim.x) tw[t] = ld2(twiddle128, t);
+    __syncthreads();
+    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const int4 itm = items[it];
+        const ProdJob &J = jobs[itm.x];
+        switch (J.n) {
+#define MOT_MIXED_SLAB(NN)                                                                                     \
+    case NN:                                                                                                   \
+        fft_slab_item<NN, INVERSE, kMixedN / NN>(J, itm, tw, X, reinterpret_cast<float2(*)[NN]>(zl));          \
+        break;
+            MOT_MIXED_SLAB(16)
+            MOT_MIXED_SLAB(32)
+            MOT_MIXED_SLAB(64)
+            MOT_MIXED_SLAB(128)
+#undef MOT_MIXED_SLAB
+        default: break;
         }
     }
 }
@@ -475,6 +563,21 @@ hipError_t launch_fft_pass(int kind, int n, const ProdJob *jobs, const int4 *ite
                            const float2 *twiddle, hipStream_t s)
 {
     if (n_items == 0) return hipSuccess;
+    if (n == 0) {  // jobs with grids n <= 128 of several sizes; twiddle: the 128-point table
+        const int grid = n_items < 8192 ? n_items : 8192;
+        switch (kind) {
+        case 0: hipLaunchKernelGGL(fft_pass_mixed_kernel<0>, dim3(grid), dim3(256), 0, s, jobs, items, n_items, twiddle); break;
+        case 1: hipLaunchKernelGGL(fft_pass_mixed_kernel<1>, dim3(grid), dim3(256), 0, s, jobs, items, n_items, twiddle); break;
+        case 2: hipLaunchKernelGGL(fft_pass_mixed_kernel<2>, dim3(grid), dim3(256), 0, s, jobs, items, n_items, twiddle); break;
+        case 3: hipLaunchKernelGGL(fft_pass_mixed_kernel<3>, dim3(grid), dim3(256), 0, s, jobs, items, n_items, twiddle); break;
+        case 4: hipLaunchKernelGGL(fft_pass_mixed_kernel<4>, dim3(grid), dim3(256), 0, s, jobs, items, n_items, twiddle); break;
+        case 5: hipLaunchKernelGGL(fft_pass_mixed_kernel<5>, dim3(grid), dim3(256), 0, s, jobs, items, n_items, twiddle); break;
+        case 6: hipLaunchKernelGGL(fft_slab_mixed_kernel<false>, dim3(grid), dim3(kSlabThreads), 0, s, jobs, items, n_items, twiddle); break;
+        case 7: hipLaunchKernelGGL(fft_slab_mixed_kernel<true>, dim3(grid), dim3(kSlabThreads), 0, s, jobs, items, n_items, twiddle); break;
+        default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
     switch (n) {
     case 16: return launch_n<16>(kind, jobs, items, n_items, twiddle, s);
     case 32: return launch_n<32>(kind, jobs, items, n_items, twiddle, s);

@@ -660,6 +660,7 @@ __device__ __forceinline__ void fold_item(const ProdJob &J, int f0, Tab tch)
     gp(J.grid)[(int64_t)line * Ll + g] = acc;
 }
 
+// D = 0: every item takes its job's own d (batches of plans of several dimensions).
 template <int D>
 __global__ __launch_bounds__(kFoldCellsPerItem) void fold_kernel(const ProdJob *__restrict__ jobs,
                                                                  const int2 *__restrict__ items, int n_items)
@@ -668,17 +669,25 @@ __global__ __launch_bounds__(kFoldCellsPerItem) void fold_kernel(const ProdJob *
     for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
         const int2 itm = items[it];
         const ProdJob &J = jobs[itm.x];
+        const int d = D > 0 ? D : J.d;
         int ntab = 1;
-        for (int c = 0; c < D; ++c) ntab *= J.ntile[c];
+        for (int c = 0; c < d; ++c) ntab *= J.ntile[c];
         ++ntab;
-        if (ntab <= kFoldTab) {
+        const bool staged = ntab <= kFoldTab;
+        if (staged) {
             __syncthreads();  // the previous item's reads of the table are done
             const MOT_GLOBAL int32_t *tg = gp(J.src_tile_chunks);
             for (int i = threadIdx.x; i < ntab; i += blockDim.x) s_tab[i] = tg[i];
             __syncthreads();
-            fold_item<D>(J, itm.y, static_cast<const int32_t *>(s_tab));
+        }
+        const int32_t *lt = static_cast<const int32_t *>(s_tab);
+        const MOT_GLOBAL int32_t *gt = gp(J.src_tile_chunks);
+        if (d == 3) {
+            if (staged) fold_item<3>(J, itm.y, lt); else fold_item<3>(J, itm.y, gt);
+        } else if (d == 2) {
+            if (staged) fold_item<2>(J, itm.y, lt); else fold_item<2>(J, itm.y, gt);
         } else {
-            fold_item<D>(J, itm.y, gp(J.src_tile_chunks));
+            if (staged) fold_item<1>(J, itm.y, lt); else fold_item<1>(J, itm.y, gt);
         }
     }
 }
@@ -911,7 +920,10 @@ hipError_t launch_spread(int d, const ProdJob *jobs, const int2 *items, int n_it
 hipError_t launch_fold(int d, const ProdJob *jobs, const int2 *items, int n_items, hipStream_t s)
 {
     if (n_items == 0) return hipSuccess;
-    if (d == 3)
+    if (d == 0)
+        hipLaunchKernelGGL(fold_kernel<0>, dim3(nfft_grid(n_items)), dim3(kFoldCellsPerItem), 0, s, jobs, items,
+                           n_items);
+    else if (d == 3)
         hipLaunchKernelGGL(fold_kernel<3>, dim3(nfft_grid(n_items)), dim3(kFoldCellsPerItem), 0, s, jobs, items,
                            n_items);
     else if (d == 2)

@@ -202,17 +202,20 @@ hipError_t launch_node(const NodeJob *jobs_dev, const int2 *items, int n_items, 
 }
 
 // ---------------------------------------------------------------------------------------
-// Sweep finalisation.  item = (job, first root element).  Computes the root marginal
-// P_0 = phi^0 * prod_{t in C_0} beta_t after the upward pass and its L1 error; the last
-// block of a job (atomic ticket) reduces all partial sums in a fixed order, records
-//   S^(r) = eta * (sum mu log phi_old - sum (mu / phi_new) phi_old)
-// and the error at the plan's sweep counter, and re-arms the exponent slots and the
-// ticket for the next sweep.
-__global__ __launch_bounds__(256) void finalize_kernel(const FinalJob *__restrict__ jobs,
-                                                       const int2 *__restrict__ items, int n_items)
+// Sweep finalisation, two launches.
+//   finalize_l1_kernel, item = (job, first root element): the root marginal
+//     P_0 = phi^0 * prod_{t in C_0} beta_t after the upward pass and the L1 error of the
+//     item's elements, one partial per item;
+//   finalize_reduce_kernel, one block per job: the partial sums in a fixed order,
+//     S^(r) = eta * (sum mu log phi_old - sum (mu / phi_new) phi_old)
+//     and the error recorded at the plan's sweep counter, the exponent slots re-armed for
+//     the next sweep.
+// The kernel boundary orders the partials before their reduction, so no block waits on
+// another and no device-scope fence is needed.
+__global__ __launch_bounds__(256) void finalize_l1_kernel(const FinalJob *__restrict__ jobs,
+                                                          const int2 *__restrict__ items, int n_items)
 {
     __shared__ double red[4];
-    __shared__ int last;
     const int tid = threadIdx.x;
     for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
         const int2 itm = items[it];
@@ -257,60 +260,59 @@ __global__ __launch_bounds__(256) void finalize_kernel(const FinalJob *__restric
             }
         }
         const double tot = block_sum(l1, red);
-        const int blk = (int)(itm.y / kNodeElems);
-        if (tid == 0) {
-            J.l1_partial[blk] = tot;
-            __threadfence();
-            const int ticket = atomicAdd(J.ticket, 1);
-            last = ticket == J.n_items - 1;
-        }
-        __syncthreads();
-        if (last) {
-            __threadfence();
-            // every thread sums a fixed strided subset; block_sum combines them in a fixed
-            // order, so the result does not depend on timing
-            // eight strided partials are loaded before they are added (in the same order), so
-            // the loads of a thread are in flight together
-            constexpr int U = 8;
-            double s1 = 0.0, s2 = 0.0, e1 = 0.0;
-            for (int p0 = tid; p0 < J.n_partials; p0 += U * (int)blockDim.x) {
-                double a[U], b[U];
-#pragma unroll
-                for (int q = 0; q < U; ++q) {
-                    const int p = p0 + q * (int)blockDim.x;
-                    a[q] = p < J.n_partials ? J.s_partial[2 * p] : 0.0;
-                    b[q] = p < J.n_partials ? J.s_partial[2 * p + 1] : 0.0;
-                }
-#pragma unroll
-                for (int q = 0; q < U; ++q)
-                    if (p0 + q * (int)blockDim.x < J.n_partials) {
-                        s1 += a[q];
-                        s2 += b[q];
-                    }
-            }
-            for (int p = tid; p < J.n_items; p += blockDim.x) e1 += J.l1_partial[p];
-            s1 = block_sum(s1, red);
-            s2 = block_sum(s2, red);
-            e1 = block_sum(e1, red);
-            if (tid == 0) {
-                const int r = *J.sweep_ctr;
-                const int slot = r % J.hist_cap;
-                J.S_hist[slot] = J.eta * (s1 - s2);
-                J.err_hist[slot] = e1;
-                J.flag_hist[slot] = *J.flag;
-                *J.sweep_ctr = r + 1;
-                *J.ticket = 0;
-            }
-            for (int s = tid; s < J.n_exp_slots; s += blockDim.x) J.exp_slots[s] = INT32_MIN;
-        }
-        __syncthreads();
+        if (tid == 0) J.l1_partial[itm.y / kNodeElems] = tot;
     }
 }
 
-hipError_t launch_finalize(const FinalJob *jobs, const int2 *items, int n_items, hipStream_t s)
+__global__ __launch_bounds__(256) void finalize_reduce_kernel(const FinalJob *__restrict__ jobs, int n_jobs)
 {
-    if (n_items == 0) return hipSuccess;
-    hipLaunchKernelGGL(finalize_kernel, dim3(n_items), dim3(256), 0, s, jobs, items, n_items);
+    __shared__ double red[4];
+    const int tid = threadIdx.x;
+    for (int j = blockIdx.x; j < n_jobs; j += gridDim.x) {
+        const FinalJob &J = jobs[j];
+        // every thread sums a fixed strided subset; block_sum combines them in a fixed
+        // order.  Eight strided partials are loaded before they are added (in the same
+        // order), so the loads of a thread are in flight together.
+        constexpr int U = 8;
+        double s1 = 0.0, s2 = 0.0, e1 = 0.0;
+        for (int p0 = tid; p0 < J.n_partials; p0 += U * (int)blockDim.x) {
+            double a[U], b[U];
+#pragma unroll
+            for (int q = 0; q < U; ++q) {
+                const int p = p0 + q * (int)blockDim.x;
+                a[q] = p < J.n_partials ? J.s_partial[2 * p] : 0.0;
+                b[q] = p < J.n_partials ? J.s_partial[2 * p + 1] : 0.0;
+            }
+#pragma unroll
+            for (int q = 0; q < U; ++q)
+                if (p0 + q * (int)blockDim.x < J.n_partials) {
+                    s1 += a[q];
+                    s2 += b[q];
+                }
+        }
+        for (int p = tid; p < J.n_items; p += blockDim.x) e1 += J.l1_partial[p];
+        s1 = block_sum(s1, red);
+        s2 = block_sum(s2, red);
+        e1 = block_sum(e1, red);
+        if (tid == 0) {
+            const int r = *J.sweep_ctr;
+            const int slot = r % J.hist_cap;
+            J.S_hist[slot] = J.eta * (s1 - s2);
+            J.err_hist[slot] = e1;
+            J.flag_hist[slot] = *J.flag;
+            *J.sweep_ctr = r + 1;
+        }
+        for (int s = tid; s < J.n_exp_slots; s += blockDim.x) J.exp_slots[s] = INT32_MIN;
+        __syncthreads();  // red is reused by the next job
+    }
+}
+
+hipError_t launch_finalize(const FinalJob *jobs, const int2 *items, int n_items, int n_jobs, hipStream_t s)
+{
+    if (n_items == 0 || n_jobs == 0) return hipSuccess;
+    hipLaunchKernelGGL(finalize_l1_kernel, dim3(n_items < 8192 ? n_items : 8192), dim3(256), 0, s, jobs, items,
+                       n_items);
+    hipLaunchKernelGGL(finalize_reduce_kernel, dim3(n_jobs < 8192 ? n_jobs : 8192), dim3(256), 0, s, jobs, n_jobs);
     return hipGetLastError();
 }
 

@@ -136,7 +136,7 @@ struct FinalJob {
     const double *s_partial;         // node partial sums (2 per slot)
     int32_t n_partials, hist_cap;
     double *l1_partial;              // [n_items]
-    int32_t *ticket, *sweep_ctr, *flag, *flag_hist;
+    int32_t *sweep_ctr, *flag, *flag_hist;
     double *S_hist, *err_hist;
     int32_t *exp_slots;
     int32_t n_exp_slots, pad;
@@ -156,7 +156,7 @@ hipError_t launch_trunc(int d, int precision, int R, int wide, const ProdJob *jo
 hipError_t launch_direct(int d, const ProdJob *jobs_dev, const int4 *items, int n_items,
                          int precision, int diff, hipStream_t s);
 hipError_t launch_node(const NodeJob *jobs_dev, const int2 *items, int n_items, hipStream_t s);
-hipError_t launch_finalize(const FinalJob *jobs, const int2 *items, int n_items, hipStream_t s);
+hipError_t launch_finalize(const FinalJob *jobs, const int2 *items, int n_items, int n_jobs, hipStream_t s);
 hipError_t launch_fill_int(int32_t *p, int32_t value, int64_t count, hipStream_t s);
 hipError_t launch_fill_double(double *p, double value, int64_t count, hipStream_t s);
 hipError_t launch_vec_exp(const double *v, int64_t n, int32_t *slot, hipStream_t s);
@@ -208,6 +208,8 @@ hipError_t launch_interp(int d, const ProdJob *jobs, const int2 *items, int n_it
 // lines (23 complex) is two rounds and its 33 half-spectrum lines (M = 32) three.
 constexpr int kSlabThreads = 768;
 constexpr int kSlabLds = 48 * 1024;  // bytes of LDS for a slab's half spectrum L1 x (M+1)
+// n = 0: the items' jobs have grids n <= 128 of several sizes (twiddle: the 128-point
+// table); results equal those of the launch per size.
 hipError_t launch_fft_pass(int kind, int n, const ProdJob *jobs, const int4 *items, int n_items,
                            const float2 *twiddle, hipStream_t s);
 

@@ -162,7 +162,7 @@ int run_steps(const std::vector<Step> &steps, hipStream_t s)
                                   st.max_patch, s));
             break;
         case ST_FINAL:
-            MOT_HIP(launch_finalize((const FinalJob *)st.jobs, (const int2 *)st.items, st.n_items, s));
+            MOT_HIP(launch_finalize((const FinalJob *)st.jobs, (const int2 *)st.items, st.n_items, st.n_jobs, s));
             break;
         case ST_FILL_INT:
             MOT_HIP(launch_fill_int(st.fill_ptr, st.fill_value, st.fill_count, s));
@@ -219,6 +219,7 @@ struct StepBuilder {
         st.jobs = jobs_dev;
         st.items = upload(items);
         st.n_items = (int)items.size();
+        st.n_jobs = (int)host_jobs.size();
         out->push_back(st);
     }
 
@@ -249,7 +250,7 @@ struct StepBuilder {
         // 3-D spreading: jobs by the points they spread from (a binned marginal's rows)
         std::map<const float *, std::vector<int>> spread3_src;
         std::map<int, std::vector<int32_t>> spread_pts, interp_pts;  // points of each item
-        std::map<std::pair<int, int>, std::vector<int4>> fft[8]; // (d, n) per pass kind
+        std::map<int, std::vector<int4>> fft[8];  // items per grid size n, per pass kind
         std::map<int, int> max_patch;
         for (int j : ids) {
             const ProdJob &J = host_jobs[j];
@@ -320,19 +321,19 @@ struct StepBuilder {
             const int nk = J.d == 3 ? 5 : (J.d == 2 ? 3 : 2);
             if (slab) {
                 for (int g0 = 0; g0 < J.L[0]; ++g0) {
-                    fft[6][{J.d, J.n}].push_back(make_int4(j, g0, 0, 0));
-                    fft[7][{J.d, J.n}].push_back(make_int4(j, g0, 0, 0));
+                    fft[6][J.n].push_back(make_int4(j, g0, 0, 0));
+                    fft[7][J.n].push_back(make_int4(j, g0, 0, 0));
                 }
                 int A2, A1;
                 fft_dims(J, 2, &A2, &A1);
-                auto &v = fft[5][{J.d, J.n}];
+                auto &v = fft[5][J.n];
                 for (int a2 = 0; a2 < A2; ++a2)
                     for (int a1 = 0; a1 < A1; a1 += kFftLinesPerItem) v.push_back(make_int4(j, a2, a1, 0));
             } else {
                 for (int q = 0; q < nk; ++q) {
                     int A2, A1;
                     fft_dims(J, kinds[q], &A2, &A1);
-                    auto &v = fft[kinds[q]][{J.d, J.n}];
+                    auto &v = fft[kinds[q]][J.n];
                     for (int a2 = 0; a2 < A2; ++a2)
                         for (int a1 = 0; a1 < A1; a1 += kFftLinesPerItem) v.push_back(make_int4(j, a2, a1, 0));
                 }
@@ -421,6 +422,13 @@ struct StepBuilder {
             st.n_items = (int)kv.second.size();
             out->push_back(st);
         }
+        // jobs of several dimensions fold in one launch (each item takes its job's d)
+        if (fold.size() > 1) {
+            std::vector<int2> all;
+            for (auto &kv : fold) all.insert(all.end(), kv.second.begin(), kv.second.end());
+            fold.clear();
+            fold[0] = all;
+        }
         for (auto &kv : fold) {
             Step st{ST_FOLD};
             st.d = kv.first;
@@ -429,20 +437,33 @@ struct StepBuilder {
             st.n_items = (int)kv.second.size();
             out->push_back(st);
         }
-        // per job the chain order holds: 0 < 1 < 2 < 3 < 4 and 6 < 5 < 7
-        for (int kind : {0, 6, 1, 2, 5, 3, 4, 7})
+        // per job the chain order holds: 0 < 1 < 2 < 3 < 4 and 6 < 5 < 7.  A pass kernel
+        // serves every d; grids n <= 128 of several sizes share one launch (n = 0).
+        for (int kind : {0, 6, 1, 2, 5, 3, 4, 7}) {
+            std::vector<std::pair<int, std::vector<int4>>> launches;
+            std::vector<int4> mixed;
+            int small = 0;
+            for (auto &kv : fft[kind]) small += kv.first <= 128;
             for (auto &kv : fft[kind]) {
+                if (small > 1 && kv.first <= 128)
+                    mixed.insert(mixed.end(), kv.second.begin(), kv.second.end());
+                else
+                    launches.push_back({kv.first, kv.second});
+            }
+            if (!mixed.empty()) launches.insert(launches.begin(), {0, mixed});
+            for (auto &l : launches) {
                 Step st{ST_FFT};
-                st.d = kv.first.first;
-                st.n = kv.first.second;
+                st.d = kind >= 5 ? 3 : 0;
+                st.n = l.first;
                 st.fft_kind = kind;
-                st.twiddle = device_twiddle(st.n);
+                st.twiddle = device_twiddle(st.n == 0 ? 128 : st.n);
                 if (!st.twiddle) rc = MOT_EDEVICE;
                 st.jobs = jobs_dev;
-                st.items = upload(kv.second);
-                st.n_items = (int)kv.second.size();
+                st.items = upload(l.second);
+                st.n_items = (int)l.second.size();
                 out->push_back(st);
             }
+        }
         for (auto &kv : interp) {
             Step st{ST_INTERP};
             st.d = kv.first;
@@ -579,7 +600,6 @@ int tree_build_schedule(mot_plan_s *P)
         F.n_partials = T->n_down_partials;
         F.hist_cap = P->hist_cap;
         F.l1_partial = P->l1_partial;
-        F.ticket = P->ticket;
         F.sweep_ctr = P->sweep_ctr;
         F.flag = P->flag;
         F.flag_hist = P->flag_hist;
@@ -894,7 +914,6 @@ static int plan_stats_alloc(mot_plan_s *P, int n_partials_hint)
     P->hist_cap = 1 << 16;
     MOT_TRY(P->arena.get_n(4, &P->sweep_ctr));
     MOT_TRY(P->arena.get_n(4, &P->flag));
-    MOT_TRY(P->arena.get_n(4, &P->ticket));
     MOT_TRY(P->arena.get_n(P->hist_cap, &P->flag_hist));
     MOT_TRY(P->arena.get_n(P->hist_cap, &P->S_hist));
     MOT_TRY(P->arena.get_n(P->hist_cap, &P->err_hist));
@@ -902,7 +921,6 @@ static int plan_stats_alloc(mot_plan_s *P, int n_partials_hint)
     MOT_TRY(P->arena.get_n((size_t)n_partials_hint + 16, &P->l1_partial));
     MOT_HIP(launch_fill_int(P->sweep_ctr, 0, 1, P->stream));
     MOT_HIP(launch_fill_int(P->flag, 0, 1, P->stream));
-    MOT_HIP(launch_fill_int(P->ticket, 0, 1, P->stream));
     return MOT_OK;
 }
 

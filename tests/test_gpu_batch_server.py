@@ -16,20 +16,23 @@ def mot():
     return m
 
 
-def small_batch_instances(count=6):
-    out = []
-    for i in range(count):
-        inst = W.batched_instance(i, n_range=(300, 3000))
-        out.append(inst)
-    return out
+def small_batch_instances(count=6, extra=()):
+    return [W.batched_instance(i, n_range=(300, 3000)) for i in list(range(count)) + list(extra)]
 
 
 @pytest.mark.parametrize("use_graph", [True, False])
 def test_batched_sweeps_equal_single_plans(mot, use_graph):
-    insts = small_batch_instances()
+    """Eight instances of d = 1, 2, 3 whose grids include several sizes n <= 128 in 1-D/2-D
+    and in 3-D: the batch's launches then mix dimensions (fold) and grid sizes (FFT passes
+    and slabs), and every result still equals its plan's result alone, bit for bit."""
+    insts = small_batch_instances(6, extra=(7, 12))
     stream = mot.current_stream()
     plans = [mot.Plan(x.points, x.weights, W.TREE, x.parent, x.eta, path=mot.NFFT, stream=stream)
              for x in insts]
+    grids = [(p.info()["d"], p.info()["n"]) for p in plans]
+    assert len({n for d, n in grids if d < 3 and n <= 128}) >= 2, grids
+    assert len({n for d, n in grids if d == 3 and n <= 128}) >= 2, grids
+    assert len({d for d, n in grids}) == 3, grids
     batch = mot.Batch(plans)
     batch.sinkhorn(12, use_graph=use_graph)
     for x, p in zip(insts, plans):
