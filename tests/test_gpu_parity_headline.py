@@ -5,7 +5,8 @@ stopping rule, and the boundary's device pointers and caller-supplied memory.
   M = 32, tau = 1, eps_B = 1/8, p = 3) at N = 1e4 per marginal over the full 200 sweeps
   against the FP64 oracle's Algorithm 2 (Sec. 4.1), with the fixed parameters the
   benchmark uses: gauge-fixed scaling vectors within 1e-5, marginals within 1e-6 in L1,
-  S history within 1e-6 relative.
+  S^(0) within (K - 1) 2e-6 relative and S^(r >= 1) within eta (K + 2.2) 1e-5 absolute
+  (the bound the scaling gate implies; derivation at the assertion).
 * The binned order of every marginal, as the plan holds it, equals the oracle's binning
   definition bit for bit: the (tile, cell mod T, index) order in 3-D, the plain tile order
   in 1-D and 2-D, the cell order of the truncated path.
