@@ -74,14 +74,22 @@ __device__ __forceinline__ void fft_dif(float2 (&x)[FftShape<N>::E], int g, cons
                 x[e + eb] = cmul(csub(a, b), w);
             }
         } else {
-            const float2 w = tw[(g & (h - 1)) * tstride * TWS];
+            // the same operations on every lane, so the wavefront does not split: the top
+            // lane of a pair forms x + y, the bottom lane (y - x) w, as s x + y with s = +-1
+            // times w or 1 (exact for the top lane)
             const bool bottom = (g & h) != 0;
+            const float2 w = bottom ? tw[(g & (h - 1)) * tstride * TWS] : make_float2(1.0f, 0.0f);
+            const float sg = bottom ? -1.0f : 1.0f;
+            float2 y[E];
 #pragma unroll
             for (int e = 0; e < E; ++e) {
-                float2 y;
-                y.x = __shfl_xor(x[e].x, h);
-                y.y = __shfl_xor(x[e].y, h);
-                x[e] = bottom ? cmul(csub(y, x[e]), w) : cadd(x[e], y);
+                y[e].x = __shfl_xor(x[e].x, h);
+                y[e].y = __shfl_xor(x[e].y, h);
+            }
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const float2 t = make_float2(fmaf(sg, x[e].x, y[e].x), fmaf(sg, x[e].y, y[e].y));
+                x[e] = cmul(t, w);
             }
         }
     }
@@ -106,14 +114,20 @@ __device__ __forceinline__ void fft_dit_inv(float2 (&x)[FftShape<N>::E], int g, 
                 x[e + eb] = csub(a, b);
             }
         } else {
-            const float2 w = tw[(g & (h - 1)) * tstride * TWS];
+            // branch-free: with a the top lane's value and b the bottom lane's, the top lane
+            // forms a + b conj(w) and the bottom lane a - b conj(w).  Every lane first
+            // multiplies its own value by conj(w) (the top lane by 1, exactly) and the
+            // products are exchanged, so each lane ends with s z + y, s = +-1.
             const bool bottom = (g & h) != 0;
+            const float2 w = bottom ? tw[(g & (h - 1)) * tstride * TWS] : make_float2(1.0f, 0.0f);
+            const float sg = bottom ? -1.0f : 1.0f;
 #pragma unroll
             for (int e = 0; e < E; ++e) {
+                const float2 z = cmulc(x[e], w);
                 float2 y;
-                y.x = __shfl_xor(x[e].x, h);
-                y.y = __shfl_xor(x[e].y, h);
-                x[e] = bottom ? csub(y, cmulc(x[e], w)) : cadd(x[e], cmulc(y, w));
+                y.x = __shfl_xor(z.x, h);
+                y.y = __shfl_xor(z.y, h);
+                x[e] = make_float2(fmaf(sg, z.x, y.x), fmaf(sg, z.y, y.y));
             }
         }
     }
