@@ -324,6 +324,25 @@ constexpr int kInterpWaves = 4;
 // one stage ahead of the MFMA work, so the row stream overlaps the contractions.
 constexpr int kStage = 64;
 
+// Staged 3-D window rows: a point's 48 floats are its rows for dimensions 0, 1, 2.  The
+// dimension-1 row w_1[0..15] is stored transposed, position 4 i + q holding w_1[4 q + i], so
+// that the four values w_1[w], w_1[w + 4], w_1[w + 8], w_1[w + 12] a wavefront w takes are
+// one 16-byte read at position 4 w.  idx is the 16-byte piece (12 per point).
+__device__ __forceinline__ void store_piece3(unsigned char *buf, int idx, f32x4 v)
+{
+    const int piece = idx % 12;
+    if (piece >= 4 && piece < 8) {
+        float *row = reinterpret_cast<float *>(buf) + (idx - piece + 4) * 4;
+        const int q = piece - 4;
+        row[q] = v[0];
+        row[4 + q] = v[1];
+        row[8 + q] = v[2];
+        row[12 + q] = v[3];
+    } else {
+        reinterpret_cast<f32x4 *>(buf)[idx] = v;
+    }
+}
+
 template <int D, bool WITH_V>
 struct Stage {
     static constexpr int kRow4 = kStage * D * kPatch / 4;  // 16-byte row pieces per stage
@@ -349,14 +368,20 @@ struct Stage {
             if (threadIdx.x < kStage && p < p1) v = gp(vsrc)[p];
         }
     }
-    // LDS <- registers; source values are stored as FP32 v 2^-e.
+    // LDS <- registers; source values are stored as FP32 v 2^-e.  In 3-D the dimension-1
+    // row of a point is stored transposed (see store_rows3).
     __device__ __forceinline__ void store(unsigned char *buf, int e) const
     {
         f32x4 *rl = reinterpret_cast<f32x4 *>(buf);
 #pragma unroll
         for (int i = 0; i < kPer; ++i) {
             const int idx = threadIdx.x + 256 * i;
-            if (idx < kRow4) rl[idx] = r[i];
+            if (idx < kRow4) {
+                if constexpr (D == 3)
+                    store_piece3(buf, idx, r[i]);
+                else
+                    rl[idx] = r[i];
+            }
         }
         if constexpr (WITH_V)
             if (threadIdx.x < kStage) reinterpret_cast<float *>(buf + kRow4 * 16)[threadIdx.x] = (float)ldexp(v, -e);
@@ -473,14 +498,14 @@ struct SpreadStage3 {
         const int64_t p = pb + (threadIdx.x % kStage);
         if (threadIdx.x / kStage < G && p < p1) v = gp(vq)[p];
     }
-    // LDS <- registers; job q's values are stored as FP32 v 2^-eq.
+    // LDS <- registers (dimension-1 rows transposed, store_piece3); job q's values are
+    // stored as FP32 v 2^-eq.
     __device__ __forceinline__ void store(unsigned char *buf, int eq) const
     {
-        f32x4 *rl = reinterpret_cast<f32x4 *>(buf);
 #pragma unroll
         for (int i = 0; i < kPer; ++i) {
             const int idx = threadIdx.x + 256 * i;
-            if (idx < kRow4) rl[idx] = r[i];
+            if (idx < kRow4) store_piece3(buf, idx, r[i]);
         }
         if (threadIdx.x / kStage < G) reinterpret_cast<float *>(buf + kRow4 * 16)[threadIdx.x] = (float)ldexp(v, -eq);
     }
@@ -532,9 +557,8 @@ __global__ __launch_bounds__(64 * kSpreadWaves, G == 1 ? 6 : (G == 2 ? 5 : 4)) v
 #pragma unroll
                 for (int g = 0; g < G; ++g) x[g] = vl[g * kStage + pi] * w0;
                 const float w2 = row[2 * kPatch + li];
-                // w_1,p[b] for the wave's b = wave + 4 u
-                const f32x4 w1 = f32x4{row[kPatch + wave], row[kPatch + wave + 4], row[kPatch + wave + 8],
-                                       row[kPatch + wave + 12]};
+                // w_1,p[b] for the wave's b = wave + 4 u (one read of the transposed row)
+                const f32x4 w1 = reinterpret_cast<const f32x4 *>(row + kPatch)[wave];
 #pragma unroll
                 for (int u = 0; u < 4; ++u)
                     // B is zero when b = w + 4 u is outside the window of all four points:
@@ -850,8 +874,7 @@ __global__ __launch_bounds__(64 * kInterpWaves, 6) void interp3_kernel(const Pro
 #pragma unroll 1
             for (int g = 0; g < 4; ++g) {
                 const float *row = rl + (16 * g + li) * (3 * kPatch);  // point 16 g + l % 16
-                const f32x4 wy = f32x4{row[kPatch + wave], row[kPatch + wave + 4], row[kPatch + wave + 8],
-                                       row[kPatch + wave + 12]};
+                const f32x4 wy = reinterpret_cast<const f32x4 *>(row + kPatch)[wave];  // transposed row
                 const f32x4 wz = reinterpret_cast<const f32x4 *>(row + 2 * kPatch)[lk];
                 f32x4 acc = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
