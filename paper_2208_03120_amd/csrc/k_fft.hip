@@ -33,7 +33,6 @@
 
 namespace mot {
 
-constexpr int kTL = 16;  // lines per work item
 
 template <int N>
 struct FftShape {
@@ -167,8 +166,9 @@ __device__ __forceinline__ PassGeom pass_geom(const ProdJob &J)
     return P;
 }
 
-// One work item of a pass (kTL lines of one job), all threads of the block.  stage holds
-// kTL rows of N and zl (KIND 0) 4 LW rows of N; tw the twiddles (stride TWS).
+// One work item of a pass (kTL = fft_lines_per_item lines of one job), all threads of the
+// block.  stage holds kTL rows of N and zl (KIND 0) 4 LW rows of N; tw the twiddles
+// (stride TWS).
 template <int N, int KIND, int TWS>
 __device__ __forceinline__ void fft_pass_item(const ProdJob &J, const int4 itm, const float2 *tw,
                                               float2 (*stage)[N], float2 (*zl)[N])
@@ -176,6 +176,7 @@ __device__ __forceinline__ void fft_pass_item(const ProdJob &J, const int4 itm, 
     using S = FftShape<N>;
     constexpr int G = S::G, E = S::E, LW = S::LW, LOG = S::LOG;
     constexpr int LPR = 4 * LW;  // complex lines per round (4 waves)
+    constexpr int kTL = fft_lines_per_item(KIND, N);
     constexpr bool FWD = KIND <= 2 || KIND == 5, MUL = KIND == 2 || KIND == 5, INV = KIND >= 2;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int g = lane % G, slot = wave * LW + lane / G;
@@ -329,7 +330,7 @@ __global__ __launch_bounds__(256) void fft_pass_kernel(const ProdJob *__restrict
 {
     constexpr int LPR = 4 * FftShape<N>::LW;
     __shared__ float2 tw[N / 2];
-    __shared__ float2 stage[kTL][N];
+    __shared__ float2 stage[fft_lines_per_item(KIND, N)][N];
     __shared__ float2 zl[KIND == 0 ? LPR : 1][N];
     for (int t = threadIdx.x; t < N / 2; t += blockDim.x) tw[t] = ld2(twiddle, t);
     __syncthreads();
@@ -341,8 +342,8 @@ __global__ __launch_bounds__(256) void fft_pass_kernel(const ProdJob *__restrict
 
 // Mixed grid sizes n <= 128 in one launch (batches of plans): each item runs the pass of
 // its job's n with the 128-point twiddles at stride 128 / n, so its values are those of
-// fft_pass_kernel<n>.  LDS is that of the 128-point kernel (stage and zl hold kTL x 128
-// and 512 complex values for every n <= 128).
+// fft_pass_kernel<n>.  For every n <= 128 an item's lines times n is 512 complex values
+// (1024 in the real-data passes 0 and 4), which stage holds, and zl holds 512.
 constexpr int kMixedN = 128;
 
 template <int KIND>
@@ -351,7 +352,7 @@ __global__ __launch_bounds__(256) void fft_pass_mixed_kernel(const ProdJob *__re
                                                              const float2 *__restrict__ twiddle128)
 {
     __shared__ float2 tw[kMixedN / 2];
-    __shared__ float2 stage[kTL * kMixedN];
+    __shared__ float2 stage[(KIND == 0 || KIND == 4 ? 2 : 1) * 4 * kMixedN];
     __shared__ float2 zl[KIND == 0 ? 512 : kMixedN];
     for (int t = threadIdx.x; t < kMixedN / 2; t += blockDim.x) tw[t] = ld2(twiddle128, t);
     __syncthreads();

@@ -191,7 +191,13 @@ hipError_t launch_window_rows(int d, int64_t npts, const double *pts, double s, 
 // NFFT pipeline kernels (a2-a6).
 constexpr int kNodeItemElems = 512;  // elements per node / finalisation item
 constexpr int kFoldCellsPerItem = 128;  // box cells per fold item (one per thread)
-constexpr int kFftLinesPerItem = 16;
+// Lines of one FFT line-pass work item: one round of the block's four wavefronts, G =
+// min(64, n/2) lanes per line (two real lines per complex line in the real-data passes 0
+// and 4).  One round per item keeps an item's chain of loads, transforms and stores short.
+constexpr int fft_lines_per_item(int kind, int n)
+{
+    return (kind == 0 || kind == 4 ? 2 : 1) * 4 * (64 / (n / 2 < 64 ? n / 2 : 64));
+}
 hipError_t launch_spread(int d, const ProdJob *jobs, const int2 *items, int n_items,
                          int max_patch_elems, hipStream_t s);  // d = 1, 2
 // 3-D spreading; items int4 (job_0, .., job_{group-1}, chunk): group jobs (1..3) that spread

@@ -327,15 +327,17 @@ struct StepBuilder {
                 int A2, A1;
                 fft_dims(J, 2, &A2, &A1);
                 auto &v = fft[5][J.n];
+                const int per = fft_lines_per_item(5, J.n);
                 for (int a2 = 0; a2 < A2; ++a2)
-                    for (int a1 = 0; a1 < A1; a1 += kFftLinesPerItem) v.push_back(make_int4(j, a2, a1, 0));
+                    for (int a1 = 0; a1 < A1; a1 += per) v.push_back(make_int4(j, a2, a1, 0));
             } else {
                 for (int q = 0; q < nk; ++q) {
                     int A2, A1;
                     fft_dims(J, kinds[q], &A2, &A1);
                     auto &v = fft[kinds[q]][J.n];
+                    const int per = fft_lines_per_item(kinds[q], J.n);
                     for (int a2 = 0; a2 < A2; ++a2)
-                        for (int a1 = 0; a1 < A1; a1 += kFftLinesPerItem) v.push_back(make_int4(j, a2, a1, 0));
+                        for (int a1 = 0; a1 < A1; a1 += per) v.push_back(make_int4(j, a2, a1, 0));
                 }
             }
         }
@@ -1720,6 +1722,20 @@ int mot_plan_get_order(mot_plan P, int32_t k, int32_t *perm_out, int32_t ptr_kin
     return MOT_OK;
 }
 
+// FFT line-pass items of one product job: the step builder's count for the job's chain.
+static int64_t fft_items_of(int d, int n, int M, const int L[3])
+{
+    const int H = M + 1, B = 2 * M + 1;
+    auto items = [n](int kind, int64_t a2, int64_t a1) {
+        const int per = mot::fft_lines_per_item(kind, n);
+        return a2 * ((a1 + per - 1) / per);
+    };
+    if (d == 1) return 2;
+    if (d == 2) return items(0, 1, L[0]) + items(2, 1, H) + items(4, 1, L[0]);
+    if ((int64_t)L[1] * H * 8 <= mot::kSlabLds) return 2 * (int64_t)L[0] + items(5, H, B);
+    return items(0, L[0], L[1]) + items(1, H, L[0]) + items(2, H, B) + items(3, L[0], H) + items(4, L[0], L[1]);
+}
+
 int mot_plan_footprint(int32_t K, int32_t d, const int64_t *n, int32_t topology, int32_t path,
                        int32_t precision, double eta, double half_width,
                        const mot_fastsum_params *fs, size_t *bytes)
@@ -1762,7 +1778,7 @@ int mot_plan_footprint(int32_t K, int32_t d, const int64_t *n, int32_t topology,
             const int64_t maxc = tiles + nmax / std::max(1, Q.chunk) + 1;
             const int64_t n1 = n[0];
             b += (size_t)n1 * ((size_t)maxc * pe * 4 + (size_t)cells * 4 + (size_t)spec * 16 + 3 * 256);
-            const int64_t fft_items = 3 * (int64_t)Q.L[0] + 2 * H + B + 8;
+            const int64_t fft_items = fft_items_of(d, Q.n, Q.M, Q.L) + 8;
             const int64_t per_job = (int64_t)sizeof(ProdJob) + 8 * 2 * maxc + 8 * (cells / kFoldCellsPerItem + 1) +
                                     16 * fft_items;
             b += (size_t)(2 * (K - 2)) * ((size_t)n1 * per_job + 16 * 256);
@@ -1795,6 +1811,9 @@ int mot_plan_footprint(int32_t K, int32_t d, const int64_t *n, int32_t topology,
         b += (size_t)(2 * (K - 1) + 1) * (cells * 4 + spec * 16);
         b += (size_t)(2 * (K - 1) + 1) * chunks_per_job * pe * 4;
         b += (size_t)H * B * B * 4;
+        // launch items: FFT passes, spreading and interpolation chunks, fold cells
+        b += (size_t)(2 * (K - 1)) * (16 * (fft_items_of(d, Q.n, Q.M, Q.L) + 8) + 8 * 2 * chunks_per_job +
+                                      8 * (cells / kFoldCellsPerItem + 1));
     } else if (path == MOT_TRUNC) {
         Extent E;
         for (int c = 0; c < d; ++c) {
