@@ -179,6 +179,25 @@ int run_steps(const std::vector<Step> &steps, hipStream_t s)
 // ---------------------------------------------------------------------------------------
 // Step construction.
 
+// Workgroups are dealt to the XCDs round-robin by block index (eight XCDs, each with its
+// own L2), and a launch's block b takes item b first.  Items that read neighbouring data
+// (consecutive line groups of an FFT pass, consecutive cells of a fold) are therefore
+// placed `group` to an XCD: within every run of kXcds * group items, positions r, r + kXcds,
+// ..., r + (group - 1) kXcds receive group consecutive items.  Results do not depend on the
+// order of items.
+constexpr int kXcds = 8;
+
+template <class T>
+static void xcd_group(std::vector<T> &v, int group)
+{
+    const size_t run = (size_t)kXcds * group;
+    std::vector<T> out(v);
+    for (size_t q = 0; q + run <= v.size(); q += run)
+        for (int r = 0; r < kXcds; ++r)
+            for (int j = 0; j < group; ++j) out[q + (size_t)j * kXcds + r] = v[q + (size_t)r * group + j];
+    v.swap(out);
+}
+
 struct StepBuilder {
     Arena *arena;
     std::vector<Step> *out;
@@ -432,6 +451,7 @@ struct StepBuilder {
             fold[0] = all;
         }
         for (auto &kv : fold) {
+            xcd_group(kv.second, 4);
             Step st{ST_FOLD};
             st.d = kv.first;
             st.jobs = jobs_dev;
@@ -461,6 +481,7 @@ struct StepBuilder {
                 st.twiddle = device_twiddle(st.n == 0 ? 128 : st.n);
                 if (!st.twiddle) rc = MOT_EDEVICE;
                 st.jobs = jobs_dev;
+                if (kind <= 5) xcd_group(l.second, 4);  // line passes: 4 neighbouring line groups
                 st.items = upload(l.second);
                 st.n_items = (int)l.second.size();
                 out->push_back(st);
