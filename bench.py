@@ -32,23 +32,24 @@ PEAK_FP32_TFLOPS = 157.3  # dense FP32 MFMA
 # this script performs first (fold, FFT and interpolation launches averaged over the down
 # and up products; spread per item grouping: "spread" is the up launch, one job per item,
 # "spread_g3" the down launch, whose items take three jobs spreading from the root's
-# points).  Valid only for the kernel source it was measured on (SHA-256 of its file).
+# points).  Valid only for the sources it was measured on (SHA-256 of the kernel file, and
+# for fold and the FFT passes also of plan.cpp, whose launch item order sets their traffic).
 COPY_MIB = 256
 TRAFFIC = {
-    "spread": {"bytes_per_launch": 231933516, "source": "k_nfft.hip",
-               "sha256": "943f4489a2b20900745162af79e4b953dae097909db2ee0f407b5a1fc9c3a8e7"},
-    "spread_g3": {"bytes_per_launch": 110931878, "source": "k_nfft.hip",
-                  "sha256": "943f4489a2b20900745162af79e4b953dae097909db2ee0f407b5a1fc9c3a8e7"},
-    "fold": {"bytes_per_launch": 79216329, "source": "k_nfft.hip",
-             "sha256": "943f4489a2b20900745162af79e4b953dae097909db2ee0f407b5a1fc9c3a8e7"},
-    "interp": {"bytes_per_launch": 198702322, "source": "k_nfft.hip",
-               "sha256": "943f4489a2b20900745162af79e4b953dae097909db2ee0f407b5a1fc9c3a8e7"},
-    "fft6": {"bytes_per_launch": 10832430, "source": "k_fft.hip",
-             "sha256": "0fdb613e3aa356b695e37243d8a0803c82e512974bd0f3a4f21196a7c2e62e6f"},
-    "fft5": {"bytes_per_launch": 28824010, "source": "k_fft.hip",
-             "sha256": "0fdb613e3aa356b695e37243d8a0803c82e512974bd0f3a4f21196a7c2e62e6f"},
-    "fft7": {"bytes_per_launch": 10842984, "source": "k_fft.hip",
-             "sha256": "0fdb613e3aa356b695e37243d8a0803c82e512974bd0f3a4f21196a7c2e62e6f"},
+    "spread": {"bytes_per_launch": 231948833, "source": "k_nfft.hip",
+            "sha256": "e95beabf6ee9f74433a7bef0ca9f0ae0990f9eeddcb4f03e4c0070d85db2cefe"},
+    "spread_g3": {"bytes_per_launch": 110941004, "source": "k_nfft.hip",
+               "sha256": "e95beabf6ee9f74433a7bef0ca9f0ae0990f9eeddcb4f03e4c0070d85db2cefe"},
+    "fold": {"bytes_per_launch": 61192852, "source": "k_nfft.hip+plan.cpp",
+          "sha256": "5985ff6cb748a32defc3bba2c89e6af9498f6c1db10912059b4366167213f36e"},
+    "interp": {"bytes_per_launch": 213287365, "source": "k_nfft.hip",
+            "sha256": "e95beabf6ee9f74433a7bef0ca9f0ae0990f9eeddcb4f03e4c0070d85db2cefe"},
+    "fft6": {"bytes_per_launch": 10824014, "source": "k_fft.hip+plan.cpp",
+          "sha256": "a9b73d6135afb9b558e9ca5bb7eeb9e1057792d428a19b7816ef8dd89a0b1ab4"},
+    "fft5": {"bytes_per_launch": 26587002, "source": "k_fft.hip+plan.cpp",
+          "sha256": "a9b73d6135afb9b558e9ca5bb7eeb9e1057792d428a19b7816ef8dd89a0b1ab4"},
+    "fft7": {"bytes_per_launch": 10822490, "source": "k_fft.hip+plan.cpp",
+          "sha256": "a9b73d6135afb9b558e9ca5bb7eeb9e1057792d428a19b7816ef8dd89a0b1ab4"}
 }
 
 
@@ -63,11 +64,14 @@ def cpu_model():
     return "unknown"
 
 
-def source_sha(name):
+def source_sha(names):
+    """SHA-256 of the named csrc files, concatenated ("a.hip+b.cpp")."""
     import hashlib
-    path = os.path.join(ROOT, "paper_2208_03120_amd", "csrc", name)
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+    h = hashlib.sha256()
+    for name in names.split("+"):
+        with open(os.path.join(ROOT, "paper_2208_03120_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def traffic_of(kernel, n_points):
