@@ -150,6 +150,8 @@ struct Step {
     const void *items = nullptr;  // device int2 / int4 array
     int n_items = 0;
     int n_jobs = 0;               // finalisation: jobs (plans) of the launch
+    const void *items2 = nullptr; // FP64 direct: reduction items (int2), n_items2 of them
+    int n_items2 = 0;
     const float2 *twiddle = nullptr;
     int32_t *fill_ptr = nullptr;
     int32_t fill_value = 0;

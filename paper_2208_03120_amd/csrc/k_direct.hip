@@ -1,8 +1,9 @@
 // Direct Gaussian-kernel products (a7), the plain O(n_t n_s) path:
 //   out_i = sum_j v_j exp(-|x_i - y_j|^2 / eta)      (Sec. 5, eq. fastsum-sum)
 //
-// FP64 variant: one target per thread, sources staged through LDS in tiles of 256,
-// accumulated sequentially in ascending source order (the order of the definition).
+// FP64 variant: one target per lane, a block's four wavefronts summing quarters of a
+// source range in ascending source order, the quarters (and ranges) then added in order
+// (details at direct_fp64_kernel).
 //
 // Mixed variant: FP32 transcendental with FP64 accumulation across tiles.  With
 // c = log2(e) / eta and coordinates taken relative to the point cloud's centre,
@@ -17,49 +18,83 @@
 // 2^-e (e = exponent of max v) so FP32 never under- or overflows; partial sums over 64
 // sources are added into FP64 accumulators.  Each thread owns R targets to reuse every
 // LDS read R times.  This kernel is bound by the transcendental and vector issue rates.
+#include <algorithm>
 #include <type_traits>
 
 #include "mot_internal.h"
 
 namespace mot {
 
+// FP64 variant: an item is 64 targets (one per lane) and one of the job's dsplit equal
+// source ranges; the block's four wavefronts take the four quarters of that range, each
+// summing its sources in ascending order, and the quarters are added in order.  With
+// dsplit > 1 the item writes its partial sums to the job's partial buffer and
+// direct_fp64_reduce_kernel adds the ranges in order; dsplit grows as the targets get
+// fewer, so that small products still spread over the chip.
+constexpr int kDirectT = 64;
+
+int direct_source_split(int64_t nt, int64_t ns)
+{
+    const int64_t groups = (nt + kDirectT - 1) / kDirectT;
+    const int64_t want = (1024 + groups - 1) / groups;  // about a thousand items per launch
+    const int64_t most = (ns + 63) / 64;               // at least 16 sources per wavefront
+    return (int)std::max<int64_t>(1, std::min<int64_t>(std::min(want, most), 64));
+}
+
 template <int D>
 __global__ __launch_bounds__(256) void direct_fp64_kernel(const ProdJob *__restrict__ jobs,
                                                           const int4 *__restrict__ items, int n_items)
 {
-    __shared__ double sy[256 * D];
-    __shared__ double sv[256];
-    const int tid = threadIdx.x;
+    __shared__ double red[3][kDirectT];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
         const int4 itm = items[it];
         const ProdJob &J = jobs[itm.x];
-        const int64_t i = (int64_t)itm.y + tid;
+        const int64_t i = (int64_t)itm.y + lane;
         const bool act = i < J.nt;
         double x[D];
 #pragma unroll
         for (int c = 0; c < D; ++c) x[c] = act ? J.tgt_pts[i * D + c] : 0.0;
         const double eta = J.eta;
+        const int64_t per = (J.ns + J.dsplit - 1) / J.dsplit;
+        const int64_t a = (int64_t)itm.z * per, b = min(J.ns, a + per);
+        const int64_t q = (b - a + 3) / 4;
+        const int64_t ja = min(b, a + wave * q), jb = min(b, ja + q);
         double acc = 0.0;
-        for (int64_t j0 = 0; j0 < J.ns; j0 += 256) {
-            const int nj = (int)min((int64_t)256, J.ns - j0);
-            __syncthreads();
-            if (tid < nj) {
+        for (int64_t j = ja; j < jb; ++j) {
+            double d2 = 0.0;
 #pragma unroll
-                for (int c = 0; c < D; ++c) sy[tid * D + c] = J.src_pts[(j0 + tid) * D + c];
-                sv[tid] = J.v[j0 + tid];
+            for (int c = 0; c < D; ++c) {
+                const double df = x[c] - J.src_pts[j * D + c];
+                d2 += df * df;
             }
-            __syncthreads();
-            for (int jj = 0; jj < nj; ++jj) {
-                double d2 = 0.0;
-#pragma unroll
-                for (int c = 0; c < D; ++c) {
-                    const double df = x[c] - sy[jj * D + c];
-                    d2 += df * df;
-                }
-                acc += sv[jj] * exp(-d2 / eta);
-            }
+            acc += J.v[j] * exp(-d2 / eta);
         }
-        if (act) J.out[i] = acc;
+        __syncthreads();  // the previous item's reads of red are done
+        if (wave > 0) red[wave - 1][lane] = acc;
+        __syncthreads();
+        if (wave == 0 && act) {
+            const double sum = ((acc + red[0][lane]) + red[1][lane]) + red[2][lane];
+            if (J.dsplit > 1)
+                J.dpart[(int64_t)itm.z * J.nt + i] = sum;
+            else
+                J.out[i] = sum;
+        }
+    }
+}
+
+// out_i = sum over the job's source ranges, in range order, of the partial sums.
+__global__ __launch_bounds__(256) void direct_fp64_reduce_kernel(const ProdJob *__restrict__ jobs,
+                                                                 const int2 *__restrict__ items, int n_items)
+{
+    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const int2 itm = items[it];
+        const ProdJob &J = jobs[itm.x];
+        const int64_t i = (int64_t)itm.y + threadIdx.x;
+        if (i >= J.nt) continue;
+        double acc = 0.0;
+        for (int r = 0; r < J.dsplit; ++r) acc += J.dpart[(int64_t)r * J.nt + i];
+        J.out[i] = acc;
     }
 }
 
@@ -168,10 +203,10 @@ __global__ __launch_bounds__(256) void direct_mixed_kernel(const ProdJob *__rest
     }
 }
 
-int direct_targets_per_item(int precision) { return precision == MOT_PREC_FP64 ? 256 : 256 * kDirectR; }
+int direct_targets_per_item(int precision) { return precision == MOT_PREC_FP64 ? kDirectT : 256 * kDirectR; }
 
-hipError_t launch_direct(int d, const ProdJob *jobs_dev, const int4 *items, int n_items,
-                         int precision, int diff, hipStream_t s)
+hipError_t launch_direct(int d, const ProdJob *jobs_dev, const int4 *items, int n_items, const int2 *red_items,
+                         int n_red, int precision, int diff, hipStream_t s)
 {
     if (n_items == 0) return hipSuccess;
     const int grid = n_items < 16384 ? n_items : 16384;
@@ -179,6 +214,9 @@ hipError_t launch_direct(int d, const ProdJob *jobs_dev, const int4 *items, int 
         if (d == 1) hipLaunchKernelGGL(direct_fp64_kernel<1>, dim3(grid), dim3(256), 0, s, jobs_dev, items, n_items);
         if (d == 2) hipLaunchKernelGGL(direct_fp64_kernel<2>, dim3(grid), dim3(256), 0, s, jobs_dev, items, n_items);
         if (d == 3) hipLaunchKernelGGL(direct_fp64_kernel<3>, dim3(grid), dim3(256), 0, s, jobs_dev, items, n_items);
+        if (n_red > 0)
+            hipLaunchKernelGGL(direct_fp64_reduce_kernel, dim3(n_red < 16384 ? n_red : 16384), dim3(256), 0, s, jobs_dev,
+                               red_items, n_red);
     } else if (diff) {
         if (d == 1) hipLaunchKernelGGL((direct_mixed_kernel<1, true>), dim3(grid), dim3(256), 0, s, jobs_dev, items, n_items);
         if (d == 2) hipLaunchKernelGGL((direct_mixed_kernel<2, true>), dim3(grid), dim3(256), 0, s, jobs_dev, items, n_items);

@@ -66,6 +66,8 @@ struct ProdJob {
     int32_t *v_exp;    // slot holding max_j exponent(|v_j|) (atomicMax), reset per sweep
     double *out;       // target vector, n_t entries
     int64_t ns, nt;
+    double *dpart;     // FP64 direct path: partial sums, dsplit x n_t (dsplit > 1 only)
+    int32_t dsplit, pad_d;
     double eta;
     double ctr[3];     // centre of the point cloud (mixed direct path works relative to it)
     // direct path: sorted FP64 coordinates (n x d) of sources and targets
@@ -146,6 +148,9 @@ struct FinalJob {
 // ---------------------------------------------------------------------------------------
 // Kernel launchers (implemented in the .hip files).
 int direct_targets_per_item(int precision);
+// FP64 direct products: source ranges per job (partial sums added by a second kernel when
+// above 1), from the target and source counts
+int direct_source_split(int64_t nt, int64_t ns);
 constexpr int kMaxTruncRows = 400;  // neighbour rows per truncated work item, (2w + 1)^(d-1)
 // Truncated products: items int4 (job, first cell of a run of B cells of one row, first
 // sorted target, count | B << 16), count <= 64 * R; R = 1, 2 or 4 (FP64: 1 or 2).
@@ -153,8 +158,8 @@ constexpr int kMaxTruncRows = 400;  // neighbour rows per truncated work item, (
 hipError_t launch_trunc(int d, int precision, int R, int wide, const ProdJob *jobs_dev, const int4 *items,
                         int n_items, hipStream_t s);
 // diff != 0: mixed-precision pairs with the exponent formed in FP64 (small eta)
-hipError_t launch_direct(int d, const ProdJob *jobs_dev, const int4 *items, int n_items,
-                         int precision, int diff, hipStream_t s);
+hipError_t launch_direct(int d, const ProdJob *jobs_dev, const int4 *items, int n_items, const int2 *red_items,
+                         int n_red, int precision, int diff, hipStream_t s);
 hipError_t launch_node(const NodeJob *jobs_dev, const int2 *items, int n_items, hipStream_t s);
 hipError_t launch_finalize(const FinalJob *jobs, const int2 *items, int n_items, int n_jobs, hipStream_t s);
 hipError_t launch_fill_int(int32_t *p, int32_t value, int64_t count, hipStream_t s);

@@ -141,7 +141,7 @@ int run_steps(const std::vector<Step> &steps, hipStream_t s)
             break;
         case ST_DIRECT:
             MOT_HIP(launch_direct(st.d, (const ProdJob *)st.jobs, (const int4 *)st.items, st.n_items,
-                                  st.precision, st.diff, s));
+                                  (const int2 *)st.items2, st.n_items2, st.precision, st.diff, s));
             break;
         case ST_SPREAD:
             if (st.group > 0)
@@ -264,6 +264,7 @@ struct StepBuilder {
                   const std::vector<int> &ids)
     {
         std::map<std::tuple<int, int, int>, std::vector<int4>> direct;  // (d, precision, diff)
+        std::map<std::tuple<int, int, int>, std::vector<int2>> direct_red;  // FP64 range sums
         std::map<std::tuple<int, int, int, int>, std::vector<std::pair<double, int4>>> trunc;  // (d, prec, R, wide)
         std::map<int, std::vector<int2>> spread, fold, interp;   // d
         // 3-D spreading: jobs by the points they spread from (a binned marginal's rows)
@@ -275,8 +276,13 @@ struct StepBuilder {
             const ProdJob &J = host_jobs[j];
             if (J.path == MOT_DIRECT) {
                 const int tpi = direct_targets_per_item(J.precision);
-                auto &v = direct[std::make_tuple(J.d, J.precision, J.diff)];
-                for (int64_t t = 0; t < J.nt; t += tpi) v.push_back(make_int4(j, (int)t, 0, 0));
+                const auto key = std::make_tuple(J.d, J.precision, J.diff);
+                auto &v = direct[key];
+                const int split = J.precision == MOT_PREC_FP64 ? std::max(1, J.dsplit) : 1;
+                for (int64_t t = 0; t < J.nt; t += tpi)
+                    for (int r = 0; r < split; ++r) v.push_back(make_int4(j, (int)t, r, 0));
+                if (split > 1)
+                    for (int64_t t = 0; t < J.nt; t += 256) direct_red[key].push_back(make_int2(j, (int)t));
                 continue;
             }
             if (J.path == MOT_TRUNC) {
@@ -386,6 +392,11 @@ struct StepBuilder {
             st.jobs = jobs_dev;
             st.items = upload(kv.second);
             st.n_items = (int)kv.second.size();
+            auto red = direct_red.find(kv.first);
+            if (red != direct_red.end()) {
+                st.items2 = upload(red->second);
+                st.n_items2 = (int)red->second.size();
+            }
             out->push_back(st);
         }
         // largest chunks first: the blocks of a launch start roughly in item order, so the
@@ -862,6 +873,14 @@ int mot::make_prod_job(mot_plan_s *P, int t, int s, const double *v, int32_t *sl
     Q.diff = P->precision == MOT_PREC_MIXED && 1.4426950408889634 * half * half / Q.eta > 8.0;
     Q.src_pts = P->marg[s].pts;
     Q.tgt_pts = P->marg[t].pts;
+    Q.dsplit = 1;
+    if (P->path == MOT_DIRECT && P->precision == MOT_PREC_FP64 && alloc_buffers) {
+        const int split = direct_source_split(Q.nt, Q.ns);
+        if (split > 1) {
+            MOT_TRY(P->arena.get_n((size_t)split * Q.nt, &Q.dpart));
+            Q.dsplit = split;
+        }
+    }
     if (P->path == MOT_TRUNC) {
         const TruncParams &T = P->TP;
         Q.src_cell_off = P->marg[s].cell_off;
@@ -1835,6 +1854,9 @@ int mot_plan_footprint(int32_t K, int32_t d, const int64_t *n, int32_t topology,
         // launch items: FFT passes, spreading and interpolation chunks, fold cells
         b += (size_t)(2 * (K - 1)) * (16 * (fft_items_of(d, Q.n, Q.M, Q.L) + 8) + 8 * 2 * chunks_per_job +
                                       8 * (cells / kFoldCellsPerItem + 1));
+    } else if (path == MOT_DIRECT && precision == MOT_PREC_FP64 && topology == MOT_TREE) {
+        // partial sums of the source ranges: split x n_t <= 1024 x 64 + n_t + 64 per job
+        b += (size_t)(2 * (K - 1)) * (size_t)(1024 * 64 + nmax + 64) * 8;
     } else if (path == MOT_TRUNC) {
         Extent E;
         for (int c = 0; c < d; ++c) {
