@@ -67,6 +67,24 @@ def test_path_fp64_direct_sinkhorn_parity(mot):
     plan.close()
 
 
+@pytest.mark.parametrize("sizes,parent", [([3, 1, 70, 129], [-1, 0, 0, 2]), ([2, 257, 5], [-1, 0, 1])])
+def test_fp64_direct_ragged_sizes_parity(mot, sizes, parent):
+    """FP64 direct sums split their sources over blocks (64 targets x one of several
+    source ranges, each range summed by four wavefronts in quarters); marginals of 1 to
+    257 points leave quarters and ranges of one or no source and ragged target groups.
+    30 sweeps of Algorithm 2 against the oracle, as the config-1 test."""
+    r = rng(61 + len(sizes))
+    inst = W.make_instance(r, len(sizes), sizes, 2, W.TREE, 0.1, parent=parent)
+    plan = mot.Plan(inst.points, inst.weights, W.TREE, inst.parent, inst.eta,
+                    path=mot.DIRECT, precision=mot.PREC_FP64)
+    rc, done, _, _ = plan.sinkhorn(30)
+    assert rc == mot.MAXITER and done == 30
+    ophi, oS, _, _ = oracle.tree_sinkhorn(inst.points, inst.weights, inst.parent, inst.eta, 30)
+    assert max_rel(gauge_fix(plan.scalings(), inst.weights), gauge_fix(ophi, inst.weights)) < 1e-11
+    np.testing.assert_allclose(plan.S_history(), oS, rtol=1e-12, atol=1e-14)
+    plan.close()
+
+
 @pytest.mark.parametrize("d", [1, 2, 3])
 def test_direct_mixed_product(mot, d):
     r = rng(7 + d)
