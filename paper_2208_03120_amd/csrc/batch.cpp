@@ -12,6 +12,7 @@
 struct mot_batch_s {
     std::vector<mot_plan_s *> plans;
     hipStream_t stream = nullptr;
+    mot::Lanes lanes;  // two lanes of plans (created when the batch has two or more plans)
     mot::Arena arena;
     std::vector<mot::Step> sweep, init_up, marg;
     hipGraph_t graph_def = nullptr;
@@ -20,12 +21,15 @@ struct mot_batch_s {
 
 using namespace mot;
 
+static const Lanes *lanes_of(mot_batch_s *B) { return B->lanes.side ? &B->lanes : nullptr; }
+
 extern "C" {
 
 int mot_batch_destroy(mot_batch B)
 {
     if (!B) return MOT_EINVAL;
     if (B->stream) (void)hipStreamSynchronize(B->stream);
+    B->lanes.destroy();
     if (B->graph) (void)hipGraphExecDestroy(B->graph);
     if (B->graph_def) (void)hipGraphDestroy(B->graph_def);
     B->arena.release();
@@ -76,7 +80,9 @@ int mot::batch_create(mot_batch *out, mot_plan *plans, int32_t count, const mot_
                     hipMemcpy(nj_dev, nj.data(), nj.size() * sizeof(NodeJob), hipMemcpyHostToDevice) != hipSuccess ||
                     hipMemcpy(fj_dev, fj.data(), fj.size() * sizeof(FinalJob), hipMemcpyHostToDevice) != hipSuccess))
         rc = MOT_EDEVICE;
-    if (rc >= 0) rc = tree_steps(refs, pj, pj_dev, nj, nj_dev, fj, fj_dev, B->arena, B->sweep, B->init_up, B->marg);
+    bool two = false;
+    if (rc >= 0) rc = tree_steps(refs, pj, pj_dev, nj, nj_dev, fj, fj_dev, B->arena, B->sweep, B->init_up, B->marg, &two);
+    if (rc >= 0 && two) rc = B->lanes.create();
     if (rc < 0) {
         mot_batch_destroy(B);
         return rc;
@@ -88,7 +94,7 @@ int mot::batch_create(mot_batch *out, mot_plan *plans, int32_t count, const mot_
 // Enqueue sweeps of the batch on its stream without waiting for them (no graph).
 int mot::batch_enqueue(mot_batch B, int sweeps)
 {
-    for (int r = 0; r < sweeps; ++r) MOT_TRY(run_steps(B->sweep, B->stream));
+    for (int r = 0; r < sweeps; ++r) MOT_TRY(run_steps(B->sweep, B->stream, lanes_of(B)));
     for (mot_plan_s *P : B->plans) P->host_sweeps += sweeps;
     return MOT_OK;
 }
@@ -103,7 +109,9 @@ int mot_batch_create(mot_batch *out, mot_plan *plans, int32_t count)
 int mot_batch_launches(mot_batch B)
 {
     if (!B) return MOT_EINVAL;
-    return (int)B->sweep.size();
+    int n = 0;
+    for (const Step &st : B->sweep) n += st.kind != ST_FORK && st.kind != ST_JOIN;
+    return n;
 }
 
 int mot_batch_sinkhorn(mot_batch B, int32_t sweeps, int32_t use_graph)
@@ -114,7 +122,7 @@ int mot_batch_sinkhorn(mot_batch B, int32_t sweeps, int32_t use_graph)
         if (P->stream != B->stream) MOT_HIP(hipStreamSynchronize(P->stream));
     if (use_graph && !B->graph && sweeps > 0) {
         MOT_HIP(hipStreamBeginCapture(B->stream, hipStreamCaptureModeThreadLocal));
-        int rc = run_steps(B->sweep, B->stream);
+        int rc = run_steps(B->sweep, B->stream, lanes_of(B));
         hipError_t e = hipStreamEndCapture(B->stream, &B->graph_def);
         if (rc < 0) return rc;
         MOT_HIP(e);
@@ -124,7 +132,7 @@ int mot_batch_sinkhorn(mot_batch B, int32_t sweeps, int32_t use_graph)
         if (use_graph) {
             MOT_HIP(hipGraphLaunch(B->graph, B->stream));
         } else {
-            MOT_TRY(run_steps(B->sweep, B->stream));
+            MOT_TRY(run_steps(B->sweep, B->stream, lanes_of(B)));
         }
     }
     for (mot_plan_s *P : B->plans) P->host_sweeps += sweeps;

@@ -140,10 +140,11 @@ double kb_fourier(double k, const NfftParams &P);  // normalised window transfor
 // A launch step of a sweep schedule.  Steps reference device job and item arrays owned
 // by the schedule.
 enum StepKind { ST_NODE, ST_DIRECT, ST_SPREAD, ST_FOLD, ST_FFT, ST_INTERP, ST_FINAL, ST_FILL_INT,
-                ST_TRUNC };
+                ST_TRUNC, ST_FORK, ST_JOIN };
 
 struct Step {
     StepKind kind;
+    int lane = 0;                 // 1: runs on the side stream between an ST_FORK and an ST_JOIN
     int d = 0, n = 0, fft_kind = 0, precision = 0, max_patch = 0, trunc_r = 0, diff = 0;
     int group = 0;                // 3-D spreading: jobs per item (items int4)
     const void *jobs = nullptr;   // device ProdJob / NodeJob / FinalJob array
@@ -158,7 +159,19 @@ struct Step {
     int64_t fill_count = 0;
 };
 
-int run_steps(const std::vector<Step> &steps, hipStream_t s);
+// Two lanes of a sweep: steps of lane 1 run on `side`, after the ST_FORK step (which marks
+// the main stream's position) and before the ST_JOIN step (from which the main stream waits
+// for the side stream), so the two lanes' launches can overlap on the device.
+struct Lanes {
+    hipStream_t side = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+    int create();
+    void destroy();
+};
+
+// Launch the steps on s; with lanes, lane-1 steps on lanes->side.  Without lanes every step
+// runs on s in order and ST_FORK / ST_JOIN do nothing.
+int run_steps(const std::vector<Step> &steps, hipStream_t s, const Lanes *lanes = nullptr);
 
 // ---------------------------------------------------------------------------------------
 // Per-marginal device data (binned order).
@@ -259,7 +272,7 @@ struct TreeRef {
 int tree_steps(const std::vector<TreeRef> &refs, const std::vector<ProdJob> &pj, const ProdJob *pj_dev,
                const std::vector<NodeJob> &nj, const NodeJob *nj_dev, const std::vector<FinalJob> &fj,
                const FinalJob *fj_dev, Arena &arena, std::vector<Step> &sweep, std::vector<Step> &init_up,
-               std::vector<Step> &marg);
+               std::vector<Step> &marg, bool *two_lanes = nullptr);
 int tree_build_schedule(mot_plan_s *P);
 int tree_run_sweeps(mot_plan_s *P, int sweeps, bool use_graph);
 int tree_marginals(mot_plan_s *P, double *P_sorted_all);

@@ -100,6 +100,26 @@ void Arena::release()
     slab_used = slab_size = 0;
 }
 
+int Lanes::create()
+{
+    if (side) return MOT_OK;
+    // default priority (streams of different priorities are not used)
+    MOT_HIP(hipStreamCreateWithFlags(&side, hipStreamNonBlocking));
+    MOT_HIP(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
+    MOT_HIP(hipEventCreateWithFlags(&join, hipEventDisableTiming));
+    return MOT_OK;
+}
+
+void Lanes::destroy()
+{
+    if (side) (void)hipStreamSynchronize(side);
+    if (fork) (void)hipEventDestroy(fork);
+    if (join) (void)hipEventDestroy(join);
+    if (side) (void)hipStreamDestroy(side);
+    side = nullptr;
+    fork = join = nullptr;
+}
+
 void Schedule::destroy()
 {
     if (graph) (void)hipGraphExecDestroy(graph);
@@ -132,10 +152,23 @@ const float2 *device_twiddle(int n)
     return d;
 }
 
-int run_steps(const std::vector<Step> &steps, hipStream_t s)
+int run_steps(const std::vector<Step> &steps, hipStream_t s0, const Lanes *lanes)
 {
     for (const Step &st : steps) {
+        const hipStream_t s = lanes && st.lane ? lanes->side : s0;
         switch (st.kind) {
+        case ST_FORK:
+            if (lanes) {
+                MOT_HIP(hipEventRecord(lanes->fork, s0));
+                MOT_HIP(hipStreamWaitEvent(lanes->side, lanes->fork, 0));
+            }
+            break;
+        case ST_JOIN:
+            if (lanes) {
+                MOT_HIP(hipEventRecord(lanes->join, lanes->side));
+                MOT_HIP(hipStreamWaitEvent(s0, lanes->join, 0));
+            }
+            break;
         case ST_NODE:
             MOT_HIP(launch_node((const NodeJob *)st.jobs, (const int2 *)st.items, st.n_items, s));
             break;
@@ -658,39 +691,78 @@ int tree_build_schedule(mot_plan_s *P)
 int tree_steps(const std::vector<TreeRef> &refs, const std::vector<ProdJob> &pj,
                const ProdJob *pj_dev, const std::vector<NodeJob> &nj, const NodeJob *nj_dev,
                const std::vector<FinalJob> &fj, const FinalJob *fj_dev, Arena &arena,
-               std::vector<Step> &sweep, std::vector<Step> &init_up, std::vector<Step> &marg)
+               std::vector<Step> &sweep, std::vector<Step> &init_up, std::vector<Step> &marg, bool *two_lanes)
 {
     int maxD = 0;
     for (auto &r : refs) maxD = std::max(maxD, r.P->depth_max);
+    // Lanes of a batched sweep: plans do not depend on each other, so two lanes of them,
+    // balanced by their points, run on two streams between the fork and the finalisation,
+    // and one lane's latency-bound passes overlap the other's spreading and interpolation.
+    // (Splitting one plan's root subtrees the same way measured slower: the lanes' launches
+    // hold half the jobs each.)  Plan r is in lane lane[r].
+    std::vector<int> lane(refs.size(), 0);
+    const bool two = refs.size() >= 2;
+    if (two) {
+        double load[2] = {0.0, 0.0};
+        for (size_t r = 0; r < refs.size(); ++r) {
+            double pts = 0.0;
+            for (int k = 0; k < refs[r].P->K; ++k) pts += (double)refs[r].P->marg[k].n;
+            lane[r] = load[1] < load[0] ? 1 : 0;
+            load[lane[r]] += pts;
+        }
+    }
+    if (two_lanes) *two_lanes = two;
     StepBuilder B{&arena, &sweep};
-    auto nodes_at = [&](int level, int which, bool inner_only, bool nonroot) {
+    // ln = -2: every lane
+    auto nodes_at = [&](int level, int which, bool inner_only, bool nonroot, int ln = -2) {
         std::vector<int> ids;
-        for (auto &r : refs) {
+        for (size_t ri = 0; ri < refs.size(); ++ri) {
+            const TreeRef &r = refs[ri];
             const int K = r.P->K;
             for (int k = 0; k < K; ++k) {
                 if (r.P->depth[k] != level) continue;
                 if (inner_only && r.P->children[k].empty()) continue;
                 if (nonroot && k == 0) continue;
+                if (ln != -2 && lane[ri] != ln) continue;
                 ids.push_back(r.nbase + which * K + k);
             }
         }
         return ids;
     };
-    auto prods_at = [&](int level, int dir) {  // dir 0: down job (gamma_k), 1: up (beta_k)
+    auto prods_at = [&](int level, int dir, int ln = -2) {  // dir 0: down job (gamma_k), 1: up (beta_k)
         std::vector<int> ids;
-        for (auto &r : refs)
+        for (size_t ri = 0; ri < refs.size(); ++ri) {
+            const TreeRef &r = refs[ri];
             for (int k = 1; k < r.P->K; ++k)
-                if (r.P->depth[k] == level) ids.push_back(r.pbase + 2 * k + dir);
+                if (r.P->depth[k] == level && (ln == -2 || lane[ri] == ln)) ids.push_back(r.pbase + 2 * k + dir);
+        }
         return ids;
     };
     // ---- sweep
-    for (int l = 0; l <= maxD; ++l) {
-        B.node(nj_dev, nj, nodes_at(l, 0, false, false));
-        if (l < maxD) B.products(pj_dev, pj, prods_at(l + 1, 0));
-    }
-    for (int l = maxD; l >= 1; --l) {
-        B.products(pj_dev, pj, prods_at(l, 1));
-        if (l - 1 >= 1) B.node(nj_dev, nj, nodes_at(l - 1, 1, true, true));
+    if (!two) {
+        for (int l = 0; l <= maxD; ++l) {
+            B.node(nj_dev, nj, nodes_at(l, 0, false, false));
+            if (l < maxD) B.products(pj_dev, pj, prods_at(l + 1, 0));
+        }
+        for (int l = maxD; l >= 1; --l) {
+            B.products(pj_dev, pj, prods_at(l, 1));
+            if (l - 1 >= 1) B.node(nj_dev, nj, nodes_at(l - 1, 1, true, true));
+        }
+    } else {
+        sweep.push_back(Step{ST_FORK});
+        for (int ln = 0; ln < 2; ++ln) {
+            const size_t first = sweep.size();
+            for (int l = 0; l <= maxD; ++l) {
+                B.node(nj_dev, nj, nodes_at(l, 0, false, false, ln));
+                if (l < maxD) B.products(pj_dev, pj, prods_at(l + 1, 0, ln));
+            }
+            for (int l = maxD; l >= 1; --l) {
+                B.products(pj_dev, pj, prods_at(l, 1, ln));
+                if (l - 1 >= 1) B.node(nj_dev, nj, nodes_at(l - 1, 1, true, true, ln));
+            }
+            for (size_t i = first; i < sweep.size(); ++i) sweep[i].lane = ln;
+        }
+        sweep.push_back(Step{ST_JOIN});
     }
     B.final_(fj_dev, fj);
     if (B.rc < 0) return B.rc;
@@ -1502,7 +1574,11 @@ int mot_plan_profile(mot_plan P, int32_t sweeps, mot_step_timing *out, int32_t m
 {
     if (!P || sweeps < 1 || (!out && max_out > 0)) return MOT_EINVAL;
     if (P->topology != MOT_TREE) return MOT_EUNSUPPORTED;
-    const auto &steps = P->sched.sweep;
+    // every launch of the schedule, one after another on the plan's stream (the lanes'
+    // fork and join markers are not launches)
+    std::vector<Step> steps;
+    for (const Step &st : P->sched.sweep)
+        if (st.kind != ST_FORK && st.kind != ST_JOIN) steps.push_back(st);
     const size_t ns = steps.size();
     // events destroyed on every return path
     struct Events {
