@@ -353,13 +353,16 @@ int mot_plan_get_order(mot_plan plan, int32_t k, int32_t *perm_out, int32_t ptr_
  * Run `sweeps` Sinkhorn sweeps on `count` tree plans at once: every level of
  * every plan's sweep is executed by shared launches (all edges at a tree depth
  * across all plans in one set of kernels), and the whole batched sweep is
- * captured once as a HIP graph and replayed.  All plans must share one stream
+ * captured once as a HIP graph and replayed.  The plans are split into up to four lanes
+ * balanced by their points; each lane's launches go to a stream of its own (the plans'
+ * stream and up to three the batch creates, joined back into the plans' stream before the
+ * sweep's finalisation), so the lanes' kernels overlap.  All plans must share one stream
  * and use the NFFT, direct or truncated path.  Equivalent, plan by plan, to mot_sinkhorn
- * with the same sweep count and no stopping tests. */
+ * with the same sweep count and no stopping tests (bit for bit). */
 typedef struct mot_batch_s *mot_batch;
 int mot_batch_create(mot_batch *out, mot_plan *plans, int32_t count);
 int mot_batch_sinkhorn(mot_batch batch, int32_t sweeps, int32_t use_graph);
-/* Kernel launches of one batched sweep (the nodes of its graph), for reporting. */
+/* Kernel launch steps of one batched sweep (over all lanes), for reporting. */
 int mot_batch_launches(mot_batch batch);
 int mot_batch_destroy(mot_batch batch);
 

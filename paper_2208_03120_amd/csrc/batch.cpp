@@ -12,7 +12,7 @@
 struct mot_batch_s {
     std::vector<mot_plan_s *> plans;
     hipStream_t stream = nullptr;
-    mot::Lanes lanes;  // two lanes of plans (created when the batch has two or more plans)
+    mot::Lanes lanes;  // lanes of plans (created when the batch has two or more plans)
     mot::Arena arena;
     std::vector<mot::Step> sweep, init_up, marg;
     hipGraph_t graph_def = nullptr;
@@ -21,7 +21,7 @@ struct mot_batch_s {
 
 using namespace mot;
 
-static const Lanes *lanes_of(mot_batch_s *B) { return B->lanes.side ? &B->lanes : nullptr; }
+static const Lanes *lanes_of(mot_batch_s *B) { return B->lanes.n > 1 ? &B->lanes : nullptr; }
 
 extern "C" {
 
@@ -40,7 +40,7 @@ int mot_batch_destroy(mot_batch B)
 }  // extern "C"
 
 // A batch whose device memory comes from alloc (NULL: hipMalloc slabs).
-int mot::batch_create(mot_batch *out, mot_plan *plans, int32_t count, const mot_allocator *alloc)
+int mot::batch_create(mot_batch *out, mot_plan *plans, int32_t count, const mot_allocator *alloc, int max_lanes)
 {
     if (!out || !plans || count < 1) return MOT_EINVAL;
     *out = nullptr;
@@ -80,9 +80,11 @@ int mot::batch_create(mot_batch *out, mot_plan *plans, int32_t count, const mot_
                     hipMemcpy(nj_dev, nj.data(), nj.size() * sizeof(NodeJob), hipMemcpyHostToDevice) != hipSuccess ||
                     hipMemcpy(fj_dev, fj.data(), fj.size() * sizeof(FinalJob), hipMemcpyHostToDevice) != hipSuccess))
         rc = MOT_EDEVICE;
-    bool two = false;
-    if (rc >= 0) rc = tree_steps(refs, pj, pj_dev, nj, nj_dev, fj, fj_dev, B->arena, B->sweep, B->init_up, B->marg, &two);
-    if (rc >= 0 && two) rc = B->lanes.create();
+    int lanes = 1;
+    if (rc >= 0)
+        rc = tree_steps(refs, pj, pj_dev, nj, nj_dev, fj, fj_dev, B->arena, B->sweep, B->init_up, B->marg, max_lanes,
+                        &lanes);
+    if (rc >= 0 && lanes > 1) rc = B->lanes.create(lanes);
     if (rc < 0) {
         mot_batch_destroy(B);
         return rc;
@@ -103,7 +105,7 @@ extern "C" {
 
 int mot_batch_create(mot_batch *out, mot_plan *plans, int32_t count)
 {
-    return batch_create(out, plans, count, nullptr);
+    return batch_create(out, plans, count, nullptr, kLanes);
 }
 
 int mot_batch_launches(mot_batch B)

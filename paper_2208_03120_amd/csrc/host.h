@@ -144,7 +144,7 @@ enum StepKind { ST_NODE, ST_DIRECT, ST_SPREAD, ST_FOLD, ST_FFT, ST_INTERP, ST_FI
 
 struct Step {
     StepKind kind;
-    int lane = 0;                 // 1: runs on the side stream between an ST_FORK and an ST_JOIN
+    int lane = 0;                 // i >= 1: runs on side stream i - 1 between ST_FORK and ST_JOIN
     int d = 0, n = 0, fft_kind = 0, precision = 0, max_patch = 0, trunc_r = 0, diff = 0;
     int group = 0;                // 3-D spreading: jobs per item (items int4)
     const void *jobs = nullptr;   // device ProdJob / NodeJob / FinalJob array
@@ -159,18 +159,20 @@ struct Step {
     int64_t fill_count = 0;
 };
 
-// Two lanes of a sweep: steps of lane 1 run on `side`, after the ST_FORK step (which marks
-// the main stream's position) and before the ST_JOIN step (from which the main stream waits
-// for the side stream), so the two lanes' launches can overlap on the device.
+// Lanes of a sweep: steps of lane i >= 1 run on side[i - 1], after the ST_FORK step (which
+// marks the main stream's position) and before the ST_JOIN step (from which the main stream
+// waits for every side stream), so the lanes' launches can overlap on the device.
+constexpr int kLanes = 4;  // the main stream and three side streams (four hardware queues)
 struct Lanes {
-    hipStream_t side = nullptr;
-    hipEvent_t fork = nullptr, join = nullptr;
-    int create();
+    int n = 0;  // lanes including the main stream's; 0 until created
+    hipStream_t side[kLanes - 1] = {};
+    hipEvent_t fork = nullptr, join[kLanes - 1] = {};
+    int create(int lanes);
     void destroy();
 };
 
-// Launch the steps on s; with lanes, lane-1 steps on lanes->side.  Without lanes every step
-// runs on s in order and ST_FORK / ST_JOIN do nothing.
+// Launch the steps on s; with lanes, lane-i steps (i >= 1) on lanes->side[i - 1].  Without
+// lanes every step runs on s in order and ST_FORK / ST_JOIN do nothing.
 int run_steps(const std::vector<Step> &steps, hipStream_t s, const Lanes *lanes = nullptr);
 
 // ---------------------------------------------------------------------------------------
@@ -272,7 +274,7 @@ struct TreeRef {
 int tree_steps(const std::vector<TreeRef> &refs, const std::vector<ProdJob> &pj, const ProdJob *pj_dev,
                const std::vector<NodeJob> &nj, const NodeJob *nj_dev, const std::vector<FinalJob> &fj,
                const FinalJob *fj_dev, Arena &arena, std::vector<Step> &sweep, std::vector<Step> &init_up,
-               std::vector<Step> &marg, bool *two_lanes = nullptr);
+               std::vector<Step> &marg, int max_lanes = 1, int *lanes = nullptr);
 int tree_build_schedule(mot_plan_s *P);
 int tree_run_sweeps(mot_plan_s *P, int sweeps, bool use_graph);
 int tree_marginals(mot_plan_s *P, double *P_sorted_all);
@@ -292,7 +294,8 @@ int circle_pair_marginal(mot_plan_s *P, int k, double *out);
 void circle_destroy(mot_plan_s *P);
 size_t circle_footprint(int K, const int64_t *n, int path, int precision);
 // batch.cpp: a batch on an allocator of the caller's; sweeps enqueued without a wait
-int batch_create(mot_batch *out, mot_plan *plans, int32_t count, const mot_allocator *alloc);
+// max_lanes: streams the batched sweep may use (1: the batch's stream only)
+int batch_create(mot_batch *out, mot_plan *plans, int32_t count, const mot_allocator *alloc, int max_lanes);
 int batch_enqueue(mot_batch B, int sweeps);
 const float2 *device_twiddle(int n);
 }  // namespace mot

@@ -100,24 +100,31 @@ void Arena::release()
     slab_used = slab_size = 0;
 }
 
-int Lanes::create()
+int Lanes::create(int lanes)
 {
-    if (side) return MOT_OK;
-    // default priority (streams of different priorities are not used)
-    MOT_HIP(hipStreamCreateWithFlags(&side, hipStreamNonBlocking));
+    if (n) return MOT_OK;
+    n = std::max(1, std::min(lanes, kLanes));
     MOT_HIP(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
-    MOT_HIP(hipEventCreateWithFlags(&join, hipEventDisableTiming));
+    for (int i = 0; i + 1 < n; ++i) {
+        // default priority (streams of different priorities are not used)
+        MOT_HIP(hipStreamCreateWithFlags(&side[i], hipStreamNonBlocking));
+        MOT_HIP(hipEventCreateWithFlags(&join[i], hipEventDisableTiming));
+    }
     return MOT_OK;
 }
 
 void Lanes::destroy()
 {
-    if (side) (void)hipStreamSynchronize(side);
+    for (int i = 0; i + 1 < kLanes; ++i) {
+        if (side[i]) (void)hipStreamSynchronize(side[i]);
+        if (join[i]) (void)hipEventDestroy(join[i]);
+        if (side[i]) (void)hipStreamDestroy(side[i]);
+        side[i] = nullptr;
+        join[i] = nullptr;
+    }
     if (fork) (void)hipEventDestroy(fork);
-    if (join) (void)hipEventDestroy(join);
-    if (side) (void)hipStreamDestroy(side);
-    side = nullptr;
-    fork = join = nullptr;
+    fork = nullptr;
+    n = 0;
 }
 
 void Schedule::destroy()
@@ -155,19 +162,20 @@ const float2 *device_twiddle(int n)
 int run_steps(const std::vector<Step> &steps, hipStream_t s0, const Lanes *lanes)
 {
     for (const Step &st : steps) {
-        const hipStream_t s = lanes && st.lane ? lanes->side : s0;
+        const hipStream_t s = lanes && st.lane ? lanes->side[st.lane - 1] : s0;
         switch (st.kind) {
         case ST_FORK:
             if (lanes) {
                 MOT_HIP(hipEventRecord(lanes->fork, s0));
-                MOT_HIP(hipStreamWaitEvent(lanes->side, lanes->fork, 0));
+                for (int i = 0; i + 1 < lanes->n; ++i) MOT_HIP(hipStreamWaitEvent(lanes->side[i], lanes->fork, 0));
             }
             break;
         case ST_JOIN:
-            if (lanes) {
-                MOT_HIP(hipEventRecord(lanes->join, lanes->side));
-                MOT_HIP(hipStreamWaitEvent(s0, lanes->join, 0));
-            }
+            if (lanes)
+                for (int i = 0; i + 1 < lanes->n; ++i) {
+                    MOT_HIP(hipEventRecord(lanes->join[i], lanes->side[i]));
+                    MOT_HIP(hipStreamWaitEvent(s0, lanes->join[i], 0));
+                }
             break;
         case ST_NODE:
             MOT_HIP(launch_node((const NodeJob *)st.jobs, (const int2 *)st.items, st.n_items, s));
@@ -691,27 +699,29 @@ int tree_build_schedule(mot_plan_s *P)
 int tree_steps(const std::vector<TreeRef> &refs, const std::vector<ProdJob> &pj,
                const ProdJob *pj_dev, const std::vector<NodeJob> &nj, const NodeJob *nj_dev,
                const std::vector<FinalJob> &fj, const FinalJob *fj_dev, Arena &arena,
-               std::vector<Step> &sweep, std::vector<Step> &init_up, std::vector<Step> &marg, bool *two_lanes)
+               std::vector<Step> &sweep, std::vector<Step> &init_up, std::vector<Step> &marg, int max_lanes,
+               int *lanes_out)
 {
     int maxD = 0;
     for (auto &r : refs) maxD = std::max(maxD, r.P->depth_max);
-    // Lanes of a batched sweep: plans do not depend on each other, so two lanes of them,
-    // balanced by their points, run on two streams between the fork and the finalisation,
-    // and one lane's latency-bound passes overlap the other's spreading and interpolation.
-    // (Splitting one plan's root subtrees the same way measured slower: the lanes' launches
-    // hold half the jobs each.)  Plan r is in lane lane[r].
+    // Lanes of a batched sweep: plans do not depend on each other, so kLanes lanes of them,
+    // balanced by their points, run on their own streams between the fork and the
+    // finalisation, and one lane's latency-bound passes overlap another's spreading and
+    // interpolation.  (Splitting one plan's root subtrees the same way measured slower: the
+    // lanes' launches hold a fraction of the jobs each.)  Plan r is in lane lane[r].
+    const int nl = (int)std::min<size_t>(refs.size(), std::max(1, std::min(max_lanes, kLanes)));
     std::vector<int> lane(refs.size(), 0);
-    const bool two = refs.size() >= 2;
-    if (two) {
-        double load[2] = {0.0, 0.0};
+    {
+        std::vector<double> load(nl, 0.0);
         for (size_t r = 0; r < refs.size(); ++r) {
             double pts = 0.0;
             for (int k = 0; k < refs[r].P->K; ++k) pts += (double)refs[r].P->marg[k].n;
-            lane[r] = load[1] < load[0] ? 1 : 0;
+            lane[r] = (int)(std::min_element(load.begin(), load.end()) - load.begin());
             load[lane[r]] += pts;
         }
     }
-    if (two_lanes) *two_lanes = two;
+    const bool two = nl >= 2;
+    if (lanes_out) *lanes_out = nl;
     StepBuilder B{&arena, &sweep};
     // ln = -2: every lane
     auto nodes_at = [&](int level, int which, bool inner_only, bool nonroot, int ln = -2) {
@@ -750,7 +760,7 @@ int tree_steps(const std::vector<TreeRef> &refs, const std::vector<ProdJob> &pj,
         }
     } else {
         sweep.push_back(Step{ST_FORK});
-        for (int ln = 0; ln < 2; ++ln) {
+        for (int ln = 0; ln < nl; ++ln) {
             const size_t first = sweep.size();
             for (int l = 0; l <= maxD; ++l) {
                 B.node(nj_dev, nj, nodes_at(l, 0, false, false, ln));
