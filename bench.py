@@ -36,20 +36,20 @@ PEAK_FP32_TFLOPS = 157.3  # dense FP32 MFMA
 # for fold and the FFT passes also of plan.cpp, whose launch item order sets their traffic).
 COPY_MIB = 256
 TRAFFIC = {
-    "spread": {"bytes_per_launch": 231948833, "source": "k_nfft.hip",
+    "spread": {"bytes_per_launch": 231945458, "source": "k_nfft.hip",
             "sha256": "e95beabf6ee9f74433a7bef0ca9f0ae0990f9eeddcb4f03e4c0070d85db2cefe"},
-    "spread_g3": {"bytes_per_launch": 110941004, "source": "k_nfft.hip",
+    "spread_g3": {"bytes_per_launch": 110943190, "source": "k_nfft.hip",
                "sha256": "e95beabf6ee9f74433a7bef0ca9f0ae0990f9eeddcb4f03e4c0070d85db2cefe"},
-    "fold": {"bytes_per_launch": 61192852, "source": "k_nfft.hip+plan.cpp",
-          "sha256": "5985ff6cb748a32defc3bba2c89e6af9498f6c1db10912059b4366167213f36e"},
-    "interp": {"bytes_per_launch": 213287365, "source": "k_nfft.hip",
+    "interp": {"bytes_per_launch": 213232044, "source": "k_nfft.hip",
             "sha256": "e95beabf6ee9f74433a7bef0ca9f0ae0990f9eeddcb4f03e4c0070d85db2cefe"},
-    "fft6": {"bytes_per_launch": 10824014, "source": "k_fft.hip+plan.cpp",
-          "sha256": "a9b73d6135afb9b558e9ca5bb7eeb9e1057792d428a19b7816ef8dd89a0b1ab4"},
-    "fft5": {"bytes_per_launch": 26587002, "source": "k_fft.hip+plan.cpp",
-          "sha256": "a9b73d6135afb9b558e9ca5bb7eeb9e1057792d428a19b7816ef8dd89a0b1ab4"},
-    "fft7": {"bytes_per_launch": 10822490, "source": "k_fft.hip+plan.cpp",
-          "sha256": "a9b73d6135afb9b558e9ca5bb7eeb9e1057792d428a19b7816ef8dd89a0b1ab4"}
+    "fold": {"bytes_per_launch": 61193520, "source": "k_nfft.hip+plan.cpp",
+          "sha256": "470bcf05aa3bf05609d9535bd5c3359e72f0da6d883bbdbd1fffd34aa7f9ec88"},
+    "fft6": {"bytes_per_launch": 10823564, "source": "k_fft.hip+plan.cpp",
+          "sha256": "aa940acee0f5103507efa2d3d046a4e276d1cfdfbe6e0304d1c01592f302622e"},
+    "fft5": {"bytes_per_launch": 26586593, "source": "k_fft.hip+plan.cpp",
+          "sha256": "aa940acee0f5103507efa2d3d046a4e276d1cfdfbe6e0304d1c01592f302622e"},
+    "fft7": {"bytes_per_launch": 10822070, "source": "k_fft.hip+plan.cpp",
+          "sha256": "aa940acee0f5103507efa2d3d046a4e276d1cfdfbe6e0304d1c01592f302622e"}
 }
 
 
