@@ -35,7 +35,7 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 
-constexpr int kBM = 128, kBN = 128, kBK = 32, kLdsK = kBK + 8;  // padded LDS row (elements)
+constexpr int kBK = 32, kLdsK = kBK + 8;  // K step and padded LDS row (elements) of gemm_kernel
 
 __device__ __forceinline__ unsigned short bf16_bits(float x)
 {
@@ -56,84 +56,81 @@ __device__ __forceinline__ unsigned short f16_bits(float x)
 // C[M x N] (row-major, ldc) = A'[M x K] B[N x K]^T with A' from scale_rows16_kernel (lda)
 // and B the 16-bit kernel matrix (ldb), all dimensions padded to the tile sizes by the
 // caller (zero padding).  MODE: 0 BF16, 1 FP16, 2 split BF16 (hi hi + hi lo + lo hi), the
-// three products accumulated in one FP32 accumulator.  Used for small products, where one
-// fused launch beats the library's calls.
-template <int MODE>
+// three products accumulated in one FP32 accumulator.  A workgroup of four wavefronts owns a
+// BT x BT tile of C (BT = 128, or 64 for products too small to give every compute unit a
+// 128 x 128 tile), wave w the (BT/2) x (BT/2) block (w / 2, w % 2).
+template <int MODE, int BT>
 __global__ __launch_bounds__(256) void gemm_kernel(const unsigned short *__restrict__ Ah,
                                                    const unsigned short *__restrict__ Al, int lda,
                                                    const unsigned short *__restrict__ Bh,
                                                    const unsigned short *__restrict__ Bl, int ldb,
                                                    float *__restrict__ C, int ldc, int K)
 {
-    __shared__ unsigned short As[kBM * kLdsK], Bs[kBN * kLdsK];
-    __shared__ unsigned short Asl[MODE == 2 ? kBM * kLdsK : 1], Bsl[MODE == 2 ? kBN * kLdsK : 1];
+    constexpr int WT = BT / 2, FR = WT / 32;  // wave tile, 32 x 32 fragments per dimension
+    constexpr int TPR = 256 / BT, NU = 4 / TPR;  // threads per staged row, 16-byte loads each
+    __shared__ unsigned short As[BT * kLdsK], Bs[BT * kLdsK];
+    __shared__ unsigned short Asl[MODE == 2 ? BT * kLdsK : 1], Bsl[MODE == 2 ? BT * kLdsK : 1];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;  // wave's 64 x 64 sub-tile
-    const int m0 = blockIdx.y * kBM, n0 = blockIdx.x * kBN;
-    f32x16 acc[2][2];
+    const int wm = (wave >> 1) * WT, wn = (wave & 1) * WT;
+    const int m0 = blockIdx.y * BT, n0 = blockIdx.x * BT;
+    f32x16 acc[FR][FR];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < FR; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < FR; ++j)
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
-    // global staging assignment: A: row tid/2, 16 columns from (tid&1)*16; B: row tid/2, 16
-    const int ar = tid >> 1, ac = (tid & 1) * 16;
-    // the next K step's tiles are fetched into registers while the current one is multiplied
+    // global staging assignment: row tid / TPR of each operand tile, 8 NU k values from
+    // (tid % TPR) 8 NU; the next K step's tiles are fetched into registers while the current
+    // one is multiplied
+    const int ar = tid / TPR, ac = (tid % TPR) * 8 * NU;
     const unsigned short *pa = Ah + (int64_t)(m0 + ar) * lda + ac, *pb = Bh + (int64_t)(n0 + ar) * ldb + ac;
     const unsigned short *pal = MODE == 2 ? Al + (int64_t)(m0 + ar) * lda + ac : nullptr;
     const unsigned short *pbl = MODE == 2 ? Bl + (int64_t)(n0 + ar) * ldb + ac : nullptr;
-    uint4 ga0 = reinterpret_cast<const uint4 *>(pa)[0], ga1 = reinterpret_cast<const uint4 *>(pa)[1];
-    uint4 gb0 = reinterpret_cast<const uint4 *>(pb)[0], gb1 = reinterpret_cast<const uint4 *>(pb)[1];
-    uint4 gal0 = ga0, gal1 = ga1, gbl0 = gb0, gbl1 = gb1;
-    if (MODE == 2) {
-        gal0 = reinterpret_cast<const uint4 *>(pal)[0];
-        gal1 = reinterpret_cast<const uint4 *>(pal)[1];
-        gbl0 = reinterpret_cast<const uint4 *>(pbl)[0];
-        gbl1 = reinterpret_cast<const uint4 *>(pbl)[1];
+    uint4 ga[NU], gb[NU], gal[NU], gbl[NU];
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+        ga[u] = reinterpret_cast<const uint4 *>(pa)[u];
+        gb[u] = reinterpret_cast<const uint4 *>(pb)[u];
+        if (MODE == 2) {
+            gal[u] = reinterpret_cast<const uint4 *>(pal)[u];
+            gbl[u] = reinterpret_cast<const uint4 *>(pbl)[u];
+        }
     }
     for (int k0 = 0; k0 < K; k0 += kBK) {
-        {
-            uint4 *ad = reinterpret_cast<uint4 *>(&As[ar * kLdsK + ac]);
-            uint4 *bd = reinterpret_cast<uint4 *>(&Bs[ar * kLdsK + ac]);
-            ad[0] = ga0;
-            ad[1] = ga1;
-            bd[0] = gb0;
-            bd[1] = gb1;
+#pragma unroll
+        for (int u = 0; u < NU; ++u) {
+            reinterpret_cast<uint4 *>(&As[ar * kLdsK + ac])[u] = ga[u];
+            reinterpret_cast<uint4 *>(&Bs[ar * kLdsK + ac])[u] = gb[u];
             if (MODE == 2) {
-                uint4 *adl = reinterpret_cast<uint4 *>(&Asl[ar * kLdsK + ac]);
-                uint4 *bdl = reinterpret_cast<uint4 *>(&Bsl[ar * kLdsK + ac]);
-                adl[0] = gal0;
-                adl[1] = gal1;
-                bdl[0] = gbl0;
-                bdl[1] = gbl1;
+                reinterpret_cast<uint4 *>(&Asl[ar * kLdsK + ac])[u] = gal[u];
+                reinterpret_cast<uint4 *>(&Bsl[ar * kLdsK + ac])[u] = gbl[u];
             }
         }
         __syncthreads();
         if (k0 + kBK < K) {
             const int kn = k0 + kBK;
-            ga0 = reinterpret_cast<const uint4 *>(pa + kn)[0];
-            ga1 = reinterpret_cast<const uint4 *>(pa + kn)[1];
-            gb0 = reinterpret_cast<const uint4 *>(pb + kn)[0];
-            gb1 = reinterpret_cast<const uint4 *>(pb + kn)[1];
-            if (MODE == 2) {
-                gal0 = reinterpret_cast<const uint4 *>(pal + kn)[0];
-                gal1 = reinterpret_cast<const uint4 *>(pal + kn)[1];
-                gbl0 = reinterpret_cast<const uint4 *>(pbl + kn)[0];
-                gbl1 = reinterpret_cast<const uint4 *>(pbl + kn)[1];
+#pragma unroll
+            for (int u = 0; u < NU; ++u) {
+                ga[u] = reinterpret_cast<const uint4 *>(pa + kn)[u];
+                gb[u] = reinterpret_cast<const uint4 *>(pb + kn)[u];
+                if (MODE == 2) {
+                    gal[u] = reinterpret_cast<const uint4 *>(pal + kn)[u];
+                    gbl[u] = reinterpret_cast<const uint4 *>(pbl + kn)[u];
+                }
             }
         }
 #pragma unroll
         for (int ks = 0; ks < kBK; ks += 16) {
             const int kk = ks + 8 * (lane >> 5);
 #pragma unroll
-            for (int i = 0; i < 2; ++i) {
+            for (int i = 0; i < FR; ++i) {
                 const int ra = wm + 32 * i + (lane & 31);
                 const uint4 a_h = *reinterpret_cast<const uint4 *>(&As[ra * kLdsK + kk]);
                 uint4 a_l;
                 if (MODE == 2) a_l = *reinterpret_cast<const uint4 *>(&Asl[ra * kLdsK + kk]);
 #pragma unroll
-                for (int j = 0; j < 2; ++j) {
+                for (int j = 0; j < FR; ++j) {
                     const int rb = wn + 32 * j + (lane & 31);
                     const uint4 b_h = *reinterpret_cast<const uint4 *>(&Bs[rb * kLdsK + kk]);
                     if (MODE == 1) {
@@ -157,9 +154,9 @@ __global__ __launch_bounds__(256) void gemm_kernel(const unsigned short *__restr
     }
     // epilogue: acc[i][j][r] -> row wm + 32i + 8(r/4) + 4(lane/32) + r%4, col wn + 32j + lane%32
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < FR; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < FR; ++j)
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 const int row = m0 + wm + 32 * i + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
@@ -461,19 +458,20 @@ __global__ void kernel_matrix_kernel(const double *__restrict__ xa, int64_t na, 
 }
 
 // Column sums with FP64 accumulation (Theorem 4.3's row-wise inner products, stored
-// transposed): part[ch][j] = sum_{i in chunk ch} Yb[i][j] w_i Yg[i][j] over kColRows rows,
-// ascending, with w_i = phi^0_i 2^(sb[i] + sg[i]) formed here (sb, sg: the two matrices'
-// row scales on the dense path; NULL on the NFFT path).  One column per thread.
-constexpr int kColRows = 64;
+// transposed): part[ch][j] = sum_{i in chunk ch} Yb[i][j] w_i Yg[i][j] over the chunk's
+// chunk_rows rows (at most kColRows), ascending, with w_i = phi^0_i 2^(sb[i] + sg[i]) formed
+// here (sb, sg: the two matrices' row scales on the dense path; NULL on the NFFT path).
+// One column per thread.
+constexpr int kColRows = 64, kColRowsMin = 16;
 template <class T>
 __global__ __launch_bounds__(256) void colsum_kernel(const T *__restrict__ Yb, const T *__restrict__ Yg, int ld,
                                                      int64_t n1, int64_t nk, const double *__restrict__ phi0,
                                                      const int32_t *__restrict__ sb, const int32_t *__restrict__ sg,
-                                                     double *__restrict__ part)
+                                                     int chunk_rows, double *__restrict__ part)
 {
     __shared__ double w[kColRows];
-    const int64_t i0 = (int64_t)blockIdx.y * kColRows;
-    const int rows = (int)min((int64_t)kColRows, n1 - i0);
+    const int64_t i0 = (int64_t)blockIdx.y * chunk_rows;
+    const int rows = (int)min((int64_t)chunk_rows, n1 - i0);
     if ((int)threadIdx.x < rows) {
         const int64_t i = i0 + threadIdx.x;
         w[threadIdx.x] = sb ? ldexp(phi0[i], sb[i] + sg[i]) : phi0[i];
@@ -691,11 +689,33 @@ static int32_t *Yscale(CircleState &C, int which_gamma, int k)  // dense path on
 // the products take gemm_big_kernel), of 128 below.
 static int dense_pad(int64_t n) { return n >= 1024 ? pad_to(n, 256) : pad_to(n, 128); }
 
+// Tile edge of a dense product's GEMM: 256 (gemm_big_kernel / gemm_big_split_kernel) when
+// M, N and K are multiples of 256, 256 and 128 and the product has at least kBigMinTiles
+// such tiles; else 128 when that still gives each compute unit a tile, else 64 (gemm_kernel).
+constexpr int kBigMinTiles = 64, kGemmUnits = 256;
+static int gemm_tile(int Mp, int Np, int Kp)
+{
+    if (Mp % kBigT == 0 && Np % kBigT == 0 && Kp % (4 * kBigK) == 0 && (Mp / kBigT) * (Np / kBigT) >= kBigMinTiles)
+        return kBigT;
+    return (Mp / 128) * (Np / 128) >= kGemmUnits ? 128 : 64;
+}
+
+template <int MODE>
+static void launch_gemm_small(int tile, const unsigned short *Ah, const unsigned short *Al, int lda,
+                              const unsigned short *Bh, const unsigned short *Bl, int ldb, float *Cm, int ldc, int Mp,
+                              int Np, int Kp, hipStream_t s)
+{
+    if (tile == 128)
+        hipLaunchKernelGGL((gemm_kernel<MODE, 128>), dim3(Np / 128, Mp / 128), dim3(256), 0, s, Ah, Al, lda, Bh, Bl,
+                           ldb, Cm, ldc, Kp);
+    else
+        hipLaunchKernelGGL((gemm_kernel<MODE, 64>), dim3(Np / 64, Mp / 64), dim3(256), 0, s, Ah, Al, lda, Bh, Bl, ldb,
+                           Cm, ldc, Kp);
+}
+
 // One product of the recursions on the dense path: the row scales and the scaled left
 // operand A' = diag(2^-rexp) A diag(phi) in 16-bit form in one pass, then C = A' B^T with 16-bit
-// operands and FP32 accumulation and output: one launch of gemm_big_kernel /
-// gemm_big_split_kernel when M, N and K are multiples of 256, 256 and 128, else of the
-// 128 x 128-tile gemm_kernel.
+// operands and FP32 accumulation and output in one GEMM launch of the tile gemm_tile picks.
 static hipError_t launch_gemm(const CircleState &C, const float *A, int lda, const double *phi,
                               const unsigned short *Bh, const unsigned short *Bl, int ldb, float *Cm,
                               int ldc, int Mp, int Np, int Kp, const int32_t *s_in, int32_t *s_out,
@@ -710,7 +730,8 @@ static hipError_t launch_gemm(const CircleState &C, const float *A, int lda, con
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const unsigned short *Ah = C.Ah, *Al = C.Al;
-    if (Mp % kBigT == 0 && Np % kBigT == 0 && Kp % (4 * kBigK) == 0) {
+    const int tile = gemm_tile(Mp, Np, Kp);
+    if (tile == kBigT) {
         const int tm = Mp / kBigT, tn = Np / kBigT;
         const dim3 grid((unsigned)(tm * tn)), block(64 * kBigWaves);
         if (C.mode == 2)
@@ -722,13 +743,12 @@ static hipError_t launch_gemm(const CircleState &C, const float *A, int lda, con
             hipLaunchKernelGGL(gemm_big_kernel<0>, grid, block, 0, s, Ah, lda, Bh, ldb, Cm, ldc, Kp, tm, tn);
         return hipGetLastError();
     }
-    const dim3 grid(Np / kBN, Mp / kBM);
     if (C.mode == 1)
-        hipLaunchKernelGGL(gemm_kernel<1>, grid, dim3(256), 0, s, Ah, Al, lda, Bh, Bl, ldb, Cm, ldc, Kp);
+        launch_gemm_small<1>(tile, Ah, Al, lda, Bh, Bl, ldb, Cm, ldc, Mp, Np, Kp, s);
     else if (C.mode == 2)
-        hipLaunchKernelGGL(gemm_kernel<2>, grid, dim3(256), 0, s, Ah, Al, lda, Bh, Bl, ldb, Cm, ldc, Kp);
+        launch_gemm_small<2>(tile, Ah, Al, lda, Bh, Bl, ldb, Cm, ldc, Mp, Np, Kp, s);
     else
-        hipLaunchKernelGGL(gemm_kernel<0>, grid, dim3(256), 0, s, Ah, Al, lda, Bh, Bl, ldb, Cm, ldc, Kp);
+        launch_gemm_small<0>(tile, Ah, Al, lda, Bh, Bl, ldb, Cm, ldc, Mp, Np, Kp, s);
     return hipGetLastError();
 }
 
@@ -753,21 +773,32 @@ static int circle_product(mot_plan_s *P, CircleState &C, int gamma, int k)
     return run_steps(gamma ? C.steps_g[k] : C.steps_b[k], st);
 }
 
+// Rows per chunk of a column sum: kColRows, halved down to kColRowsMin while the launch
+// has fewer than 512 workgroups (small products are bound by the latency of the chunk's
+// sequential loads, not by bandwidth).
+static int colsum_rows(int64_t n1, int64_t nk)
+{
+    int rows = kColRows;
+    while (rows > kColRowsMin && ((nk + 255) / 256) * ((n1 + rows - 1) / rows) < 512) rows /= 2;
+    return rows;
+}
+
 static int colsum_phi(mot_plan_s *P, CircleState &C, int k, bool marg_only)
 {
     hipStream_t st = P->stream;
     const int64_t n1 = C.n1, nk = P->n[k];
-    const int chunks = (int)((n1 + kColRows - 1) / kColRows);
+    const int rows = colsum_rows(n1, nk);
+    const int chunks = (int)((n1 + rows - 1) / rows);
     const dim3 g((unsigned)((nk + 255) / 256), (unsigned)chunks);
     const void *Yb = C.Yb[k], *Yg = Ymat(C, 1, k);
     if (C.nfft)
         hipLaunchKernelGGL(colsum_kernel<double>, g, dim3(256), 0, st, (const double *)Yb, (const double *)Yg, C.ld[k],
                            n1, nk, (const double *)P->marg[0].phi, (const int32_t *)nullptr, (const int32_t *)nullptr,
-                           C.part);
+                           rows, C.part);
     else
         hipLaunchKernelGGL(colsum_kernel<float>, g, dim3(256), 0, st, (const float *)Yb, (const float *)Yg, C.ld[k],
                            n1, nk, (const double *)P->marg[0].phi, (const int32_t *)Yscale(C, 0, k),
-                           (const int32_t *)Yscale(C, 1, k), C.part);
+                           (const int32_t *)Yscale(C, 1, k), rows, C.part);
     MOT_HIP(hipGetLastError());
     const unsigned blocks = (unsigned)((nk + 255) / 256);
     double *sout = marg_only ? C.m_part : C.s_part + 2 * C.s_slot[k];
@@ -917,7 +948,7 @@ int circle_create(mot_plan_s *P, const std::vector<double> &pts_h, const std::ve
         MOT_TRY(P->arena.get_n((size_t)C.n1p, &C.szero));
         MOT_HIP(launch_fill_int(C.szero, 0, C.n1p, st));
     }
-    const int chunks = (int)((C.n1 + kColRows - 1) / kColRows);
+    const int chunks = (int)((C.n1 + kColRowsMin - 1) / kColRowsMin);  // at most, for any rows per chunk
     MOT_TRY(P->arena.get_n((size_t)chunks * nmax, &C.part));
     MOT_TRY(P->arena.get_n((size_t)C.n1, &C.den0));
     C.s_slot.assign(K, 0);
@@ -1050,6 +1081,7 @@ size_t circle_footprint(int K, const int64_t *n, int path, int precision)
         b += (size_t)n1 * ldmax * 2 * parts;                       // scaled left operand
     }
     else b += (size_t)n1 * ldmax * 8 + (size_t)n1 * 8;  // product sources, row exponents
+    b += (size_t)((n[0] + kColRowsMin - 1) / kColRowsMin) * ldmax * 8;  // column-sum partials
     return b;
 }
 
