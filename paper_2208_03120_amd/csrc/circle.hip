@@ -15,8 +15,9 @@
 // the 16-bit operand (scale_rows16_kernel); C = A' B^T is then a 16-bit GEMM with FP32
 // accumulation and output on the MFMA units (v_mfma_f32_32x32x16_bf16 / _f16):
 // gemm_big_kernel / gemm_big_split_kernel for products whose dimensions are multiples of
-// 256, gemm_kernel otherwise.  Precision modes: BF16, FP16 and split
-// BF16 (A' = Ah + Al, B = Bh + Bl, C = Ah Bh + Ah Bl + Al Bh).  The
+// 256 with enough 256 x 256 tiles to fill the chip, gemm_kernel (64 x 64 tiles) otherwise.
+// Precision modes: BF16, FP16 and split BF16 (A' = Ah + Al, B = Bh + Bl,
+// C = Ah Bh + Ah Bl + Al Bh).  The
 // FP32 matrices carry a power-of-two scale per row: before each product the rows of
 // A diag(phi) are normalised (exponent of their largest entry, taken in FP64) and the
 // exponent is added to the row's scale, so long chains of products (K up to thousands of
@@ -57,16 +58,18 @@ __device__ __forceinline__ unsigned short f16_bits(float x)
 // and B the 16-bit kernel matrix (ldb), all dimensions padded to the tile sizes by the
 // caller (zero padding).  MODE: 0 BF16, 1 FP16, 2 split BF16 (hi hi + hi lo + lo hi), the
 // three products accumulated in one FP32 accumulator.  A workgroup of four wavefronts owns a
-// BT x BT tile of C (BT = 128, or 64 for products too small to give every compute unit a
-// 128 x 128 tile), wave w the (BT/2) x (BT/2) block (w / 2, w % 2).
-template <int MODE, int BT>
+// BT x BT tile of C, wave w the (BT/2) x (BT/2) block (w / 2, w % 2).  BT = 64: a 128 x 128
+// tile (64 x 64 per wave) ran slower at every measured shape, from 512 to 2304 rows (fewer
+// workgroups to hide the latency of the register-staged loads).
+constexpr int kSmallT = 64;
+template <int MODE>
 __global__ __launch_bounds__(256) void gemm_kernel(const unsigned short *__restrict__ Ah,
                                                    const unsigned short *__restrict__ Al, int lda,
                                                    const unsigned short *__restrict__ Bh,
                                                    const unsigned short *__restrict__ Bl, int ldb,
                                                    float *__restrict__ C, int ldc, int K)
 {
-    constexpr int WT = BT / 2, FR = WT / 32;  // wave tile, 32 x 32 fragments per dimension
+    constexpr int BT = kSmallT, WT = BT / 2, FR = WT / 32;  // wave tile, 32 x 32 fragments per dimension
     constexpr int TPR = 256 / BT, NU = 4 / TPR;  // threads per staged row, 16-byte loads each
     __shared__ unsigned short As[BT * kLdsK], Bs[BT * kLdsK];
     __shared__ unsigned short Asl[MODE == 2 ? BT * kLdsK : 1], Bsl[MODE == 2 ? BT * kLdsK : 1];
@@ -167,7 +170,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(const unsigned short *__restr
 
 // ---------------------------------------------------------------------------------------
 // Large products, C[M x N] = A'[M x K] B[N x K]^T with M and N multiples of 256 and K of
-// 128 (the dense matrices of at least 1024 points are padded to 256).  A workgroup of 16
+// 128 (the dense matrices of at least 2048 points are padded to 256).  A workgroup of 16
 // wavefronts owns a 256 x 256 tile of C, wave w the 64 x 64 block (w / 4, w % 4): per k16
 // step two A and two B fragments from LDS and four 32x32x16 MFMAs.  Operand tiles of 256
 // rows x 32 k move from global memory straight into LDS with global_load_lds_dwordx4 (no
@@ -685,37 +688,25 @@ static int32_t *Yscale(CircleState &C, int which_gamma, int k)  // dense path on
     return k == C.K - 1 ? C.szero : C.sb[k];
 }
 
-// Rows and columns of the dense path's matrices: multiples of 256 from 1024 points on (so
-// the products take gemm_big_kernel), of 128 below.
-static int dense_pad(int64_t n) { return n >= 1024 ? pad_to(n, 256) : pad_to(n, 128); }
+// Rows and columns of the dense path's matrices: multiples of 256 from 2048 points on (the
+// shapes gemm_big can take), of 64 (gemm_kernel's tile) below.
+static int dense_pad(int64_t n) { return n >= 2048 ? pad_to(n, 256) : pad_to(n, 64); }
 
-// Tile edge of a dense product's GEMM: 256 (gemm_big_kernel / gemm_big_split_kernel) when
-// M, N and K are multiples of 256, 256 and 128 and the product has at least kBigMinTiles
-// such tiles; else 128 when that still gives each compute unit a tile, else 64 (gemm_kernel).
-constexpr int kBigMinTiles = 64, kGemmUnits = 256;
-static int gemm_tile(int Mp, int Np, int Kp)
+// A dense product's GEMM runs on gemm_big_kernel / gemm_big_split_kernel when M, N and K
+// are multiples of 256, 256 and 128 and the product has at least kBigMinTiles tiles of
+// 256 x 256, else on the 64 x 64 tiles of gemm_kernel.  Below about 96 tiles the large
+// kernel leaves most compute units idle: at 81 tiles (2304 rows) split BF16 ran 857 sweeps/s
+// on it and 1095 on the small tiles; at 121 tiles (2816 rows) 692 against 617.
+constexpr int kBigMinTiles = 96;
+static bool gemm_big(int Mp, int Np, int Kp)
 {
-    if (Mp % kBigT == 0 && Np % kBigT == 0 && Kp % (4 * kBigK) == 0 && (Mp / kBigT) * (Np / kBigT) >= kBigMinTiles)
-        return kBigT;
-    return (Mp / 128) * (Np / 128) >= kGemmUnits ? 128 : 64;
-}
-
-template <int MODE>
-static void launch_gemm_small(int tile, const unsigned short *Ah, const unsigned short *Al, int lda,
-                              const unsigned short *Bh, const unsigned short *Bl, int ldb, float *Cm, int ldc, int Mp,
-                              int Np, int Kp, hipStream_t s)
-{
-    if (tile == 128)
-        hipLaunchKernelGGL((gemm_kernel<MODE, 128>), dim3(Np / 128, Mp / 128), dim3(256), 0, s, Ah, Al, lda, Bh, Bl,
-                           ldb, Cm, ldc, Kp);
-    else
-        hipLaunchKernelGGL((gemm_kernel<MODE, 64>), dim3(Np / 64, Mp / 64), dim3(256), 0, s, Ah, Al, lda, Bh, Bl, ldb,
-                           Cm, ldc, Kp);
+    return Mp % kBigT == 0 && Np % kBigT == 0 && Kp % (4 * kBigK) == 0 &&
+           (Mp / kBigT) * (Np / kBigT) >= kBigMinTiles;
 }
 
 // One product of the recursions on the dense path: the row scales and the scaled left
 // operand A' = diag(2^-rexp) A diag(phi) in 16-bit form in one pass, then C = A' B^T with 16-bit
-// operands and FP32 accumulation and output in one GEMM launch of the tile gemm_tile picks.
+// operands and FP32 accumulation and output in one GEMM launch (tile chosen by gemm_big).
 static hipError_t launch_gemm(const CircleState &C, const float *A, int lda, const double *phi,
                               const unsigned short *Bh, const unsigned short *Bl, int ldb, float *Cm,
                               int ldc, int Mp, int Np, int Kp, const int32_t *s_in, int32_t *s_out,
@@ -730,8 +721,7 @@ static hipError_t launch_gemm(const CircleState &C, const float *A, int lda, con
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const unsigned short *Ah = C.Ah, *Al = C.Al;
-    const int tile = gemm_tile(Mp, Np, Kp);
-    if (tile == kBigT) {
+    if (gemm_big(Mp, Np, Kp)) {
         const int tm = Mp / kBigT, tn = Np / kBigT;
         const dim3 grid((unsigned)(tm * tn)), block(64 * kBigWaves);
         if (C.mode == 2)
@@ -743,12 +733,13 @@ static hipError_t launch_gemm(const CircleState &C, const float *A, int lda, con
             hipLaunchKernelGGL(gemm_big_kernel<0>, grid, block, 0, s, Ah, lda, Bh, ldb, Cm, ldc, Kp, tm, tn);
         return hipGetLastError();
     }
+    const dim3 grid(Np / kSmallT, Mp / kSmallT);
     if (C.mode == 1)
-        launch_gemm_small<1>(tile, Ah, Al, lda, Bh, Bl, ldb, Cm, ldc, Mp, Np, Kp, s);
+        hipLaunchKernelGGL(gemm_kernel<1>, grid, dim3(256), 0, s, Ah, Al, lda, Bh, Bl, ldb, Cm, ldc, Kp);
     else if (C.mode == 2)
-        launch_gemm_small<2>(tile, Ah, Al, lda, Bh, Bl, ldb, Cm, ldc, Mp, Np, Kp, s);
+        hipLaunchKernelGGL(gemm_kernel<2>, grid, dim3(256), 0, s, Ah, Al, lda, Bh, Bl, ldb, Cm, ldc, Kp);
     else
-        launch_gemm_small<0>(tile, Ah, Al, lda, Bh, Bl, ldb, Cm, ldc, Mp, Np, Kp, s);
+        hipLaunchKernelGGL(gemm_kernel<0>, grid, dim3(256), 0, s, Ah, Al, lda, Bh, Bl, ldb, Cm, ldc, Kp);
     return hipGetLastError();
 }
 

@@ -92,14 +92,14 @@ def test_dense_long_cycle_stays_in_range(mot, long_cycle, prec, bound):
 
 
 @pytest.mark.parametrize("prec,bound", [("BF16X3", 1e-5), ("FP16", 5e-4), ("BF16", 5e-3)])
-@pytest.mark.parametrize("sizes", [[2100, 2050, 2080], [1400, 1380, 1410], [1100, 600, 1300], [6600, 600, 620]])
+@pytest.mark.parametrize("sizes", [[2600, 2550, 2580], [2100, 2050, 2080], [1400, 1380, 1410],
+                                   [1100, 600, 1300], [6600, 600, 620]])
 def test_dense_circle_large_gemm(mot, prec, bound, sizes):
-    """K = 3 on each GEMM tile: 2100 points (padded to 2304, 81 tiles of 256 x 256) run on
-    the 256 x 256-tile kernel; 1400 points (1536, only 36 such tiles) and 1100 / 600 / 1300
-    points (1280, 640, 1536) on the 64 x 64 tile; 6600 / 600 / 620 points (6656 x 640
-    products: 260 tiles of 128 x 128, a dimension no multiple of 256) on the 128 x 128 tile.
-    Marginals at the plan's own scaling vectors after 3 sweeps against the FP64 oracle's at
-    the same phi."""
+    """K = 3 on both GEMM kernels: 2600 points (padded to 2816, 121 tiles of 256 x 256) run
+    on the 256 x 256-tile kernel; 2100 points (2304, 81 such tiles: too few), 1400 points
+    (padded to 1408), 1100 / 600 / 1300 points (1152, 640, 1344) and 6600 / 600 / 620 points
+    (6656 x 640 products) on the 64 x 64 tiles.  Marginals at the plan's own scaling vectors
+    after 3 sweeps against the FP64 oracle's at the same phi."""
     inst = W.make_instance(rng(59), 3, sizes, 2, W.CIRCLE, 0.1)
     p = getattr(mot, "PREC_" + prec)
     plan = mot.Plan(inst.points, inst.weights, W.CIRCLE, None, inst.eta, path=mot.DENSE, precision=p)
