@@ -302,16 +302,18 @@ __global__ __launch_bounds__(64 * kBigWaves, 1) void gemm_big_kernel(const unsig
 }
 
 // Split BF16: Ah Bh + Ah Bl + Al Bh in one accumulator per block (three MFMAs per fragment
-// pair).  A stage holds four operand tiles (64 KB), so two stages in one dynamic LDS
-// buffer: tile kt + 1 is requested while tile kt is multiplied, and the barrier (with its
-// wait for every load of the wave) separates the steps.
+// pair).  A stage holds four operand tiles (64 KB), so two stages, each its own __shared__
+// object as in gemm_big_kernel (with both in one array the compiler waits for the next
+// tile's loads before every read of the current one): tile kt + 1 is requested while tile
+// kt is multiplied, and the barrier (with its wait for every load of the wave) separates the
+// steps.  K is a multiple of 4 kBigK.
 __global__ __launch_bounds__(64 * kBigWaves, 1) void gemm_big_split_kernel(
     const unsigned short *__restrict__ Ah, const unsigned short *__restrict__ Al, int lda,
     const unsigned short *__restrict__ Bh, const unsigned short *__restrict__ Bl, int ldb, float *__restrict__ C,
     int ldc, int K, int tiles_m, int tiles_n)
 {
     constexpr int TILE = kBigT * kBigK, STAGE = 4 * TILE;  // Ah, Bh, Al, Bl
-    extern __shared__ __align__(16) unsigned short big_lds[];
+    __shared__ __align__(16) unsigned short t0[STAGE], t1[STAGE];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wm = (wave >> 2) * 64, wn = (wave & 3) * 64;
     int m0, n0;
@@ -323,18 +325,12 @@ __global__ __launch_bounds__(64 * kBigWaves, 1) void gemm_big_split_kernel(
         for (int j = 0; j < 2; ++j)
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
-    auto issue = [&](int kt, int st) {
-        unsigned short *s = big_lds + st * STAGE;
+    auto issue = [&](int kt, unsigned short *s) {
         big_issue(Ah, lda, Bh, ldb, m0, n0, kt * kBigK, s, s + TILE, wave, lane);
         big_issue(Al, lda, Bl, ldb, m0, n0, kt * kBigK, s + 2 * TILE, s + 3 * TILE, wave, lane);
     };
-    const int nk = K / kBigK;
-    issue(0, 0);
-    for (int kt = 0; kt < nk; ++kt) {
-        __syncthreads();  // tile kt in LDS for every wave; tile kt - 1 no longer read
-        if (kt + 1 < nk) issue(kt + 1, (kt + 1) & 1);
-        const unsigned short *sAh = big_lds + (kt & 1) * STAGE, *sBh = sAh + TILE, *sAl = sAh + 2 * TILE,
-                             *sBl = sAh + 3 * TILE;
+    auto mult = [&](const unsigned short *sAh) {
+        const unsigned short *sBh = sAh + TILE, *sAl = sAh + 2 * TILE, *sBl = sAh + 3 * TILE;
 #pragma unroll
         for (int ks = 0; ks < kBigK; ks += 16) {
             uint4 ah[2], al[2], bh[2], bl[2];
@@ -354,6 +350,16 @@ __global__ __launch_bounds__(64 * kBigWaves, 1) void gemm_big_split_kernel(
                     acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, al[i]), __builtin_bit_cast(bf16x8, bh[j]), acc[i][j], 0, 0, 0);
                 }
         }
+    };
+    const int nk = K / kBigK;  // even
+    issue(0, t0);
+    for (int kt = 0; kt < nk; kt += 2) {
+        __syncthreads();  // tile kt in t0 for every wave; t1 no longer read
+        issue(kt + 1, t1);
+        mult(t0);
+        __syncthreads();  // tile kt + 1 in t1; t0 no longer read
+        if (kt + 2 < nk) issue(kt + 2, t0);
+        mult(t1);
     }
     big_store(acc, C, ldc, m0, n0, wm, wn, lane);
 }
@@ -725,8 +731,7 @@ static hipError_t launch_gemm(const CircleState &C, const float *A, int lda, con
         const int tm = Mp / kBigT, tn = Np / kBigT;
         const dim3 grid((unsigned)(tm * tn)), block(64 * kBigWaves);
         if (C.mode == 2)
-            hipLaunchKernelGGL(gemm_big_split_kernel, grid, block, 2 * 4 * kBigT * kBigK * sizeof(unsigned short), s,
-                               Ah, Al, lda, Bh, Bl, ldb, Cm, ldc, Kp, tm, tn);
+            hipLaunchKernelGGL(gemm_big_split_kernel, grid, block, 0, s, Ah, Al, lda, Bh, Bl, ldb, Cm, ldc, Kp, tm, tn);
         else if (C.mode == 1)
             hipLaunchKernelGGL(gemm_big_kernel<1>, grid, block, 0, s, Ah, lda, Bh, ldb, Cm, ldc, Kp, tm, tn);
         else
@@ -928,9 +933,6 @@ int circle_create(mot_plan_s *P, const std::vector<double> &pts_h, const std::ve
         MOT_TRY(P->arena.get_n((size_t)C.n1p, &C.rexp));
         MOT_TRY(P->arena.get_n((size_t)C.n1p * ldmax, &C.Ah));
         if (C.mode == 2) MOT_TRY(P->arena.get_n((size_t)C.n1p * ldmax, &C.Al));
-        // the split kernel's two stages of four operand tiles live in dynamic LDS (128 KB)
-        MOT_HIP(hipFuncSetAttribute((const void *)gemm_big_split_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    2 * 4 * kBigT * kBigK * (int)sizeof(unsigned short)));
         C.K = K;
         C.sb.assign(K, nullptr);
         for (int k = 1; k < K - 1; ++k) MOT_TRY(P->arena.get_n((size_t)C.n1p, &C.sb[k]));
