@@ -125,10 +125,23 @@ int mot_batch_sinkhorn(mot_batch B, int32_t sweeps, int32_t use_graph)
     if (use_graph && !B->graph && sweeps > 0) {
         MOT_HIP(hipStreamBeginCapture(B->stream, hipStreamCaptureModeThreadLocal));
         int rc = run_steps(B->sweep, B->stream, lanes_of(B));
-        hipError_t e = hipStreamEndCapture(B->stream, &B->graph_def);
-        if (rc < 0) return rc;
-        MOT_HIP(e);
-        MOT_HIP(hipGraphInstantiate(&B->graph, B->graph_def, nullptr, nullptr, 0));
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(B->stream, &g);
+        if (e == hipErrorStreamCaptureInvalidated) {
+            // other work of the process invalidated the capture; none of its launches ran:
+            // this call sweeps without the graph, the next one captures again
+            if (g) (void)hipGraphDestroy(g);
+            (void)hipGetLastError();
+            use_graph = 0;
+        } else {
+            if (rc < 0) {
+                if (g) (void)hipGraphDestroy(g);
+                return rc;
+            }
+            MOT_HIP(e);
+            B->graph_def = g;
+            MOT_HIP(hipGraphInstantiate(&B->graph, B->graph_def, nullptr, nullptr, 0));
+        }
     }
     for (int r = 0; r < sweeps; ++r) {
         if (use_graph) {

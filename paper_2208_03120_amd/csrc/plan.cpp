@@ -1242,10 +1242,21 @@ int tree_run_sweeps(mot_plan_s *P, int sweeps, bool use_graph)
         MOT_HIP(hipStreamBeginCapture(P->stream, hipStreamCaptureModeThreadLocal));
         int rc = run_steps(P->sched.sweep, P->stream);
         hipError_t e = hipStreamEndCapture(P->stream, &g);
-        if (rc < 0) return rc;
-        MOT_HIP(e);
-        MOT_HIP(hipGraphInstantiate(&P->sched.graph, g, nullptr, nullptr, 0));
-        P->sched.graph_def = g;
+        if (e == hipErrorStreamCaptureInvalidated) {
+            // other work of the process invalidated the capture; none of its launches ran:
+            // this call sweeps without the graph, the next one captures again
+            if (g) (void)hipGraphDestroy(g);
+            (void)hipGetLastError();
+            use_graph = false;
+        } else {
+            if (rc < 0) {
+                if (g) (void)hipGraphDestroy(g);
+                return rc;
+            }
+            MOT_HIP(e);
+            MOT_HIP(hipGraphInstantiate(&P->sched.graph, g, nullptr, nullptr, 0));
+            P->sched.graph_def = g;
+        }
     }
     for (int r = 0; r < sweeps; ++r) {
         if (use_graph) {
