@@ -57,25 +57,40 @@ __device__ __forceinline__ unsigned short f16_bits(float x)
 // C[M x N] (row-major, ldc) = A'[M x K] B[N x K]^T with A' from scale_rows16_kernel (lda)
 // and B the 16-bit kernel matrix (ldb), all dimensions padded to the tile sizes by the
 // caller (zero padding).  MODE: 0 BF16, 1 FP16, 2 split BF16 (hi hi + hi lo + lo hi), the
-// three products accumulated in one FP32 accumulator.  A workgroup of four wavefronts owns a
+// three products accumulated in one FP32 accumulator.  A group of four wavefronts owns a
 // BT x BT tile of C, wave w the (BT/2) x (BT/2) block (w / 2, w % 2).  BT = 64: a 128 x 128
 // tile (64 x 64 per wave) ran slower at every measured shape, from 512 to 2304 rows (fewer
 // workgroups to hide the latency of the register-staged loads).
+//
+// A workgroup holds KS such groups that split the K steps of its tile: group g takes the
+// contiguous steps [g S / KS, (g + 1) S / KS) of the S = K / kBK, and the groups'
+// accumulators are added in group order through LDS at the end.  Each K step waits on a
+// round trip of its operand loads and holds little MFMA work, so a product with few tiles
+// (a few hundred rows) is bound by that chain; KS > 1 shortens it without another launch
+// and keeps the sum order fixed for a given shape.
 constexpr int kSmallT = 64;
-template <int MODE>
-__global__ __launch_bounds__(256) void gemm_kernel(const unsigned short *__restrict__ Ah,
-                                                   const unsigned short *__restrict__ Al, int lda,
-                                                   const unsigned short *__restrict__ Bh,
-                                                   const unsigned short *__restrict__ Bl, int ldb,
-                                                   float *__restrict__ C, int ldc, int K)
+template <int MODE, int KS>
+__global__ __launch_bounds__(256 * KS) void gemm_kernel(const unsigned short *__restrict__ Ah,
+                                                        const unsigned short *__restrict__ Al, int lda,
+                                                        const unsigned short *__restrict__ Bh,
+                                                        const unsigned short *__restrict__ Bl, int ldb,
+                                                        float *__restrict__ C, int ldc, int K)
 {
     constexpr int BT = kSmallT, WT = BT / 2, FR = WT / 32;  // wave tile, 32 x 32 fragments per dimension
     constexpr int TPR = 256 / BT, NU = 4 / TPR;  // threads per staged row, 16-byte loads each
-    __shared__ unsigned short As[BT * kLdsK], Bs[BT * kLdsK];
-    __shared__ unsigned short Asl[MODE == 2 ? BT * kLdsK : 1], Bsl[MODE == 2 ? BT * kLdsK : 1];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    constexpr int TS = BT * kLdsK;               // one staged operand tile (elements)
+    constexpr int NOP = MODE == 2 ? 4 : 2;       // staged operands: Ah, Bh (, Al, Bl)
+    // the LDS holds the groups' staged tiles, and at the end the partial accumulators of
+    // groups 1 .. KS-1 (16 floats per lane)
+    constexpr int kPart = (KS - 1) * 4 * 64 * 16 * 2, kStaged = KS * NOP * TS;
+    static_assert(FR == 1, "one 32 x 32 accumulator per wave");
+    __shared__ __align__(16) unsigned short lds[kStaged > kPart ? kStaged : kPart];
+    const int grp = KS == 1 ? 0 : (int)(threadIdx.x >> 8), tid = threadIdx.x & 255, lane = tid & 63, wave = tid >> 6;
+    unsigned short *As = lds + grp * NOP * TS, *Bs = As + TS, *Asl = As + 2 * TS, *Bsl = As + 3 * TS;
     const int wm = (wave >> 1) * WT, wn = (wave & 1) * WT;
     const int m0 = blockIdx.y * BT, n0 = blockIdx.x * BT;
+    const int steps = K / kBK, s_lo = grp * steps / KS, s_hi = (grp + 1) * steps / KS;
+    const int s_max = (steps + KS - 1) / KS;  // every group runs s_max rounds (barriers are block-wide)
     f32x16 acc[FR][FR];
 #pragma unroll
     for (int i = 0; i < FR; ++i)
@@ -91,69 +106,81 @@ __global__ __launch_bounds__(256) void gemm_kernel(const unsigned short *__restr
     const unsigned short *pal = MODE == 2 ? Al + (int64_t)(m0 + ar) * lda + ac : nullptr;
     const unsigned short *pbl = MODE == 2 ? Bl + (int64_t)(n0 + ar) * ldb + ac : nullptr;
     uint4 ga[NU], gb[NU], gal[NU], gbl[NU];
-#pragma unroll
-    for (int u = 0; u < NU; ++u) {
-        ga[u] = reinterpret_cast<const uint4 *>(pa)[u];
-        gb[u] = reinterpret_cast<const uint4 *>(pb)[u];
-        if (MODE == 2) {
-            gal[u] = reinterpret_cast<const uint4 *>(pal)[u];
-            gbl[u] = reinterpret_cast<const uint4 *>(pbl)[u];
-        }
-    }
-    for (int k0 = 0; k0 < K; k0 += kBK) {
+    auto fetch = [&](int step) {
+        const int kn = step * kBK;
 #pragma unroll
         for (int u = 0; u < NU; ++u) {
-            reinterpret_cast<uint4 *>(&As[ar * kLdsK + ac])[u] = ga[u];
-            reinterpret_cast<uint4 *>(&Bs[ar * kLdsK + ac])[u] = gb[u];
+            ga[u] = reinterpret_cast<const uint4 *>(pa + kn)[u];
+            gb[u] = reinterpret_cast<const uint4 *>(pb + kn)[u];
             if (MODE == 2) {
-                reinterpret_cast<uint4 *>(&Asl[ar * kLdsK + ac])[u] = gal[u];
-                reinterpret_cast<uint4 *>(&Bsl[ar * kLdsK + ac])[u] = gbl[u];
+                gal[u] = reinterpret_cast<const uint4 *>(pal + kn)[u];
+                gbl[u] = reinterpret_cast<const uint4 *>(pbl + kn)[u];
             }
         }
-        __syncthreads();
-        if (k0 + kBK < K) {
-            const int kn = k0 + kBK;
+    };
+    if (s_lo < s_hi) fetch(s_lo);
+    for (int it = 0; it < s_max; ++it) {
+        const bool active = s_lo + it < s_hi;
+        if (active) {
 #pragma unroll
             for (int u = 0; u < NU; ++u) {
-                ga[u] = reinterpret_cast<const uint4 *>(pa + kn)[u];
-                gb[u] = reinterpret_cast<const uint4 *>(pb + kn)[u];
+                reinterpret_cast<uint4 *>(&As[ar * kLdsK + ac])[u] = ga[u];
+                reinterpret_cast<uint4 *>(&Bs[ar * kLdsK + ac])[u] = gb[u];
                 if (MODE == 2) {
-                    gal[u] = reinterpret_cast<const uint4 *>(pal + kn)[u];
-                    gbl[u] = reinterpret_cast<const uint4 *>(pbl + kn)[u];
+                    reinterpret_cast<uint4 *>(&Asl[ar * kLdsK + ac])[u] = gal[u];
+                    reinterpret_cast<uint4 *>(&Bsl[ar * kLdsK + ac])[u] = gbl[u];
                 }
             }
         }
+        __syncthreads();
+        if (s_lo + it + 1 < s_hi) fetch(s_lo + it + 1);
+        if (active) {
 #pragma unroll
-        for (int ks = 0; ks < kBK; ks += 16) {
-            const int kk = ks + 8 * (lane >> 5);
+            for (int ks = 0; ks < kBK; ks += 16) {
+                const int kk = ks + 8 * (lane >> 5);
 #pragma unroll
-            for (int i = 0; i < FR; ++i) {
-                const int ra = wm + 32 * i + (lane & 31);
-                const uint4 a_h = *reinterpret_cast<const uint4 *>(&As[ra * kLdsK + kk]);
-                uint4 a_l;
-                if (MODE == 2) a_l = *reinterpret_cast<const uint4 *>(&Asl[ra * kLdsK + kk]);
+                for (int i = 0; i < FR; ++i) {
+                    const int ra = wm + 32 * i + (lane & 31);
+                    const uint4 a_h = *reinterpret_cast<const uint4 *>(&As[ra * kLdsK + kk]);
+                    uint4 a_l;
+                    if (MODE == 2) a_l = *reinterpret_cast<const uint4 *>(&Asl[ra * kLdsK + kk]);
 #pragma unroll
-                for (int j = 0; j < FR; ++j) {
-                    const int rb = wn + 32 * j + (lane & 31);
-                    const uint4 b_h = *reinterpret_cast<const uint4 *>(&Bs[rb * kLdsK + kk]);
-                    if (MODE == 1) {
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
-                            __builtin_bit_cast(f16x8, a_h), __builtin_bit_cast(f16x8, b_h), acc[i][j], 0, 0, 0);
-                    } else {
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                            __builtin_bit_cast(bf16x8, a_h), __builtin_bit_cast(bf16x8, b_h), acc[i][j], 0, 0, 0);
-                        if (MODE == 2) {
-                            const uint4 b_l = *reinterpret_cast<const uint4 *>(&Bsl[rb * kLdsK + kk]);
+                    for (int j = 0; j < FR; ++j) {
+                        const int rb = wn + 32 * j + (lane & 31);
+                        const uint4 b_h = *reinterpret_cast<const uint4 *>(&Bs[rb * kLdsK + kk]);
+                        if (MODE == 1) {
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
+                                __builtin_bit_cast(f16x8, a_h), __builtin_bit_cast(f16x8, b_h), acc[i][j], 0, 0, 0);
+                        } else {
                             acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                                __builtin_bit_cast(bf16x8, a_h), __builtin_bit_cast(bf16x8, b_l), acc[i][j], 0, 0, 0);
-                            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                                __builtin_bit_cast(bf16x8, a_l), __builtin_bit_cast(bf16x8, b_h), acc[i][j], 0, 0, 0);
+                                __builtin_bit_cast(bf16x8, a_h), __builtin_bit_cast(bf16x8, b_h), acc[i][j], 0, 0, 0);
+                            if (MODE == 2) {
+                                const uint4 b_l = *reinterpret_cast<const uint4 *>(&Bsl[rb * kLdsK + kk]);
+                                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                                    __builtin_bit_cast(bf16x8, a_h), __builtin_bit_cast(bf16x8, b_l), acc[i][j], 0, 0, 0);
+                                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                                    __builtin_bit_cast(bf16x8, a_l), __builtin_bit_cast(bf16x8, b_h), acc[i][j], 0, 0, 0);
+                            }
                         }
                     }
                 }
             }
         }
         __syncthreads();
+    }
+    if constexpr (KS > 1) {
+        // groups 1 .. KS-1 leave their accumulators in the (now idle) staging LDS; group 0
+        // adds them in group order
+        f32x16 *part = reinterpret_cast<f32x16 *>(lds);
+        if (grp > 0) part[((grp - 1) * 4 + wave) * 64 + lane] = acc[0][0];
+        __syncthreads();
+        if (grp > 0) return;
+#pragma unroll
+        for (int g = 1; g < KS; ++g) {
+            const f32x16 v = part[((g - 1) * 4 + wave) * 64 + lane];
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[0][0][r] += v[r];
+        }
     }
     // epilogue: acc[i][j][r] -> row wm + 32i + 8(r/4) + 4(lane/32) + r%4, col wn + 32j + lane%32
 #pragma unroll
@@ -717,6 +744,23 @@ static bool gemm_big(int Mp, int Np, int Kp)
            (Mp / kBigT) * (Np / kBigT) >= kBigMinTiles;
 }
 
+// K split of gemm_kernel by the product's count of 64 x 64 tiles: 1 from kSplitK1Tiles
+// tiles on, 2 from kSplitK2Tiles, else 4.
+constexpr int kSplitK1Tiles = 512, kSplitK2Tiles = 128;
+
+template <int MODE>
+static void launch_gemm_small(int ks, dim3 grid, const unsigned short *Ah, const unsigned short *Al, int lda,
+                              const unsigned short *Bh, const unsigned short *Bl, int ldb, float *Cm, int ldc, int Kp,
+                              hipStream_t s)
+{
+    if (ks == 4)
+        hipLaunchKernelGGL((gemm_kernel<MODE, 4>), grid, dim3(1024), 0, s, Ah, Al, lda, Bh, Bl, ldb, Cm, ldc, Kp);
+    else if (ks == 2)
+        hipLaunchKernelGGL((gemm_kernel<MODE, 2>), grid, dim3(512), 0, s, Ah, Al, lda, Bh, Bl, ldb, Cm, ldc, Kp);
+    else
+        hipLaunchKernelGGL((gemm_kernel<MODE, 1>), grid, dim3(256), 0, s, Ah, Al, lda, Bh, Bl, ldb, Cm, ldc, Kp);
+}
+
 // One product of the recursions on the dense path: the row scales and the scaled left
 // operand A' = diag(2^-rexp) A diag(phi) in 16-bit form in one pass, then C = A' B^T with 16-bit
 // operands and FP32 accumulation and output in one GEMM launch (tile chosen by gemm_big).
@@ -746,12 +790,14 @@ static hipError_t launch_gemm(const CircleState &C, const float *A, int lda, con
         return hipGetLastError();
     }
     const dim3 grid(Np / kSmallT, Mp / kSmallT);
+    const int tiles = (Np / kSmallT) * (Mp / kSmallT);
+    const int ks = tiles >= kSplitK1Tiles ? 1 : (tiles >= kSplitK2Tiles ? 2 : 4);
     if (C.mode == 1)
-        hipLaunchKernelGGL(gemm_kernel<1>, grid, dim3(256), 0, s, Ah, Al, lda, Bh, Bl, ldb, Cm, ldc, Kp);
+        launch_gemm_small<1>(ks, grid, Ah, Al, lda, Bh, Bl, ldb, Cm, ldc, Kp, s);
     else if (C.mode == 2)
-        hipLaunchKernelGGL(gemm_kernel<2>, grid, dim3(256), 0, s, Ah, Al, lda, Bh, Bl, ldb, Cm, ldc, Kp);
+        launch_gemm_small<2>(ks, grid, Ah, Al, lda, Bh, Bl, ldb, Cm, ldc, Kp, s);
     else
-        hipLaunchKernelGGL(gemm_kernel<0>, grid, dim3(256), 0, s, Ah, Al, lda, Bh, Bl, ldb, Cm, ldc, Kp);
+        launch_gemm_small<0>(ks, grid, Ah, Al, lda, Bh, Bl, ldb, Cm, ldc, Kp, s);
     return hipGetLastError();
 }
 
