@@ -92,6 +92,24 @@ def test_dense_long_cycle_stays_in_range(mot, long_cycle, prec, bound):
 
 
 @pytest.mark.parametrize("prec,bound", [("BF16X3", 1e-5), ("FP16", 5e-4), ("BF16", 5e-3)])
+@pytest.mark.parametrize("sizes", [[40, 33, 50, 20, 1], [70, 129, 64, 65]])
+def test_dense_circle_tiny(mot, prec, bound, sizes):
+    """Marginals of 1 to 129 points: matrices padded to 64, 128 or 192 columns, so a product
+    has one to six 64 x 64 tiles (four K groups per workgroup) and two to six K steps, with
+    some groups idle where the steps are fewer than the groups; a marginal of one point.
+    Scaling vectors after 10 sweeps against the FP64 oracle's."""
+    inst = W.make_instance(rng(63), len(sizes), sizes, 2, W.CIRCLE, 0.1)
+    ophi, oS, _, _ = oracle.circle_sinkhorn(inst.points, inst.weights, inst.eta, 10)
+    p = getattr(mot, "PREC_" + prec)
+    plan = mot.Plan(inst.points, inst.weights, W.CIRCLE, None, inst.eta, path=mot.DENSE, precision=p)
+    plan.sinkhorn(10)
+    rel = max_rel(gauge_fix(plan.scalings(), inst.weights), gauge_fix(ophi, inst.weights))
+    print("dense %s tiny %s: gauge-fixed phi rel err %.3e" % (prec, sizes, rel))
+    assert rel < bound
+    plan.close()
+
+
+@pytest.mark.parametrize("prec,bound", [("BF16X3", 1e-5), ("FP16", 5e-4), ("BF16", 5e-3)])
 @pytest.mark.parametrize("sizes", [[2600, 2550, 2580], [2100, 2050, 2080], [1400, 1380, 1410],
                                    [1100, 600, 1300], [6600, 600, 620]])
 def test_dense_circle_large_gemm(mot, prec, bound, sizes):
