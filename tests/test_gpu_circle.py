@@ -91,6 +91,25 @@ def test_dense_long_cycle_stays_in_range(mot, long_cycle, prec, bound):
     plan.close()
 
 
+@pytest.mark.parametrize("path", ["nfft", "dense"])
+def test_circle_3d(mot, path):
+    """A circle in three dimensions (K = 4, 260 to 330 points per marginal, eta = 0.1).  On
+    the NFFT path every row of a product is its own job, and the rows spread from the same
+    source points go three to an item of the 3-D spreading kernel; the dense path builds its
+    kernel matrices from 3-D distances.  Scaling vectors and every S after 10 sweeps against
+    the FP64 oracle's (split BF16 on the dense path)."""
+    inst = W.make_instance(rng(65), 4, [300, 261, 330, 287], 3, W.CIRCLE, 0.1)
+    ophi, oS, _, _ = oracle.circle_sinkhorn(inst.points, inst.weights, inst.eta, 10)
+    p, prec = (mot.NFFT, mot.PREC_MIXED) if path == "nfft" else (mot.DENSE, mot.PREC_BF16X3)
+    plan = mot.Plan(inst.points, inst.weights, W.CIRCLE, None, inst.eta, path=p, precision=prec)
+    plan.sinkhorn(10)
+    rel = max_rel(gauge_fix(plan.scalings(), inst.weights), gauge_fix(ophi, inst.weights))
+    print("circle 3-D %s: gauge-fixed phi rel err %.3e" % (path, rel))
+    assert rel < 1e-5
+    np.testing.assert_allclose(plan.S_history(), oS, rtol=1e-6)
+    plan.close()
+
+
 @pytest.mark.parametrize("prec,bound", [("BF16X3", 1e-5), ("FP16", 5e-4), ("BF16", 5e-3)])
 @pytest.mark.parametrize("sizes", [[40, 33, 50, 20, 1], [70, 129, 64, 65]])
 def test_dense_circle_tiny(mot, prec, bound, sizes):
