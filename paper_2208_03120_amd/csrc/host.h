@@ -147,6 +147,7 @@ struct Step {
     int lane = 0;                 // i >= 1: runs on side stream i - 1 between ST_FORK and ST_JOIN
     int d = 0, n = 0, fft_kind = 0, precision = 0, max_patch = 0, trunc_r = 0, diff = 0;
     int group = 0;                // 3-D spreading: jobs per item (items int4)
+    int max_children = 0;         // node update: most children of a node in the launch
     const void *jobs = nullptr;   // device ProdJob / NodeJob / FinalJob array
     const void *items = nullptr;  // device int2 / int4 array
     int n_items = 0;

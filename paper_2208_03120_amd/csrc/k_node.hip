@@ -21,7 +21,8 @@ namespace mot {
 
 constexpr int kNodeElems = kNodeItemElems;   // elements per node item
 constexpr int kNodeEPT = kNodeElems / 256;     // elements per thread (256 threads)
-constexpr int kRegChildren = 16;  // children held in registers
+constexpr int kRegChildren = 16;  // children held in registers (more: read from memory)
+constexpr int kFewChildren = 4;   // the same, for launches of nodes with at most 4 children
 
 __device__ __forceinline__ int exp_of(double v)
 {
@@ -48,11 +49,12 @@ __device__ __forceinline__ double block_sum(double v, double *red)
     return s;
 }
 
+template <int RC>
 __global__ __launch_bounds__(256) void node_kernel(const NodeJob *__restrict__ jobs,
                                                    const int2 *__restrict__ items, int n_items)
 {
     __shared__ double red[4];
-    __shared__ int emx[4][kRegChildren + 1];
+    __shared__ int emx[4][RC + 1];
     const int tid = threadIdx.x;
     for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
         const int2 itm = items[it];
@@ -61,31 +63,31 @@ __global__ __launch_bounds__(256) void node_kernel(const NodeJob *__restrict__ j
         const bool upd = op & 1, dsrc = op & 2, usrc = op & 4, root = op & 8, marg = op & 16;
         const bool freen = op & 32;
         const int nch = J.nchild;
-        const bool regs = nch <= kRegChildren;
+        const bool regs = nch <= RC;
         double s1 = 0.0, s2 = 0.0;
         int em_up = INT32_MIN;
-        int em[kRegChildren];
+        int em[RC];
 #pragma unroll
-        for (int c = 0; c < kRegChildren; ++c) em[c] = INT32_MIN;
+        for (int c = 0; c < RC; ++c) em[c] = INT32_MIN;
         bool bad = false;
         // the inputs of all of this thread's elements (children's messages too, when they
         // fit in registers) are loaded before any output is written, so that the loads
         // are in flight together
         double mu_k[kNodeEPT], ph_k[kNodeEPT], g_k[kNodeEPT];
-        double b[kRegChildren][kNodeEPT];
+        double b[RC][kNodeEPT];
 #pragma unroll
         for (int k = 0; k < kNodeEPT; ++k) {
             const int64_t i = (int64_t)itm.y + tid + 256 * k;
             mu_k[k] = ph_k[k] = g_k[k] = 1.0;
 #pragma unroll
-            for (int t = 0; t < kRegChildren; ++t) b[t][k] = 1.0;
+            for (int t = 0; t < RC; ++t) b[t][k] = 1.0;
             if (i < J.n) {
                 mu_k[k] = gp(J.mu)[i];
                 ph_k[k] = gp(J.phi)[i];
                 if (!root) g_k[k] = gp(J.gamma)[i];
                 if (regs)
 #pragma unroll
-                    for (int t = 0; t < kRegChildren; ++t)
+                    for (int t = 0; t < RC; ++t)
                         if (t < nch) b[t][k] = gp(gp(J.beta)[t])[i];
             }
         }
@@ -96,7 +98,7 @@ __global__ __launch_bounds__(256) void node_kernel(const NodeJob *__restrict__ j
             double cp = 1.0;
             if (regs) {
 #pragma unroll
-                for (int t = 0; t < kRegChildren; ++t)
+                for (int t = 0; t < RC; ++t)
                     if (t < nch) cp *= b[t][k];
             } else {
                 for (int t = 0; t < nch; ++t) cp *= gp(gp(J.beta)[t])[i];
@@ -131,11 +133,11 @@ __global__ __launch_bounds__(256) void node_kernel(const NodeJob *__restrict__ j
                 const double pg = ph * g;
                 if (regs) {
 #pragma unroll
-                    for (int c = 0; c < kRegChildren; ++c) {
+                    for (int c = 0; c < RC; ++c) {
                         if (c >= nch) break;
                         double w = 1.0;
 #pragma unroll
-                        for (int t = 0; t < kRegChildren; ++t)
+                        for (int t = 0; t < RC; ++t)
                             if (t < nch && t != c) w *= b[t][k];
                         const double u = pg * w;
                         gp(gp(J.down_src)[c])[i] = u;
@@ -160,11 +162,11 @@ __global__ __launch_bounds__(256) void node_kernel(const NodeJob *__restrict__ j
             __syncthreads();
             if (usrc) {
                 const int m = wave_max_int(em_up);
-                if (lane == 0) emx[wave][kRegChildren] = m;
+                if (lane == 0) emx[wave][RC] = m;
             }
             if (dsrc && regs) {
 #pragma unroll
-                for (int c = 0; c < kRegChildren; ++c) {
+                for (int c = 0; c < RC; ++c) {
                     if (c < nch) {  // nch is uniform over the block
                         const int m = wave_max_int(em[c]);
                         if (lane == 0) emx[wave][c] = m;
@@ -172,8 +174,8 @@ __global__ __launch_bounds__(256) void node_kernel(const NodeJob *__restrict__ j
                 }
             }
             __syncthreads();
-            if (tid <= kRegChildren) {
-                const bool is_up = tid == kRegChildren;
+            if (tid <= RC) {
+                const bool is_up = tid == RC;
                 if ((is_up && usrc) || (!is_up && dsrc && regs && tid < nch)) {
                     int m = emx[0][tid];
                     for (int w = 1; w < (int)(blockDim.x >> 6); ++w) m = max(m, emx[w][tid]);
@@ -193,11 +195,19 @@ __global__ __launch_bounds__(256) void node_kernel(const NodeJob *__restrict__ j
     }
 }
 
-hipError_t launch_node(const NodeJob *jobs_dev, const int2 *items, int n_items, hipStream_t s)
+hipError_t launch_node(const NodeJob *jobs_dev, const int2 *items, int n_items, int max_children, hipStream_t s)
 {
     if (n_items == 0) return hipSuccess;
     const int grid = n_items < 8192 ? n_items : 8192;
-    hipLaunchKernelGGL(node_kernel, dim3(grid), dim3(256), 0, s, jobs_dev, items, n_items);
+    // the register copies of the children's messages set the kernel's register count, and
+    // with it how many blocks run at once: launches whose nodes have at most one or at most
+    // kFewChildren children take the smaller forms
+    if (max_children <= 1)  // leaves and the nodes of a path
+        hipLaunchKernelGGL(node_kernel<1>, dim3(grid), dim3(256), 0, s, jobs_dev, items, n_items);
+    else if (max_children <= kFewChildren)
+        hipLaunchKernelGGL(node_kernel<kFewChildren>, dim3(grid), dim3(256), 0, s, jobs_dev, items, n_items);
+    else
+        hipLaunchKernelGGL(node_kernel<kRegChildren>, dim3(grid), dim3(256), 0, s, jobs_dev, items, n_items);
     return hipGetLastError();
 }
 

@@ -160,7 +160,8 @@ hipError_t launch_trunc(int d, int precision, int R, int wide, const ProdJob *jo
 // diff != 0: mixed-precision pairs with the exponent formed in FP64 (small eta)
 hipError_t launch_direct(int d, const ProdJob *jobs_dev, const int4 *items, int n_items, const int2 *red_items,
                          int n_red, int precision, int diff, hipStream_t s);
-hipError_t launch_node(const NodeJob *jobs_dev, const int2 *items, int n_items, hipStream_t s);
+hipError_t launch_node(const NodeJob *jobs_dev, const int2 *items, int n_items, int max_children,
+                       hipStream_t s);
 hipError_t launch_finalize(const FinalJob *jobs, const int2 *items, int n_items, int n_jobs, hipStream_t s);
 hipError_t launch_fill_int(int32_t *p, int32_t value, int64_t count, hipStream_t s);
 hipError_t launch_fill_double(double *p, double value, int64_t count, hipStream_t s);

@@ -178,7 +178,7 @@ int run_steps(const std::vector<Step> &steps, hipStream_t s0, const Lanes *lanes
                 }
             break;
         case ST_NODE:
-            MOT_HIP(launch_node((const NodeJob *)st.jobs, (const int2 *)st.items, st.n_items, s));
+            MOT_HIP(launch_node((const NodeJob *)st.jobs, (const int2 *)st.items, st.n_items, st.max_children, s));
             break;
         case ST_DIRECT:
             MOT_HIP(launch_direct(st.d, (const ProdJob *)st.jobs, (const int4 *)st.items, st.n_items,
@@ -264,6 +264,7 @@ struct StepBuilder {
             for (int64_t e = 0; e < host_jobs[j].n; e += kNodeItemElems) items.push_back(make_int2(j, (int)e));
         if (items.empty()) return;
         Step st{ST_NODE};
+        for (int j : ids) st.max_children = std::max(st.max_children, host_jobs[j].nchild);
         st.jobs = jobs_dev;
         st.items = upload(items);
         st.n_items = (int)items.size();
