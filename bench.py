@@ -36,20 +36,20 @@ PEAK_FP32_TFLOPS = 157.3  # dense FP32 MFMA
 # for fold and the FFT passes also of plan.cpp, whose launch item order sets their traffic).
 COPY_MIB = 256
 TRAFFIC = {
-    "spread": {"bytes_per_launch": 231944121, "source": "k_nfft.hip",
+    "spread": {"bytes_per_launch": 231944683, "source": "k_nfft.hip",
              "sha256": "e95beabf6ee9f74433a7bef0ca9f0ae0990f9eeddcb4f03e4c0070d85db2cefe"},
-    "spread_g3": {"bytes_per_launch": 110941252, "source": "k_nfft.hip",
+    "spread_g3": {"bytes_per_launch": 110942743, "source": "k_nfft.hip",
                 "sha256": "e95beabf6ee9f74433a7bef0ca9f0ae0990f9eeddcb4f03e4c0070d85db2cefe"},
-    "interp": {"bytes_per_launch": 213599231, "source": "k_nfft.hip",
+    "interp": {"bytes_per_launch": 213263908, "source": "k_nfft.hip",
              "sha256": "e95beabf6ee9f74433a7bef0ca9f0ae0990f9eeddcb4f03e4c0070d85db2cefe"},
-    "fold": {"bytes_per_launch": 61193520, "source": "k_nfft.hip+plan.cpp",
-           "sha256": "6129d3d0a3c9da6a549c7e17e6808a3e26eae661a3313b279ad7e15704197fd1"},
-    "fft6": {"bytes_per_launch": 10823548, "source": "k_fft.hip+plan.cpp",
-           "sha256": "d85e2812822b82e320f8643b041c1923ac57c4bc636e69fed990ba01250181e8"},
-    "fft5": {"bytes_per_launch": 26586465, "source": "k_fft.hip+plan.cpp",
-           "sha256": "d85e2812822b82e320f8643b041c1923ac57c4bc636e69fed990ba01250181e8"},
-    "fft7": {"bytes_per_launch": 10822070, "source": "k_fft.hip+plan.cpp",
-           "sha256": "d85e2812822b82e320f8643b041c1923ac57c4bc636e69fed990ba01250181e8"}
+    "fold": {"bytes_per_launch": 61193355, "source": "k_nfft.hip+plan.cpp",
+           "sha256": "a50644c4b46fca7e35a1c7346401ca21e0aaeb0ff38ae98507b4ee0d7e003034"},
+    "fft6": {"bytes_per_launch": 10823506, "source": "k_fft.hip+plan.cpp",
+           "sha256": "b36e97569b327f182bae76981ba8e27a0de1b2b778b57b21267438e78693c3ee"},
+    "fft5": {"bytes_per_launch": 26586437, "source": "k_fft.hip+plan.cpp",
+           "sha256": "b36e97569b327f182bae76981ba8e27a0de1b2b778b57b21267438e78693c3ee"},
+    "fft7": {"bytes_per_launch": 10822049, "source": "k_fft.hip+plan.cpp",
+           "sha256": "b36e97569b327f182bae76981ba8e27a0de1b2b778b57b21267438e78693c3ee"}
 }
 
 
