@@ -67,6 +67,45 @@ def test_path_fp64_direct_sinkhorn_parity(mot):
     plan.close()
 
 
+@pytest.mark.parametrize("shape", ["star20", "hub18"])
+@pytest.mark.parametrize("path", ["direct", "nfft"])
+def test_wide_nodes_parity(mot, shape, path):
+    """Nodes with more children than the node update holds in registers (16): a star of 20
+    marginals (19 leaves on the root) and a root whose one child has 18 children.  Those
+    nodes take the update's memory path for the children's messages and their exponent
+    maxima, and the finalisation's for the root marginal.  Scaling vectors, the S history and
+    the marginals after 12 sweeps against the FP64 oracle: FP64 direct within 1e-11, NFFT
+    within 1e-5 (gauge-fixed); the NFFT S history as in the headline parity test (S at phi = 1
+    relatively within (K - 1) times a product's 2e-6, later S absolutely within
+    eta (K + 2.2) 1e-5)."""
+    K = 20
+    parent = W.star_parent(K) if shape == "star20" else np.array([-1, 0] + [1] * (K - 2), dtype=np.int32)
+    sizes = [int(x) for x in rng(501).integers(150, 400, K)]
+    inst = W.make_instance(rng(502), K, sizes, 2, W.TREE, 0.05, parent=parent)
+    ophi, oS, _, _ = oracle.tree_sinkhorn(inst.points, inst.weights, inst.parent, inst.eta, 12)
+    if path == "direct":
+        plan = mot.Plan(inst.points, inst.weights, W.TREE, inst.parent, inst.eta, path=mot.DIRECT,
+                        precision=mot.PREC_FP64)
+        bound = 1e-11
+    else:
+        plan = mot.Plan(inst.points, inst.weights, W.TREE, inst.parent, inst.eta, path=mot.NFFT)
+        bound = 1e-5
+    plan.sinkhorn(12)
+    rel = max_rel(gauge_fix(plan.scalings(), inst.weights), gauge_fix(ophi, inst.weights))
+    print("%s %s: gauge-fixed phi rel err %.3e" % (shape, path, rel))
+    assert rel < bound
+    S = plan.S_history()
+    if path == "direct":
+        np.testing.assert_allclose(S, oS, rtol=1e-12, atol=1e-14)
+    else:
+        assert abs(S[0] - oS[0]) / abs(oS[0]) < (K - 1) * 2e-6
+        assert float(np.max(np.abs(S[1:] - oS[1:]))) < inst.eta * (K + 2.2) * 1e-5
+    P, _ = plan.marginals()
+    oP = oracle.tree_marginals(inst.points, inst.parent, inst.eta, plan.scalings())
+    assert max_rel(P, oP) < (1e-11 if path == "direct" else 1e-5)
+    plan.close()
+
+
 @pytest.mark.parametrize("sizes,parent", [([3, 1, 70, 129], [-1, 0, 0, 2]), ([2, 257, 5], [-1, 0, 1])])
 def test_fp64_direct_ragged_sizes_parity(mot, sizes, parent):
     """FP64 direct sums split their sources over blocks (64 targets x one of several
