@@ -49,6 +49,10 @@ __device__ __forceinline__ double block_sum(double v, double *red)
     return s;
 }
 
+// One node item: up to kNodeItemElems elements of one node.  The messages of up to RC
+// children are held in registers (loaded before any output is written); a node with more
+// children reads them from memory for every product and records the exponent maxima of its
+// down sources with one atomic per element.
 template <int RC>
 __global__ __launch_bounds__(256) void node_kernel(const NodeJob *__restrict__ jobs,
                                                    const int2 *__restrict__ items, int n_items)
