@@ -58,6 +58,67 @@ def test_batched_instance_matches_oracle(mot):
     plan.close()
 
 
+def test_batched_direct_paths_equal_alone(mot):
+    """A batch of a plan on the FP64 direct path (a path of 500 points per marginal, whose
+    products split the sources over blocks and add the partial sums in a fixed order), one
+    on the mixed direct path (d = 3) and one on NFFT: each equals its plan alone bit for bit
+    (scaling vectors and S history), and the FP64 plan matches the oracle within 1e-11."""
+    r = np.random.Generator(np.random.PCG64(601))
+    a = W.path_fp64_direct(seed=1, N=500)
+    b = W.make_instance(r, 3, [700, 650, 600], 3, W.TREE, 0.05, parent=[-1, 0, 0])
+    c = W.make_instance(r, 4, [900, 800, 850, 700], 2, W.TREE, 0.05, parent=[-1, 0, 1, 1])
+    cases = [(a, dict(path=mot.DIRECT, precision=mot.PREC_FP64)), (b, dict(path=mot.DIRECT, precision=mot.PREC_MIXED)),
+             (c, dict(path=mot.NFFT))]
+    stream = mot.current_stream()
+    plans = [mot.Plan(x.points, x.weights, W.TREE, x.parent, x.eta, stream=stream, **kw) for x, kw in cases]
+    batch = mot.Batch(plans)
+    batch.sinkhorn(8)
+    for (x, kw), p in zip(cases, plans):
+        alone = mot.Plan(x.points, x.weights, W.TREE, x.parent, x.eta, **kw)
+        alone.sinkhorn(8)
+        for u, v in zip(p.scalings(), alone.scalings()):
+            np.testing.assert_array_equal(u, v)
+        np.testing.assert_array_equal(p.S_history(), alone.S_history())
+        alone.close()
+    ophi, _, _, _ = oracle.tree_sinkhorn(a.points, a.weights, a.parent, a.eta, 8)
+    assert max_rel(plans[0].scalings(), ophi) < 1e-11
+    batch.close()
+    for p in plans:
+        p.close()
+
+
+def test_server_serves_circle_nfft_requests(mot):
+    """Circle requests on the row-by-row NFFT path served beside tree requests: each equals
+    its stand-alone result bit for bit, and the circles match the oracle's Algorithm 3 for the
+    same sweeps (gauge-fixed, 1e-5)."""
+    r = np.random.Generator(np.random.PCG64(83))
+    reqs = []
+    for i in range(4):
+        if i % 2 == 0:
+            reqs.append(W.make_instance(r, 4, [int(x) for x in r.integers(200, 400, 4)], 2, W.CIRCLE, 0.1))
+        else:
+            reqs.append(W.make_instance(r, 3, [int(x) for x in r.integers(300, 700, 3)], 2, W.TREE, 0.05,
+                                        parent=[-1, 0, 0]))
+    srv = mot.Server(hbm_budget=8 << 30, max_slots=8)
+    tickets = [srv.submit(q, tol=1e-6, max_sweeps=300, path=mot.NFFT)[1] for q in reqs]
+    srv.run(60.0, idle_exit=True)
+    res = [srv.fetch(t, want_phi=True) for t in tickets]
+    srv.close()
+    assert all(x is not None and x["status"] in (mot.OK, mot.MAXITER) for x in res)
+    for q, x in zip(reqs, res):
+        solo = mot.Server(hbm_budget=8 << 30, max_slots=1)
+        _, t = solo.submit(q, tol=1e-6, max_sweeps=300, path=mot.NFFT)
+        solo.run(60.0, idle_exit=True)
+        y = solo.fetch(t, want_phi=True)
+        solo.close()
+        assert y["sweeps"] == x["sweeps"]
+        for a, b in zip(y["phi"], x["phi"]):
+            np.testing.assert_array_equal(a, b)
+        if q.topology == W.CIRCLE:
+            ophi, _, _, _ = oracle.circle_sinkhorn(q.points, q.weights, q.eta, x["sweeps"])
+            assert max_rel(gauge_fix(x["phi"], q.weights), gauge_fix(ophi, q.weights)) < 1e-5
+
+
 def _requests():
     stream = W.request_stream(seed=7, count=10, n_range=(300, 2500), circle_n_max=400)
     return [inst for _, inst in stream]
